@@ -1,0 +1,27 @@
+"""CPU oracle for context-free path querying under relational semantics.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the GPU library imports, links or calls
+this package; only the test-suite, the smoke check and the benchmark's CPU
+baseline do.  It shares no code with the GPU path: the only common input is the
+seeded generator package ``workloads``, which holds no query arithmetic.
+
+Contents and what each follows:
+
+* ``worklist`` (C, ``cfpq_worklist.c``): the least set of triples (A, i, j)
+  containing the edge-derived triples and closed under every rule A -> B C,
+  i.e. the relations R_A of section 2, which Theorem 2 says the matrix closure
+  computes.  The main oracle.
+* ``alg1``: Algorithm 1 of section 4.2 written out with numpy, one Boolean
+  product per binary rule (Valiant's remark, section 3); gives the loop count
+  of the paper's simultaneous update, and Valiant's closure a^+ of section 2
+  truncated at a path length.
+* ``brute``: CYK over a CNF grammar and enumeration of every path up to a
+  length bound, straight from the definition of R_A (section 2).
+
+Pins (tests/test_oracle_*.py): the worked example of section 4.3 (every
+printed T_k, the loop count 6 and all seven R_A), a closed form for two label
+cycles of coprime length, textbook special cases (transitive closure, CYK on a
+chain, bracket matching, terminal-only grammars), brute force on tiny graphs,
+and invariants (closure, monotonicity, permutation equivariance, disjoint
+union).  Every function here has at least one such pin.
+"""

@@ -1,0 +1,81 @@
+"""Brute force straight from the definitions of section 2 (test infrastructure).
+
+``cyk_table`` decides A =>* w for every substring of a word (CYK over a CNF
+grammar).  ``paths_up_to`` enumerates every path of at most ``max_len`` edges
+and records, for each nonterminal A, the pairs (i, j) joined by a path whose
+label word A derives: that is R_A of section 2 restricted to paths of bounded
+length, so it is a subset of R_A for any bound and equals R_A on a DAG once the
+bound reaches n - 1.
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Set, Tuple
+
+
+def _by_term(grammar) -> Dict[int, Set[int]]:
+    by_term: Dict[int, Set[int]] = {}
+    for a, x in grammar.term:
+        by_term.setdefault(x, set()).add(a)
+    return by_term
+
+
+def _combine(left: Set[int], right: Set[int], rules) -> Set[int]:
+    """N1 . N2 of section 2: {A : B in N1, C in N2, A -> B C}."""
+    if not left or not right:
+        return set()
+    return {a for a, b, c in rules if b in left and c in right}
+
+
+def cyk_table(word: List[int], grammar) -> List[List[Set[int]]]:
+    """table[s][e] = {A : A =>* word[s:e]} for 0 <= s < e <= len(word)."""
+    by_term = _by_term(grammar)
+    rules = list(grammar.bin)
+    L = len(word)
+    tab = [[set() for _ in range(L + 1)] for _ in range(L + 1)]
+    for s in range(L):
+        tab[s][s + 1] = set(by_term.get(word[s], ()))
+    for width in range(2, L + 1):
+        for s in range(0, L - width + 1):
+            e = s + width
+            for m in range(s + 1, e):
+                tab[s][e] |= _combine(tab[s][m], tab[m][e], rules)
+    return tab
+
+
+def derives(word: List[int], grammar) -> Set[int]:
+    if not word:
+        return set()
+    return cyk_table(word, grammar)[0][len(word)]
+
+
+def paths_up_to(n: int, edges, grammar, max_len: int) -> Dict[int, Set[Tuple[int, int]]]:
+    """{A: {(i, j)}} over all paths of 1..max_len edges (multi-edges and
+    self-loops are followed like any other edge).  Along a path the CYK table
+    grows by one column per edge: col[e][s] = {A : A =>* labels[s:e]}."""
+    by_term = _by_term(grammar)
+    rules = list(grammar.bin)
+    out_edges: Dict[int, List[Tuple[int, int]]] = {}
+    for u, x, v in (tuple(int(t) for t in e) for e in edges):
+        out_edges.setdefault(u, []).append((x, v))
+    result: Dict[int, Set[Tuple[int, int]]] = {a: set() for a in range(grammar.n_nonterminals)}
+
+    def walk(start: int, node: int, cols: List[List[Set[int]]]):
+        depth = len(cols) - 1          # edges on the path so far
+        if depth == max_len:
+            return
+        for x, v in out_edges.get(node, ()):
+            e = depth + 1
+            new: List[Set[int]] = [set() for _ in range(e)]
+            new[e - 1] = set(by_term.get(x, ()))
+            for s in range(e - 2, -1, -1):
+                for m in range(s + 1, e):
+                    new[s] |= _combine(cols[m][s], new[m], rules)
+            for a in new[0]:
+                result[a].add((start, v))
+            cols.append(new)
+            walk(start, v, cols)
+            cols.pop()
+
+    for start in range(n):
+        walk(start, start, [[]])
+    return result
