@@ -1,0 +1,135 @@
+#!/usr/bin/env python3
+"""Benchmark: CFPQ closure throughput on one MI355X.
+
+A step is one full relational closure (matrix initialisation, every product,
+union and change check until the fixpoint) of the Dyck grammar on a seeded
+G(16384, 65536) graph with labels a/b, edges already in device memory.  The
+value is closure Gbit-op/s: 2 npad^3 Boolean operations (one AND and one OR per
+(i, k, j)) per executed product, divided by the wall time of the closure.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "closure Gbitop/s at n=16384; batched queries/s + p50/p99 latency vs plain"
+# MI355X peaks used for the roofline fraction.
+PEAK_INT8_TOPS = 5000.0  # dense int8 MFMA, 5.0 POP/s (1 MAC = 2 ops = AND + OR here)
+# VALU: 256 CUs x 64 lanes per clock x 2.4 GHz x 64 bit-operations per v_and_or_b32
+PEAK_VALU_BITOPS_T = 256 * 64 * 2.4e9 * 64 / 1e12
+
+
+def cpu_baseline(inst, seconds_target=12.0):
+    """The oracle's own Boolean product (oracle/alg1.py, float64 BLAS) timed on
+    a bounded row block of the first product of the same workload."""
+    import numpy as np
+    from oracle import alg1
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    t0 = alg1.initial_matrix(inst.n, inst.edges, inst.grammar)
+    b, c = t0[inst.grammar.nt("A")], t0[inst.grammar.nt("B")]
+    rows = 128
+    t = time.perf_counter()
+    alg1.bool_product(b[:rows], c)
+    dt = time.perf_counter() - t
+    rows = int(min(inst.n, max(rows, rows * seconds_target / max(dt, 1e-6))))
+    t = time.perf_counter()
+    alg1.bool_product(b[:rows], c)
+    dt = time.perf_counter() - t
+    n = inst.n
+    return {"value": round(2.0 * rows * n * n / dt / 1e9, 3), "unit": "Gbitop/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"oracle Boolean product (float64 BLAS) of rows 0..{rows - 1} of T_A by T_B at n={n}, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--path", default="auto", choices=["auto", "bits", "mfma"])
+    ap.add_argument("--schedule", default="inplace", choices=["inplace", "jacobi"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on a single GPU "
+              "(one GPU's throughput is the value)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1707_01007_amd as cfpq
+    from workloads import configs
+
+    torch.cuda.set_device(0)
+    inst = configs.config3(args.n)
+    g = inst.grammar
+    edges = torch.from_numpy(inst.edges).cuda()
+    res = cfpq.closure(inst.n, edges, g, path=args.path, schedule=args.schedule)  # sizes buffers
+    out, ws = res.bits.view(-1), None
+    print(f"[bench] warmup {args.warmup} x closure n={inst.n} path={args.path}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        res = cfpq.closure(inst.n, edges, g, path=args.path, schedule=args.schedule, out=out)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        res = cfpq.closure(inst.n, edges, g, path=args.path, schedule=args.schedule, out=out, profile=True)
+        stats.append(res.stats)
+        print(f"[bench] step {k}: {res.stats['device_ms']:.1f} ms, {res.stats['iterations']} loops, "
+              f"{res.stats['products']} products", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bitops = sum(s["bitops"] for s in stats)
+    products = sum(s["products"] for s in stats)
+    prod_ms = sum(s["product_ms"] for s in stats)
+    path_used = {1: "bits", 2: "mfma"}[stats[-1]["path_used"]]
+    npad = cfpq.padded_rows(inst.n)
+    per_launch = 2.0 * npad ** 3
+    achieved_t = per_launch / (prod_ms / products / 1e3) / 1e12 if products else 0.0
+    if path_used == "mfma":
+        roof = {"bound": "mfma", "achieved": round(achieved_t, 1), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
+                "frac": round(achieved_t / PEAK_INT8_TOPS, 4), "traffic": None}
+    else:
+        roof = {"bound": "alu", "achieved": round(achieved_t, 1), "peak": round(PEAK_VALU_BITOPS_T, 1),
+                "unit": "TOP/s", "frac": round(achieved_t / PEAK_VALU_BITOPS_T, 4), "traffic": None}
+    roof["kernel"] = "mfma_product_kernel" if path_used == "mfma" else "bits_product_kernel"
+    roof["per_launch_bitops"] = per_launch
+    line = {
+        "metric": METRIC,
+        "value": round(bitops / wall / 1e9, 1),
+        "unit": "Gbitop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8" if path_used == "mfma" else "u32",
+        "data": "synthetic",
+        "config": {"workload": inst.tag, "n": inst.n, "edges": int(len(inst.edges)), "grammar": g.name,
+                   "path": path_used, "schedule": args.schedule,
+                   "loops_per_closure": stats[-1]["iterations"], "products_per_closure": stats[-1]["products"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(inst)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

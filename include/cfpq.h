@@ -1,0 +1,185 @@
+/*
+ * cfpq.h -- context-free path querying (relational semantics) on AMD gfx950.
+ *
+ * The library computes, for an edge-labelled graph D = (V, E) and a grammar
+ * G = (N, Sigma, P) in Chomsky normal form without start symbol or epsilon
+ * rules (section 2 of Azimov & Grigorev, "Context-Free Path Querying by Matrix
+ * Multiplication", EDBT 2018), the context-free relation
+ *     R_A = { (i, j) : some path i -> j spells a word derivable from A }
+ * for every nonterminal A.  It follows Algorithm 1 (section 4.2): initialise
+ * one Boolean matrix per nonterminal from the edges, then repeat
+ * T_A |= T_B x T_C for every rule A -> B C until no matrix changes.  Theorem 2
+ * (section 4.1) states that the fixpoint is exactly R.
+ *
+ * Conventions for every entry point:
+ *  - Ids are dense, 0-based int32: nodes 0..n-1, terminals 0..n_terminals-1,
+ *    nonterminals 0..n_nonterminals-1.
+ *  - Matrix layout ("bit layout"): a matrix is cfpq_padded_rows(n) rows of
+ *    cfpq_row_words(n) uint64 words; bit (j % 64) of word (j / 64) of row i is
+ *    1 iff (i, j) is in the relation.  The result buffer holds n_nonterminals
+ *    such matrices back to back.  Rows >= n and bits >= n are 0 on return.
+ *  - Memory: pointers named d_* are device memory owned by the caller; every
+ *    other pointer is host memory borrowed for the duration of the call.  The
+ *    library allocates no device memory inside cfpq_closure: its scratch space
+ *    is the caller's workspace.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    ordered on it.  cfpq_closure returns after the fixpoint is reached (it
+ *    reads a change flag back after every loop), so results and stats are
+ *    valid on return.
+ *  - Errors: every entry point returns a cfpq_status.  Argument errors are
+ *    reported before any device work; cfpq_last_error() gives a message for the
+ *    calling thread.  A HIP failure returns CFPQ_EDEVICE with the HIP error
+ *    text in the message.
+ */
+#ifndef CFPQ_H
+#define CFPQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFPQ_ABI_VERSION 1
+
+#if defined(__GNUC__)
+#define CFPQ_API __attribute__((visibility("default")))
+#else
+#define CFPQ_API
+#endif
+
+typedef enum {
+    CFPQ_OK = 0,
+    CFPQ_EINVAL = -1,     /* an argument is out of range or NULL */
+    CFPQ_ENOMEM = -2,     /* workspace or memory budget too small */
+    CFPQ_EDEVICE = -3,    /* a HIP call failed */
+    CFPQ_ENOTCONV = -4,   /* max_iters reached; the partial result is sound (a subset of R) */
+    CFPQ_EBUSY = -5,      /* no free slot (serving) */
+    CFPQ_ENOTREADY = -6   /* request still running (serving) */
+} cfpq_status;
+
+/* Edge (src, label, dst) of E (section 2).  Multi-edges and self-loops are allowed. */
+typedef struct { int32_t src, label, dst; } cfpq_edge;
+/* Production A -> x. */
+typedef struct { int32_t lhs, terminal; } cfpq_term_rule;
+/* Production A -> B C. */
+typedef struct { int32_t lhs, left, right; } cfpq_bin_rule;
+
+typedef struct {
+    int32_t n_nodes;           /* |V| >= 0 */
+    int32_t edges_on_device;   /* 0: `edges` is host memory; 1: device memory */
+    int64_t n_edges;           /* |E| >= 0 */
+    const cfpq_edge* edges;    /* n_edges records */
+} cfpq_graph;
+
+typedef struct {
+    int32_t n_nonterminals;    /* 1..CFPQ_MAX_NONTERMINALS */
+    int32_t n_terminals;       /* >= 0; every edge label must be below it */
+    int32_t n_term_rules;
+    int32_t n_bin_rules;
+    const cfpq_term_rule* term_rules;   /* host */
+    const cfpq_bin_rule* bin_rules;     /* host */
+} cfpq_grammar;
+
+#define CFPQ_MAX_NONTERMINALS 64
+#define CFPQ_MAX_NODES (1 << 20)
+
+enum { CFPQ_PATH_AUTO = 0, CFPQ_PATH_BITS = 1, CFPQ_PATH_MFMA = 2 };
+enum { CFPQ_SCHEDULE_INPLACE = 0, CFPQ_SCHEDULE_JACOBI = 1 };
+
+typedef struct {
+    int32_t path;            /* CFPQ_PATH_*: product kernel (AUTO = autotuned choice) */
+    int32_t schedule;        /* CFPQ_SCHEDULE_JACOBI: every product of a loop reads the
+                                matrices of the previous loop (Algorithm 1 exactly);
+                                CFPQ_SCHEDULE_INPLACE: products read the latest matrices
+                                (same fixpoint, usually fewer loops) */
+    int32_t dirty_worklist;  /* nonzero: a rule A -> B C runs in a loop only if B or C
+                                changed in the previous loop (all rules run in loop 1) */
+    int32_t profile;         /* nonzero: time every product with HIP events on `stream`
+                                (stats.product_ms); costs one event pair per product */
+    int64_t max_iters;       /* loop cap; 0 = |V|^2 |N| + 1 (Theorem 3's bound) */
+} cfpq_options;
+
+typedef struct {
+    int64_t iterations;      /* loop executions, including the final one that changed nothing */
+    int64_t products;        /* Boolean products executed */
+    double bitops;           /* 2 * npad^3 per executed product, npad = cfpq_padded_rows(n) */
+    double device_ms;        /* device time from matrix initialisation to the last flag */
+    double product_ms;       /* summed duration of the product kernels (options.profile), else 0 */
+    int32_t path_used;       /* CFPQ_PATH_BITS or CFPQ_PATH_MFMA */
+    int32_t converged;       /* 1 if the fixpoint was reached */
+} cfpq_stats;
+
+/* ABI version of the loaded library (CFPQ_ABI_VERSION). */
+CFPQ_API int32_t cfpq_abi_version(void);
+
+/* Message for the last error on the calling thread ("" if none).  The pointer
+ * stays valid until the next call on this thread. */
+CFPQ_API const char* cfpq_last_error(void);
+
+/* Fill `opt` with defaults: AUTO path, in-place schedule, dirty worklist on. */
+CFPQ_API void cfpq_default_options(cfpq_options* opt);
+
+/* Words per matrix row: ceil(n/64) rounded up to a multiple of 4 (n >= 0). */
+CFPQ_API int64_t cfpq_row_words(int32_t n_nodes);
+
+/* Rows per matrix: 64 * cfpq_row_words(n) (the padded matrix is square). */
+CFPQ_API int64_t cfpq_padded_rows(int32_t n_nodes);
+
+/* Bytes of the result buffer: n_nonterminals * padded_rows * row_words * 8. */
+CFPQ_API size_t cfpq_result_bytes(int32_t n_nodes, int32_t n_nonterminals);
+
+/* Workspace bytes that cfpq_closure needs for this graph size, grammar and
+ * options (it depends on n_edges only through edges copied from the host).
+ * Returns CFPQ_EINVAL for invalid arguments. */
+CFPQ_API cfpq_status cfpq_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* grammar,
+                                 const cfpq_options* opt, size_t* bytes);
+
+/*
+ * Relational CFPQ closure (Algorithm 1, section 4.2).
+ *   graph, grammar   inputs as above (validated on the host; with
+ *                    edges_on_device = 1 the edge ids are checked by the
+ *                    initialisation kernel and an out-of-range edge makes the
+ *                    call return CFPQ_EINVAL before any product runs)
+ *   opt              NULL = cfpq_default_options
+ *   stream           hipStream_t or NULL
+ *   d_workspace      device scratch of at least cfpq_workspace_bytes bytes
+ *   d_result         device buffer of cfpq_result_bytes bytes; overwritten with
+ *                    R in the bit layout
+ *   stats            optional (NULL allowed)
+ * Returns CFPQ_OK, CFPQ_ENOTCONV (max_iters reached, d_result is a sound
+ * subset of R), CFPQ_EINVAL, CFPQ_ENOMEM (workspace too small) or CFPQ_EDEVICE.
+ */
+CFPQ_API cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar,
+                         const cfpq_options* opt, void* stream,
+                         void* d_workspace, size_t workspace_bytes,
+                         uint64_t* d_result, cfpq_stats* stats);
+
+/*
+ * One Boolean matrix product with union (the product of section 2 for a
+ * single rule A -> B C, fused with the union of Algorithm 1):
+ *     d_a |= d_b x d_c,   P_ij = OR_k (b_ik AND c_kj)
+ * All three are npad x npad matrices in the bit layout for `n_nodes`.  d_a may
+ * alias d_b and/or d_c (the in-place update; bits are only ever set, so every
+ * value read is a subset of the final one).  path = CFPQ_PATH_BITS or
+ * CFPQ_PATH_MFMA (AUTO picks one).  If d_changed is not NULL, *d_changed
+ * (device int32) is OR-ed with 1 when d_a gained a bit.  d_workspace may be
+ * NULL for the BITS path; the MFMA path needs cfpq_product_workspace_bytes.
+ */
+CFPQ_API size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path);
+CFPQ_API cfpq_status cfpq_product(int32_t n_nodes, int32_t path, const uint64_t* d_b, const uint64_t* d_c,
+                         uint64_t* d_a, int32_t* d_changed, void* d_workspace,
+                         size_t workspace_bytes, void* stream);
+
+/* Number of set bits of each of `count` consecutive matrices of the bit
+ * layout for n_nodes (|R_A| per nonterminal for a result buffer), written to
+ * the device array d_counts[count].  Stream-ordered; does not synchronise. */
+CFPQ_API cfpq_status cfpq_popcount(int32_t n_nodes, int32_t count, const uint64_t* d_mats,
+                          unsigned long long* d_counts, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CFPQ_H */

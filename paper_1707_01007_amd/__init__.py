@@ -1,0 +1,178 @@
+"""Context-free path querying (relational semantics) on AMD gfx950.
+
+Python face of the C ABI in ``include/cfpq.h``.  PyTorch provides device
+memory and the stream; every step of the query (matrix initialisation,
+products, unions, change detection) runs in the HIP library ``libcfpq.so``.
+There is no fallback: if the library is missing, importing the binding's
+functions raises.
+
+    import paper_1707_01007_amd as cfpq
+    res = cfpq.closure(n, edges, grammar)          # edges: int32 [m, 3] (src, label, dst)
+    bits = cfpq.result_bits(res)                   # numpy uint64 [|N|, n, ceil(n/64)]
+
+A grammar is any object with ``n_nonterminals``, ``n_terminals``, ``term``
+(pairs (A, x) for A -> x) and ``bin`` (triples (A, B, C) for A -> B C).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import (CfpqError, PATH_AUTO, PATH_BITS, PATH_MFMA, SCHEDULE_INPLACE,  # noqa: F401
+                   SCHEDULE_JACOBI)
+
+_PATHS = {"auto": PATH_AUTO, "bits": PATH_BITS, "mfma": PATH_MFMA}
+_SCHEDULES = {"inplace": SCHEDULE_INPLACE, "jacobi": SCHEDULE_JACOBI}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def lib():
+    return _abi.load()
+
+
+def row_words(n: int) -> int:
+    return int(lib().cfpq_row_words(n))
+
+
+def padded_rows(n: int) -> int:
+    return int(lib().cfpq_padded_rows(n))
+
+
+def _grammar_struct(grammar):
+    term = list(grammar.term)
+    binr = list(grammar.bin)
+    t_arr = (_abi.TermRule * max(1, len(term)))(*[_abi.TermRule(int(a), int(x)) for a, x in term])
+    b_arr = (_abi.BinRule * max(1, len(binr)))(*[_abi.BinRule(int(a), int(b), int(c)) for a, b, c in binr])
+    g = _abi.Grammar(int(grammar.n_nonterminals), int(grammar.n_terminals), len(term), len(binr),
+                     ctypes.cast(t_arr, ctypes.POINTER(_abi.TermRule)),
+                     ctypes.cast(b_arr, ctypes.POINTER(_abi.BinRule)))
+    return g, (t_arr, b_arr)
+
+
+def _options(path="auto", schedule="inplace", dirty=True, max_iters=0, profile=False):
+    o = _abi.Options()
+    lib().cfpq_default_options(ctypes.byref(o))
+    o.profile = 1 if profile else 0
+    o.path = _PATHS[path] if isinstance(path, str) else int(path)
+    o.schedule = _SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+    o.dirty_worklist = 1 if dirty else 0
+    o.max_iters = int(max_iters)
+    return o
+
+
+@dataclass
+class Result:
+    n: int
+    n_nonterminals: int
+    bits: "object"           # torch.int64 tensor [|N|, npad, W] on the device (uint64 bit rows)
+    stats: dict
+    status: int
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=True, max_iters=0,
+            device=None, stream=None, out=None, workspace=None, allow_partial=False,
+            profile=False) -> Result:
+    """Relational CFPQ closure (Algorithm 1) through ``cfpq_closure``.
+
+    ``edges`` is an int32 array [m, 3] of (src, label, dst) on the host, or an
+    int32 CUDA tensor of that shape (then checked on the device).  Returns a
+    ``Result`` whose ``bits`` hold R_A for every nonterminal in the library's
+    bit layout.  Raises ``CfpqError`` on any error (``allow_partial`` accepts
+    CFPQ_ENOTCONV and returns the sound partial result)."""
+    torch = _torch()
+    L = lib()
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    g, keep = _grammar_struct(grammar)
+    if isinstance(edges, torch.Tensor) and edges.is_cuda:
+        e_dev = edges.to(torch.int32).contiguous().view(-1, 3)
+        graph = _abi.Graph(int(n), 1, int(e_dev.shape[0]), ctypes.c_void_p(e_dev.data_ptr()))
+        e_host = None
+    else:
+        e_host = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
+        graph = _abi.Graph(int(n), 0, int(e_host.shape[0]), ctypes.c_void_p(e_host.ctypes.data))
+    opt = _options(path, schedule, dirty, max_iters, profile)
+    need = ctypes.c_size_t(0)
+    _abi.check(L.cfpq_workspace_bytes(ctypes.byref(graph), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(need)))
+    res_words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8
+    npad, W = padded_rows(n), row_words(n)
+    if out is None:
+        out = torch.empty(res_words, dtype=torch.int64, device=device)
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=device)
+    st = _abi.Stats()
+    status = L.cfpq_closure(ctypes.byref(graph), ctypes.byref(g), ctypes.byref(opt), _stream_ptr(stream),
+                            ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()),
+                            ctypes.c_void_p(out.data_ptr()), ctypes.byref(st))
+    del keep, e_host
+    if status != _abi.CFPQ_OK and not (allow_partial and status == _abi.CFPQ_ENOTCONV):
+        _abi.check(status)
+    bits = out.view(int(grammar.n_nonterminals), npad, W)
+    return Result(int(n), int(grammar.n_nonterminals), bits, st.as_dict(), status)
+
+
+def result_bits(res: Result) -> np.ndarray:
+    """Copy the result to the host as uint64 [|N|, n, ceil(n/64)] (padding
+    stripped) -- the same layout the oracle returns."""
+    w = max(1, (res.n + 63) // 64)
+    host = res.bits[:, : res.n, :w].contiguous().cpu().numpy()
+    return host.view(np.uint64)
+
+
+def product(n: int, b, c, a, *, path="bits", changed=None, workspace=None, stream=None):
+    """``a |= b x c`` on device matrices in the bit layout (``cfpq_product``).
+    Returns the device int32 change flag."""
+    torch = _torch()
+    L = lib()
+    p = _PATHS[path] if isinstance(path, str) else int(path)
+    if changed is None:
+        changed = torch.zeros(1, dtype=torch.int32, device=a.device)
+    need = int(L.cfpq_product_workspace_bytes(int(n), p))
+    if need and (workspace is None or workspace.numel() < need):
+        workspace = torch.empty(need, dtype=torch.uint8, device=a.device)
+    ws_ptr = workspace.data_ptr() if workspace is not None else 0
+    ws_len = workspace.numel() if workspace is not None else 0
+    _abi.check(L.cfpq_product(int(n), p, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                              ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(changed.data_ptr()),
+                              ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_len), _stream_ptr(stream)))
+    return changed
+
+
+def popcount(n: int, mats, count: int, stream=None):
+    """Set bits per matrix for ``count`` matrices (``cfpq_popcount``); returns
+    a host list of ints."""
+    torch = _torch()
+    counts = torch.zeros(count, dtype=torch.int64, device=mats.device)
+    _abi.check(lib().cfpq_popcount(int(n), int(count), ctypes.c_void_p(mats.data_ptr()),
+                                   ctypes.c_void_p(counts.data_ptr()), _stream_ptr(stream)))
+    return [int(x) for x in counts.cpu().tolist()]
+
+
+def new_matrices(n: int, count: int, device=None):
+    """Zeroed device buffer for ``count`` matrices, shaped [count, npad, W]."""
+    torch = _torch()
+    return torch.zeros((count, padded_rows(n), row_words(n)), dtype=torch.int64,
+                       device=device if device is not None else "cuda")
+
+
+def upload_bits(n: int, host_bits: np.ndarray, device=None):
+    """Host uint64 [count, n, ceil(n/64)] -> device [count, npad, W] (zero padded)."""
+    torch = _torch()
+    host_bits = np.asarray(host_bits, dtype=np.uint64)
+    count = host_bits.shape[0]
+    buf = np.zeros((count, padded_rows(n), row_words(n)), dtype=np.uint64)
+    buf[:, :n, : host_bits.shape[2]] = host_bits
+    return torch.from_numpy(buf.view(np.int64)).to(device if device is not None else "cuda")

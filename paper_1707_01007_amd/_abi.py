@@ -1,0 +1,110 @@
+"""ctypes declarations of the C ABI in ``include/cfpq.h`` (argument
+marshalling only; every step of the query runs in the HIP library)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcfpq.so")
+
+CFPQ_OK, CFPQ_EINVAL, CFPQ_ENOMEM, CFPQ_EDEVICE, CFPQ_ENOTCONV, CFPQ_EBUSY, CFPQ_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
+PATH_AUTO, PATH_BITS, PATH_MFMA = 0, 1, 2
+SCHEDULE_INPLACE, SCHEDULE_JACOBI = 0, 1
+STATUS_NAMES = {0: "CFPQ_OK", -1: "CFPQ_EINVAL", -2: "CFPQ_ENOMEM", -3: "CFPQ_EDEVICE",
+                -4: "CFPQ_ENOTCONV", -5: "CFPQ_EBUSY", -6: "CFPQ_ENOTREADY"}
+
+EXPORTED = (
+    "cfpq_abi_version", "cfpq_last_error", "cfpq_default_options", "cfpq_row_words",
+    "cfpq_padded_rows", "cfpq_result_bytes", "cfpq_workspace_bytes", "cfpq_closure",
+    "cfpq_product_workspace_bytes", "cfpq_product", "cfpq_popcount",
+)
+
+
+class Edge(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int32), ("label", ctypes.c_int32), ("dst", ctypes.c_int32)]
+
+
+class TermRule(ctypes.Structure):
+    _fields_ = [("lhs", ctypes.c_int32), ("terminal", ctypes.c_int32)]
+
+
+class BinRule(ctypes.Structure):
+    _fields_ = [("lhs", ctypes.c_int32), ("left", ctypes.c_int32), ("right", ctypes.c_int32)]
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("edges_on_device", ctypes.c_int32),
+                ("n_edges", ctypes.c_int64), ("edges", ctypes.c_void_p)]
+
+
+class Grammar(ctypes.Structure):
+    _fields_ = [("n_nonterminals", ctypes.c_int32), ("n_terminals", ctypes.c_int32),
+                ("n_term_rules", ctypes.c_int32), ("n_bin_rules", ctypes.c_int32),
+                ("term_rules", ctypes.POINTER(TermRule)), ("bin_rules", ctypes.POINTER(BinRule))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("schedule", ctypes.c_int32), ("dirty_worklist", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("max_iters", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("products", ctypes.c_int64), ("bitops", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("product_ms", ctypes.c_double), ("path_used", ctypes.c_int32),
+                ("converged", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+class CfpqError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library.  Raises if it has not been built: there is no
+    fallback implementation."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing; build it with `python -m paper_1707_01007_amd.build`")
+    lib = ctypes.CDLL(path)
+    i32, i64, p, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    lib.cfpq_abi_version.restype = i32
+    lib.cfpq_last_error.restype = ctypes.c_char_p
+    lib.cfpq_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.cfpq_row_words.argtypes = [i32]
+    lib.cfpq_row_words.restype = i64
+    lib.cfpq_padded_rows.argtypes = [i32]
+    lib.cfpq_padded_rows.restype = i64
+    lib.cfpq_result_bytes.argtypes = [i32, i32]
+    lib.cfpq_result_bytes.restype = sz
+    lib.cfpq_workspace_bytes.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar),
+                                         ctypes.POINTER(Options), ctypes.POINTER(sz)]
+    lib.cfpq_workspace_bytes.restype = ctypes.c_int
+    lib.cfpq_closure.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar), ctypes.POINTER(Options),
+                                 p, p, sz, p, ctypes.POINTER(Stats)]
+    lib.cfpq_closure.restype = ctypes.c_int
+    lib.cfpq_product_workspace_bytes.argtypes = [i32, i32]
+    lib.cfpq_product_workspace_bytes.restype = sz
+    lib.cfpq_product.argtypes = [i32, i32, p, p, p, p, p, sz, p]
+    lib.cfpq_product.restype = ctypes.c_int
+    lib.cfpq_popcount.argtypes = [i32, i32, p, p, p]
+    lib.cfpq_popcount.restype = ctypes.c_int
+    if lib.cfpq_abi_version() != 1:
+        raise ImportError("libcfpq ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != CFPQ_OK:
+        msg = _lib.cfpq_last_error().decode() if _lib is not None else ""
+        raise CfpqError(status, msg)

@@ -1,0 +1,62 @@
+// Internal declarations shared by the kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "cfpq.h"
+
+namespace cfpq {
+
+// Bit layout of one matrix: npad rows of W uint64 words, npad = 64 * W, W a
+// multiple of 4, so a padded matrix is square and both sides are multiples of
+// 256.  Bit j % 64 of word j / 64 of row i holds entry (i, j).
+struct Layout {
+    int32_t n = 0;
+    int64_t W = 0;          // uint64 words per row
+    int64_t npad = 0;       // rows (= columns) after padding
+    int64_t mat_words = 0;  // uint64 words per matrix
+};
+
+inline Layout layout_for(int32_t n) {
+    Layout L;
+    L.n = n;
+    int64_t w = (static_cast<int64_t>(n) + 63) / 64;
+    if (w < 1) w = 1;
+    L.W = (w + 3) / 4 * 4;
+    L.npad = 64 * L.W;
+    L.mat_words = L.npad * L.W;
+    return L;
+}
+
+// ---- kernels (each launcher only enqueues work on `s`) ----
+
+// Fill `words` uint64 with zero by a kernel (safe inside captured graphs).
+hipError_t launch_zero(uint64_t* p, size_t words, hipStream_t s);
+
+// Matrix initialisation of Algorithm 1: for every edge (i, x, j) and every
+// rule A -> x, set bit (i, j) of matrix A.  Term rules are given as CSR over
+// terminals: lhs ids term_lhs[term_off[x] .. term_off[x+1]).  Edges with an id
+// out of range are skipped and counted in *bad.
+hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t* term_off,
+                               const int32_t* term_lhs, int32_t n_terminals, int32_t n,
+                               uint64_t* T, const Layout& L, int32_t* bad, hipStream_t s);
+
+// A |= B x C on the VALU: AND/OR over bit-packed rows.
+hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L,
+                               int32_t* changed, hipStream_t s);
+
+// A |= B x C on the int8 matrix cores; CT is the transpose of C.
+hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
+                               int32_t* changed, hipStream_t s);
+
+// dst = transpose(src) (bit matrix, npad x npad).
+hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s);
+
+// counts[m] = number of set bits of matrix m (count matrices), added to counts.
+hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,
+                           unsigned long long* counts, hipStream_t s);
+
+}  // namespace cfpq

@@ -1,0 +1,409 @@
+// Host driver and C ABI: the fixpoint loop of Algorithm 1 (section 4.2).
+//
+//   initialise T_A from the edges (matrix initialisation),
+//   repeat: for every rule A -> B C: T_A |= T_B x T_C
+//   until a loop changes no matrix ("while matrix T is changing").
+//
+// Schedules.  JACOBI reads every operand from the matrices of the previous
+// loop, exactly Algorithm 1's T <- T u (T x T): two buffers X (read) and Y
+// (written); Y starts as a copy of X, products OR into Y, and after the loop
+// the nonterminals that changed are copied back so X == Y again before the
+// buffers swap roles.  INPLACE reads and writes one buffer, so a product sees
+// bits set earlier in the same loop.  Both only ever add true facts, so both
+// reach the same least fixpoint (Theorem 3's monotonicity); only the loop
+// count differs.
+//
+// Dirty-rule worklist.  A rule A -> B C must run again only if B or C gained
+// bits since it last read them.  Every product of loop t reads operands whose
+// changes up to loop t-1 are complete, so "B or C changed in loop t-1" (or
+// t = 1) is a sufficient condition; a loop with no change anywhere proves the
+// fixpoint because then every rule ran on final operands or was clean.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cfpq_internal.h"
+
+namespace cfpq {
+
+thread_local std::string g_last_error;
+
+cfpq_status fail(cfpq_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+#define CFPQ_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(CFPQ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+cfpq_status validate_grammar(const cfpq_grammar* g) {
+    if (!g) return fail(CFPQ_EINVAL, "grammar is NULL");
+    if (g->n_nonterminals < 1 || g->n_nonterminals > CFPQ_MAX_NONTERMINALS)
+        return fail(CFPQ_EINVAL, "n_nonterminals must be in 1.." + std::to_string(CFPQ_MAX_NONTERMINALS));
+    if (g->n_terminals < 0 || g->n_term_rules < 0 || g->n_bin_rules < 0)
+        return fail(CFPQ_EINVAL, "negative grammar size");
+    if (g->n_term_rules > 0 && !g->term_rules) return fail(CFPQ_EINVAL, "term_rules is NULL");
+    if (g->n_bin_rules > 0 && !g->bin_rules) return fail(CFPQ_EINVAL, "bin_rules is NULL");
+    for (int32_t r = 0; r < g->n_term_rules; ++r) {
+        const auto& t = g->term_rules[r];
+        if (t.lhs < 0 || t.lhs >= g->n_nonterminals || t.terminal < 0 || t.terminal >= g->n_terminals)
+            return fail(CFPQ_EINVAL, "term rule " + std::to_string(r) + " has an id out of range");
+    }
+    for (int32_t r = 0; r < g->n_bin_rules; ++r) {
+        const auto& b = g->bin_rules[r];
+        if (b.lhs < 0 || b.lhs >= g->n_nonterminals || b.left < 0 || b.left >= g->n_nonterminals ||
+            b.right < 0 || b.right >= g->n_nonterminals)
+            return fail(CFPQ_EINVAL, "binary rule " + std::to_string(r) + " has an id out of range");
+    }
+    return CFPQ_OK;
+}
+
+cfpq_status validate_graph(const cfpq_graph* g, const cfpq_grammar* gr) {
+    if (!g) return fail(CFPQ_EINVAL, "graph is NULL");
+    if (g->n_nodes < 0 || g->n_nodes > CFPQ_MAX_NODES)
+        return fail(CFPQ_EINVAL, "n_nodes must be in 0.." + std::to_string(CFPQ_MAX_NODES));
+    if (g->n_edges < 0) return fail(CFPQ_EINVAL, "n_edges is negative");
+    if (g->n_edges > 0 && !g->edges) return fail(CFPQ_EINVAL, "edges is NULL");
+    if (g->edges_on_device != 0 && g->edges_on_device != 1)
+        return fail(CFPQ_EINVAL, "edges_on_device must be 0 or 1");
+    if (!g->edges_on_device) {
+        for (int64_t e = 0; e < g->n_edges; ++e) {
+            const auto& ed = g->edges[e];
+            if (ed.src < 0 || ed.src >= g->n_nodes || ed.dst < 0 || ed.dst >= g->n_nodes ||
+                ed.label < 0 || ed.label >= gr->n_terminals)
+                return fail(CFPQ_EINVAL, "edge " + std::to_string(e) + " has an id out of range");
+        }
+    }
+    return CFPQ_OK;
+}
+
+cfpq_options resolve(const cfpq_options* opt) {
+    cfpq_options o;
+    cfpq_default_options(&o);
+    if (opt) o = *opt;
+    return o;
+}
+
+// Workspace carve-up (all offsets 256-byte aligned).
+struct Plan {
+    Layout L;
+    int32_t n_nt = 0;
+    int32_t path = CFPQ_PATH_BITS;
+    bool jacobi = false;
+    std::vector<int32_t> right_slot;  // per nonterminal: transpose slot or -1
+    int32_t n_right = 0;
+    size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0;
+    size_t off_second = 0, off_trans = 0, total = 0;
+};
+
+int32_t choose_path(const Layout& L, int32_t requested) {
+    if (requested == CFPQ_PATH_BITS || requested == CFPQ_PATH_MFMA) return requested;
+    (void)L;
+    return CFPQ_PATH_BITS;
+}
+
+Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& o) {
+    Plan p;
+    p.L = layout_for(g->n_nodes);
+    p.n_nt = gr->n_nonterminals;
+    p.path = choose_path(p.L, o.path);
+    p.jacobi = o.schedule == CFPQ_SCHEDULE_JACOBI;
+    p.right_slot.assign(p.n_nt, -1);
+    if (p.path == CFPQ_PATH_MFMA) {
+        for (int32_t r = 0; r < gr->n_bin_rules; ++r) {
+            int32_t c = gr->bin_rules[r].right;
+            if (p.right_slot[c] < 0) p.right_slot[c] = p.n_right++;
+        }
+    }
+    const size_t mat_bytes = static_cast<size_t>(p.L.mat_words) * 8;
+    size_t off = 0;
+    p.off_edges = off;
+    if (!g->edges_on_device) off += align_up(static_cast<size_t>(g->n_edges) * sizeof(cfpq_edge), 256);
+    p.off_term_off = off;
+    off += align_up(static_cast<size_t>(gr->n_terminals + 1) * 4, 256);
+    p.off_term_lhs = off;
+    off += align_up(static_cast<size_t>(std::max(gr->n_term_rules, 1)) * 4, 256);
+    p.off_flags = off;
+    off += align_up(static_cast<size_t>(p.n_nt) * 4, 256);
+    p.off_bad = off;
+    off += 256;
+    p.off_second = off;
+    if (p.jacobi) off += mat_bytes * p.n_nt;
+    p.off_trans = off;
+    off += mat_bytes * p.n_right;
+    p.total = off;
+    return p;
+}
+
+}  // namespace
+}  // namespace cfpq
+
+using namespace cfpq;
+
+extern "C" {
+
+int32_t cfpq_abi_version(void) { return CFPQ_ABI_VERSION; }
+
+const char* cfpq_last_error(void) { return g_last_error.c_str(); }
+
+void cfpq_default_options(cfpq_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->path = CFPQ_PATH_AUTO;
+    opt->schedule = CFPQ_SCHEDULE_INPLACE;
+    opt->dirty_worklist = 1;
+    opt->max_iters = 0;
+}
+
+int64_t cfpq_row_words(int32_t n_nodes) { return layout_for(n_nodes < 0 ? 0 : n_nodes).W; }
+
+int64_t cfpq_padded_rows(int32_t n_nodes) { return layout_for(n_nodes < 0 ? 0 : n_nodes).npad; }
+
+size_t cfpq_result_bytes(int32_t n_nodes, int32_t n_nonterminals) {
+    if (n_nonterminals < 0) return 0;
+    return static_cast<size_t>(layout_for(n_nodes < 0 ? 0 : n_nodes).mat_words) * 8 *
+           static_cast<size_t>(n_nonterminals);
+}
+
+cfpq_status cfpq_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* grammar,
+                                 const cfpq_options* opt, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(CFPQ_EINVAL, "bytes is NULL");
+    cfpq_status st = validate_grammar(grammar);
+    if (st != CFPQ_OK) return st;
+    if (!graph) return fail(CFPQ_EINVAL, "graph is NULL");
+    if (graph->n_nodes < 0 || graph->n_nodes > CFPQ_MAX_NODES || graph->n_edges < 0)
+        return fail(CFPQ_EINVAL, "graph size out of range");
+    *bytes = make_plan(graph, grammar, resolve(opt)).total;
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, const cfpq_options* opt,
+                         void* stream, void* d_workspace, size_t workspace_bytes, uint64_t* d_result,
+                         cfpq_stats* stats) {
+    g_last_error.clear();
+    cfpq_status st = validate_grammar(grammar);
+    if (st != CFPQ_OK) return st;
+    st = validate_graph(graph, grammar);
+    if (st != CFPQ_OK) return st;
+    if (!d_result) return fail(CFPQ_EINVAL, "d_result is NULL");
+    const cfpq_options o = resolve(opt);
+    if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_MFMA) return fail(CFPQ_EINVAL, "unknown path");
+    if (o.schedule != CFPQ_SCHEDULE_INPLACE && o.schedule != CFPQ_SCHEDULE_JACOBI)
+        return fail(CFPQ_EINVAL, "unknown schedule");
+    if (o.max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
+    const Plan p = make_plan(graph, grammar, o);
+    if (p.total > 0 && !d_workspace) return fail(CFPQ_EINVAL, "d_workspace is NULL");
+    if (workspace_bytes < p.total)
+        return fail(CFPQ_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(d_workspace);
+    const Layout& L = p.L;
+    const size_t mat_words = static_cast<size_t>(L.mat_words);
+    const int32_t n_nt = p.n_nt;
+
+    // Term rules as CSR over terminals (host), then one copy.
+    std::vector<int32_t> term_off(grammar->n_terminals + 1, 0), term_lhs(std::max(grammar->n_term_rules, 1), 0);
+    for (int32_t r = 0; r < grammar->n_term_rules; ++r) term_off[grammar->term_rules[r].terminal + 1]++;
+    for (int32_t x = 0; x < grammar->n_terminals; ++x) term_off[x + 1] += term_off[x];
+    {
+        std::vector<int32_t> fill(term_off.begin(), term_off.end() - 1);
+        for (int32_t r = 0; r < grammar->n_term_rules; ++r)
+            term_lhs[fill[grammar->term_rules[r].terminal]++] = grammar->term_rules[r].lhs;
+    }
+    auto* d_term_off = reinterpret_cast<int32_t*>(ws + p.off_term_off);
+    auto* d_term_lhs = reinterpret_cast<int32_t*>(ws + p.off_term_lhs);
+    auto* d_flags = reinterpret_cast<int32_t*>(ws + p.off_flags);
+    auto* d_bad = reinterpret_cast<int32_t*>(ws + p.off_bad);
+    const cfpq_edge* d_edges = graph->edges;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    CFPQ_HIP(hipEventCreate(&ev0));
+    CFPQ_HIP(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); }
+    } guard{ev0, ev1};
+
+    CFPQ_HIP(hipMemcpyAsync(d_term_off, term_off.data(), term_off.size() * 4, hipMemcpyHostToDevice, s));
+    CFPQ_HIP(hipMemcpyAsync(d_term_lhs, term_lhs.data(), term_lhs.size() * 4, hipMemcpyHostToDevice, s));
+    if (!graph->edges_on_device && graph->n_edges > 0) {
+        auto* dst = reinterpret_cast<cfpq_edge*>(ws + p.off_edges);
+        CFPQ_HIP(hipMemcpyAsync(dst, graph->edges, static_cast<size_t>(graph->n_edges) * sizeof(cfpq_edge),
+                                hipMemcpyHostToDevice, s));
+        d_edges = dst;
+    }
+    CFPQ_HIP(hipMemsetAsync(d_bad, 0, 4, s));
+    CFPQ_HIP(hipEventRecord(ev0, s));
+
+    // Matrix initialisation.
+    uint64_t* X = d_result;
+    uint64_t* Y = p.jacobi ? reinterpret_cast<uint64_t*>(ws + p.off_second) : d_result;
+    uint64_t* TT = reinterpret_cast<uint64_t*>(ws + p.off_trans);
+    CFPQ_HIP(launch_zero(X, mat_words * n_nt, s));
+    CFPQ_HIP(launch_init_scatter(d_edges, graph->n_edges, d_term_off, d_term_lhs, grammar->n_terminals,
+                                 graph->n_nodes, X, L, d_bad, s));
+    if (graph->edges_on_device) {
+        int32_t bad = 0;
+        CFPQ_HIP(hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipStreamSynchronize(s));
+        if (bad) return fail(CFPQ_EINVAL, std::to_string(bad) + " device edges have an id out of range");
+    }
+    if (p.jacobi) CFPQ_HIP(hipMemcpyAsync(Y, X, mat_words * 8 * n_nt, hipMemcpyDeviceToDevice, s));
+    for (int32_t a = 0; a < n_nt; ++a)
+        if (p.right_slot[a] >= 0)
+            CFPQ_HIP(launch_transpose(X + a * mat_words, TT + p.right_slot[a] * mat_words, L, s));
+
+    // Optional per-product timing: an event pair around every product.
+    std::vector<hipEvent_t> pev;
+    struct PevGuard {
+        std::vector<hipEvent_t>& v;
+        ~PevGuard() { for (auto e : v) hipEventDestroy(e); }
+    } pguard{pev};
+    auto product_event = [&](size_t idx) -> hipEvent_t {
+        while (pev.size() <= idx) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pev.push_back(e);
+        }
+        return pev[idx];
+    };
+    double product_ms = 0.0;
+
+    const int64_t nn = static_cast<int64_t>(graph->n_nodes);
+    const int64_t cap = o.max_iters > 0 ? o.max_iters : nn * nn * n_nt + 1;
+    std::vector<int32_t> prev(n_nt, 1), flags(n_nt, 0);
+    int64_t iters = 0, products = 0;
+    bool converged = false;
+    const bool any_rules = grammar->n_bin_rules > 0 && graph->n_nodes > 0;
+    if (!any_rules) converged = true;
+    while (!converged && iters < cap) {
+        CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
+        size_t launched = 0;
+        for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
+            const auto& br = grammar->bin_rules[r];
+            if (o.dirty_worklist && iters > 0 && !prev[br.left] && !prev[br.right]) continue;
+            const uint64_t* Bm = X + br.left * mat_words;
+            uint64_t* Am = Y + br.lhs * mat_words;
+            if (o.profile) {
+                hipEvent_t e = product_event(2 * launched);
+                if (!e) return fail(CFPQ_EDEVICE, "hipEventCreate failed");
+                CFPQ_HIP(hipEventRecord(e, s));
+            }
+            if (p.path == CFPQ_PATH_MFMA) {
+                const uint64_t* CT = TT + p.right_slot[br.right] * mat_words;
+                CFPQ_HIP(launch_mfma_product(Bm, CT, Am, L, d_flags + br.lhs, s));
+            } else {
+                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, d_flags + br.lhs, s));
+            }
+            if (o.profile) {
+                hipEvent_t e = product_event(2 * launched + 1);
+                if (!e) return fail(CFPQ_EDEVICE, "hipEventCreate failed");
+                CFPQ_HIP(hipEventRecord(e, s));
+            }
+            ++launched;
+            ++products;
+        }
+        CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipStreamSynchronize(s));
+        for (size_t q = 0; o.profile && q < launched; ++q) {
+            float pm = 0.f;
+            CFPQ_HIP(hipEventElapsedTime(&pm, pev[2 * q], pev[2 * q + 1]));
+            product_ms += pm;
+        }
+        ++iters;
+        bool any = false;
+        for (int32_t a = 0; a < n_nt; ++a) any = any || flags[a] != 0;
+        if (!any) {
+            converged = true;
+            break;
+        }
+        for (int32_t a = 0; a < n_nt; ++a) {
+            if (!flags[a]) continue;
+            if (p.jacobi)
+                CFPQ_HIP(hipMemcpyAsync(X + a * mat_words, Y + a * mat_words, mat_words * 8,
+                                        hipMemcpyDeviceToDevice, s));
+            if (p.right_slot[a] >= 0)
+                CFPQ_HIP(launch_transpose(Y + a * mat_words, TT + p.right_slot[a] * mat_words, L, s));
+        }
+        if (p.jacobi) std::swap(X, Y);
+        prev = flags;
+    }
+    // In Jacobi mode X == Y after the last loop; make sure d_result holds it.
+    if (p.jacobi && X != d_result)
+        CFPQ_HIP(hipMemcpyAsync(d_result, X, mat_words * 8 * n_nt, hipMemcpyDeviceToDevice, s));
+    CFPQ_HIP(hipEventRecord(ev1, s));
+    CFPQ_HIP(hipEventSynchronize(ev1));
+    float ms = 0.f;
+    CFPQ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    if (stats) {
+        stats->iterations = iters;
+        stats->products = products;
+        stats->bitops = 2.0 * static_cast<double>(L.npad) * static_cast<double>(L.npad) *
+                        static_cast<double>(L.npad) * static_cast<double>(products);
+        stats->device_ms = ms;
+        stats->product_ms = product_ms;
+        stats->path_used = p.path;
+        stats->converged = converged ? 1 : 0;
+    }
+    if (!converged) return fail(CFPQ_ENOTCONV, "max_iters reached before the fixpoint");
+    return CFPQ_OK;
+}
+
+size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path) {
+    if (path != CFPQ_PATH_MFMA) return 0;
+    return static_cast<size_t>(layout_for(n_nodes < 0 ? 0 : n_nodes).mat_words) * 8;
+}
+
+cfpq_status cfpq_product(int32_t n_nodes, int32_t path, const uint64_t* d_b, const uint64_t* d_c,
+                         uint64_t* d_a, int32_t* d_changed, void* d_workspace, size_t workspace_bytes,
+                         void* stream) {
+    g_last_error.clear();
+    if (n_nodes < 0 || n_nodes > CFPQ_MAX_NODES) return fail(CFPQ_EINVAL, "n_nodes out of range");
+    if (!d_b || !d_c || !d_a) return fail(CFPQ_EINVAL, "matrix pointer is NULL");
+    if (path == CFPQ_PATH_AUTO) path = CFPQ_PATH_BITS;
+    if (path != CFPQ_PATH_BITS && path != CFPQ_PATH_MFMA) return fail(CFPQ_EINVAL, "unknown path");
+    const Layout L = layout_for(n_nodes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t* flag = d_changed;
+    if (path == CFPQ_PATH_MFMA) {
+        if (workspace_bytes < cfpq_product_workspace_bytes(n_nodes, path) || !d_workspace)
+            return fail(CFPQ_ENOMEM, "MFMA product needs a workspace for the transposed operand");
+        auto* ct = static_cast<uint64_t*>(d_workspace);
+        CFPQ_HIP(launch_transpose(d_c, ct, L, s));
+        if (!flag) return fail(CFPQ_EINVAL, "d_changed is required");
+        CFPQ_HIP(launch_mfma_product(d_b, ct, d_a, L, flag, s));
+        return CFPQ_OK;
+    }
+    if (!flag) return fail(CFPQ_EINVAL, "d_changed is required");
+    CFPQ_HIP(launch_bits_product(d_b, d_c, d_a, L, flag, s));
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_popcount(int32_t n_nodes, int32_t count, const uint64_t* d_mats, unsigned long long* d_counts,
+                          void* stream) {
+    g_last_error.clear();
+    if (n_nodes < 0 || count < 0) return fail(CFPQ_EINVAL, "negative size");
+    if (count > 0 && (!d_mats || !d_counts)) return fail(CFPQ_EINVAL, "NULL pointer");
+    const Layout L = layout_for(n_nodes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CFPQ_HIP(hipMemsetAsync(d_counts, 0, static_cast<size_t>(count) * 8, s));
+    CFPQ_HIP(launch_popcount(d_mats, count, L, d_counts, s));
+    return CFPQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Matrix initialisation, bit transpose, popcount and fill kernels.
+#include "cfpq_internal.h"
+
+namespace cfpq {
+namespace {
+
+__global__ void zero_kernel(uint64_t* __restrict__ p, size_t words) {
+    size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (; i < words; i += stride) p[i] = 0;
+}
+
+// One thread per edge.  Matrix initialisation of Algorithm 1 (section 4.2):
+// T_ij gains every A with A -> x for an edge (i, x, j); parallel edges with
+// different labels each add their own nonterminals, hence the atomic OR.
+__global__ void init_scatter_kernel(const cfpq_edge* __restrict__ edges, int64_t m,
+                                    const int32_t* __restrict__ term_off,
+                                    const int32_t* __restrict__ term_lhs, int32_t n_terminals,
+                                    int32_t n, uint64_t* __restrict__ T, int64_t mat_words,
+                                    int64_t W, int32_t* __restrict__ bad) {
+    int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    cfpq_edge ed = edges[e];
+    if (ed.src < 0 || ed.src >= n || ed.dst < 0 || ed.dst >= n || ed.label < 0 ||
+        ed.label >= n_terminals) {
+        atomicAdd(bad, 1);
+        return;
+    }
+    unsigned long long bit = 1ull << (ed.dst & 63);
+    int64_t off = static_cast<int64_t>(ed.src) * W + (ed.dst >> 6);
+    for (int32_t r = term_off[ed.label]; r < term_off[ed.label + 1]; ++r) {
+        auto* word = reinterpret_cast<unsigned long long*>(T + term_lhs[r] * mat_words + off);
+        atomicOr(word, bit);
+    }
+}
+
+// Bit-matrix transpose, one wavefront per 64 x 64 block.  Lane t holds row
+// r0 + t of the block as one 64-bit word; column j of the block is the ballot
+// of bit j over the lanes, which lane j keeps and writes as row c0 + j of the
+// transpose.
+__global__ __launch_bounds__(256) void transpose_kernel(const uint64_t* __restrict__ src,
+                                                        uint64_t* __restrict__ dst, int64_t W) {
+    const int lane = threadIdx.x & 63;
+    const int64_t blocks = W * W;  // (npad/64)^2 blocks of 64 x 64
+    int64_t blk = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (blk >= blocks) return;
+    const int64_t br = blk / W;  // block row (word index of the source rows / 64)
+    const int64_t bc = blk % W;  // block column (word column)
+    uint64_t word = src[(br * 64 + lane) * W + bc];
+    uint64_t mine = 0;
+#pragma unroll 8
+    for (int j = 0; j < 64; ++j) {
+        uint64_t col = __ballot((word >> j) & 1ull);
+        mine = (lane == j) ? col : mine;
+    }
+    dst[(bc * 64 + lane) * W + br] = mine;
+}
+
+__global__ __launch_bounds__(256) void popcount_kernel(const uint64_t* __restrict__ mats,
+                                                       int64_t mat_words,
+                                                       unsigned long long* __restrict__ counts) {
+    const uint64_t* m = mats + static_cast<int64_t>(blockIdx.y) * mat_words;
+    unsigned long long c = 0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < mat_words;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        c += __popcll(m[i]);
+    // wavefront reduction, then one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(counts + blockIdx.y, c);
+}
+
+}  // namespace
+
+hipError_t launch_zero(uint64_t* p, size_t words, hipStream_t s) {
+    if (words == 0) return hipSuccess;
+    size_t blocks = (words + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    zero_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(p, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t* term_off,
+                               const int32_t* term_lhs, int32_t n_terminals, int32_t n,
+                               uint64_t* T, const Layout& L, int32_t* bad, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    int64_t blocks = (m + 255) / 256;
+    init_scatter_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(
+        edges, m, term_off, term_lhs, n_terminals, n, T, L.mat_words, L.W, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s) {
+    int64_t blocks = L.W * L.W;
+    int64_t wgs = (blocks + 3) / 4;
+    transpose_kernel<<<dim3(static_cast<unsigned>(wgs)), dim3(256), 0, s>>>(src, dst, L.W);
+    return hipGetLastError();
+}
+
+hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,
+                           unsigned long long* counts, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (L.mat_words + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    popcount_kernel<<<dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(count)), dim3(256), 0,
+                      s>>>(mats, L.mat_words, counts);
+    return hipGetLastError();
+}
+
+}  // namespace cfpq

@@ -1,0 +1,130 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before any device work (no GPU needed)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cfpq.h")
+
+
+def _lib():
+    from paper_1707_01007_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("libcfpq.so not built (run __graft_entry__.build())")
+    return _abi.load()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"CFPQ_API\s+[\w\s\*]+?\b(cfpq_\w+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    assert "cfpq_closure" in syms and "cfpq_product" in syms and len(syms) >= 10
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+    from paper_1707_01007_amd import _abi
+    assert set(declared_symbols()) == set(_abi.EXPORTED)
+
+
+def test_layout_functions():
+    lib = _lib()
+    for n, w in [(0, 4), (1, 4), (64, 4), (256, 4), (257, 8), (1000, 16), (4096, 64), (16384, 256)]:
+        assert lib.cfpq_row_words(n) == w
+        assert lib.cfpq_padded_rows(n) == 64 * w
+        assert lib.cfpq_result_bytes(n, 3) == 3 * 64 * w * w * 8
+    assert lib.cfpq_abi_version() == 1
+
+
+def _structs(n=4, edges=((0, 0, 1), (1, 1, 2)), n_nt=4, n_t=2, term=((2, 0), (3, 1)),
+             binr=((0, 2, 3),)):
+    from paper_1707_01007_amd import _abi
+    e = np.asarray(edges, dtype=np.int32).reshape(-1, 3)
+    t_arr = (_abi.TermRule * max(1, len(term)))(*[_abi.TermRule(*r) for r in term])
+    b_arr = (_abi.BinRule * max(1, len(binr)))(*[_abi.BinRule(*r) for r in binr])
+    g = _abi.Grammar(n_nt, n_t, len(term), len(binr), ctypes.cast(t_arr, ctypes.POINTER(_abi.TermRule)),
+                     ctypes.cast(b_arr, ctypes.POINTER(_abi.BinRule)))
+    gr = _abi.Graph(n, 0, len(e), ctypes.c_void_p(e.ctypes.data))
+    return gr, g, (e, t_arr, b_arr)
+
+
+def test_workspace_bytes_valid_and_invalid():
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+    opt = _abi.Options()
+    lib.cfpq_default_options(ctypes.byref(opt))
+    assert opt.path == _abi.PATH_AUTO and opt.schedule == _abi.SCHEDULE_INPLACE and opt.dirty_worklist == 1
+    sz = ctypes.c_size_t(0)
+    assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz)) == 0
+    assert sz.value > 0
+    opt.schedule = _abi.SCHEDULE_JACOBI
+    sz2 = ctypes.c_size_t(0)
+    assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz2)) == 0
+    assert sz2.value >= sz.value + 4 * lib.cfpq_result_bytes(4, 1)  # the second buffer
+    g.n_nonterminals = 0
+    assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz)) == _abi.CFPQ_EINVAL
+    assert b"n_nonterminals" in lib.cfpq_last_error()
+
+
+@pytest.mark.parametrize("case,kw", [
+    ("edge_src", dict(edges=((5, 0, 1),))),
+    ("edge_dst", dict(edges=((0, 0, -1),))),
+    ("edge_label", dict(edges=((0, 2, 1),))),
+    ("term_lhs", dict(term=((4, 0),))),
+    ("term_terminal", dict(term=((0, 7),))),
+    ("bin_right", dict(binr=((0, 1, 9),))),
+    ("negative_n", dict(n=-1, edges=())),
+])
+def test_closure_rejects_bad_ids_before_device_work(case, kw):
+    """Every one of these returns CFPQ_EINVAL from host validation, before the
+    first HIP call (this machine has no GPU)."""
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs(**kw)
+    st = _abi.Stats()
+    rc = lib.cfpq_closure(ctypes.byref(gr), ctypes.byref(g), None, None, ctypes.c_void_p(1 << 20),
+                          ctypes.c_size_t(1 << 30), ctypes.c_void_p(1 << 21), ctypes.byref(st))
+    assert rc == _abi.CFPQ_EINVAL, case
+    assert lib.cfpq_last_error()
+
+
+def test_closure_rejects_small_workspace_and_null_result():
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+    rc = lib.cfpq_closure(ctypes.byref(gr), ctypes.byref(g), None, None, ctypes.c_void_p(1 << 20),
+                          ctypes.c_size_t(16), ctypes.c_void_p(1 << 21), None)
+    assert rc == _abi.CFPQ_ENOMEM
+    rc = lib.cfpq_closure(ctypes.byref(gr), ctypes.byref(g), None, None, ctypes.c_void_p(1 << 20),
+                          ctypes.c_size_t(1 << 30), None, None)
+    assert rc == _abi.CFPQ_EINVAL
+    opt = _abi.Options()
+    lib.cfpq_default_options(ctypes.byref(opt))
+    opt.schedule = 7
+    rc = lib.cfpq_closure(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), None, ctypes.c_void_p(1 << 20),
+                          ctypes.c_size_t(1 << 30), ctypes.c_void_p(1 << 21), None)
+    assert rc == _abi.CFPQ_EINVAL
+
+
+def test_product_rejects_bad_arguments():
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    assert lib.cfpq_product(-1, 1, None, None, None, None, None, 0, None) == _abi.CFPQ_EINVAL
+    assert lib.cfpq_product(64, 1, None, None, None, None, None, 0, None) == _abi.CFPQ_EINVAL
+    p = ctypes.c_void_p(1 << 20)
+    assert lib.cfpq_product(64, 9, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL
+    assert lib.cfpq_product(64, 2, p, p, p, p, None, 0, None) == _abi.CFPQ_ENOMEM
+    assert lib.cfpq_product_workspace_bytes(256, 1) == 0
+    assert lib.cfpq_product_workspace_bytes(256, 2) == lib.cfpq_result_bytes(256, 1)

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bit-exact everywhere (the whole computation is Boolean).  Cases span the
+paper's worked example, the five workload recipes at oracle-friendly sizes,
+ragged sizes around the 64/256 tile edges, degenerate inputs, and both product
+kernels under both schedules.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import alg1, worklist
+from workloads import configs, grammars, graphs
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+PATHS = ["bits", "mfma"]
+SCHEDULES = ["inplace", "jacobi"]
+
+
+@pytest.fixture(scope="module")
+def cfpq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_01007_amd as m
+    m.lib()
+    return m
+
+
+def _say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def _run(cfpq, inst, **kw):
+    _say(inst.tag, inst.n, kw)
+    res = cfpq.closure(inst.n, inst.edges, inst.grammar, **kw)
+    return cfpq.result_bits(res), res
+
+
+def _digest(bits):
+    return hashlib.sha256(np.ascontiguousarray(bits).astype("<u8").tobytes()).hexdigest()
+
+
+# ---------------------------------------------------------------- paper example
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_worked_example(cfpq, path, schedule):
+    gold = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    inst = configs.worked_example()
+    bits, res = _run(cfpq, inst, path=path, schedule=schedule, dirty=(schedule == "inplace"))
+    rel = worklist.relations(bits, inst.n)
+    for name in inst.grammar.nonterminals:
+        assert rel[inst.grammar.nt(name)] == {tuple(p) for p in gold["relations"][name]}, name
+    if schedule == "jacobi":
+        assert res.stats["iterations"] == gold["loops"]["k"] == 6
+    assert res.stats["converged"] == 1
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_two_cycles(cfpq, path):
+    inst = configs.config1()
+    want = worklist.closure(inst.n, inst.edges, inst.grammar)
+    bits, res = _run(cfpq, inst, path=path, schedule="inplace")
+    assert np.array_equal(bits, want)
+
+
+def test_two_cycles_jacobi_loop_count(cfpq):
+    """8065 loops (Lemma 3 with the closed form; the oracle tests pin it)."""
+    inst = configs.config1()
+    bits, res = _run(cfpq, inst, path="bits", schedule="jacobi", dirty=True)
+    assert res.stats["iterations"] == 8065
+    assert np.array_equal(bits, worklist.closure(inst.n, inst.edges, inst.grammar))
+
+
+# ---------------------------------------------------------------- digests of larger workloads
+
+DIGESTS = json.load(open(os.path.join(GOLD, "digests.json")))
+MAKERS = {
+    "hierarchy4096_samegen": lambda: configs.config2(),
+    "hierarchy4096_rev_samegen": lambda: configs.config2(reverse=True),
+    "er16384_induced1024_dyck": lambda: configs.config3_induced(1024),
+    "er1024_dyck": lambda: configs.config3(1024),
+    "er2048_dyck": lambda: configs.config3(2048),
+    "er4096_dyck": lambda: configs.config3(4096),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MAKERS))
+@pytest.mark.parametrize("path", PATHS)
+def test_workload_digest(cfpq, name, path):
+    inst = MAKERS[name]()
+    bits, res = _run(cfpq, inst, path=path)
+    d = DIGESTS[name]
+    got = [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits]
+    assert got == d["counts"]
+    assert _digest(bits) == d["sha256"]
+
+
+def test_jacobi_equals_inplace_er(cfpq):
+    inst = configs.config3(1024)
+    a, ra = _run(cfpq, inst, path="mfma", schedule="jacobi", dirty=False)
+    b, rb = _run(cfpq, inst, path="bits", schedule="inplace", dirty=True)
+    assert np.array_equal(a, b)
+    assert rb.stats["iterations"] <= ra.stats["iterations"]
+
+
+# ---------------------------------------------------------------- ragged sizes, random grammars
+
+RAGGED = [1, 2, 63, 64, 65, 127, 200, 255, 256, 257, 300, 511, 513, 700]
+
+
+@pytest.mark.parametrize("n", RAGGED)
+@pytest.mark.parametrize("path", PATHS)
+def test_ragged_sizes(cfpq, n, path):
+    g = grammars.dyck()
+    _, e = graphs.erdos_renyi(n, max(1, 2 * n), 1000 + n, labels=2)
+    inst = configs.Instance(n, e, g, f"er{n}")
+    want = worklist.closure(n, e, g)
+    bits, _ = _run(cfpq, inst, path=path, schedule="inplace")
+    assert np.array_equal(bits, want)
+
+
+@pytest.mark.parametrize("name", ["same_generation", "adjacent_layers", "anbn", "transitive_closure"])
+@pytest.mark.parametrize("path", PATHS)
+def test_grammars_on_hierarchy_and_er(cfpq, name, path):
+    g = grammars.BY_NAME[name]()
+    if g.terminals == grammars.HIERARCHY_TERMINALS:
+        n, e = graphs.hierarchy(600, 21, roots=3, reverse=True)
+    else:
+        n, e = graphs.erdos_renyi(600, 1500, 22, labels=2)
+    want = worklist.closure(n, e, g)
+    bits, _ = _run(cfpq, configs.Instance(n, e, g, name), path=path, schedule="jacobi")
+    assert np.array_equal(bits, want)
+
+
+# ---------------------------------------------------------------- degenerate inputs
+
+def test_empty_graph_and_no_edges(cfpq):
+    g = grammars.dyck()
+    for n in (0, 5):
+        res = cfpq.closure(n, np.zeros((0, 3), np.int32), g)
+        assert not cfpq.result_bits(res).any()
+        assert res.stats["converged"] == 1
+
+
+def test_no_binary_rules_gives_edge_set(cfpq):
+    g = grammars.CNF(("X", "Y"), ("a", "b"), ((0, 0), (1, 0), (1, 1)), (), "terminal_only")
+    n, e = graphs.erdos_renyi(100, 300, 5, labels=2)
+    res = cfpq.closure(n, e, g)
+    assert np.array_equal(cfpq.result_bits(res), worklist.closure(n, e, g))
+
+
+def test_multi_edges_and_self_loops(cfpq):
+    g = grammars.dyck()
+    e = np.array([[0, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, 1], [1, 1, 0], [1, 1, 1]], np.int32)
+    res = cfpq.closure(2, e, g)
+    assert np.array_equal(cfpq.result_bits(res), worklist.closure(2, e, g))
+
+
+def test_device_edges_and_invalid_device_edges(cfpq):
+    import torch
+    g = grammars.dyck()
+    n, e = graphs.erdos_renyi(300, 900, 6, labels=2)
+    res = cfpq.closure(n, torch.from_numpy(e).cuda(), g)
+    assert np.array_equal(cfpq.result_bits(res), worklist.closure(n, e, g))
+    bad = e.copy()
+    bad[7, 2] = n + 3
+    with pytest.raises(cfpq.CfpqError) as ei:
+        cfpq.closure(n, torch.from_numpy(bad).cuda(), g)
+    assert ei.value.status == -1
+
+
+def test_max_iters_partial_is_sound(cfpq):
+    inst = configs.config1()
+    res = cfpq.closure(inst.n, inst.edges, inst.grammar, schedule="jacobi", max_iters=100, allow_partial=True)
+    assert res.status == -4 and res.stats["converged"] == 0
+    part = worklist.unpack(cfpq.result_bits(res), inst.n)
+    full = worklist.unpack(worklist.closure(inst.n, inst.edges, inst.grammar), inst.n)
+    assert not (part & ~full).any()
+    # Jacobi after 100 loops holds exactly the triples of derivation height <= 101 (Lemma 3)
+    t, _, _ = alg1.closure(inst.n, inst.edges, inst.grammar, max_loops=100)
+    assert np.array_equal(part, t)
+
+
+# ---------------------------------------------------------------- single products
+
+@pytest.mark.parametrize("n", [64, 256, 300, 1000, 2048])
+@pytest.mark.parametrize("density", [0.002, 0.05, 0.5])
+@pytest.mark.parametrize("path", PATHS)
+def test_product_against_boolean_matmul(cfpq, n, density, path):
+    import torch
+    rng = np.random.default_rng(n + int(density * 1000))
+    b = rng.random((n, n)) < density
+    c = rng.random((n, n)) < density
+    a0 = rng.random((n, n)) < 0.01
+    want = a0 | alg1.bool_product(b, c)
+    dev = cfpq.upload_bits(n, worklist.pack(np.stack([b, c, a0])))
+    _say("product", n, density, path)
+    changed = cfpq.product(n, dev[0], dev[1], dev[2], path=path)
+    torch.cuda.synchronize()
+    got = worklist.unpack(dev[2, :n, : (n + 63) // 64].cpu().numpy().view(np.uint64), n)
+    assert np.array_equal(got, want)
+    assert int(changed.item()) == int((want != a0).any())
+    # repeating the product changes nothing and leaves the flag clear
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cfpq.product(n, dev[0], dev[1], dev[2], path=path, changed=flag)
+    assert int(flag.item()) == 0
+
+
+def test_popcount(cfpq):
+    n = 777
+    rng = np.random.default_rng(3)
+    d = rng.random((3, n, n)) < 0.2
+    dev = cfpq.upload_bits(n, worklist.pack(d))
+    assert cfpq.popcount(n, dev, 3) == [int(x.sum()) for x in d]
