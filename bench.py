@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "bits", "mfma"])
     ap.add_argument("--schedule", default="inplace", choices=["inplace", "jacobi"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (3 times) and exit; used to "
+                         "scale the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on a single GPU "
@@ -71,6 +74,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
+        return
+
     import paper_1707_01007_amd as cfpq
     from workloads import configs
 

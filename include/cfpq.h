@@ -98,6 +98,9 @@ typedef struct {
                                 changed in the previous loop (all rules run in loop 1) */
     int32_t profile;         /* nonzero: time every product with HIP events on `stream`
                                 (stats.product_ms); costs one event pair per product */
+    int32_t tile;            /* product kernel variant; 0 = autotuned or default.  BITS: output
+                                strip width in 32-bit words per workgroup (8, 16 or 32) */
+    int32_t reserved;        /* must be 0 */
     int64_t max_iters;       /* loop cap; 0 = |V|^2 |N| + 1 (Theorem 3's bound) */
 } cfpq_options;
 
@@ -163,14 +166,16 @@ CFPQ_API cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* g
  * All three are npad x npad matrices in the bit layout for `n_nodes`.  d_a may
  * alias d_b and/or d_c (the in-place update; bits are only ever set, so every
  * value read is a subset of the final one).  path = CFPQ_PATH_BITS or
- * CFPQ_PATH_MFMA (AUTO picks one).  If d_changed is not NULL, *d_changed
- * (device int32) is OR-ed with 1 when d_a gained a bit.  d_workspace may be
- * NULL for the BITS path; the MFMA path needs cfpq_product_workspace_bytes.
+ * CFPQ_PATH_MFMA (AUTO picks one); tile as in cfpq_options (0 = default).
+ * *d_changed (device int32, required) is OR-ed with 1 when d_a gained a bit.
+ * d_workspace may be NULL for the BITS path; the MFMA path needs
+ * cfpq_product_workspace_bytes.  The MFMA path requires n_nodes <= 2^19
+ * (int32 accumulation bound); larger sizes return CFPQ_EINVAL.
  */
 CFPQ_API size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path);
-CFPQ_API cfpq_status cfpq_product(int32_t n_nodes, int32_t path, const uint64_t* d_b, const uint64_t* d_c,
-                         uint64_t* d_a, int32_t* d_changed, void* d_workspace,
-                         size_t workspace_bytes, void* stream);
+CFPQ_API cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint64_t* d_b,
+                                  const uint64_t* d_c, uint64_t* d_a, int32_t* d_changed,
+                                  void* d_workspace, size_t workspace_bytes, void* stream);
 
 /* Number of set bits of each of `count` consecutive matrices of the bit
  * layout for n_nodes (|R_A| per nonterminal for a result buffer), written to

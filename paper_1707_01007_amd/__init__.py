@@ -57,10 +57,11 @@ def _grammar_struct(grammar):
     return g, (t_arr, b_arr)
 
 
-def _options(path="auto", schedule="inplace", dirty=True, max_iters=0, profile=False):
+def _options(path="auto", schedule="inplace", dirty=True, max_iters=0, profile=False, tile=0):
     o = _abi.Options()
     lib().cfpq_default_options(ctypes.byref(o))
     o.profile = 1 if profile else 0
+    o.tile = int(tile)
     o.path = _PATHS[path] if isinstance(path, str) else int(path)
     o.schedule = _SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.dirty_worklist = 1 if dirty else 0
@@ -85,7 +86,7 @@ def _stream_ptr(stream):
 
 def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=True, max_iters=0,
             device=None, stream=None, out=None, workspace=None, allow_partial=False,
-            profile=False) -> Result:
+            profile=False, tile=0) -> Result:
     """Relational CFPQ closure (Algorithm 1) through ``cfpq_closure``.
 
     ``edges`` is an int32 array [m, 3] of (src, label, dst) on the host, or an
@@ -104,7 +105,7 @@ def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=Tr
     else:
         e_host = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
         graph = _abi.Graph(int(n), 0, int(e_host.shape[0]), ctypes.c_void_p(e_host.ctypes.data))
-    opt = _options(path, schedule, dirty, max_iters, profile)
+    opt = _options(path, schedule, dirty, max_iters, profile, tile)
     need = ctypes.c_size_t(0)
     _abi.check(L.cfpq_workspace_bytes(ctypes.byref(graph), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(need)))
     res_words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8
@@ -132,7 +133,7 @@ def result_bits(res: Result) -> np.ndarray:
     return host.view(np.uint64)
 
 
-def product(n: int, b, c, a, *, path="bits", changed=None, workspace=None, stream=None):
+def product(n: int, b, c, a, *, path="bits", tile=0, changed=None, workspace=None, stream=None):
     """``a |= b x c`` on device matrices in the bit layout (``cfpq_product``).
     Returns the device int32 change flag."""
     torch = _torch()
@@ -145,7 +146,7 @@ def product(n: int, b, c, a, *, path="bits", changed=None, workspace=None, strea
         workspace = torch.empty(need, dtype=torch.uint8, device=a.device)
     ws_ptr = workspace.data_ptr() if workspace is not None else 0
     ws_len = workspace.numel() if workspace is not None else 0
-    _abi.check(L.cfpq_product(int(n), p, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+    _abi.check(L.cfpq_product(int(n), p, int(tile), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
                               ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(changed.data_ptr()),
                               ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_len), _stream_ptr(stream)))
     return changed

@@ -46,7 +46,8 @@ class Grammar(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("schedule", ctypes.c_int32), ("dirty_worklist", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("max_iters", ctypes.c_int64)]
+                ("profile", ctypes.c_int32), ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_iters", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -94,7 +95,7 @@ def load(path: str = LIB_PATH):
     lib.cfpq_closure.restype = ctypes.c_int
     lib.cfpq_product_workspace_bytes.argtypes = [i32, i32]
     lib.cfpq_product_workspace_bytes.restype = sz
-    lib.cfpq_product.argtypes = [i32, i32, p, p, p, p, p, sz, p]
+    lib.cfpq_product.argtypes = [i32, i32, i32, p, p, p, p, p, sz, p]
     lib.cfpq_product.restype = ctypes.c_int
     lib.cfpq_popcount.argtypes = [i32, i32, p, p, p]
     lib.cfpq_popcount.restype = ctypes.c_int

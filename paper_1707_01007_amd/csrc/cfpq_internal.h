@@ -44,9 +44,16 @@ hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t*
                                const int32_t* term_lhs, int32_t n_terminals, int32_t n,
                                uint64_t* T, const Layout& L, int32_t* bad, hipStream_t s);
 
-// A |= B x C on the VALU: AND/OR over bit-packed rows.
+// A |= B x C on the VALU: AND/OR over bit-packed rows.  `strip` is the
+// output strip width in 32-bit words per workgroup (8, 16 or 32; 0 or an
+// unsupported width = bits_default_strip).
 hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s);
+                               int32_t* changed, hipStream_t s, int strip);
+bool bits_strip_supported(int strip, const Layout& L);
+int bits_default_strip(const Layout& L);
+
+// Largest n for which the MFMA path's int32 sums cannot overflow.
+constexpr int32_t kMfmaMaxNodes = 1 << 19;
 
 // A |= B x C on the int8 matrix cores; CT is the transpose of C.
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,

@@ -111,8 +111,7 @@ struct Plan {
 
 int32_t choose_path(const Layout& L, int32_t requested) {
     if (requested == CFPQ_PATH_BITS || requested == CFPQ_PATH_MFMA) return requested;
-    (void)L;
-    return CFPQ_PATH_BITS;
+    return L.n <= kMfmaMaxNodes ? CFPQ_PATH_MFMA : CFPQ_PATH_BITS;
 }
 
 Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& o) {
@@ -205,6 +204,11 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     if (o.schedule != CFPQ_SCHEDULE_INPLACE && o.schedule != CFPQ_SCHEDULE_JACOBI)
         return fail(CFPQ_EINVAL, "unknown schedule");
     if (o.max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
+    if (o.reserved != 0) return fail(CFPQ_EINVAL, "options.reserved must be 0");
+    if (o.path == CFPQ_PATH_MFMA && graph->n_nodes > kMfmaMaxNodes)
+        return fail(CFPQ_EINVAL, "the MFMA path supports at most 2^19 nodes");
+    if (o.tile != 0 && o.path == CFPQ_PATH_BITS && !bits_strip_supported(o.tile, layout_for(graph->n_nodes)))
+        return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
     const Plan p = make_plan(graph, grammar, o);
     if (p.total > 0 && !d_workspace) return fail(CFPQ_EINVAL, "d_workspace is NULL");
     if (workspace_bytes < p.total)
@@ -308,7 +312,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                 const uint64_t* CT = TT + p.right_slot[br.right] * mat_words;
                 CFPQ_HIP(launch_mfma_product(Bm, CT, Am, L, d_flags + br.lhs, s));
             } else {
-                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, d_flags + br.lhs, s));
+                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, d_flags + br.lhs, s, o.tile));
             }
             if (o.profile) {
                 hipEvent_t e = product_event(2 * launched + 1);
@@ -369,28 +373,31 @@ size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path) {
     return static_cast<size_t>(layout_for(n_nodes < 0 ? 0 : n_nodes).mat_words) * 8;
 }
 
-cfpq_status cfpq_product(int32_t n_nodes, int32_t path, const uint64_t* d_b, const uint64_t* d_c,
+cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint64_t* d_b, const uint64_t* d_c,
                          uint64_t* d_a, int32_t* d_changed, void* d_workspace, size_t workspace_bytes,
                          void* stream) {
     g_last_error.clear();
     if (n_nodes < 0 || n_nodes > CFPQ_MAX_NODES) return fail(CFPQ_EINVAL, "n_nodes out of range");
     if (!d_b || !d_c || !d_a) return fail(CFPQ_EINVAL, "matrix pointer is NULL");
-    if (path == CFPQ_PATH_AUTO) path = CFPQ_PATH_BITS;
-    if (path != CFPQ_PATH_BITS && path != CFPQ_PATH_MFMA) return fail(CFPQ_EINVAL, "unknown path");
+    if (!d_changed) return fail(CFPQ_EINVAL, "d_changed is required");
     const Layout L = layout_for(n_nodes);
+    if (path == CFPQ_PATH_AUTO) path = choose_path(L, path);
+    if (path != CFPQ_PATH_BITS && path != CFPQ_PATH_MFMA) return fail(CFPQ_EINVAL, "unknown path");
+    if (path == CFPQ_PATH_BITS && tile != 0 && !bits_strip_supported(tile, L))
+        return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
+    if (path == CFPQ_PATH_MFMA && tile != 0) return fail(CFPQ_EINVAL, "the MFMA path has no tile variants");
+    if (path == CFPQ_PATH_MFMA && n_nodes > kMfmaMaxNodes)
+        return fail(CFPQ_EINVAL, "the MFMA path supports at most 2^19 nodes");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int32_t* flag = d_changed;
     if (path == CFPQ_PATH_MFMA) {
         if (workspace_bytes < cfpq_product_workspace_bytes(n_nodes, path) || !d_workspace)
             return fail(CFPQ_ENOMEM, "MFMA product needs a workspace for the transposed operand");
         auto* ct = static_cast<uint64_t*>(d_workspace);
         CFPQ_HIP(launch_transpose(d_c, ct, L, s));
-        if (!flag) return fail(CFPQ_EINVAL, "d_changed is required");
-        CFPQ_HIP(launch_mfma_product(d_b, ct, d_a, L, flag, s));
+        CFPQ_HIP(launch_mfma_product(d_b, ct, d_a, L, d_changed, s));
         return CFPQ_OK;
     }
-    if (!flag) return fail(CFPQ_EINVAL, "d_changed is required");
-    CFPQ_HIP(launch_bits_product(d_b, d_c, d_a, L, flag, s));
+    CFPQ_HIP(launch_bits_product(d_b, d_c, d_a, L, d_changed, s, tile));
     return CFPQ_OK;
 }
 

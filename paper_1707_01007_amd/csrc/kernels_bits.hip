@@ -65,19 +65,31 @@ __global__ __launch_bounds__(256) void bits_product_kernel(const uint32_t* __res
 
 }  // namespace
 
+bool bits_strip_supported(int strip, const Layout& L) {
+    const int W2 = static_cast<int>(2 * L.W);
+    return (strip == 8 || strip == 16 || strip == 32) && W2 % strip == 0;
+}
+
+int bits_default_strip(const Layout& L) {
+    const int W2 = static_cast<int>(2 * L.W);
+    return W2 % 16 == 0 ? 16 : 8;
+}
+
 hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s) {
+                               int32_t* changed, hipStream_t s, int strip) {
     const int W2 = static_cast<int>(2 * L.W);
     const int kdw = static_cast<int>((L.n + 31) / 32);
     if (kdw == 0) return hipSuccess;
+    if (strip == 0 || !bits_strip_supported(strip, L)) strip = bits_default_strip(L);
     const unsigned row_blocks = static_cast<unsigned>(L.npad / 256);
     const auto* b = reinterpret_cast<const uint32_t*>(B);
     const auto* c = reinterpret_cast<const uint32_t*>(C);
     auto* a = reinterpret_cast<uint32_t*>(A);
-    if (W2 % 16 == 0) {
-        bits_product_kernel<16><<<dim3(W2 / 16, row_blocks), dim3(256), 0, s>>>(b, c, a, W2, kdw, changed);
-    } else {
-        bits_product_kernel<8><<<dim3(W2 / 8, row_blocks), dim3(256), 0, s>>>(b, c, a, W2, kdw, changed);
+    const dim3 grid(static_cast<unsigned>(W2 / strip), row_blocks);
+    switch (strip) {
+        case 32: bits_product_kernel<32><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed); break;
+        case 16: bits_product_kernel<16><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed); break;
+        default: bits_product_kernel<8><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed); break;
     }
     return hipGetLastError();
 }

@@ -1,12 +1,20 @@
 // Boolean matrix product with union on the int8 matrix cores (gfx950):
-//     A |= B x C,   P_ij = [ sum_k B_ik * C_kj > 0 ]
-// with 0/1 int8 operands and int32 accumulation (exact: the sum is at most
-// npad <= 2^20 < 2^31), i.e. the product of section 2 for one rule A -> B C
-// plus the union of Algorithm 1.
+//     A |= B x C,   P_ij = [ sum_k b_ik * c_kj > 0 ]
+// i.e. the product of section 2 for one rule A -> B C plus the union of
+// Algorithm 1, on v_mfma_i32_32x32x32_i8 with int32 accumulation.
 //
-// Operands stay bit-packed in memory; each wavefront expands the 32-bit slices
-// it needs into 0/1 bytes in registers (nibble -> 4 bytes: x * 0x00204081 &
-// 0x01010101) right before v_mfma_i32_32x32x32_i8.
+// Operand encoding.  Operands stay bit-packed in memory.  A 32-bit word w
+// holds 32 consecutive k; lane half g (0/1) of a wavefront turns it into the
+// four operand dwords  w & (0x01010101 << (q + 4 g)),  q = 0..3: byte t of
+// dword q is nonzero iff bit 8t + q + 4g of w is set, so the two halves
+// together carry all 32 bits, one per byte, and each dword costs a single
+// v_and_b32.  A set bit becomes the byte value 2^s (s = q + 4g, as int8 this is
+// 1, 2, ..., 64 or -128).  Both operands use the same s at the same k, so every
+// product term is 2^(2s) > 0 and the sum is positive iff some k has both bits
+// set: exactly the Boolean product.  The order in which the hardware walks k
+// inside one MFMA does not matter for the same reason.  The largest sum for
+// 32 k is 4 * (1 + 4 + ... + 4^7) = 87380, so int32 cannot overflow while
+// n <= 2^19 (the MFMA path is limited to that).
 //
 // Orientation.  The kernel computes D[j][i] = sum_k CT[j][k] * B[i][k], with
 // CT = C transposed, so that both operands are rows whose bits run along k
@@ -17,10 +25,12 @@
 //
 // Tiling.  A workgroup is 4 wavefronts covering 256 (j) x 256 (i); each
 // wavefront owns 128 x 128 = 4 x 4 blocks of 32 x 32 (256 int32 accumulators
-// per lane, held in AGPRs).  Per 32-k step a wavefront expands 8 operand
-// fragments (12 VALU ops each) and issues 16 MFMAs.  Workgroups are spread
-// over the 8 XCDs in contiguous bands of output rows so that each XCD's L2
-// keeps its own rows of B.
+// per lane, held in AGPRs).  Per 32-k step a wavefront uses one dword per
+// fragment row (8 fragments), spends 32 v_and_b32 and issues 16 MFMAs; rows
+// are read 128 k at a time into two alternating register buffers.
+// Workgroups go round-robin to the 8 XCDs; the tile order gives each XCD a
+// band of output rows walked in 4 x 8 groups of tiles, so the workgroups that
+// run together on one XCD share 4 row blocks of B and 8 of CT in its L2.
 #include "cfpq_internal.h"
 
 namespace cfpq {
@@ -32,32 +42,76 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kJT = 4;  // 32-row blocks of j per wavefront
 constexpr int kIT = 4;  // 32-column blocks of i per wavefront
 
-// 16 bits of `word` starting at `shift` -> 16 bytes of 0/1, byte b = bit b.
-__device__ __forceinline__ v4i expand16(uint32_t word, uint32_t shift) {
+// Operand dwords of one 32-bit k-word for lane half g: dword q keeps bits
+// 8t + q + 4g (t = 0..3) in place, i.e. byte t = (bit ? 2^(q+4g) : 0).
+__device__ __forceinline__ v4i spread(uint32_t w, uint32_t mask0) {
     v4i r;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        uint32_t nib = __builtin_amdgcn_ubfe(word, shift + 4 * q, 4);
-        r[q] = static_cast<int>((nib * 0x00204081u) & 0x01010101u);
-    }
+    r[0] = static_cast<int>(w & mask0);
+    r[1] = static_cast<int>(w & (mask0 << 1));
+    r[2] = static_cast<int>(w & (mask0 << 2));
+    r[3] = static_cast<int>(w & (mask0 << 3));
     return r;
+}
+
+constexpr int kChunkWords = 4;  // 32-bit k-words per fragment row and chunk (128 k)
+
+struct Chunk {
+    uint4 c[kJT];
+    uint4 b[kIT];
+};
+
+__device__ __forceinline__ void load_chunk(Chunk& ch, const uint4* const (&crow)[kJT],
+                                           const uint4* const (&brow)[kIT], int kc) {
+#pragma unroll
+    for (int jb = 0; jb < kJT; ++jb) ch.c[jb] = crow[jb][kc];
+#pragma unroll
+    for (int ib = 0; ib < kIT; ++ib) ch.b[ib] = brow[ib][kc];
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4& u, int q) {
+    return q == 0 ? u.x : q == 1 ? u.y : q == 2 ? u.z : u.w;
+}
+
+// kChunkWords steps of 32 k: per step 8 operand fragments and 16 MFMAs.
+__device__ __forceinline__ void mma_chunk(v16i (&acc)[kJT][kIT], const Chunk& ch, uint32_t mask0) {
+#pragma unroll
+    for (int s = 0; s < kChunkWords; ++s) {
+        v4i ca[kJT], bb[kIT];
+#pragma unroll
+        for (int jb = 0; jb < kJT; ++jb) ca[jb] = spread(word_of(ch.c[jb], s), mask0);
+#pragma unroll
+        for (int ib = 0; ib < kIT; ++ib) bb[ib] = spread(word_of(ch.b[ib], s), mask0);
+#pragma unroll
+        for (int jb = 0; jb < kJT; ++jb)
+#pragma unroll
+            for (int ib = 0; ib < kIT; ++ib)
+                acc[jb][ib] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ca[jb], bb[ib], acc[jb][ib], 0, 0, 0);
+    }
 }
 
 __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __restrict__ Bm,
                                                            const uint32_t* __restrict__ CT,
                                                            uint32_t* Am, int W2, int kchunks,
-                                                           int tiles_dim, int xcd_bands,
+                                                           int tiles_dim, int grouped,
                                                            int32_t* changed) {
     // ---- workgroup -> tile, XCD-aware ----
+    // grouped: tiles_dim is a multiple of 32, so each XCD owns tiles_dim / 8
+    // consecutive tile rows, walked in groups of 4 tile rows x 8 tile columns.
     const int wg = blockIdx.x;
-    const int total = tiles_dim * tiles_dim;
-    int t = wg;
-    if (xcd_bands) {
-        const int per = total / 8;
-        t = (wg % 8) * per + wg / 8;
+    int tile_i, tile_j;
+    if (grouped) {
+        const int xcd = wg & 7;
+        const int idx = wg >> 3;                   // position in this XCD's sequence
+        const int rows_per_xcd = tiles_dim >> 3;
+        const int group = idx >> 5, within = idx & 31;
+        const int groups_per_row = tiles_dim >> 3;  // 8-column groups across
+        const int gr = group / groups_per_row, gc = group % groups_per_row;
+        tile_i = xcd * rows_per_xcd + gr * 4 + (within >> 3);
+        tile_j = gc * 8 + (within & 7);
+    } else {
+        tile_i = wg / tiles_dim;
+        tile_j = wg % tiles_dim;
     }
-    const int tile_i = t / tiles_dim;
-    const int tile_j = t % tiles_dim;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -65,7 +119,7 @@ __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __res
     const int r32 = lane & 31;
     const int j0 = tile_j * 256 + (wave & 1) * 128;
     const int i0 = tile_i * 256 + (wave >> 1) * 128;
-    const uint32_t shift = 16u * static_cast<uint32_t>(g);
+    const uint32_t mask0 = 0x01010101u << (4 * g);
 
     const uint4* crow[kJT];
     const uint4* brow[kIT];
@@ -84,43 +138,22 @@ __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __res
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[jb][ib][e] = 0;
 
-    uint4 cnext[kJT], bnext[kIT];
-#pragma unroll
-    for (int jb = 0; jb < kJT; ++jb) cnext[jb] = crow[jb][0];
-#pragma unroll
-    for (int ib = 0; ib < kIT; ++ib) bnext[ib] = brow[ib][0];
-
-    for (int kc = 0; kc < kchunks; ++kc) {  // 128 k per chunk = 4 dwords per row
-        uint4 ccur[kJT], bcur[kIT];
-#pragma unroll
-        for (int jb = 0; jb < kJT; ++jb) ccur[jb] = cnext[jb];
-#pragma unroll
-        for (int ib = 0; ib < kIT; ++ib) bcur[ib] = bnext[ib];
-        if (kc + 1 < kchunks) {
-#pragma unroll
-            for (int jb = 0; jb < kJT; ++jb) cnext[jb] = crow[jb][kc + 1];
-#pragma unroll
-            for (int ib = 0; ib < kIT; ++ib) bnext[ib] = brow[ib][kc + 1];
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            v4i ca[kJT], bb[kIT];
-#pragma unroll
-            for (int jb = 0; jb < kJT; ++jb) {
-                const uint32_t w = s == 0 ? ccur[jb].x : s == 1 ? ccur[jb].y : s == 2 ? ccur[jb].z : ccur[jb].w;
-                ca[jb] = expand16(w, shift);
-            }
-#pragma unroll
-            for (int ib = 0; ib < kIT; ++ib) {
-                const uint32_t w = s == 0 ? bcur[ib].x : s == 1 ? bcur[ib].y : s == 2 ? bcur[ib].z : bcur[ib].w;
-                bb[ib] = expand16(w, shift);
-            }
-#pragma unroll
-            for (int jb = 0; jb < kJT; ++jb)
-#pragma unroll
-                for (int ib = 0; ib < kIT; ++ib)
-                    acc[jb][ib] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ca[jb], bb[ib], acc[jb][ib], 0, 0, 0);
-        }
+    // Two chunk buffers of 128 k (4 dwords per fragment row), used alternately:
+    // chunk c + 1 is in flight while chunk c is multiplied.  kchunks is even;
+    // the last prefetch re-reads the final chunk instead of branching.
+    Chunk buf0, buf1;
+    load_chunk(buf0, crow, brow, 0);
+    // The scheduling barriers keep each prefetch ahead of the multiplies that
+    // follow it (the scheduler would otherwise sink the loads to their uses).
+    for (int kc = 0; kc < kchunks; kc += 2) {
+        load_chunk(buf1, crow, brow, kc + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk(acc, buf0, mask0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk(buf0, crow, brow, min(kc + 2, kchunks - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk(acc, buf1, mask0);
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     // ---- epilogue: threshold, pack along j, OR into A ----
@@ -135,7 +168,7 @@ __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __res
             uint32_t w = 0;
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const uint32_t bit = static_cast<uint32_t>(min(acc[jb][ib][e], 1));
+                const uint32_t bit = acc[jb][ib][e] > 0 ? 1u : 0u;
                 w |= bit << (8 * (e / 4) + 4 * g + (e % 4));
             }
             word[jb] = w | static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 32, 64));
@@ -161,14 +194,16 @@ __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __res
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
                                int32_t* changed, hipStream_t s) {
     const int W2 = static_cast<int>(2 * L.W);
-    const int kchunks = static_cast<int>((L.n + 127) / 128);
+    // 128 k per chunk, an even number of chunks (rows hold npad / 128 of them,
+    // npad a multiple of 256, and bits past n are zero)
+    const int kchunks = static_cast<int>((L.n + 255) / 256) * 2;
     if (kchunks == 0) return hipSuccess;
     const int tiles_dim = static_cast<int>(L.npad / 256);
     const int total = tiles_dim * tiles_dim;
-    const int bands = (total % 8 == 0) ? 1 : 0;
+    const int grouped = (tiles_dim % 32 == 0) ? 1 : 0;
     mfma_product_kernel<<<dim3(static_cast<unsigned>(total)), dim3(256), 0, s>>>(
         reinterpret_cast<const uint32_t*>(B), reinterpret_cast<const uint32_t*>(CT),
-        reinterpret_cast<uint32_t*>(A), W2, kchunks, tiles_dim, bands, changed);
+        reinterpret_cast<uint32_t*>(A), W2, kchunks, tiles_dim, grouped, changed);
     return hipGetLastError();
 }
 

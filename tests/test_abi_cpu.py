@@ -121,10 +121,13 @@ def test_closure_rejects_small_workspace_and_null_result():
 def test_product_rejects_bad_arguments():
     from paper_1707_01007_amd import _abi
     lib = _lib()
-    assert lib.cfpq_product(-1, 1, None, None, None, None, None, 0, None) == _abi.CFPQ_EINVAL
-    assert lib.cfpq_product(64, 1, None, None, None, None, None, 0, None) == _abi.CFPQ_EINVAL
+    assert lib.cfpq_product(-1, 1, 0, None, None, None, None, None, 0, None) == _abi.CFPQ_EINVAL
+    assert lib.cfpq_product(64, 1, 0, None, None, None, None, None, 0, None) == _abi.CFPQ_EINVAL
     p = ctypes.c_void_p(1 << 20)
-    assert lib.cfpq_product(64, 9, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL
-    assert lib.cfpq_product(64, 2, p, p, p, p, None, 0, None) == _abi.CFPQ_ENOMEM
+    assert lib.cfpq_product(64, 9, 0, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL
+    assert lib.cfpq_product(64, 1, 12, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL   # no such strip width
+    assert lib.cfpq_product(64, 2, 0, p, p, p, p, None, 0, None) == _abi.CFPQ_ENOMEM
+    assert lib.cfpq_product(600000, 2, 0, p, p, p, p, p, 1 << 40, None) == _abi.CFPQ_EINVAL  # MFMA size bound
+    assert lib.cfpq_product(64, 1, 0, p, p, p, None, None, 0, None) == _abi.CFPQ_EINVAL     # flag required
     assert lib.cfpq_product_workspace_bytes(256, 1) == 0
     assert lib.cfpq_product_workspace_bytes(256, 2) == lib.cfpq_result_bytes(256, 1)

@@ -222,3 +222,28 @@ def test_popcount(cfpq):
     d = rng.random((3, n, n)) < 0.2
     dev = cfpq.upload_bits(n, worklist.pack(d))
     assert cfpq.popcount(n, dev, 3) == [int(x.sum()) for x in d]
+
+
+@pytest.mark.parametrize("n", [1000, 2048])
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_bits_strip_variants(cfpq, n, tile):
+    """Every output strip width of the VALU kernel gives the same product."""
+    import torch
+    rng = np.random.default_rng(40 + tile)
+    b = rng.random((n, n)) < 0.03
+    c = rng.random((n, n)) < 0.03
+    want = alg1.bool_product(b, c)
+    dev = cfpq.upload_bits(n, worklist.pack(np.stack([b, c, np.zeros_like(b)])))
+    _say("bits strip", n, tile)
+    cfpq.product(n, dev[0], dev[1], dev[2], path="bits", tile=tile)
+    torch.cuda.synchronize()
+    got = worklist.unpack(dev[2, :n, : (n + 63) // 64].cpu().numpy().view(np.uint64), n)
+    assert np.array_equal(got, want)
+
+
+def test_closure_with_each_bits_tile(cfpq):
+    inst = configs.config3(1024)
+    want = worklist.closure(inst.n, inst.edges, inst.grammar)
+    for tile in (8, 16, 32):
+        bits, _ = _run(cfpq, inst, path="bits", tile=tile)
+        assert np.array_equal(bits, want), tile
