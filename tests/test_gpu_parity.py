@@ -247,3 +247,20 @@ def test_closure_with_each_bits_tile(cfpq):
     for tile in (8, 16, 32):
         bits, _ = _run(cfpq, inst, path="bits", tile=tile)
         assert np.array_equal(bits, want), tile
+
+
+@pytest.mark.parametrize("path", ["auto", "bits"])
+def test_full_size_er16384(cfpq, path):
+    """The benchmark workload at full size (n = 16384, device-resident edges,
+    the benchmark's launch configuration for "auto"), bit-exact against the
+    oracle's stored digest."""
+    import torch
+    inst = configs.config3(16384)
+    d = DIGESTS.get("er16384_dyck")
+    if d is None:
+        pytest.skip("digest for the 16384-node workload not generated")
+    _say(inst.tag, path)
+    res = cfpq.closure(inst.n, torch.from_numpy(inst.edges).cuda(), inst.grammar, path=path)
+    bits = cfpq.result_bits(res)
+    assert [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits] == d["counts"]
+    assert _digest(bits) == d["sha256"]
