@@ -91,16 +91,19 @@ def main():
     inst = configs.config3(args.n)
     g = inst.grammar
     edges = torch.from_numpy(inst.edges).cuda()
-    res = cfpq.closure(inst.n, edges, g, path=args.path, schedule=args.schedule)  # sizes buffers
-    out, ws = res.bits.view(-1), None
+    # Every closure here uses the same options as the timed ones: per-product
+    # HIP events on the library's stream (host-driven loop, no skipped launches).
+    kw = dict(path=args.path, schedule=args.schedule, profile=True)
+    res = cfpq.closure(inst.n, edges, g, **kw)  # sizes buffers
+    out = res.bits.view(-1)
     print(f"[bench] warmup {args.warmup} x closure n={inst.n} path={args.path}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        res = cfpq.closure(inst.n, edges, g, path=args.path, schedule=args.schedule, out=out)
+        res = cfpq.closure(inst.n, edges, g, out=out, **kw)
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        res = cfpq.closure(inst.n, edges, g, path=args.path, schedule=args.schedule, out=out, profile=True)
+        res = cfpq.closure(inst.n, edges, g, out=out, **kw)
         stats.append(res.stats)
         print(f"[bench] step {k}: {res.stats['device_ms']:.1f} ms, {res.stats['iterations']} loops, "
               f"{res.stats['products']} products", file=sys.stderr, flush=True)

@@ -100,7 +100,11 @@ typedef struct {
                                 (stats.product_ms); costs one event pair per product */
     int32_t tile;            /* product kernel variant; 0 = autotuned or default.  BITS: output
                                 strip width in 32-bit words per workgroup (8, 16 or 32) */
-    int32_t reserved;        /* must be 0 */
+    int32_t capture;         /* loops per captured HIP graph: the loop state (per-rule dirty
+                                decisions, change flags, loop count) lives on the device and the
+                                host reads it back once per `capture` loops; 0 = host-driven
+                                loop with one read-back per loop.  Ignored when profile is set.
+                                Default 8. */
     int64_t max_iters;       /* loop cap; 0 = |V|^2 |N| + 1 (Theorem 3's bound) */
 } cfpq_options;
 
@@ -121,7 +125,8 @@ CFPQ_API int32_t cfpq_abi_version(void);
  * stays valid until the next call on this thread. */
 CFPQ_API const char* cfpq_last_error(void);
 
-/* Fill `opt` with defaults: AUTO path, in-place schedule, dirty worklist on. */
+/* Fill `opt` with defaults: AUTO path, in-place schedule, dirty worklist on,
+ * 8 loops per captured graph, no per-product timing, max_iters from Theorem 3. */
 CFPQ_API void cfpq_default_options(cfpq_options* opt);
 
 /* Words per matrix row: ceil(n/64) rounded up to a multiple of 4 (n >= 0). */

@@ -57,9 +57,11 @@ def _grammar_struct(grammar):
     return g, (t_arr, b_arr)
 
 
-def _options(path="auto", schedule="inplace", dirty=True, max_iters=0, profile=False, tile=0):
+def _options(path="auto", schedule="inplace", dirty=True, max_iters=0, profile=False, tile=0, capture=None):
     o = _abi.Options()
     lib().cfpq_default_options(ctypes.byref(o))
+    if capture is not None:
+        o.capture = int(capture)
     o.profile = 1 if profile else 0
     o.tile = int(tile)
     o.path = _PATHS[path] if isinstance(path, str) else int(path)
@@ -86,7 +88,7 @@ def _stream_ptr(stream):
 
 def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=True, max_iters=0,
             device=None, stream=None, out=None, workspace=None, allow_partial=False,
-            profile=False, tile=0) -> Result:
+            profile=False, tile=0, capture=None) -> Result:
     """Relational CFPQ closure (Algorithm 1) through ``cfpq_closure``.
 
     ``edges`` is an int32 array [m, 3] of (src, label, dst) on the host, or an
@@ -105,7 +107,7 @@ def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=Tr
     else:
         e_host = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
         graph = _abi.Graph(int(n), 0, int(e_host.shape[0]), ctypes.c_void_p(e_host.ctypes.data))
-    opt = _options(path, schedule, dirty, max_iters, profile, tile)
+    opt = _options(path, schedule, dirty, max_iters, profile, tile, capture)
     need = ctypes.c_size_t(0)
     _abi.check(L.cfpq_workspace_bytes(ctypes.byref(graph), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(need)))
     res_words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8

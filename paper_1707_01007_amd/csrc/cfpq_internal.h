@@ -31,6 +31,18 @@ inline Layout layout_for(int32_t n) {
     return L;
 }
 
+// Device-side loop state for captured closures (see kernels_control.hip).
+struct LoopState {
+    int32_t changed[CFPQ_MAX_NONTERMINALS];       // set by products during the current loop
+    int32_t changed_prev[CFPQ_MAX_NONTERMINALS];  // flags of the previous loop
+    int32_t done;                                 // fixpoint reached or cap hit
+    int32_t capped;                               // stopped by max_iters
+    int32_t active;                               // the current loop is a real one
+    int32_t pad;
+    int64_t iterations;                           // loops executed
+    int64_t products;                             // products executed
+};
+
 // ---- kernels (each launcher only enqueues work on `s`) ----
 
 // Fill `words` uint64 with zero by a kernel (safe inside captured graphs).
@@ -47,8 +59,10 @@ hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t*
 // A |= B x C on the VALU: AND/OR over bit-packed rows.  `strip` is the
 // output strip width in 32-bit words per workgroup (8, 16 or 32; 0 or an
 // unsupported width = bits_default_strip).
+// A non-null `go` makes the whole launch a no-op unless *go != 0 (read on the
+// device, so the launch can sit in a captured graph).
 hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s, int strip);
+                               int32_t* changed, hipStream_t s, int strip, const int32_t* go = nullptr);
 bool bits_strip_supported(int strip, const Layout& L);
 int bits_default_strip(const Layout& L);
 
@@ -57,10 +71,20 @@ constexpr int32_t kMfmaMaxNodes = 1 << 19;
 
 // A |= B x C on the int8 matrix cores; CT is the transpose of C.
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s);
+                               int32_t* changed, hipStream_t s, const int32_t* go = nullptr);
 
 // dst = transpose(src) (bit matrix, npad x npad).
-hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s);
+hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s,
+                            const int32_t* pred = nullptr);
+
+// Loop control (kernels_control.hip).  `rules` holds (lhs, left, right)
+// triples on the device; go[r] receives the decision for rule r.
+hipError_t launch_loop_state_init(LoopState* st, hipStream_t s);
+hipError_t launch_plan(LoopState* st, int32_t* go, const int32_t* rules, int32_t n_rules, int32_t n_nt,
+                       int32_t dirty, int64_t max_iters, hipStream_t s);
+hipError_t launch_finish(LoopState* st, int32_t n_nt, hipStream_t s);
+hipError_t launch_copy_if(const uint64_t* src, uint64_t* dst, size_t words, const int32_t* pred,
+                          hipStream_t s);
 
 // counts[m] = number of set bits of matrix m (count matrices), added to counts.
 hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,

@@ -106,6 +106,7 @@ struct Plan {
     std::vector<int32_t> right_slot;  // per nonterminal: transpose slot or -1
     int32_t n_right = 0;
     size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0;
+    size_t off_rules = 0, off_go = 0, off_state = 0;
     size_t off_second = 0, off_trans = 0, total = 0;
 };
 
@@ -139,12 +140,35 @@ Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& 
     off += align_up(static_cast<size_t>(p.n_nt) * 4, 256);
     p.off_bad = off;
     off += 256;
+    p.off_rules = off;
+    off += align_up(static_cast<size_t>(std::max(gr->n_bin_rules, 1)) * 12, 256);
+    p.off_go = off;
+    off += align_up(static_cast<size_t>(std::max(gr->n_bin_rules, 1)) * 4, 256);
+    p.off_state = off;
+    off += align_up(sizeof(LoopState), 256);
     p.off_second = off;
     if (p.jacobi) off += mat_bytes * p.n_nt;
     p.off_trans = off;
     off += mat_bytes * p.n_right;
     p.total = off;
     return p;
+}
+
+// A private non-blocking stream per thread and device for graph capture (the
+// legacy default stream cannot be captured); graphs are launched on the
+// caller's stream.
+hipError_t capture_stream(hipStream_t* out) {
+    thread_local std::vector<hipStream_t> per_device;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (static_cast<int>(per_device.size()) <= dev) per_device.resize(dev + 1, nullptr);
+    if (!per_device[dev]) {
+        e = hipStreamCreateWithFlags(&per_device[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    *out = per_device[dev];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -164,6 +188,7 @@ void cfpq_default_options(cfpq_options* opt) {
     opt->path = CFPQ_PATH_AUTO;
     opt->schedule = CFPQ_SCHEDULE_INPLACE;
     opt->dirty_worklist = 1;
+    opt->capture = 8;
     opt->max_iters = 0;
 }
 
@@ -204,7 +229,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     if (o.schedule != CFPQ_SCHEDULE_INPLACE && o.schedule != CFPQ_SCHEDULE_JACOBI)
         return fail(CFPQ_EINVAL, "unknown schedule");
     if (o.max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
-    if (o.reserved != 0) return fail(CFPQ_EINVAL, "options.reserved must be 0");
+    if (o.capture < 0) return fail(CFPQ_EINVAL, "options.capture is negative");
     if (o.path == CFPQ_PATH_MFMA && graph->n_nodes > kMfmaMaxNodes)
         return fail(CFPQ_EINVAL, "the MFMA path supports at most 2^19 nodes");
     if (o.tile != 0 && o.path == CFPQ_PATH_BITS && !bits_strip_supported(o.tile, layout_for(graph->n_nodes)))
@@ -295,7 +320,79 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     bool converged = false;
     const bool any_rules = grammar->n_bin_rules > 0 && graph->n_nodes > 0;
     if (!any_rules) converged = true;
-    while (!converged && iters < cap) {
+
+    // ---- captured loops: K loops per HIP graph, loop state on the device ----
+    const bool captured = any_rules && o.capture > 0 && !o.profile;
+    if (captured) {
+        const int32_t n_rules = grammar->n_bin_rules;
+        auto* d_rules = reinterpret_cast<int32_t*>(ws + p.off_rules);
+        auto* d_go = reinterpret_cast<int32_t*>(ws + p.off_go);
+        auto* st = reinterpret_cast<LoopState*>(ws + p.off_state);
+        std::vector<int32_t> rules(3 * static_cast<size_t>(n_rules));
+        for (int32_t r = 0; r < n_rules; ++r) {
+            rules[3 * r] = grammar->bin_rules[r].lhs;
+            rules[3 * r + 1] = grammar->bin_rules[r].left;
+            rules[3 * r + 2] = grammar->bin_rules[r].right;
+        }
+        CFPQ_HIP(hipMemcpyAsync(d_rules, rules.data(), rules.size() * 4, hipMemcpyHostToDevice, s));
+        CFPQ_HIP(launch_loop_state_init(st, s));
+        int32_t K = o.capture;
+        if (p.jacobi && (K & 1)) ++K;  // buffers swap every loop: an even count restores them
+        hipStream_t cs = nullptr;
+        CFPQ_HIP(capture_stream(&cs));
+        hipGraph_t g = nullptr;
+        hipGraphExec_t exec = nullptr;
+        struct GraphGuard {
+            hipGraph_t& g;
+            hipGraphExec_t& e;
+            ~GraphGuard() {
+                if (e) hipGraphExecDestroy(e);
+                if (g) hipGraphDestroy(g);
+            }
+        } gguard{g, exec};
+        CFPQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        uint64_t* cx = X;
+        uint64_t* cy = Y;
+        for (int32_t it = 0; it < K && ce == hipSuccess; ++it) {
+            ce = launch_plan(st, d_go, d_rules, n_rules, n_nt, o.dirty_worklist, cap, cs);
+            for (int32_t r = 0; r < n_rules && ce == hipSuccess; ++r) {
+                const auto& br = grammar->bin_rules[r];
+                int32_t* flag = &st->changed[br.lhs];
+                if (p.path == CFPQ_PATH_MFMA)
+                    ce = launch_mfma_product(cx + br.left * mat_words, TT + p.right_slot[br.right] * mat_words,
+                                             cy + br.lhs * mat_words, L, flag, cs, d_go + r);
+                else
+                    ce = launch_bits_product(cx + br.left * mat_words, cx + br.right * mat_words,
+                                             cy + br.lhs * mat_words, L, flag, cs, o.tile, d_go + r);
+            }
+            for (int32_t a = 0; a < n_nt && ce == hipSuccess; ++a) {
+                if (p.right_slot[a] >= 0)
+                    ce = launch_transpose(cy + a * mat_words, TT + p.right_slot[a] * mat_words, L, cs,
+                                          &st->changed[a]);
+                if (ce == hipSuccess && p.jacobi)
+                    ce = launch_copy_if(cy + a * mat_words, cx + a * mat_words, mat_words, &st->changed[a], cs);
+            }
+            if (ce == hipSuccess) ce = launch_finish(st, n_nt, cs);
+            if (p.jacobi) std::swap(cx, cy);
+        }
+        hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (ce != hipSuccess) return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+        if (ee != hipSuccess) return fail(CFPQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+        CFPQ_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+        LoopState hs;
+        do {
+            CFPQ_HIP(hipGraphLaunch(exec, s));
+            CFPQ_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+            CFPQ_HIP(hipStreamSynchronize(s));
+        } while (!hs.done);
+        iters = hs.iterations;
+        products = hs.products;
+        converged = hs.capped == 0;
+    }
+
+    // ---- host-driven loop: one flag read-back per loop ----
+    while (!captured && !converged && iters < cap) {
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         size_t launched = 0;
         for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {

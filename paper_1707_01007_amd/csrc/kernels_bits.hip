@@ -25,7 +25,8 @@ template <int R>
 __global__ __launch_bounds__(256) void bits_product_kernel(const uint32_t* __restrict__ Bm,
                                                            const uint32_t* __restrict__ Cm,
                                                            uint32_t* Am, int W2, int kdw,
-                                                           int32_t* changed) {
+                                                           int32_t* changed, const int32_t* go) {
+    if (go != nullptr && *go == 0) return;
     const int strip = blockIdx.x;
     const int row = blockIdx.y * 256 + threadIdx.x;
     const uint32_t* brow = Bm + static_cast<size_t>(row) * W2;
@@ -76,7 +77,7 @@ int bits_default_strip(const Layout& L) {
 }
 
 hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s, int strip) {
+                               int32_t* changed, hipStream_t s, int strip, const int32_t* go) {
     const int W2 = static_cast<int>(2 * L.W);
     const int kdw = static_cast<int>((L.n + 31) / 32);
     if (kdw == 0) return hipSuccess;
@@ -87,9 +88,9 @@ hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A
     auto* a = reinterpret_cast<uint32_t*>(A);
     const dim3 grid(static_cast<unsigned>(W2 / strip), row_blocks);
     switch (strip) {
-        case 32: bits_product_kernel<32><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed); break;
-        case 16: bits_product_kernel<16><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed); break;
-        default: bits_product_kernel<8><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed); break;
+        case 32: bits_product_kernel<32><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed, go); break;
+        case 16: bits_product_kernel<16><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed, go); break;
+        default: bits_product_kernel<8><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed, go); break;
     }
     return hipGetLastError();
 }

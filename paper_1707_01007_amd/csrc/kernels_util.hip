@@ -39,7 +39,9 @@ __global__ void init_scatter_kernel(const cfpq_edge* __restrict__ edges, int64_t
 // of bit j over the lanes, which lane j keeps and writes as row c0 + j of the
 // transpose.
 __global__ __launch_bounds__(256) void transpose_kernel(const uint64_t* __restrict__ src,
-                                                        uint64_t* __restrict__ dst, int64_t W) {
+                                                        uint64_t* __restrict__ dst, int64_t W,
+                                                        const int32_t* __restrict__ pred) {
+    if (pred != nullptr && *pred == 0) return;
     const int lane = threadIdx.x & 63;
     const int64_t blocks = W * W;  // (npad/64)^2 blocks of 64 x 64
     int64_t blk = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -89,10 +91,11 @@ hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s) {
+hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s,
+                            const int32_t* pred) {
     int64_t blocks = L.W * L.W;
     int64_t wgs = (blocks + 3) / 4;
-    transpose_kernel<<<dim3(static_cast<unsigned>(wgs)), dim3(256), 0, s>>>(src, dst, L.W);
+    transpose_kernel<<<dim3(static_cast<unsigned>(wgs)), dim3(256), 0, s>>>(src, dst, L.W, pred);
     return hipGetLastError();
 }
 

@@ -53,10 +53,11 @@ def _digest(bits):
 
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("schedule", SCHEDULES)
-def test_worked_example(cfpq, path, schedule):
+@pytest.mark.parametrize("capture", [0, 1, 8])
+def test_worked_example(cfpq, path, schedule, capture):
     gold = json.load(open(os.path.join(GOLD, "worked_example.json")))
     inst = configs.worked_example()
-    bits, res = _run(cfpq, inst, path=path, schedule=schedule, dirty=(schedule == "inplace"))
+    bits, res = _run(cfpq, inst, path=path, schedule=schedule, dirty=(schedule == "inplace"), capture=capture)
     rel = worklist.relations(bits, inst.n)
     for name in inst.grammar.nonterminals:
         assert rel[inst.grammar.nt(name)] == {tuple(p) for p in gold["relations"][name]}, name
@@ -73,10 +74,12 @@ def test_two_cycles(cfpq, path):
     assert np.array_equal(bits, want)
 
 
-def test_two_cycles_jacobi_loop_count(cfpq):
-    """8065 loops (Lemma 3 with the closed form; the oracle tests pin it)."""
+@pytest.mark.parametrize("capture", [0, 64])
+def test_two_cycles_jacobi_loop_count(cfpq, capture):
+    """8065 loops (Lemma 3 with the closed form; the oracle tests pin it),
+    host-driven and with 64 captured loops per graph."""
     inst = configs.config1()
-    bits, res = _run(cfpq, inst, path="bits", schedule="jacobi", dirty=True)
+    bits, res = _run(cfpq, inst, path="bits", schedule="jacobi", dirty=True, capture=capture)
     assert res.stats["iterations"] == 8065
     assert np.array_equal(bits, worklist.closure(inst.n, inst.edges, inst.grammar))
 
@@ -103,6 +106,18 @@ def test_workload_digest(cfpq, name, path):
     got = [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits]
     assert got == d["counts"]
     assert _digest(bits) == d["sha256"]
+
+
+def test_host_loop_equals_captured_loop(cfpq):
+    """Same loop counts and products with and without device-side loop control."""
+    inst = configs.config3(1024)
+    for schedule in SCHEDULES:
+        a, ra = _run(cfpq, inst, path="bits", schedule=schedule, capture=0)
+        b, rb = _run(cfpq, inst, path="bits", schedule=schedule, capture=3)
+        assert np.array_equal(a, b)
+        if schedule == "jacobi":
+            assert ra.stats["iterations"] == rb.stats["iterations"]
+            assert ra.stats["products"] == rb.stats["products"]
 
 
 def test_jacobi_equals_inplace_er(cfpq):
@@ -179,9 +194,12 @@ def test_device_edges_and_invalid_device_edges(cfpq):
     assert ei.value.status == -1
 
 
-def test_max_iters_partial_is_sound(cfpq):
+@pytest.mark.parametrize("capture", [0, 8])
+def test_max_iters_partial_is_sound(cfpq, capture):
     inst = configs.config1()
-    res = cfpq.closure(inst.n, inst.edges, inst.grammar, schedule="jacobi", max_iters=100, allow_partial=True)
+    res = cfpq.closure(inst.n, inst.edges, inst.grammar, schedule="jacobi", max_iters=100, allow_partial=True,
+                       capture=capture)
+    assert res.stats["iterations"] == 100
     assert res.status == -4 and res.stats["converged"] == 0
     part = worklist.unpack(cfpq.result_bits(res), inst.n)
     full = worklist.unpack(worklist.closure(inst.n, inst.edges, inst.grammar), inst.n)
