@@ -55,6 +55,41 @@ def cpu_baseline(inst, seconds_target=12.0):
                       f"{dt:.1f} s"}
 
 
+def bench_batch(cfpq, torch, steps=3):
+    """Batched closure of the 512-instance workload (sizes log-uniform in
+    [64, 2048], hierarchy or G(n, 3n), same-generation or Dyck) against the
+    same queries run one at a time with the plain closure (no batching, no
+    captured loops).  Edges are in device memory for both."""
+    from workloads import configs
+    insts = configs.config4()
+    items = [(i.n, torch.from_numpy(i.edges).cuda(), i.grammar) for i in insts]
+    torch.cuda.synchronize()
+    res = cfpq.batch_closure(items)  # warmup + buffers
+    outs = [r.bits.view(-1) for r in res]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = cfpq.batch_closure(items, outs=outs)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    bitops = sum(r.stats["bitops"] for r in res)
+    print(f"[bench] batch of {len(items)}: {t_batch * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    for it, o in zip(items[:8], outs[:8]):  # warm the plain path
+        cfpq.closure(*it, capture=0, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it, o in zip(items, outs):
+        cfpq.closure(*it, capture=0, out=o)
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t0
+    print(f"[bench] serial plain: {t_serial * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"workload": "batch512_seed4", "instances": len(items),
+            "queries_per_s": round(len(items) / t_batch, 1), "ms_per_batch": round(t_batch * 1e3, 3),
+            "Gbitop_per_s": round(bitops / t_batch / 1e9, 1),
+            "serial_plain_queries_per_s": round(len(items) / t_serial, 1),
+            "speedup_vs_serial_plain": round(t_serial / t_batch, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +99,7 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "bits", "mfma"])
     ap.add_argument("--schedule", default="inplace", choices=["inplace", "jacobi"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-closure section")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -142,6 +178,8 @@ def main():
                    "loops_per_closure": stats[-1]["iterations"], "products_per_closure": stats[-1]["products"]},
         "roofline": roof,
     }
+    if not args.no_batch:
+        line["batch"] = bench_batch(cfpq, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(line), flush=True)

@@ -188,6 +188,41 @@ CFPQ_API cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, c
 CFPQ_API cfpq_status cfpq_popcount(int32_t n_nodes, int32_t count, const uint64_t* d_mats,
                           unsigned long long* d_counts, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched closure: many independent instances of uneven size in one call.
+ * ------------------------------------------------------------------------ */
+
+/* One query of a batch.  d_result: device buffer of
+ * cfpq_result_bytes(graph.n_nodes, grammar->n_nonterminals) bytes, owned by
+ * the caller, overwritten with that instance's R in the bit layout. */
+typedef struct {
+    cfpq_graph graph;
+    const cfpq_grammar* grammar;
+    uint64_t* d_result;
+} cfpq_instance;
+
+/* Workspace bytes for cfpq_batch_closure with these instances and options. */
+CFPQ_API cfpq_status cfpq_batch_workspace_bytes(int32_t n_instances, const cfpq_instance* instances,
+                                                const cfpq_options* opt, size_t* bytes);
+
+/*
+ * Relational closure (Algorithm 1, in-place schedule) of every instance,
+ * computed together.  Instances with a padded side of at most 512 run their
+ * whole fixpoint in one workgroup each (VALU product); larger ones share a
+ * per-loop work list of 256 x 256 int8-MFMA tiles, with `opt->capture` loops
+ * (0 = 8) per captured HIP graph.  Results are bit-identical to
+ * cfpq_closure on each instance alone.  opt: schedule must be INPLACE;
+ * dirty_worklist, capture and max_iters apply to every instance; path, tile
+ * and profile are ignored.  Instances are limited to 2^19 nodes.
+ * stats: NULL or n_instances entries (device_ms is the whole batch's time).
+ * Returns CFPQ_OK, CFPQ_ENOTCONV (some instance hit max_iters; all results
+ * are sound), CFPQ_EINVAL (message names the instance), CFPQ_ENOMEM or
+ * CFPQ_EDEVICE.  Synchronises `stream` before returning.
+ */
+CFPQ_API cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instances,
+                                        const cfpq_options* opt, void* stream, void* d_workspace,
+                                        size_t workspace_bytes, cfpq_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -127,6 +127,51 @@ def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=Tr
     return Result(int(n), int(grammar.n_nonterminals), bits, st.as_dict(), status)
 
 
+def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=None, stream=None,
+                  outs=None, workspace=None, allow_partial=False):
+    """Closure of many independent instances in one call (``cfpq_batch_closure``).
+
+    ``instances`` is a sequence of (n, edges, grammar); edges on the host or as
+    int32 CUDA tensors.  Returns one ``Result`` per instance (each with its own
+    device result buffer, or the buffers in ``outs``)."""
+    torch = _torch()
+    L = lib()
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    k = len(instances)
+    arr = (_abi.Instance * max(1, k))()
+    keep, results_out = [], []
+    for i, (n, edges, grammar) in enumerate(instances):
+        g, kg = _grammar_struct(grammar)
+        keep.append((g, kg))
+        if isinstance(edges, torch.Tensor) and edges.is_cuda:
+            e = edges.to(torch.int32).contiguous().view(-1, 3)
+            graph = _abi.Graph(int(n), 1, int(e.shape[0]), ctypes.c_void_p(e.data_ptr()))
+        else:
+            e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
+            graph = _abi.Graph(int(n), 0, int(e.shape[0]), ctypes.c_void_p(e.ctypes.data))
+        keep.append(e)
+        words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8
+        out = outs[i] if outs is not None else torch.empty(words, dtype=torch.int64, device=device)
+        results_out.append(out)
+        arr[i] = _abi.Instance(graph, ctypes.pointer(g), ctypes.c_void_p(out.data_ptr()))
+    opt = _options("auto", "inplace", dirty, max_iters, False, 0, capture)
+    need = ctypes.c_size_t(0)
+    _abi.check(L.cfpq_batch_workspace_bytes(k, arr, ctypes.byref(opt), ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=device)
+    stats = (_abi.Stats * max(1, k))()
+    status = L.cfpq_batch_closure(k, arr, ctypes.byref(opt), _stream_ptr(stream), ctypes.c_void_p(workspace.data_ptr()),
+                                  ctypes.c_size_t(workspace.numel()), stats)
+    if status != _abi.CFPQ_OK and not (allow_partial and status == _abi.CFPQ_ENOTCONV):
+        _abi.check(status)
+    res = []
+    for i, (n, edges, grammar) in enumerate(instances):
+        bits = results_out[i].view(int(grammar.n_nonterminals), padded_rows(n), row_words(n))
+        res.append(Result(int(n), int(grammar.n_nonterminals), bits, stats[i].as_dict(), status))
+    del keep
+    return res
+
+
 def result_bits(res: Result) -> np.ndarray:
     """Copy the result to the host as uint64 [|N|, n, ceil(n/64)] (padding
     stripped) -- the same layout the oracle returns."""

@@ -18,6 +18,7 @@ EXPORTED = (
     "cfpq_abi_version", "cfpq_last_error", "cfpq_default_options", "cfpq_row_words",
     "cfpq_padded_rows", "cfpq_result_bytes", "cfpq_workspace_bytes", "cfpq_closure",
     "cfpq_product_workspace_bytes", "cfpq_product", "cfpq_popcount",
+    "cfpq_batch_workspace_bytes", "cfpq_batch_closure",
 )
 
 
@@ -42,6 +43,10 @@ class Grammar(ctypes.Structure):
     _fields_ = [("n_nonterminals", ctypes.c_int32), ("n_terminals", ctypes.c_int32),
                 ("n_term_rules", ctypes.c_int32), ("n_bin_rules", ctypes.c_int32),
                 ("term_rules", ctypes.POINTER(TermRule)), ("bin_rules", ctypes.POINTER(BinRule))]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("graph", Graph), ("grammar", ctypes.POINTER(Grammar)), ("d_result", ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
@@ -99,6 +104,12 @@ def load(path: str = LIB_PATH):
     lib.cfpq_product.restype = ctypes.c_int
     lib.cfpq_popcount.argtypes = [i32, i32, p, p, p]
     lib.cfpq_popcount.restype = ctypes.c_int
+    lib.cfpq_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(Instance), ctypes.POINTER(Options),
+                                               ctypes.POINTER(sz)]
+    lib.cfpq_batch_workspace_bytes.restype = ctypes.c_int
+    lib.cfpq_batch_closure.argtypes = [i32, ctypes.POINTER(Instance), ctypes.POINTER(Options), p, p, sz,
+                                       ctypes.POINTER(Stats)]
+    lib.cfpq_batch_closure.restype = ctypes.c_int
     if lib.cfpq_abi_version() != 1:
         raise ImportError("libcfpq ABI version mismatch")
     _lib = lib

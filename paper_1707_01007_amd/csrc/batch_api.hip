@@ -1,0 +1,354 @@
+// cfpq_batch_closure: many independent instances in one engine run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "batch_engine.h"
+
+namespace cfpq {
+namespace {
+
+// Host-side tables and the workspace carve-up of one batch.
+struct BatchPlan {
+    int32_t n = 0;
+    std::vector<SlotDesc> descs;
+    std::vector<int32_t> rules, trans, term, large, small8, small16, all_ids;
+    std::vector<int64_t> edge_begin;
+    std::vector<size_t> edge_copy_off;  // per slot: byte offset in the edge region, or SIZE_MAX (device edges)
+    int64_t total_edges = 0;
+    int32_t large_rules = 0, large_trans = 0;
+    bool any_device_edges = false;
+    size_t off_descs = 0, off_states = 0, off_rules = 0, off_go = 0, off_trans = 0, off_term = 0;
+    size_t off_jobs = 0, off_tjobs = 0, off_large = 0, off_small8 = 0, off_small16 = 0, off_all = 0;
+    size_t off_edge_begin = 0, off_es = 0, off_edges = 0, off_tt = 0, total = 0;
+    std::vector<size_t> tt_off;  // per slot: byte offset of its transposes (large) in the tt region
+};
+
+cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options& o, BatchPlan& p) {
+    p.n = n;
+    p.descs.resize(n);
+    p.edge_copy_off.assign(n, SIZE_MAX);
+    p.tt_off.assign(n, 0);
+    p.edge_begin.assign(n + 1, 0);
+    size_t edge_bytes = 0, tt_bytes = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const cfpq_graph& g = inst[i].graph;
+        const cfpq_grammar* gr = inst[i].grammar;
+        const Layout L = layout_for(g.n_nodes);
+        SlotDesc& d = p.descs[i];
+        std::memset(&d, 0, sizeof(d));
+        d.n = g.n_nodes;
+        d.W = static_cast<int32_t>(L.W);
+        d.npad = static_cast<int32_t>(L.npad);
+        d.n_nt = gr->n_nonterminals;
+        d.n_edges = g.n_edges;
+        const int64_t nn = g.n_nodes;
+        d.max_iters = o.max_iters > 0 ? o.max_iters : nn * nn * gr->n_nonterminals + 1;
+        d.dirty = o.dirty_worklist ? 1 : 0;
+        d.rule_off = static_cast<int32_t>(p.rules.size() / 3);
+        d.n_rules = (g.n_nodes > 0) ? gr->n_bin_rules : 0;
+        for (int32_t r = 0; r < d.n_rules; ++r) {
+            p.rules.push_back(gr->bin_rules[r].lhs);
+            p.rules.push_back(gr->bin_rules[r].left);
+            p.rules.push_back(gr->bin_rules[r].right);
+        }
+        d.n_terminals = gr->n_terminals;
+        d.term_off = static_cast<int32_t>(p.term.size());
+        std::vector<int32_t> toff(gr->n_terminals + 1, 0);
+        for (int32_t r = 0; r < gr->n_term_rules; ++r) toff[gr->term_rules[r].terminal + 1]++;
+        for (int32_t x = 0; x < gr->n_terminals; ++x) toff[x + 1] += toff[x];
+        p.term.insert(p.term.end(), toff.begin(), toff.end());
+        d.term_lhs_off = static_cast<int32_t>(p.term.size());
+        std::vector<int32_t> lhs(std::max(gr->n_term_rules, 0));
+        {
+            std::vector<int32_t> fill(toff.begin(), toff.end() - 1);
+            for (int32_t r = 0; r < gr->n_term_rules; ++r)
+                lhs[fill[gr->term_rules[r].terminal]++] = gr->term_rules[r].lhs;
+        }
+        p.term.insert(p.term.end(), lhs.begin(), lhs.end());
+        d.kind = (L.npad <= kSmallMaxPad) ? kSlotSmall : kSlotLarge;
+        d.trans_off = static_cast<int32_t>(p.trans.size());
+        int32_t n_right = 0;
+        std::vector<int32_t> tr(d.n_nt, -1);
+        if (d.kind == kSlotLarge) {
+            for (int32_t r = 0; r < d.n_rules; ++r) {
+                const int32_t c = gr->bin_rules[r].right;
+                if (tr[c] < 0) tr[c] = n_right++;
+            }
+            p.tt_off[i] = tt_bytes;
+            tt_bytes += static_cast<size_t>(n_right) * L.mat_words * 8;
+            p.large_rules += d.n_rules;
+            p.large_trans += n_right;
+        }
+        p.trans.insert(p.trans.end(), tr.begin(), tr.end());
+        p.edge_begin[i + 1] = p.edge_begin[i] + g.n_edges;
+        if (g.edges_on_device) {
+            p.any_device_edges = true;
+        } else if (g.n_edges > 0) {
+            p.edge_copy_off[i] = edge_bytes;
+            edge_bytes += align_up(static_cast<size_t>(g.n_edges) * sizeof(cfpq_edge), 256);
+        }
+        if (d.n_rules == 0) {
+            // nothing to iterate: initialisation only
+        } else if (d.kind == kSlotLarge) {
+            p.large.push_back(i);
+        } else if (d.W == 4) {
+            p.small8.push_back(i);
+        } else {
+            p.small16.push_back(i);
+        }
+        p.all_ids.push_back(i);
+    }
+    p.total_edges = p.edge_begin[n];
+    std::stable_sort(p.large.begin(), p.large.end(),
+                     [&](int32_t a, int32_t b) { return p.descs[a].npad > p.descs[b].npad; });
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(std::max<size_t>(bytes, 1), 256);
+        return at;
+    };
+    p.off_descs = take(sizeof(SlotDesc) * n);
+    p.off_states = take(sizeof(SlotState) * n);
+    p.off_rules = take(4 * p.rules.size());
+    p.off_go = take(4 * (p.rules.size() / 3));
+    p.off_trans = take(4 * p.trans.size());
+    p.off_term = take(4 * p.term.size());
+    p.off_jobs = take(sizeof(Job) * std::max(p.large_rules, 1));
+    p.off_tjobs = take(sizeof(Job) * std::max(p.large_trans, 1));
+    p.off_large = take(4 * p.large.size());
+    p.off_small8 = take(4 * p.small8.size());
+    p.off_small16 = take(4 * p.small16.size());
+    p.off_all = take(4 * p.all_ids.size());
+    p.off_edge_begin = take(8 * p.edge_begin.size());
+    p.off_es = take(sizeof(EngineState));
+    p.off_edges = take(edge_bytes);
+    p.off_tt = take(tt_bytes);
+    p.total = off;
+    return CFPQ_OK;
+}
+
+cfpq_status validate_batch(int32_t n, const cfpq_instance* inst, const cfpq_options& o) {
+    if (n < 0) return fail(CFPQ_EINVAL, "n_instances is negative");
+    if (n > 0 && !inst) return fail(CFPQ_EINVAL, "instances is NULL");
+    if (o.schedule != CFPQ_SCHEDULE_INPLACE)
+        return fail(CFPQ_EINVAL, "the batched engine runs the in-place schedule only");
+    if (o.max_iters < 0 || o.capture < 0) return fail(CFPQ_EINVAL, "negative option");
+    for (int32_t i = 0; i < n; ++i) {
+        cfpq_status st = validate_grammar(inst[i].grammar);
+        if (st != CFPQ_OK) return fail(st, "instance " + std::to_string(i) + ": " + cfpq_last_error());
+        st = validate_graph(&inst[i].graph, inst[i].grammar);
+        if (st != CFPQ_OK) return fail(st, "instance " + std::to_string(i) + ": " + cfpq_last_error());
+        if (!inst[i].d_result) return fail(CFPQ_EINVAL, "instance " + std::to_string(i) + ": d_result is NULL");
+        if (inst[i].graph.n_nodes > kMfmaMaxNodes)
+            return fail(CFPQ_EINVAL, "instance " + std::to_string(i) + ": the batched engine supports at most 2^19 nodes");
+    }
+    return CFPQ_OK;
+}
+
+cfpq_options resolve_batch(const cfpq_options* opt) {
+    cfpq_options o;
+    cfpq_default_options(&o);
+    if (opt) o = *opt;
+    return o;
+}
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+}  // namespace
+}  // namespace cfpq
+
+using namespace cfpq;
+
+extern "C" {
+
+cfpq_status cfpq_batch_workspace_bytes(int32_t n_instances, const cfpq_instance* instances, const cfpq_options* opt,
+                                       size_t* bytes) {
+    clear_last_error();
+    if (!bytes) return fail(CFPQ_EINVAL, "bytes is NULL");
+    const cfpq_options o = resolve_batch(opt);
+    cfpq_status st = validate_batch(n_instances, instances, o);
+    if (st != CFPQ_OK) return st;
+    BatchPlan p;
+    plan_batch(n_instances, instances, o, p);
+    *bytes = p.total;
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instances, const cfpq_options* opt,
+                               void* stream, void* d_workspace, size_t workspace_bytes, cfpq_stats* stats) {
+    clear_last_error();
+    const cfpq_options o = resolve_batch(opt);
+    cfpq_status vst = validate_batch(n_instances, instances, o);
+    if (vst != CFPQ_OK) return vst;
+    BatchPlan p;
+    plan_batch(n_instances, instances, o, p);
+    if (workspace_bytes < p.total || (p.total > 0 && !d_workspace))
+        return fail(CFPQ_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");
+    if (n_instances == 0) return CFPQ_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(d_workspace);
+    EngineBuffers b;
+    b.descs = reinterpret_cast<SlotDesc*>(ws + p.off_descs);
+    b.states = reinterpret_cast<SlotState*>(ws + p.off_states);
+    b.rules_tab = reinterpret_cast<int32_t*>(ws + p.off_rules);
+    b.go_tab = reinterpret_cast<int32_t*>(ws + p.off_go);
+    b.trans_tab = reinterpret_cast<int32_t*>(ws + p.off_trans);
+    b.term_tab = reinterpret_cast<int32_t*>(ws + p.off_term);
+    b.jobs = reinterpret_cast<Job*>(ws + p.off_jobs);
+    b.tjobs = reinterpret_cast<Job*>(ws + p.off_tjobs);
+    b.large_ids = reinterpret_cast<int32_t*>(ws + p.off_large);
+    b.small_ids = reinterpret_cast<int32_t*>(ws + p.off_small8);
+    b.edge_begin = reinterpret_cast<int64_t*>(ws + p.off_edge_begin);
+    b.es = reinterpret_cast<EngineState*>(ws + p.off_es);
+    int32_t* small16_ids = reinterpret_cast<int32_t*>(ws + p.off_small16);
+    int32_t* all_ids = reinterpret_cast<int32_t*>(ws + p.off_all);
+
+    // Final device pointers in the descriptors.
+    for (int32_t i = 0; i < n_instances; ++i) {
+        SlotDesc& d = p.descs[i];
+        d.T = instances[i].d_result;
+        d.TT = reinterpret_cast<uint64_t*>(ws + p.off_tt + p.tt_off[i]);
+        if (instances[i].graph.edges_on_device || p.edge_copy_off[i] == SIZE_MAX)
+            d.edges = instances[i].graph.edges;
+        else
+            d.edges = reinterpret_cast<const cfpq_edge*>(ws + p.off_edges + p.edge_copy_off[i]);
+    }
+    std::vector<SlotState> hstates(n_instances);
+    std::memset(hstates.data(), 0, sizeof(SlotState) * hstates.size());
+    for (int32_t i = 0; i < n_instances; ++i) hstates[i].active = p.descs[i].n_rules > 0 ? 1 : 0;
+    if (p.descs.empty()) return CFPQ_OK;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, fork = nullptr, join = nullptr;
+    CFPQ_HIP(hipEventCreate(&ev0));
+    CFPQ_HIP(hipEventCreate(&ev1));
+    CFPQ_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    CFPQ_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    struct Ev {
+        hipEvent_t a, b, c, d;
+        ~Ev() { hipEventDestroy(a); hipEventDestroy(b); hipEventDestroy(c); hipEventDestroy(d); }
+    } evguard{ev0, ev1, fork, join};
+
+    auto h2d = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    CFPQ_HIP(h2d(b.descs, p.descs.data(), sizeof(SlotDesc) * p.descs.size()));
+    CFPQ_HIP(h2d(b.states, hstates.data(), sizeof(SlotState) * hstates.size()));
+    CFPQ_HIP(h2d(b.rules_tab, p.rules.data(), 4 * p.rules.size()));
+    CFPQ_HIP(h2d(b.trans_tab, p.trans.data(), 4 * p.trans.size()));
+    CFPQ_HIP(h2d(b.term_tab, p.term.data(), 4 * p.term.size()));
+    CFPQ_HIP(h2d(b.large_ids, p.large.data(), 4 * p.large.size()));
+    CFPQ_HIP(h2d(b.small_ids, p.small8.data(), 4 * p.small8.size()));
+    CFPQ_HIP(h2d(small16_ids, p.small16.data(), 4 * p.small16.size()));
+    CFPQ_HIP(h2d(all_ids, p.all_ids.data(), 4 * p.all_ids.size()));
+    CFPQ_HIP(h2d(b.edge_begin, p.edge_begin.data(), 8 * p.edge_begin.size()));
+    for (int32_t i = 0; i < n_instances; ++i) {
+        if (p.edge_copy_off[i] == SIZE_MAX || instances[i].graph.edges_on_device) continue;
+        CFPQ_HIP(h2d(ws + p.off_edges + p.edge_copy_off[i], instances[i].graph.edges,
+                     static_cast<size_t>(instances[i].graph.n_edges) * sizeof(cfpq_edge)));
+    }
+    CFPQ_HIP(hipMemsetAsync(b.es, 0, sizeof(EngineState), s));
+    CFPQ_HIP(hipEventRecord(ev0, s));
+
+    // Matrix initialisation of every instance.
+    CFPQ_HIP(engine_zero(b, all_ids, n_instances, s));
+    CFPQ_HIP(engine_scatter(b, all_ids, n_instances, p.total_edges, s));
+    if (p.any_device_edges) {
+        CFPQ_HIP(hipMemcpyAsync(hstates.data(), b.states, sizeof(SlotState) * hstates.size(),
+                                hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < n_instances; ++i)
+            if (hstates[i].bad_edges)
+                return fail(CFPQ_EINVAL, "instance " + std::to_string(i) + ": " +
+                                             std::to_string(hstates[i].bad_edges) + " device edges out of range");
+    }
+
+    // Small instances: one resident workgroup each, on a side stream.
+    const bool any_small = !p.small8.empty() || !p.small16.empty();
+    hipStream_t side = nullptr;
+    if (any_small) {
+        CFPQ_HIP(aux_stream(&side));
+        CFPQ_HIP(hipEventRecord(fork, s));
+        CFPQ_HIP(hipStreamWaitEvent(side, fork, 0));
+        CFPQ_HIP(engine_resident(b, b.small_ids, static_cast<int32_t>(p.small8.size()), 8, side));
+        CFPQ_HIP(engine_resident(b, small16_ids, static_cast<int32_t>(p.small16.size()), 16, side));
+        CFPQ_HIP(hipEventRecord(join, side));
+    }
+
+    // Large instances: captured loops over the shared work list.
+    const int32_t n_large = static_cast<int32_t>(p.large.size());
+    if (n_large > 0) {
+        const int cus = device_cus();
+        const int32_t grid_p = cus, grid_t = 4 * cus;
+        CFPQ_HIP(engine_tplan(b, n_large, 1, s));
+        CFPQ_HIP(engine_transposes(b, grid_t, s));
+        const int32_t K = o.capture > 0 ? o.capture : 8;
+        hipStream_t cs = nullptr;
+        CFPQ_HIP(capture_stream(&cs));
+        hipGraph_t g = nullptr;
+        hipGraphExec_t exec = nullptr;
+        struct GraphGuard {
+            hipGraph_t& g;
+            hipGraphExec_t& e;
+            ~GraphGuard() {
+                if (e) hipGraphExecDestroy(e);
+                if (g) hipGraphDestroy(g);
+            }
+        } gguard{g, exec};
+        CFPQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int32_t it = 0; it < K && ce == hipSuccess; ++it) {
+            ce = engine_plan(b, n_large, cs);
+            if (ce == hipSuccess) ce = engine_products(b, grid_p, cs);
+            if (ce == hipSuccess) ce = engine_tplan(b, n_large, 0, cs);
+            if (ce == hipSuccess) ce = engine_transposes(b, grid_t, cs);
+            if (ce == hipSuccess) ce = engine_finish(b, n_large, cs);
+        }
+        hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (ce != hipSuccess) return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+        if (ee != hipSuccess) return fail(CFPQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+        CFPQ_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+        EngineState hes;
+        do {
+            CFPQ_HIP(hipGraphLaunch(exec, s));
+            CFPQ_HIP(hipMemcpyAsync(&hes, b.es, sizeof(hes), hipMemcpyDeviceToHost, s));
+            CFPQ_HIP(hipStreamSynchronize(s));
+        } while (hes.running > 0);
+    }
+    if (any_small) CFPQ_HIP(hipStreamWaitEvent(s, join, 0));
+    CFPQ_HIP(hipEventRecord(ev1, s));
+    CFPQ_HIP(hipMemcpyAsync(hstates.data(), b.states, sizeof(SlotState) * hstates.size(), hipMemcpyDeviceToHost, s));
+    CFPQ_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    CFPQ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    bool all_conv = true;
+    for (int32_t i = 0; i < n_instances; ++i) {
+        const SlotDesc& d = p.descs[i];
+        const bool conv = hstates[i].capped == 0;
+        all_conv = all_conv && conv;
+        if (stats) {
+            cfpq_stats& st = stats[i];
+            st.iterations = hstates[i].iterations;
+            st.products = hstates[i].products;
+            st.bitops = 2.0 * static_cast<double>(d.npad) * d.npad * d.npad * static_cast<double>(st.products);
+            st.device_ms = ms;
+            st.product_ms = 0.0;
+            st.path_used = d.kind == kSlotLarge ? CFPQ_PATH_MFMA : CFPQ_PATH_BITS;
+            st.converged = conv ? 1 : 0;
+        }
+    }
+    if (!all_conv) return fail(CFPQ_ENOTCONV, "max_iters reached before the fixpoint in some instance");
+    return CFPQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Batched closure engine: many independent (graph, grammar) instances of
+// uneven size computed together.  Shared by cfpq_batch_closure and the server.
+//
+// Instances live in "slots" of a device table.  Two kinds:
+//  * small (padded side <= kSmallMaxPad): one workgroup runs the instance's
+//    whole fixpoint in a single resident kernel launch (VALU product with the
+//    right operand staged in LDS, change flags in LDS);
+//  * large: every loop, a plan kernel turns the dirty rules of all running
+//    large slots into a work list of 256 x 256 MFMA tiles, a persistent kernel
+//    pulls tiles from an atomic counter, transposes of the right operands that
+//    changed are rebuilt the same way, and a finish kernel counts the loop and
+//    retires slots that reached their fixpoint.  The loop is captured into a
+//    HIP graph once; which slots take part is data, so the same graph serves a
+//    batch that gains and loses members between replays.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cfpq_internal.h"
+
+namespace cfpq {
+
+constexpr int32_t kSmallMaxPad = 512;
+
+enum : int32_t { kSlotLarge = 1, kSlotSmall = 2 };
+
+struct SlotDesc {
+    uint64_t* T;              // |N| result matrices (bit layout)
+    uint64_t* TT;             // transposed right operands (large slots)
+    const cfpq_edge* edges;   // device edges
+    int64_t n_edges;
+    int64_t max_iters;
+    int32_t n, W, npad, n_nt;
+    int32_t rule_off, n_rules;  // rules_tab[3 * (rule_off + r) ...] = (lhs, left, right)
+    int32_t trans_off;          // trans_tab[trans_off + a] = transpose slot of a, or -1
+    int32_t term_off;           // term_tab[term_off .. term_off + n_terminals] = CSR offsets
+    int32_t term_lhs_off;       // term_tab[term_lhs_off + q] = lhs of terminal rule q
+    int32_t n_terminals;
+    int32_t kind;
+    int32_t dirty;
+};
+
+struct SlotState {
+    int32_t active;     // 1 while the slot runs
+    int32_t done;       // fixpoint reached or cap hit
+    int32_t capped;     // stopped by max_iters
+    int32_t in_loop;    // takes part in the current loop (large slots)
+    int32_t bad_edges;  // edges with an id out of range (device edges)
+    int32_t pad;
+    int64_t iterations;
+    int64_t products;
+    int32_t changed[CFPQ_MAX_NONTERMINALS];
+    int32_t changed_prev[CFPQ_MAX_NONTERMINALS];
+};
+
+struct Job {
+    int32_t slot, what, item_begin, dim;  // what: rule index (products) or nonterminal (transposes)
+};
+
+struct EngineState {
+    int32_t n_jobs, total_items, next_item, pad0;
+    int32_t n_tjobs, total_titems, next_titem, pad1;
+    int32_t running;  // large slots still running after the last finish
+    int32_t pad2[7];
+};
+
+// Device buffers of an engine (all carved from one allocation by the owner).
+struct EngineBuffers {
+    SlotDesc* descs = nullptr;
+    SlotState* states = nullptr;
+    int32_t* rules_tab = nullptr;
+    int32_t* trans_tab = nullptr;
+    int32_t* term_tab = nullptr;
+    int32_t* go_tab = nullptr;
+    Job* jobs = nullptr;
+    Job* tjobs = nullptr;
+    int32_t* large_ids = nullptr;
+    int32_t* small_ids = nullptr;
+    int64_t* edge_begin = nullptr;
+    EngineState* es = nullptr;
+};
+
+// ---- launchers (batch_engine.hip) ----
+hipError_t engine_zero(const EngineBuffers& b, const int32_t* ids, int32_t count, hipStream_t s);
+hipError_t engine_scatter(const EngineBuffers& b, const int32_t* ids, int32_t count, int64_t total_edges,
+                          hipStream_t s);
+hipError_t engine_resident(const EngineBuffers& b, const int32_t* ids, int32_t count, int32_t cw,
+                           hipStream_t s);
+hipError_t engine_plan(const EngineBuffers& b, int32_t n_large, hipStream_t s);
+hipError_t engine_products(const EngineBuffers& b, int32_t grid, hipStream_t s);
+hipError_t engine_tplan(const EngineBuffers& b, int32_t n_large, int32_t all, hipStream_t s);
+hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, hipStream_t s);
+hipError_t engine_finish(const EngineBuffers& b, int32_t n_large, hipStream_t s);
+
+}  // namespace cfpq

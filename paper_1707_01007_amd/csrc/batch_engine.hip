@@ -1,0 +1,445 @@
+// Kernels of the batched closure engine (see batch_engine.h).
+#include "batch_engine.h"
+#include "mfma_tile.h"
+
+namespace cfpq {
+namespace {
+
+// Index k with begin[k] <= x < begin[k + 1] (begin ascending, begin[0] = 0).
+template <typename T>
+__device__ __forceinline__ int find_range(const T* begin, int count, T x) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int job_of(const Job* jobs, int n_jobs, int item) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- init
+
+__global__ __launch_bounds__(256) void engine_zero_kernel(const SlotDesc* __restrict__ descs,
+                                                          const int32_t* __restrict__ ids) {
+    const SlotDesc& d = descs[ids[blockIdx.y]];
+    const size_t quads = static_cast<size_t>(d.n_nt) * d.npad * d.W / 2;  // uint4 units
+    uint4* p = reinterpret_cast<uint4*>(d.T);
+    for (size_t q = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; q < quads;
+         q += static_cast<size_t>(gridDim.x) * blockDim.x)
+        p[q] = make_uint4(0, 0, 0, 0);
+}
+
+// One thread per edge of all listed slots: matrix initialisation of
+// Algorithm 1 (T_ij gains A for every edge (i, x, j) and rule A -> x).
+__global__ __launch_bounds__(256) void engine_scatter_kernel(const SlotDesc* __restrict__ descs,
+                                                             SlotState* states,
+                                                             const int32_t* __restrict__ term_tab,
+                                                             const int32_t* __restrict__ ids, int32_t count,
+                                                             const int64_t* __restrict__ edge_begin,
+                                                             int64_t total) {
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int k = find_range<int64_t>(edge_begin, count, g);
+    const int slot = ids[k];
+    const SlotDesc& d = descs[slot];
+    const cfpq_edge ed = d.edges[g - edge_begin[k]];
+    if (ed.src < 0 || ed.src >= d.n || ed.dst < 0 || ed.dst >= d.n || ed.label < 0 || ed.label >= d.n_terminals) {
+        atomicAdd(&states[slot].bad_edges, 1);
+        return;
+    }
+    const int64_t mw = static_cast<int64_t>(d.npad) * d.W;
+    const int64_t off = static_cast<int64_t>(ed.src) * d.W + (ed.dst >> 6);
+    const unsigned long long bit = 1ull << (ed.dst & 63);
+    const int32_t* toff = term_tab + d.term_off;
+    for (int32_t q = toff[ed.label]; q < toff[ed.label + 1]; ++q) {
+        const int32_t a = term_tab[d.term_lhs_off + q];
+        atomicOr(reinterpret_cast<unsigned long long*>(d.T + a * mw + off), bit);
+    }
+}
+
+// ---------------------------------------------------------------- small slots
+
+// One workgroup runs the whole fixpoint of one small slot (npad <= 512,
+// CW = 2 * W 32-bit words per row).  In-place schedule with the dirty-rule
+// worklist.  Thread t always owns rows t, t + 256, so a row of any matrix is
+// only ever written by one thread; the right operand of each product is staged
+// in LDS after a barrier, so every read sees all earlier writes of the
+// workgroup.  A loop in which no rule set a bit ends the fixpoint.
+template <int CW>
+__global__ __launch_bounds__(256) void engine_resident_kernel(const SlotDesc* __restrict__ descs,
+                                                              SlotState* states,
+                                                              const int32_t* __restrict__ rules_tab,
+                                                              const int32_t* __restrict__ ids) {
+    const int slot = ids[blockIdx.x];
+    const SlotDesc d = descs[slot];
+    __shared__ __align__(16) uint32_t cst[kSmallMaxPad * CW];
+    __shared__ int32_t chg[CFPQ_MAX_NONTERMINALS], prev[CFPQ_MAX_NONTERMINALS];
+    __shared__ int32_t any_s;
+    const int tid = threadIdx.x;
+    const int kdw = (d.n + 31) / 32;  // 32-bit k words (and rows / 32) that can hold bits
+    const int rows = kdw * 32;
+    const size_t mdw = static_cast<size_t>(d.npad) * d.W * 2;  // dwords per matrix
+    uint32_t* T = reinterpret_cast<uint32_t*>(d.T);
+    if (tid < CFPQ_MAX_NONTERMINALS) {
+        chg[tid] = 0;
+        prev[tid] = 0;
+    }
+    int64_t iters = 0, products = 0;
+    int capped = 0;
+    __syncthreads();
+    while (true) {
+        if (iters >= d.max_iters) {
+            capped = 1;
+            break;
+        }
+        for (int r = 0; r < d.n_rules; ++r) {
+            const int ra = rules_tab[3 * (d.rule_off + r)];
+            const int rb = rules_tab[3 * (d.rule_off + r) + 1];
+            const int rc = rules_tab[3 * (d.rule_off + r) + 2];
+            if (d.dirty && iters > 0 && !prev[rb] && !prev[rc]) continue;
+            ++products;
+            const uint32_t* Bm = T + static_cast<size_t>(rb) * mdw;
+            const uint32_t* Cm = T + static_cast<size_t>(rc) * mdw;
+            uint32_t* Am = T + static_cast<size_t>(ra) * mdw;
+            for (int idx = tid; idx < rows * CW; idx += 256) cst[idx] = Cm[idx];  // rows are CW words apart
+            __syncthreads();
+            bool ch = false;
+            for (int row = tid; row < rows; row += 256) {
+                uint32_t acc[CW];
+#pragma unroll
+                for (int c = 0; c < CW; ++c) acc[c] = 0;
+                const uint32_t* brow = Bm + static_cast<size_t>(row) * CW;
+                for (int kw = 0; kw < kdw; ++kw) {
+                    const uint32_t a = brow[kw];
+                    if (a == 0) continue;
+                    const uint32_t* cblk = cst + kw * 32 * CW;
+#pragma unroll 4
+                    for (int kk = 0; kk < 32; ++kk) {
+                        const uint32_t mask = static_cast<uint32_t>(-static_cast<int32_t>((a >> kk) & 1u));
+                        const uint4* crow = reinterpret_cast<const uint4*>(cblk + kk * CW);
+#pragma unroll
+                        for (int c4 = 0; c4 < CW / 4; ++c4) {
+                            const uint4 v = crow[c4];
+                            acc[4 * c4] |= mask & v.x;
+                            acc[4 * c4 + 1] |= mask & v.y;
+                            acc[4 * c4 + 2] |= mask & v.z;
+                            acc[4 * c4 + 3] |= mask & v.w;
+                        }
+                    }
+                }
+                uint32_t* arow = Am + static_cast<size_t>(row) * CW;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const uint32_t old = arow[c];
+                    const uint32_t nw = old | acc[c];
+                    if (nw != old) {
+                        arow[c] = nw;
+                        ch = true;
+                    }
+                }
+            }
+            if (ch) chg[ra] = 1;
+            __syncthreads();
+        }
+        ++iters;
+        if (tid == 0) {
+            int any = 0;
+            for (int a = 0; a < d.n_nt; ++a) any |= chg[a];
+            any_s = any;
+        }
+        __syncthreads();
+        if (!any_s) break;
+        if (tid < CFPQ_MAX_NONTERMINALS) {
+            prev[tid] = chg[tid];
+            chg[tid] = 0;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        SlotState* st = states + slot;
+        st->iterations = iters;
+        st->products = products;
+        st->capped = capped;
+        st->done = 1;
+        st->active = 0;
+    }
+}
+
+// ---------------------------------------------------------------- large slots
+
+// Exclusive scan of per-thread (a, b) counts over one workgroup of 256; the
+// totals land in *ta, *tb.
+__device__ void scan2(int32_t* sa, int32_t* sb, int32_t& a, int32_t& b, int32_t* ta, int32_t* tb) {
+    const int t = threadIdx.x;
+    sa[t] = a;
+    sb[t] = b;
+    __syncthreads();
+    if (t == 0) {
+        int32_t xa = 0, xb = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int32_t va = sa[i], vb = sb[i];
+            sa[i] = xa;
+            sb[i] = xb;
+            xa += va;
+            xb += vb;
+        }
+        *ta = xa;
+        *tb = xb;
+    }
+    __syncthreads();
+    a = sa[t];
+    b = sb[t];
+}
+
+// Start of a loop: for every running large slot decide which rules run
+// (dirty worklist), clear the slot's change flags, and lay out the work list
+// of 256 x 256 tiles.  Slots are handled in list order (largest first), so the
+// biggest tiles are handed out first.
+__global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
+                                                          const int32_t* __restrict__ rules_tab, int32_t* go_tab,
+                                                          Job* jobs, EngineState* es,
+                                                          const int32_t* __restrict__ large_ids, int32_t n_large) {
+    __shared__ int32_t sa[256], sb[256];
+    const int t = threadIdx.x;
+    const int per = (n_large + 255) / 256;
+    const int q0 = t * per, q1 = min(n_large, q0 + per);
+    int32_t my_jobs = 0, my_items = 0;
+    for (int q = q0; q < q1; ++q) {
+        const int slot = large_ids[q];
+        const SlotDesc& d = descs[slot];
+        SlotState* st = states + slot;
+        st->in_loop = 0;
+        if (!st->active) continue;
+        if (st->iterations >= d.max_iters) {
+            st->capped = 1;
+            st->done = 1;
+            st->active = 0;
+            continue;
+        }
+        st->in_loop = 1;
+        for (int a = 0; a < d.n_nt; ++a) st->changed[a] = 0;
+        const int dim = d.npad / 256;
+        int launched = 0;
+        for (int r = 0; r < d.n_rules; ++r) {
+            const int rb = rules_tab[3 * (d.rule_off + r) + 1];
+            const int rc = rules_tab[3 * (d.rule_off + r) + 2];
+            const int go = (!d.dirty || st->iterations == 0 || st->changed_prev[rb] || st->changed_prev[rc]) ? 1 : 0;
+            go_tab[d.rule_off + r] = go;
+            launched += go;
+        }
+        st->products += launched;
+        my_jobs += launched;
+        my_items += launched * dim * dim;
+    }
+    scan2(sa, sb, my_jobs, my_items, &es->n_jobs, &es->total_items);
+    if (t == 0) es->next_item = 0;
+    for (int q = q0; q < q1; ++q) {
+        const int slot = large_ids[q];
+        const SlotDesc& d = descs[slot];
+        if (!states[slot].in_loop) continue;
+        const int dim = d.npad / 256;
+        for (int r = 0; r < d.n_rules; ++r) {
+            if (!go_tab[d.rule_off + r]) continue;
+            jobs[my_jobs++] = Job{slot, r, my_items, dim};
+            my_items += dim * dim;
+        }
+    }
+}
+
+// Persistent product kernel: workgroups pull tiles from the loop's work list.
+__global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
+                                                             const int32_t* __restrict__ rules_tab,
+                                                             const int32_t* __restrict__ trans_tab,
+                                                             const Job* __restrict__ jobs, EngineState* es) {
+    __shared__ int32_t item_s;
+    const int n_jobs = es->n_jobs;
+    const int total = es->total_items;
+    while (true) {
+        if (threadIdx.x == 0) item_s = atomicAdd(&es->next_item, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= total) break;
+        const Job jb = jobs[job_of(jobs, n_jobs, item)];
+        const SlotDesc& d = descs[jb.slot];
+        const int r = d.rule_off + jb.what;
+        const int ra = rules_tab[3 * r], rb = rules_tab[3 * r + 1], rc = rules_tab[3 * r + 2];
+        const int local = item - jb.item_begin;
+        const size_t mdw = static_cast<size_t>(d.npad) * d.W * 2;
+        const uint32_t* Bm = reinterpret_cast<const uint32_t*>(d.T) + rb * mdw;
+        const uint32_t* CT = reinterpret_cast<const uint32_t*>(d.TT) + trans_tab[d.trans_off + rc] * mdw;
+        uint32_t* Am = reinterpret_cast<uint32_t*>(d.T) + ra * mdw;
+        const int kchunks = ((d.n + 255) / 256) * 2;
+        mfma::mfma_tile<true>(Bm, CT, Am, 2 * d.W, kchunks, local / jb.dim, local % jb.dim,
+                              &states[jb.slot].changed[ra]);
+    }
+}
+
+// Work list of transposes: every right operand of every running large slot
+// that changed in this loop (all = 1: every right operand of every active
+// slot, used once before the first loop).
+__global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __restrict__ descs,
+                                                           const SlotState* __restrict__ states,
+                                                           const int32_t* __restrict__ trans_tab, Job* tjobs,
+                                                           EngineState* es, const int32_t* __restrict__ large_ids,
+                                                           int32_t n_large, int32_t all) {
+    __shared__ int32_t sa[256], sb[256];
+    const int t = threadIdx.x;
+    const int per = (n_large + 255) / 256;
+    const int q0 = t * per, q1 = min(n_large, q0 + per);
+    int32_t my_jobs = 0, my_items = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int q = q0; q < q1; ++q) {
+            const int slot = large_ids[q];
+            const SlotDesc& d = descs[slot];
+            const SlotState& st = states[slot];
+            if (all ? !st.active : !st.in_loop) continue;
+            const int items = (d.W * d.W + 3) / 4;
+            for (int a = 0; a < d.n_nt; ++a) {
+                if (trans_tab[d.trans_off + a] < 0) continue;
+                if (!all && !st.changed[a]) continue;
+                if (pass == 1) tjobs[my_jobs] = Job{slot, a, my_items, d.W};
+                ++my_jobs;
+                my_items += items;
+            }
+        }
+        if (pass == 0) {
+            scan2(sa, sb, my_jobs, my_items, &es->n_tjobs, &es->total_titems);
+            if (t == 0) es->next_titem = 0;
+        }
+    }
+}
+
+// Persistent transpose kernel: an item is four 64 x 64 blocks, one per
+// wavefront (ballot transpose as in transpose_kernel).
+__global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* __restrict__ descs,
+                                                               const int32_t* __restrict__ trans_tab,
+                                                               const Job* __restrict__ tjobs, EngineState* es) {
+    __shared__ int32_t item_s;
+    const int n_jobs = es->n_tjobs;
+    const int total = es->total_titems;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    while (true) {
+        if (threadIdx.x == 0) item_s = atomicAdd(&es->next_titem, 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= total) break;
+        const Job jb = tjobs[job_of(tjobs, n_jobs, item)];
+        const SlotDesc& d = descs[jb.slot];
+        const int64_t W = d.W;
+        const int64_t blk = static_cast<int64_t>(item - jb.item_begin) * 4 + wave;
+        if (blk < W * W) {
+            const int64_t mw = static_cast<int64_t>(d.npad) * W;
+            const uint64_t* src = d.T + jb.what * mw;
+            uint64_t* dst = d.TT + trans_tab[d.trans_off + jb.what] * mw;
+            const int64_t br = blk / W, bc = blk % W;
+            const uint64_t word = src[(br * 64 + lane) * W + bc];
+            uint64_t mine = 0;
+#pragma unroll 8
+            for (int j = 0; j < 64; ++j) {
+                const uint64_t col = __ballot((word >> j) & 1ull);
+                mine = (lane == j) ? col : mine;
+            }
+            dst[(bc * 64 + lane) * W + br] = mine;
+        }
+    }
+}
+
+// End of a loop: count it for every slot that took part; a slot whose loop set
+// no bit has reached its fixpoint.
+__global__ __launch_bounds__(256) void engine_finish_kernel(SlotState* states, EngineState* es,
+                                                            const SlotDesc* __restrict__ descs,
+                                                            const int32_t* __restrict__ large_ids, int32_t n_large) {
+    __shared__ int32_t running;
+    if (threadIdx.x == 0) running = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < n_large; q += blockDim.x) {
+        const int slot = large_ids[q];
+        SlotState* st = states + slot;
+        if (st->in_loop) {
+            st->iterations += 1;
+            const int n_nt = descs[slot].n_nt;
+            int any = 0;
+            for (int a = 0; a < n_nt; ++a) any |= st->changed[a];
+            if (!any) {
+                st->done = 1;
+                st->active = 0;
+            } else {
+                for (int a = 0; a < n_nt; ++a) st->changed_prev[a] = st->changed[a];
+            }
+            st->in_loop = 0;
+        }
+        if (st->active) atomicAdd(&running, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) es->running = running;
+}
+
+}  // namespace
+
+hipError_t engine_zero(const EngineBuffers& b, const int32_t* ids, int32_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    engine_zero_kernel<<<dim3(64, static_cast<unsigned>(count)), dim3(256), 0, s>>>(b.descs, ids);
+    return hipGetLastError();
+}
+
+hipError_t engine_scatter(const EngineBuffers& b, const int32_t* ids, int32_t count, int64_t total_edges,
+                          hipStream_t s) {
+    if (count <= 0 || total_edges <= 0) return hipSuccess;
+    const int64_t blocks = (total_edges + 255) / 256;
+    engine_scatter_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(
+        b.descs, b.states, b.term_tab, ids, count, b.edge_begin, total_edges);
+    return hipGetLastError();
+}
+
+hipError_t engine_resident(const EngineBuffers& b, const int32_t* ids, int32_t count, int32_t cw,
+                           hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (cw == 8)
+        engine_resident_kernel<8><<<dim3(static_cast<unsigned>(count)), dim3(256), 0, s>>>(b.descs, b.states,
+                                                                                          b.rules_tab, ids);
+    else
+        engine_resident_kernel<16><<<dim3(static_cast<unsigned>(count)), dim3(256), 0, s>>>(b.descs, b.states,
+                                                                                           b.rules_tab, ids);
+    return hipGetLastError();
+}
+
+hipError_t engine_plan(const EngineBuffers& b, int32_t n_large, hipStream_t s) {
+    engine_plan_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab, b.go_tab, b.jobs, b.es,
+                                                     b.large_ids, n_large);
+    return hipGetLastError();
+}
+
+hipError_t engine_products(const EngineBuffers& b, int32_t grid, hipStream_t s) {
+    engine_product_kernel<<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab,
+                                                                                b.trans_tab, b.jobs, b.es);
+    return hipGetLastError();
+}
+
+hipError_t engine_tplan(const EngineBuffers& b, int32_t n_large, int32_t all, hipStream_t s) {
+    engine_tplan_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.trans_tab, b.tjobs, b.es, b.large_ids,
+                                                      n_large, all);
+    return hipGetLastError();
+}
+
+hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, hipStream_t s) {
+    engine_transpose_kernel<<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, s>>>(b.descs, b.trans_tab, b.tjobs,
+                                                                                  b.es);
+    return hipGetLastError();
+}
+
+hipError_t engine_finish(const EngineBuffers& b, int32_t n_large, hipStream_t s) {
+    engine_finish_kernel<<<dim3(1), dim3(256), 0, s>>>(b.states, b.es, b.descs, b.large_ids, n_large);
+    return hipGetLastError();
+}
+
+}  // namespace cfpq

@@ -5,10 +5,27 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "cfpq.h"
 
 namespace cfpq {
+
+// ---- host helpers (closure.hip) ----
+cfpq_status fail(cfpq_status st, const std::string& msg);  // sets the thread's last error
+void clear_last_error();
+cfpq_status validate_grammar(const cfpq_grammar* g);
+cfpq_status validate_graph(const cfpq_graph* g, const cfpq_grammar* gr);  // host edges checked here
+size_t align_up(size_t x, size_t a);
+hipError_t capture_stream(hipStream_t* out);  // private stream for graph capture
+hipError_t aux_stream(hipStream_t* out);      // private stream for overlapping side work
+
+#define CFPQ_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::cfpq::fail(CFPQ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
 
 // Bit layout of one matrix: npad rows of W uint64 words, npad = 64 * W, W a
 // multiple of 4, so a padded matrix is square and both sides are multiples of

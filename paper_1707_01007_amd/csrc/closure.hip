@@ -38,14 +38,7 @@ cfpq_status fail(cfpq_status st, const std::string& msg) {
     return st;
 }
 
-#define CFPQ_HIP(call)                                                                        \
-    do {                                                                                      \
-        hipError_t e_ = (call);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail(CFPQ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
-    } while (0)
-
-namespace {
+void clear_last_error() { g_last_error.clear(); }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -89,6 +82,8 @@ cfpq_status validate_graph(const cfpq_graph* g, const cfpq_grammar* gr) {
     }
     return CFPQ_OK;
 }
+
+namespace {
 
 cfpq_options resolve(const cfpq_options* opt) {
     cfpq_options o;
@@ -154,24 +149,29 @@ Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& 
     return p;
 }
 
-// A private non-blocking stream per thread and device for graph capture (the
-// legacy default stream cannot be captured); graphs are launched on the
-// caller's stream.
-hipError_t capture_stream(hipStream_t* out) {
-    thread_local std::vector<hipStream_t> per_device;
+}  // namespace
+
+// Private non-blocking streams per thread and device (index 0: graph capture,
+// since the legacy default stream cannot be captured; index 1: side work that
+// overlaps the caller's stream).  Default priority.
+static hipError_t private_stream(int which, hipStream_t* out) {
+    thread_local std::vector<hipStream_t> per_device[2];
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    if (static_cast<int>(per_device.size()) <= dev) per_device.resize(dev + 1, nullptr);
-    if (!per_device[dev]) {
-        e = hipStreamCreateWithFlags(&per_device[dev], hipStreamNonBlocking);
+    auto& v = per_device[which];
+    if (static_cast<int>(v.size()) <= dev) v.resize(dev + 1, nullptr);
+    if (!v[dev]) {
+        e = hipStreamCreateWithFlags(&v[dev], hipStreamNonBlocking);
         if (e != hipSuccess) return e;
     }
-    *out = per_device[dev];
+    *out = v[dev];
     return hipSuccess;
 }
 
-}  // namespace
+hipError_t capture_stream(hipStream_t* out) { return private_stream(0, out); }
+hipError_t aux_stream(hipStream_t* out) { return private_stream(1, out); }
+
 }  // namespace cfpq
 
 using namespace cfpq;

@@ -31,63 +31,10 @@
 // Workgroups go round-robin to the 8 XCDs; the tile order gives each XCD a
 // band of output rows walked in 4 x 8 groups of tiles, so the workgroups that
 // run together on one XCD share 4 row blocks of B and 8 of CT in its L2.
-#include "cfpq_internal.h"
+#include "mfma_tile.h"
 
 namespace cfpq {
 namespace {
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
-
-constexpr int kJT = 4;  // 32-row blocks of j per wavefront
-constexpr int kIT = 4;  // 32-column blocks of i per wavefront
-
-// Operand dwords of one 32-bit k-word for lane half g: dword q keeps bits
-// 8t + q + 4g (t = 0..3) in place, i.e. byte t = (bit ? 2^(q+4g) : 0).
-__device__ __forceinline__ v4i spread(uint32_t w, uint32_t mask0) {
-    v4i r;
-    r[0] = static_cast<int>(w & mask0);
-    r[1] = static_cast<int>(w & (mask0 << 1));
-    r[2] = static_cast<int>(w & (mask0 << 2));
-    r[3] = static_cast<int>(w & (mask0 << 3));
-    return r;
-}
-
-constexpr int kChunkWords = 4;  // 32-bit k-words per fragment row and chunk (128 k)
-
-struct Chunk {
-    uint4 c[kJT];
-    uint4 b[kIT];
-};
-
-__device__ __forceinline__ void load_chunk(Chunk& ch, const uint4* const (&crow)[kJT],
-                                           const uint4* const (&brow)[kIT], int kc) {
-#pragma unroll
-    for (int jb = 0; jb < kJT; ++jb) ch.c[jb] = crow[jb][kc];
-#pragma unroll
-    for (int ib = 0; ib < kIT; ++ib) ch.b[ib] = brow[ib][kc];
-}
-
-__device__ __forceinline__ uint32_t word_of(const uint4& u, int q) {
-    return q == 0 ? u.x : q == 1 ? u.y : q == 2 ? u.z : u.w;
-}
-
-// kChunkWords steps of 32 k: per step 8 operand fragments and 16 MFMAs.
-__device__ __forceinline__ void mma_chunk(v16i (&acc)[kJT][kIT], const Chunk& ch, uint32_t mask0) {
-#pragma unroll
-    for (int s = 0; s < kChunkWords; ++s) {
-        v4i ca[kJT], bb[kIT];
-#pragma unroll
-        for (int jb = 0; jb < kJT; ++jb) ca[jb] = spread(word_of(ch.c[jb], s), mask0);
-#pragma unroll
-        for (int ib = 0; ib < kIT; ++ib) bb[ib] = spread(word_of(ch.b[ib], s), mask0);
-#pragma unroll
-        for (int jb = 0; jb < kJT; ++jb)
-#pragma unroll
-            for (int ib = 0; ib < kIT; ++ib)
-                acc[jb][ib] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ca[jb], bb[ib], acc[jb][ib], 0, 0, 0);
-    }
-}
 
 __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __restrict__ Bm,
                                                            const uint32_t* __restrict__ CT,
@@ -114,84 +61,10 @@ __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __res
         tile_j = wg % tiles_dim;
     }
 
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int g = lane >> 5;          // which 16-k half of a 32-k step this lane feeds
-    const int r32 = lane & 31;
-    const int j0 = tile_j * 256 + (wave & 1) * 128;
-    const int i0 = tile_i * 256 + (wave >> 1) * 128;
-    const uint32_t mask0 = 0x01010101u << (4 * g);
-
-    const uint4* crow[kJT];
-    const uint4* brow[kIT];
-#pragma unroll
-    for (int jb = 0; jb < kJT; ++jb)
-        crow[jb] = reinterpret_cast<const uint4*>(CT + static_cast<size_t>(j0 + jb * 32 + r32) * W2);
-#pragma unroll
-    for (int ib = 0; ib < kIT; ++ib)
-        brow[ib] = reinterpret_cast<const uint4*>(Bm + static_cast<size_t>(i0 + ib * 32 + r32) * W2);
-
-    v16i acc[kJT][kIT];
-#pragma unroll
-    for (int jb = 0; jb < kJT; ++jb)
-#pragma unroll
-        for (int ib = 0; ib < kIT; ++ib)
-#pragma unroll
-            for (int e = 0; e < 16; ++e) acc[jb][ib][e] = 0;
-
-    // Two chunk buffers of 128 k (4 dwords per fragment row), used alternately:
-    // chunk c + 1 is in flight while chunk c is multiplied.  kchunks is even;
-    // the last prefetch re-reads the final chunk instead of branching.
-    Chunk buf0, buf1;
-    load_chunk(buf0, crow, brow, 0);
-    // The scheduling barriers keep each prefetch ahead of the multiplies that
-    // follow it (the scheduler would otherwise sink the loads to their uses).
-    for (int kc = 0; kc < kchunks; kc += 2) {
-        load_chunk(buf1, crow, brow, kc + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        mma_chunk(acc, buf0, mask0);
-        __builtin_amdgcn_sched_barrier(0);
-        load_chunk(buf0, crow, brow, min(kc + 2, kchunks - 1));
-        __builtin_amdgcn_sched_barrier(0);
-        mma_chunk(acc, buf1, mask0);
-        __builtin_amdgcn_sched_barrier(0);
-    }
-
-    // ---- epilogue: threshold, pack along j, OR into A ----
-    // Accumulator e of lane (g, r32) in block (jb, ib) is D[j][i] with
-    // i = i0 + 32 ib + r32 and j = j0 + 32 jb + 8 (e / 4) + 4 g + (e % 4).
-    bool ch = false;
-#pragma unroll
-    for (int ib = 0; ib < kIT; ++ib) {
-        uint32_t word[kJT];
-#pragma unroll
-        for (int jb = 0; jb < kJT; ++jb) {
-            uint32_t w = 0;
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t bit = acc[jb][ib][e] > 0 ? 1u : 0u;
-                w |= bit << (8 * (e / 4) + 4 * g + (e % 4));
-            }
-            word[jb] = w | static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 32, 64));
-        }
-        // lanes with g = 0 write columns j0..j0+63, g = 1 write j0+64..j0+127
-        const uint64_t lo = g == 0 ? word[0] : word[2];
-        const uint64_t hi = g == 0 ? word[1] : word[3];
-        const uint64_t add = lo | (hi << 32);
-        const int i = i0 + ib * 32 + r32;
-        uint64_t* dst = reinterpret_cast<uint64_t*>(Am + static_cast<size_t>(i) * W2) + (j0 / 64) + g;
-        const uint64_t old = *dst;
-        const uint64_t nw = old | add;
-        if (nw != old) {
-            *dst = nw;
-            ch = true;
-        }
-    }
-    if (__ballot(ch) != 0 && lane == 0) atomicOr(changed, 1);
+    mfma::mfma_tile<false>(Bm, CT, Am, W2, kchunks, tile_i, tile_j, changed);
 }
 
 }  // namespace
-
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
                                int32_t* changed, hipStream_t s, const int32_t* go) {
     const int W2 = static_cast<int>(2 * L.W);

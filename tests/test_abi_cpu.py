@@ -131,3 +131,26 @@ def test_product_rejects_bad_arguments():
     assert lib.cfpq_product(64, 1, 0, p, p, p, None, None, 0, None) == _abi.CFPQ_EINVAL     # flag required
     assert lib.cfpq_product_workspace_bytes(256, 1) == 0
     assert lib.cfpq_product_workspace_bytes(256, 2) == lib.cfpq_result_bytes(256, 1)
+
+
+def test_batch_validation_on_host():
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+    inst = (_abi.Instance * 2)(_abi.Instance(gr, ctypes.pointer(g), ctypes.c_void_p(1 << 21)),
+                               _abi.Instance(gr, ctypes.pointer(g), ctypes.c_void_p(1 << 22)))
+    sz = ctypes.c_size_t(0)
+    assert lib.cfpq_batch_workspace_bytes(2, inst, None, ctypes.byref(sz)) == 0 and sz.value > 0
+    opt = _abi.Options()
+    lib.cfpq_default_options(ctypes.byref(opt))
+    opt.schedule = _abi.SCHEDULE_JACOBI
+    assert lib.cfpq_batch_workspace_bytes(2, inst, ctypes.byref(opt), ctypes.byref(sz)) == _abi.CFPQ_EINVAL
+    gr2, g2, keep2 = _structs(edges=((0, 5, 1),))
+    inst[1] = _abi.Instance(gr2, ctypes.pointer(g2), ctypes.c_void_p(1 << 22))
+    assert lib.cfpq_batch_workspace_bytes(2, inst, None, ctypes.byref(sz)) == _abi.CFPQ_EINVAL
+    assert b"instance 1" in lib.cfpq_last_error()
+    rc = lib.cfpq_batch_closure(2, inst, None, None, ctypes.c_void_p(1 << 20), ctypes.c_size_t(1 << 30), None)
+    assert rc == _abi.CFPQ_EINVAL
+    inst[1] = _abi.Instance(gr, ctypes.pointer(g), None)
+    assert lib.cfpq_batch_closure(2, inst, None, None, ctypes.c_void_p(1 << 20), ctypes.c_size_t(1 << 30),
+                                  None) == _abi.CFPQ_EINVAL

@@ -1,0 +1,123 @@
+"""GPU parity of the batched engine (cfpq_batch_closure) against the oracle:
+every instance bit-exact, alone or in the mix."""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import worklist
+from workloads import configs, grammars, graphs
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def cfpq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_01007_amd as m
+    m.lib()
+    return m
+
+
+def _say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def _digest(bits):
+    return hashlib.sha256(np.ascontiguousarray(bits).astype("<u8").tobytes()).hexdigest()
+
+
+def _mixed_instances():
+    insts = [configs.worked_example(), configs.config1()]
+    insts += configs.config4(count=40)
+    n, e = graphs.erdos_renyi(0, 0, 1)
+    insts.append(configs.Instance(0, e, grammars.dyck(), "empty"))
+    n, e = graphs.erdos_renyi(300, 600, 2)
+    insts.append(configs.Instance(n, e, grammars.CNF(("X",), ("a", "b"), ((0, 0),), (), "terminal_only"), "term_only"))
+    n, e = graphs.erdos_renyi(1500, 6000, 3)
+    insts.append(configs.Instance(n, e, grammars.dyck(), "er1500"))
+    n, e = graphs.hierarchy(3000, 4, roots=3, reverse=True)
+    insts.append(configs.Instance(n, e, grammars.same_generation(), "hier3000_rev"))
+    return insts
+
+
+def test_mixed_batch_matches_oracle(cfpq):
+    insts = _mixed_instances()
+    _say("mixed batch", len(insts), "instances, sizes", sorted(i.n for i in insts)[-5:])
+    res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts])
+    for inst, r in zip(insts, res):
+        want = worklist.closure(inst.n, inst.edges, inst.grammar)
+        assert np.array_equal(cfpq.result_bits(r), want), inst.tag
+        assert r.stats["converged"] == 1
+
+
+def test_batch_alone_equals_in_mix(cfpq):
+    """Disjoint-union invariant: the same query gives the same bits alone and
+    inside a batch."""
+    insts = _mixed_instances()
+    mix = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts])
+    for k in (0, 1, 5, len(insts) - 1, len(insts) - 2):
+        inst = insts[k]
+        alone = cfpq.closure(inst.n, inst.edges, inst.grammar)
+        alone_b = cfpq.batch_closure([(inst.n, inst.edges, inst.grammar)])[0]
+        a = cfpq.result_bits(alone)
+        assert np.array_equal(a, cfpq.result_bits(mix[k])), inst.tag
+        assert np.array_equal(a, cfpq.result_bits(alone_b)), inst.tag
+
+
+def test_full_batch_workload_digests(cfpq):
+    """All 512 instances of the batch workload, each against its stored
+    oracle digest."""
+    path = os.path.join(GOLD, "batch_digests.json")
+    if not os.path.exists(path):
+        pytest.skip("batch digests not generated")
+    gold = json.load(open(path))["batch512"]
+    insts = configs.config4()
+    _say("batch512")
+    res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts])
+    for k, (inst, r) in enumerate(zip(insts, res)):
+        bits = cfpq.result_bits(r)
+        assert [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits] == gold[k]["counts"], (k, inst.tag)
+        assert _digest(bits) == gold[k]["sha256"], (k, inst.tag)
+
+
+def test_batch_device_edges_and_errors(cfpq):
+    import torch
+    insts = configs.config4(count=6)
+    items = [(i.n, torch.from_numpy(i.edges).cuda(), i.grammar) for i in insts]
+    res = cfpq.batch_closure(items)
+    for inst, r in zip(insts, res):
+        assert np.array_equal(cfpq.result_bits(r), worklist.closure(inst.n, inst.edges, inst.grammar))
+    bad = insts[3].edges.copy()
+    bad[0, 0] = insts[3].n + 1
+    items[3] = (insts[3].n, torch.from_numpy(bad).cuda(), insts[3].grammar)
+    with pytest.raises(cfpq.CfpqError) as ei:
+        cfpq.batch_closure(items)
+    assert ei.value.status == -1 and "instance 3" in str(ei.value)
+
+
+def test_batch_max_iters_partial_is_sound(cfpq):
+    insts = [configs.config1(), configs.config3(1024)]
+    res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], max_iters=3, allow_partial=True)
+    assert res[0].status == -4
+    for inst, r in zip(insts, res):
+        part = worklist.unpack(cfpq.result_bits(r), inst.n)
+        full = worklist.unpack(worklist.closure(inst.n, inst.edges, inst.grammar), inst.n)
+        assert not (part & ~full).any()
+        assert r.stats["iterations"] == 3 and r.stats["converged"] == 0
+
+
+@pytest.mark.parametrize("capture", [1, 3, 16])
+def test_batch_capture_depths(cfpq, capture):
+    insts = configs.config4(count=12)
+    res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], capture=capture)
+    for inst, r in zip(insts, res):
+        assert np.array_equal(cfpq.result_bits(r), worklist.closure(inst.n, inst.edges, inst.grammar)), inst.tag
