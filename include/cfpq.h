@@ -223,6 +223,67 @@ CFPQ_API cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance
                                         const cfpq_options* opt, void* stream, void* d_workspace,
                                         size_t workspace_bytes, cfpq_stats* stats);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of CFPQ queries.
+ *
+ * A server owns one device allocation of hbm_budget bytes (made once, at
+ * creation) holding its tables and an arena for the queries' matrices,
+ * transposed right operands and edges.  A worker thread admits queued
+ * queries in arrival order whenever a slot is free and the query's footprint
+ * fits the arena, keeps their matrices resident until their fixpoint, and
+ * runs every admitted query's loops together with the others in flight
+ * (the batched engine of cfpq_batch_closure).  On completion the query's
+ * matrices are copied to its d_result and its latency is recorded.
+ * ------------------------------------------------------------------------ */
+
+typedef struct cfpq_server cfpq_server;
+
+typedef struct {
+    size_t hbm_budget;     /* device bytes the server may use (tables + arena); default 8 GiB */
+    int32_t max_slots;     /* queries resident at once, 1..4096; default 256 */
+    int32_t capture;       /* loops per replay of the captured engine loop, 1..256; default 4 */
+    int32_t max_pending;   /* queued (not yet admitted) queries; submit returns CFPQ_EBUSY beyond */
+    int32_t reserved;      /* must be 0 */
+} cfpq_server_config;
+
+typedef struct {
+    int32_t done;          /* 1 when the result is in d_result */
+    cfpq_status status;    /* CFPQ_OK, CFPQ_ENOTCONV, CFPQ_EINVAL (bad device edge) or CFPQ_EDEVICE;
+                              CFPQ_ENOTREADY while running */
+    double queue_ms;       /* submit -> admission */
+    double run_ms;         /* admission -> result copied */
+    double latency_ms;     /* submit -> result copied */
+    cfpq_stats stats;      /* iterations, products, bitops of this query */
+} cfpq_request_info;
+
+CFPQ_API void cfpq_server_default_config(cfpq_server_config* cfg);
+
+/* Create a server on the current device.  stream: hipStream_t for all of the
+ * server's device work, or NULL for a private non-blocking stream.  Fails with
+ * CFPQ_ENOMEM if hbm_budget cannot be allocated or does not cover the tables. */
+CFPQ_API cfpq_status cfpq_server_create(const cfpq_server_config* cfg, void* stream, cfpq_server** out);
+
+/* Queue one query.  graph/grammar are copied (host edges are copied at submit;
+ * device edges must stay valid until the query is done).  d_result: device
+ * buffer of cfpq_result_bytes(n, |N|) bytes, written when the query completes.
+ * Limits: 2^19 nodes, 64 binary rules, 64 terminals, 256 terminal rules.
+ * Returns CFPQ_OK with *ticket set, CFPQ_EINVAL, CFPQ_ENOMEM (the query can
+ * never fit the arena) or CFPQ_EBUSY (queue full).  Thread-safe. */
+CFPQ_API cfpq_status cfpq_server_submit(cfpq_server* srv, const cfpq_graph* graph, const cfpq_grammar* grammar,
+                                        uint64_t* d_result, int64_t* ticket);
+
+/* Non-blocking status of a ticket.  Returns CFPQ_ENOTREADY while queued or
+ * running; once done, fills info, releases the ticket and returns the query's
+ * status.  Thread-safe. */
+CFPQ_API cfpq_status cfpq_server_poll(cfpq_server* srv, int64_t ticket, cfpq_request_info* info);
+
+/* Like cfpq_server_poll but blocks until the query is done. */
+CFPQ_API cfpq_status cfpq_server_wait(cfpq_server* srv, int64_t ticket, cfpq_request_info* info);
+
+/* Stop admitting, finish the queries already admitted, drop queued ones,
+ * free everything.  Returns CFPQ_EDEVICE if the worker hit a HIP error. */
+CFPQ_API cfpq_status cfpq_server_destroy(cfpq_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,7 +46,24 @@ def padded_rows(n: int) -> int:
     return int(lib().cfpq_padded_rows(n))
 
 
+_GRAMMAR_CACHE = {}
+
+
 def _grammar_struct(grammar):
+    """ctypes form of a grammar; memoised for hashable (frozen) grammars."""
+    try:
+        key = (grammar.n_nonterminals, grammar.n_terminals, tuple(grammar.term), tuple(grammar.bin))
+    except TypeError:
+        return _grammar_struct_new(grammar)
+    hit = _GRAMMAR_CACHE.get(key)
+    if hit is None:
+        if len(_GRAMMAR_CACHE) > 4096:
+            _GRAMMAR_CACHE.clear()
+        hit = _GRAMMAR_CACHE[key] = _grammar_struct_new(grammar)
+    return hit
+
+
+def _grammar_struct_new(grammar):
     term = list(grammar.term)
     binr = list(grammar.bin)
     t_arr = (_abi.TermRule * max(1, len(term)))(*[_abi.TermRule(int(a), int(x)) for a, x in term])
@@ -170,6 +187,85 @@ def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=No
         res.append(Result(int(n), int(grammar.n_nonterminals), bits, stats[i].as_dict(), status))
     del keep
     return res
+
+
+class Server:
+    """Continuous-batching server (``cfpq_server_*``).
+
+    ``submit`` queues a query and returns a ticket; ``poll`` returns None while
+    it runs and a dict (done, status, queue_ms, run_ms, latency_ms, stats,
+    result) when it is done; ``wait`` blocks.  The result is a ``Result`` whose
+    bits were written by the server into a buffer this object allocated (or the
+    ``out`` given to ``submit``)."""
+
+    def __init__(self, hbm_budget=8 << 30, max_slots=256, capture=4, max_pending=1 << 16, stream=None):
+        torch = _torch()
+        L = lib()
+        cfg = _abi.ServerConfig()
+        L.cfpq_server_default_config(ctypes.byref(cfg))
+        cfg.hbm_budget, cfg.max_slots, cfg.capture, cfg.max_pending = int(hbm_budget), int(max_slots), int(capture), int(max_pending)
+        self._handle = ctypes.c_void_p()
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _abi.check(L.cfpq_server_create(ctypes.byref(cfg), s, ctypes.byref(self._handle)))
+        self._live = {}
+        self._device = torch.device("cuda", torch.cuda.current_device())
+
+    def submit(self, n, edges, grammar, out=None):
+        torch = _torch()
+        L = lib()
+        g, kg = _grammar_struct(grammar)
+        if isinstance(edges, torch.Tensor) and edges.is_cuda:
+            e = edges.to(torch.int32).contiguous().view(-1, 3)
+            graph = _abi.Graph(int(n), 1, int(e.shape[0]), ctypes.c_void_p(e.data_ptr()))
+        else:
+            e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
+            graph = _abi.Graph(int(n), 0, int(e.shape[0]), ctypes.c_void_p(e.ctypes.data))
+        if out is None:
+            words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8
+            out = torch.empty(words, dtype=torch.int64, device=self._device)
+        t = ctypes.c_int64(0)
+        _abi.check(L.cfpq_server_submit(self._handle, ctypes.byref(graph), ctypes.byref(g),
+                                        ctypes.c_void_p(out.data_ptr()), ctypes.byref(t)))
+        self._live[t.value] = (int(n), grammar, out, e, (g, kg))
+        return t.value
+
+    def _finish(self, ticket, status, info):
+        n, grammar, out, _, _ = self._live.pop(ticket)
+        d = info.as_dict()
+        bits = out.view(int(grammar.n_nonterminals), padded_rows(n), row_words(n))
+        d["result"] = Result(n, int(grammar.n_nonterminals), bits, d["stats"], status)
+        return d
+
+    def poll(self, ticket):
+        info = _abi.RequestInfo()
+        st = lib().cfpq_server_poll(self._handle, ctypes.c_int64(ticket), ctypes.byref(info))
+        if st == _abi.CFPQ_ENOTREADY:
+            return None
+        return self._finish(ticket, st, info)
+
+    def wait(self, ticket):
+        info = _abi.RequestInfo()
+        st = lib().cfpq_server_wait(self._handle, ctypes.c_int64(ticket), ctypes.byref(info))
+        return self._finish(ticket, st, info)
+
+    def close(self):
+        if self._handle:
+            st = lib().cfpq_server_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+            _abi.check(st)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self._handle:
+                lib().cfpq_server_destroy(self._handle)
+        except Exception:
+            pass
 
 
 def result_bits(res: Result) -> np.ndarray:

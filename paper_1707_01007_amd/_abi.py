@@ -19,6 +19,8 @@ EXPORTED = (
     "cfpq_padded_rows", "cfpq_result_bytes", "cfpq_workspace_bytes", "cfpq_closure",
     "cfpq_product_workspace_bytes", "cfpq_product", "cfpq_popcount",
     "cfpq_batch_workspace_bytes", "cfpq_batch_closure",
+    "cfpq_server_default_config", "cfpq_server_create", "cfpq_server_submit", "cfpq_server_poll",
+    "cfpq_server_wait", "cfpq_server_destroy",
 )
 
 
@@ -62,6 +64,21 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("capture", ctypes.c_int32),
+                ("max_pending", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("queue_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double), ("stats", Stats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "stats"}
+        d["stats"] = self.stats.as_dict()
+        return d
 
 
 _lib = None
@@ -110,6 +127,18 @@ def load(path: str = LIB_PATH):
     lib.cfpq_batch_closure.argtypes = [i32, ctypes.POINTER(Instance), ctypes.POINTER(Options), p, p, sz,
                                        ctypes.POINTER(Stats)]
     lib.cfpq_batch_closure.restype = ctypes.c_int
+    lib.cfpq_server_default_config.argtypes = [ctypes.POINTER(ServerConfig)]
+    lib.cfpq_server_create.argtypes = [ctypes.POINTER(ServerConfig), p, ctypes.POINTER(p)]
+    lib.cfpq_server_create.restype = ctypes.c_int
+    lib.cfpq_server_submit.argtypes = [p, ctypes.POINTER(Graph), ctypes.POINTER(Grammar), p,
+                                       ctypes.POINTER(ctypes.c_int64)]
+    lib.cfpq_server_submit.restype = ctypes.c_int
+    lib.cfpq_server_poll.argtypes = [p, ctypes.c_int64, ctypes.POINTER(RequestInfo)]
+    lib.cfpq_server_poll.restype = ctypes.c_int
+    lib.cfpq_server_wait.argtypes = [p, ctypes.c_int64, ctypes.POINTER(RequestInfo)]
+    lib.cfpq_server_wait.restype = ctypes.c_int
+    lib.cfpq_server_destroy.argtypes = [p]
+    lib.cfpq_server_destroy.restype = ctypes.c_int
     if lib.cfpq_abi_version() != 1:
         raise ImportError("libcfpq ABI version mismatch")
     _lib = lib

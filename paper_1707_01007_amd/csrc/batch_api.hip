@@ -225,7 +225,10 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
     }
     std::vector<SlotState> hstates(n_instances);
     std::memset(hstates.data(), 0, sizeof(SlotState) * hstates.size());
-    for (int32_t i = 0; i < n_instances; ++i) hstates[i].active = p.descs[i].n_rules > 0 ? 1 : 0;
+    for (int32_t i = 0; i < n_instances; ++i) {
+        hstates[i].active = p.descs[i].n_rules > 0 ? 1 : 0;
+        hstates[i].fresh = 1;
+    }
     if (p.descs.empty()) return CFPQ_OK;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr, fork = nullptr, join = nullptr;
@@ -257,7 +260,10 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
         CFPQ_HIP(h2d(ws + p.off_edges + p.edge_copy_off[i], instances[i].graph.edges,
                      static_cast<size_t>(instances[i].graph.n_edges) * sizeof(cfpq_edge)));
     }
-    CFPQ_HIP(hipMemsetAsync(b.es, 0, sizeof(EngineState), s));
+    EngineState es0;
+    std::memset(&es0, 0, sizeof(es0));
+    es0.n_large = static_cast<int32_t>(p.large.size());
+    CFPQ_HIP(h2d(b.es, &es0, sizeof(es0)));
     CFPQ_HIP(hipEventRecord(ev0, s));
 
     // Matrix initialisation of every instance.
@@ -290,7 +296,7 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
     if (n_large > 0) {
         const int cus = device_cus();
         const int32_t grid_p = cus, grid_t = 4 * cus;
-        CFPQ_HIP(engine_tplan(b, n_large, 1, s));
+        CFPQ_HIP(engine_tplan(b, 1, s));
         CFPQ_HIP(engine_transposes(b, grid_t, s));
         const int32_t K = o.capture > 0 ? o.capture : 8;
         hipStream_t cs = nullptr;
@@ -308,11 +314,11 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
         CFPQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
         for (int32_t it = 0; it < K && ce == hipSuccess; ++it) {
-            ce = engine_plan(b, n_large, cs);
+            ce = engine_plan(b, cs);
             if (ce == hipSuccess) ce = engine_products(b, grid_p, cs);
-            if (ce == hipSuccess) ce = engine_tplan(b, n_large, 0, cs);
+            if (ce == hipSuccess) ce = engine_tplan(b, 0, cs);
             if (ce == hipSuccess) ce = engine_transposes(b, grid_t, cs);
-            if (ce == hipSuccess) ce = engine_finish(b, n_large, cs);
+            if (ce == hipSuccess) ce = engine_finish(b, cs);
         }
         hipError_t ee = hipStreamEndCapture(cs, &g);
         if (ce != hipSuccess) return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));

@@ -49,7 +49,7 @@ struct SlotState {
     int32_t capped;     // stopped by max_iters
     int32_t in_loop;    // takes part in the current loop (large slots)
     int32_t bad_edges;  // edges with an id out of range (device edges)
-    int32_t pad;
+    int32_t fresh;      // admitted, transposes not built yet (large slots)
     int64_t iterations;
     int64_t products;
     int32_t changed[CFPQ_MAX_NONTERMINALS];
@@ -64,7 +64,8 @@ struct EngineState {
     int32_t n_jobs, total_items, next_item, pad0;
     int32_t n_tjobs, total_titems, next_titem, pad1;
     int32_t running;  // large slots still running after the last finish
-    int32_t pad2[7];
+    int32_t n_large;  // entries of the large-slot list (set by the host between replays)
+    int32_t pad2[6];
 };
 
 // Device buffers of an engine (all carved from one allocation by the owner).
@@ -89,10 +90,13 @@ hipError_t engine_scatter(const EngineBuffers& b, const int32_t* ids, int32_t co
                           hipStream_t s);
 hipError_t engine_resident(const EngineBuffers& b, const int32_t* ids, int32_t count, int32_t cw,
                            hipStream_t s);
-hipError_t engine_plan(const EngineBuffers& b, int32_t n_large, hipStream_t s);
+// The large-slot list has es->n_large entries (device memory, so a captured
+// loop serves any membership).  engine_tplan(fresh = 1) builds the first
+// transposes of newly admitted slots and clears their `fresh` flag.
+hipError_t engine_plan(const EngineBuffers& b, hipStream_t s);
 hipError_t engine_products(const EngineBuffers& b, int32_t grid, hipStream_t s);
-hipError_t engine_tplan(const EngineBuffers& b, int32_t n_large, int32_t all, hipStream_t s);
+hipError_t engine_tplan(const EngineBuffers& b, int32_t fresh, hipStream_t s);
 hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, hipStream_t s);
-hipError_t engine_finish(const EngineBuffers& b, int32_t n_large, hipStream_t s);
+hipError_t engine_finish(const EngineBuffers& b, hipStream_t s);
 
 }  // namespace cfpq

@@ -206,9 +206,10 @@ __device__ void scan2(int32_t* sa, int32_t* sb, int32_t& a, int32_t& b, int32_t*
 __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
                                                           const int32_t* __restrict__ rules_tab, int32_t* go_tab,
                                                           Job* jobs, EngineState* es,
-                                                          const int32_t* __restrict__ large_ids, int32_t n_large) {
+                                                          const int32_t* __restrict__ large_ids) {
     __shared__ int32_t sa[256], sb[256];
     const int t = threadIdx.x;
+    const int n_large = es->n_large;
     const int per = (n_large + 255) / 256;
     const int q0 = t * per, q1 = min(n_large, q0 + per);
     int32_t my_jobs = 0, my_items = 0;
@@ -284,15 +285,16 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
 }
 
 // Work list of transposes: every right operand of every running large slot
-// that changed in this loop (all = 1: every right operand of every active
-// slot, used once before the first loop).
+// that changed in this loop (fresh = 1: every right operand of every newly
+// admitted slot, whose `fresh` flag is then cleared).
 __global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __restrict__ descs,
-                                                           const SlotState* __restrict__ states,
+                                                           SlotState* states,
                                                            const int32_t* __restrict__ trans_tab, Job* tjobs,
                                                            EngineState* es, const int32_t* __restrict__ large_ids,
-                                                           int32_t n_large, int32_t all) {
+                                                           int32_t fresh) {
     __shared__ int32_t sa[256], sb[256];
     const int t = threadIdx.x;
+    const int n_large = es->n_large;
     const int per = (n_large + 255) / 256;
     const int q0 = t * per, q1 = min(n_large, q0 + per);
     int32_t my_jobs = 0, my_items = 0;
@@ -300,16 +302,17 @@ __global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __res
         for (int q = q0; q < q1; ++q) {
             const int slot = large_ids[q];
             const SlotDesc& d = descs[slot];
-            const SlotState& st = states[slot];
-            if (all ? !st.active : !st.in_loop) continue;
-            const int items = (d.W * d.W + 3) / 4;
+            SlotState& st = states[slot];
+            if (fresh ? !(st.active && st.fresh) : !st.in_loop) continue;
+            const int items = d.W * d.W;  // 64 x 64 blocks
             for (int a = 0; a < d.n_nt; ++a) {
                 if (trans_tab[d.trans_off + a] < 0) continue;
-                if (!all && !st.changed[a]) continue;
+                if (!fresh && !st.changed[a]) continue;
                 if (pass == 1) tjobs[my_jobs] = Job{slot, a, my_items, d.W};
                 ++my_jobs;
                 my_items += items;
             }
+            if (pass == 1 && fresh) st.fresh = 0;
         }
         if (pass == 0) {
             scan2(sa, sb, my_jobs, my_items, &es->n_tjobs, &es->total_titems);
@@ -318,39 +321,33 @@ __global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __res
     }
 }
 
-// Persistent transpose kernel: an item is four 64 x 64 blocks, one per
-// wavefront (ballot transpose as in transpose_kernel).
+// Transposes of the loop's work list: an item is one 64 x 64 block (ballot
+// transpose as in transpose_kernel); each wavefront takes items
+// w, w + waves, ... (static striding: items are cheap and uniform).
 __global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* __restrict__ descs,
                                                                const int32_t* __restrict__ trans_tab,
                                                                const Job* __restrict__ tjobs, EngineState* es) {
-    __shared__ int32_t item_s;
     const int n_jobs = es->n_tjobs;
     const int total = es->total_titems;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    while (true) {
-        if (threadIdx.x == 0) item_s = atomicAdd(&es->next_titem, 1);
-        __syncthreads();
-        const int item = item_s;
-        __syncthreads();
-        if (item >= total) break;
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * (blockDim.x >> 6);
+    for (int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); item < total; item += waves) {
         const Job jb = tjobs[job_of(tjobs, n_jobs, item)];
         const SlotDesc& d = descs[jb.slot];
         const int64_t W = d.W;
-        const int64_t blk = static_cast<int64_t>(item - jb.item_begin) * 4 + wave;
-        if (blk < W * W) {
-            const int64_t mw = static_cast<int64_t>(d.npad) * W;
-            const uint64_t* src = d.T + jb.what * mw;
-            uint64_t* dst = d.TT + trans_tab[d.trans_off + jb.what] * mw;
-            const int64_t br = blk / W, bc = blk % W;
-            const uint64_t word = src[(br * 64 + lane) * W + bc];
-            uint64_t mine = 0;
+        const int64_t blk = item - jb.item_begin;
+        const int64_t mw = static_cast<int64_t>(d.npad) * W;
+        const uint64_t* src = d.T + jb.what * mw;
+        uint64_t* dst = d.TT + trans_tab[d.trans_off + jb.what] * mw;
+        const int64_t br = blk / W, bc = blk % W;
+        const uint64_t word = src[(br * 64 + lane) * W + bc];
+        uint64_t mine = 0;
 #pragma unroll 8
-            for (int j = 0; j < 64; ++j) {
-                const uint64_t col = __ballot((word >> j) & 1ull);
-                mine = (lane == j) ? col : mine;
-            }
-            dst[(bc * 64 + lane) * W + br] = mine;
+        for (int j = 0; j < 64; ++j) {
+            const uint64_t col = __ballot((word >> j) & 1ull);
+            mine = (lane == j) ? col : mine;
         }
+        dst[(bc * 64 + lane) * W + br] = mine;
     }
 }
 
@@ -358,8 +355,9 @@ __global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* _
 // no bit has reached its fixpoint.
 __global__ __launch_bounds__(256) void engine_finish_kernel(SlotState* states, EngineState* es,
                                                             const SlotDesc* __restrict__ descs,
-                                                            const int32_t* __restrict__ large_ids, int32_t n_large) {
+                                                            const int32_t* __restrict__ large_ids) {
     __shared__ int32_t running;
+    const int n_large = es->n_large;
     if (threadIdx.x == 0) running = 0;
     __syncthreads();
     for (int q = threadIdx.x; q < n_large; q += blockDim.x) {
@@ -413,9 +411,9 @@ hipError_t engine_resident(const EngineBuffers& b, const int32_t* ids, int32_t c
     return hipGetLastError();
 }
 
-hipError_t engine_plan(const EngineBuffers& b, int32_t n_large, hipStream_t s) {
+hipError_t engine_plan(const EngineBuffers& b, hipStream_t s) {
     engine_plan_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab, b.go_tab, b.jobs, b.es,
-                                                     b.large_ids, n_large);
+                                                     b.large_ids);
     return hipGetLastError();
 }
 
@@ -425,9 +423,9 @@ hipError_t engine_products(const EngineBuffers& b, int32_t grid, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t engine_tplan(const EngineBuffers& b, int32_t n_large, int32_t all, hipStream_t s) {
+hipError_t engine_tplan(const EngineBuffers& b, int32_t fresh, hipStream_t s) {
     engine_tplan_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.trans_tab, b.tjobs, b.es, b.large_ids,
-                                                      n_large, all);
+                                                      fresh);
     return hipGetLastError();
 }
 
@@ -437,8 +435,8 @@ hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t engine_finish(const EngineBuffers& b, int32_t n_large, hipStream_t s) {
-    engine_finish_kernel<<<dim3(1), dim3(256), 0, s>>>(b.states, b.es, b.descs, b.large_ids, n_large);
+hipError_t engine_finish(const EngineBuffers& b, hipStream_t s) {
+    engine_finish_kernel<<<dim3(1), dim3(256), 0, s>>>(b.states, b.es, b.descs, b.large_ids);
     return hipGetLastError();
 }
 

@@ -1,0 +1,654 @@
+// Serving with continuous batching: cfpq_server_*.
+//
+// A worker thread owns the engine (batch_engine.h).  Each turn it
+//  1. admits queued requests in arrival order while a slot is free and the
+//     request's HBM footprint fits the arena (first fit),
+//  2. initialises the admitted requests' matrices; small ones start their
+//     resident fixpoint on a side stream, large ones join the shared work list,
+//  3. replays the captured loops of the large engine once (K loops),
+//  4. retires every request that reached its fixpoint: copies its matrices to
+//     the caller's buffer, frees its slot and arena block, stamps its latency.
+// Requests that arrive while others are on the GPU therefore join at the next
+// turn, and their work overlaps on the device with everything in flight.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "batch_engine.h"
+
+namespace cfpq {
+namespace {
+
+constexpr int32_t kSrvMaxRules = 64;       // binary rules per query
+constexpr int32_t kSrvMaxTerminals = 64;   // terminals per query
+constexpr int32_t kSrvMaxTermRules = 256;  // terminal rules per query
+constexpr int32_t kTermStride = kSrvMaxTerminals + 1 + kSrvMaxTermRules;
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    int64_t ticket = 0;
+    int32_t n = 0, n_nt = 0, n_terminals = 0;
+    std::vector<cfpq_term_rule> term;
+    std::vector<cfpq_bin_rule> bin;
+    std::vector<cfpq_edge> host_edges;  // copied at submit (host edges)
+    const cfpq_edge* dev_edges = nullptr;
+    int64_t n_edges = 0;
+    uint64_t* d_result = nullptr;
+    Layout L;
+    bool small = false;
+    int32_t n_right = 0;
+    size_t footprint = 0;
+    // life cycle
+    int32_t slot = -1;
+    size_t arena_off = 0;
+    int32_t state = 0;  // 0 queued, 1 running, 2 done
+    cfpq_status status = CFPQ_OK;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    cfpq_stats stats{};
+    int64_t small_batch = -1;
+};
+
+struct SmallBatch {
+    hipEvent_t done = nullptr;  // recorded after the batch's resident launches
+    int32_t live = 0;           // its requests not yet retired
+};
+
+class Arena {
+  public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = align_up(std::max<size_t>(bytes, 1), 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align_up(std::max<size_t>(bytes, 1), 256);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> free_;
+};
+
+}  // namespace
+}  // namespace cfpq
+
+struct cfpq_server {
+    cfpq_server_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;  // all engine work
+    hipStream_t side = nullptr;    // resident kernels of small requests
+    void* dmem = nullptr;
+    cfpq::EngineBuffers b;
+    int32_t* ids_init = nullptr;   // per admission round: slots to initialise
+    int32_t* ids_small8 = nullptr;
+    int32_t* ids_small16 = nullptr;
+    char* arena_base = nullptr;
+    size_t arena_size = 0;
+    cfpq::Arena arena;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<cfpq::SlotState> hstates;
+    std::vector<int32_t> free_slots;
+    std::vector<cfpq::Request*> slot_req;
+    std::map<int64_t, cfpq::SmallBatch> small_batches;
+    int64_t next_batch = 0;
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::deque<cfpq::Request*> pending;
+    std::unordered_map<int64_t, std::unique_ptr<cfpq::Request>> tickets;
+    int64_t next_ticket = 1;
+    bool stop = false;
+    cfpq_status worker_error = CFPQ_OK;
+    std::string worker_message;
+    std::thread worker;
+    std::atomic<int64_t> completed{0};
+    int cus = 256;
+};
+
+namespace cfpq {
+namespace {
+
+size_t footprint_of(const Request& r) {
+    const size_t mat = static_cast<size_t>(r.L.mat_words) * 8;
+    size_t f = align_up(mat * r.n_nt, 256);
+    if (!r.small) f += align_up(mat * r.n_right, 256);
+    f += align_up(r.host_edges.size() * sizeof(cfpq_edge), 256);
+    return f;
+}
+
+#define SRV_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            srv->worker_error = CFPQ_EDEVICE;                                                      \
+            srv->worker_message = std::string(#call) + ": " + hipGetErrorString(e_);               \
+            return false;                                                                          \
+        }                                                                                          \
+    } while (0)
+
+// Build the descriptor and tables of an admitted request in slot `slot`.
+void fill_slot(cfpq_server* srv, Request& r, SlotDesc& d, std::vector<int32_t>& rules, std::vector<int32_t>& trans,
+               std::vector<int32_t>& term) {
+    const int32_t s = r.slot;
+    std::memset(&d, 0, sizeof(d));
+    char* base = srv->arena_base + r.arena_off;
+    const size_t mat = static_cast<size_t>(r.L.mat_words) * 8;
+    d.T = reinterpret_cast<uint64_t*>(base);
+    size_t off = align_up(mat * r.n_nt, 256);
+    d.TT = reinterpret_cast<uint64_t*>(base + off);
+    if (!r.small) off += align_up(mat * r.n_right, 256);
+    d.edges = r.dev_edges ? r.dev_edges : reinterpret_cast<const cfpq_edge*>(base + off);
+    d.n_edges = r.n_edges;
+    d.n = r.n;
+    d.W = static_cast<int32_t>(r.L.W);
+    d.npad = static_cast<int32_t>(r.L.npad);
+    d.n_nt = r.n_nt;
+    const int64_t nn = r.n;
+    d.max_iters = nn * nn * r.n_nt + 1;
+    d.dirty = 1;
+    d.rule_off = s * kSrvMaxRules;
+    d.n_rules = r.n > 0 ? static_cast<int32_t>(r.bin.size()) : 0;
+    rules.assign(3 * kSrvMaxRules, 0);
+    for (size_t q = 0; q < r.bin.size(); ++q) {
+        rules[3 * q] = r.bin[q].lhs;
+        rules[3 * q + 1] = r.bin[q].left;
+        rules[3 * q + 2] = r.bin[q].right;
+    }
+    d.trans_off = s * CFPQ_MAX_NONTERMINALS;
+    trans.assign(CFPQ_MAX_NONTERMINALS, -1);
+    int32_t nr = 0;
+    if (!r.small)
+        for (const auto& br : r.bin)
+            if (trans[br.right] < 0) trans[br.right] = nr++;
+    d.n_terminals = r.n_terminals;
+    d.term_off = s * kTermStride;
+    d.term_lhs_off = d.term_off + kSrvMaxTerminals + 1;
+    term.assign(kTermStride, 0);
+    std::vector<int32_t> cnt(r.n_terminals + 1, 0);
+    for (const auto& t : r.term) cnt[t.terminal + 1]++;
+    for (int32_t x = 0; x < r.n_terminals; ++x) cnt[x + 1] += cnt[x];
+    for (int32_t x = 0; x <= r.n_terminals; ++x) term[x] = cnt[x];
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (const auto& t : r.term) term[kSrvMaxTerminals + 1 + fill[t.terminal]++] = t.lhs;
+    d.kind = r.small ? kSlotSmall : kSlotLarge;
+}
+
+// One turn of the worker.  Returns false on a device error (recorded in srv).
+bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
+    hipStream_t s = srv->stream;
+    const int32_t S = srv->cfg.max_slots;
+    // ---- 2. initialise admitted requests ----
+    if (!admitted.empty()) {
+        std::vector<int32_t> init_ids, s8, s16;
+        std::vector<int64_t> ebegin(1, 0);
+        for (Request* r : admitted) {
+            SlotDesc d;
+            std::vector<int32_t> rules, trans, term;
+            fill_slot(srv, *r, d, rules, trans, term);
+            SRV_HIP(hipMemcpyAsync(srv->b.descs + r->slot, &d, sizeof(d), hipMemcpyHostToDevice, s));
+            SRV_HIP(hipMemcpyAsync(srv->b.rules_tab + 3 * d.rule_off, rules.data(), rules.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+            SRV_HIP(hipMemcpyAsync(srv->b.trans_tab + d.trans_off, trans.data(), trans.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+            SRV_HIP(hipMemcpyAsync(srv->b.term_tab + d.term_off, term.data(), term.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+            if (!r->host_edges.empty())
+                SRV_HIP(hipMemcpyAsync(const_cast<cfpq_edge*>(d.edges), r->host_edges.data(),
+                                       r->host_edges.size() * sizeof(cfpq_edge), hipMemcpyHostToDevice, s));
+            SlotState st;
+            std::memset(&st, 0, sizeof(st));
+            st.active = d.n_rules > 0 ? 1 : 0;
+            st.fresh = 1;
+            SRV_HIP(hipMemcpyAsync(srv->b.states + r->slot, &st, sizeof(st), hipMemcpyHostToDevice, s));
+            srv->hstates[r->slot] = st;
+            init_ids.push_back(r->slot);
+            ebegin.push_back(ebegin.back() + r->n_edges);
+            if (d.n_rules > 0 && r->small) (d.W == 4 ? s8 : s16).push_back(r->slot);
+        }
+        const int32_t k = static_cast<int32_t>(init_ids.size());
+        SRV_HIP(hipMemcpyAsync(srv->ids_init, init_ids.data(), 4 * k, hipMemcpyHostToDevice, s));
+        SRV_HIP(hipMemcpyAsync(srv->b.edge_begin, ebegin.data(), 8 * ebegin.size(), hipMemcpyHostToDevice, s));
+        SRV_HIP(engine_zero(srv->b, srv->ids_init, k, s));
+        SRV_HIP(engine_scatter(srv->b, srv->ids_init, k, ebegin.back(), s));
+        bool any_dev = false;
+        for (Request* r : admitted) any_dev = any_dev || r->dev_edges != nullptr;
+        if (any_dev) {
+            std::vector<SlotState> tmp(S);
+            SRV_HIP(hipMemcpyAsync(tmp.data(), srv->b.states, sizeof(SlotState) * S, hipMemcpyDeviceToHost, s));
+            SRV_HIP(hipStreamSynchronize(s));
+            for (Request* r : admitted) {
+                if (tmp[r->slot].bad_edges) {
+                    r->status = CFPQ_EINVAL;
+                    SlotState st;
+                    std::memset(&st, 0, sizeof(st));
+                    st.done = 1;
+                    SRV_HIP(hipMemcpyAsync(srv->b.states + r->slot, &st, sizeof(st), hipMemcpyHostToDevice, s));
+                    srv->hstates[r->slot] = st;
+                    s8.erase(std::remove(s8.begin(), s8.end(), r->slot), s8.end());
+                    s16.erase(std::remove(s16.begin(), s16.end(), r->slot), s16.end());
+                }
+            }
+        }
+        if (!s8.empty() || !s16.empty()) {
+            // The slot list of a launch sits at one of 64 ring positions in
+            // device memory; the batch that used the position before must have
+            // finished reading it.
+            const int64_t id = srv->next_batch++;
+            auto prev = srv->small_batches.find(id - 64);
+            if (prev != srv->small_batches.end()) SRV_HIP(hipEventSynchronize(prev->second.done));
+            std::vector<int32_t> both(s8);
+            both.insert(both.end(), s16.begin(), s16.end());
+            int32_t* list = srv->ids_small8 + (id % 64) * S;
+            SRV_HIP(hipMemcpyAsync(list, both.data(), 4 * both.size(), hipMemcpyHostToDevice, s));
+            SmallBatch sb;
+            SRV_HIP(hipEventCreateWithFlags(&sb.done, hipEventDisableTiming));
+            hipEvent_t ready = nullptr;
+            SRV_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+            SRV_HIP(hipEventRecord(ready, s));
+            SRV_HIP(hipStreamWaitEvent(srv->side, ready, 0));
+            hipEventDestroy(ready);
+            SRV_HIP(engine_resident(srv->b, list, static_cast<int32_t>(s8.size()), 8, srv->side));
+            SRV_HIP(engine_resident(srv->b, list + s8.size(), static_cast<int32_t>(s16.size()), 16, srv->side));
+            SRV_HIP(hipEventRecord(sb.done, srv->side));
+            sb.live = static_cast<int32_t>(both.size());
+            for (int32_t q : both) srv->slot_req[q]->small_batch = id;
+            srv->small_batches.emplace(id, sb);
+        }
+    }
+    // ---- 3. large slots: the current list (new ones included), their first
+    //         transposes, then one replay of the captured loops ----
+    std::vector<int32_t> large;
+    for (int32_t q = 0; q < S; ++q) {
+        Request* r = srv->slot_req[q];
+        if (r && !r->small && r->status == CFPQ_OK && srv->hstates[q].active && !srv->hstates[q].done)
+            large.push_back(q);
+    }
+    std::stable_sort(large.begin(), large.end(), [&](int32_t a, int32_t c) {
+        return srv->slot_req[a]->L.npad > srv->slot_req[c]->L.npad;
+    });
+    const int32_t nl = static_cast<int32_t>(large.size());
+    if (nl > 0 || !admitted.empty()) {
+        if (nl > 0)
+            SRV_HIP(hipMemcpyAsync(srv->b.large_ids, large.data(), 4 * large.size(), hipMemcpyHostToDevice, s));
+        SRV_HIP(hipMemcpyAsync(&srv->b.es->n_large, &nl, 4, hipMemcpyHostToDevice, s));
+    }
+    if (!admitted.empty() && nl > 0) {
+        SRV_HIP(engine_tplan(srv->b, 1, s));
+        SRV_HIP(engine_transposes(srv->b, 4 * srv->cus, s));
+    }
+    if (nl > 0) SRV_HIP(hipGraphLaunch(srv->exec, s));
+    // ---- 4. retire ----
+    SRV_HIP(hipMemcpyAsync(srv->hstates.data(), srv->b.states, sizeof(SlotState) * S, hipMemcpyDeviceToHost, s));
+    SRV_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> finished;
+    for (int32_t q = 0; q < S; ++q) {
+        Request* r = srv->slot_req[q];
+        if (!r) continue;
+        if (r->small && r->small_batch >= 0 && r->status == CFPQ_OK) {
+            hipError_t e = hipEventQuery(srv->small_batches.at(r->small_batch).done);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) SRV_HIP(e);
+            SlotState st;
+            SRV_HIP(hipMemcpy(&st, srv->b.states + q, sizeof(st), hipMemcpyDeviceToHost));
+            srv->hstates[q] = st;
+            finished.push_back(q);
+        } else if (r->status != CFPQ_OK || srv->hstates[q].done || !srv->hstates[q].active) {
+            finished.push_back(q);
+        }
+    }
+    if (!finished.empty()) {
+        for (int32_t q : finished) {
+            Request* r = srv->slot_req[q];
+            if (r->status == CFPQ_OK && r->d_result)
+                SRV_HIP(hipMemcpyAsync(r->d_result, srv->arena_base + r->arena_off,
+                                       static_cast<size_t>(r->L.mat_words) * 8 * r->n_nt, hipMemcpyDeviceToDevice, s));
+        }
+        SRV_HIP(hipStreamSynchronize(s));
+        const double t = now_s();
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (int32_t q : finished) {
+            Request* r = srv->slot_req[q];
+            const SlotState& st = srv->hstates[q];
+            r->t_done = t;
+            r->stats.iterations = st.iterations;
+            r->stats.products = st.products;
+            r->stats.bitops = 2.0 * static_cast<double>(r->L.npad) * r->L.npad * r->L.npad * st.products;
+            r->stats.device_ms = (r->t_done - r->t_admit) * 1e3;
+            r->stats.product_ms = 0.0;
+            r->stats.path_used = r->small ? CFPQ_PATH_BITS : CFPQ_PATH_MFMA;
+            r->stats.converged = (r->status == CFPQ_OK && !st.capped) ? 1 : 0;
+            if (r->status == CFPQ_OK && st.capped) r->status = CFPQ_ENOTCONV;
+            r->state = 2;
+            if (r->small && r->small_batch >= 0) srv->small_batches.at(r->small_batch).live -= 1;
+            srv->arena.release(r->arena_off, r->footprint);
+            srv->slot_req[q] = nullptr;
+            srv->free_slots.push_back(q);
+            srv->completed.fetch_add(1);
+        }
+        srv->done_cv.notify_all();
+    }
+    // drop small batches whose requests are all retired
+    for (auto it = srv->small_batches.begin(); it != srv->small_batches.end();) {
+        if (it->second.live == 0) {
+            hipEventDestroy(it->second.done);
+            it = srv->small_batches.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return true;
+}
+
+void worker_main(cfpq_server* srv) {
+    hipSetDevice(srv->device);
+    while (true) {
+        std::vector<Request*> admitted;
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            bool busy = false;
+            for (auto* r : srv->slot_req) busy = busy || r != nullptr;
+            if (!busy && srv->pending.empty())
+                srv->cv.wait(lk, [&] { return srv->stop || !srv->pending.empty(); });
+            if (srv->stop) {
+                bool any = false;
+                for (auto* r : srv->slot_req) any = any || r != nullptr;
+                if (!any) return;
+            }
+            if (srv->stop) srv->pending.clear();  // shutting down: queued queries are dropped
+            // 1. admission: arrival order, a free slot and room in the arena
+            while (!srv->pending.empty() && !srv->free_slots.empty()) {
+                Request* r = srv->pending.front();
+                size_t off = 0;
+                if (!srv->arena.alloc(r->footprint, &off)) break;
+                srv->pending.pop_front();
+                r->arena_off = off;
+                r->slot = srv->free_slots.back();
+                srv->free_slots.pop_back();
+                srv->slot_req[r->slot] = r;
+                r->state = 1;
+                r->t_admit = now_s();
+                admitted.push_back(r);
+            }
+        }
+        if (!turn(srv, admitted)) {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            for (auto& kv : srv->tickets) {
+                if (kv.second->state != 2) {
+                    kv.second->state = 2;
+                    kv.second->status = CFPQ_EDEVICE;
+                }
+            }
+            srv->pending.clear();
+            srv->done_cv.notify_all();
+            return;
+        }
+        bool busy_small_only = true, any = false;
+        for (auto* r : srv->slot_req) {
+            if (!r) continue;
+            any = true;
+            busy_small_only = busy_small_only && r->small;
+        }
+        if (any && busy_small_only) std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+}  // namespace
+}  // namespace cfpq
+
+using namespace cfpq;
+
+extern "C" {
+
+void cfpq_server_default_config(cfpq_server_config* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->hbm_budget = static_cast<size_t>(8) << 30;
+    cfg->max_slots = 256;
+    cfg->capture = 4;
+    cfg->max_pending = 1 << 16;
+}
+
+cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, cfpq_server** out) {
+    clear_last_error();
+    if (!out) return fail(CFPQ_EINVAL, "out is NULL");
+    *out = nullptr;
+    cfpq_server_config cfg;
+    cfpq_server_default_config(&cfg);
+    if (cfg_in) cfg = *cfg_in;
+    if (cfg.max_slots < 1 || cfg.max_slots > 4096) return fail(CFPQ_EINVAL, "max_slots must be in 1..4096");
+    if (cfg.capture < 1 || cfg.capture > 256) return fail(CFPQ_EINVAL, "capture must be in 1..256");
+    if (cfg.max_pending < 1) return fail(CFPQ_EINVAL, "max_pending must be positive");
+    if (cfg.reserved != 0) return fail(CFPQ_EINVAL, "reserved must be 0");
+    auto srv = std::make_unique<cfpq_server>();
+    srv->cfg = cfg;
+    CFPQ_HIP(hipGetDevice(&srv->device));
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, srv->device) == hipSuccess && cus > 0)
+        srv->cus = cus;
+    if (stream) {
+        srv->stream = static_cast<hipStream_t>(stream);
+    } else {
+        CFPQ_HIP(hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking));
+    }
+    CFPQ_HIP(hipStreamCreateWithFlags(&srv->side, hipStreamNonBlocking));
+    const int32_t S = cfg.max_slots;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(std::max<size_t>(bytes, 1), 256);
+        return at;
+    };
+    const size_t o_descs = take(sizeof(SlotDesc) * S), o_states = take(sizeof(SlotState) * S);
+    const size_t o_rules = take(4 * 3 * static_cast<size_t>(kSrvMaxRules) * S);
+    const size_t o_go = take(4 * static_cast<size_t>(kSrvMaxRules) * S);
+    const size_t o_trans = take(4 * static_cast<size_t>(CFPQ_MAX_NONTERMINALS) * S);
+    const size_t o_term = take(4 * static_cast<size_t>(kTermStride) * S);
+    const size_t o_jobs = take(sizeof(Job) * kSrvMaxRules * S);
+    const size_t o_tjobs = take(sizeof(Job) * CFPQ_MAX_NONTERMINALS * S);
+    const size_t o_large = take(4 * static_cast<size_t>(S));
+    const size_t o_init = take(4 * static_cast<size_t>(S));
+    const size_t o_s8 = take(4 * static_cast<size_t>(S) * 64);  // ring of 64 slot lists
+    const size_t o_s16 = take(4 * static_cast<size_t>(S));
+    const size_t o_eb = take(8 * (static_cast<size_t>(S) + 1));
+    const size_t o_es = take(sizeof(EngineState));
+    const size_t tables = off;
+    if (cfg.hbm_budget <= tables) return fail(CFPQ_ENOMEM, "hbm_budget does not cover the server's tables");
+    // One allocation at creation; nothing is allocated per request.
+    CFPQ_HIP(hipMalloc(&srv->dmem, cfg.hbm_budget));
+    char* base = static_cast<char*>(srv->dmem);
+    srv->b.descs = reinterpret_cast<SlotDesc*>(base + o_descs);
+    srv->b.states = reinterpret_cast<SlotState*>(base + o_states);
+    srv->b.rules_tab = reinterpret_cast<int32_t*>(base + o_rules);
+    srv->b.go_tab = reinterpret_cast<int32_t*>(base + o_go);
+    srv->b.trans_tab = reinterpret_cast<int32_t*>(base + o_trans);
+    srv->b.term_tab = reinterpret_cast<int32_t*>(base + o_term);
+    srv->b.jobs = reinterpret_cast<Job*>(base + o_jobs);
+    srv->b.tjobs = reinterpret_cast<Job*>(base + o_tjobs);
+    srv->b.large_ids = reinterpret_cast<int32_t*>(base + o_large);
+    srv->b.edge_begin = reinterpret_cast<int64_t*>(base + o_eb);
+    srv->b.es = reinterpret_cast<EngineState*>(base + o_es);
+    srv->ids_init = reinterpret_cast<int32_t*>(base + o_init);
+    srv->ids_small8 = reinterpret_cast<int32_t*>(base + o_s8);
+    srv->ids_small16 = reinterpret_cast<int32_t*>(base + o_s16);
+    srv->arena_base = base + align_up(tables, 4096);
+    srv->arena_size = cfg.hbm_budget - align_up(tables, 4096);
+    srv->arena.reset(srv->arena_size);
+    CFPQ_HIP(hipMemsetAsync(base, 0, tables, srv->stream));
+    // The large engine's loops, captured once; membership is read from the device.
+    hipStream_t cs = nullptr;
+    CFPQ_HIP(capture_stream(&cs));
+    CFPQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (int32_t it = 0; it < cfg.capture && ce == hipSuccess; ++it) {
+        ce = engine_plan(srv->b, cs);
+        if (ce == hipSuccess) ce = engine_products(srv->b, srv->cus, cs);
+        if (ce == hipSuccess) ce = engine_tplan(srv->b, 0, cs);
+        if (ce == hipSuccess) ce = engine_transposes(srv->b, 4 * srv->cus, cs);
+        if (ce == hipSuccess) ce = engine_finish(srv->b, cs);
+    }
+    hipError_t ee = hipStreamEndCapture(cs, &srv->graph);
+    if (ce != hipSuccess || ee != hipSuccess) {
+        hipFree(srv->dmem);
+        return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
+    }
+    CFPQ_HIP(hipGraphInstantiate(&srv->exec, srv->graph, nullptr, nullptr, 0));
+    CFPQ_HIP(hipStreamSynchronize(srv->stream));
+    srv->hstates.assign(S, SlotState{});
+    srv->slot_req.assign(S, nullptr);
+    for (int32_t q = S - 1; q >= 0; --q) srv->free_slots.push_back(q);
+    cfpq_server* raw = srv.release();
+    raw->worker = std::thread(worker_main, raw);
+    *out = raw;
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_server_submit(cfpq_server* srv, const cfpq_graph* graph, const cfpq_grammar* grammar,
+                               uint64_t* d_result, int64_t* ticket) {
+    clear_last_error();
+    if (!srv || !ticket) return fail(CFPQ_EINVAL, "server or ticket is NULL");
+    cfpq_status st = validate_grammar(grammar);
+    if (st != CFPQ_OK) return st;
+    st = validate_graph(graph, grammar);
+    if (st != CFPQ_OK) return st;
+    if (!d_result) return fail(CFPQ_EINVAL, "d_result is NULL");
+    if (graph->n_nodes > kMfmaMaxNodes) return fail(CFPQ_EINVAL, "the server supports at most 2^19 nodes");
+    if (grammar->n_bin_rules > kSrvMaxRules || grammar->n_terminals > kSrvMaxTerminals ||
+        grammar->n_term_rules > kSrvMaxTermRules)
+        return fail(CFPQ_EINVAL, "grammar exceeds the server's limits (64 binary rules, 64 terminals, "
+                                 "256 terminal rules)");
+    auto r = std::make_unique<Request>();
+    r->n = graph->n_nodes;
+    r->n_nt = grammar->n_nonterminals;
+    r->n_terminals = grammar->n_terminals;
+    r->term.assign(grammar->term_rules, grammar->term_rules + grammar->n_term_rules);
+    r->bin.assign(grammar->bin_rules, grammar->bin_rules + grammar->n_bin_rules);
+    r->n_edges = graph->n_edges;
+    if (graph->edges_on_device) r->dev_edges = graph->edges;
+    else r->host_edges.assign(graph->edges, graph->edges + graph->n_edges);
+    r->d_result = d_result;
+    r->L = layout_for(graph->n_nodes);
+    r->small = r->L.npad <= kSmallMaxPad;
+    std::vector<int32_t> seen(r->n_nt, 0);
+    for (const auto& b : r->bin)
+        if (!seen[b.right]) {
+            seen[b.right] = 1;
+            ++r->n_right;
+        }
+    r->footprint = footprint_of(*r);
+    if (r->footprint > srv->arena_size)
+        return fail(CFPQ_ENOMEM, "request needs " + std::to_string(r->footprint) +
+                                     " bytes, more than the server's arena");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->worker_error != CFPQ_OK) return fail(srv->worker_error, srv->worker_message);
+    if (srv->stop) return fail(CFPQ_EINVAL, "server is shutting down");
+    if (static_cast<int32_t>(srv->pending.size()) >= srv->cfg.max_pending)
+        return fail(CFPQ_EBUSY, "submit queue is full");
+    r->ticket = srv->next_ticket++;
+    r->t_submit = now_s();
+    *ticket = r->ticket;
+    srv->pending.push_back(r.get());
+    srv->tickets[r->ticket] = std::move(r);
+    srv->cv.notify_all();
+    return CFPQ_OK;
+}
+
+static cfpq_status report(cfpq_server* srv, int64_t ticket, cfpq_request_info* info, bool wait) {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->tickets.find(ticket);
+    if (it == srv->tickets.end()) return fail(CFPQ_EINVAL, "unknown ticket");
+    Request* r = it->second.get();
+    if (wait) srv->done_cv.wait(lk, [&] { return r->state == 2; });
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->done = r->state == 2 ? 1 : 0;
+        info->status = r->state == 2 ? r->status : CFPQ_ENOTREADY;
+        if (r->state == 2) {
+            info->queue_ms = (r->t_admit - r->t_submit) * 1e3;
+            info->run_ms = (r->t_done - r->t_admit) * 1e3;
+            info->latency_ms = (r->t_done - r->t_submit) * 1e3;
+            info->stats = r->stats;
+        }
+    }
+    if (r->state != 2) return CFPQ_ENOTREADY;
+    const cfpq_status st = r->status;
+    srv->tickets.erase(it);
+    if (st != CFPQ_OK) return fail(st, "request finished with an error");
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_server_poll(cfpq_server* srv, int64_t ticket, cfpq_request_info* info) {
+    clear_last_error();
+    if (!srv) return fail(CFPQ_EINVAL, "server is NULL");
+    return report(srv, ticket, info, false);
+}
+
+cfpq_status cfpq_server_wait(cfpq_server* srv, int64_t ticket, cfpq_request_info* info) {
+    clear_last_error();
+    if (!srv) return fail(CFPQ_EINVAL, "server is NULL");
+    return report(srv, ticket, info, true);
+}
+
+cfpq_status cfpq_server_destroy(cfpq_server* srv) {
+    clear_last_error();
+    if (!srv) return CFPQ_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->cv.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    hipStreamSynchronize(srv->stream);
+    hipStreamSynchronize(srv->side);
+    for (auto& kv : srv->small_batches)
+        if (kv.second.done) hipEventDestroy(kv.second.done);
+    if (srv->exec) hipGraphExecDestroy(srv->exec);
+    if (srv->graph) hipGraphDestroy(srv->graph);
+    hipStreamDestroy(srv->side);
+    hipFree(srv->dmem);
+    cfpq_status st = srv->worker_error;
+    delete srv;
+    return st;
+}
+
+}  // extern "C"

@@ -154,3 +154,18 @@ def test_batch_validation_on_host():
     inst[1] = _abi.Instance(gr, ctypes.pointer(g), None)
     assert lib.cfpq_batch_closure(2, inst, None, None, ctypes.c_void_p(1 << 20), ctypes.c_size_t(1 << 30),
                                   None) == _abi.CFPQ_EINVAL
+
+
+def test_server_config_validation_on_host():
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    cfg = _abi.ServerConfig()
+    lib.cfpq_server_default_config(ctypes.byref(cfg))
+    assert cfg.max_slots == 256 and cfg.capture == 4 and cfg.hbm_budget == 8 << 30
+    out = ctypes.c_void_p()
+    for field, bad in (("max_slots", 0), ("capture", 0), ("max_pending", 0), ("reserved", 1)):
+        c = _abi.ServerConfig()
+        lib.cfpq_server_default_config(ctypes.byref(c))
+        setattr(c, field, bad)
+        assert lib.cfpq_server_create(ctypes.byref(c), None, ctypes.byref(out)) == _abi.CFPQ_EINVAL, field
+    assert lib.cfpq_server_create(ctypes.byref(cfg), None, None) == _abi.CFPQ_EINVAL

@@ -1,0 +1,144 @@
+"""GPU parity of the continuous-batching server: every query bit-exact
+against the oracle, identical alone and in the mix, under admission pressure
+and with queries arriving while others run."""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import worklist
+from workloads import configs, grammars, graphs
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def cfpq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_01007_amd as m
+    m.lib()
+    return m
+
+
+def _say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def _digest(bits):
+    return hashlib.sha256(np.ascontiguousarray(bits).astype("<u8").tobytes()).hexdigest()
+
+
+def _queries():
+    qs = [configs.worked_example(), configs.config1()]
+    insts, _ = configs.config5(count=24)
+    qs += [i for i in insts if i.n <= 3000]
+    n, e = graphs.erdos_renyi(2500, 10000, 9)
+    qs.append(configs.Instance(n, e, grammars.dyck(), "er2500"))
+    return qs
+
+
+def test_server_results_match_oracle(cfpq):
+    qs = _queries()
+    _say("server", len(qs), "queries")
+    with cfpq.Server(hbm_budget=4 << 30, max_slots=64) as srv:
+        tickets = [srv.submit(q.n, q.edges, q.grammar) for q in qs]
+        infos = [srv.wait(t) for t in tickets]
+    for q, info in zip(qs, infos):
+        assert info["status"] == 0 and info["done"] == 1, q.tag
+        assert np.array_equal(cfpq.result_bits(info["result"]), worklist.closure(q.n, q.edges, q.grammar)), q.tag
+        assert info["latency_ms"] >= info["run_ms"] >= 0
+
+
+def test_server_alone_equals_in_mix(cfpq):
+    qs = _queries()
+    with cfpq.Server(hbm_budget=4 << 30, max_slots=64) as srv:
+        mix = [srv.wait(t) for t in [srv.submit(q.n, q.edges, q.grammar) for q in qs]]
+        for k in (0, 1, 3, len(qs) - 1):
+            alone = srv.wait(srv.submit(qs[k].n, qs[k].edges, qs[k].grammar))
+            a = cfpq.result_bits(alone["result"])
+            assert np.array_equal(a, cfpq.result_bits(mix[k]["result"])), qs[k].tag
+            plain = cfpq.closure(qs[k].n, qs[k].edges, qs[k].grammar)
+            assert np.array_equal(a, cfpq.result_bits(plain)), qs[k].tag
+
+
+def test_server_admission_by_footprint(cfpq):
+    """A budget that holds only a couple of large queries at once: later ones
+    wait in the queue (queue_ms > 0) and still come out exact."""
+    big = []
+    for s in range(6):
+        n, e = graphs.erdos_renyi(2048, 8192, 50 + s)
+        big.append(configs.Instance(n, e, grammars.dyck(), f"er2048_{s}"))
+    # each: 4 matrices + 3 transposes of 512 KiB plus edges, about 3.7 MiB
+    with cfpq.Server(hbm_budget=12 << 20, max_slots=16) as srv:
+        tickets = [srv.submit(q.n, q.edges, q.grammar) for q in big]
+        infos = [srv.wait(t) for t in tickets]
+    assert max(i["queue_ms"] for i in infos) > 0.0
+    for q, info in zip(big, infos):
+        assert np.array_equal(cfpq.result_bits(info["result"]), worklist.closure(q.n, q.edges, q.grammar)), q.tag
+
+
+def test_server_arrivals_while_running(cfpq):
+    """Queries submitted from two threads while earlier ones run."""
+    qs = _queries()
+    out = {}
+    with cfpq.Server(hbm_budget=4 << 30, max_slots=32) as srv:
+        def client(idx):
+            for k in idx:
+                out[k] = srv.submit(qs[k].n, qs[k].edges, qs[k].grammar)
+                time.sleep(0.0005)
+        th = [threading.Thread(target=client, args=(list(range(j, len(qs), 2)),)) for j in range(2)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        infos = {k: srv.wait(t) for k, t in out.items()}
+    for k, info in infos.items():
+        assert np.array_equal(cfpq.result_bits(info["result"]), worklist.closure(qs[k].n, qs[k].edges, qs[k].grammar))
+
+
+def test_server_stream_digests(cfpq):
+    """The first 200 requests of the serving stream against stored oracle digests."""
+    path = os.path.join(GOLD, "batch_digests.json")
+    if not os.path.exists(path):
+        pytest.skip("digests not generated")
+    gold = json.load(open(path))["serve200"]
+    insts, _ = configs.config5(count=200)
+    with cfpq.Server(hbm_budget=16 << 30, max_slots=128) as srv:
+        tickets = [srv.submit(i.n, i.edges, i.grammar) for i in insts]
+        infos = [srv.wait(t) for t in tickets]
+    for k, (inst, info) in enumerate(zip(insts, infos)):
+        bits = cfpq.result_bits(info["result"])
+        assert [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits] == gold[k]["counts"], (k, inst.tag)
+        assert _digest(bits) == gold[k]["sha256"], (k, inst.tag)
+
+
+def test_server_errors(cfpq):
+    import torch
+    g = grammars.dyck()
+    with cfpq.Server(hbm_budget=64 << 20, max_slots=4) as srv:
+        with pytest.raises(cfpq.CfpqError) as ei:
+            srv.submit(10, np.array([[0, 5, 1]], np.int32), g)
+        assert ei.value.status == -1
+        n, e = graphs.erdos_renyi(16384, 100, 1)
+        with pytest.raises(cfpq.CfpqError) as ei:
+            srv.submit(n, e, g)  # 4 matrices of 32 MiB: never fits a 64 MiB budget
+        assert ei.value.status == -2
+        n, e = graphs.erdos_renyi(300, 900, 2)
+        bad = e.copy()
+        bad[3, 2] = 301
+        t = srv.submit(n, torch.from_numpy(bad).cuda(), g)
+        info = srv.wait(t)
+        assert info["status"] == -1
+        ok = srv.wait(srv.submit(n, e, g))
+        assert ok["status"] == 0
+        assert np.array_equal(cfpq.result_bits(ok["result"]), worklist.closure(n, e, g))
