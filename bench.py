@@ -40,19 +40,41 @@ def cpu_baseline(inst, seconds_target=12.0):
         cores = os.cpu_count() or 1
     t0 = alg1.initial_matrix(inst.n, inst.edges, inst.grammar)
     b, c = t0[inst.grammar.nt("A")], t0[inst.grammar.nt("B")]
-    rows = 128
-    t = time.perf_counter()
-    alg1.bool_product(b[:rows], c)
-    dt = time.perf_counter() - t
-    rows = int(min(inst.n, max(rows, rows * seconds_target / max(dt, 1e-6))))
-    t = time.perf_counter()
-    alg1.bool_product(b[:rows], c)
-    dt = time.perf_counter() - t
     n = inst.n
-    return {"value": round(2.0 * rows * n * n / dt / 1e9, 3), "unit": "Gbitop/s", "cores": cores,
+    rows, reps, dt = min(n, 1024), 0, 0.0
+    t = time.perf_counter()
+    alg1.bool_product(b[:rows], c)
+    probe = time.perf_counter() - t
+    rows = int(min(n, max(rows, rows * seconds_target / max(probe, 1e-6))))
+    while dt < seconds_target:
+        t = time.perf_counter()
+        alg1.bool_product(b[:rows], c)
+        dt += time.perf_counter() - t
+        reps += 1
+    return {"value": round(2.0 * rows * n * n * reps / dt / 1e9, 3), "unit": "Gbitop/s", "cores": cores,
             "kind": "oracle",
             "sample": f"oracle Boolean product (float64 BLAS) of rows 0..{rows - 1} of T_A by T_B at n={n}, "
-                      f"{dt:.1f} s"}
+                      f"{reps} time(s), {dt:.1f} s"}
+
+
+def profiled_traffic(profile_md, sources):
+    """HBM bytes per launch from a committed rocprofv3 summary, or None when
+    the kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile_md)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "source_sha256"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if vals.get("source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def bench_batch(cfpq, torch, steps=3):
@@ -198,6 +220,9 @@ def main():
     inst = configs.config3(args.n)
     g = inst.grammar
     edges = torch.from_numpy(inst.edges).cuda()
+    tuned = cfpq.autotune(inst.n) if args.path == "auto" else None
+    if tuned:
+        print(f"[bench] autotune n={inst.n}: {tuned}", file=sys.stderr, flush=True)
     # Every closure here uses the same options as the timed ones: per-product
     # HIP events on the library's stream (host-driven loop, no skipped launches).
     kw = dict(path=args.path, schedule=args.schedule, profile=True)
@@ -229,6 +254,10 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(achieved_t, 1), "peak": round(PEAK_VALU_BITOPS_T, 1),
                 "unit": "TOP/s", "frac": round(achieved_t / PEAK_VALU_BITOPS_T, 4), "traffic": None}
+    if path_used == "mfma":
+        roof["traffic"] = profiled_traffic("mfma_product_er16384_dyck.md",
+                                           ["paper_1707_01007_amd/csrc/mfma_tile.h",
+                                            "paper_1707_01007_amd/csrc/kernels_mfma.hip"])
     roof["kernel"] = "mfma_product_kernel" if path_used == "mfma" else "bits_product_kernel"
     roof["per_launch_bitops"] = per_launch
     line = {
@@ -246,7 +275,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": inst.tag, "n": inst.n, "edges": int(len(inst.edges)), "grammar": g.name,
                    "path": path_used, "schedule": args.schedule,
-                   "loops_per_closure": stats[-1]["iterations"], "products_per_closure": stats[-1]["products"]},
+                   "loops_per_closure": stats[-1]["iterations"], "products_per_closure": stats[-1]["products"],
+                   "autotune": tuned},
         "roofline": roof,
     }
     if not args.no_batch:

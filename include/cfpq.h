@@ -189,6 +189,47 @@ CFPQ_API cfpq_status cfpq_popcount(int32_t n_nodes, int32_t count, const uint64_
                           unsigned long long* d_counts, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Autotuner: the fastest product kernel per size bucket.
+ *
+ * cfpq_autotune times every product variant (int8 MFMA; VALU with 8, 16 and
+ * 32-word strips) on synthetic operands of the padded size for n_nodes and
+ * records the fastest for the bucket ceil(log2(npad)) in a process-wide
+ * table.  The AUTO path of cfpq_closure and cfpq_product then uses it (an
+ * untuned bucket uses MFMA up to 2^19 nodes, else BITS).  All variants give
+ * identical bits.  The environment variable CFPQ_TUNE_CACHE names a JSON file
+ * (as written by cfpq_tune_save) loaded at first use.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t npad;              /* padded size the entry was measured at */
+    int32_t path;              /* CFPQ_PATH_MFMA or CFPQ_PATH_BITS */
+    int32_t tile;              /* BITS strip width (0 = default) */
+    float ms;                  /* the chosen kernel's time per product */
+    int32_t n_candidates;      /* entries used below (filled by cfpq_autotune only) */
+    int32_t candidate_path[4];
+    int32_t candidate_tile[4];
+    float candidates_ms[4];
+} cfpq_tune_entry;
+
+/* Device workspace for cfpq_autotune: four matrices of the bit layout. */
+CFPQ_API size_t cfpq_autotune_workspace_bytes(int32_t n_nodes);
+
+/* Measure and record the bucket of n_nodes (synchronises `stream`). */
+CFPQ_API cfpq_status cfpq_autotune(int32_t n_nodes, void* stream, void* d_workspace, size_t workspace_bytes,
+                                   cfpq_tune_entry* out);
+
+/* The recorded entry for n_nodes' bucket; CFPQ_ENOTREADY if none. */
+CFPQ_API cfpq_status cfpq_tune_get(int32_t n_nodes, cfpq_tune_entry* out);
+
+/* Write / merge-read the table as JSON text; CFPQ_EINVAL if the file cannot
+ * be opened.  Unrecognised lines are ignored. */
+CFPQ_API cfpq_status cfpq_tune_save(const char* path);
+CFPQ_API cfpq_status cfpq_tune_load(const char* path);
+
+/* Forget every entry (and do not read CFPQ_TUNE_CACHE afterwards). */
+CFPQ_API void cfpq_tune_clear(void);
+
+/* ------------------------------------------------------------------------
  * Batched closure: many independent instances of uneven size in one call.
  * ------------------------------------------------------------------------ */
 

@@ -320,3 +320,38 @@ def upload_bits(n: int, host_bits: np.ndarray, device=None):
     buf = np.zeros((count, padded_rows(n), row_words(n)), dtype=np.uint64)
     buf[:, :n, : host_bits.shape[2]] = host_bits
     return torch.from_numpy(buf.view(np.int64)).to(device if device is not None else "cuda")
+
+
+def autotune(n: int, stream=None, device=None) -> dict:
+    """Time every product kernel at size n and record the fastest for n's
+    size bucket (``cfpq_autotune``); AUTO closures then use it."""
+    torch = _torch()
+    L = lib()
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    ws = torch.empty(int(L.cfpq_autotune_workspace_bytes(int(n))), dtype=torch.uint8, device=device)
+    e = _abi.TuneEntry()
+    _abi.check(L.cfpq_autotune(int(n), _stream_ptr(stream), ctypes.c_void_p(ws.data_ptr()),
+                               ctypes.c_size_t(ws.numel()), ctypes.byref(e)))
+    return e.as_dict()
+
+
+def tune_get(n: int):
+    """The recorded tuning entry for n's bucket, or None."""
+    e = _abi.TuneEntry()
+    st = lib().cfpq_tune_get(int(n), ctypes.byref(e))
+    if st == _abi.CFPQ_ENOTREADY:
+        return None
+    _abi.check(st)
+    return e.as_dict()
+
+
+def tune_save(path: str):
+    _abi.check(lib().cfpq_tune_save(str(path).encode()))
+
+
+def tune_load(path: str):
+    _abi.check(lib().cfpq_tune_load(str(path).encode()))
+
+
+def tune_clear():
+    lib().cfpq_tune_clear()

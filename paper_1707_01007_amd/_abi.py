@@ -21,6 +21,8 @@ EXPORTED = (
     "cfpq_batch_workspace_bytes", "cfpq_batch_closure",
     "cfpq_server_default_config", "cfpq_server_create", "cfpq_server_submit", "cfpq_server_poll",
     "cfpq_server_wait", "cfpq_server_destroy",
+    "cfpq_autotune_workspace_bytes", "cfpq_autotune", "cfpq_tune_get", "cfpq_tune_save", "cfpq_tune_load",
+    "cfpq_tune_clear",
 )
 
 
@@ -64,6 +66,19 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("npad", ctypes.c_int32), ("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("n_candidates", ctypes.c_int32), ("candidate_path", ctypes.c_int32 * 4),
+                ("candidate_tile", ctypes.c_int32 * 4), ("candidates_ms", ctypes.c_float * 4)]
+
+    def as_dict(self):
+        names = {PATH_BITS: "bits", PATH_MFMA: "mfma"}
+        cands = {f"{names.get(self.candidate_path[k], '?')}{self.candidate_tile[k] or ''}": round(self.candidates_ms[k], 4)
+                 for k in range(self.n_candidates)}
+        return {"npad": self.npad, "path": names.get(self.path, "?"), "tile": self.tile,
+                "ms": round(self.ms, 4), "candidates_ms": cands}
 
 
 class ServerConfig(ctypes.Structure):
@@ -139,6 +154,18 @@ def load(path: str = LIB_PATH):
     lib.cfpq_server_wait.restype = ctypes.c_int
     lib.cfpq_server_destroy.argtypes = [p]
     lib.cfpq_server_destroy.restype = ctypes.c_int
+    lib.cfpq_autotune_workspace_bytes.argtypes = [i32]
+    lib.cfpq_autotune_workspace_bytes.restype = sz
+    lib.cfpq_autotune.argtypes = [i32, p, p, sz, ctypes.POINTER(TuneEntry)]
+    lib.cfpq_autotune.restype = ctypes.c_int
+    lib.cfpq_tune_get.argtypes = [i32, ctypes.POINTER(TuneEntry)]
+    lib.cfpq_tune_get.restype = ctypes.c_int
+    lib.cfpq_tune_save.argtypes = [ctypes.c_char_p]
+    lib.cfpq_tune_save.restype = ctypes.c_int
+    lib.cfpq_tune_load.argtypes = [ctypes.c_char_p]
+    lib.cfpq_tune_load.restype = ctypes.c_int
+    lib.cfpq_tune_clear.argtypes = []
+    lib.cfpq_tune_clear.restype = None
     if lib.cfpq_abi_version() != 1:
         raise ImportError("libcfpq ABI version mismatch")
     _lib = lib

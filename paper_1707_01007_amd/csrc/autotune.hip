@@ -1,0 +1,246 @@
+// Autotuner: per size bucket, the fastest product kernel (path and tile).
+//
+// cfpq_autotune(n) times every candidate -- the int8 MFMA product and the
+// VALU product with 8, 16 and 32-word strips -- on synthetic operands of the
+// padded size for n (counter-based pseudo-random bits, density 1/2, made on
+// the device), keeps the fastest in a process-wide table keyed by
+// ceil(log2(npad)), and the AUTO path of cfpq_closure / cfpq_product uses
+// that entry.  The table can be saved to and loaded from a small JSON file;
+// the environment variable CFPQ_TUNE_CACHE names a file loaded at first use.
+// Every candidate computes the same bits, so tuning never changes a result.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "cfpq_internal.h"
+
+namespace cfpq {
+namespace {
+
+struct TuneTable {
+    std::mutex mu;
+    std::map<int32_t, cfpq_tune_entry> by_bucket;
+    bool env_loaded = false;
+};
+
+TuneTable& table() {
+    static TuneTable t;
+    return t;
+}
+
+int32_t bucket_of(int64_t npad) {
+    int32_t b = 0;
+    while ((int64_t{1} << b) < npad) ++b;
+    return b;
+}
+
+// splitmix64 of (seed, index): a counter-based generator, so the operands
+// are the same for every launch configuration.
+__global__ void fill_random_kernel(uint64_t* __restrict__ p, size_t words, uint64_t seed) {
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < words;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        uint64_t z = seed + 0x9E3779B97F4A7C15ull * (i + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        p[i] = z ^ (z >> 31);
+    }
+}
+
+const char* path_name(int32_t p) { return p == CFPQ_PATH_MFMA ? "mfma" : "bits"; }
+
+cfpq_status load_file(const char* path, std::map<int32_t, cfpq_tune_entry>& out) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(CFPQ_EINVAL, std::string("cannot open ") + path);
+    char line[512];
+    int n_ok = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        // {"bucket": B, "npad": P, "path": "mfma", "tile": T, "ms": X}
+        cfpq_tune_entry e;
+        std::memset(&e, 0, sizeof e);
+        char name[16] = {0};
+        int bucket = 0;
+        if (std::sscanf(line, " {\"bucket\": %d, \"npad\": %d, \"path\": \"%15[a-z]\", \"tile\": %d, \"ms\": %f",
+                        &bucket, &e.npad, name, &e.tile, &e.ms) == 5) {
+            if (std::strcmp(name, "mfma") == 0) e.path = CFPQ_PATH_MFMA;
+            else if (std::strcmp(name, "bits") == 0) e.path = CFPQ_PATH_BITS;
+            else continue;
+            if (bucket < 0 || bucket > 40 || e.npad <= 0) continue;
+            out[bucket] = e;
+            ++n_ok;
+        }
+    }
+    std::fclose(f);
+    (void)n_ok;
+    return CFPQ_OK;
+}
+
+void ensure_env_loaded(TuneTable& t) {
+    if (t.env_loaded) return;
+    t.env_loaded = true;
+    const char* p = std::getenv("CFPQ_TUNE_CACHE");
+    if (p && *p) {
+        std::map<int32_t, cfpq_tune_entry> m;
+        if (load_file(p, m) == CFPQ_OK)
+            for (auto& kv : m) t.by_bucket[kv.first] = kv.second;
+        clear_last_error();
+    }
+}
+
+}  // namespace
+
+bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile) {
+    TuneTable& t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    ensure_env_loaded(t);
+    auto it = t.by_bucket.find(bucket_of(L.npad));
+    if (it == t.by_bucket.end()) return false;
+    const cfpq_tune_entry& e = it->second;
+    if (e.path == CFPQ_PATH_MFMA && L.n > kMfmaMaxNodes) return false;
+    if (e.path == CFPQ_PATH_BITS && e.tile != 0 && !bits_strip_supported(e.tile, L)) {
+        *path = CFPQ_PATH_BITS;
+        *tile = 0;
+        return true;
+    }
+    *path = e.path;
+    *tile = e.tile;
+    return true;
+}
+
+}  // namespace cfpq
+
+using namespace cfpq;
+
+extern "C" {
+
+size_t cfpq_autotune_workspace_bytes(int32_t n_nodes) {
+    if (n_nodes < 0) return 0;
+    return static_cast<size_t>(layout_for(n_nodes).mat_words) * 8 * 4 + 256;
+}
+
+cfpq_status cfpq_autotune(int32_t n_nodes, void* stream, void* d_workspace, size_t workspace_bytes,
+                          cfpq_tune_entry* out) {
+    clear_last_error();
+    if (n_nodes < 1 || n_nodes > CFPQ_MAX_NODES) return fail(CFPQ_EINVAL, "n_nodes out of range");
+    if (!d_workspace || workspace_bytes < cfpq_autotune_workspace_bytes(n_nodes))
+        return fail(CFPQ_ENOMEM, "workspace smaller than cfpq_autotune_workspace_bytes");
+    const Layout L = layout_for(n_nodes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t mw = static_cast<size_t>(L.mat_words);
+    auto* base = static_cast<uint64_t*>(d_workspace);
+    uint64_t *B = base, *C = base + mw, *A = base + 2 * mw, *CT = base + 3 * mw;
+    auto* flag = reinterpret_cast<int32_t*>(base + 4 * mw);
+    fill_random_kernel<<<dim3(1024), dim3(256), 0, s>>>(base, 2 * mw, 0x5EEDull + static_cast<uint64_t>(n_nodes));
+    CFPQ_HIP(hipGetLastError());
+    CFPQ_HIP(launch_transpose(C, CT, L, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CFPQ_HIP(hipEventCreate(&e0));
+    CFPQ_HIP(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() { hipEventDestroy(a); hipEventDestroy(b); }
+    } guard{e0, e1};
+    struct Cand {
+        int32_t path, tile;
+    };
+    std::vector<Cand> cands;
+    if (L.n <= kMfmaMaxNodes) cands.push_back({CFPQ_PATH_MFMA, 0});
+    for (int strip : {8, 16, 32})
+        if (bits_strip_supported(strip, L)) cands.push_back({CFPQ_PATH_BITS, strip});
+    const double work = static_cast<double>(L.npad) * L.npad * L.npad;
+    const int reps = work > 1e12 ? 2 : (work > 1e10 ? 5 : 20);
+    cfpq_tune_entry best;
+    std::memset(&best, 0, sizeof best);
+    best.npad = static_cast<int32_t>(L.npad);
+    best.ms = 1e30f;
+    for (size_t c = 0; c < cands.size() && c < 4; ++c) {
+        auto launch = [&]() -> hipError_t {
+            if (cands[c].path == CFPQ_PATH_MFMA) return launch_mfma_product(B, CT, A, L, flag, s);
+            return launch_bits_product(B, C, A, L, flag, s, cands[c].tile);
+        };
+        CFPQ_HIP(launch());  // warm up
+        CFPQ_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) CFPQ_HIP(launch());
+        CFPQ_HIP(hipEventRecord(e1, s));
+        CFPQ_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CFPQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms /= reps;
+        best.candidates_ms[c] = ms;
+        best.candidate_path[c] = cands[c].path;
+        best.candidate_tile[c] = cands[c].tile;
+        if (ms < best.ms) {
+            best.ms = ms;
+            best.path = cands[c].path;
+            best.tile = cands[c].tile;
+        }
+    }
+    best.n_candidates = static_cast<int32_t>(std::min<size_t>(cands.size(), 4));
+    {
+        TuneTable& t = table();
+        std::lock_guard<std::mutex> lk(t.mu);
+        ensure_env_loaded(t);
+        t.by_bucket[bucket_of(L.npad)] = best;
+    }
+    if (out) *out = best;
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_tune_get(int32_t n_nodes, cfpq_tune_entry* out) {
+    clear_last_error();
+    if (n_nodes < 0 || !out) return fail(CFPQ_EINVAL, "bad argument");
+    TuneTable& t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    ensure_env_loaded(t);
+    auto it = t.by_bucket.find(bucket_of(layout_for(n_nodes).npad));
+    if (it == t.by_bucket.end()) return CFPQ_ENOTREADY;
+    *out = it->second;
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_tune_save(const char* path) {
+    clear_last_error();
+    if (!path) return fail(CFPQ_EINVAL, "path is NULL");
+    TuneTable& t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(CFPQ_EINVAL, std::string("cannot write ") + path);
+    std::fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [\n");
+    size_t k = 0;
+    for (auto& kv : t.by_bucket) {
+        const cfpq_tune_entry& e = kv.second;
+        std::fprintf(f, " {\"bucket\": %d, \"npad\": %d, \"path\": \"%s\", \"tile\": %d, \"ms\": %.6f}%s\n", kv.first,
+                     e.npad, path_name(e.path), e.tile, e.ms, (++k < t.by_bucket.size()) ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    std::fclose(f);
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_tune_load(const char* path) {
+    clear_last_error();
+    if (!path) return fail(CFPQ_EINVAL, "path is NULL");
+    std::map<int32_t, cfpq_tune_entry> m;
+    cfpq_status st = load_file(path, m);
+    if (st != CFPQ_OK) return st;
+    TuneTable& t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.env_loaded = true;
+    for (auto& kv : m) t.by_bucket[kv.first] = kv.second;
+    return CFPQ_OK;
+}
+
+void cfpq_tune_clear(void) {
+    TuneTable& t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.by_bucket.clear();
+    t.env_loaded = true;
+}
+
+}  // extern "C"

@@ -86,6 +86,9 @@ int bits_default_strip(const Layout& L);
 // Largest n for which the MFMA path's int32 sums cannot overflow.
 constexpr int32_t kMfmaMaxNodes = 1 << 19;
 
+// Autotuned (path, tile) for L's size bucket, if one is recorded (autotune.hip).
+bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile);
+
 // A |= B x C on the int8 matrix cores; CT is the transpose of C.
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
                                int32_t* changed, hipStream_t s, const int32_t* go = nullptr);

@@ -97,6 +97,7 @@ struct Plan {
     Layout L;
     int32_t n_nt = 0;
     int32_t path = CFPQ_PATH_BITS;
+    int32_t tile = 0;
     bool jacobi = false;
     std::vector<int32_t> right_slot;  // per nonterminal: transpose slot or -1
     int32_t n_right = 0;
@@ -105,8 +106,15 @@ struct Plan {
     size_t off_second = 0, off_trans = 0, total = 0;
 };
 
-int32_t choose_path(const Layout& L, int32_t requested) {
+// AUTO: the autotuned kernel of the size bucket, else MFMA while int32 sums
+// are exact.  *tile is only changed for an autotuned choice.
+int32_t choose_path(const Layout& L, int32_t requested, int32_t* tile = nullptr) {
     if (requested == CFPQ_PATH_BITS || requested == CFPQ_PATH_MFMA) return requested;
+    int32_t p = 0, t = 0;
+    if (tuned_choice(L, &p, &t)) {
+        if (tile) *tile = t;
+        return p;
+    }
     return L.n <= kMfmaMaxNodes ? CFPQ_PATH_MFMA : CFPQ_PATH_BITS;
 }
 
@@ -114,7 +122,8 @@ Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& 
     Plan p;
     p.L = layout_for(g->n_nodes);
     p.n_nt = gr->n_nonterminals;
-    p.path = choose_path(p.L, o.path);
+    p.tile = o.tile;
+    p.path = choose_path(p.L, o.path, o.tile == 0 ? &p.tile : nullptr);
     p.jacobi = o.schedule == CFPQ_SCHEDULE_JACOBI;
     p.right_slot.assign(p.n_nt, -1);
     if (p.path == CFPQ_PATH_MFMA) {
@@ -364,7 +373,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                                              cy + br.lhs * mat_words, L, flag, cs, d_go + r);
                 else
                     ce = launch_bits_product(cx + br.left * mat_words, cx + br.right * mat_words,
-                                             cy + br.lhs * mat_words, L, flag, cs, o.tile, d_go + r);
+                                             cy + br.lhs * mat_words, L, flag, cs, p.tile, d_go + r);
             }
             for (int32_t a = 0; a < n_nt && ce == hipSuccess; ++a) {
                 if (p.right_slot[a] >= 0)
@@ -409,7 +418,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                 const uint64_t* CT = TT + p.right_slot[br.right] * mat_words;
                 CFPQ_HIP(launch_mfma_product(Bm, CT, Am, L, d_flags + br.lhs, s));
             } else {
-                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, d_flags + br.lhs, s, o.tile));
+                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, d_flags + br.lhs, s, p.tile));
             }
             if (o.profile) {
                 hipEvent_t e = product_event(2 * launched + 1);
@@ -478,7 +487,7 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
     if (!d_b || !d_c || !d_a) return fail(CFPQ_EINVAL, "matrix pointer is NULL");
     if (!d_changed) return fail(CFPQ_EINVAL, "d_changed is required");
     const Layout L = layout_for(n_nodes);
-    if (path == CFPQ_PATH_AUTO) path = choose_path(L, path);
+    if (path == CFPQ_PATH_AUTO) path = choose_path(L, path, tile == 0 ? &tile : nullptr);
     if (path != CFPQ_PATH_BITS && path != CFPQ_PATH_MFMA) return fail(CFPQ_EINVAL, "unknown path");
     if (path == CFPQ_PATH_BITS && tile != 0 && !bits_strip_supported(tile, L))
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");

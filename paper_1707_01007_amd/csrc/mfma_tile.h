@@ -126,7 +126,8 @@ __device__ __forceinline__ void mfma_tile(const uint32_t* __restrict__ Bm, const
             uint32_t w = 0;
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const uint32_t bit = acc[jb][ib][e] > 0 ? 1u : 0u;
+                // sums are never negative (squares), so min(sum, 1) is the Boolean value
+                const uint32_t bit = min(static_cast<uint32_t>(acc[jb][ib][e]), 1u);
                 w |= bit << (8 * (e / 4) + 4 * g + (e % 4));
             }
             word[jb] = w | static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 32, 64));
