@@ -5,7 +5,11 @@ A step is one full relational closure (matrix initialisation, every product,
 union and change check until the fixpoint) of the Dyck grammar on a seeded
 G(16384, 65536) graph with labels a/b, edges already in device memory.  The
 value is closure Gbit-op/s: 2 npad^3 Boolean operations (one AND and one OR per
-(i, k, j)) per executed product, divided by the wall time of the closure.
+(i, k, j)) per executed product, divided by the wall time of the closure, with
+every product dense (the autotuned kernel).  The "hybrid" object times the
+same closure with the per-product choice between the dense kernel and the
+sparse-operand products (the library default), whose sparse products are
+not counted as bit-operations: its figure is time to the fixpoint.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one
 GPU.
@@ -110,6 +114,29 @@ def bench_batch(cfpq, torch, steps=3):
             "Gbitop_per_s": round(bitops / t_batch / 1e9, 1),
             "serial_plain_queries_per_s": round(len(items) / t_serial, 1),
             "speedup_vs_serial_plain": round(t_serial / t_batch, 2)}
+
+
+def bench_hybrid(cfpq, torch, inst, edges, dense_out, args, dense_s):
+    """The same closure with the hybrid product choice (host-driven loop, no
+    per-product events); its result must equal the dense closure's bits."""
+    kw = dict(path=args.path, schedule=args.schedule, hybrid=1)
+    res = cfpq.closure(inst.n, edges, inst.grammar, **kw)
+    out = res.bits.view(-1)
+    for _ in range(args.warmup):
+        res = cfpq.closure(inst.n, edges, inst.grammar, out=out, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = cfpq.closure(inst.n, edges, inst.grammar, out=out, **kw)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    same = bool(torch.equal(out, dense_out))
+    st = res.stats
+    print(f"[bench] hybrid: {t * 1e3:.1f} ms per closure ({st['products'] - st['sparse_products']} dense + "
+          f"{st['sparse_products']} sparse products), identical bits: {same}", file=sys.stderr, flush=True)
+    return {"ms_per_closure": round(t * 1e3, 3), "speedup_vs_dense": round(dense_s / t, 2),
+            "closures_per_s": round(1.0 / t, 2), "dense_products": st["products"] - st["sparse_products"],
+            "sparse_products": st["sparse_products"], "loops": st["iterations"], "identical_to_dense": same}
 
 
 def _pct(xs, q):
@@ -225,7 +252,7 @@ def main():
         print(f"[bench] autotune n={inst.n}: {tuned}", file=sys.stderr, flush=True)
     # Every closure here uses the same options as the timed ones: per-product
     # HIP events on the library's stream (host-driven loop, no skipped launches).
-    kw = dict(path=args.path, schedule=args.schedule, profile=True)
+    kw = dict(path=args.path, schedule=args.schedule, profile=True, hybrid=0)
     res = cfpq.closure(inst.n, edges, g, **kw)  # sizes buffers
     out = res.bits.view(-1)
     print(f"[bench] warmup {args.warmup} x closure n={inst.n} path={args.path}", file=sys.stderr, flush=True)
@@ -245,6 +272,7 @@ def main():
     products = sum(s["products"] for s in stats)
     prod_ms = sum(s["product_ms"] for s in stats)
     path_used = {1: "bits", 2: "mfma"}[stats[-1]["path_used"]]
+    assert all(s["sparse_products"] == 0 for s in stats)
     npad = cfpq.padded_rows(inst.n)
     per_launch = 2.0 * npad ** 3
     achieved_t = per_launch / (prod_ms / products / 1e3) / 1e12 if products else 0.0
@@ -279,6 +307,7 @@ def main():
                    "autotune": tuned},
         "roofline": roof,
     }
+    line["hybrid"] = bench_hybrid(cfpq, torch, inst, edges, out, args, wall / args.steps)
     if not args.no_batch:
         line["batch"] = bench_batch(cfpq, torch)
     if not args.no_serve:

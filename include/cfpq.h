@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define CFPQ_ABI_VERSION 1
+#define CFPQ_ABI_VERSION 2
 
 #if defined(__GNUC__)
 #define CFPQ_API __attribute__((visibility("default")))
@@ -85,11 +85,20 @@ typedef struct {
 #define CFPQ_MAX_NONTERMINALS 64
 #define CFPQ_MAX_NODES (1 << 20)
 
-enum { CFPQ_PATH_AUTO = 0, CFPQ_PATH_BITS = 1, CFPQ_PATH_MFMA = 2 };
+/* Product kernels.  AUTO, BITS and MFMA compute the dense product (every
+ * word of both operands is read).  ROWS and COLS skip the zero entries of one
+ * operand: ROWS forms row i of B x C as the OR of the rows C[k, :] for the set
+ * bits k of B[i, :] (cost ~ nnz(B) rows of C); COLS does the same on the
+ * transposed product (B x C)^T = C^T x B^T (cost ~ nnz(C) rows of B^T, plus
+ * transposes).  All give identical bits. */
+enum { CFPQ_PATH_AUTO = 0, CFPQ_PATH_BITS = 1, CFPQ_PATH_MFMA = 2, CFPQ_PATH_ROWS = 3, CFPQ_PATH_COLS = 4 };
+/* Hybrid product choice of cfpq_closure (options.hybrid). */
+enum { CFPQ_HYBRID_OFF = 0, CFPQ_HYBRID_AUTO = 1 };
 enum { CFPQ_SCHEDULE_INPLACE = 0, CFPQ_SCHEDULE_JACOBI = 1 };
 
 typedef struct {
-    int32_t path;            /* CFPQ_PATH_*: product kernel (AUTO = autotuned choice) */
+    int32_t path;            /* CFPQ_PATH_*: product kernel.  AUTO = autotuned dense kernel;
+                                ROWS / COLS run every product that way (hybrid ignored) */
     int32_t schedule;        /* CFPQ_SCHEDULE_JACOBI: every product of a loop reads the
                                 matrices of the previous loop (Algorithm 1 exactly);
                                 CFPQ_SCHEDULE_INPLACE: products read the latest matrices
@@ -103,19 +112,27 @@ typedef struct {
     int32_t capture;         /* loops per captured HIP graph: the loop state (per-rule dirty
                                 decisions, change flags, loop count) lives on the device and the
                                 host reads it back once per `capture` loops; 0 = host-driven
-                                loop with one read-back per loop.  Ignored when profile is set.
-                                Default 8. */
+                                loop with one read-back per loop.  Ignored when profile is set
+                                or the hybrid choice is in effect.  Default 8. */
+    int32_t hybrid;          /* CFPQ_HYBRID_AUTO (default): for padded sizes of at least 4096,
+                                each product of each loop picks the dense kernel, ROWS or COLS
+                                from the current number of set bits of its operands (a cost
+                                model; the bits are the same whichever runs).  The loop is then
+                                host-driven.  CFPQ_HYBRID_OFF: every product is dense. */
+    int32_t reserved;        /* must be 0 */
     int64_t max_iters;       /* loop cap; 0 = |V|^2 |N| + 1 (Theorem 3's bound) */
 } cfpq_options;
 
 typedef struct {
     int64_t iterations;      /* loop executions, including the final one that changed nothing */
-    int64_t products;        /* Boolean products executed */
-    double bitops;           /* 2 * npad^3 per executed product, npad = cfpq_padded_rows(n) */
+    int64_t products;        /* Boolean products executed (dense and sparse) */
+    double bitops;           /* 2 * npad^3 per executed dense product, npad = cfpq_padded_rows(n);
+                                ROWS / COLS products are not counted */
     double device_ms;        /* device time from matrix initialisation to the last flag */
     double product_ms;       /* summed duration of the product kernels (options.profile), else 0 */
-    int32_t path_used;       /* CFPQ_PATH_BITS or CFPQ_PATH_MFMA */
+    int32_t path_used;       /* CFPQ_PATH_BITS or CFPQ_PATH_MFMA (dense kernel), ROWS or COLS */
     int32_t converged;       /* 1 if the fixpoint was reached */
+    int64_t sparse_products; /* products of `products` that ran as ROWS or COLS */
 } cfpq_stats;
 
 /* ABI version of the loaded library (CFPQ_ABI_VERSION). */
@@ -125,8 +142,9 @@ CFPQ_API int32_t cfpq_abi_version(void);
  * stays valid until the next call on this thread. */
 CFPQ_API const char* cfpq_last_error(void);
 
-/* Fill `opt` with defaults: AUTO path, in-place schedule, dirty worklist on,
- * 8 loops per captured graph, no per-product timing, max_iters from Theorem 3. */
+/* Fill `opt` with defaults: AUTO path, hybrid choice on, in-place schedule,
+ * dirty worklist on, 8 loops per captured graph, no per-product timing,
+ * max_iters from Theorem 3. */
 CFPQ_API void cfpq_default_options(cfpq_options* opt);
 
 /* Words per matrix row: ceil(n/64) rounded up to a multiple of 4 (n >= 0). */
@@ -170,12 +188,15 @@ CFPQ_API cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* g
  *     d_a |= d_b x d_c,   P_ij = OR_k (b_ik AND c_kj)
  * All three are npad x npad matrices in the bit layout for `n_nodes`.  d_a may
  * alias d_b and/or d_c (the in-place update; bits are only ever set, so every
- * value read is a subset of the final one).  path = CFPQ_PATH_BITS or
- * CFPQ_PATH_MFMA (AUTO picks one); tile as in cfpq_options (0 = default).
+ * value read is a subset of the final one).  path = any CFPQ_PATH_* (AUTO
+ * picks the autotuned dense kernel); tile as in cfpq_options (0 = default).
  * *d_changed (device int32, required) is OR-ed with 1 when d_a gained a bit.
- * d_workspace may be NULL for the BITS path; the MFMA path needs
+ * d_workspace may be NULL for BITS and ROWS; MFMA (one transposed operand)
+ * and COLS (two transposed operands and the transposed product) need
  * cfpq_product_workspace_bytes.  The MFMA path requires n_nodes <= 2^19
- * (int32 accumulation bound); larger sizes return CFPQ_EINVAL.
+ * (int32 accumulation bound); larger sizes return CFPQ_EINVAL.  Every product
+ * kernel only reads rows and columns below n_nodes of its operands, which
+ * must be zero beyond them (as in every matrix of the bit layout).
  */
 CFPQ_API size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path);
 CFPQ_API cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint64_t* d_b,

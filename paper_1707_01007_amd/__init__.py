@@ -22,10 +22,10 @@ from typing import Optional
 import numpy as np
 
 from . import _abi
-from ._abi import (CfpqError, PATH_AUTO, PATH_BITS, PATH_MFMA, SCHEDULE_INPLACE,  # noqa: F401
+from ._abi import (CfpqError, PATH_AUTO, PATH_BITS, PATH_MFMA, PATH_ROWS, PATH_COLS, SCHEDULE_INPLACE,  # noqa: F401
                    SCHEDULE_JACOBI)
 
-_PATHS = {"auto": PATH_AUTO, "bits": PATH_BITS, "mfma": PATH_MFMA}
+_PATHS = {"auto": PATH_AUTO, "bits": PATH_BITS, "mfma": PATH_MFMA, "rows": PATH_ROWS, "cols": PATH_COLS}
 _SCHEDULES = {"inplace": SCHEDULE_INPLACE, "jacobi": SCHEDULE_JACOBI}
 
 
@@ -74,11 +74,14 @@ def _grammar_struct_new(grammar):
     return g, (t_arr, b_arr)
 
 
-def _options(path="auto", schedule="inplace", dirty=True, max_iters=0, profile=False, tile=0, capture=None):
+def _options(path="auto", schedule="inplace", dirty=True, max_iters=0, profile=False, tile=0, capture=None,
+             hybrid=None):
     o = _abi.Options()
     lib().cfpq_default_options(ctypes.byref(o))
     if capture is not None:
         o.capture = int(capture)
+    if hybrid is not None:
+        o.hybrid = int(hybrid)
     o.profile = 1 if profile else 0
     o.tile = int(tile)
     o.path = _PATHS[path] if isinstance(path, str) else int(path)
@@ -105,14 +108,17 @@ def _stream_ptr(stream):
 
 def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=True, max_iters=0,
             device=None, stream=None, out=None, workspace=None, allow_partial=False,
-            profile=False, tile=0, capture=None) -> Result:
+            profile=False, tile=0, capture=None, hybrid=None) -> Result:
     """Relational CFPQ closure (Algorithm 1) through ``cfpq_closure``.
 
     ``edges`` is an int32 array [m, 3] of (src, label, dst) on the host, or an
     int32 CUDA tensor of that shape (then checked on the device).  Returns a
     ``Result`` whose ``bits`` hold R_A for every nonterminal in the library's
     bit layout.  Raises ``CfpqError`` on any error (``allow_partial`` accepts
-    CFPQ_ENOTCONV and returns the sound partial result)."""
+    CFPQ_ENOTCONV and returns the sound partial result).  ``path`` is "auto",
+    "bits", "mfma" (dense kernel), "rows" or "cols" (every product skips the
+    zeros of one operand); ``hybrid`` (None = library default, on) lets each
+    product choose between the dense kernel and rows/cols."""
     torch = _torch()
     L = lib()
     device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -124,7 +130,7 @@ def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=Tr
     else:
         e_host = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
         graph = _abi.Graph(int(n), 0, int(e_host.shape[0]), ctypes.c_void_p(e_host.ctypes.data))
-    opt = _options(path, schedule, dirty, max_iters, profile, tile, capture)
+    opt = _options(path, schedule, dirty, max_iters, profile, tile, capture, hybrid)
     need = ctypes.c_size_t(0)
     _abi.check(L.cfpq_workspace_bytes(ctypes.byref(graph), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(need)))
     res_words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8

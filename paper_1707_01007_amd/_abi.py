@@ -9,7 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcfpq.so")
 
 CFPQ_OK, CFPQ_EINVAL, CFPQ_ENOMEM, CFPQ_EDEVICE, CFPQ_ENOTCONV, CFPQ_EBUSY, CFPQ_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
-PATH_AUTO, PATH_BITS, PATH_MFMA = 0, 1, 2
+PATH_AUTO, PATH_BITS, PATH_MFMA, PATH_ROWS, PATH_COLS = 0, 1, 2, 3, 4
+HYBRID_OFF, HYBRID_AUTO = 0, 1
+ABI_VERSION = 2
 SCHEDULE_INPLACE, SCHEDULE_JACOBI = 0, 1
 STATUS_NAMES = {0: "CFPQ_OK", -1: "CFPQ_EINVAL", -2: "CFPQ_ENOMEM", -3: "CFPQ_EDEVICE",
                 -4: "CFPQ_ENOTCONV", -5: "CFPQ_EBUSY", -6: "CFPQ_ENOTREADY"}
@@ -56,13 +58,13 @@ class Instance(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("schedule", ctypes.c_int32), ("dirty_worklist", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("tile", ctypes.c_int32), ("capture", ctypes.c_int32),
-                ("max_iters", ctypes.c_int64)]
+                ("hybrid", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_iters", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("products", ctypes.c_int64), ("bitops", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("product_ms", ctypes.c_double), ("path_used", ctypes.c_int32),
-                ("converged", ctypes.c_int32)]
+                ("converged", ctypes.c_int32), ("sparse_products", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -166,7 +168,7 @@ def load(path: str = LIB_PATH):
     lib.cfpq_tune_load.restype = ctypes.c_int
     lib.cfpq_tune_clear.argtypes = []
     lib.cfpq_tune_clear.restype = None
-    if lib.cfpq_abi_version() != 1:
+    if lib.cfpq_abi_version() != ABI_VERSION:
         raise ImportError("libcfpq ABI version mismatch")
     _lib = lib
     return lib

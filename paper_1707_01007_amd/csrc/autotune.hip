@@ -95,7 +95,7 @@ void ensure_env_loaded(TuneTable& t) {
 
 }  // namespace
 
-bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile) {
+bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile, float* ms) {
     TuneTable& t = table();
     std::lock_guard<std::mutex> lk(t.mu);
     ensure_env_loaded(t);
@@ -110,6 +110,7 @@ bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile) {
     }
     *path = e.path;
     *tile = e.tile;
+    if (ms) *ms = e.ms;
     return true;
 }
 

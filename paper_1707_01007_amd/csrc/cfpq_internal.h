@@ -62,8 +62,12 @@ struct LoopState {
 
 // ---- kernels (each launcher only enqueues work on `s`) ----
 
+// Predicates: a launch given a non-null `go` does nothing unless *go == want
+// (read on the device, so the launch can sit in a captured graph).  For
+// launch_transpose, want = 0 means "unless *go != 0".
+
 // Fill `words` uint64 with zero by a kernel (safe inside captured graphs).
-hipError_t launch_zero(uint64_t* p, size_t words, hipStream_t s);
+hipError_t launch_zero(uint64_t* p, size_t words, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1);
 
 // Matrix initialisation of Algorithm 1: for every edge (i, x, j) and every
 // rule A -> x, set bit (i, j) of matrix A.  Term rules are given as CSR over
@@ -76,26 +80,37 @@ hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t*
 // A |= B x C on the VALU: AND/OR over bit-packed rows.  `strip` is the
 // output strip width in 32-bit words per workgroup (8, 16 or 32; 0 or an
 // unsupported width = bits_default_strip).
-// A non-null `go` makes the whole launch a no-op unless *go != 0 (read on the
-// device, so the launch can sit in a captured graph).
+// nnz (optional): incremented by the number of bits the product added.
 hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s, int strip, const int32_t* go = nullptr);
+                               int32_t* changed, hipStream_t s, int strip, const int32_t* go = nullptr,
+                               int32_t want = 1, unsigned long long* nnz = nullptr);
 bool bits_strip_supported(int strip, const Layout& L);
 int bits_default_strip(const Layout& L);
 
 // Largest n for which the MFMA path's int32 sums cannot overflow.
 constexpr int32_t kMfmaMaxNodes = 1 << 19;
 
-// Autotuned (path, tile) for L's size bucket, if one is recorded (autotune.hip).
-bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile);
+// Autotuned (path, tile) for L's size bucket, if one is recorded (autotune.hip);
+// *ms (optional) gets the measured time of one product of that kernel.
+bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile, float* ms = nullptr);
 
 // A |= B x C on the int8 matrix cores; CT is the transpose of C.
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s, const int32_t* go = nullptr);
+                               int32_t* changed, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1,
+                               unsigned long long* nnz = nullptr);
+
+// Sparse-operand products (kernels_sparse.hip): A[i,:] |= OR_{k in nz(B[i,:])} C[k,:]
+// for rows i < n, and A |= transpose(Pt).
+hipError_t launch_rowor_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L, int32_t* changed,
+                                unsigned long long* nnz, hipStream_t s, const int32_t* go = nullptr,
+                                int32_t want = 1);
+hipError_t launch_transpose_or(const uint64_t* Pt, uint64_t* A, const Layout& L, int32_t* changed,
+                               unsigned long long* nnz, hipStream_t s, const int32_t* go = nullptr,
+                               int32_t want = 1);
 
 // dst = transpose(src) (bit matrix, npad x npad).
 hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s,
-                            const int32_t* pred = nullptr);
+                            const int32_t* pred = nullptr, int32_t want = 0);
 
 // Loop control (kernels_control.hip).  `rules` holds (lhs, left, right)
 // triples on the device; go[r] receives the decision for rule r.
@@ -105,6 +120,32 @@ hipError_t launch_plan(LoopState* st, int32_t* go, const int32_t* rules, int32_t
 hipError_t launch_finish(LoopState* st, int32_t n_nt, hipStream_t s);
 hipError_t launch_copy_if(const uint64_t* src, uint64_t* dst, size_t words, const int32_t* pred,
                           hipStream_t s);
+
+// ---- hybrid product choice ----
+// Per-product modes (also the predicate values of predicated launches).
+enum ProductMode : int32_t { kModeSkip = 0, kModeDense = 1, kModeRows = 2, kModeCols = 3 };
+
+// Padded size from which cfpq_closure's hybrid choice is in effect: below it a
+// dense product takes a few microseconds and the choice cannot pay.
+constexpr int64_t kHybridMinRows = 4096;
+
+// Estimated time (us) of each way to run T_A |= T_B x T_C from the current set
+// bit counts of B and C.  Only speed depends on it: every mode gives the same
+// bits.
+struct HybridModel {
+    double dense_us = 0;  // one dense product at this size
+    double fixed_us = 5;  // launch and fixed cost of one sparse kernel
+    double row_us = 0;    // reading one W-word row of the other operand
+    double mat_us = 0;    // one full pass over a matrix
+};
+
+inline int32_t hybrid_mode(const HybridModel& m, double nnz_b, double nnz_c, bool left_transposed) {
+    const double rows = m.fixed_us + nnz_b * m.row_us + 3.0 * m.mat_us;
+    const double cols = 3.0 * m.fixed_us + nnz_c * m.row_us + (left_transposed ? 6.0 : 8.0) * m.mat_us;
+    if (rows <= cols && rows < m.dense_us) return kModeRows;
+    if (cols < rows && cols < m.dense_us) return kModeCols;
+    return kModeDense;
+}
 
 // counts[m] = number of set bits of matrix m (count matrices), added to counts.
 hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,

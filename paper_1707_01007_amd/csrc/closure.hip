@@ -96,14 +96,18 @@ cfpq_options resolve(const cfpq_options* opt) {
 struct Plan {
     Layout L;
     int32_t n_nt = 0;
-    int32_t path = CFPQ_PATH_BITS;
+    int32_t path = CFPQ_PATH_BITS;  // dense kernel, or ROWS / COLS for every product
     int32_t tile = 0;
+    int32_t forced = kModeDense;    // mode of every product unless hybrid
+    bool hybrid = false;            // per-product choice by the cost model
+    HybridModel model;
     bool jacobi = false;
     std::vector<int32_t> right_slot;  // per nonterminal: transpose slot or -1
     int32_t n_right = 0;
     size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0;
-    size_t off_rules = 0, off_go = 0, off_state = 0;
-    size_t off_second = 0, off_trans = 0, total = 0;
+    size_t off_rules = 0, off_go = 0, off_state = 0, off_nnz = 0;
+    size_t off_second = 0, off_trans = 0, off_bt = 0, off_pt = 0, total = 0;
+    bool temps = false;  // off_bt / off_pt hold a transposed left operand and product
 };
 
 // AUTO: the autotuned kernel of the size bucket, else MFMA while int32 sums
@@ -118,15 +122,37 @@ int32_t choose_path(const Layout& L, int32_t requested, int32_t* tile = nullptr)
     return L.n <= kMfmaMaxNodes ? CFPQ_PATH_MFMA : CFPQ_PATH_BITS;
 }
 
+HybridModel make_model(const Layout& L, int32_t path, float tuned_ms) {
+    HybridModel m;
+    const double npad = static_cast<double>(L.npad);
+    // dense rates measured for the two kernels at n = 16384 (bit-ops per us)
+    const double rate = path == CFPQ_PATH_MFMA ? 4.0e9 : 1.8e9;
+    m.dense_us = tuned_ms > 0 ? 1000.0 * tuned_ms : 5.0 + 2.0 * npad * npad * npad / rate;
+    m.row_us = static_cast<double>(L.W) * 8.0 / 3.0e6;                // gathered rows, ~3 TB/s
+    m.mat_us = static_cast<double>(L.mat_words) * 8.0 / 4.0e6;        // streamed, ~4 TB/s
+    return m;
+}
+
 Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& o) {
     Plan p;
     p.L = layout_for(g->n_nodes);
     p.n_nt = gr->n_nonterminals;
     p.tile = o.tile;
-    p.path = choose_path(p.L, o.path, o.tile == 0 ? &p.tile : nullptr);
+    if (o.path == CFPQ_PATH_ROWS || o.path == CFPQ_PATH_COLS) {
+        p.path = o.path;
+        p.forced = o.path == CFPQ_PATH_ROWS ? kModeRows : kModeCols;
+    } else {
+        float tuned_ms = 0.f;
+        int32_t tp = 0, tt = 0;
+        p.path = choose_path(p.L, o.path, o.tile == 0 ? &p.tile : nullptr);
+        if (!(tuned_choice(p.L, &tp, &tt, &tuned_ms) && tp == p.path)) tuned_ms = 0.f;
+        p.hybrid = o.hybrid == CFPQ_HYBRID_AUTO && p.L.npad >= kHybridMinRows;
+        p.model = make_model(p.L, p.path, tuned_ms);
+    }
     p.jacobi = o.schedule == CFPQ_SCHEDULE_JACOBI;
+    p.temps = p.hybrid || p.forced == kModeCols;
     p.right_slot.assign(p.n_nt, -1);
-    if (p.path == CFPQ_PATH_MFMA) {
+    if (p.path == CFPQ_PATH_MFMA || p.temps) {
         for (int32_t r = 0; r < gr->n_bin_rules; ++r) {
             int32_t c = gr->bin_rules[r].right;
             if (p.right_slot[c] < 0) p.right_slot[c] = p.n_right++;
@@ -150,10 +176,16 @@ Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& 
     off += align_up(static_cast<size_t>(std::max(gr->n_bin_rules, 1)) * 4, 256);
     p.off_state = off;
     off += align_up(sizeof(LoopState), 256);
+    p.off_nnz = off;  // n_nt set-bit counters, then one spare flag
+    off += align_up(static_cast<size_t>(p.n_nt) * 8 + 8, 256);
     p.off_second = off;
     if (p.jacobi) off += mat_bytes * p.n_nt;
     p.off_trans = off;
     off += mat_bytes * p.n_right;
+    p.off_bt = off;
+    if (p.temps) off += mat_bytes;
+    p.off_pt = off;
+    if (p.temps) off += mat_bytes;
     p.total = off;
     return p;
 }
@@ -198,6 +230,7 @@ void cfpq_default_options(cfpq_options* opt) {
     opt->schedule = CFPQ_SCHEDULE_INPLACE;
     opt->dirty_worklist = 1;
     opt->capture = 8;
+    opt->hybrid = CFPQ_HYBRID_AUTO;
     opt->max_iters = 0;
 }
 
@@ -234,7 +267,9 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     if (st != CFPQ_OK) return st;
     if (!d_result) return fail(CFPQ_EINVAL, "d_result is NULL");
     const cfpq_options o = resolve(opt);
-    if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_MFMA) return fail(CFPQ_EINVAL, "unknown path");
+    if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_COLS) return fail(CFPQ_EINVAL, "unknown path");
+    if (o.hybrid != CFPQ_HYBRID_OFF && o.hybrid != CFPQ_HYBRID_AUTO) return fail(CFPQ_EINVAL, "unknown hybrid mode");
+    if (o.reserved != 0) return fail(CFPQ_EINVAL, "options.reserved must be 0");
     if (o.schedule != CFPQ_SCHEDULE_INPLACE && o.schedule != CFPQ_SCHEDULE_JACOBI)
         return fail(CFPQ_EINVAL, "unknown schedule");
     if (o.max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
@@ -243,6 +278,8 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         return fail(CFPQ_EINVAL, "the MFMA path supports at most 2^19 nodes");
     if (o.tile != 0 && o.path == CFPQ_PATH_BITS && !bits_strip_supported(o.tile, layout_for(graph->n_nodes)))
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
+    if (o.tile != 0 && (o.path == CFPQ_PATH_ROWS || o.path == CFPQ_PATH_COLS))
+        return fail(CFPQ_EINVAL, "the ROWS and COLS paths have no tile variants");
     const Plan p = make_plan(graph, grammar, o);
     if (p.total > 0 && !d_workspace) return fail(CFPQ_EINVAL, "d_workspace is NULL");
     if (workspace_bytes < p.total)
@@ -331,7 +368,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     if (!any_rules) converged = true;
 
     // ---- captured loops: K loops per HIP graph, loop state on the device ----
-    const bool captured = any_rules && o.capture > 0 && !o.profile;
+    const bool captured = any_rules && o.capture > 0 && !o.profile && !p.hybrid && p.forced == kModeDense;
     if (captured) {
         const int32_t n_rules = grammar->n_bin_rules;
         auto* d_rules = reinterpret_cast<int32_t*>(ws + p.off_rules);
@@ -401,6 +438,19 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     }
 
     // ---- host-driven loop: one flag read-back per loop ----
+    auto* d_nnz = reinterpret_cast<unsigned long long*>(ws + p.off_nnz);
+    auto* d_spare = reinterpret_cast<int32_t*>(d_nnz + n_nt);  // change flag nobody reads
+    uint64_t* BT = reinterpret_cast<uint64_t*>(ws + p.off_bt);
+    uint64_t* PT = reinterpret_cast<uint64_t*>(ws + p.off_pt);
+    std::vector<unsigned long long> nnz(n_nt, 0);
+    int64_t sparse_products = 0;
+    if (!captured && p.hybrid && !converged) {
+        CFPQ_HIP(hipMemsetAsync(d_nnz, 0, static_cast<size_t>(n_nt) * 8, s));
+        CFPQ_HIP(launch_popcount(X, n_nt, L, d_nnz, s));
+        CFPQ_HIP(hipMemcpyAsync(nnz.data(), d_nnz, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipStreamSynchronize(s));
+    }
+    unsigned long long* nnz_of = p.hybrid ? d_nnz : nullptr;
     while (!captured && !converged && iters < cap) {
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         size_t launched = 0;
@@ -414,12 +464,30 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                 if (!e) return fail(CFPQ_EDEVICE, "hipEventCreate failed");
                 CFPQ_HIP(hipEventRecord(e, s));
             }
-            if (p.path == CFPQ_PATH_MFMA) {
+            const int32_t mode = p.hybrid ? hybrid_mode(p.model, static_cast<double>(nnz[br.left]),
+                                                         static_cast<double>(nnz[br.right]),
+                                                         p.right_slot[br.left] >= 0)
+                                          : p.forced;
+            int32_t* flag = d_flags + br.lhs;
+            unsigned long long* cnt = nnz_of ? nnz_of + br.lhs : nullptr;
+            if (mode == kModeRows) {
+                CFPQ_HIP(launch_rowor_product(Bm, X + br.right * mat_words, Am, L, flag, cnt, s));
+            } else if (mode == kModeCols) {
+                // (B x C)^T = C^T x B^T by rows of C^T, then transposed into A
                 const uint64_t* CT = TT + p.right_slot[br.right] * mat_words;
-                CFPQ_HIP(launch_mfma_product(Bm, CT, Am, L, d_flags + br.lhs, s));
+                const uint64_t* BTm = BT;
+                if (p.right_slot[br.left] >= 0) BTm = TT + p.right_slot[br.left] * mat_words;
+                else CFPQ_HIP(launch_transpose(Bm, BT, L, s));
+                CFPQ_HIP(launch_zero(PT, mat_words, s));
+                CFPQ_HIP(launch_rowor_product(CT, BTm, PT, L, d_spare, nullptr, s));
+                CFPQ_HIP(launch_transpose_or(PT, Am, L, flag, cnt, s));
+            } else if (p.path == CFPQ_PATH_MFMA) {
+                const uint64_t* CT = TT + p.right_slot[br.right] * mat_words;
+                CFPQ_HIP(launch_mfma_product(Bm, CT, Am, L, flag, s, nullptr, 1, cnt));
             } else {
-                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, d_flags + br.lhs, s, p.tile));
+                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, flag, s, p.tile, nullptr, 1, cnt));
             }
+            if (mode != kModeDense) ++sparse_products;
             if (o.profile) {
                 hipEvent_t e = product_event(2 * launched + 1);
                 if (!e) return fail(CFPQ_EDEVICE, "hipEventCreate failed");
@@ -429,6 +497,8 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             ++products;
         }
         CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
+        if (nnz_of)
+            CFPQ_HIP(hipMemcpyAsync(nnz.data(), d_nnz, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
         CFPQ_HIP(hipStreamSynchronize(s));
         for (size_t q = 0; o.profile && q < launched; ++q) {
             float pm = 0.f;
@@ -464,7 +534,8 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         stats->iterations = iters;
         stats->products = products;
         stats->bitops = 2.0 * static_cast<double>(L.npad) * static_cast<double>(L.npad) *
-                        static_cast<double>(L.npad) * static_cast<double>(products);
+                        static_cast<double>(L.npad) * static_cast<double>(products - sparse_products);
+        stats->sparse_products = sparse_products;
         stats->device_ms = ms;
         stats->product_ms = product_ms;
         stats->path_used = p.path;
@@ -475,8 +546,10 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
 }
 
 size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path) {
-    if (path != CFPQ_PATH_MFMA) return 0;
-    return static_cast<size_t>(layout_for(n_nodes < 0 ? 0 : n_nodes).mat_words) * 8;
+    const size_t mat = static_cast<size_t>(layout_for(n_nodes < 0 ? 0 : n_nodes).mat_words) * 8;
+    if (path == CFPQ_PATH_MFMA) return mat;
+    if (path == CFPQ_PATH_COLS) return 3 * mat + 256;
+    return 0;
 }
 
 cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint64_t* d_b, const uint64_t* d_c,
@@ -488,22 +561,41 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
     if (!d_changed) return fail(CFPQ_EINVAL, "d_changed is required");
     const Layout L = layout_for(n_nodes);
     if (path == CFPQ_PATH_AUTO) path = choose_path(L, path, tile == 0 ? &tile : nullptr);
-    if (path != CFPQ_PATH_BITS && path != CFPQ_PATH_MFMA) return fail(CFPQ_EINVAL, "unknown path");
+    if (path < CFPQ_PATH_BITS || path > CFPQ_PATH_COLS) return fail(CFPQ_EINVAL, "unknown path");
     if (path == CFPQ_PATH_BITS && tile != 0 && !bits_strip_supported(tile, L))
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
-    if (path == CFPQ_PATH_MFMA && tile != 0) return fail(CFPQ_EINVAL, "the MFMA path has no tile variants");
+    if (path != CFPQ_PATH_BITS && tile != 0) return fail(CFPQ_EINVAL, "only the BITS path has tile variants");
     if (path == CFPQ_PATH_MFMA && n_nodes > kMfmaMaxNodes)
         return fail(CFPQ_EINVAL, "the MFMA path supports at most 2^19 nodes");
+    const size_t need = cfpq_product_workspace_bytes(n_nodes, path);
+    if (need > 0 && (workspace_bytes < need || !d_workspace))
+        return fail(CFPQ_ENOMEM, "workspace smaller than cfpq_product_workspace_bytes");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (path == CFPQ_PATH_MFMA) {
-        if (workspace_bytes < cfpq_product_workspace_bytes(n_nodes, path) || !d_workspace)
-            return fail(CFPQ_ENOMEM, "MFMA product needs a workspace for the transposed operand");
-        auto* ct = static_cast<uint64_t*>(d_workspace);
-        CFPQ_HIP(launch_transpose(d_c, ct, L, s));
-        CFPQ_HIP(launch_mfma_product(d_b, ct, d_a, L, d_changed, s));
-        return CFPQ_OK;
+    const size_t mw = static_cast<size_t>(L.mat_words);
+    auto* ws = static_cast<uint64_t*>(d_workspace);
+    switch (path) {
+        case CFPQ_PATH_MFMA:
+            CFPQ_HIP(launch_transpose(d_c, ws, L, s));
+            CFPQ_HIP(launch_mfma_product(d_b, ws, d_a, L, d_changed, s));
+            break;
+        case CFPQ_PATH_ROWS:
+            CFPQ_HIP(launch_rowor_product(d_b, d_c, d_a, L, d_changed, nullptr, s));
+            break;
+        case CFPQ_PATH_COLS: {
+            // workspace: C^T, B^T, the transposed product, a flag nobody reads
+            uint64_t *ct = ws, *bt = ws + mw, *pt = ws + 2 * mw;
+            auto* spare = reinterpret_cast<int32_t*>(ws + 3 * mw);
+            CFPQ_HIP(launch_transpose(d_c, ct, L, s));
+            CFPQ_HIP(launch_transpose(d_b, bt, L, s));
+            CFPQ_HIP(launch_zero(pt, mw, s));
+            CFPQ_HIP(launch_rowor_product(ct, bt, pt, L, spare, nullptr, s));
+            CFPQ_HIP(launch_transpose_or(pt, d_a, L, d_changed, nullptr, s));
+            break;
+        }
+        default:
+            CFPQ_HIP(launch_bits_product(d_b, d_c, d_a, L, d_changed, s, tile));
+            break;
     }
-    CFPQ_HIP(launch_bits_product(d_b, d_c, d_a, L, d_changed, s, tile));
     return CFPQ_OK;
 }
 

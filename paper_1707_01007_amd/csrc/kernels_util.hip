@@ -4,7 +4,9 @@
 namespace cfpq {
 namespace {
 
-__global__ void zero_kernel(uint64_t* __restrict__ p, size_t words) {
+__global__ void zero_kernel(uint64_t* __restrict__ p, size_t words, const int32_t* __restrict__ pred,
+                            int32_t want) {
+    if (pred != nullptr && *pred != want) return;
     size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     for (; i < words; i += stride) p[i] = 0;
@@ -40,8 +42,8 @@ __global__ void init_scatter_kernel(const cfpq_edge* __restrict__ edges, int64_t
 // transpose.
 __global__ __launch_bounds__(256) void transpose_kernel(const uint64_t* __restrict__ src,
                                                         uint64_t* __restrict__ dst, int64_t W,
-                                                        const int32_t* __restrict__ pred) {
-    if (pred != nullptr && *pred == 0) return;
+                                                        const int32_t* __restrict__ pred, int32_t want) {
+    if (pred != nullptr && (want == 0 ? *pred == 0 : *pred != want)) return;
     const int lane = threadIdx.x & 63;
     const int64_t blocks = W * W;  // (npad/64)^2 blocks of 64 x 64
     int64_t blk = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -73,11 +75,11 @@ __global__ __launch_bounds__(256) void popcount_kernel(const uint64_t* __restric
 
 }  // namespace
 
-hipError_t launch_zero(uint64_t* p, size_t words, hipStream_t s) {
+hipError_t launch_zero(uint64_t* p, size_t words, hipStream_t s, const int32_t* pred, int32_t want) {
     if (words == 0) return hipSuccess;
     size_t blocks = (words + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    zero_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(p, words);
+    zero_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(p, words, pred, want);
     return hipGetLastError();
 }
 
@@ -92,10 +94,10 @@ hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t*
 }
 
 hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s,
-                            const int32_t* pred) {
+                            const int32_t* pred, int32_t want) {
     int64_t blocks = L.W * L.W;
     int64_t wgs = (blocks + 3) / 4;
-    transpose_kernel<<<dim3(static_cast<unsigned>(wgs)), dim3(256), 0, s>>>(src, dst, L.W, pred);
+    transpose_kernel<<<dim3(static_cast<unsigned>(wgs)), dim3(256), 0, s>>>(src, dst, L.W, pred, want);
     return hipGetLastError();
 }
 

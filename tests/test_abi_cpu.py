@@ -44,7 +44,7 @@ def test_layout_functions():
         assert lib.cfpq_row_words(n) == w
         assert lib.cfpq_padded_rows(n) == 64 * w
         assert lib.cfpq_result_bytes(n, 3) == 3 * 64 * w * w * 8
-    assert lib.cfpq_abi_version() == 1
+    assert lib.cfpq_abi_version() == 2
 
 
 def _structs(n=4, edges=((0, 0, 1), (1, 1, 2)), n_nt=4, n_t=2, term=((2, 0), (3, 1)),
@@ -118,6 +118,88 @@ def test_closure_rejects_small_workspace_and_null_result():
     assert rc == _abi.CFPQ_EINVAL
 
 
+@pytest.mark.parametrize("field,value", [("hybrid", 5), ("reserved", 1), ("path", 5), ("path", -1)])
+def test_closure_rejects_bad_options_before_device_work(field, value):
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+    opt = _abi.Options()
+    lib.cfpq_default_options(ctypes.byref(opt))
+    assert opt.hybrid == _abi.HYBRID_AUTO and opt.reserved == 0
+    setattr(opt, field, value)
+    rc = lib.cfpq_closure(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), None, ctypes.c_void_p(1 << 20),
+                          ctypes.c_size_t(1 << 30), ctypes.c_void_p(1 << 21), None)
+    assert rc == _abi.CFPQ_EINVAL, field
+    assert lib.cfpq_last_error()
+
+
+@pytest.mark.parametrize("path", [3, 4])
+def test_sparse_paths_take_no_tile(path):
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+    opt = _abi.Options()
+    lib.cfpq_default_options(ctypes.byref(opt))
+    opt.path, opt.tile = path, 8
+    rc = lib.cfpq_closure(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), None, ctypes.c_void_p(1 << 20),
+                          ctypes.c_size_t(1 << 30), ctypes.c_void_p(1 << 21), None)
+    assert rc == _abi.CFPQ_EINVAL
+    assert b"tile" in lib.cfpq_last_error()
+
+
+def test_workspace_grows_with_sparse_temporaries():
+    """COLS (and the hybrid choice at padded sizes >= 4096) needs the
+    transposed right operands plus two temporaries; ROWS needs none."""
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    n = 5000
+    gr, g, keep = _structs(n=n, edges=((0, 0, 1),))
+    mat = lib.cfpq_result_bytes(n, 1)
+    opt = _abi.Options()
+    lib.cfpq_default_options(ctypes.byref(opt))
+    sizes = {}
+    for name, path, hybrid in [("mfma_dense", 2, 0), ("bits_dense", 1, 0), ("rows", 3, 0), ("cols", 4, 0),
+                               ("bits_hybrid", 1, 1)]:
+        opt.path, opt.hybrid = path, hybrid
+        sz = ctypes.c_size_t(0)
+        assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz)) == 0
+        sizes[name] = sz.value
+    assert sizes["rows"] == sizes["bits_dense"]
+    assert sizes["cols"] == sizes["mfma_dense"] + 2 * mat   # one right operand (B) transposed in both
+    assert sizes["bits_hybrid"] == sizes["cols"]
+    assert lib.cfpq_product_workspace_bytes(n, 3) == 0
+    assert lib.cfpq_product_workspace_bytes(n, 4) == 3 * mat + 256
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes mirrors of the C structs: size and every field offset as the C
+    compiler lays them out from include/cfpq.h."""
+    import shutil
+    import subprocess
+    from paper_1707_01007_amd import _abi
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    structs = {"cfpq_options": _abi.Options, "cfpq_stats": _abi.Stats, "cfpq_graph": _abi.Graph,
+               "cfpq_grammar": _abi.Grammar, "cfpq_instance": _abi.Instance, "cfpq_tune_entry": _abi.TuneEntry,
+               "cfpq_server_config": _abi.ServerConfig, "cfpq_request_info": _abi.RequestInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cfpq.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert c[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert c[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
 def test_product_rejects_bad_arguments():
     from paper_1707_01007_amd import _abi
     lib = _lib()
@@ -125,6 +207,8 @@ def test_product_rejects_bad_arguments():
     assert lib.cfpq_product(64, 1, 0, None, None, None, None, None, 0, None) == _abi.CFPQ_EINVAL
     p = ctypes.c_void_p(1 << 20)
     assert lib.cfpq_product(64, 9, 0, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL
+    assert lib.cfpq_product(64, 3, 8, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL    # ROWS has no tiles
+    assert lib.cfpq_product(64, 4, 0, p, p, p, p, None, 0, None) == _abi.CFPQ_ENOMEM    # COLS needs workspace
     assert lib.cfpq_product(64, 1, 12, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL   # no such strip width
     assert lib.cfpq_product(64, 2, 0, p, p, p, p, None, 0, None) == _abi.CFPQ_ENOMEM
     assert lib.cfpq_product(600000, 2, 0, p, p, p, p, p, 1 << 40, None) == _abi.CFPQ_EINVAL  # MFMA size bound

@@ -2,8 +2,9 @@
 
 Bit-exact everywhere (the whole computation is Boolean).  Cases span the
 paper's worked example, the five workload recipes at oracle-friendly sizes,
-ragged sizes around the 64/256 tile edges, degenerate inputs, and both product
-kernels under both schedules.
+ragged sizes around the 64/256 tile edges, degenerate inputs, and every
+product kernel (dense VALU, dense MFMA, sparse rows, sparse columns, and the
+hybrid per-product choice) under both schedules.
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ from workloads import configs, grammars, graphs
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
-PATHS = ["bits", "mfma"]
+PATHS = ["bits", "mfma", "rows", "cols"]
 SCHEDULES = ["inplace", "jacobi"]
 
 
@@ -98,10 +99,11 @@ MAKERS = {
 
 
 @pytest.mark.parametrize("name", sorted(MAKERS))
-@pytest.mark.parametrize("path", PATHS)
-def test_workload_digest(cfpq, name, path):
+@pytest.mark.parametrize("path,hybrid", [("bits", 0), ("mfma", 0), ("rows", 0), ("cols", 0), ("bits", 1),
+                                         ("mfma", 1)])
+def test_workload_digest(cfpq, name, path, hybrid):
     inst = MAKERS[name]()
-    bits, res = _run(cfpq, inst, path=path)
+    bits, res = _run(cfpq, inst, path=path, hybrid=hybrid)
     d = DIGESTS[name]
     got = [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits]
     assert got == d["counts"]
@@ -267,18 +269,57 @@ def test_closure_with_each_bits_tile(cfpq):
         assert np.array_equal(bits, want), tile
 
 
-@pytest.mark.parametrize("path", ["auto", "bits"])
-def test_full_size_er16384(cfpq, path):
+@pytest.mark.parametrize("path,hybrid", [("auto", 0), ("auto", 1), ("bits", 1)])
+def test_full_size_er16384(cfpq, path, hybrid):
     """The benchmark workload at full size (n = 16384, device-resident edges,
-    the benchmark's launch configuration for "auto"), bit-exact against the
-    oracle's stored digest."""
+    the benchmark's launch configurations: the dense autotuned kernel, and the
+    hybrid choice), bit-exact against the oracle's stored digest."""
     import torch
     inst = configs.config3(16384)
     d = DIGESTS.get("er16384_dyck")
     if d is None:
         pytest.skip("digest for the 16384-node workload not generated")
-    _say(inst.tag, path)
-    res = cfpq.closure(inst.n, torch.from_numpy(inst.edges).cuda(), inst.grammar, path=path)
+    _say(inst.tag, path, hybrid)
+    res = cfpq.closure(inst.n, torch.from_numpy(inst.edges).cuda(), inst.grammar, path=path, hybrid=hybrid)
     bits = cfpq.result_bits(res)
     assert [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits] == d["counts"]
     assert _digest(bits) == d["sha256"]
+    if hybrid:
+        # the three rules with a terminal operand run sparse, S -> S S dense
+        assert 0 < res.stats["sparse_products"] < res.stats["products"]
+    else:
+        assert res.stats["sparse_products"] == 0
+
+
+# ---------------------------------------------------------------- hybrid choice
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_hybrid_equals_dense_and_oracle(cfpq, schedule):
+    """At a padded size where the hybrid choice is in effect: identical bits
+    with and without it, equal to the oracle; loop counts agree (the choice
+    changes only how a product is computed, never what it adds)."""
+    inst = configs.config3(4096)
+    want = worklist.closure(inst.n, inst.edges, inst.grammar)
+    a, ra = _run(cfpq, inst, path="mfma", schedule=schedule, hybrid=0, capture=0)
+    b, rb = _run(cfpq, inst, path="mfma", schedule=schedule, hybrid=1)
+    assert np.array_equal(a, want) and np.array_equal(b, want)
+    assert rb.stats["sparse_products"] > 0
+    assert ra.stats["sparse_products"] == 0
+    if schedule == "jacobi":
+        assert ra.stats["iterations"] == rb.stats["iterations"]
+        assert ra.stats["products"] == rb.stats["products"]
+    # the dense products are the only ones counted as bit-operations
+    npad = cfpq.padded_rows(inst.n)
+    dense = rb.stats["products"] - rb.stats["sparse_products"]
+    assert rb.stats["bitops"] == 2.0 * npad ** 3 * dense
+
+
+@pytest.mark.parametrize("path", ["rows", "cols"])
+def test_sparse_paths_under_jacobi_give_algorithm_1_loops(cfpq, path):
+    """Jacobi with the sparse products reproduces Algorithm 1's loop count on
+    the two-cycle graph (8065, pinned by the oracle tests)."""
+    inst = configs.config1()
+    bits, res = _run(cfpq, inst, path=path, schedule="jacobi", dirty=True)
+    assert res.stats["iterations"] == 8065
+    assert res.stats["sparse_products"] == res.stats["products"]
+    assert np.array_equal(bits, worklist.closure(inst.n, inst.edges, inst.grammar))
