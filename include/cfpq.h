@@ -119,7 +119,12 @@ typedef struct {
                                 from the current number of set bits of its operands (a cost
                                 model; the bits are the same whichever runs).  The loop is then
                                 host-driven.  CFPQ_HYBRID_OFF: every product is dense. */
-    int32_t reserved;        /* must be 0 */
+    int32_t warm_start;      /* 0: d_result is overwritten.  1: d_result already holds matrices in
+                                the bit layout that are subsets of R (for example a result of
+                                CFPQ_ENOTCONV, or R of the same graph with fewer edges); the edge
+                                initialisation is OR-ed into them and the loop continues from
+                                there.  The fixpoint is the same (R is the least fixpoint above the
+                                initial matrices, Theorem 2); only the loop count drops. */
     int64_t max_iters;       /* loop cap; 0 = |V|^2 |N| + 1 (Theorem 3's bound) */
 } cfpq_options;
 
@@ -143,8 +148,8 @@ CFPQ_API int32_t cfpq_abi_version(void);
 CFPQ_API const char* cfpq_last_error(void);
 
 /* Fill `opt` with defaults: AUTO path, hybrid choice on, in-place schedule,
- * dirty worklist on, 8 loops per captured graph, no per-product timing,
- * max_iters from Theorem 3. */
+ * dirty worklist on, 8 loops per captured graph, no per-product timing, no
+ * warm start, max_iters from Theorem 3. */
 CFPQ_API void cfpq_default_options(cfpq_options* opt);
 
 /* Words per matrix row: ceil(n/64) rounded up to a multiple of 4 (n >= 0). */
@@ -273,9 +278,10 @@ CFPQ_API cfpq_status cfpq_batch_workspace_bytes(int32_t n_instances, const cfpq_
  * whole fixpoint in one workgroup each (VALU product); larger ones share a
  * per-loop work list of 256 x 256 int8-MFMA tiles, with `opt->capture` loops
  * (0 = 8) per captured HIP graph.  Results are bit-identical to
- * cfpq_closure on each instance alone.  opt: schedule must be INPLACE;
- * dirty_worklist, capture and max_iters apply to every instance; path, tile
- * and profile are ignored.  Instances are limited to 2^19 nodes.
+ * cfpq_closure on each instance alone.  opt: schedule must be INPLACE and
+ * warm_start 0; dirty_worklist, capture and max_iters apply to every
+ * instance; path, tile, hybrid and profile are ignored.  Instances are limited
+ * to 2^19 nodes.
  * stats: NULL or n_instances entries (device_ms is the whole batch's time).
  * Returns CFPQ_OK, CFPQ_ENOTCONV (some instance hit max_iters; all results
  * are sound), CFPQ_EINVAL (message names the instance), CFPQ_ENOMEM or

@@ -75,13 +75,14 @@ def _grammar_struct_new(grammar):
 
 
 def _options(path="auto", schedule="inplace", dirty=True, max_iters=0, profile=False, tile=0, capture=None,
-             hybrid=None):
+             hybrid=None, warm_start=False):
     o = _abi.Options()
     lib().cfpq_default_options(ctypes.byref(o))
     if capture is not None:
         o.capture = int(capture)
     if hybrid is not None:
         o.hybrid = int(hybrid)
+    o.warm_start = 1 if warm_start else 0
     o.profile = 1 if profile else 0
     o.tile = int(tile)
     o.path = _PATHS[path] if isinstance(path, str) else int(path)
@@ -108,7 +109,7 @@ def _stream_ptr(stream):
 
 def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=True, max_iters=0,
             device=None, stream=None, out=None, workspace=None, allow_partial=False,
-            profile=False, tile=0, capture=None, hybrid=None) -> Result:
+            profile=False, tile=0, capture=None, hybrid=None, warm_start=False) -> Result:
     """Relational CFPQ closure (Algorithm 1) through ``cfpq_closure``.
 
     ``edges`` is an int32 array [m, 3] of (src, label, dst) on the host, or an
@@ -118,7 +119,8 @@ def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=Tr
     CFPQ_ENOTCONV and returns the sound partial result).  ``path`` is "auto",
     "bits", "mfma" (dense kernel), "rows" or "cols" (every product skips the
     zeros of one operand); ``hybrid`` (None = library default, on) lets each
-    product choose between the dense kernel and rows/cols."""
+    product choose between the dense kernel and rows/cols.  ``warm_start``
+    continues from the matrices already in ``out`` (each a subset of R)."""
     torch = _torch()
     L = lib()
     device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -130,7 +132,9 @@ def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=Tr
     else:
         e_host = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
         graph = _abi.Graph(int(n), 0, int(e_host.shape[0]), ctypes.c_void_p(e_host.ctypes.data))
-    opt = _options(path, schedule, dirty, max_iters, profile, tile, capture, hybrid)
+    if warm_start and out is None:
+        raise ValueError("warm_start needs `out` holding the initial matrices")
+    opt = _options(path, schedule, dirty, max_iters, profile, tile, capture, hybrid, warm_start)
     need = ctypes.c_size_t(0)
     _abi.check(L.cfpq_workspace_bytes(ctypes.byref(graph), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(need)))
     res_words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8

@@ -58,7 +58,7 @@ class Instance(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("schedule", ctypes.c_int32), ("dirty_worklist", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("tile", ctypes.c_int32), ("capture", ctypes.c_int32),
-                ("hybrid", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_iters", ctypes.c_int64)]
+                ("hybrid", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("max_iters", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):

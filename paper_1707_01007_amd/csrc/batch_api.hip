@@ -138,6 +138,7 @@ cfpq_status validate_batch(int32_t n, const cfpq_instance* inst, const cfpq_opti
     if (o.schedule != CFPQ_SCHEDULE_INPLACE)
         return fail(CFPQ_EINVAL, "the batched engine runs the in-place schedule only");
     if (o.max_iters < 0 || o.capture < 0) return fail(CFPQ_EINVAL, "negative option");
+    if (o.warm_start != 0) return fail(CFPQ_EINVAL, "the batched engine has no warm start");
     for (int32_t i = 0; i < n; ++i) {
         cfpq_status st = validate_grammar(inst[i].grammar);
         if (st != CFPQ_OK) return fail(st, "instance " + std::to_string(i) + ": " + cfpq_last_error());

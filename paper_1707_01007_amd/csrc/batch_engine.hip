@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
         uint32_t* Am = reinterpret_cast<uint32_t*>(d.T) + ra * mdw;
         const int kchunks = ((d.n + 255) / 256) * 2;
         mfma::mfma_tile<true>(Bm, CT, Am, 2 * d.W, kchunks, local / jb.dim, local % jb.dim,
-                              &states[jb.slot].changed[ra], nullptr);
+                              &states[jb.slot].changed[ra]);
     }
 }
 

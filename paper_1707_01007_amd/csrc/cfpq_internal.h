@@ -80,10 +80,9 @@ hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t*
 // A |= B x C on the VALU: AND/OR over bit-packed rows.  `strip` is the
 // output strip width in 32-bit words per workgroup (8, 16 or 32; 0 or an
 // unsupported width = bits_default_strip).
-// nnz (optional): incremented by the number of bits the product added.
 hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L,
                                int32_t* changed, hipStream_t s, int strip, const int32_t* go = nullptr,
-                               int32_t want = 1, unsigned long long* nnz = nullptr);
+                               int32_t want = 1);
 bool bits_strip_supported(int strip, const Layout& L);
 int bits_default_strip(const Layout& L);
 
@@ -96,17 +95,15 @@ bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile, float* ms = nul
 
 // A |= B x C on the int8 matrix cores; CT is the transpose of C.
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1,
-                               unsigned long long* nnz = nullptr);
+                               int32_t* changed, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1);
 
 // Sparse-operand products (kernels_sparse.hip): A[i,:] |= OR_{k in nz(B[i,:])} C[k,:]
-// for rows i < n, and A |= transpose(Pt).
+// for rows i < n, and A |= transpose(Pt).  `changed` may be NULL for the
+// row product (no flag wanted).
 hipError_t launch_rowor_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L, int32_t* changed,
-                                unsigned long long* nnz, hipStream_t s, const int32_t* go = nullptr,
-                                int32_t want = 1);
-hipError_t launch_transpose_or(const uint64_t* Pt, uint64_t* A, const Layout& L, int32_t* changed,
-                               unsigned long long* nnz, hipStream_t s, const int32_t* go = nullptr,
-                               int32_t want = 1);
+                                hipStream_t s, const int32_t* go = nullptr, int32_t want = 1);
+hipError_t launch_transpose_or(const uint64_t* Pt, uint64_t* A, const Layout& L, int32_t* changed, hipStream_t s,
+                               const int32_t* go = nullptr, int32_t want = 1);
 
 // dst = transpose(src) (bit matrix, npad x npad).
 hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s,
@@ -131,17 +128,19 @@ constexpr int64_t kHybridMinRows = 4096;
 
 // Estimated time (us) of each way to run T_A |= T_B x T_C from the current set
 // bit counts of B and C.  Only speed depends on it: every mode gives the same
-// bits.
+// bits.  Constants from measurements of the kernels at n = 16384 (rows: about
+// 0.17 ns per set bit of the sparse operand per 2 KiB row; a bit transpose
+// about 9 matrix passes' worth of time).
 struct HybridModel {
     double dense_us = 0;  // one dense product at this size
-    double fixed_us = 5;  // launch and fixed cost of one sparse kernel
+    double fixed_us = 10; // launch and fixed cost of one sparse kernel
     double row_us = 0;    // reading one W-word row of the other operand
-    double mat_us = 0;    // one full pass over a matrix
+    double mat_us = 0;    // one streamed pass over a matrix
 };
 
 inline int32_t hybrid_mode(const HybridModel& m, double nnz_b, double nnz_c, bool left_transposed) {
     const double rows = m.fixed_us + nnz_b * m.row_us + 3.0 * m.mat_us;
-    const double cols = 3.0 * m.fixed_us + nnz_c * m.row_us + (left_transposed ? 6.0 : 8.0) * m.mat_us;
+    const double cols = 3.0 * m.fixed_us + nnz_c * m.row_us + (left_transposed ? 14.0 : 23.0) * m.mat_us;
     if (rows <= cols && rows < m.dense_us) return kModeRows;
     if (cols < rows && cols < m.dense_us) return kModeCols;
     return kModeDense;

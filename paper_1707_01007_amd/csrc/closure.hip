@@ -128,8 +128,8 @@ HybridModel make_model(const Layout& L, int32_t path, float tuned_ms) {
     // dense rates measured for the two kernels at n = 16384 (bit-ops per us)
     const double rate = path == CFPQ_PATH_MFMA ? 4.0e9 : 1.8e9;
     m.dense_us = tuned_ms > 0 ? 1000.0 * tuned_ms : 5.0 + 2.0 * npad * npad * npad / rate;
-    m.row_us = static_cast<double>(L.W) * 8.0 / 3.0e6;                // gathered rows, ~3 TB/s
-    m.mat_us = static_cast<double>(L.mat_words) * 8.0 / 4.0e6;        // streamed, ~4 TB/s
+    m.row_us = static_cast<double>(L.W) * 8.0 / 12.0e6;              // gathered rows, mostly cache hits
+    m.mat_us = static_cast<double>(L.mat_words) * 8.0 / 5.0e6;       // streamed, ~5 TB/s
     return m;
 }
 
@@ -176,8 +176,8 @@ Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& 
     off += align_up(static_cast<size_t>(std::max(gr->n_bin_rules, 1)) * 4, 256);
     p.off_state = off;
     off += align_up(sizeof(LoopState), 256);
-    p.off_nnz = off;  // n_nt set-bit counters, then one spare flag
-    off += align_up(static_cast<size_t>(p.n_nt) * 8 + 8, 256);
+    p.off_nnz = off;  // n_nt set-bit counters
+    off += align_up(static_cast<size_t>(p.n_nt) * 8, 256);
     p.off_second = off;
     if (p.jacobi) off += mat_bytes * p.n_nt;
     p.off_trans = off;
@@ -269,7 +269,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     const cfpq_options o = resolve(opt);
     if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_COLS) return fail(CFPQ_EINVAL, "unknown path");
     if (o.hybrid != CFPQ_HYBRID_OFF && o.hybrid != CFPQ_HYBRID_AUTO) return fail(CFPQ_EINVAL, "unknown hybrid mode");
-    if (o.reserved != 0) return fail(CFPQ_EINVAL, "options.reserved must be 0");
+    if (o.warm_start != 0 && o.warm_start != 1) return fail(CFPQ_EINVAL, "options.warm_start must be 0 or 1");
     if (o.schedule != CFPQ_SCHEDULE_INPLACE && o.schedule != CFPQ_SCHEDULE_JACOBI)
         return fail(CFPQ_EINVAL, "unknown schedule");
     if (o.max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
@@ -329,7 +329,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     uint64_t* X = d_result;
     uint64_t* Y = p.jacobi ? reinterpret_cast<uint64_t*>(ws + p.off_second) : d_result;
     uint64_t* TT = reinterpret_cast<uint64_t*>(ws + p.off_trans);
-    CFPQ_HIP(launch_zero(X, mat_words * n_nt, s));
+    if (!o.warm_start) CFPQ_HIP(launch_zero(X, mat_words * n_nt, s));
     CFPQ_HIP(launch_init_scatter(d_edges, graph->n_edges, d_term_off, d_term_lhs, grammar->n_terminals,
                                  graph->n_nodes, X, L, d_bad, s));
     if (graph->edges_on_device) {
@@ -438,22 +438,29 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     }
 
     // ---- host-driven loop: one flag read-back per loop ----
+    // Hybrid choice: set-bit counts of every matrix at the start of each loop,
+    // read back with the change flags.
     auto* d_nnz = reinterpret_cast<unsigned long long*>(ws + p.off_nnz);
-    auto* d_spare = reinterpret_cast<int32_t*>(d_nnz + n_nt);  // change flag nobody reads
     uint64_t* BT = reinterpret_cast<uint64_t*>(ws + p.off_bt);
     uint64_t* PT = reinterpret_cast<uint64_t*>(ws + p.off_pt);
     std::vector<unsigned long long> nnz(n_nt, 0);
+    std::vector<char> written(n_nt, 0);  // a product wrote this nonterminal in the current loop
     int64_t sparse_products = 0;
-    if (!captured && p.hybrid && !converged) {
+    auto count_bits = [&](const uint64_t* mats) -> cfpq_status {
         CFPQ_HIP(hipMemsetAsync(d_nnz, 0, static_cast<size_t>(n_nt) * 8, s));
-        CFPQ_HIP(launch_popcount(X, n_nt, L, d_nnz, s));
+        CFPQ_HIP(launch_popcount(mats, n_nt, L, d_nnz, s));
         CFPQ_HIP(hipMemcpyAsync(nnz.data(), d_nnz, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
+        return CFPQ_OK;
+    };
+    if (!captured && p.hybrid && !converged) {
+        st = count_bits(X);
+        if (st != CFPQ_OK) return st;
         CFPQ_HIP(hipStreamSynchronize(s));
     }
-    unsigned long long* nnz_of = p.hybrid ? d_nnz : nullptr;
     while (!captured && !converged && iters < cap) {
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         size_t launched = 0;
+        std::fill(written.begin(), written.end(), 0);
         for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
             const auto& br = grammar->bin_rules[r];
             if (o.dirty_worklist && iters > 0 && !prev[br.left] && !prev[br.right]) continue;
@@ -464,30 +471,33 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                 if (!e) return fail(CFPQ_EDEVICE, "hipEventCreate failed");
                 CFPQ_HIP(hipEventRecord(e, s));
             }
+            // COLS reads B^T: the kept transpose, unless (in place) B was written
+            // earlier in this loop, when a fresh transpose lets the product see
+            // those bits now rather than a loop later
+            const bool left_kept = p.right_slot[br.left] >= 0 && !(!p.jacobi && written[br.left]);
             const int32_t mode = p.hybrid ? hybrid_mode(p.model, static_cast<double>(nnz[br.left]),
-                                                         static_cast<double>(nnz[br.right]),
-                                                         p.right_slot[br.left] >= 0)
+                                                         static_cast<double>(nnz[br.right]), left_kept)
                                           : p.forced;
             int32_t* flag = d_flags + br.lhs;
-            unsigned long long* cnt = nnz_of ? nnz_of + br.lhs : nullptr;
             if (mode == kModeRows) {
-                CFPQ_HIP(launch_rowor_product(Bm, X + br.right * mat_words, Am, L, flag, cnt, s));
+                CFPQ_HIP(launch_rowor_product(Bm, X + br.right * mat_words, Am, L, flag, s));
             } else if (mode == kModeCols) {
                 // (B x C)^T = C^T x B^T by rows of C^T, then transposed into A
                 const uint64_t* CT = TT + p.right_slot[br.right] * mat_words;
                 const uint64_t* BTm = BT;
-                if (p.right_slot[br.left] >= 0) BTm = TT + p.right_slot[br.left] * mat_words;
+                if (left_kept) BTm = TT + p.right_slot[br.left] * mat_words;
                 else CFPQ_HIP(launch_transpose(Bm, BT, L, s));
                 CFPQ_HIP(launch_zero(PT, mat_words, s));
-                CFPQ_HIP(launch_rowor_product(CT, BTm, PT, L, d_spare, nullptr, s));
-                CFPQ_HIP(launch_transpose_or(PT, Am, L, flag, cnt, s));
+                CFPQ_HIP(launch_rowor_product(CT, BTm, PT, L, nullptr, s));
+                CFPQ_HIP(launch_transpose_or(PT, Am, L, flag, s));
             } else if (p.path == CFPQ_PATH_MFMA) {
                 const uint64_t* CT = TT + p.right_slot[br.right] * mat_words;
-                CFPQ_HIP(launch_mfma_product(Bm, CT, Am, L, flag, s, nullptr, 1, cnt));
+                CFPQ_HIP(launch_mfma_product(Bm, CT, Am, L, flag, s));
             } else {
-                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, flag, s, p.tile, nullptr, 1, cnt));
+                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, flag, s, p.tile));
             }
             if (mode != kModeDense) ++sparse_products;
+            written[br.lhs] = 1;
             if (o.profile) {
                 hipEvent_t e = product_event(2 * launched + 1);
                 if (!e) return fail(CFPQ_EDEVICE, "hipEventCreate failed");
@@ -497,8 +507,10 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             ++products;
         }
         CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
-        if (nnz_of)
-            CFPQ_HIP(hipMemcpyAsync(nnz.data(), d_nnz, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
+        if (p.hybrid) {
+            st = count_bits(Y);
+            if (st != CFPQ_OK) return st;
+        }
         CFPQ_HIP(hipStreamSynchronize(s));
         for (size_t q = 0; o.profile && q < launched; ++q) {
             float pm = 0.f;
@@ -548,7 +560,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
 size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path) {
     const size_t mat = static_cast<size_t>(layout_for(n_nodes < 0 ? 0 : n_nodes).mat_words) * 8;
     if (path == CFPQ_PATH_MFMA) return mat;
-    if (path == CFPQ_PATH_COLS) return 3 * mat + 256;
+    if (path == CFPQ_PATH_COLS) return 3 * mat;
     return 0;
 }
 
@@ -579,17 +591,16 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
             CFPQ_HIP(launch_mfma_product(d_b, ws, d_a, L, d_changed, s));
             break;
         case CFPQ_PATH_ROWS:
-            CFPQ_HIP(launch_rowor_product(d_b, d_c, d_a, L, d_changed, nullptr, s));
+            CFPQ_HIP(launch_rowor_product(d_b, d_c, d_a, L, d_changed, s));
             break;
         case CFPQ_PATH_COLS: {
-            // workspace: C^T, B^T, the transposed product, a flag nobody reads
+            // workspace: C^T, B^T, the transposed product
             uint64_t *ct = ws, *bt = ws + mw, *pt = ws + 2 * mw;
-            auto* spare = reinterpret_cast<int32_t*>(ws + 3 * mw);
             CFPQ_HIP(launch_transpose(d_c, ct, L, s));
             CFPQ_HIP(launch_transpose(d_b, bt, L, s));
             CFPQ_HIP(launch_zero(pt, mw, s));
-            CFPQ_HIP(launch_rowor_product(ct, bt, pt, L, spare, nullptr, s));
-            CFPQ_HIP(launch_transpose_or(pt, d_a, L, d_changed, nullptr, s));
+            CFPQ_HIP(launch_rowor_product(ct, bt, pt, L, nullptr, s));
+            CFPQ_HIP(launch_transpose_or(pt, d_a, L, d_changed, s));
             break;
         }
         default:

@@ -25,8 +25,7 @@ template <int R>
 __global__ __launch_bounds__(256) void bits_product_kernel(const uint32_t* __restrict__ Bm,
                                                            const uint32_t* __restrict__ Cm,
                                                            uint32_t* Am, int W2, int kdw,
-                                                           int32_t* changed, unsigned long long* nnz,
-                                                           const int32_t* go, int32_t want) {
+                                                           int32_t* changed, const int32_t* go, int32_t want) {
     if (go != nullptr && *go != want) return;
     const int strip = blockIdx.x;
     const int row = blockIdx.y * 256 + threadIdx.x;
@@ -53,20 +52,14 @@ __global__ __launch_bounds__(256) void bits_product_kernel(const uint32_t* __res
 
     uint32_t* arow = Am + static_cast<size_t>(row) * W2 + static_cast<size_t>(strip) * R;
     bool ch = false;
-    unsigned long long fresh = 0;
 #pragma unroll
     for (int r = 0; r < R; r += 4) {
         uint4 old = *reinterpret_cast<const uint4*>(arow + r);
         uint4 nw = make_uint4(old.x | acc[r], old.y | acc[r + 1], old.z | acc[r + 2], old.w | acc[r + 3]);
         if (nw.x != old.x || nw.y != old.y || nw.z != old.z || nw.w != old.w) {
             *reinterpret_cast<uint4*>(arow + r) = nw;
-            fresh += __popc(nw.x ^ old.x) + __popc(nw.y ^ old.y) + __popc(nw.z ^ old.z) + __popc(nw.w ^ old.w);
             ch = true;
         }
-    }
-    if (nnz) {
-        for (int off = 32; off > 0; off >>= 1) fresh += __shfl_down(fresh, off, 64);
-        if ((threadIdx.x & 63) == 0 && fresh) atomicAdd(nnz, fresh);
     }
     if (__ballot(ch) != 0 && (threadIdx.x & 63) == 0) atomicOr(changed, 1);
 }
@@ -84,8 +77,7 @@ int bits_default_strip(const Layout& L) {
 }
 
 hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s, int strip, const int32_t* go, int32_t want,
-                               unsigned long long* nnz) {
+                               int32_t* changed, hipStream_t s, int strip, const int32_t* go, int32_t want) {
     const int W2 = static_cast<int>(2 * L.W);
     const int kdw = static_cast<int>((L.n + 31) / 32);
     if (kdw == 0) return hipSuccess;
@@ -96,9 +88,9 @@ hipError_t launch_bits_product(const uint64_t* B, const uint64_t* C, uint64_t* A
     auto* a = reinterpret_cast<uint32_t*>(A);
     const dim3 grid(static_cast<unsigned>(W2 / strip), row_blocks);
     switch (strip) {
-        case 32: bits_product_kernel<32><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed, nnz, go, want); break;
-        case 16: bits_product_kernel<16><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed, nnz, go, want); break;
-        default: bits_product_kernel<8><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed, nnz, go, want); break;
+        case 32: bits_product_kernel<32><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed, go, want); break;
+        case 16: bits_product_kernel<16><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed, go, want); break;
+        default: bits_product_kernel<8><<<grid, dim3(256), 0, s>>>(b, c, a, W2, kdw, changed, go, want); break;
     }
     return hipGetLastError();
 }

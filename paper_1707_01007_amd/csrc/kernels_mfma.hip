@@ -40,8 +40,7 @@ __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __res
                                                            const uint32_t* __restrict__ CT,
                                                            uint32_t* Am, int W2, int kchunks,
                                                            int tiles_dim, int grouped,
-                                                           int32_t* changed, unsigned long long* nnz,
-                                                           const int32_t* go, int32_t want) {
+                                                           int32_t* changed, const int32_t* go, int32_t want) {
     if (go != nullptr && *go != want) return;
     // ---- workgroup -> tile, XCD-aware ----
     // grouped: tiles_dim is a multiple of 32, so each XCD owns tiles_dim / 8
@@ -62,13 +61,12 @@ __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __res
         tile_j = wg % tiles_dim;
     }
 
-    mfma::mfma_tile<false>(Bm, CT, Am, W2, kchunks, tile_i, tile_j, changed, nnz);
+    mfma::mfma_tile<false>(Bm, CT, Am, W2, kchunks, tile_i, tile_j, changed);
 }
 
 }  // namespace
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
-                               int32_t* changed, hipStream_t s, const int32_t* go, int32_t want,
-                               unsigned long long* nnz) {
+                               int32_t* changed, hipStream_t s, const int32_t* go, int32_t want) {
     const int W2 = static_cast<int>(2 * L.W);
     // 128 k per chunk, an even number of chunks (rows hold npad / 128 of them,
     // npad a multiple of 256, and bits past n are zero)
@@ -79,7 +77,7 @@ hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* 
     const int grouped = (tiles_dim % 32 == 0) ? 1 : 0;
     mfma_product_kernel<<<dim3(static_cast<unsigned>(total)), dim3(256), 0, s>>>(
         reinterpret_cast<const uint32_t*>(B), reinterpret_cast<const uint32_t*>(CT),
-        reinterpret_cast<uint32_t*>(A), W2, kchunks, tiles_dim, grouped, changed, nnz, go, want);
+        reinterpret_cast<uint32_t*>(A), W2, kchunks, tiles_dim, grouped, changed, go, want);
     return hipGetLastError();
 }
 

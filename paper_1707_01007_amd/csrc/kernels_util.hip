@@ -68,9 +68,15 @@ __global__ __launch_bounds__(256) void popcount_kernel(const uint64_t* __restric
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < mat_words;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
         c += __popcll(m[i]);
-    // wavefront reduction, then one atomic per wave
+    // wavefront reduction, then one atomic per workgroup
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(counts + blockIdx.y, c);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(counts + blockIdx.y, t);
+    }
 }
 
 }  // namespace
@@ -105,7 +111,7 @@ hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,
                            unsigned long long* counts, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     int64_t blocks = (L.mat_words + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > 2048) blocks = 2048;
     popcount_kernel<<<dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(count)), dim3(256), 0,
                       s>>>(mats, L.mat_words, counts);
     return hipGetLastError();

@@ -70,7 +70,7 @@ __device__ __forceinline__ void mma_chunk(v16i (&acc)[kJT][kIT], const Chunk& ch
 template <bool kAtomic>
 __device__ __forceinline__ void mfma_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
                                           uint32_t* Am, int W2, int kchunks, int tile_i, int tile_j,
-                                          int32_t* changed, unsigned long long* nnz) {
+                                          int32_t* changed) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 5;          // which 16-k half of a 32-k step this lane feeds
@@ -118,7 +118,6 @@ __device__ __forceinline__ void mfma_tile(const uint32_t* __restrict__ Bm, const
     // Accumulator e of lane (g, r32) in block (jb, ib) is D[j][i] with
     // i = i0 + 32 ib + r32 and j = j0 + 32 jb + 8 (e / 4) + 4 g + (e % 4).
     bool ch = false;
-    unsigned long long fresh = 0;
 #pragma unroll
     for (int ib = 0; ib < kIT; ++ib) {
         uint32_t word[kJT];
@@ -144,20 +143,12 @@ __device__ __forceinline__ void mfma_tile(const uint32_t* __restrict__ Bm, const
             if (kAtomic) {
                 const uint64_t prev = atomicOr(reinterpret_cast<unsigned long long*>(dst),
                                                static_cast<unsigned long long>(add));
-                if ((add & ~prev) != 0) {
-                    ch = true;
-                    fresh += __popcll(add & ~prev);
-                }
+                if ((add & ~prev) != 0) ch = true;
             } else {
                 *dst = old | add;
-                fresh += __popcll(add & ~old);
                 ch = true;
             }
         }
-    }
-    if (nnz) {
-        for (int off = 32; off > 0; off >>= 1) fresh += __shfl_down(fresh, off, 64);
-        if (lane == 0 && fresh) atomicAdd(nnz, fresh);
     }
     if (__ballot(ch) != 0 && lane == 0) atomicOr(changed, 1);
 }

@@ -118,14 +118,14 @@ def test_closure_rejects_small_workspace_and_null_result():
     assert rc == _abi.CFPQ_EINVAL
 
 
-@pytest.mark.parametrize("field,value", [("hybrid", 5), ("reserved", 1), ("path", 5), ("path", -1)])
+@pytest.mark.parametrize("field,value", [("hybrid", 5), ("warm_start", 2), ("path", 5), ("path", -1)])
 def test_closure_rejects_bad_options_before_device_work(field, value):
     from paper_1707_01007_amd import _abi
     lib = _lib()
     gr, g, keep = _structs()
     opt = _abi.Options()
     lib.cfpq_default_options(ctypes.byref(opt))
-    assert opt.hybrid == _abi.HYBRID_AUTO and opt.reserved == 0
+    assert opt.hybrid == _abi.HYBRID_AUTO and opt.warm_start == 0
     setattr(opt, field, value)
     rc = lib.cfpq_closure(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), None, ctypes.c_void_p(1 << 20),
                           ctypes.c_size_t(1 << 30), ctypes.c_void_p(1 << 21), None)
@@ -168,7 +168,7 @@ def test_workspace_grows_with_sparse_temporaries():
     assert sizes["cols"] == sizes["mfma_dense"] + 2 * mat   # one right operand (B) transposed in both
     assert sizes["bits_hybrid"] == sizes["cols"]
     assert lib.cfpq_product_workspace_bytes(n, 3) == 0
-    assert lib.cfpq_product_workspace_bytes(n, 4) == 3 * mat + 256
+    assert lib.cfpq_product_workspace_bytes(n, 4) == 3 * mat
 
 
 def test_struct_layouts_match_the_header(tmp_path):

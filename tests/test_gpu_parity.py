@@ -323,3 +323,32 @@ def test_sparse_paths_under_jacobi_give_algorithm_1_loops(cfpq, path):
     assert res.stats["iterations"] == 8065
     assert res.stats["sparse_products"] == res.stats["products"]
     assert np.array_equal(bits, worklist.closure(inst.n, inst.edges, inst.grammar))
+
+
+# ---------------------------------------------------------------- warm start
+
+@pytest.mark.parametrize("path", ["bits", "mfma", "rows", "cols"])
+def test_warm_start_resumes_a_partial_result(cfpq, path):
+    """A result cut short by max_iters (a sound subset of R) continues to R."""
+    inst = configs.config3(1024)
+    want = worklist.closure(inst.n, inst.edges, inst.grammar)
+    _say("warm start partial", path)
+    part = cfpq.closure(inst.n, inst.edges, inst.grammar, path=path, max_iters=2, allow_partial=True)
+    assert part.status == -4
+    assert not np.array_equal(cfpq.result_bits(part), want)
+    res = cfpq.closure(inst.n, inst.edges, inst.grammar, path=path, out=part.bits.view(-1), warm_start=True)
+    assert np.array_equal(cfpq.result_bits(res), want)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_warm_start_after_adding_edges(cfpq, schedule):
+    """R of a graph is a subset of R of the graph with more edges
+    (monotonicity), so it is a valid starting point for the larger graph."""
+    inst = configs.config3(2048)
+    half = inst.edges[: len(inst.edges) // 2]
+    _say("warm start edges", schedule)
+    first = cfpq.closure(inst.n, half, inst.grammar, schedule=schedule)
+    assert np.array_equal(cfpq.result_bits(first), worklist.closure(inst.n, half, inst.grammar))
+    res = cfpq.closure(inst.n, inst.edges, inst.grammar, schedule=schedule, out=first.bits.view(-1),
+                       warm_start=True)
+    assert np.array_equal(cfpq.result_bits(res), worklist.closure(inst.n, inst.edges, inst.grammar))
