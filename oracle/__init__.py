@@ -17,11 +17,16 @@ Contents and what each follows:
   truncated at a path length.
 * ``brute``: CYK over a CNF grammar and enumeration of every path up to a
   length bound, straight from the definition of R_A (section 2).
+* ``single_path``: the path lengths of section 5 (l_A = l_B + l_C when a step
+  first adds A to a cell, kept afterwards; the smallest sum when one step
+  offers several) and a witness path for any stored length.
 
 Pins (tests/test_oracle_*.py): the worked example of section 4.3 (every
 printed T_k, the loop count 6 and all seven R_A), a closed form for two label
 cycles of coprime length, textbook special cases (transitive closure, CYK on a
 chain, bracket matching, terminal-only grammars), brute force on tiny graphs,
 and invariants (closure, monotonicity, permutation equivariance, disjoint
-union).  Every function here has at least one such pin.
+union); for the lengths, breadth-first search, chains, the two-cycle closed
+form, a first-found-is-kept case and CYK on every witness.  Every function here
+has at least one such pin.
 """
