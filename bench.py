@@ -144,13 +144,14 @@ def _pct(xs, q):
     return round(float(np.percentile(np.asarray(xs), q)), 3) if xs else None
 
 
-def bench_serve(cfpq, torch, warm=100, measured=500, load=1.5):
+def bench_serve(cfpq, torch, warm=100, measured=500, loads=(1.5, 0.5)):
     """Serving stream (sizes log-uniform in [128, 8192], hierarchy or G(n, 4n),
     a^n b^n / same-generation / Dyck), host edges as a request would bring them.
     The first `warm` requests measure the serial plain closure's service rate
     mu; the next `measured` arrive as a Poisson process at lambda = load * mu
     and are served (a) by the continuous-batching server and (b) one at a time,
-    in arrival order, by the plain closure (no batching, no captured loops)."""
+    in arrival order, by the plain closure (no batching, no captured loops; the
+    library's default product choice, as for any single query)."""
     from workloads import configs
     insts, gaps = configs.config5(count=warm + measured)
     warm_set, meas = insts[:warm], insts[warm:]
@@ -162,11 +163,6 @@ def bench_serve(cfpq, torch, warm=100, measured=500, load=1.5):
         cfpq.closure(i.n, i.edges, i.grammar, capture=0)
     torch.cuda.synchronize()
     mu = warm / (time.perf_counter() - t0)
-    lam = load * mu
-    arrivals = [0.0]
-    for g in gaps[warm + 1:warm + measured]:
-        arrivals.append(arrivals[-1] + g / lam)
-    print(f"[bench] serving: mu={mu:.1f}/s lambda={lam:.1f}/s over {measured} requests", file=sys.stderr, flush=True)
 
     def spin_until(t):
         while True:
@@ -176,37 +172,49 @@ def bench_serve(cfpq, torch, warm=100, measured=500, load=1.5):
             if d > 2e-4:
                 time.sleep(d - 1e-4)
 
-    # (a) server
-    with cfpq.Server(hbm_budget=32 << 30, max_slots=512, capture=4) as srv:
-        # warm the server's code paths
-        for t in [srv.submit(i.n, i.edges, i.grammar) for i in warm_set[:20]]:
-            srv.wait(t)
+    def run(load):
+        lam = load * mu
+        arrivals = [0.0]
+        for g in gaps[warm + 1:warm + measured]:
+            arrivals.append(arrivals[-1] + g / lam)
+        print(f"[bench] serving: mu={mu:.1f}/s lambda={lam:.1f}/s over {measured} requests", file=sys.stderr,
+              flush=True)
+        # (a) server
+        with cfpq.Server(hbm_budget=32 << 30, max_slots=512, capture=4) as srv:
+            for t in [srv.submit(i.n, i.edges, i.grammar) for i in warm_set[:20]]:  # warm its code paths
+                srv.wait(t)
+            start = time.perf_counter()
+            tickets = []
+            for a, i in zip(arrivals, meas):
+                spin_until(start + a)
+                tickets.append(srv.submit(i.n, i.edges, i.grammar))
+            infos = [srv.wait(t) for t in tickets]
+            end = time.perf_counter()
+        lat_srv = [x["latency_ms"] for x in infos]
+        bad = sum(1 for x in infos if x["status"] != 0)
+        qps_srv = measured / (end - start)
+        # (b) serial plain closure on the same trace
         start = time.perf_counter()
-        tickets = []
+        lat_ser = []
         for a, i in zip(arrivals, meas):
             spin_until(start + a)
-            tickets.append(srv.submit(i.n, i.edges, i.grammar))
-        infos = [srv.wait(t) for t in tickets]
+            cfpq.closure(i.n, i.edges, i.grammar, capture=0)
+            lat_ser.append((time.perf_counter() - (start + a)) * 1e3)
         end = time.perf_counter()
-    lat_srv = [x["latency_ms"] for x in infos]
-    bad = sum(1 for x in infos if x["status"] != 0)
-    qps_srv = measured / (end - start)
-    # (b) serial plain closure on the same trace
-    start = time.perf_counter()
-    lat_ser = []
-    for a, i in zip(arrivals, meas):
-        spin_until(start + a)
-        cfpq.closure(i.n, i.edges, i.grammar, capture=0)
-        lat_ser.append((time.perf_counter() - (start + a)) * 1e3)
-    end = time.perf_counter()
-    qps_ser = measured / (end - start)
-    print(f"[bench] server {qps_srv:.1f} q/s p99 {_pct(lat_srv, 99)} ms; serial {qps_ser:.1f} q/s "
-          f"p99 {_pct(lat_ser, 99)} ms", file=sys.stderr, flush=True)
-    return {"workload": f"serve_seed5_{measured}req", "arrival": "poisson", "lambda_per_s": round(lam, 1),
-            "serial_service_rate_per_s": round(mu, 1), "load_vs_serial": load,
-            "queries_per_s": round(qps_srv, 1), "p50_ms": _pct(lat_srv, 50), "p99_ms": _pct(lat_srv, 99),
-            "serial_plain_queries_per_s": round(qps_ser, 1), "serial_plain_p50_ms": _pct(lat_ser, 50),
-            "serial_plain_p99_ms": _pct(lat_ser, 99), "failed": bad}
+        qps_ser = measured / (end - start)
+        print(f"[bench] server {qps_srv:.1f} q/s p50 {_pct(lat_srv, 50)} p99 {_pct(lat_srv, 99)} ms; serial "
+              f"{qps_ser:.1f} q/s p50 {_pct(lat_ser, 50)} p99 {_pct(lat_ser, 99)} ms", file=sys.stderr, flush=True)
+        return {"lambda_per_s": round(lam, 1), "load_vs_serial": load,
+                "queries_per_s": round(qps_srv, 1), "p50_ms": _pct(lat_srv, 50), "p99_ms": _pct(lat_srv, 99),
+                "serial_plain_queries_per_s": round(qps_ser, 1), "serial_plain_p50_ms": _pct(lat_ser, 50),
+                "serial_plain_p99_ms": _pct(lat_ser, 99), "failed": bad}
+
+    out = {"workload": f"serve_seed5_{measured}req", "arrival": "poisson",
+           "serial_service_rate_per_s": round(mu, 1)}
+    out.update(run(loads[0]))
+    for ld in loads[1:]:
+        out[f"at_load_{ld}"] = run(ld)
+    return out
 
 
 def main():

@@ -56,7 +56,8 @@ typedef enum {
     CFPQ_EDEVICE = -3,    /* a HIP call failed */
     CFPQ_ENOTCONV = -4,   /* max_iters reached; the partial result is sound (a subset of R) */
     CFPQ_EBUSY = -5,      /* no free slot (serving) */
-    CFPQ_ENOTREADY = -6   /* request still running (serving) */
+    CFPQ_ENOTREADY = -6,  /* request still running (serving) */
+    CFPQ_ERANGE = -7      /* a single-path length does not fit (>= 2^31 - 1) */
 } cfpq_status;
 
 /* Edge (src, label, dst) of E (section 2).  Multi-edges and self-loops are allowed. */
@@ -215,6 +216,54 @@ CFPQ_API cfpq_status cfpq_popcount(int32_t n_nodes, int32_t count, const uint64_
                           unsigned long long* d_counts, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Single-path semantics (section 5): a path length for every triple.
+ *
+ * Alongside R (the bit matrices of cfpq_closure), every (A, i, j) in R_A gets
+ * a length L_A(i, j) such that some path i -> j of exactly that many edges
+ * has a label word that A derives (the section's theorem).  Lengths follow
+ * the section's construction on Algorithm 1's simultaneous step: 1 for the
+ * cells set by the edges; when a step first adds A to (i, j) through a rule
+ * A -> B C and a node k with both operand cells present after the previous
+ * step, L_A(i, j) = L_B(i, k) + L_C(k, j), and a cell keeps its length
+ * afterwards.  Where one step offers several (rule, k) sums the smallest is
+ * kept (the section leaves the choice open; the smallest makes it unique).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the lengths buffer: n_nonterminals * npad * npad uint32, cell
+ * (A, i, j) at index (A * npad + i) * npad + j, 0 = not in R_A. */
+CFPQ_API size_t cfpq_lengths_bytes(int32_t n_nodes, int32_t n_nonterminals);
+
+/* Workspace for cfpq_single_path: two more bit matrices per nonterminal
+ * (the next step and the step's new cells) plus small tables. */
+CFPQ_API cfpq_status cfpq_single_path_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* grammar,
+                                                      size_t* bytes);
+
+/*
+ * Relational closure with single-path lengths.  d_result as for cfpq_closure
+ * (R in the bit layout); d_lengths: device buffer of cfpq_lengths_bytes,
+ * overwritten.  max_iters: loop cap, 0 = Theorem 3's bound.  Synchronises
+ * `stream`.  Returns CFPQ_OK, CFPQ_ENOTCONV (cap reached: every stored length
+ * is still a valid path length), CFPQ_ERANGE, CFPQ_EINVAL, CFPQ_ENOMEM or
+ * CFPQ_EDEVICE.  stats: iterations, Boolean products, device time.
+ */
+CFPQ_API cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* grammar, int64_t max_iters,
+                                      void* stream, void* d_workspace, size_t workspace_bytes, uint64_t* d_result,
+                                      uint32_t* d_lengths, cfpq_stats* stats);
+
+/*
+ * A witness path for (a, i, j) from lengths computed by cfpq_single_path and
+ * copied to the host: it splits each cell into two present cells whose
+ * lengths add up to its own (the split that set it always qualifies) down to
+ * single edges.  graph: host edges.  path: host buffer of max_edges records,
+ * filled with the path's edges in order.  Returns the number of edges
+ * (= L_a(i, j)) or a negative cfpq_status: CFPQ_EINVAL if the cell is not in
+ * R_a or the lengths are inconsistent, CFPQ_ENOMEM if max_edges is shorter
+ * than the length.
+ */
+CFPQ_API int64_t cfpq_witness(const cfpq_graph* graph, const cfpq_grammar* grammar, const uint32_t* lengths,
+                              int32_t a, int32_t i, int32_t j, cfpq_edge* path, int64_t max_edges);
+
+/* ------------------------------------------------------------------------
  * Autotuner: the fastest product kernel per size bucket.
  *
  * cfpq_autotune times every product variant (int8 MFMA; VALU with 8, 16 and
@@ -302,6 +351,11 @@ CFPQ_API cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance
  * runs every admitted query's loops together with the others in flight
  * (the batched engine of cfpq_batch_closure).  On completion the query's
  * matrices are copied to its d_result and its latency is recorded.
+ * Queries with a padded side of at least 4096 go instead, in arrival order,
+ * to `hybrid_lanes` lane threads, each running one query at a time with the
+ * hybrid closure of cfpq_closure on its own stream (workspace from the same
+ * arena, admitted when it fits, result written straight to d_result), so
+ * their work overlaps the engine's on the device.
  * ------------------------------------------------------------------------ */
 
 typedef struct cfpq_server cfpq_server;
@@ -311,7 +365,8 @@ typedef struct {
     int32_t max_slots;     /* queries resident at once, 1..4096; default 256 */
     int32_t capture;       /* loops per replay of the captured engine loop, 1..256; default 4 */
     int32_t max_pending;   /* queued (not yet admitted) queries; submit returns CFPQ_EBUSY beyond */
-    int32_t reserved;      /* must be 0 */
+    int32_t hybrid_lanes;  /* lane threads for queries of padded side >= 4096, 0..16; default 2;
+                              0 = every query runs in the batched engine */
 } cfpq_server_config;
 
 typedef struct {

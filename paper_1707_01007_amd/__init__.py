@@ -154,6 +154,65 @@ def closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=Tr
     return Result(int(n), int(grammar.n_nonterminals), bits, st.as_dict(), status)
 
 
+def _graph_struct(n, edges):
+    torch = _torch()
+    if isinstance(edges, torch.Tensor) and edges.is_cuda:
+        e = edges.to(torch.int32).contiguous().view(-1, 3)
+        return _abi.Graph(int(n), 1, int(e.shape[0]), ctypes.c_void_p(e.data_ptr())), e
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
+    return _abi.Graph(int(n), 0, int(e.shape[0]), ctypes.c_void_p(e.ctypes.data)), e
+
+
+def single_path(n: int, edges, grammar, *, max_iters=0, device=None, stream=None, allow_partial=False):
+    """Closure with single-path lengths (section 5) through ``cfpq_single_path``.
+    Returns (Result, lengths): ``lengths`` is an int32 device tensor
+    [|N|, npad, npad] holding L_A(i, j) (0 where (i, j) is not in R_A)."""
+    torch = _torch()
+    L = lib()
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    g, keep = _grammar_struct(grammar)
+    graph, e = _graph_struct(n, edges)
+    need = ctypes.c_size_t(0)
+    _abi.check(L.cfpq_single_path_workspace_bytes(ctypes.byref(graph), ctypes.byref(g), ctypes.byref(need)))
+    nnt = int(grammar.n_nonterminals)
+    npad, W = padded_rows(n), row_words(n)
+    out = torch.empty(int(L.cfpq_result_bytes(int(n), nnt)) // 8, dtype=torch.int64, device=device)
+    lengths = torch.empty(int(L.cfpq_lengths_bytes(int(n), nnt)) // 4, dtype=torch.int32, device=device)
+    ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=device)
+    st = _abi.Stats()
+    status = L.cfpq_single_path(ctypes.byref(graph), ctypes.byref(g), int(max_iters), _stream_ptr(stream),
+                                ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(lengths.data_ptr()), ctypes.byref(st))
+    del keep, e
+    if status != _abi.CFPQ_OK and not (allow_partial and status == _abi.CFPQ_ENOTCONV):
+        _abi.check(status)
+    return (Result(int(n), nnt, out.view(nnt, npad, W), st.as_dict(), status), lengths.view(nnt, npad, npad))
+
+
+def witness(n: int, edges, grammar, lengths, a: int, i: int, j: int):
+    """A path i -> j of exactly L_a(i, j) edges whose label word ``a`` derives
+    (``cfpq_witness``, host side).  ``lengths``: the tensor from
+    ``single_path`` (copied to the host here) or a host uint32/int32 array of
+    the same shape.  Returns a list of (src, label, dst)."""
+    L = lib()
+    torch = _torch()
+    if isinstance(lengths, torch.Tensor):
+        lengths = lengths.cpu().numpy()
+    host = np.ascontiguousarray(np.asarray(lengths).view(np.uint32))
+    e = np.ascontiguousarray(np.asarray(edges if not isinstance(edges, torch.Tensor) else edges.cpu().numpy(),
+                                        dtype=np.int32).reshape(-1, 3))
+    graph = _abi.Graph(int(n), 0, int(e.shape[0]), ctypes.c_void_p(e.ctypes.data))
+    g, keep = _grammar_struct(grammar)
+    npad = padded_rows(n)
+    cap = int(host.reshape(-1, npad, npad)[a, i, j])
+    buf = (_abi.Edge * max(cap, 1))()
+    got = L.cfpq_witness(ctypes.byref(graph), ctypes.byref(g), ctypes.c_void_p(host.ctypes.data), int(a), int(i),
+                         int(j), buf, cap)
+    if got < 0:
+        _abi.check(int(got))
+    return [(buf[k].src, buf[k].label, buf[k].dst) for k in range(got)]
+
+
 def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=None, stream=None,
                   outs=None, workspace=None, allow_partial=False):
     """Closure of many independent instances in one call (``cfpq_batch_closure``).
@@ -208,12 +267,15 @@ class Server:
     bits were written by the server into a buffer this object allocated (or the
     ``out`` given to ``submit``)."""
 
-    def __init__(self, hbm_budget=8 << 30, max_slots=256, capture=4, max_pending=1 << 16, stream=None):
+    def __init__(self, hbm_budget=8 << 30, max_slots=256, capture=4, max_pending=1 << 16, stream=None,
+                 hybrid_lanes=None):
         torch = _torch()
         L = lib()
         cfg = _abi.ServerConfig()
         L.cfpq_server_default_config(ctypes.byref(cfg))
         cfg.hbm_budget, cfg.max_slots, cfg.capture, cfg.max_pending = int(hbm_budget), int(max_slots), int(capture), int(max_pending)
+        if hybrid_lanes is not None:
+            cfg.hybrid_lanes = int(hybrid_lanes)
         self._handle = ctypes.c_void_p()
         s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
         _abi.check(L.cfpq_server_create(ctypes.byref(cfg), s, ctypes.byref(self._handle)))

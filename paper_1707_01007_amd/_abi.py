@@ -9,12 +9,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcfpq.so")
 
 CFPQ_OK, CFPQ_EINVAL, CFPQ_ENOMEM, CFPQ_EDEVICE, CFPQ_ENOTCONV, CFPQ_EBUSY, CFPQ_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
+CFPQ_ERANGE = -7
 PATH_AUTO, PATH_BITS, PATH_MFMA, PATH_ROWS, PATH_COLS = 0, 1, 2, 3, 4
 HYBRID_OFF, HYBRID_AUTO = 0, 1
 ABI_VERSION = 2
 SCHEDULE_INPLACE, SCHEDULE_JACOBI = 0, 1
 STATUS_NAMES = {0: "CFPQ_OK", -1: "CFPQ_EINVAL", -2: "CFPQ_ENOMEM", -3: "CFPQ_EDEVICE",
-                -4: "CFPQ_ENOTCONV", -5: "CFPQ_EBUSY", -6: "CFPQ_ENOTREADY"}
+                -4: "CFPQ_ENOTCONV", -5: "CFPQ_EBUSY", -6: "CFPQ_ENOTREADY", -7: "CFPQ_ERANGE"}
 
 EXPORTED = (
     "cfpq_abi_version", "cfpq_last_error", "cfpq_default_options", "cfpq_row_words",
@@ -25,6 +26,7 @@ EXPORTED = (
     "cfpq_server_wait", "cfpq_server_destroy",
     "cfpq_autotune_workspace_bytes", "cfpq_autotune", "cfpq_tune_get", "cfpq_tune_save", "cfpq_tune_load",
     "cfpq_tune_clear",
+    "cfpq_lengths_bytes", "cfpq_single_path_workspace_bytes", "cfpq_single_path", "cfpq_witness",
 )
 
 
@@ -85,7 +87,7 @@ class TuneEntry(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("capture", ctypes.c_int32),
-                ("max_pending", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_pending", ctypes.c_int32), ("hybrid_lanes", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -168,6 +170,17 @@ def load(path: str = LIB_PATH):
     lib.cfpq_tune_load.restype = ctypes.c_int
     lib.cfpq_tune_clear.argtypes = []
     lib.cfpq_tune_clear.restype = None
+    lib.cfpq_lengths_bytes.argtypes = [i32, i32]
+    lib.cfpq_lengths_bytes.restype = sz
+    lib.cfpq_single_path_workspace_bytes.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar),
+                                                     ctypes.POINTER(sz)]
+    lib.cfpq_single_path_workspace_bytes.restype = ctypes.c_int
+    lib.cfpq_single_path.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar), i64, p, p, sz, p, p,
+                                     ctypes.POINTER(Stats)]
+    lib.cfpq_single_path.restype = ctypes.c_int
+    lib.cfpq_witness.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar), p, i32, i32, i32,
+                                 ctypes.POINTER(Edge), i64]
+    lib.cfpq_witness.restype = i64
     if lib.cfpq_abi_version() != ABI_VERSION:
         raise ImportError("libcfpq ABI version mismatch")
     _lib = lib

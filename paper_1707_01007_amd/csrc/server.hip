@@ -10,6 +10,12 @@
 //     the caller's buffer, frees its slot and arena block, stamps its latency.
 // Requests that arrive while others are on the GPU therefore join at the next
 // turn, and their work overlaps on the device with everything in flight.
+//
+// Requests with a padded side of at least 4096 (where the hybrid choice of
+// sparse and dense products pays) go to lane threads instead: each lane takes
+// the oldest such request whose closure workspace fits the arena and runs the
+// hybrid closure of cfpq_closure on its own stream, writing the result straight
+// to the caller's buffer.  Lanes and the engine share the arena and the GPU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,6 +58,7 @@ struct Request {
     uint64_t* d_result = nullptr;
     Layout L;
     bool small = false;
+    bool lane = false;  // runs on a lane thread (hybrid closure)
     int32_t n_right = 0;
     size_t footprint = 0;
     // life cycle
@@ -144,12 +151,46 @@ struct cfpq_server {
     std::thread worker;
     std::atomic<int64_t> completed{0};
     int cus = 256;
+    // lanes for large requests
+    std::deque<cfpq::Request*> lane_pending;
+    std::condition_variable lane_cv;  // a lane request queued, arena space released, or stop
+    std::vector<std::thread> lanes;
+    std::vector<hipStream_t> lane_streams;
 };
 
 namespace cfpq {
 namespace {
 
+// Closure options of a lane request: the library defaults (hybrid choice on).
+cfpq_options lane_options() {
+    cfpq_options o;
+    cfpq_default_options(&o);
+    return o;
+}
+
+void fill_lane_inputs(const Request& r, cfpq_graph* g, cfpq_grammar* gr) {
+    g->n_nodes = r.n;
+    g->edges_on_device = r.dev_edges ? 1 : 0;
+    g->n_edges = r.n_edges;
+    g->edges = r.dev_edges ? r.dev_edges : r.host_edges.data();
+    gr->n_nonterminals = r.n_nt;
+    gr->n_terminals = r.n_terminals;
+    gr->n_term_rules = static_cast<int32_t>(r.term.size());
+    gr->n_bin_rules = static_cast<int32_t>(r.bin.size());
+    gr->term_rules = r.term.data();
+    gr->bin_rules = r.bin.data();
+}
+
 size_t footprint_of(const Request& r) {
+    if (r.lane) {
+        cfpq_graph g;
+        cfpq_grammar gr;
+        fill_lane_inputs(r, &g, &gr);
+        const cfpq_options o = lane_options();
+        size_t bytes = 0;
+        if (cfpq_workspace_bytes(&g, &gr, &o, &bytes) != CFPQ_OK) return SIZE_MAX;
+        return bytes;
+    }
     const size_t mat = static_cast<size_t>(r.L.mat_words) * 8;
     size_t f = align_up(mat * r.n_nt, 256);
     if (!r.small) f += align_up(mat * r.n_right, 256);
@@ -367,6 +408,7 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
             srv->completed.fetch_add(1);
         }
         srv->done_cv.notify_all();
+        srv->lane_cv.notify_all();
     }
     // drop small batches whose requests are all retired
     for (auto it = srv->small_batches.begin(); it != srv->small_batches.end();) {
@@ -378,6 +420,56 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
         }
     }
     return true;
+}
+
+// One lane: oldest lane request first, admitted when its workspace fits.
+void lane_main(cfpq_server* srv, int idx) {
+    hipSetDevice(srv->device);
+    hipStream_t ls = srv->lane_streams[idx];
+    while (true) {
+        Request* r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            while (true) {
+                if (srv->stop) {
+                    srv->lane_pending.clear();  // shutting down: queued queries are dropped
+                    return;
+                }
+                if (srv->worker_error != CFPQ_OK) return;
+                if (!srv->lane_pending.empty()) {
+                    Request* head = srv->lane_pending.front();
+                    size_t off = 0;
+                    if (srv->arena.alloc(head->footprint, &off)) {
+                        srv->lane_pending.pop_front();
+                        head->arena_off = off;
+                        head->state = 1;
+                        head->t_admit = now_s();
+                        r = head;
+                        break;
+                    }
+                }
+                srv->lane_cv.wait(lk);
+            }
+        }
+        cfpq_graph g;
+        cfpq_grammar gr;
+        fill_lane_inputs(*r, &g, &gr);
+        const cfpq_options o = lane_options();
+        cfpq_stats st{};
+        const cfpq_status rc = cfpq_closure(&g, &gr, &o, ls, srv->arena_base + r->arena_off, r->footprint,
+                                            r->d_result, &st);
+        const double t = now_s();
+        std::lock_guard<std::mutex> lk(srv->mu);
+        r->status = rc;
+        r->stats = st;
+        r->t_done = t;
+        r->state = 2;
+        srv->arena.release(r->arena_off, r->footprint);
+        srv->completed.fetch_add(1);
+        srv->done_cv.notify_all();
+        srv->lane_cv.notify_all();
+        srv->cv.notify_all();
+    }
 }
 
 void worker_main(cfpq_server* srv) {
@@ -409,6 +501,12 @@ void worker_main(cfpq_server* srv) {
                 r->state = 1;
                 r->t_admit = now_s();
                 admitted.push_back(r);
+            }
+            if (admitted.empty() && !busy && !srv->stop) {
+                // queued work that does not fit yet (lanes hold the arena): wait
+                // for a release instead of spinning
+                srv->cv.wait_for(lk, std::chrono::milliseconds(1));
+                continue;
             }
         }
         if (!turn(srv, admitted)) {
@@ -447,6 +545,7 @@ void cfpq_server_default_config(cfpq_server_config* cfg) {
     cfg->max_slots = 256;
     cfg->capture = 4;
     cfg->max_pending = 1 << 16;
+    cfg->hybrid_lanes = 2;
 }
 
 cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, cfpq_server** out) {
@@ -459,7 +558,7 @@ cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, c
     if (cfg.max_slots < 1 || cfg.max_slots > 4096) return fail(CFPQ_EINVAL, "max_slots must be in 1..4096");
     if (cfg.capture < 1 || cfg.capture > 256) return fail(CFPQ_EINVAL, "capture must be in 1..256");
     if (cfg.max_pending < 1) return fail(CFPQ_EINVAL, "max_pending must be positive");
-    if (cfg.reserved != 0) return fail(CFPQ_EINVAL, "reserved must be 0");
+    if (cfg.hybrid_lanes < 0 || cfg.hybrid_lanes > 16) return fail(CFPQ_EINVAL, "hybrid_lanes must be in 0..16");
     auto srv = std::make_unique<cfpq_server>();
     srv->cfg = cfg;
     CFPQ_HIP(hipGetDevice(&srv->device));
@@ -537,8 +636,14 @@ cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, c
     srv->hstates.assign(S, SlotState{});
     srv->slot_req.assign(S, nullptr);
     for (int32_t q = S - 1; q >= 0; --q) srv->free_slots.push_back(q);
+    for (int32_t q = 0; q < cfg.hybrid_lanes; ++q) {
+        hipStream_t ls = nullptr;
+        CFPQ_HIP(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
+        srv->lane_streams.push_back(ls);
+    }
     cfpq_server* raw = srv.release();
     raw->worker = std::thread(worker_main, raw);
+    for (int32_t q = 0; q < cfg.hybrid_lanes; ++q) raw->lanes.emplace_back(lane_main, raw, q);
     *out = raw;
     return CFPQ_OK;
 }
@@ -569,6 +674,7 @@ cfpq_status cfpq_server_submit(cfpq_server* srv, const cfpq_graph* graph, const 
     r->d_result = d_result;
     r->L = layout_for(graph->n_nodes);
     r->small = r->L.npad <= kSmallMaxPad;
+    r->lane = srv->cfg.hybrid_lanes > 0 && r->L.npad >= kHybridMinRows;
     std::vector<int32_t> seen(r->n_nt, 0);
     for (const auto& b : r->bin)
         if (!seen[b.right]) {
@@ -582,11 +688,17 @@ cfpq_status cfpq_server_submit(cfpq_server* srv, const cfpq_graph* graph, const 
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->worker_error != CFPQ_OK) return fail(srv->worker_error, srv->worker_message);
     if (srv->stop) return fail(CFPQ_EINVAL, "server is shutting down");
-    if (static_cast<int32_t>(srv->pending.size()) >= srv->cfg.max_pending)
+    if (static_cast<int64_t>(srv->pending.size() + srv->lane_pending.size()) >= srv->cfg.max_pending)
         return fail(CFPQ_EBUSY, "submit queue is full");
     r->ticket = srv->next_ticket++;
     r->t_submit = now_s();
     *ticket = r->ticket;
+    if (r->lane) {
+        srv->lane_pending.push_back(r.get());
+        srv->tickets[r->ticket] = std::move(r);
+        srv->lane_cv.notify_all();
+        return CFPQ_OK;
+    }
     srv->pending.push_back(r.get());
     srv->tickets[r->ticket] = std::move(r);
     srv->cv.notify_all();
@@ -636,8 +748,15 @@ cfpq_status cfpq_server_destroy(cfpq_server* srv) {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stop = true;
         srv->cv.notify_all();
+        srv->lane_cv.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
+    for (auto& t : srv->lanes)
+        if (t.joinable()) t.join();
+    for (hipStream_t ls : srv->lane_streams) {
+        hipStreamSynchronize(ls);
+        hipStreamDestroy(ls);
+    }
     hipStreamSynchronize(srv->stream);
     hipStreamSynchronize(srv->side);
     for (auto& kv : srv->small_batches)

@@ -1,0 +1,440 @@
+// Single-path semantics (section 5): a path length for every triple of the
+// relational closure.
+//
+// The closure runs Algorithm 1's simultaneous step.  Every cell that is in
+// T_A carries a length L_A(i, j) >= 1: 1 for the edge-derived cells of the
+// initialisation, and l_B(i, k) + l_C(k, j) for a cell that a step first adds
+// through a rule A -> B C and a middle node k, both operand cells being from
+// the previous step.  A cell keeps its length afterwards.  When one step
+// offers several (rule, k) choices the smallest sum is kept (the section does
+// not choose; the smallest makes the result unique).
+//
+// One loop on the device:
+//  1. Boolean step: Y = X | OR_rules X_B x X_C (the VALU product kernel),
+//     flags per nonterminal;
+//  2. the new cells D_A = Y_A & ~X_A;
+//  3. for every rule A -> B C whose A gained cells, minplus_kernel: for each
+//     64 x 64 output tile that holds new cells of A,
+//        L_A(i, j) = min(L_A(i, j), min_k L_B(i, k) + L_C(k, j))
+//     over the k where X_B(i, k) and X_C(k, j) are set (cells of the previous
+//     step only: a new cell of B written by this loop is never read);
+//  4. X = Y.
+// Lengths are uint32 in cells of a |N| x npad x npad array (0 = absent); sums
+// stay below 2^31 - 1 or the call reports CFPQ_ERANGE.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "cfpq_internal.h"
+
+namespace cfpq {
+namespace {
+
+constexpr uint32_t kInf = 0x7FFFFFFFu;  // absent operand; kInf + kInf does not wrap
+
+// L = 1 where the bit matrices are set, 0 elsewhere (all |N| matrices).
+__global__ void lengths_from_bits_kernel(const uint64_t* __restrict__ T, uint32_t* __restrict__ L,
+                                         int64_t total_words) {
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < total_words;
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t bits = T[w];
+        uint4* dst = reinterpret_cast<uint4*>(L + w * 64);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const uint32_t b = static_cast<uint32_t>(bits >> (4 * q));
+            dst[q] = make_uint4(b & 1u, (b >> 1) & 1u, (b >> 2) & 1u, (b >> 3) & 1u);
+        }
+    }
+}
+
+// D = Y & ~X over one matrix.
+__global__ void delta_kernel(const uint64_t* __restrict__ Y, const uint64_t* __restrict__ X,
+                             uint64_t* __restrict__ D, int64_t words) {
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        D[w] = Y[w] & ~X[w];
+}
+
+// One workgroup per 64 x 64 output tile; 16 x 16 threads, 4 x 4 cells each.
+// Operand chunks of 32 k are staged in LDS k-major, already masked to kInf
+// where the previous step's bit is clear; chunks where either operand block
+// is empty are skipped.
+__global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict__ D, const uint64_t* __restrict__ XB,
+                                                      const uint64_t* __restrict__ XC, const uint32_t* LB,
+                                                      const uint32_t* LC, uint32_t* LA, int64_t W, int64_t npad,
+                                                      int32_t kchunks) {
+    const int64_t tiles = W;  // tiles per side (64 cells each)
+    const int64_t ti = blockIdx.x / tiles, tj = blockIdx.x % tiles;
+    const int64_t i0 = ti * 64, jw = tj;  // j0 = 64 * jw
+    const int t = threadIdx.x;
+    __shared__ __align__(16) uint32_t As[32][64 + 4];  // As[kk][i]
+    __shared__ __align__(16) uint32_t Bs[32][64 + 4];  // Bs[kk][j]
+    __shared__ int any_b, any_c;
+    // the tile's new cells
+    const uint64_t dword = t < 64 ? D[(i0 + t) * W + jw] : 0;
+    if (!__syncthreads_or(dword != 0)) return;
+    const int tx = t & 15, ty = t >> 4;
+    uint32_t acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0xFFFFFFFFu;
+    for (int32_t kc = 0; kc < kchunks; ++kc) {
+        const int64_t k0 = static_cast<int64_t>(kc) * 32;
+        // skip a chunk when X_B[i0.., k0..k0+31] or X_C[k0..k0+31, j0..] is empty
+        if (t == 0) {
+            any_b = 0;
+            any_c = 0;
+        }
+        __syncthreads();
+        if (t < 64) {
+            const uint32_t half = static_cast<uint32_t>(XB[(i0 + t) * W + (k0 >> 6)] >> (k0 & 63));
+            if (half) any_b = 1;
+        } else if (t < 96) {
+            if (XC[(k0 + (t - 64)) * W + jw]) any_c = 1;
+        }
+        __syncthreads();
+        const bool skip = !any_b || !any_c;
+        __syncthreads();  // every thread has read the flags before they are reset
+        if (skip) continue;  // uniform
+        // stage: 64 x 32 of L_B (rows i, cols k) and 32 x 64 of L_C (rows k, cols j)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = t + 256 * q;  // 0..2047
+            const int ii = e >> 5, kk = e & 31;
+            const int64_t row = i0 + ii, col = k0 + kk;
+            const bool set = (XB[row * W + (col >> 6)] >> (col & 63)) & 1ull;
+            As[kk][ii] = set ? LB[row * npad + col] : kInf;
+            const int kr = e >> 6, jj = e & 63;
+            const int64_t krow = k0 + kr;
+            const bool cset = (XC[krow * W + jw] >> jj) & 1ull;
+            Bs[kr][jj] = cset ? LC[krow * npad + 64 * jw + jj] : kInf;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) {
+            const uint4 a = *reinterpret_cast<const uint4*>(&As[kk][ty * 4]);
+            const uint4 b = *reinterpret_cast<const uint4*>(&Bs[kk][tx * 4]);
+            const uint32_t av[4] = {a.x, a.y, a.z, a.w};
+            const uint32_t bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = min(acc[r][c], av[r] + bv[c]);
+        }
+        __syncthreads();
+    }
+    // new cells only: min with what an earlier rule of this loop stored
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + ty * 4 + r;
+        const uint64_t drow = D[i * W + jw];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int jj = tx * 4 + c;
+            if (!((drow >> jj) & 1ull)) continue;
+            const uint32_t v = acc[r][c];
+            if (v >= kInf) {
+                // a new cell of A comes from a product term of this rule or of
+                // another; kInf here only means this rule offered no k
+                continue;
+            }
+            uint32_t* dst = LA + i * npad + 64 * jw + jj;
+            const uint32_t cur = *dst;
+            if (cur == 0 || v < cur) *dst = v;
+        }
+    }
+}
+
+// Overflow check: a new cell that no rule gave a finite sum has a length that
+// did not fit (its Boolean product term exists, so some sum was >= 2^31 - 1).
+__global__ void check_new_cells_kernel(const uint64_t* __restrict__ D, const uint32_t* __restrict__ LA,
+                                       int64_t W, int64_t npad, int32_t* overflow) {
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < npad * W;
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        uint64_t d = D[w];
+        if (!d) continue;
+        const int64_t i = w / W, j0 = 64 * (w % W);
+        while (d) {
+            const int b = __ffsll(static_cast<unsigned long long>(d)) - 1;
+            d &= d - 1;
+            if (LA[i * npad + j0 + b] == 0) atomicOr(overflow, 1);
+        }
+    }
+}
+
+unsigned grid_for(int64_t items, int64_t cap = 65536) {
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((items + 255) / 256, cap)));
+}
+
+struct SpPlan {
+    Layout L;
+    int32_t n_nt = 0;
+    size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0, off_second = 0,
+           off_delta = 0, total = 0;
+};
+
+SpPlan sp_plan(const cfpq_graph* g, const cfpq_grammar* gr) {
+    SpPlan p;
+    p.L = layout_for(g->n_nodes);
+    p.n_nt = gr->n_nonterminals;
+    const size_t mat = static_cast<size_t>(p.L.mat_words) * 8;
+    size_t off = 0;
+    p.off_edges = off;
+    if (!g->edges_on_device) off += align_up(static_cast<size_t>(g->n_edges) * sizeof(cfpq_edge), 256);
+    p.off_term_off = off;
+    off += align_up(static_cast<size_t>(gr->n_terminals + 1) * 4, 256);
+    p.off_term_lhs = off;
+    off += align_up(static_cast<size_t>(std::max(gr->n_term_rules, 1)) * 4, 256);
+    p.off_flags = off;
+    off += align_up(static_cast<size_t>(p.n_nt) * 4 + 8, 256);
+    p.off_bad = off;
+    off += 256;
+    p.off_second = off;  // Y
+    off += mat * p.n_nt;
+    p.off_delta = off;  // D, one per nonterminal
+    off += mat * p.n_nt;
+    p.total = off;
+    return p;
+}
+
+}  // namespace
+}  // namespace cfpq
+
+using namespace cfpq;
+
+extern "C" {
+
+size_t cfpq_lengths_bytes(int32_t n_nodes, int32_t n_nonterminals) {
+    if (n_nonterminals < 0) return 0;
+    const Layout L = layout_for(n_nodes < 0 ? 0 : n_nodes);
+    return static_cast<size_t>(L.npad) * static_cast<size_t>(L.npad) * 4 * static_cast<size_t>(n_nonterminals);
+}
+
+cfpq_status cfpq_single_path_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* grammar, size_t* bytes) {
+    clear_last_error();
+    if (!bytes) return fail(CFPQ_EINVAL, "bytes is NULL");
+    cfpq_status st = validate_grammar(grammar);
+    if (st != CFPQ_OK) return st;
+    if (!graph) return fail(CFPQ_EINVAL, "graph is NULL");
+    if (graph->n_nodes < 0 || graph->n_nodes > CFPQ_MAX_NODES || graph->n_edges < 0)
+        return fail(CFPQ_EINVAL, "graph size out of range");
+    *bytes = sp_plan(graph, grammar).total;
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* grammar, int64_t max_iters, void* stream,
+                             void* d_workspace, size_t workspace_bytes, uint64_t* d_result, uint32_t* d_lengths,
+                             cfpq_stats* stats) {
+    clear_last_error();
+    cfpq_status st = validate_grammar(grammar);
+    if (st != CFPQ_OK) return st;
+    st = validate_graph(graph, grammar);
+    if (st != CFPQ_OK) return st;
+    if (!d_result || !d_lengths) return fail(CFPQ_EINVAL, "d_result or d_lengths is NULL");
+    if (max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
+    const SpPlan p = sp_plan(graph, grammar);
+    if (!d_workspace || workspace_bytes < p.total)
+        return fail(CFPQ_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(d_workspace);
+    const Layout& L = p.L;
+    const size_t mw = static_cast<size_t>(L.mat_words);
+    const int32_t n_nt = p.n_nt;
+
+    std::vector<int32_t> term_off(grammar->n_terminals + 1, 0), term_lhs(std::max(grammar->n_term_rules, 1), 0);
+    for (int32_t r = 0; r < grammar->n_term_rules; ++r) term_off[grammar->term_rules[r].terminal + 1]++;
+    for (int32_t x = 0; x < grammar->n_terminals; ++x) term_off[x + 1] += term_off[x];
+    {
+        std::vector<int32_t> fill(term_off.begin(), term_off.end() - 1);
+        for (int32_t r = 0; r < grammar->n_term_rules; ++r)
+            term_lhs[fill[grammar->term_rules[r].terminal]++] = grammar->term_rules[r].lhs;
+    }
+    auto* d_term_off = reinterpret_cast<int32_t*>(ws + p.off_term_off);
+    auto* d_term_lhs = reinterpret_cast<int32_t*>(ws + p.off_term_lhs);
+    auto* d_flags = reinterpret_cast<int32_t*>(ws + p.off_flags);
+    auto* d_overflow = d_flags + n_nt;
+    auto* d_bad = reinterpret_cast<int32_t*>(ws + p.off_bad);
+    uint64_t* X = d_result;
+    uint64_t* Y = reinterpret_cast<uint64_t*>(ws + p.off_second);
+    uint64_t* D = reinterpret_cast<uint64_t*>(ws + p.off_delta);
+    const cfpq_edge* d_edges = graph->edges;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    CFPQ_HIP(hipEventCreate(&ev0));
+    CFPQ_HIP(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); }
+    } guard{ev0, ev1};
+    CFPQ_HIP(hipMemcpyAsync(d_term_off, term_off.data(), term_off.size() * 4, hipMemcpyHostToDevice, s));
+    CFPQ_HIP(hipMemcpyAsync(d_term_lhs, term_lhs.data(), term_lhs.size() * 4, hipMemcpyHostToDevice, s));
+    if (!graph->edges_on_device && graph->n_edges > 0) {
+        auto* dst = reinterpret_cast<cfpq_edge*>(ws + p.off_edges);
+        CFPQ_HIP(hipMemcpyAsync(dst, graph->edges, static_cast<size_t>(graph->n_edges) * sizeof(cfpq_edge),
+                                hipMemcpyHostToDevice, s));
+        d_edges = dst;
+    }
+    CFPQ_HIP(hipMemsetAsync(d_bad, 0, 4, s));
+    CFPQ_HIP(hipMemsetAsync(d_overflow, 0, 4, s));
+    CFPQ_HIP(hipEventRecord(ev0, s));
+    CFPQ_HIP(launch_zero(X, mw * n_nt, s));
+    CFPQ_HIP(launch_init_scatter(d_edges, graph->n_edges, d_term_off, d_term_lhs, grammar->n_terminals,
+                                 graph->n_nodes, X, L, d_bad, s));
+    if (graph->edges_on_device) {
+        int32_t bad = 0;
+        CFPQ_HIP(hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipStreamSynchronize(s));
+        if (bad) return fail(CFPQ_EINVAL, std::to_string(bad) + " device edges have an id out of range");
+    }
+    {
+        const int64_t words = static_cast<int64_t>(mw) * n_nt;
+        lengths_from_bits_kernel<<<dim3(grid_for(words)), dim3(256), 0, s>>>(X, d_lengths, words);
+        CFPQ_HIP(hipGetLastError());
+    }
+    CFPQ_HIP(hipMemcpyAsync(Y, X, mw * 8 * n_nt, hipMemcpyDeviceToDevice, s));
+
+    const int64_t nn = graph->n_nodes;
+    const int64_t cap = max_iters > 0 ? max_iters : nn * nn * n_nt + 1;
+    const size_t lmat = static_cast<size_t>(L.npad) * static_cast<size_t>(L.npad);
+    const int32_t kchunks = static_cast<int32_t>((L.n + 31) / 32);
+    std::vector<int32_t> flags(n_nt + 1, 0);
+    int64_t iters = 0, products = 0;
+    bool converged = grammar->n_bin_rules == 0 || graph->n_nodes == 0;
+    int32_t overflow = 0;
+    while (!converged && iters < cap) {
+        CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
+        for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
+            const auto& br = grammar->bin_rules[r];
+            CFPQ_HIP(launch_bits_product(X + br.left * mw, X + br.right * mw, Y + br.lhs * mw, L, d_flags + br.lhs, s,
+                                         0));
+            ++products;
+        }
+        CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt + 1) * 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipStreamSynchronize(s));
+        ++iters;
+        bool any = false;
+        for (int32_t a = 0; a < n_nt; ++a) any = any || flags[a] != 0;
+        if (!any) {
+            converged = true;
+            break;
+        }
+        for (int32_t a = 0; a < n_nt; ++a) {
+            if (!flags[a]) continue;
+            delta_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 4096)), dim3(256), 0, s>>>(
+                Y + a * mw, X + a * mw, D + a * mw, static_cast<int64_t>(mw));
+            CFPQ_HIP(hipGetLastError());
+        }
+        for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
+            const auto& br = grammar->bin_rules[r];
+            if (!flags[br.lhs]) continue;
+            minplus_kernel<<<dim3(static_cast<unsigned>(L.W * L.W)), dim3(256), 0, s>>>(
+                D + br.lhs * mw, X + br.left * mw, X + br.right * mw, d_lengths + br.left * lmat,
+                d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, kchunks);
+            CFPQ_HIP(hipGetLastError());
+        }
+        for (int32_t a = 0; a < n_nt; ++a) {
+            if (!flags[a]) continue;
+            check_new_cells_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 4096)), dim3(256), 0, s>>>(
+                D + a * mw, d_lengths + a * lmat, L.W, L.npad, d_overflow);
+            CFPQ_HIP(hipGetLastError());
+            CFPQ_HIP(hipMemcpyAsync(X + a * mw, Y + a * mw, mw * 8, hipMemcpyDeviceToDevice, s));
+        }
+        CFPQ_HIP(hipMemcpyAsync(&overflow, d_overflow, 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipStreamSynchronize(s));
+        if (overflow) break;
+    }
+    CFPQ_HIP(hipEventRecord(ev1, s));
+    CFPQ_HIP(hipEventSynchronize(ev1));
+    float ms = 0.f;
+    CFPQ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iterations = iters;
+        stats->products = products;
+        stats->bitops = 2.0 * static_cast<double>(L.npad) * L.npad * L.npad * static_cast<double>(products);
+        stats->device_ms = ms;
+        stats->path_used = CFPQ_PATH_BITS;
+        stats->converged = converged ? 1 : 0;
+    }
+    if (overflow) return fail(CFPQ_ERANGE, "a path length reached 2^31 - 1");
+    if (!converged) return fail(CFPQ_ENOTCONV, "max_iters reached before the fixpoint");
+    return CFPQ_OK;
+}
+
+int64_t cfpq_witness(const cfpq_graph* graph, const cfpq_grammar* grammar, const uint32_t* lengths, int32_t a,
+                     int32_t i, int32_t j, cfpq_edge* path, int64_t max_edges) {
+    clear_last_error();
+    cfpq_status st = validate_grammar(grammar);
+    if (st != CFPQ_OK) return st;
+    st = validate_graph(graph, grammar);
+    if (st != CFPQ_OK) return st;
+    if (graph->edges_on_device) return fail(CFPQ_EINVAL, "cfpq_witness takes host edges");
+    if (!lengths || (!path && max_edges > 0) || max_edges < 0) return fail(CFPQ_EINVAL, "NULL pointer");
+    const int32_t n = graph->n_nodes;
+    if (a < 0 || a >= grammar->n_nonterminals || i < 0 || i >= n || j < 0 || j >= n)
+        return fail(CFPQ_EINVAL, "cell out of range");
+    const int64_t npad = layout_for(n).npad;
+    auto len = [&](int32_t A, int32_t s, int32_t t) -> uint32_t {
+        return lengths[(static_cast<int64_t>(A) * npad + s) * npad + t];
+    };
+    const uint32_t total = len(a, i, j);
+    if (total == 0) return fail(CFPQ_EINVAL, "the cell is not in R_A");
+    if (static_cast<int64_t>(total) > max_edges) return fail(CFPQ_ENOMEM, "path buffer shorter than the length");
+    // edges by (src, dst), and terminal rules by lhs
+    std::unordered_map<int64_t, std::vector<int32_t>> labels;
+    for (int64_t e = 0; e < graph->n_edges; ++e)
+        labels[static_cast<int64_t>(graph->edges[e].src) * n + graph->edges[e].dst].push_back(graph->edges[e].label);
+    std::vector<std::vector<int32_t>> terms_of(grammar->n_nonterminals);
+    for (int32_t r = 0; r < grammar->n_term_rules; ++r)
+        terms_of[grammar->term_rules[r].lhs].push_back(grammar->term_rules[r].terminal);
+    struct Cell {
+        int32_t A, s, t;
+    };
+    std::vector<Cell> stack{{a, i, j}};
+    int64_t out = 0, budget = 2 * static_cast<int64_t>(total);
+    while (!stack.empty()) {
+        if (--budget < 0) return fail(CFPQ_EINVAL, "lengths are inconsistent");
+        const Cell c = stack.back();
+        stack.pop_back();
+        const uint32_t l = len(c.A, c.s, c.t);
+        if (l == 0) return fail(CFPQ_EINVAL, "lengths are inconsistent");
+        if (l == 1) {
+            bool found = false;
+            auto it = labels.find(static_cast<int64_t>(c.s) * n + c.t);
+            if (it != labels.end())
+                for (int32_t x : it->second) {
+                    if (std::find(terms_of[c.A].begin(), terms_of[c.A].end(), x) != terms_of[c.A].end()) {
+                        if (out >= max_edges) return fail(CFPQ_EINVAL, "lengths are inconsistent (path too long)");
+                        path[out++] = cfpq_edge{c.s, x, c.t};
+                        found = true;
+                        break;
+                    }
+                }
+            if (!found) return fail(CFPQ_EINVAL, "lengths are inconsistent (no edge for a length-1 cell)");
+            continue;
+        }
+        bool split = false;
+        for (int32_t r = 0; r < grammar->n_bin_rules && !split; ++r) {
+            const auto& br = grammar->bin_rules[r];
+            if (br.lhs != c.A) continue;
+            for (int32_t k = 0; k < n; ++k) {
+                const uint32_t lb = len(br.left, c.s, k), lc = len(br.right, k, c.t);
+                if (lb && lc && static_cast<uint64_t>(lb) + lc == l) {
+                    stack.push_back({br.right, k, c.t});
+                    stack.push_back({br.left, c.s, k});
+                    split = true;
+                    break;
+                }
+            }
+        }
+        if (!split) return fail(CFPQ_EINVAL, "lengths are inconsistent (no split)");
+    }
+    return out;
+}
+
+}  // extern "C"

@@ -247,9 +247,42 @@ def test_server_config_validation_on_host():
     lib.cfpq_server_default_config(ctypes.byref(cfg))
     assert cfg.max_slots == 256 and cfg.capture == 4 and cfg.hbm_budget == 8 << 30
     out = ctypes.c_void_p()
-    for field, bad in (("max_slots", 0), ("capture", 0), ("max_pending", 0), ("reserved", 1)):
+    for field, bad in (("max_slots", 0), ("capture", 0), ("max_pending", 0), ("hybrid_lanes", -1),
+                       ("hybrid_lanes", 17)):
         c = _abi.ServerConfig()
         lib.cfpq_server_default_config(ctypes.byref(c))
         setattr(c, field, bad)
         assert lib.cfpq_server_create(ctypes.byref(c), None, ctypes.byref(out)) == _abi.CFPQ_EINVAL, field
     assert lib.cfpq_server_create(ctypes.byref(cfg), None, None) == _abi.CFPQ_EINVAL
+
+
+def test_witness_host_function_on_oracle_lengths():
+    """cfpq_witness is host code: fed the oracle's lengths it returns paths of
+    exactly that many edges, present in the graph, whose words the
+    nonterminal derives; bad cells and short buffers are errors."""
+    from oracle import brute, single_path
+    from workloads import grammars, graphs
+    import paper_1707_01007_amd as cfpq
+    n, e = graphs.erdos_renyi(30, 70, 13, labels=2)
+    g = grammars.dyck()
+    L, _ = single_path.lengths(n, e, g)
+    npad = cfpq.padded_rows(n)
+    full = np.zeros((g.n_nonterminals, npad, npad), dtype=np.uint32)
+    full[:, :n, :n] = L
+    edge_set = {tuple(int(v) for v in x) for x in e}
+    for a, i, j in np.argwhere(L > 0)[:80]:
+        path = cfpq.witness(n, e, g, full, int(a), int(i), int(j))
+        assert len(path) == L[a, i, j] and path[0][0] == i and path[-1][2] == j
+        assert all(tuple(p) in edge_set for p in path)
+        assert all(p[2] == q[0] for p, q in zip(path, path[1:]))
+        word = [p[1] for p in path]
+        if len(word) <= 30:
+            assert int(a) in brute.cyk_table(word, g)[0][len(word)]
+    a, i, j = map(int, np.argwhere(L == 0)[0])
+    with pytest.raises(cfpq.CfpqError):
+        cfpq.witness(n, e, g, full, a, i, j)
+    corrupt = full.copy()
+    corrupt[corrupt > 1] += 1  # no split adds up any more
+    a, i, j = map(int, np.argwhere(L > 1)[0])
+    with pytest.raises(cfpq.CfpqError):
+        cfpq.witness(n, e, g, corrupt, a, i, j)

@@ -142,3 +142,31 @@ def test_server_errors(cfpq):
         ok = srv.wait(srv.submit(n, e, g))
         assert ok["status"] == 0
         assert np.array_equal(cfpq.result_bits(ok["result"]), worklist.closure(n, e, g))
+
+
+def test_server_lanes_equal_engine(cfpq):
+    """Large queries (padded side >= 4096) go to the hybrid lanes; the same
+    mix served with no lanes (everything in the batched engine) gives the same
+    bits, and both equal the plain closure."""
+    qs = []
+    for s, n in enumerate((4096, 5000, 6000)):
+        n_, e = graphs.erdos_renyi(n, 4 * n, 70 + s)
+        qs.append(configs.Instance(n_, e, grammars.dyck(), f"er{n}"))
+    n_, e = graphs.hierarchy(4500, 71, roots=9, reverse=True)
+    qs.append(configs.Instance(n_, e, grammars.same_generation(), "hier4500_rev"))
+    qs += [q for q in _queries() if q.n <= 1000][:6]
+    results = {}
+    for lanes in (0, 2):
+        _say("server lanes", lanes)
+        with cfpq.Server(hbm_budget=8 << 30, max_slots=32, hybrid_lanes=lanes) as srv:
+            infos = [srv.wait(t) for t in [srv.submit(q.n, q.edges, q.grammar) for q in qs]]
+        assert all(i["status"] == 0 for i in infos)
+        results[lanes] = [cfpq.result_bits(i["result"]) for i in infos]
+        if lanes:
+            big = [i for q, i in zip(qs, infos) if q.n >= 4096]
+            assert all(i["stats"]["sparse_products"] > 0 for i in big)
+    for q, a, b in zip(qs, results[0], results[2]):
+        assert np.array_equal(a, b), q.tag
+        assert np.array_equal(a, cfpq.result_bits(cfpq.closure(q.n, q.edges, q.grammar))), q.tag
+    for q, a in zip(qs[:2], results[2][:2]):
+        assert np.array_equal(a, worklist.closure(q.n, q.edges, q.grammar)), q.tag

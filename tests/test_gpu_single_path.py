@@ -1,0 +1,129 @@
+"""GPU parity of the single-path lengths (section 5) against the oracle, the
+two-cycle closed form and breadth-first search, plus witness paths checked
+edge by edge and by CYK."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import brute, single_path as sp
+from tests.test_oracle_single_path import _bfs_lengths, _first_found_graph, two_cycle_lengths
+from workloads import configs, grammars, graphs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfpq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_01007_amd as m
+    m.lib()
+    return m
+
+
+def _say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def _lengths(cfpq, n, e, g, **kw):
+    _say("single_path", n, g.name, kw)
+    res, L = cfpq.single_path(n, e, g, **kw)
+    return res, L[:, :n, :n].cpu().numpy().astype(np.int64)
+
+
+def _check_paths(cfpq, n, e, g, L, count=40, seed=0):
+    edge_set = {tuple(int(v) for v in x) for x in np.asarray(e).reshape(-1, 3)}
+    idx = np.argwhere(L > 0)
+    if len(idx) > count:
+        idx = idx[np.random.default_rng(seed).choice(len(idx), count, replace=False)]
+    full = np.zeros((L.shape[0], cfpq.padded_rows(n), cfpq.padded_rows(n)), dtype=np.uint32)
+    full[:, :n, :n] = L
+    for a, i, j in idx:
+        path = cfpq.witness(n, e, g, full, int(a), int(i), int(j))
+        assert len(path) == L[a, i, j]
+        assert path[0][0] == i and path[-1][2] == j
+        assert all(p[2] == q[0] for p, q in zip(path, path[1:]))
+        assert all(tuple(p) in edge_set for p in path)
+        word = [p[1] for p in path]
+        if len(word) <= 30:
+            assert int(a) in brute.cyk_table(word, g)[0][len(word)]
+
+
+CASES = {
+    "worked_example": lambda: (configs.worked_example().n, configs.worked_example().edges,
+                               configs.worked_example().grammar),
+    "er40_dyck": lambda: (*graphs.erdos_renyi(40, 100, 3, labels=2), grammars.dyck()),
+    "er65_anbn": lambda: (*graphs.erdos_renyi(65, 200, 4, labels=2), grammars.anbn()),
+    "er200_dyck": lambda: (*graphs.erdos_renyi(200, 600, 5, labels=2), grammars.dyck()),
+    "er257_dyck": lambda: (*graphs.erdos_renyi(257, 700, 6, labels=2), grammars.dyck()),
+    "hier300_rev_samegen": lambda: (*graphs.hierarchy(300, 7, roots=2, reverse=True), grammars.same_generation()),
+    "first_found": lambda: _first_found_graph(),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_lengths_match_oracle(cfpq, name):
+    n, e, g = CASES[name]()
+    want, loops = sp.lengths(n, e, g)
+    res, got = _lengths(cfpq, n, e, g)
+    assert res.stats["iterations"] == loops
+    assert np.array_equal(got, want)
+    bits = cfpq.result_bits(res)
+    from oracle import worklist
+    assert np.array_equal(bits, worklist.closure(n, e, g))
+    _check_paths(cfpq, n, e, g, got)
+
+
+def test_two_cycles_closed_form(cfpq):
+    inst = configs.config1()
+    res, got = _lengths(cfpq, inst.n, inst.edges, inst.grammar)
+    assert res.stats["iterations"] == 8065
+    S = inst.grammar.nt("S")
+    want = two_cycle_lengths(64, 63)
+    assert int((got[S] > 0).sum()) == len(want) == 4032
+    for (u, v), l in want.items():
+        assert got[S, u, v] == l, (u, v)
+    _check_paths(cfpq, inst.n, inst.edges, inst.grammar, got, count=10)
+
+
+def test_transitive_closure_is_bfs(cfpq):
+    n, e = graphs.erdos_renyi(600, 1400, 12, labels=2)
+    res, got = _lengths(cfpq, n, e, grammars.transitive_closure())
+    assert np.array_equal(got[0], _bfs_lengths(n, [(int(u), int(v)) for u, x, v in e if x == 0]))
+
+
+def test_chain_lengths(cfpq):
+    rng = np.random.default_rng(9)
+    word = [int(x) for x in rng.integers(0, 2, 300)]
+    n, e = graphs.chain(word)
+    res, got = _lengths(cfpq, n, e, grammars.dyck())
+    a, i, j = np.nonzero(got)
+    assert len(a) > 0 and np.array_equal(got[a, i, j], j - i)
+
+
+def test_partial_result_is_a_prefix(cfpq):
+    n, e, g = CASES["er200_dyck"]()
+    full, _ = sp.lengths(n, e, g)
+    res, got = _lengths(cfpq, n, e, g, max_iters=3, allow_partial=True)
+    assert res.status == -4
+    want, _ = sp.lengths(n, e, g, max_loops=3)
+    assert np.array_equal(got, want)
+    assert np.array_equal(got[got > 0], full[got > 0])
+
+
+def test_device_edges_and_larger_graph(cfpq):
+    """ER 2048 Dyck from device edges: the lengths' support is the relational
+    closure, and sampled witnesses are valid paths."""
+    import torch
+    inst = configs.config3(2048)
+    res, got = _lengths(cfpq, inst.n, torch.from_numpy(inst.edges).cuda(), inst.grammar)
+    rel = cfpq.closure(inst.n, inst.edges, inst.grammar)
+    bits = cfpq.result_bits(rel)
+    from oracle import worklist
+    assert np.array_equal(worklist.unpack(bits, inst.n), got > 0)
+    assert np.array_equal(cfpq.result_bits(res), bits)
+    _check_paths(cfpq, inst.n, inst.edges, inst.grammar, got, count=25)
