@@ -21,7 +21,8 @@
  *  - Memory: pointers named d_* are device memory owned by the caller; every
  *    other pointer is host memory borrowed for the duration of the call.  The
  *    library allocates no device memory inside cfpq_closure: its scratch space
- *    is the caller's workspace.
+ *    is the caller's workspace.  Matrix buffers and workspaces must be 16-byte
+ *    aligned (every hipMalloc'd pointer is); misaligned ones are CFPQ_EINVAL.
  *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Work is
  *    ordered on it.  cfpq_closure returns after the fixpoint is reached (it
  *    reads a change flag back after every loop), so results and stats are

@@ -145,6 +145,8 @@ cfpq_status validate_batch(int32_t n, const cfpq_instance* inst, const cfpq_opti
         st = validate_graph(&inst[i].graph, inst[i].grammar);
         if (st != CFPQ_OK) return fail(st, "instance " + std::to_string(i) + ": " + cfpq_last_error());
         if (!inst[i].d_result) return fail(CFPQ_EINVAL, "instance " + std::to_string(i) + ": d_result is NULL");
+        if (reinterpret_cast<uintptr_t>(inst[i].d_result) % 16)
+            return fail(CFPQ_EINVAL, "instance " + std::to_string(i) + ": d_result must be 16-byte aligned");
         if (inst[i].graph.n_nodes > kMfmaMaxNodes)
             return fail(CFPQ_EINVAL, "instance " + std::to_string(i) + ": the batched engine supports at most 2^19 nodes");
     }

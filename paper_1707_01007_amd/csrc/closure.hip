@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -266,6 +267,8 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     st = validate_graph(graph, grammar);
     if (st != CFPQ_OK) return st;
     if (!d_result) return fail(CFPQ_EINVAL, "d_result is NULL");
+    if (reinterpret_cast<uintptr_t>(d_result) % 16 || reinterpret_cast<uintptr_t>(d_workspace) % 16)
+        return fail(CFPQ_EINVAL, "d_result and d_workspace must be 16-byte aligned");
     const cfpq_options o = resolve(opt);
     if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_COLS) return fail(CFPQ_EINVAL, "unknown path");
     if (o.hybrid != CFPQ_HYBRID_OFF && o.hybrid != CFPQ_HYBRID_AUTO) return fail(CFPQ_EINVAL, "unknown hybrid mode");
@@ -571,6 +574,9 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
     if (n_nodes < 0 || n_nodes > CFPQ_MAX_NODES) return fail(CFPQ_EINVAL, "n_nodes out of range");
     if (!d_b || !d_c || !d_a) return fail(CFPQ_EINVAL, "matrix pointer is NULL");
     if (!d_changed) return fail(CFPQ_EINVAL, "d_changed is required");
+    if ((reinterpret_cast<uintptr_t>(d_b) | reinterpret_cast<uintptr_t>(d_c) | reinterpret_cast<uintptr_t>(d_a) |
+         reinterpret_cast<uintptr_t>(d_workspace)) % 16)
+        return fail(CFPQ_EINVAL, "matrices and workspace must be 16-byte aligned");
     const Layout L = layout_for(n_nodes);
     if (path == CFPQ_PATH_AUTO) path = choose_path(L, path, tile == 0 ? &tile : nullptr);
     if (path < CFPQ_PATH_BITS || path > CFPQ_PATH_COLS) return fail(CFPQ_EINVAL, "unknown path");
@@ -615,6 +621,7 @@ cfpq_status cfpq_popcount(int32_t n_nodes, int32_t count, const uint64_t* d_mats
     g_last_error.clear();
     if (n_nodes < 0 || count < 0) return fail(CFPQ_EINVAL, "negative size");
     if (count > 0 && (!d_mats || !d_counts)) return fail(CFPQ_EINVAL, "NULL pointer");
+    if (reinterpret_cast<uintptr_t>(d_mats) % 16) return fail(CFPQ_EINVAL, "d_mats must be 16-byte aligned");
     const Layout L = layout_for(n_nodes);
     hipStream_t s = static_cast<hipStream_t>(stream);
     CFPQ_HIP(hipMemsetAsync(d_counts, 0, static_cast<size_t>(count) * 8, s));

@@ -60,14 +60,25 @@ __global__ __launch_bounds__(256) void transpose_kernel(const uint64_t* __restri
     dst[(bc * 64 + lane) * W + br] = mine;
 }
 
+// counts[y] += set bits of matrix y; `pairs` 16-byte loads per matrix (the
+// matrices are 16-byte aligned: whole matrices are an even number of words).
 __global__ __launch_bounds__(256) void popcount_kernel(const uint64_t* __restrict__ mats,
                                                        int64_t mat_words,
                                                        unsigned long long* __restrict__ counts) {
-    const uint64_t* m = mats + static_cast<int64_t>(blockIdx.y) * mat_words;
+    const ulonglong2* m = reinterpret_cast<const ulonglong2*>(mats + static_cast<int64_t>(blockIdx.y) * mat_words);
+    const int64_t pairs = mat_words / 2;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     unsigned long long c = 0;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < mat_words;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        c += __popcll(m[i]);
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < pairs; i += 4 * stride) {
+        const ulonglong2 a = m[i], b = m[i + stride], d = m[i + 2 * stride], e = m[i + 3 * stride];
+        c += __popcll(a.x) + __popcll(a.y) + __popcll(b.x) + __popcll(b.y) + __popcll(d.x) + __popcll(d.y) +
+             __popcll(e.x) + __popcll(e.y);
+    }
+    for (; i < pairs; i += stride) {
+        const ulonglong2 a = m[i];
+        c += __popcll(a.x) + __popcll(a.y);
+    }
     // wavefront reduction, then one atomic per workgroup
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
     __shared__ unsigned long long part[4];
@@ -110,8 +121,8 @@ hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L,
 hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,
                            unsigned long long* counts, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    int64_t blocks = (L.mat_words + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    int64_t blocks = (L.mat_words / 2 + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
     popcount_kernel<<<dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(count)), dim3(256), 0,
                       s>>>(mats, L.mat_words, counts);
     return hipGetLastError();

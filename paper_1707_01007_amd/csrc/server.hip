@@ -657,6 +657,7 @@ cfpq_status cfpq_server_submit(cfpq_server* srv, const cfpq_graph* graph, const 
     st = validate_graph(graph, grammar);
     if (st != CFPQ_OK) return st;
     if (!d_result) return fail(CFPQ_EINVAL, "d_result is NULL");
+    if (reinterpret_cast<uintptr_t>(d_result) % 16) return fail(CFPQ_EINVAL, "d_result must be 16-byte aligned");
     if (graph->n_nodes > kMfmaMaxNodes) return fail(CFPQ_EINVAL, "the server supports at most 2^19 nodes");
     if (grammar->n_bin_rules > kSrvMaxRules || grammar->n_terminals > kSrvMaxTerminals ||
         grammar->n_term_rules > kSrvMaxTermRules)

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -236,6 +237,9 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
     st = validate_graph(graph, grammar);
     if (st != CFPQ_OK) return st;
     if (!d_result || !d_lengths) return fail(CFPQ_EINVAL, "d_result or d_lengths is NULL");
+    if ((reinterpret_cast<uintptr_t>(d_result) | reinterpret_cast<uintptr_t>(d_lengths) |
+         reinterpret_cast<uintptr_t>(d_workspace)) % 16)
+        return fail(CFPQ_EINVAL, "d_result, d_lengths and d_workspace must be 16-byte aligned");
     if (max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
     const SpPlan p = sp_plan(graph, grammar);
     if (!d_workspace || workspace_bytes < p.total)

@@ -286,3 +286,15 @@ def test_witness_host_function_on_oracle_lengths():
     a, i, j = map(int, np.argwhere(L > 1)[0])
     with pytest.raises(cfpq.CfpqError):
         cfpq.witness(n, e, g, corrupt, a, i, j)
+
+
+def test_misaligned_buffers_are_rejected_before_device_work():
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+    rc = lib.cfpq_closure(ctypes.byref(gr), ctypes.byref(g), None, None, ctypes.c_void_p(1 << 20),
+                          ctypes.c_size_t(1 << 30), ctypes.c_void_p((1 << 21) + 8), None)
+    assert rc == _abi.CFPQ_EINVAL and b"aligned" in lib.cfpq_last_error()
+    p, q = ctypes.c_void_p(1 << 20), ctypes.c_void_p((1 << 20) + 8)
+    assert lib.cfpq_product(64, 1, 0, p, q, p, p, None, 0, None) == _abi.CFPQ_EINVAL
+    assert lib.cfpq_popcount(64, 1, q, p, None) == _abi.CFPQ_EINVAL
