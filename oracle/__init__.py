@@ -17,6 +17,9 @@ Contents and what each follows:
   truncated at a path length.
 * ``brute``: CYK over a CNF grammar and enumeration of every path up to a
   length bound, straight from the definition of R_A (section 2).
+* ``conjunctive``: Algorithm 1 generalised to conjunctive grammars (the
+  conclusion's remark): T_A gains the AND over a rule's conjuncts of their
+  products; ``brute.conj_cyk_table`` is CYK for such grammars.
 * ``single_path``: the path lengths of section 5 (l_A = l_B + l_C when a step
   first adds A to a cell, kept afterwards; the smallest sum when one step
   offers several) and a witness path for any stored length.

@@ -79,3 +79,44 @@ def paths_up_to(n: int, edges, grammar, max_len: int) -> Dict[int, Set[Tuple[int
     for start in range(n):
         walk(start, start, [[]])
     return result
+
+
+def conj_cyk_table(word: List[int], grammar) -> List[List[Set[int]]]:
+    """CYK for a conjunctive grammar in binary normal form: A =>* word[s:e]
+    through A -> B1 C1 & ... & Bk Ck iff every conjunct m has its own split
+    point p with Bm =>* word[s:p] and Cm =>* word[p:e]."""
+    by_term = _by_term(grammar)
+    L = len(word)
+    tab = [[set() for _ in range(L + 1)] for _ in range(L + 1)]
+    for s in range(L):
+        tab[s][s + 1] = set(by_term.get(word[s], ()))
+    for width in range(2, L + 1):
+        for s in range(0, L - width + 1):
+            e = s + width
+            for a, parts in grammar.conj:
+                if all(any(b in tab[s][p] and c in tab[p][e] for p in range(s + 1, e)) for b, c in parts):
+                    tab[s][e].add(a)
+    return tab
+
+
+def conj_paths_up_to(n: int, edges, grammar, max_len: int) -> Dict[int, Set[Tuple[int, int]]]:
+    """{A: {(i, j)}} for every path of 1..max_len edges whose label word A
+    derives in the conjunctive grammar (each word checked by conj_cyk_table)."""
+    out_edges: Dict[int, List[Tuple[int, int]]] = {}
+    for u, x, v in (tuple(int(t) for t in e) for e in edges):
+        out_edges.setdefault(u, []).append((x, v))
+    result: Dict[int, Set[Tuple[int, int]]] = {a: set() for a in range(grammar.n_nonterminals)}
+
+    def walk(start: int, node: int, word: List[int]):
+        if len(word) == max_len:
+            return
+        for x, v in out_edges.get(node, ()):
+            word.append(x)
+            for a in conj_cyk_table(word, grammar)[0][len(word)]:
+                result[a].add((start, v))
+            walk(start, v, word)
+            word.pop()
+
+    for start in range(n):
+        walk(start, start, [])
+    return result

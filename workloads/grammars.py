@@ -131,3 +131,64 @@ BY_NAME = {
     "dyck": dyck,
     "transitive_closure": transitive_closure,
 }
+
+
+# ---------------------------------------------------------------- conjunctive grammars
+
+@dataclass(frozen=True)
+class ConjCNF:
+    """Conjunctive grammar in binary normal form (the generalisation named in
+    the paper's conclusion): rules A -> x and A -> B1 C1 & ... & Bk Ck (k >= 1;
+    k = 1 is an ordinary CNF rule).  Data only."""
+    nonterminals: Tuple[str, ...]
+    terminals: Tuple[str, ...]
+    term: Tuple[Tuple[int, int], ...]                              # (A, x)
+    conj: Tuple[Tuple[int, Tuple[Tuple[int, int], ...]], ...]     # (A, ((B1, C1), ..., (Bk, Ck)))
+    name: str = field(default="")
+
+    @property
+    def n_nonterminals(self) -> int:
+        return len(self.nonterminals)
+
+    @property
+    def n_terminals(self) -> int:
+        return len(self.terminals)
+
+    def nt(self, name: str) -> int:
+        return self.nonterminals.index(name)
+
+
+def conjunctive_from_cnf(g: CNF) -> ConjCNF:
+    """The same grammar with every binary rule as a one-conjunct rule."""
+    return ConjCNF(g.nonterminals, g.terminals, g.term, tuple((a, ((b, c),)) for a, b, c in g.bin), g.name)
+
+
+def _mk_conj(name: str, nts: List[str], ts: List[str], term, conj) -> ConjCNF:
+    nt = {s: i for i, s in enumerate(nts)}
+    t = {s: i for i, s in enumerate(ts)}
+    return ConjCNF(tuple(nts), tuple(ts), tuple((nt[a], t[x]) for a, x in term),
+                   tuple((nt[a], tuple((nt[b], nt[c]) for b, c in parts)) for a, parts in conj), name)
+
+
+def anbncn() -> ConjCNF:
+    """{a^n b^n c^n : n >= 1} as the intersection of a^n b^n c^+ and a^+ b^n c^n:
+    S -> P Cp & Ap Q with P => a^n b^n, Cp => c^+, Ap => a^+, Q => b^n c^n."""
+    return _mk_conj("anbncn", ["S", "P", "P1", "Q", "Q1", "Ap", "Cp", "A", "B", "C"], ["a", "b", "c"],
+                    [("A", "a"), ("B", "b"), ("C", "c"), ("Ap", "a"), ("Cp", "c")],
+                    [("S", [("P", "Cp"), ("Ap", "Q")]),
+                     ("P", [("A", "B")]), ("P", [("A", "P1")]), ("P1", [("P", "B")]),
+                     ("Q", [("B", "C")]), ("Q", [("B", "Q1")]), ("Q1", [("Q", "C")]),
+                     ("Ap", [("A", "Ap")]), ("Cp", [("C", "Cp")])])
+
+
+def dyck_and_anbn() -> ConjCNF:
+    """Words in both Dyck(a, b) and a^n b^n (which is all of a^n b^n): the
+    start rules of both grammars, conjoined pairwise; used to check that a
+    conjunction never adds what either conjunct lacks."""
+    return _mk_conj("dyck_and_anbn", ["S", "D", "D1", "E", "E1", "A", "B"], ["a", "b"],
+                    [("A", "a"), ("B", "b")],
+                    [("S", [("D", "D"), ("A", "E1")]), ("S", [("D", "D"), ("A", "B")]),
+                     ("S", [("A", "D1"), ("A", "E1")]), ("S", [("A", "D1"), ("A", "B")]),
+                     ("S", [("A", "B"), ("A", "E1")]), ("S", [("A", "B"), ("A", "B")]),
+                     ("D", [("D", "D")]), ("D", [("A", "D1")]), ("D", [("A", "B")]), ("D1", [("D", "B")]),
+                     ("E", [("A", "E1")]), ("E", [("A", "B")]), ("E1", [("E", "B")])])
