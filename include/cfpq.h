@@ -265,6 +265,43 @@ CFPQ_API int64_t cfpq_witness(const cfpq_graph* graph, const cfpq_grammar* gramm
                               int32_t a, int32_t i, int32_t j, cfpq_edge* path, int64_t max_edges);
 
 /* ------------------------------------------------------------------------
+ * Conjunctive grammars (the generalisation named in the paper's conclusion).
+ *
+ * Rules A -> B1 C1 & ... & Bk Ck (k >= 1) join the grammar's terminal rules
+ * and its binary rules (which are one-conjunct rules).  Algorithm 1's step
+ * becomes T_A |= AND over m of (T_Bm x T_Cm).  The fixpoint contains every
+ * (A, i, j) joined by a path whose word A derives, and possibly more (each
+ * conjunct may use another path between the same nodes); on a graph with one
+ * path between any two nodes it is exact.
+ * ------------------------------------------------------------------------ */
+
+typedef struct { int32_t left, right; } cfpq_conjunct;         /* one conjunct B C */
+typedef struct {
+    int32_t lhs;                      /* A */
+    int32_t n_conjuncts;              /* k >= 1 */
+    const cfpq_conjunct* conjuncts;   /* k entries, host memory */
+} cfpq_conj_rule;
+
+/* Workspace for cfpq_conjunctive_closure (as cfpq_workspace_bytes, plus two
+ * scratch matrices when some rule has k >= 2). */
+CFPQ_API cfpq_status cfpq_conjunctive_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* grammar,
+                                                      int32_t n_conj_rules, const cfpq_conj_rule* conj_rules,
+                                                      const cfpq_options* opt, size_t* bytes);
+
+/*
+ * Closure for a conjunctive grammar: grammar (terminal rules, one-conjunct
+ * binary rules) plus n_conj_rules rules with any number of conjuncts.
+ * opt: path AUTO, BITS or MFMA (dense products), schedule, dirty_worklist,
+ * tile and max_iters as for cfpq_closure; warm_start must be 0; hybrid,
+ * capture and profile are ignored (host-driven loop).  d_result, stream,
+ * workspace, stats and the return codes as for cfpq_closure.
+ */
+CFPQ_API cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar* grammar,
+                                              int32_t n_conj_rules, const cfpq_conj_rule* conj_rules,
+                                              const cfpq_options* opt, void* stream, void* d_workspace,
+                                              size_t workspace_bytes, uint64_t* d_result, cfpq_stats* stats);
+
+/* ------------------------------------------------------------------------
  * Autotuner: the fastest product kernel per size bucket.
  *
  * cfpq_autotune times every product variant (int8 MFMA; VALU with 8, 16 and

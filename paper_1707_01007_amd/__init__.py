@@ -213,6 +213,45 @@ def witness(n: int, edges, grammar, lengths, a: int, i: int, j: int):
     return [(buf[k].src, buf[k].label, buf[k].dst) for k in range(got)]
 
 
+def conjunctive_closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=True, max_iters=0,
+                        tile=0, device=None, stream=None, allow_partial=False) -> Result:
+    """Closure for a conjunctive grammar (``cfpq_conjunctive_closure``).
+    ``grammar`` has ``nonterminals``, ``terminals``, ``term`` = [(A, x)] and
+    ``conj`` = [(A, ((B1, C1), ..., (Bk, Ck)))]; one-conjunct rules are passed
+    as ordinary binary rules."""
+    torch = _torch()
+    L = lib()
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    nnt = len(grammar.nonterminals)
+    term = list(grammar.term)
+    binr = [(a, parts[0][0], parts[0][1]) for a, parts in grammar.conj if len(parts) == 1]
+    multi = [(a, parts) for a, parts in grammar.conj if len(parts) > 1]
+    t_arr = (_abi.TermRule * max(1, len(term)))(*[_abi.TermRule(a, x) for a, x in term])
+    b_arr = (_abi.BinRule * max(1, len(binr)))(*[_abi.BinRule(*r) for r in binr])
+    g = _abi.Grammar(nnt, len(grammar.terminals), len(term), len(binr),
+                     ctypes.cast(t_arr, ctypes.POINTER(_abi.TermRule)), ctypes.cast(b_arr, ctypes.POINTER(_abi.BinRule)))
+    parts_keep = [(_abi.Conjunct * len(parts))(*[_abi.Conjunct(b, c) for b, c in parts]) for _, parts in multi]
+    c_arr = (_abi.ConjRule * max(1, len(multi)))(
+        *[_abi.ConjRule(a, len(parts), ctypes.cast(pk, ctypes.POINTER(_abi.Conjunct)))
+          for (a, parts), pk in zip(multi, parts_keep)])
+    graph, e = _graph_struct(n, edges)
+    opt = _options(path, schedule, dirty, max_iters, False, tile, None)
+    need = ctypes.c_size_t(0)
+    _abi.check(L.cfpq_conjunctive_workspace_bytes(ctypes.byref(graph), ctypes.byref(g), len(multi), c_arr,
+                                                  ctypes.byref(opt), ctypes.byref(need)))
+    npad, W = padded_rows(n), row_words(n)
+    out = torch.empty(int(L.cfpq_result_bytes(int(n), nnt)) // 8, dtype=torch.int64, device=device)
+    ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=device)
+    st = _abi.Stats()
+    status = L.cfpq_conjunctive_closure(ctypes.byref(graph), ctypes.byref(g), len(multi), c_arr, ctypes.byref(opt),
+                                        _stream_ptr(stream), ctypes.c_void_p(ws.data_ptr()),
+                                        ctypes.c_size_t(ws.numel()), ctypes.c_void_p(out.data_ptr()), ctypes.byref(st))
+    del e, parts_keep, t_arr, b_arr
+    if status != _abi.CFPQ_OK and not (allow_partial and status == _abi.CFPQ_ENOTCONV):
+        _abi.check(status)
+    return Result(int(n), nnt, out.view(nnt, npad, W), st.as_dict(), status)
+
+
 def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=None, stream=None,
                   outs=None, workspace=None, allow_partial=False):
     """Closure of many independent instances in one call (``cfpq_batch_closure``).

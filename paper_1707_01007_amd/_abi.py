@@ -27,6 +27,7 @@ EXPORTED = (
     "cfpq_autotune_workspace_bytes", "cfpq_autotune", "cfpq_tune_get", "cfpq_tune_save", "cfpq_tune_load",
     "cfpq_tune_clear",
     "cfpq_lengths_bytes", "cfpq_single_path_workspace_bytes", "cfpq_single_path", "cfpq_witness",
+    "cfpq_conjunctive_workspace_bytes", "cfpq_conjunctive_closure",
 )
 
 
@@ -40,6 +41,14 @@ class TermRule(ctypes.Structure):
 
 class BinRule(ctypes.Structure):
     _fields_ = [("lhs", ctypes.c_int32), ("left", ctypes.c_int32), ("right", ctypes.c_int32)]
+
+
+class Conjunct(ctypes.Structure):
+    _fields_ = [("left", ctypes.c_int32), ("right", ctypes.c_int32)]
+
+
+class ConjRule(ctypes.Structure):
+    _fields_ = [("lhs", ctypes.c_int32), ("n_conjuncts", ctypes.c_int32), ("conjuncts", ctypes.POINTER(Conjunct))]
 
 
 class Graph(ctypes.Structure):
@@ -181,6 +190,14 @@ def load(path: str = LIB_PATH):
     lib.cfpq_witness.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar), p, i32, i32, i32,
                                  ctypes.POINTER(Edge), i64]
     lib.cfpq_witness.restype = i64
+    lib.cfpq_conjunctive_workspace_bytes.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar), i32,
+                                                     ctypes.POINTER(ConjRule), ctypes.POINTER(Options),
+                                                     ctypes.POINTER(sz)]
+    lib.cfpq_conjunctive_workspace_bytes.restype = ctypes.c_int
+    lib.cfpq_conjunctive_closure.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar), i32,
+                                             ctypes.POINTER(ConjRule), ctypes.POINTER(Options), p, p, sz, p,
+                                             ctypes.POINTER(Stats)]
+    lib.cfpq_conjunctive_closure.restype = ctypes.c_int
     if lib.cfpq_abi_version() != ABI_VERSION:
         raise ImportError("libcfpq ABI version mismatch")
     _lib = lib

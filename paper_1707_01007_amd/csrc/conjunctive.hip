@@ -1,0 +1,337 @@
+// Conjunctive grammars: Algorithm 1 generalised as the paper's conclusion
+// suggests.  A rule A -> B1 C1 & ... & Bk Ck adds to T_A the cells where every
+// conjunct's product is set:
+//     T_A |= AND over m of (T_Bm x T_Cm)
+// The fixpoint over-approximates conjunctive path querying (each conjunct may
+// be witnessed by a different path between the same two nodes) and is exact
+// where paths are unique (a chain: conjunctive CYK).
+//
+// Device work per rule with k >= 2 conjuncts: Q = B1 x C1 into a zeroed
+// scratch matrix (the dense product kernels OR into their output), then for
+// every further conjunct R = Bm x Cm into a second scratch matrix and Q &= R,
+// and finally T_A |= Q with the change flag.  One-conjunct rules are ordinary
+// products straight into T_A.  Schedules, dirty-rule worklist and product
+// kernels are those of cfpq_closure (host-driven loop).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cfpq_internal.h"
+
+namespace cfpq {
+namespace {
+
+__global__ void and_into_kernel(uint64_t* __restrict__ Q, const uint64_t* __restrict__ R, int64_t words) {
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        Q[w] &= R[w];
+}
+
+// A |= Q; *changed |= 1 when a bit was added (one atomic per workgroup).
+__global__ __launch_bounds__(256) void or_into_kernel(uint64_t* A, const uint64_t* __restrict__ Q, int64_t words,
+                                                      int32_t* changed) {
+    bool ch = false;
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t q = Q[w];
+        if (!q) continue;
+        const uint64_t old = A[w];
+        if (q & ~old) {
+            A[w] = old | q;
+            ch = true;
+        }
+    }
+    if (__syncthreads_or(ch) && threadIdx.x == 0) atomicOr(changed, 1);
+}
+
+unsigned grid_for(int64_t words) {
+    return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((words + 255) / 256, 4096)));
+}
+
+struct Rule {
+    int32_t lhs;
+    std::vector<std::pair<int32_t, int32_t>> parts;
+};
+
+struct CjPlan {
+    Layout L;
+    int32_t n_nt = 0, path = CFPQ_PATH_BITS, tile = 0;
+    bool jacobi = false, temps = false;
+    std::vector<int32_t> right_slot;
+    int32_t n_right = 0;
+    size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0, off_second = 0,
+           off_trans = 0, off_q = 0, off_r = 0, total = 0;
+};
+
+cfpq_status collect_rules(const cfpq_grammar* gr, int32_t n_conj, const cfpq_conj_rule* conj,
+                          std::vector<Rule>* out) {
+    if (n_conj < 0) return fail(CFPQ_EINVAL, "n_conj_rules is negative");
+    if (n_conj > 0 && !conj) return fail(CFPQ_EINVAL, "conj_rules is NULL");
+    out->clear();
+    for (int32_t r = 0; r < gr->n_bin_rules; ++r)
+        out->push_back({gr->bin_rules[r].lhs, {{gr->bin_rules[r].left, gr->bin_rules[r].right}}});
+    for (int32_t r = 0; r < n_conj; ++r) {
+        const cfpq_conj_rule& c = conj[r];
+        if (c.lhs < 0 || c.lhs >= gr->n_nonterminals)
+            return fail(CFPQ_EINVAL, "conjunctive rule " + std::to_string(r) + " has its head out of range");
+        if (c.n_conjuncts < 1 || !c.conjuncts)
+            return fail(CFPQ_EINVAL, "conjunctive rule " + std::to_string(r) + " has no conjuncts");
+        Rule rule{c.lhs, {}};
+        for (int32_t m = 0; m < c.n_conjuncts; ++m) {
+            const cfpq_conjunct& p = c.conjuncts[m];
+            if (p.left < 0 || p.left >= gr->n_nonterminals || p.right < 0 || p.right >= gr->n_nonterminals)
+                return fail(CFPQ_EINVAL, "conjunctive rule " + std::to_string(r) + " has an id out of range");
+            rule.parts.emplace_back(p.left, p.right);
+        }
+        out->push_back(std::move(rule));
+    }
+    return CFPQ_OK;
+}
+
+CjPlan cj_plan(const cfpq_graph* g, const cfpq_grammar* gr, const std::vector<Rule>& rules, const cfpq_options& o) {
+    CjPlan p;
+    p.L = layout_for(g->n_nodes);
+    p.n_nt = gr->n_nonterminals;
+    p.tile = o.tile;
+    p.path = o.path;
+    if (p.path == CFPQ_PATH_AUTO) p.path = g->n_nodes <= kMfmaMaxNodes ? CFPQ_PATH_MFMA : CFPQ_PATH_BITS;
+    p.jacobi = o.schedule == CFPQ_SCHEDULE_JACOBI;
+    p.right_slot.assign(p.n_nt, -1);
+    for (const Rule& r : rules) {
+        if (r.parts.size() > 1) p.temps = true;
+        if (p.path == CFPQ_PATH_MFMA)
+            for (const auto& pc : r.parts)
+                if (p.right_slot[pc.second] < 0) p.right_slot[pc.second] = p.n_right++;
+    }
+    const size_t mat = static_cast<size_t>(p.L.mat_words) * 8;
+    size_t off = 0;
+    p.off_edges = off;
+    if (!g->edges_on_device) off += align_up(static_cast<size_t>(g->n_edges) * sizeof(cfpq_edge), 256);
+    p.off_term_off = off;
+    off += align_up(static_cast<size_t>(gr->n_terminals + 1) * 4, 256);
+    p.off_term_lhs = off;
+    off += align_up(static_cast<size_t>(std::max(gr->n_term_rules, 1)) * 4, 256);
+    p.off_flags = off;  // n_nt flags, then one flag nobody reads
+    off += align_up(static_cast<size_t>(p.n_nt + 1) * 4, 256);
+    p.off_bad = off;
+    off += 256;
+    p.off_second = off;
+    if (p.jacobi) off += mat * p.n_nt;
+    p.off_trans = off;
+    off += mat * p.n_right;
+    p.off_q = off;
+    if (p.temps) off += mat;
+    p.off_r = off;
+    if (p.temps) off += mat;
+    p.total = off;
+    return p;
+}
+
+cfpq_status check_options(const cfpq_options& o, int32_t n_nodes) {
+    if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_MFMA)
+        return fail(CFPQ_EINVAL, "conjunctive closures take the AUTO, BITS or MFMA path");
+    if (o.schedule != CFPQ_SCHEDULE_INPLACE && o.schedule != CFPQ_SCHEDULE_JACOBI)
+        return fail(CFPQ_EINVAL, "unknown schedule");
+    if (o.max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
+    if (o.warm_start != 0) return fail(CFPQ_EINVAL, "conjunctive closures have no warm start");
+    if (o.path == CFPQ_PATH_MFMA && n_nodes > kMfmaMaxNodes)
+        return fail(CFPQ_EINVAL, "the MFMA path supports at most 2^19 nodes");
+    if (o.tile != 0 && (o.path != CFPQ_PATH_BITS || !bits_strip_supported(o.tile, layout_for(n_nodes))))
+        return fail(CFPQ_EINVAL, "unsupported tile");
+    return CFPQ_OK;
+}
+
+}  // namespace
+}  // namespace cfpq
+
+using namespace cfpq;
+
+extern "C" {
+
+cfpq_status cfpq_conjunctive_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* grammar,
+                                             int32_t n_conj_rules, const cfpq_conj_rule* conj_rules,
+                                             const cfpq_options* opt, size_t* bytes) {
+    clear_last_error();
+    if (!bytes) return fail(CFPQ_EINVAL, "bytes is NULL");
+    cfpq_status st = validate_grammar(grammar);
+    if (st != CFPQ_OK) return st;
+    if (!graph) return fail(CFPQ_EINVAL, "graph is NULL");
+    if (graph->n_nodes < 0 || graph->n_nodes > CFPQ_MAX_NODES || graph->n_edges < 0)
+        return fail(CFPQ_EINVAL, "graph size out of range");
+    std::vector<Rule> rules;
+    st = collect_rules(grammar, n_conj_rules, conj_rules, &rules);
+    if (st != CFPQ_OK) return st;
+    cfpq_options o;
+    cfpq_default_options(&o);
+    if (opt) o = *opt;
+    st = check_options(o, graph->n_nodes);
+    if (st != CFPQ_OK) return st;
+    *bytes = cj_plan(graph, grammar, rules, o).total;
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, int32_t n_conj_rules,
+                                     const cfpq_conj_rule* conj_rules, const cfpq_options* opt, void* stream,
+                                     void* d_workspace, size_t workspace_bytes, uint64_t* d_result,
+                                     cfpq_stats* stats) {
+    clear_last_error();
+    cfpq_status st = validate_grammar(grammar);
+    if (st != CFPQ_OK) return st;
+    st = validate_graph(graph, grammar);
+    if (st != CFPQ_OK) return st;
+    std::vector<Rule> rules;
+    st = collect_rules(grammar, n_conj_rules, conj_rules, &rules);
+    if (st != CFPQ_OK) return st;
+    if (!d_result) return fail(CFPQ_EINVAL, "d_result is NULL");
+    if ((reinterpret_cast<uintptr_t>(d_result) | reinterpret_cast<uintptr_t>(d_workspace)) % 16)
+        return fail(CFPQ_EINVAL, "d_result and d_workspace must be 16-byte aligned");
+    cfpq_options o;
+    cfpq_default_options(&o);
+    if (opt) o = *opt;
+    st = check_options(o, graph->n_nodes);
+    if (st != CFPQ_OK) return st;
+    const CjPlan p = cj_plan(graph, grammar, rules, o);
+    if (p.total > 0 && !d_workspace) return fail(CFPQ_EINVAL, "d_workspace is NULL");
+    if (workspace_bytes < p.total)
+        return fail(CFPQ_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(d_workspace);
+    const Layout& L = p.L;
+    const size_t mw = static_cast<size_t>(L.mat_words);
+    const int32_t n_nt = p.n_nt;
+    std::vector<int32_t> term_off(grammar->n_terminals + 1, 0), term_lhs(std::max(grammar->n_term_rules, 1), 0);
+    for (int32_t r = 0; r < grammar->n_term_rules; ++r) term_off[grammar->term_rules[r].terminal + 1]++;
+    for (int32_t x = 0; x < grammar->n_terminals; ++x) term_off[x + 1] += term_off[x];
+    {
+        std::vector<int32_t> fill(term_off.begin(), term_off.end() - 1);
+        for (int32_t r = 0; r < grammar->n_term_rules; ++r)
+            term_lhs[fill[grammar->term_rules[r].terminal]++] = grammar->term_rules[r].lhs;
+    }
+    auto* d_term_off = reinterpret_cast<int32_t*>(ws + p.off_term_off);
+    auto* d_term_lhs = reinterpret_cast<int32_t*>(ws + p.off_term_lhs);
+    auto* d_flags = reinterpret_cast<int32_t*>(ws + p.off_flags);
+    int32_t* d_spare = d_flags + n_nt;
+    auto* d_bad = reinterpret_cast<int32_t*>(ws + p.off_bad);
+    uint64_t* X = d_result;
+    uint64_t* Y = p.jacobi ? reinterpret_cast<uint64_t*>(ws + p.off_second) : d_result;
+    uint64_t* TT = reinterpret_cast<uint64_t*>(ws + p.off_trans);
+    uint64_t* Q = reinterpret_cast<uint64_t*>(ws + p.off_q);
+    uint64_t* R = reinterpret_cast<uint64_t*>(ws + p.off_r);
+    const cfpq_edge* d_edges = graph->edges;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    CFPQ_HIP(hipEventCreate(&ev0));
+    CFPQ_HIP(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); }
+    } guard{ev0, ev1};
+    CFPQ_HIP(hipMemcpyAsync(d_term_off, term_off.data(), term_off.size() * 4, hipMemcpyHostToDevice, s));
+    CFPQ_HIP(hipMemcpyAsync(d_term_lhs, term_lhs.data(), term_lhs.size() * 4, hipMemcpyHostToDevice, s));
+    if (!graph->edges_on_device && graph->n_edges > 0) {
+        auto* dst = reinterpret_cast<cfpq_edge*>(ws + p.off_edges);
+        CFPQ_HIP(hipMemcpyAsync(dst, graph->edges, static_cast<size_t>(graph->n_edges) * sizeof(cfpq_edge),
+                                hipMemcpyHostToDevice, s));
+        d_edges = dst;
+    }
+    CFPQ_HIP(hipMemsetAsync(d_bad, 0, 4, s));
+    CFPQ_HIP(hipEventRecord(ev0, s));
+    CFPQ_HIP(launch_zero(X, mw * n_nt, s));
+    CFPQ_HIP(launch_init_scatter(d_edges, graph->n_edges, d_term_off, d_term_lhs, grammar->n_terminals,
+                                 graph->n_nodes, X, L, d_bad, s));
+    if (graph->edges_on_device) {
+        int32_t bad = 0;
+        CFPQ_HIP(hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipStreamSynchronize(s));
+        if (bad) return fail(CFPQ_EINVAL, std::to_string(bad) + " device edges have an id out of range");
+    }
+    if (p.jacobi) CFPQ_HIP(hipMemcpyAsync(Y, X, mw * 8 * n_nt, hipMemcpyDeviceToDevice, s));
+    for (int32_t a = 0; a < n_nt; ++a)
+        if (p.right_slot[a] >= 0) CFPQ_HIP(launch_transpose(X + a * mw, TT + p.right_slot[a] * mw, L, s));
+
+    auto product = [&](int32_t b, int32_t c, uint64_t* out, int32_t* flag) -> cfpq_status {
+        if (p.path == CFPQ_PATH_MFMA)
+            CFPQ_HIP(launch_mfma_product(X + b * mw, TT + p.right_slot[c] * mw, out, L, flag, s));
+        else
+            CFPQ_HIP(launch_bits_product(X + b * mw, X + c * mw, out, L, flag, s, p.tile));
+        return CFPQ_OK;
+    };
+
+    const int64_t nn = graph->n_nodes;
+    const int64_t cap = o.max_iters > 0 ? o.max_iters : nn * nn * n_nt + 1;
+    std::vector<int32_t> prev(n_nt, 1), flags(n_nt, 0);
+    int64_t iters = 0, products = 0;
+    bool converged = rules.empty() || graph->n_nodes == 0;
+    while (!converged && iters < cap) {
+        CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
+        for (const Rule& r : rules) {
+            if (o.dirty_worklist && iters > 0) {
+                bool dirty = false;
+                for (const auto& pc : r.parts) dirty = dirty || prev[pc.first] || prev[pc.second];
+                if (!dirty) continue;
+            }
+            if (r.parts.size() == 1) {
+                st = product(r.parts[0].first, r.parts[0].second, Y + r.lhs * mw, d_flags + r.lhs);
+                if (st != CFPQ_OK) return st;
+                ++products;
+                continue;
+            }
+            CFPQ_HIP(launch_zero(Q, mw, s));
+            st = product(r.parts[0].first, r.parts[0].second, Q, d_spare);
+            if (st != CFPQ_OK) return st;
+            for (size_t m = 1; m < r.parts.size(); ++m) {
+                CFPQ_HIP(launch_zero(R, mw, s));
+                st = product(r.parts[m].first, r.parts[m].second, R, d_spare);
+                if (st != CFPQ_OK) return st;
+                and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
+                    Q, R, static_cast<int64_t>(mw));
+                CFPQ_HIP(hipGetLastError());
+            }
+            or_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
+                Y + r.lhs * mw, Q, static_cast<int64_t>(mw), d_flags + r.lhs);
+            CFPQ_HIP(hipGetLastError());
+            products += static_cast<int64_t>(r.parts.size());
+        }
+        CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipStreamSynchronize(s));
+        ++iters;
+        bool any = false;
+        for (int32_t a = 0; a < n_nt; ++a) any = any || flags[a] != 0;
+        if (!any) {
+            converged = true;
+            break;
+        }
+        for (int32_t a = 0; a < n_nt; ++a) {
+            if (!flags[a]) continue;
+            if (p.jacobi)
+                CFPQ_HIP(hipMemcpyAsync(X + a * mw, Y + a * mw, mw * 8, hipMemcpyDeviceToDevice, s));
+            if (p.right_slot[a] >= 0) CFPQ_HIP(launch_transpose(Y + a * mw, TT + p.right_slot[a] * mw, L, s));
+        }
+        if (p.jacobi) std::swap(X, Y);
+        prev = flags;
+    }
+    if (p.jacobi && X != d_result)
+        CFPQ_HIP(hipMemcpyAsync(d_result, X, mw * 8 * n_nt, hipMemcpyDeviceToDevice, s));
+    CFPQ_HIP(hipEventRecord(ev1, s));
+    CFPQ_HIP(hipEventSynchronize(ev1));
+    float ms = 0.f;
+    CFPQ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iterations = iters;
+        stats->products = products;
+        stats->bitops = 2.0 * static_cast<double>(L.npad) * L.npad * L.npad * static_cast<double>(products);
+        stats->device_ms = ms;
+        stats->path_used = p.path;
+        stats->converged = converged ? 1 : 0;
+    }
+    if (!converged) return fail(CFPQ_ENOTCONV, "max_iters reached before the fixpoint");
+    return CFPQ_OK;
+}
+
+}  // extern "C"

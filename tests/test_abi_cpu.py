@@ -181,7 +181,8 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.skip("no gcc")
     structs = {"cfpq_options": _abi.Options, "cfpq_stats": _abi.Stats, "cfpq_graph": _abi.Graph,
                "cfpq_grammar": _abi.Grammar, "cfpq_instance": _abi.Instance, "cfpq_tune_entry": _abi.TuneEntry,
-               "cfpq_server_config": _abi.ServerConfig, "cfpq_request_info": _abi.RequestInfo}
+               "cfpq_server_config": _abi.ServerConfig, "cfpq_request_info": _abi.RequestInfo,
+               "cfpq_conjunct": _abi.Conjunct, "cfpq_conj_rule": _abi.ConjRule}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cfpq.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -298,3 +299,29 @@ def test_misaligned_buffers_are_rejected_before_device_work():
     p, q = ctypes.c_void_p(1 << 20), ctypes.c_void_p((1 << 20) + 8)
     assert lib.cfpq_product(64, 1, 0, p, q, p, p, None, 0, None) == _abi.CFPQ_EINVAL
     assert lib.cfpq_popcount(64, 1, q, p, None) == _abi.CFPQ_EINVAL
+
+
+@pytest.mark.parametrize("case", ["head", "conjunct_id", "no_conjuncts", "path_rows"])
+def test_conjunctive_rules_validated_before_device_work(case):
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+    parts = (_abi.Conjunct * 2)(_abi.Conjunct(0, 0), _abi.Conjunct(0, 0))
+    rule = _abi.ConjRule(0, 2, ctypes.cast(parts, ctypes.POINTER(_abi.Conjunct)))
+    opt = _abi.Options()
+    lib.cfpq_default_options(ctypes.byref(opt))
+    if case == "head":
+        rule.lhs = 5
+    elif case == "conjunct_id":
+        parts[1].right = 9
+    elif case == "no_conjuncts":
+        rule.n_conjuncts = 0
+    else:
+        opt.path = 3
+    rules = (_abi.ConjRule * 1)(rule)
+    sz = ctypes.c_size_t(0)
+    assert lib.cfpq_conjunctive_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), 1, rules, ctypes.byref(opt),
+                                                ctypes.byref(sz)) == _abi.CFPQ_EINVAL
+    assert lib.cfpq_conjunctive_closure(ctypes.byref(gr), ctypes.byref(g), 1, rules, ctypes.byref(opt), None,
+                                        ctypes.c_void_p(1 << 20), ctypes.c_size_t(1 << 30), ctypes.c_void_p(1 << 21),
+                                        None) == _abi.CFPQ_EINVAL

@@ -1,0 +1,87 @@
+"""GPU parity of the conjunctive-grammar closure against the oracle
+(Algorithm 1 with the AND of conjunct products), bit for bit, for both dense
+product kernels and both schedules."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import conjunctive, worklist
+from workloads import grammars, graphs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfpq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_01007_amd as m
+    m.lib()
+    return m
+
+
+def _run(cfpq, n, e, g, **kw):
+    print("[gpu-case] conjunctive", n, g.name, kw, file=sys.stderr, flush=True)
+    res = cfpq.conjunctive_closure(n, e, g, **kw)
+    return worklist.unpack(cfpq.result_bits(res), n), res
+
+
+def _anbncn_chain(k_list, noise_seed):
+    rng = np.random.default_rng(noise_seed)
+    word = []
+    for k in k_list:
+        word += [0] * k + [1] * k + [2] * k
+        word += [int(x) for x in rng.integers(0, 3, 3)]
+    return graphs.chain(word)
+
+
+CASES = {
+    "chain_anbncn": lambda: (*_anbncn_chain([1, 3, 2, 5], 1), grammars.anbncn()),
+    "er90_anbncn": lambda: (*graphs.erdos_renyi(90, 400, 2, labels=3), grammars.anbncn()),
+    "er300_anbncn": lambda: (*graphs.erdos_renyi(300, 1500, 3, labels=3), grammars.anbncn()),
+    "er257_dyck_and_anbn": lambda: (*graphs.erdos_renyi(257, 800, 4, labels=2), grammars.dyck_and_anbn()),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("path", ["bits", "mfma"])
+@pytest.mark.parametrize("schedule", ["inplace", "jacobi"])
+def test_conjunctive_matches_oracle(cfpq, name, path, schedule):
+    n, e, g = CASES[name]()
+    want, loops = conjunctive.closure(n, e, g)
+    got, res = _run(cfpq, n, e, g, path=path, schedule=schedule, dirty=(schedule == "inplace"))
+    assert np.array_equal(got, want)
+    if schedule == "jacobi":
+        assert res.stats["iterations"] == loops
+
+
+def test_one_conjunct_rules_equal_plain_closure(cfpq):
+    n, e = graphs.erdos_renyi(700, 2800, 5, labels=2)
+    got, _ = _run(cfpq, n, e, grammars.conjunctive_from_cnf(grammars.dyck()))
+    plain = cfpq.closure(n, e, grammars.dyck())
+    assert np.array_equal(got, worklist.unpack(cfpq.result_bits(plain), n))
+
+
+def test_conjoined_start_rules_are_the_intersection(cfpq):
+    """R_S = R_Dyck & R_anbn on a 1500-node graph (oracle: two relational
+    closures of the C worklist)."""
+    n, e = graphs.erdos_renyi(1500, 4500, 6, labels=2)
+    g = grammars.dyck_and_anbn()
+    got, _ = _run(cfpq, n, e, g, path="mfma")
+    d = worklist.unpack(worklist.closure(n, e, grammars.dyck()), n)[0]
+    ab = worklist.unpack(worklist.closure(n, e, grammars.anbn()), n)[0]
+    assert np.array_equal(got[g.nt("S")], d & ab)
+
+
+def test_partial_and_device_edges(cfpq):
+    import torch
+    n, e, g = CASES["er90_anbncn"]()
+    want, _ = conjunctive.closure(n, e, g, max_loops=2)
+    got, res = _run(cfpq, n, torch.from_numpy(e).cuda(), g, schedule="jacobi", dirty=False, max_iters=2,
+                    allow_partial=True)
+    assert res.status in (0, -4)
+    assert np.array_equal(got, want)
