@@ -120,3 +120,29 @@ def conj_paths_up_to(n: int, edges, grammar, max_len: int) -> Dict[int, Set[Tupl
     for start in range(n):
         walk(start, start, [])
     return result
+
+
+def cfg_words(rules, max_len: int) -> Dict[str, Set[Tuple]]:
+    """Every word of length <= max_len that each nonterminal of a general
+    context-free grammar derives (the empty word included when derivable).
+    ``rules``: {A: [alternative, ...]}, an alternative a tuple of symbols,
+    nonterminal iff it is a key.  The least solution of the grammar's
+    language equations, restricted to short words (a derivation of a word of
+    length <= max_len only uses sub-words of length <= max_len)."""
+    words: Dict[str, Set[Tuple]] = {a: set() for a in rules}
+    changed = True
+    while changed:
+        changed = False
+        for a, alts in rules.items():
+            for alt in alts:
+                partial = {()}
+                for x in alt:
+                    opts = words[x] if x in rules else {(x,)}
+                    partial = {p + q for p in partial for q in opts if len(p) + len(q) <= max_len}
+                    if not partial:
+                        break
+                fresh = partial - words[a]
+                if fresh:
+                    words[a] |= fresh
+                    changed = True
+    return words
