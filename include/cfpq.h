@@ -140,6 +140,9 @@ typedef struct {
     int32_t path_used;       /* CFPQ_PATH_BITS or CFPQ_PATH_MFMA (dense kernel), ROWS or COLS */
     int32_t converged;       /* 1 if the fixpoint was reached */
     int64_t sparse_products; /* products of `products` that ran as ROWS or COLS */
+    int64_t delta_products;  /* products of `products` with a delta operand: a rule A -> B C whose
+                                operands gained the bits D_B, D_C since the previous loop started
+                                may add D_B x C and B x D_C instead of B x C (hybrid choice) */
 } cfpq_stats;
 
 /* ABI version of the loaded library (CFPQ_ABI_VERSION). */
@@ -198,8 +201,9 @@ CFPQ_API cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* g
  * value read is a subset of the final one).  path = any CFPQ_PATH_* (AUTO
  * picks the autotuned dense kernel); tile as in cfpq_options (0 = default).
  * *d_changed (device int32, required) is OR-ed with 1 when d_a gained a bit.
- * d_workspace may be NULL for BITS and ROWS; MFMA (one transposed operand)
- * and COLS (two transposed operands and the transposed product) need
+ * d_workspace may be NULL for BITS; MFMA (one transposed operand), ROWS (a
+ * list of rows long enough to be split over several wavefronts) and COLS
+ * (two transposed operands, the transposed product, the list) need
  * cfpq_product_workspace_bytes.  The MFMA path requires n_nodes <= 2^19
  * (int32 accumulation bound); larger sizes return CFPQ_EINVAL.  Every product
  * kernel only reads rows and columns below n_nodes of its operands, which

@@ -99,9 +99,12 @@ hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* 
 
 // Sparse-operand products (kernels_sparse.hip): A[i,:] |= OR_{k in nz(B[i,:])} C[k,:]
 // for rows i < n, and A |= transpose(Pt).  `changed` may be NULL for the
-// row product (no flag wanted).
+// row product (no flag wanted).  `scratch`: device memory of
+// rowor_scratch_bytes (the list of rows long enough to be split), 16-byte
+// aligned, owned by the caller; not shared by launches in flight at once.
+size_t rowor_scratch_bytes(const Layout& L);
 hipError_t launch_rowor_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L, int32_t* changed,
-                                hipStream_t s, const int32_t* go = nullptr, int32_t want = 1);
+                                int32_t* scratch, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1);
 hipError_t launch_transpose_or(const uint64_t* Pt, uint64_t* A, const Layout& L, int32_t* changed, hipStream_t s,
                                const int32_t* go = nullptr, int32_t want = 1);
 
@@ -138,13 +141,34 @@ struct HybridModel {
     double mat_us = 0;    // one streamed pass over a matrix
 };
 
-inline int32_t hybrid_mode(const HybridModel& m, double nnz_b, double nnz_c, bool left_transposed) {
+struct HybridChoice {
+    int32_t mode;
+    double us;
+};
+
+// left_kept / right_kept: B^T / C^T already exist (a kept transpose);
+// otherwise COLS, and the MFMA product for C^T, first transpose them.
+inline HybridChoice hybrid_choice(const HybridModel& m, double nnz_b, double nnz_c, bool left_kept,
+                                  bool right_kept, bool dense_needs_ct) {
+    const double transpose = 9.0 * m.mat_us;
     const double rows = m.fixed_us + nnz_b * m.row_us + 3.0 * m.mat_us;
-    const double cols = 3.0 * m.fixed_us + nnz_c * m.row_us + (left_transposed ? 14.0 : 23.0) * m.mat_us;
-    if (rows <= cols && rows < m.dense_us) return kModeRows;
-    if (cols < rows && cols < m.dense_us) return kModeCols;
-    return kModeDense;
+    const double cols = 3.0 * m.fixed_us + nnz_c * m.row_us + 14.0 * m.mat_us + (left_kept ? 0.0 : transpose) +
+                        (right_kept ? 0.0 : transpose);
+    const double dense = m.dense_us + (dense_needs_ct && !right_kept ? transpose : 0.0);
+    HybridChoice c{kModeDense, dense};
+    if (rows < c.us) c = {kModeRows, rows};
+    if (cols < c.us) c = {kModeCols, cols};
+    return c;
 }
+
+inline int32_t hybrid_mode(const HybridModel& m, double nnz_b, double nnz_c, bool left_kept) {
+    return hybrid_choice(m, nnz_b, nnz_c, left_kept, true, false).mode;
+}
+
+// Delta step of the hybrid closure (closure.hip): where *pred != 0,
+// D = cur & ~P (bits gained since the snapshot), P = cur, *count += |D|.
+hipError_t launch_delta_snapshot(const uint64_t* cur, uint64_t* P, uint64_t* D, const Layout& L,
+                                 unsigned long long* count, const int32_t* pred, hipStream_t s);
 
 // counts[m] = number of set bits of matrix m (count matrices), added to counts.
 hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,

@@ -109,6 +109,10 @@ struct Plan {
     size_t off_rules = 0, off_go = 0, off_state = 0, off_nnz = 0;
     size_t off_second = 0, off_trans = 0, off_bt = 0, off_pt = 0, total = 0;
     bool temps = false;  // off_bt / off_pt hold a transposed left operand and product
+    // hybrid only: loop-start snapshots, the bits gained since the previous
+    // snapshot, their counts, and a scratch for a transposed right operand
+    size_t off_snap = 0, off_delta = 0, off_dnnz = 0, off_ct = 0;
+    size_t off_rowor = 0;  // scratch of the row-gather product (sparse modes)
 };
 
 // AUTO: the autotuned kernel of the size bucket, else MFMA while int32 sums
@@ -187,6 +191,16 @@ Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& 
     if (p.temps) off += mat_bytes;
     p.off_pt = off;
     if (p.temps) off += mat_bytes;
+    p.off_ct = off;
+    if (p.hybrid) off += mat_bytes;
+    p.off_snap = off;
+    if (p.hybrid) off += mat_bytes * p.n_nt;
+    p.off_delta = off;
+    if (p.hybrid) off += mat_bytes * p.n_nt;
+    p.off_dnnz = off;
+    if (p.hybrid) off += align_up(static_cast<size_t>(p.n_nt) * 8, 256);
+    p.off_rowor = off;
+    if (p.hybrid || p.forced != kModeDense) off += align_up(rowor_scratch_bytes(p.L), 256);
     p.total = off;
     return p;
 }
@@ -442,13 +456,23 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
 
     // ---- host-driven loop: one flag read-back per loop ----
     // Hybrid choice: set-bit counts of every matrix at the start of each loop,
-    // read back with the change flags.
+    // read back with the change flags.  Delta products: every rule's product
+    // of loop t-1 covered its operands as they were at the start of loop t-1
+    // (in place it read at least those bits), so in loop t it is enough to add
+    // D_B x C  and  B x D_C, D being the bits gained since that loop start;
+    // each rule takes whichever of the full product and the two delta halves
+    // the cost model prices lower.  Results are the same either way.
     auto* d_nnz = reinterpret_cast<unsigned long long*>(ws + p.off_nnz);
+    auto* d_dnnz = reinterpret_cast<unsigned long long*>(ws + p.off_dnnz);
     uint64_t* BT = reinterpret_cast<uint64_t*>(ws + p.off_bt);
     uint64_t* PT = reinterpret_cast<uint64_t*>(ws + p.off_pt);
-    std::vector<unsigned long long> nnz(n_nt, 0);
+    uint64_t* CTT = reinterpret_cast<uint64_t*>(ws + p.off_ct);
+    uint64_t* SNAP = reinterpret_cast<uint64_t*>(ws + p.off_snap);
+    uint64_t* DELTA = reinterpret_cast<uint64_t*>(ws + p.off_delta);
+    auto* ROWOR = reinterpret_cast<int32_t*>(ws + p.off_rowor);
+    std::vector<unsigned long long> nnz(n_nt, 0), dnnz(n_nt, 0);
     std::vector<char> written(n_nt, 0);  // a product wrote this nonterminal in the current loop
-    int64_t sparse_products = 0;
+    int64_t sparse_products = 0, delta_products = 0;
     auto count_bits = [&](const uint64_t* mats) -> cfpq_status {
         CFPQ_HIP(hipMemsetAsync(d_nnz, 0, static_cast<size_t>(n_nt) * 8, s));
         CFPQ_HIP(launch_popcount(mats, n_nt, L, d_nnz, s));
@@ -458,8 +482,38 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     if (!captured && p.hybrid && !converged) {
         st = count_bits(X);
         if (st != CFPQ_OK) return st;
+        CFPQ_HIP(hipMemcpyAsync(SNAP, X, mat_words * 8 * n_nt, hipMemcpyDeviceToDevice, s));
         CFPQ_HIP(hipStreamSynchronize(s));
     }
+    // One product A |= B x C in `mode`.  bt / ct: B^T / C^T when they exist,
+    // else nullptr (transposed into scratch when the mode needs them).
+    auto product_by = [&](int32_t mode, const uint64_t* Bm, const uint64_t* bt, const uint64_t* Cm,
+                          const uint64_t* ct, uint64_t* Am, int32_t* flag) -> cfpq_status {
+        if (mode == kModeRows) {
+            CFPQ_HIP(launch_rowor_product(Bm, Cm, Am, L, flag, ROWOR, s));
+            return CFPQ_OK;
+        }
+        if ((mode == kModeCols || p.path == CFPQ_PATH_MFMA) && !ct) {
+            CFPQ_HIP(launch_transpose(Cm, CTT, L, s));
+            ct = CTT;
+        }
+        if (mode == kModeCols) {
+            // (B x C)^T = C^T x B^T by rows of C^T, then transposed into A
+            if (!bt) {
+                CFPQ_HIP(launch_transpose(Bm, BT, L, s));
+                bt = BT;
+            }
+            CFPQ_HIP(launch_zero(PT, mat_words, s));
+            CFPQ_HIP(launch_rowor_product(ct, bt, PT, L, nullptr, ROWOR, s));
+            CFPQ_HIP(launch_transpose_or(PT, Am, L, flag, s));
+        } else if (p.path == CFPQ_PATH_MFMA) {
+            CFPQ_HIP(launch_mfma_product(Bm, ct, Am, L, flag, s));
+        } else {
+            CFPQ_HIP(launch_bits_product(Bm, Cm, Am, L, flag, s, p.tile));
+        }
+        return CFPQ_OK;
+    };
+    const bool mfma = p.path == CFPQ_PATH_MFMA;
     while (!captured && !converged && iters < cap) {
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         size_t launched = 0;
@@ -468,38 +522,55 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             const auto& br = grammar->bin_rules[r];
             if (o.dirty_worklist && iters > 0 && !prev[br.left] && !prev[br.right]) continue;
             const uint64_t* Bm = X + br.left * mat_words;
+            const uint64_t* Cm = X + br.right * mat_words;
             uint64_t* Am = Y + br.lhs * mat_words;
+            int32_t* flag = d_flags + br.lhs;
             if (o.profile) {
                 hipEvent_t e = product_event(2 * launched);
                 if (!e) return fail(CFPQ_EDEVICE, "hipEventCreate failed");
                 CFPQ_HIP(hipEventRecord(e, s));
             }
-            // COLS reads B^T: the kept transpose, unless (in place) B was written
-            // earlier in this loop, when a fresh transpose lets the product see
-            // those bits now rather than a loop later
+            // B^T is the kept transpose unless (in place) B was written earlier
+            // in this loop: a fresh transpose lets the product see those bits
+            // now rather than a loop later.  C^T is the kept one (loop start).
             const bool left_kept = p.right_slot[br.left] >= 0 && !(!p.jacobi && written[br.left]);
-            const int32_t mode = p.hybrid ? hybrid_mode(p.model, static_cast<double>(nnz[br.left]),
-                                                         static_cast<double>(nnz[br.right]), left_kept)
-                                          : p.forced;
-            int32_t* flag = d_flags + br.lhs;
-            if (mode == kModeRows) {
-                CFPQ_HIP(launch_rowor_product(Bm, X + br.right * mat_words, Am, L, flag, s));
-            } else if (mode == kModeCols) {
-                // (B x C)^T = C^T x B^T by rows of C^T, then transposed into A
-                const uint64_t* CT = TT + p.right_slot[br.right] * mat_words;
-                const uint64_t* BTm = BT;
-                if (left_kept) BTm = TT + p.right_slot[br.left] * mat_words;
-                else CFPQ_HIP(launch_transpose(Bm, BT, L, s));
-                CFPQ_HIP(launch_zero(PT, mat_words, s));
-                CFPQ_HIP(launch_rowor_product(CT, BTm, PT, L, nullptr, s));
-                CFPQ_HIP(launch_transpose_or(PT, Am, L, flag, s));
-            } else if (p.path == CFPQ_PATH_MFMA) {
-                const uint64_t* CT = TT + p.right_slot[br.right] * mat_words;
-                CFPQ_HIP(launch_mfma_product(Bm, CT, Am, L, flag, s));
+            const uint64_t* bt = left_kept ? TT + p.right_slot[br.left] * mat_words : nullptr;
+            const uint64_t* ct = p.right_slot[br.right] >= 0 ? TT + p.right_slot[br.right] * mat_words : nullptr;
+            if (!p.hybrid) {
+                st = product_by(p.forced, Bm, bt, Cm, ct, Am, flag);
+                if (st != CFPQ_OK) return st;
+                if (p.forced != kModeDense) ++sparse_products;
             } else {
-                CFPQ_HIP(launch_bits_product(Bm, X + br.right * mat_words, Am, L, flag, s, p.tile));
+                const double nb = static_cast<double>(nnz[br.left]), nc = static_cast<double>(nnz[br.right]);
+                const HybridChoice full = hybrid_choice(p.model, nb, nc, left_kept, ct != nullptr, mfma);
+                HybridChoice h1{kModeSkip, 0.0}, h2{kModeSkip, 0.0};
+                bool use_delta = false;
+                if (iters > 0) {
+                    const double db = static_cast<double>(dnnz[br.left]), dc = static_cast<double>(dnnz[br.right]);
+                    if (db > 0) h1 = hybrid_choice(p.model, db, nc, false, ct != nullptr, mfma);
+                    if (dc > 0) h2 = hybrid_choice(p.model, nb, dc, left_kept, false, mfma);
+                    use_delta = h1.us + h2.us < full.us;
+                }
+                if (!use_delta) {
+                    st = product_by(full.mode, Bm, bt, Cm, ct, Am, flag);
+                    if (st != CFPQ_OK) return st;
+                    if (full.mode != kModeDense) ++sparse_products;
+                } else {
+                    if (h1.mode != kModeSkip) {  // D_B x C
+                        st = product_by(h1.mode, DELTA + br.left * mat_words, nullptr, Cm, ct, Am, flag);
+                        if (st != CFPQ_OK) return st;
+                        ++delta_products;
+                        if (h1.mode != kModeDense) ++sparse_products;
+                    }
+                    if (h2.mode != kModeSkip) {  // B x D_C
+                        st = product_by(h2.mode, Bm, bt, DELTA + br.right * mat_words, nullptr, Am, flag);
+                        if (st != CFPQ_OK) return st;
+                        ++delta_products;
+                        if (h2.mode != kModeDense) ++sparse_products;
+                    }
+                    if (h1.mode != kModeSkip && h2.mode != kModeSkip) ++products;  // two halves, one rule
+                }
             }
-            if (mode != kModeDense) ++sparse_products;
             written[br.lhs] = 1;
             if (o.profile) {
                 hipEvent_t e = product_event(2 * launched + 1);
@@ -513,6 +584,12 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         if (p.hybrid) {
             st = count_bits(Y);
             if (st != CFPQ_OK) return st;
+            // bits gained this loop (changed nonterminals only), new snapshots
+            CFPQ_HIP(hipMemsetAsync(d_dnnz, 0, static_cast<size_t>(n_nt) * 8, s));
+            for (int32_t a = 0; a < n_nt; ++a)
+                CFPQ_HIP(launch_delta_snapshot(Y + a * mat_words, SNAP + a * mat_words, DELTA + a * mat_words, L,
+                                               d_dnnz + a, d_flags + a, s));
+            CFPQ_HIP(hipMemcpyAsync(dnnz.data(), d_dnnz, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
         }
         CFPQ_HIP(hipStreamSynchronize(s));
         for (size_t q = 0; o.profile && q < launched; ++q) {
@@ -551,6 +628,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         stats->bitops = 2.0 * static_cast<double>(L.npad) * static_cast<double>(L.npad) *
                         static_cast<double>(L.npad) * static_cast<double>(products - sparse_products);
         stats->sparse_products = sparse_products;
+        stats->delta_products = delta_products;
         stats->device_ms = ms;
         stats->product_ms = product_ms;
         stats->path_used = p.path;
@@ -563,7 +641,9 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
 size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path) {
     const size_t mat = static_cast<size_t>(layout_for(n_nodes < 0 ? 0 : n_nodes).mat_words) * 8;
     if (path == CFPQ_PATH_MFMA) return mat;
-    if (path == CFPQ_PATH_COLS) return 3 * mat;
+    const size_t rs = align_up(rowor_scratch_bytes(layout_for(n_nodes < 0 ? 0 : n_nodes)), 256);
+    if (path == CFPQ_PATH_ROWS) return rs;
+    if (path == CFPQ_PATH_COLS) return 3 * mat + rs;
     return 0;
 }
 
@@ -597,7 +677,7 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
             CFPQ_HIP(launch_mfma_product(d_b, ws, d_a, L, d_changed, s));
             break;
         case CFPQ_PATH_ROWS:
-            CFPQ_HIP(launch_rowor_product(d_b, d_c, d_a, L, d_changed, s));
+            CFPQ_HIP(launch_rowor_product(d_b, d_c, d_a, L, d_changed, reinterpret_cast<int32_t*>(ws), s));
             break;
         case CFPQ_PATH_COLS: {
             // workspace: C^T, B^T, the transposed product
@@ -605,7 +685,7 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
             CFPQ_HIP(launch_transpose(d_c, ct, L, s));
             CFPQ_HIP(launch_transpose(d_b, bt, L, s));
             CFPQ_HIP(launch_zero(pt, mw, s));
-            CFPQ_HIP(launch_rowor_product(ct, bt, pt, L, nullptr, s));
+            CFPQ_HIP(launch_rowor_product(ct, bt, pt, L, nullptr, reinterpret_cast<int32_t*>(ws + 3 * mw), s));
             CFPQ_HIP(launch_transpose_or(pt, d_a, L, d_changed, s));
             break;
         }

@@ -24,6 +24,8 @@ namespace {
 
 constexpr int kRound = 8;            // rows of C read per round
 constexpr int kMaxWordsPerLane = 8;  // output row slice per pass: 64 lanes x 8 words = 32768 columns
+constexpr int32_t kHeavyBits = 128;     // rows with more set bits go to the workgroup kernel
+constexpr int32_t kSegmentBits = 1024;  // about this many set bits per workgroup (4 wavefronts)
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
     const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), l));
@@ -32,12 +34,82 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+// OR into acc (this lane's WPL column words at off[]) the rows C[k, :] of the
+// set bits k in words [w_begin, w_end) of B's row.  The words are loaded 64 at
+// a time; a ballot finds the nonzero ones and their bits become a wave-uniform
+// stream of row indices; rows of C are read eight per round (a missing index
+// repeats the first: OR is idempotent) so 8 * WPL loads are in flight.
+template <int WPL>
+__device__ __forceinline__ void gather_rows(const uint64_t* brow, int32_t w_begin, int32_t w_end, const uint64_t* Cm,
+                                            int64_t W, const uint32_t (&off)[WPL], uint64_t (&acc)[WPL], int lane) {
+    int32_t kb = w_begin;
+    uint64_t word = kb + lane < w_end ? brow[kb + lane] : 0;
+    uint64_t nzl = __ballot(word != 0);
+    uint64_t bits = 0;
+    int64_t base = 0;
+    bool more = true;
+    while (more) {
+        int64_t k[kRound];
+        int got = 0;
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) {
+            while (bits == 0 && more) {
+                if (nzl == 0) {
+                    kb += 64;
+                    if (kb >= w_end) {
+                        more = false;
+                        break;
+                    }
+                    word = kb + lane < w_end ? brow[kb + lane] : 0;
+                    nzl = __ballot(word != 0);
+                    continue;
+                }
+                const int l = __ffsll(static_cast<unsigned long long>(nzl)) - 1;
+                nzl &= nzl - 1;
+                bits = readlane64(word, l);
+                base = static_cast<int64_t>(kb + l) * 64;
+            }
+            if (bits) {
+                k[u] = base + (__ffsll(static_cast<unsigned long long>(bits)) - 1);
+                bits &= bits - 1;
+                ++got;
+            } else {
+                k[u] = u == 0 ? 0 : k[0];
+            }
+        }
+        if (got == 0) break;
+        uint64_t v[kRound][WPL];
+#pragma unroll
+        for (int u = 0; u < kRound; ++u) {
+            const uint64_t* crow = Cm + k[u] * W;
+#pragma unroll
+            for (int q = 0; q < WPL; ++q) v[u][q] = crow[off[q]];
+        }
+#pragma unroll
+        for (int u = 0; u < kRound; ++u)
+#pragma unroll
+            for (int q = 0; q < WPL; ++q) acc[q] |= v[u][q];
+    }
+}
+
+// Columns of pass c0 held by this lane; past the row end a lane reads the
+// last word (in bounds) and never stores, so every gather load is unconditional.
+template <int WPL>
+__device__ __forceinline__ void lane_columns(int64_t c0, int64_t W, int lane, uint32_t (&off)[WPL]) {
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) off[q] = static_cast<uint32_t>(std::min<int64_t>(c0 + lane + 64 * q, W - 1));
+}
+
+// Light rows: one wavefront per row of B (grid-stride).  A row with more than
+// kHeavyBits set bits is not processed here but appended to `heavy` (count in
+// heavy_count), so that a long row does not serialise on one wavefront.
 // Bm and Cm may alias Am (in-place update; only bits are ever added, so any
 // mix of old and new words read is a subset of the fixpoint): no __restrict__.
 template <int WPL>
 __global__ __launch_bounds__(256) void rowor_kernel(const uint64_t* Bm, const uint64_t* Cm, uint64_t* Am, int64_t W,
                                                     int32_t nrows, int32_t kwords, int32_t* changed,
-                                                    const int32_t* go, int32_t want) {
+                                                    int32_t* heavy_count, int32_t* heavy, const int32_t* go,
+                                                    int32_t want) {
     if (go != nullptr && *go != want) return;  // uniform over the grid
     const int lane = threadIdx.x & 63;
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
@@ -45,65 +117,29 @@ __global__ __launch_bounds__(256) void rowor_kernel(const uint64_t* Bm, const ui
     for (int64_t row = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); row < nrows;
          row += waves) {
         const uint64_t* brow = Bm + row * W;
+        int32_t cnt = 0;
+        for (int32_t kb = lane; kb < kwords; kb += 64) cnt += __popcll(brow[kb]);
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (cnt == 0) continue;  // uniform
+        if (cnt > kHeavyBits) {
+            // segments of about kSegmentBits bits, each taken by one workgroup
+            const int32_t nseg = (cnt + kSegmentBits - 1) / kSegmentBits;
+            if (lane == 0) {
+                const int32_t at = atomicAdd(heavy_count, nseg);
+                for (int32_t g = 0; g < nseg; ++g) {
+                    heavy[2 * (at + g)] = static_cast<int32_t>(row);
+                    heavy[2 * (at + g) + 1] = (g << 16) | nseg;
+                }
+            }
+            continue;
+        }
         for (int64_t c0 = 0; c0 < W; c0 += 64 * WPL) {
-            // this lane's columns; past the row end a lane reads the last word
-            // (in bounds) and never stores, so every load is unconditional
             uint32_t off[WPL];
-#pragma unroll
-            for (int q = 0; q < WPL; ++q)
-                off[q] = static_cast<uint32_t>(std::min<int64_t>(c0 + lane + 64 * q, W - 1));
+            lane_columns<WPL>(c0, W, lane, off);
             uint64_t acc[WPL];
 #pragma unroll
             for (int q = 0; q < WPL; ++q) acc[q] = 0;
-            // stream of set-bit indices of B's row (all wave-uniform but `word`)
-            int32_t kb = 0;
-            uint64_t word = lane < kwords ? brow[lane] : 0;
-            uint64_t nzl = __ballot(word != 0);
-            uint64_t bits = 0;
-            int64_t base = 0;
-            bool more = true;
-            while (more) {
-                int64_t k[kRound];
-                int got = 0;
-#pragma unroll
-                for (int u = 0; u < kRound; ++u) {
-                    while (bits == 0 && more) {
-                        if (nzl == 0) {
-                            kb += 64;
-                            if (kb >= kwords) {
-                                more = false;
-                                break;
-                            }
-                            word = kb + lane < kwords ? brow[kb + lane] : 0;
-                            nzl = __ballot(word != 0);
-                            continue;
-                        }
-                        const int l = __ffsll(static_cast<unsigned long long>(nzl)) - 1;
-                        nzl &= nzl - 1;
-                        bits = readlane64(word, l);
-                        base = static_cast<int64_t>(kb + l) * 64;
-                    }
-                    if (bits) {
-                        k[u] = base + (__ffsll(static_cast<unsigned long long>(bits)) - 1);
-                        bits &= bits - 1;
-                        ++got;
-                    } else {
-                        k[u] = u == 0 ? 0 : k[0];  // exhausted: repeat a row already read (OR is idempotent)
-                    }
-                }
-                if (got == 0) break;
-                uint64_t v[kRound][WPL];
-#pragma unroll
-                for (int u = 0; u < kRound; ++u) {
-                    const uint64_t* crow = Cm + k[u] * W;
-#pragma unroll
-                    for (int q = 0; q < WPL; ++q) v[u][q] = crow[off[q]];
-                }
-#pragma unroll
-                for (int u = 0; u < kRound; ++u)
-#pragma unroll
-                    for (int q = 0; q < WPL; ++q) acc[q] |= v[u][q];
-            }
+            gather_rows<WPL>(brow, 0, kwords, Cm, W, off, acc, lane);
             uint64_t* arow = Am + row * W;
 #pragma unroll
             for (int q = 0; q < WPL; ++q) {
@@ -115,6 +151,68 @@ __global__ __launch_bounds__(256) void rowor_kernel(const uint64_t* Bm, const ui
                     }
                 }
             }
+        }
+    }
+    if (__syncthreads_or(ch) && threadIdx.x == 0 && changed != nullptr) atomicOr(changed, 1);
+}
+
+// Long rows: one workgroup per segment of a row (grid-stride over the
+// segments the light kernel listed); the four wavefronts take a quarter of the
+// segment's words each and their partial rows are OR-reduced in LDS.  A row
+// in one segment is stored with a plain read-modify-write; the segments of a
+// longer row OR into it atomically.
+template <int WPL>
+__global__ __launch_bounds__(256) void rowor_heavy_kernel(const uint64_t* Bm, const uint64_t* Cm, uint64_t* Am,
+                                                          int64_t W, int32_t kwords, int32_t* changed,
+                                                          const int32_t* heavy_count, const int32_t* heavy,
+                                                          const int32_t* go, int32_t want) {
+    if (go != nullptr && *go != want) return;
+    __shared__ unsigned long long red[64 * WPL];
+    const int32_t n_seg = *heavy_count;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bool ch = false;
+    for (int32_t e = blockIdx.x; e < n_seg; e += gridDim.x) {  // uniform over the block
+        const int64_t row = heavy[2 * e];
+        const int32_t seg = heavy[2 * e + 1] >> 16, nseg = heavy[2 * e + 1] & 0xFFFF;
+        const int32_t s0 = static_cast<int32_t>(static_cast<int64_t>(kwords) * seg / nseg);
+        const int32_t s1 = static_cast<int32_t>(static_cast<int64_t>(kwords) * (seg + 1) / nseg);
+        const int32_t w0 = s0 + (s1 - s0) * wave / 4, w1 = s0 + (s1 - s0) * (wave + 1) / 4;
+        const uint64_t* brow = Bm + row * W;
+        uint64_t* arow = Am + row * W;
+        for (int64_t c0 = 0; c0 < W; c0 += 64 * WPL) {
+            for (int q = threadIdx.x; q < 64 * WPL; q += blockDim.x) red[q] = 0;
+            __syncthreads();
+            uint32_t off[WPL];
+            lane_columns<WPL>(c0, W, lane, off);
+            uint64_t acc[WPL];
+#pragma unroll
+            for (int q = 0; q < WPL; ++q) acc[q] = 0;
+            if (w0 < w1) gather_rows<WPL>(brow, w0, w1, Cm, W, off, acc, lane);
+#pragma unroll
+            for (int q = 0; q < WPL; ++q)
+                if (acc[q]) atomicOr(&red[lane + 64 * q], static_cast<unsigned long long>(acc[q]));
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int q = 0; q < WPL; ++q) {
+                    const uint64_t v = red[lane + 64 * q];
+                    if (c0 + lane + 64 * q < W && v != 0) {
+                        uint64_t* dst = arow + off[q];
+                        if (nseg == 1) {
+                            const uint64_t old = *dst;
+                            if (v & ~old) {
+                                *dst = old | v;
+                                ch = true;
+                            }
+                        } else {
+                            const unsigned long long prev =
+                                atomicOr(reinterpret_cast<unsigned long long*>(dst), static_cast<unsigned long long>(v));
+                            if (v & ~prev) ch = true;
+                        }
+                    }
+                }
+            }
+            __syncthreads();  // red is reused
         }
     }
     if (__syncthreads_or(ch) && threadIdx.x == 0 && changed != nullptr) atomicOr(changed, 1);
@@ -155,19 +253,39 @@ constexpr int64_t kSparseMaxBlocks = 2048;
 }  // namespace
 
 hipError_t launch_rowor_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L, int32_t* changed,
-                                hipStream_t s, const int32_t* go, int32_t want) {
+                                int32_t* scratch, hipStream_t s, const int32_t* go, int32_t want) {
     const int32_t nrows = L.n;
     if (nrows == 0) return hipSuccess;
     const int32_t kwords = static_cast<int32_t>((L.n + 63) / 64);
     const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((nrows + 3) / 4, kSparseMaxBlocks));
-    if (L.W <= 64 * 2)
-        rowor_kernel<2><<<dim3(blocks), dim3(256), 0, s>>>(B, C, A, L.W, nrows, kwords, changed, go, want);
-    else if (L.W <= 64 * 4)
-        rowor_kernel<4><<<dim3(blocks), dim3(256), 0, s>>>(B, C, A, L.W, nrows, kwords, changed, go, want);
-    else
-        rowor_kernel<kMaxWordsPerLane><<<dim3(blocks), dim3(256), 0, s>>>(B, C, A, L.W, nrows, kwords, changed, go,
-                                                                          want);
+    int32_t* heavy_count = scratch;
+    int32_t* heavy = scratch + 64;  // segments (row, seg << 16 | count) from byte 256 on
+    hipError_t e = launch_zero(reinterpret_cast<uint64_t*>(scratch), 1, s, go, want);
+    if (e != hipSuccess) return e;
+    const unsigned hblocks = 1024;
+    if (L.W <= 64 * 2) {
+        rowor_kernel<2><<<dim3(blocks), dim3(256), 0, s>>>(B, C, A, L.W, nrows, kwords, changed, heavy_count, heavy,
+                                                          go, want);
+        rowor_heavy_kernel<2><<<dim3(hblocks), dim3(256), 0, s>>>(B, C, A, L.W, kwords, changed, heavy_count, heavy,
+                                                                 go, want);
+    } else if (L.W <= 64 * 4) {
+        rowor_kernel<4><<<dim3(blocks), dim3(256), 0, s>>>(B, C, A, L.W, nrows, kwords, changed, heavy_count, heavy,
+                                                          go, want);
+        rowor_heavy_kernel<4><<<dim3(hblocks), dim3(256), 0, s>>>(B, C, A, L.W, kwords, changed, heavy_count, heavy,
+                                                                 go, want);
+    } else {
+        rowor_kernel<kMaxWordsPerLane><<<dim3(blocks), dim3(256), 0, s>>>(B, C, A, L.W, nrows, kwords, changed,
+                                                                          heavy_count, heavy, go, want);
+        rowor_heavy_kernel<kMaxWordsPerLane><<<dim3(hblocks), dim3(256), 0, s>>>(B, C, A, L.W, kwords, changed,
+                                                                                 heavy_count, heavy, go, want);
+    }
     return hipGetLastError();
+}
+
+// A row of at most 64 * kwords bits has at most kwords / 16 + 1 segments.
+size_t rowor_scratch_bytes(const Layout& L) {
+    const int64_t kwords = std::max<int64_t>(1, (L.n + 63) / 64);
+    return static_cast<size_t>(L.npad) * static_cast<size_t>(kwords / 16 + 1) * 8 + 256;
 }
 
 hipError_t launch_transpose_or(const uint64_t* Pt, uint64_t* A, const Layout& L, int32_t* changed, hipStream_t s,

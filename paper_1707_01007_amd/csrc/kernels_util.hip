@@ -90,7 +90,40 @@ __global__ __launch_bounds__(256) void popcount_kernel(const uint64_t* __restric
     }
 }
 
+__global__ __launch_bounds__(256) void delta_snapshot_kernel(const uint64_t* __restrict__ cur,
+                                                             uint64_t* __restrict__ P, uint64_t* __restrict__ D,
+                                                             int64_t words, unsigned long long* __restrict__ count,
+                                                             const int32_t* __restrict__ pred) {
+    if (pred != nullptr && *pred == 0) return;
+    unsigned long long c = 0;
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const uint64_t x = cur[w];
+        const uint64_t d = x & ~P[w];
+        D[w] = d;
+        P[w] = x;
+        c += __popcll(d);
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(count, t);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_delta_snapshot(const uint64_t* cur, uint64_t* P, uint64_t* D, const Layout& L,
+                                 unsigned long long* count, const int32_t* pred, hipStream_t s) {
+    int64_t blocks = (L.mat_words + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    delta_snapshot_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(cur, P, D, L.mat_words, count,
+                                                                                   pred);
+    return hipGetLastError();
+}
 
 hipError_t launch_zero(uint64_t* p, size_t words, hipStream_t s, const int32_t* pred, int32_t want) {
     if (words == 0) return hipSuccess;

@@ -148,8 +148,8 @@ def test_sparse_paths_take_no_tile(path):
 
 
 def test_workspace_grows_with_sparse_temporaries():
-    """COLS (and the hybrid choice at padded sizes >= 4096) needs the
-    transposed right operands plus two temporaries; ROWS needs none."""
+    """COLS needs the transposed right operands plus two temporaries, the
+    hybrid choice (padded sizes >= 4096) more; ROWS needs none."""
     from paper_1707_01007_amd import _abi
     lib = _lib()
     n = 5000
@@ -164,11 +164,15 @@ def test_workspace_grows_with_sparse_temporaries():
         sz = ctypes.c_size_t(0)
         assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz)) == 0
         sizes[name] = sz.value
-    assert sizes["rows"] == sizes["bits_dense"]
-    assert sizes["cols"] == sizes["mfma_dense"] + 2 * mat   # one right operand (B) transposed in both
-    assert sizes["bits_hybrid"] == sizes["cols"]
-    assert lib.cfpq_product_workspace_bytes(n, 3) == 0
-    assert lib.cfpq_product_workspace_bytes(n, 4) == 3 * mat
+    rs = lib.cfpq_product_workspace_bytes(n, 3)  # the row product's scratch
+    kwords = (n + 63) // 64
+    assert rs >= lib.cfpq_padded_rows(n) * (kwords // 16 + 1) * 8 + 256 and rs % 256 == 0
+    assert sizes["rows"] == sizes["bits_dense"] + rs
+    assert sizes["cols"] == sizes["mfma_dense"] + 2 * mat + rs  # one right operand (B) transposed in both
+    # hybrid: the COLS scratch, plus a transposed right operand, loop-start
+    # snapshots and gained bits of every nonterminal, and their counts
+    assert sizes["bits_hybrid"] == sizes["cols"] + mat + 2 * g.n_nonterminals * mat + 256
+    assert lib.cfpq_product_workspace_bytes(n, 4) == 3 * mat + rs
 
 
 def test_struct_layouts_match_the_header(tmp_path):
@@ -208,7 +212,8 @@ def test_product_rejects_bad_arguments():
     assert lib.cfpq_product(64, 1, 0, None, None, None, None, None, 0, None) == _abi.CFPQ_EINVAL
     p = ctypes.c_void_p(1 << 20)
     assert lib.cfpq_product(64, 9, 0, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL
-    assert lib.cfpq_product(64, 3, 8, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL    # ROWS has no tiles
+    assert lib.cfpq_product(64, 3, 8, p, p, p, p, p, 1 << 20, None) == _abi.CFPQ_EINVAL  # ROWS has no tiles
+    assert lib.cfpq_product(64, 3, 0, p, p, p, p, None, 0, None) == _abi.CFPQ_ENOMEM    # ROWS needs scratch
     assert lib.cfpq_product(64, 4, 0, p, p, p, p, None, 0, None) == _abi.CFPQ_ENOMEM    # COLS needs workspace
     assert lib.cfpq_product(64, 1, 12, p, p, p, p, None, 0, None) == _abi.CFPQ_EINVAL   # no such strip width
     assert lib.cfpq_product(64, 2, 0, p, p, p, p, None, 0, None) == _abi.CFPQ_ENOMEM

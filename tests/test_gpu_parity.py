@@ -285,10 +285,12 @@ def test_full_size_er16384(cfpq, path, hybrid):
     assert [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits] == d["counts"]
     assert _digest(bits) == d["sha256"]
     if hybrid:
-        # the three rules with a terminal operand run sparse, S -> S S dense
+        # the three rules with a terminal operand run sparse, S -> S S dense;
+        # the last loop, with few new bits, runs S -> S S on its deltas
         assert 0 < res.stats["sparse_products"] < res.stats["products"]
+        assert res.stats["delta_products"] > 0
     else:
-        assert res.stats["sparse_products"] == 0
+        assert res.stats["sparse_products"] == 0 and res.stats["delta_products"] == 0
 
 
 # ---------------------------------------------------------------- hybrid choice
@@ -307,7 +309,6 @@ def test_hybrid_equals_dense_and_oracle(cfpq, schedule):
     assert ra.stats["sparse_products"] == 0
     if schedule == "jacobi":
         assert ra.stats["iterations"] == rb.stats["iterations"]
-        assert ra.stats["products"] == rb.stats["products"]
     # the dense products are the only ones counted as bit-operations
     npad = cfpq.padded_rows(inst.n)
     dense = rb.stats["products"] - rb.stats["sparse_products"]
@@ -352,3 +353,26 @@ def test_warm_start_after_adding_edges(cfpq, schedule):
     res = cfpq.closure(inst.n, inst.edges, inst.grammar, schedule=schedule, out=first.bits.view(-1),
                        warm_start=True)
     assert np.array_equal(cfpq.result_bits(res), worklist.closure(inst.n, inst.edges, inst.grammar))
+
+
+@pytest.mark.parametrize("path", ["rows", "cols"])
+@pytest.mark.parametrize("n", [300, 2048, 4100])
+def test_sparse_products_with_skewed_rows(cfpq, path, n):
+    """A few rows (and columns) far denser than the rest: the row product
+    splits long rows over several wavefronts and ORs their parts atomically."""
+    import torch
+    rng = np.random.default_rng(n + 7)
+    b = rng.random((n, n)) < 0.001
+    c = rng.random((n, n)) < 0.001
+    b[[0, n // 2, n - 1], :] = rng.random((3, n)) < 0.7
+    c[:, [1, n // 3]] = rng.random((n, 2)) < 0.7
+    c[[2, n - 2], :] = rng.random((2, n)) < 0.6
+    a0 = rng.random((n, n)) < 0.002
+    want = a0 | alg1.bool_product(b, c)
+    dev = cfpq.upload_bits(n, worklist.pack(np.stack([b, c, a0])))
+    _say("skewed product", n, path)
+    changed = cfpq.product(n, dev[0], dev[1], dev[2], path=path)
+    torch.cuda.synchronize()
+    got = worklist.unpack(dev[2, :n, : (n + 63) // 64].cpu().numpy().view(np.uint64), n)
+    assert np.array_equal(got, want)
+    assert int(changed.item()) == 1
