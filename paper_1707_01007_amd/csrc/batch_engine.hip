@@ -321,8 +321,8 @@ __global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __res
     }
 }
 
-// Transposes of the loop's work list: an item is one 64 x 64 block (ballot
-// transpose as in transpose_kernel); each wavefront takes items
+// Transposes of the loop's work list: an item is one 64 x 64 block
+// (transpose64, as in transpose_kernel); each wavefront takes items
 // w, w + waves, ... (static striding: items are cheap and uniform).
 __global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* __restrict__ descs,
                                                                const int32_t* __restrict__ trans_tab,
@@ -341,13 +341,7 @@ __global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* _
         uint64_t* dst = d.TT + trans_tab[d.trans_off + jb.what] * mw;
         const int64_t br = blk / W, bc = blk % W;
         const uint64_t word = src[(br * 64 + lane) * W + bc];
-        uint64_t mine = 0;
-#pragma unroll 8
-        for (int j = 0; j < 64; ++j) {
-            const uint64_t col = __ballot((word >> j) & 1ull);
-            mine = (lane == j) ? col : mine;
-        }
-        dst[(bc * 64 + lane) * W + br] = mine;
+        dst[(bc * 64 + lane) * W + br] = transpose64(word, lane);
     }
 }
 

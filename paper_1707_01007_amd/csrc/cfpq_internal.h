@@ -166,9 +166,27 @@ inline int32_t hybrid_mode(const HybridModel& m, double nnz_b, double nnz_c, boo
 }
 
 // Delta step of the hybrid closure (closure.hip): where *pred != 0,
-// D = cur & ~P (bits gained since the snapshot), P = cur, *count += |D|.
+// D = cur & ~P (bits gained since the snapshot), P = cur, *count += |D|,
+// *count_cur += |cur|.
 hipError_t launch_delta_snapshot(const uint64_t* cur, uint64_t* P, uint64_t* D, const Layout& L,
-                                 unsigned long long* count, const int32_t* pred, hipStream_t s);
+                                 unsigned long long* count, unsigned long long* count_cur, const int32_t* pred,
+                                 hipStream_t s);
+// 64 x 64 bit transpose across a wavefront: lane t holds row t of the block
+// and gets row t of its transpose.  Six exchange stages: lanes t and t ^ j
+// (j = 32, 16, ..., 1) swap the off-diagonal j x j sub-blocks of every
+// 2j x 2j block (columns with bit j clear stay, the partner's move in).
+__device__ __forceinline__ uint64_t transpose64(uint64_t w, int lane) {
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int j = 32 >> s;
+        const uint64_t m = masks[s];
+        const uint64_t other = static_cast<uint64_t>(__shfl_xor(static_cast<unsigned long long>(w), j, 64));
+        w = (lane & j) ? (((other >> j) & m) | (w & ~m)) : ((w & m) | ((other & m) << j));
+    }
+    return w;
+}
 
 // counts[m] = number of set bits of matrix m (count matrices), added to counts.
 hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,

@@ -197,8 +197,8 @@ Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& 
     if (p.hybrid) off += mat_bytes * p.n_nt;
     p.off_delta = off;
     if (p.hybrid) off += mat_bytes * p.n_nt;
-    p.off_dnnz = off;
-    if (p.hybrid) off += align_up(static_cast<size_t>(p.n_nt) * 8, 256);
+    p.off_dnnz = off;  // |D| then |T| per nonterminal
+    if (p.hybrid) off += align_up(static_cast<size_t>(p.n_nt) * 16, 256);
     p.off_rowor = off;
     if (p.hybrid || p.forced != kModeDense) off += align_up(rowor_scratch_bytes(p.L), 256);
     p.total = off;
@@ -470,7 +470,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     uint64_t* SNAP = reinterpret_cast<uint64_t*>(ws + p.off_snap);
     uint64_t* DELTA = reinterpret_cast<uint64_t*>(ws + p.off_delta);
     auto* ROWOR = reinterpret_cast<int32_t*>(ws + p.off_rowor);
-    std::vector<unsigned long long> nnz(n_nt, 0), dnnz(n_nt, 0);
+    std::vector<unsigned long long> nnz(n_nt, 0), dnnz(2 * static_cast<size_t>(n_nt), 0);
     std::vector<char> written(n_nt, 0);  // a product wrote this nonterminal in the current loop
     int64_t sparse_products = 0, delta_products = 0;
     auto count_bits = [&](const uint64_t* mats) -> cfpq_status {
@@ -582,16 +582,18 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         }
         CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
         if (p.hybrid) {
-            st = count_bits(Y);
-            if (st != CFPQ_OK) return st;
-            // bits gained this loop (changed nonterminals only), new snapshots
-            CFPQ_HIP(hipMemsetAsync(d_dnnz, 0, static_cast<size_t>(n_nt) * 8, s));
+            // for the nonterminals that changed: bits gained this loop, new
+            // snapshot, new set-bit count (the others keep theirs)
+            CFPQ_HIP(hipMemsetAsync(d_dnnz, 0, static_cast<size_t>(n_nt) * 16, s));
             for (int32_t a = 0; a < n_nt; ++a)
                 CFPQ_HIP(launch_delta_snapshot(Y + a * mat_words, SNAP + a * mat_words, DELTA + a * mat_words, L,
-                                               d_dnnz + a, d_flags + a, s));
-            CFPQ_HIP(hipMemcpyAsync(dnnz.data(), d_dnnz, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
+                                               d_dnnz + a, d_dnnz + n_nt + a, d_flags + a, s));
+            CFPQ_HIP(hipMemcpyAsync(dnnz.data(), d_dnnz, static_cast<size_t>(n_nt) * 16, hipMemcpyDeviceToHost, s));
         }
         CFPQ_HIP(hipStreamSynchronize(s));
+        if (p.hybrid)
+            for (int32_t a = 0; a < n_nt; ++a)
+                if (flags[a]) nnz[a] = dnnz[n_nt + a];
         for (size_t q = 0; o.profile && q < launched; ++q) {
             float pm = 0.f;
             CFPQ_HIP(hipEventElapsedTime(&pm, pev[2 * q], pev[2 * q + 1]));

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void rowor_heavy_kernel(const uint64_t* Bm, co
 }
 
 // A |= transpose(Pt), with the change flag; one wavefront per 64 x 64 block
-// at a time (ballot transpose), the grid striding over blocks.
+// at a time (exchange-stage transpose), the grid striding over blocks.
 __global__ __launch_bounds__(256) void transpose_or_kernel(const uint64_t* __restrict__ Pt, uint64_t* A, int64_t W,
                                                            int32_t* changed, const int32_t* go, int32_t want) {
     if (go != nullptr && *go != want) return;
@@ -231,12 +231,7 @@ __global__ __launch_bounds__(256) void transpose_or_kernel(const uint64_t* __res
         const int64_t br = blk / W, bc = blk % W;
         const uint64_t word = Pt[(br * 64 + lane) * W + bc];
         if (__ballot(word != 0) == 0) continue;  // uniform: nothing to add from this block
-        uint64_t mine = 0;
-#pragma unroll 8
-        for (int j = 0; j < 64; ++j) {
-            const uint64_t col = __ballot((word >> j) & 1ull);
-            mine = (lane == j) ? col : mine;
-        }
+        const uint64_t mine = transpose64(word, lane);
         uint64_t* dst = A + (bc * 64 + lane) * W + br;
         const uint64_t old = *dst;
         if (mine & ~old) {

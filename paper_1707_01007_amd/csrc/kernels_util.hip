@@ -36,10 +36,10 @@ __global__ void init_scatter_kernel(const cfpq_edge* __restrict__ edges, int64_t
     }
 }
 
-// Bit-matrix transpose, one wavefront per 64 x 64 block.  Lane t holds row
-// r0 + t of the block as one 64-bit word; column j of the block is the ballot
-// of bit j over the lanes, which lane j keeps and writes as row c0 + j of the
-// transpose.
+// Bit-matrix transpose, one wavefront per 64 x 64 block: lane t holds row
+// r0 + t of the block as one 64-bit word, and six exchange stages (lanes t and
+// t ^ j swap the off-diagonal j x j sub-blocks of every 2j x 2j block,
+// j = 32, 16, ..., 1) leave row c0 + t of the transpose in lane t.
 __global__ __launch_bounds__(256) void transpose_kernel(const uint64_t* __restrict__ src,
                                                         uint64_t* __restrict__ dst, int64_t W,
                                                         const int32_t* __restrict__ pred, int32_t want) {
@@ -50,18 +50,10 @@ __global__ __launch_bounds__(256) void transpose_kernel(const uint64_t* __restri
     if (blk >= blocks) return;
     const int64_t br = blk / W;  // block row (word index of the source rows / 64)
     const int64_t bc = blk % W;  // block column (word column)
-    uint64_t word = src[(br * 64 + lane) * W + bc];
-    uint64_t mine = 0;
-#pragma unroll 8
-    for (int j = 0; j < 64; ++j) {
-        uint64_t col = __ballot((word >> j) & 1ull);
-        mine = (lane == j) ? col : mine;
-    }
-    dst[(bc * 64 + lane) * W + br] = mine;
+    const uint64_t word = src[(br * 64 + lane) * W + bc];
+    dst[(bc * 64 + lane) * W + br] = transpose64(word, lane);
 }
 
-// counts[y] += set bits of matrix y; `pairs` 16-byte loads per matrix (the
-// matrices are 16-byte aligned: whole matrices are an even number of words).
 __global__ __launch_bounds__(256) void popcount_kernel(const uint64_t* __restrict__ mats,
                                                        int64_t mat_words,
                                                        unsigned long long* __restrict__ counts) {
@@ -93,9 +85,10 @@ __global__ __launch_bounds__(256) void popcount_kernel(const uint64_t* __restric
 __global__ __launch_bounds__(256) void delta_snapshot_kernel(const uint64_t* __restrict__ cur,
                                                              uint64_t* __restrict__ P, uint64_t* __restrict__ D,
                                                              int64_t words, unsigned long long* __restrict__ count,
+                                                             unsigned long long* __restrict__ count_cur,
                                                              const int32_t* __restrict__ pred) {
     if (pred != nullptr && *pred == 0) return;
-    unsigned long long c = 0;
+    unsigned long long c = 0, cc = 0;
     for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
          w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const uint64_t x = cur[w];
@@ -103,25 +96,35 @@ __global__ __launch_bounds__(256) void delta_snapshot_kernel(const uint64_t* __r
         D[w] = d;
         P[w] = x;
         c += __popcll(d);
+        cc += __popcll(x);
     }
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-    __shared__ unsigned long long part[4];
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_down(c, off, 64);
+        cc += __shfl_down(cc, off, 64);
+    }
+    __shared__ unsigned long long part[8];
+    if ((threadIdx.x & 63) == 0) {
+        part[threadIdx.x >> 6] = c;
+        part[4 + (threadIdx.x >> 6)] = cc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        const unsigned long long tc = part[4] + part[5] + part[6] + part[7];
         if (t) atomicAdd(count, t);
+        if (tc) atomicAdd(count_cur, tc);
     }
 }
 
 }  // namespace
 
 hipError_t launch_delta_snapshot(const uint64_t* cur, uint64_t* P, uint64_t* D, const Layout& L,
-                                 unsigned long long* count, const int32_t* pred, hipStream_t s) {
+                                 unsigned long long* count, unsigned long long* count_cur, const int32_t* pred,
+                                 hipStream_t s) {
     int64_t blocks = (L.mat_words + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     delta_snapshot_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(cur, P, D, L.mat_words, count,
-                                                                                   pred);
+                                                                                   count_cur, pred);
     return hipGetLastError();
 }
 
@@ -145,6 +148,7 @@ hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t*
 
 hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s,
                             const int32_t* pred, int32_t want) {
+
     int64_t blocks = L.W * L.W;
     int64_t wgs = (blocks + 3) / 4;
     transpose_kernel<<<dim3(static_cast<unsigned>(wgs)), dim3(256), 0, s>>>(src, dst, L.W, pred, want);
