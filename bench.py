@@ -139,6 +139,59 @@ def bench_hybrid(cfpq, torch, inst, edges, dense_out, args, dense_s):
             "sparse_products": st["sparse_products"], "loops": st["iterations"], "identical_to_dense": same}
 
 
+# VALU: 256 CUs x 64 lanes per clock x 2.4 GHz 32-bit integer operations
+PEAK_VALU_INT32_T = 256 * 64 * 2.4e9 / 1e12
+
+
+def bench_single_path(cfpq, torch, n=4096, steps=2):
+    """Single-path lengths (section 5) on the ER Dyck recipe at n = 4096: time
+    per closure, and the min-plus kernel's rate against the VALU roofline (one
+    add and one min per (i, j, k) term)."""
+    from workloads import configs
+    inst = configs.config3(n)
+    edges = torch.from_numpy(inst.edges).cuda()
+    res, L = cfpq.single_path(n, edges, inst.grammar)  # warm-up and buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, L = cfpq.single_path(n, edges, inst.grammar)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    st = res.stats
+    rate_t = st["minplus_terms"] / (st["product_ms"] / 1e3) / 1e12 if st["product_ms"] else 0.0
+    achieved = 2.0 * rate_t
+    print(f"[bench] single path n={n}: {t * 1e3:.1f} ms, {st['iterations']} loops, min-plus "
+          f"{st['minplus_terms']:.3e} terms in {st['product_ms']:.1f} ms", file=sys.stderr, flush=True)
+    return {"workload": inst.tag, "n": n, "ms_per_closure": round(t * 1e3, 3), "loops": st["iterations"],
+            "minplus_terms": st["minplus_terms"], "minplus_ms": round(st["product_ms"], 3),
+            "roofline": {"bound": "alu", "kernel": "minplus_kernel", "achieved": round(achieved, 2),
+                         "peak": round(PEAK_VALU_INT32_T, 1), "unit": "Tops/s (int32 add + min per term)",
+                         "frac": round(achieved / PEAK_VALU_INT32_T, 4)}}
+
+
+def bench_conjunctive(cfpq, torch, n=8192, steps=3):
+    """Conjunctive closure (Dyck conjoined with a^n b^n at the start rules) on
+    the ER recipe at n = 8192 with dense MFMA products: time per closure and
+    Gbit-op/s of its dense products (2 npad^3 each)."""
+    from workloads import configs, grammars
+    inst = configs.config3(n)
+    g = grammars.dyck_and_anbn()
+    edges = torch.from_numpy(inst.edges).cuda()
+    res = cfpq.conjunctive_closure(n, edges, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = cfpq.conjunctive_closure(n, edges, g)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    st = res.stats
+    print(f"[bench] conjunctive n={n}: {t * 1e3:.1f} ms, {st['iterations']} loops, {st['products']} products",
+          file=sys.stderr, flush=True)
+    return {"workload": f"er{n}_dyck_and_anbn", "n": n, "ms_per_closure": round(t * 1e3, 3),
+            "loops": st["iterations"], "products": st["products"],
+            "Gbitop_per_s": round(st["bitops"] / t / 1e9, 1)}
+
+
 def _pct(xs, q):
     import numpy as np
     return round(float(np.percentile(np.asarray(xs), q)), 3) if xs else None
@@ -228,6 +281,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-closure section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-next", action="store_true", help="skip the single-path and conjunctive sections")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -316,6 +370,9 @@ def main():
         "roofline": roof,
     }
     line["hybrid"] = bench_hybrid(cfpq, torch, inst, edges, out, args, wall / args.steps)
+    if not args.no_next:
+        line["single_path"] = bench_single_path(cfpq, torch)
+        line["conjunctive"] = bench_conjunctive(cfpq, torch)
     if not args.no_batch:
         line["batch"] = bench_batch(cfpq, torch)
     if not args.no_serve:

@@ -143,6 +143,8 @@ typedef struct {
     int64_t delta_products;  /* products of `products` with a delta operand: a rule A -> B C whose
                                 operands gained the bits D_B, D_C since the previous loop started
                                 may add D_B x C and B x D_C instead of B x C (hybrid choice) */
+    double minplus_terms;    /* cfpq_single_path only: (i, j, k) terms l_B(i,k) + l_C(k,j) the min-plus
+                                kernel evaluated (product_ms is then its summed time); 0 elsewhere */
 } cfpq_stats;
 
 /* ABI version of the loaded library (CFPQ_ABI_VERSION). */
@@ -249,7 +251,8 @@ CFPQ_API cfpq_status cfpq_single_path_workspace_bytes(const cfpq_graph* graph, c
  * overwritten.  max_iters: loop cap, 0 = Theorem 3's bound.  Synchronises
  * `stream`.  Returns CFPQ_OK, CFPQ_ENOTCONV (cap reached: every stored length
  * is still a valid path length), CFPQ_ERANGE, CFPQ_EINVAL, CFPQ_ENOMEM or
- * CFPQ_EDEVICE.  stats: iterations, Boolean products, device time.
+ * CFPQ_EDEVICE.  stats: iterations, Boolean products, device time, the
+ * min-plus kernel's terms (minplus_terms) and summed time (product_ms).
  */
 CFPQ_API cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* grammar, int64_t max_iters,
                                       void* stream, void* d_workspace, size_t workspace_bytes, uint64_t* d_result,

@@ -75,7 +75,8 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("products", ctypes.c_int64), ("bitops", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("product_ms", ctypes.c_double), ("path_used", ctypes.c_int32),
-                ("converged", ctypes.c_int32), ("sparse_products", ctypes.c_int64), ("delta_products", ctypes.c_int64)]
+                ("converged", ctypes.c_int32), ("sparse_products", ctypes.c_int64), ("delta_products", ctypes.c_int64),
+                ("minplus_terms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

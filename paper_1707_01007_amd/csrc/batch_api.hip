@@ -356,6 +356,7 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
             st.converged = conv ? 1 : 0;
             st.sparse_products = 0;
             st.delta_products = 0;
+            st.minplus_terms = 0.0;
         }
     }
     if (!all_conv) return fail(CFPQ_ENOTCONV, "max_iters reached before the fixpoint in some instance");

@@ -631,6 +631,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                         static_cast<double>(L.npad) * static_cast<double>(products - sparse_products);
         stats->sparse_products = sparse_products;
         stats->delta_products = delta_products;
+        stats->minplus_terms = 0.0;
         stats->device_ms = ms;
         stats->product_ms = product_ms;
         stats->path_used = p.path;

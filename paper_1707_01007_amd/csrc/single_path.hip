@@ -67,7 +67,7 @@ __global__ void delta_kernel(const uint64_t* __restrict__ Y, const uint64_t* __r
 __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict__ D, const uint64_t* __restrict__ XB,
                                                       const uint64_t* __restrict__ XC, const uint32_t* LB,
                                                       const uint32_t* LC, uint32_t* LA, int64_t W, int64_t npad,
-                                                      int32_t kchunks) {
+                                                      int32_t kchunks, unsigned long long* cells) {
     const int64_t tiles = W;  // tiles per side (64 cells each)
     const int64_t ti = blockIdx.x / tiles, tj = blockIdx.x % tiles;
     const int64_t i0 = ti * 64, jw = tj;  // j0 = 64 * jw
@@ -78,6 +78,7 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
     // the tile's new cells
     const uint64_t dword = t < 64 ? D[(i0 + t) * W + jw] : 0;
     if (!__syncthreads_or(dword != 0)) return;
+    int32_t done_chunks = 0;
     const int tx = t & 15, ty = t >> 4;
     uint32_t acc[4][4];
 #pragma unroll
@@ -102,6 +103,7 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
         const bool skip = !any_b || !any_c;
         __syncthreads();  // every thread has read the flags before they are reset
         if (skip) continue;  // uniform
+        ++done_chunks;
         // stage: 64 x 32 of L_B (rows i, cols k) and 32 x 64 of L_C (rows k, cols j)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -129,6 +131,7 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
         }
         __syncthreads();
     }
+    if (t == 0 && done_chunks) atomicAdd(cells, static_cast<unsigned long long>(done_chunks) * 32 * 64 * 64);
     // new cells only: min with what an earlier rule of this loop stored
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -268,13 +271,22 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
     uint64_t* D = reinterpret_cast<uint64_t*>(ws + p.off_delta);
     const cfpq_edge* d_edges = graph->edges;
 
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, mp0 = nullptr, mp1 = nullptr;
     CFPQ_HIP(hipEventCreate(&ev0));
     CFPQ_HIP(hipEventCreate(&ev1));
+    CFPQ_HIP(hipEventCreate(&mp0));
+    CFPQ_HIP(hipEventCreate(&mp1));
     struct EvGuard {
-        hipEvent_t a, b;
-        ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); }
-    } guard{ev0, ev1};
+        hipEvent_t a, b, c, d;
+        ~EvGuard() {
+            hipEventDestroy(a);
+            hipEventDestroy(b);
+            hipEventDestroy(c);
+            hipEventDestroy(d);
+        }
+    } guard{ev0, ev1, mp0, mp1};
+    auto* d_cells = reinterpret_cast<unsigned long long*>(d_bad + 2);  // in the same 256-byte block
+    double minplus_ms = 0.0;
     CFPQ_HIP(hipMemcpyAsync(d_term_off, term_off.data(), term_off.size() * 4, hipMemcpyHostToDevice, s));
     CFPQ_HIP(hipMemcpyAsync(d_term_lhs, term_lhs.data(), term_lhs.size() * 4, hipMemcpyHostToDevice, s));
     if (!graph->edges_on_device && graph->n_edges > 0) {
@@ -283,7 +295,7 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
                                 hipMemcpyHostToDevice, s));
         d_edges = dst;
     }
-    CFPQ_HIP(hipMemsetAsync(d_bad, 0, 4, s));
+    CFPQ_HIP(hipMemsetAsync(d_bad, 0, 16, s));
     CFPQ_HIP(hipMemsetAsync(d_overflow, 0, 4, s));
     CFPQ_HIP(hipEventRecord(ev0, s));
     CFPQ_HIP(launch_zero(X, mw * n_nt, s));
@@ -333,14 +345,16 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
                 Y + a * mw, X + a * mw, D + a * mw, static_cast<int64_t>(mw));
             CFPQ_HIP(hipGetLastError());
         }
+        CFPQ_HIP(hipEventRecord(mp0, s));
         for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
             const auto& br = grammar->bin_rules[r];
             if (!flags[br.lhs]) continue;
             minplus_kernel<<<dim3(static_cast<unsigned>(L.W * L.W)), dim3(256), 0, s>>>(
                 D + br.lhs * mw, X + br.left * mw, X + br.right * mw, d_lengths + br.left * lmat,
-                d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, kchunks);
+                d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, kchunks, d_cells);
             CFPQ_HIP(hipGetLastError());
         }
+        CFPQ_HIP(hipEventRecord(mp1, s));
         for (int32_t a = 0; a < n_nt; ++a) {
             if (!flags[a]) continue;
             check_new_cells_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 4096)), dim3(256), 0, s>>>(
@@ -350,6 +364,9 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
         }
         CFPQ_HIP(hipMemcpyAsync(&overflow, d_overflow, 4, hipMemcpyDeviceToHost, s));
         CFPQ_HIP(hipStreamSynchronize(s));
+        float mp_ms = 0.f;
+        CFPQ_HIP(hipEventElapsedTime(&mp_ms, mp0, mp1));
+        minplus_ms += mp_ms;
         if (overflow) break;
     }
     CFPQ_HIP(hipEventRecord(ev1, s));
@@ -357,13 +374,17 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
     float ms = 0.f;
     CFPQ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     if (stats) {
+        unsigned long long cells = 0;
+        CFPQ_HIP(hipMemcpy(&cells, d_cells, 8, hipMemcpyDeviceToHost));
         std::memset(stats, 0, sizeof(*stats));
         stats->iterations = iters;
         stats->products = products;
         stats->bitops = 2.0 * static_cast<double>(L.npad) * L.npad * L.npad * static_cast<double>(products);
         stats->device_ms = ms;
+        stats->product_ms = minplus_ms;
         stats->path_used = CFPQ_PATH_BITS;
         stats->converged = converged ? 1 : 0;
+        stats->minplus_terms = static_cast<double>(cells);
     }
     if (overflow) return fail(CFPQ_ERANGE, "a path length reached 2^31 - 1");
     if (!converged) return fail(CFPQ_ENOTCONV, "max_iters reached before the fixpoint");
