@@ -192,6 +192,53 @@ def bench_conjunctive(cfpq, torch, n=8192, steps=3):
             "Gbitop_per_s": round(st["bitops"] / t / 1e9, 1)}
 
 
+def bench_small_configs(cfpq, torch, reps=5):
+    """The two small workloads: the two-cycle graph with a^n b^n (126 nodes,
+    launch/latency bound: 8065 loops under Algorithm 1's simultaneous step,
+    4033 in place) and the 4096-node hierarchy with same-generation, both
+    reversed and as generated.  Median of `reps` closures each, edges on the
+    device, default options (captured loops)."""
+    import statistics
+    from workloads import configs
+    out = {}
+    cases = [("two_cycles_anbn_inplace", configs.config1(), "inplace"),
+             ("two_cycles_anbn_jacobi", configs.config1(), "jacobi"),
+             ("hierarchy4096_samegen", configs.config2(), "inplace"),
+             ("hierarchy4096_rev_samegen", configs.config2(reverse=True), "inplace")]
+    for name, inst, sched in cases:
+        e = torch.from_numpy(inst.edges).cuda()
+        res = cfpq.closure(inst.n, e, inst.grammar, schedule=sched)
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = cfpq.closure(inst.n, e, inst.grammar, schedule=sched)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        t = statistics.median(times)
+        loops = res.stats["iterations"]
+        out[name] = {"n": inst.n, "ms": round(t * 1e3, 3), "loops": loops,
+                     "us_per_loop": round(t * 1e6 / max(loops, 1), 2),
+                     "Gbitop_per_s": round(res.stats["bitops"] / t / 1e9, 1)}
+    print(f"[bench] small configs: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def bench_end_to_end(cfpq, torch, inst, steps=3):
+    """The headline closure with host edges: the edge upload (PCIe) and its
+    validation on the host are inside the timed region."""
+    res = cfpq.closure(inst.n, inst.edges, inst.grammar, hybrid=0)
+    out = res.bits.view(-1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = cfpq.closure(inst.n, inst.edges, inst.grammar, hybrid=0, out=out)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    return {"ms_per_closure": round(t * 1e3, 3), "Gbitop_per_s": round(res.stats["bitops"] / t / 1e9, 1),
+            "edges_from": "host"}
+
+
 def _pct(xs, q):
     import numpy as np
     return round(float(np.percentile(np.asarray(xs), q)), 3) if xs else None
@@ -370,6 +417,9 @@ def main():
         "roofline": roof,
     }
     line["hybrid"] = bench_hybrid(cfpq, torch, inst, edges, out, args, wall / args.steps)
+    line["end_to_end"] = bench_end_to_end(cfpq, torch, inst)
+    if not args.no_next:
+        line["small_configs"] = bench_small_configs(cfpq, torch)
     if not args.no_next:
         line["single_path"] = bench_single_path(cfpq, torch)
         line["conjunctive"] = bench_conjunctive(cfpq, torch)

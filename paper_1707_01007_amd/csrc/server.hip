@@ -161,10 +161,13 @@ struct cfpq_server {
 namespace cfpq {
 namespace {
 
-// Closure options of a lane request: the library defaults (hybrid choice on).
+// Closure options of a lane request: the library defaults (hybrid choice on)
+// with the dense kernel fixed, so that the workspace sized at submit cannot
+// change with the autotuner's table before the request runs.
 cfpq_options lane_options() {
     cfpq_options o;
     cfpq_default_options(&o);
+    o.path = CFPQ_PATH_MFMA;  // requests are limited to 2^19 nodes
     return o;
 }
 
