@@ -371,11 +371,14 @@ CFPQ_API cfpq_status cfpq_batch_workspace_bytes(int32_t n_instances, const cfpq_
  * computed together.  Instances with a padded side of at most 512 run their
  * whole fixpoint in one workgroup each (VALU product); larger ones share a
  * per-loop work list of 256 x 256 int8-MFMA tiles, with `opt->capture` loops
- * (0 = 8) per captured HIP graph.  Results are bit-identical to
- * cfpq_closure on each instance alone.  opt: schedule must be INPLACE and
- * warm_start 0; dirty_worklist, capture and max_iters apply to every
- * instance; path, tile, hybrid and profile are ignored.  Instances are limited
- * to 2^19 nodes.
+ * (0 = 8) per captured HIP graph.  With opt->hybrid AUTO (the default), a
+ * rule of a larger instance whose left operand heads no binary rule (its
+ * matrix is fixed by the edges) runs as row gathers instead of tiles when the
+ * graph has at most npad^2 / 16 edges; OFF keeps every rule on the tiles.
+ * Results are bit-identical to cfpq_closure on each instance alone.  opt:
+ * schedule must be INPLACE and warm_start 0; dirty_worklist, capture,
+ * hybrid and max_iters apply to every instance; path, tile and profile are
+ * ignored.  Instances are limited to 2^19 nodes.
  * stats: NULL or n_instances entries (device_ms is the whole batch's time).
  * Returns CFPQ_OK, CFPQ_ENOTCONV (some instance hit max_iters; all results
  * are sound), CFPQ_EINVAL (message names the instance), CFPQ_ENOMEM or

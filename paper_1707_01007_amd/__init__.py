@@ -253,12 +253,14 @@ def conjunctive_closure(n: int, edges, grammar, *, path="auto", schedule="inplac
 
 
 def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=None, stream=None,
-                  outs=None, workspace=None, allow_partial=False):
+                  outs=None, workspace=None, allow_partial=False, hybrid=None):
     """Closure of many independent instances in one call (``cfpq_batch_closure``).
 
     ``instances`` is a sequence of (n, edges, grammar); edges on the host or as
     int32 CUDA tensors.  Returns one ``Result`` per instance (each with its own
-    device result buffer, or the buffers in ``outs``)."""
+    device result buffer, or the buffers in ``outs``).  ``hybrid`` (0/1,
+    default the library's: 1) lets rules of larger instances with an
+    edge-matrix left operand run as row gathers."""
     torch = _torch()
     L = lib()
     device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -279,7 +281,7 @@ def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=No
         out = outs[i] if outs is not None else torch.empty(words, dtype=torch.int64, device=device)
         results_out.append(out)
         arr[i] = _abi.Instance(graph, ctypes.pointer(g), ctypes.c_void_p(out.data_ptr()))
-    opt = _options("auto", "inplace", dirty, max_iters, False, 0, capture)
+    opt = _options("auto", "inplace", dirty, max_iters, False, 0, capture, hybrid=hybrid)
     need = ctypes.c_size_t(0)
     _abi.check(L.cfpq_batch_workspace_bytes(k, arr, ctypes.byref(opt), ctypes.byref(need)))
     if workspace is None or workspace.numel() < need.value:

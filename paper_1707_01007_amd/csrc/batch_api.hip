@@ -16,13 +16,13 @@ namespace {
 struct BatchPlan {
     int32_t n = 0;
     std::vector<SlotDesc> descs;
-    std::vector<int32_t> rules, trans, term, large, small8, small16, all_ids;
+    std::vector<int32_t> rules, modes, trans, term, large, small8, small16, all_ids;
     std::vector<int64_t> edge_begin;
     std::vector<size_t> edge_copy_off;  // per slot: byte offset in the edge region, or SIZE_MAX (device edges)
     int64_t total_edges = 0;
     int32_t large_rules = 0, large_trans = 0;
     bool any_device_edges = false;
-    size_t off_descs = 0, off_states = 0, off_rules = 0, off_go = 0, off_trans = 0, off_term = 0;
+    size_t off_descs = 0, off_states = 0, off_rules = 0, off_go = 0, off_mode = 0, off_trans = 0, off_term = 0;
     size_t off_jobs = 0, off_tjobs = 0, off_large = 0, off_small8 = 0, off_small16 = 0, off_all = 0;
     size_t off_edge_begin = 0, off_es = 0, off_edges = 0, off_tt = 0, total = 0;
     std::vector<size_t> tt_off;  // per slot: byte offset of its transposes (large) in the tt region
@@ -74,17 +74,19 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
         d.trans_off = static_cast<int32_t>(p.trans.size());
         int32_t n_right = 0;
         std::vector<int32_t> tr(d.n_nt, -1);
+        std::vector<int32_t> md(d.n_rules, kModeDense);
         if (d.kind == kSlotLarge) {
-            for (int32_t r = 0; r < d.n_rules; ++r) {
-                const int32_t c = gr->bin_rules[r].right;
-                if (tr[c] < 0) tr[c] = n_right++;
-            }
+            if (o.hybrid == CFPQ_HYBRID_AUTO)
+                for (int32_t r = 0; r < d.n_rules; ++r)
+                    md[r] = engine_rule_mode(gr->bin_rules, d.n_rules, r, g.n_edges, L.npad);
+            n_right = engine_right_slots(gr->bin_rules, d.n_rules, md.data(), d.n_nt, tr.data());
             p.tt_off[i] = tt_bytes;
             tt_bytes += static_cast<size_t>(n_right) * L.mat_words * 8;
             p.large_rules += d.n_rules;
             p.large_trans += n_right;
         }
         p.trans.insert(p.trans.end(), tr.begin(), tr.end());
+        p.modes.insert(p.modes.end(), md.begin(), md.end());
         p.edge_begin[i + 1] = p.edge_begin[i] + g.n_edges;
         if (g.edges_on_device) {
             p.any_device_edges = true;
@@ -116,6 +118,7 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
     p.off_states = take(sizeof(SlotState) * n);
     p.off_rules = take(4 * p.rules.size());
     p.off_go = take(4 * (p.rules.size() / 3));
+    p.off_mode = take(4 * p.modes.size());
     p.off_trans = take(4 * p.trans.size());
     p.off_term = take(4 * p.term.size());
     p.off_jobs = take(sizeof(Job) * std::max(p.large_rules, 1));
@@ -139,6 +142,7 @@ cfpq_status validate_batch(int32_t n, const cfpq_instance* inst, const cfpq_opti
         return fail(CFPQ_EINVAL, "the batched engine runs the in-place schedule only");
     if (o.max_iters < 0 || o.capture < 0) return fail(CFPQ_EINVAL, "negative option");
     if (o.warm_start != 0) return fail(CFPQ_EINVAL, "the batched engine has no warm start");
+    if (o.hybrid != CFPQ_HYBRID_OFF && o.hybrid != CFPQ_HYBRID_AUTO) return fail(CFPQ_EINVAL, "unknown hybrid mode");
     for (int32_t i = 0; i < n; ++i) {
         cfpq_status st = validate_grammar(inst[i].grammar);
         if (st != CFPQ_OK) return fail(st, "instance " + std::to_string(i) + ": " + cfpq_last_error());
@@ -205,6 +209,7 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
     b.states = reinterpret_cast<SlotState*>(ws + p.off_states);
     b.rules_tab = reinterpret_cast<int32_t*>(ws + p.off_rules);
     b.go_tab = reinterpret_cast<int32_t*>(ws + p.off_go);
+    b.mode_tab = reinterpret_cast<int32_t*>(ws + p.off_mode);
     b.trans_tab = reinterpret_cast<int32_t*>(ws + p.off_trans);
     b.term_tab = reinterpret_cast<int32_t*>(ws + p.off_term);
     b.jobs = reinterpret_cast<Job*>(ws + p.off_jobs);
@@ -251,6 +256,7 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
     CFPQ_HIP(h2d(b.descs, p.descs.data(), sizeof(SlotDesc) * p.descs.size()));
     CFPQ_HIP(h2d(b.states, hstates.data(), sizeof(SlotState) * hstates.size()));
     CFPQ_HIP(h2d(b.rules_tab, p.rules.data(), 4 * p.rules.size()));
+    CFPQ_HIP(h2d(b.mode_tab, p.modes.data(), 4 * p.modes.size()));
     CFPQ_HIP(h2d(b.trans_tab, p.trans.data(), 4 * p.trans.size()));
     CFPQ_HIP(h2d(b.term_tab, p.term.data(), 4 * p.term.size()));
     CFPQ_HIP(h2d(b.large_ids, p.large.data(), 4 * p.large.size()));

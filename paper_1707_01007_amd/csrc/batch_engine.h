@@ -6,8 +6,11 @@
 //    whole fixpoint in a single resident kernel launch (VALU product with the
 //    right operand staged in LDS, change flags in LDS);
 //  * large: every loop, a plan kernel turns the dirty rules of all running
-//    large slots into a work list of 256 x 256 MFMA tiles, a persistent kernel
-//    pulls tiles from an atomic counter, transposes of the right operands that
+//    large slots into a work list -- 256 x 256 MFMA tiles for dense rules, and
+//    blocks of four rows for rules whose left operand is derived from terminal
+//    rules only (a sparse edge matrix: the row-gather product reads just the
+//    rows of C its bits select) -- a persistent kernel pulls items from an
+//    atomic counter, transposes of the right operands of dense rules that
 //    changed are rebuilt the same way, and a finish kernel counts the loop and
 //    retires slots that reached their fixpoint.  The loop is captured into a
 //    HIP graph once; which slots take part is data, so the same graph serves a
@@ -76,6 +79,7 @@ struct EngineBuffers {
     int32_t* trans_tab = nullptr;
     int32_t* term_tab = nullptr;
     int32_t* go_tab = nullptr;
+    int32_t* mode_tab = nullptr;  // per rule (indexed like go_tab): kModeDense or kModeRows
     Job* jobs = nullptr;
     Job* tjobs = nullptr;
     int32_t* large_ids = nullptr;
@@ -83,6 +87,29 @@ struct EngineBuffers {
     int64_t* edge_begin = nullptr;
     EngineState* es = nullptr;
 };
+
+// Product mode of rule r of a large slot: ROWS when its left operand heads
+// no binary rule (its matrix is the edge matrix of its terminals, fixed and
+// sparse: at most n_edges bits) and the graph has at most npad^2 / 16 edges;
+// else the dense MFMA tiles.  Every mode gives the same bits.
+inline int32_t engine_rule_mode(const cfpq_bin_rule* rules, int32_t n_rules, int32_t r, int64_t n_edges,
+                                int64_t npad) {
+    const int32_t b = rules[r].left;
+    for (int32_t q = 0; q < n_rules; ++q)
+        if (rules[q].lhs == b) return kModeDense;
+    return n_edges <= npad * npad / 16 ? kModeRows : kModeDense;
+}
+
+// Transpose slots of a large slot: the right operands of its dense rules.
+// Fills trans[a] (slot or -1, n_nt entries) and returns the slot count.
+inline int32_t engine_right_slots(const cfpq_bin_rule* rules, int32_t n_rules, const int32_t* modes, int32_t n_nt,
+                                  int32_t* trans) {
+    for (int32_t a = 0; a < n_nt; ++a) trans[a] = -1;
+    int32_t n_right = 0;
+    for (int32_t r = 0; r < n_rules; ++r)
+        if (modes[r] == kModeDense && trans[rules[r].right] < 0) trans[rules[r].right] = n_right++;
+    return n_right;
+}
 
 // ---- launchers (batch_engine.hip) ----
 hipError_t engine_zero(const EngineBuffers& b, const int32_t* ids, int32_t count, hipStream_t s);

@@ -1,6 +1,7 @@
 // Kernels of the batched closure engine (see batch_engine.h).
 #include "batch_engine.h"
 #include "mfma_tile.h"
+#include "rowor_device.h"
 
 namespace cfpq {
 namespace {
@@ -205,8 +206,8 @@ __device__ void scan2(int32_t* sa, int32_t* sb, int32_t& a, int32_t& b, int32_t*
 // biggest tiles are handed out first.
 __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
                                                           const int32_t* __restrict__ rules_tab, int32_t* go_tab,
-                                                          Job* jobs, EngineState* es,
-                                                          const int32_t* __restrict__ large_ids) {
+                                                          const int32_t* __restrict__ mode_tab, Job* jobs,
+                                                          EngineState* es, const int32_t* __restrict__ large_ids) {
     __shared__ int32_t sa[256], sb[256];
     const int t = threadIdx.x;
     const int n_large = es->n_large;
@@ -235,10 +236,10 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             const int go = (!d.dirty || st->iterations == 0 || st->changed_prev[rb] || st->changed_prev[rc]) ? 1 : 0;
             go_tab[d.rule_off + r] = go;
             launched += go;
+            if (go) my_items += mode_tab[d.rule_off + r] == kModeRows ? (d.n + 3) / 4 : dim * dim;
         }
         st->products += launched;
         my_jobs += launched;
-        my_items += launched * dim * dim;
     }
     scan2(sa, sb, my_jobs, my_items, &es->n_jobs, &es->total_items);
     if (t == 0) es->next_item = 0;
@@ -250,15 +251,49 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
         for (int r = 0; r < d.n_rules; ++r) {
             if (!go_tab[d.rule_off + r]) continue;
             jobs[my_jobs++] = Job{slot, r, my_items, dim};
-            my_items += dim * dim;
+            my_items += mode_tab[d.rule_off + r] == kModeRows ? (d.n + 3) / 4 : dim * dim;
         }
     }
 }
 
-// Persistent product kernel: workgroups pull tiles from the loop's work list.
+// Row-gather item: rows 4 item .. 4 item + 3 of A |= B x C (one per
+// wavefront), C read in place; other items of the loop may write the same
+// rows (several rules with one head), so new bits are OR-ed atomically.
+__device__ void engine_rows_item(const SlotDesc& d, const uint64_t* Bm, const uint64_t* Cm, uint64_t* Am, int local,
+                                 int32_t* changed) {
+    constexpr int WPL = 4;
+    const int lane = threadIdx.x & 63;
+    const int64_t row = static_cast<int64_t>(local) * 4 + (threadIdx.x >> 6);
+    if (row >= d.n) return;  // whole wavefront
+    const int64_t W = d.W;
+    const int32_t kwords = (d.n + 63) / 64;
+    const uint64_t* brow = Bm + row * W;
+    uint64_t* arow = Am + row * W;
+    bool ch = false;
+    for (int64_t c0 = 0; c0 < W; c0 += 64 * WPL) {
+        uint32_t off[WPL];
+        rowor::lane_columns<WPL>(c0, W, lane, off);
+        uint64_t acc[WPL];
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) acc[q] = 0;
+        rowor::gather_rows<WPL>(brow, 0, kwords, Cm, W, off, acc, lane);
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) {
+            if (c0 + lane + 64 * q < W && (acc[q] & ~arow[off[q]]) != 0) {
+                const unsigned long long prev = atomicOr(reinterpret_cast<unsigned long long*>(arow + off[q]),
+                                                         static_cast<unsigned long long>(acc[q]));
+                if (acc[q] & ~prev) ch = true;
+            }
+        }
+    }
+    if (__ballot(ch) != 0 && lane == 0) atomicOr(changed, 1);
+}
+
+// Persistent product kernel: workgroups pull items from the loop's work list.
 __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
                                                              const int32_t* __restrict__ rules_tab,
                                                              const int32_t* __restrict__ trans_tab,
+                                                             const int32_t* __restrict__ mode_tab,
                                                              const Job* __restrict__ jobs, EngineState* es) {
     __shared__ int32_t item_s;
     const int n_jobs = es->n_jobs;
@@ -274,6 +309,11 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
         const int r = d.rule_off + jb.what;
         const int ra = rules_tab[3 * r], rb = rules_tab[3 * r + 1], rc = rules_tab[3 * r + 2];
         const int local = item - jb.item_begin;
+        if (mode_tab[r] == kModeRows) {
+            const size_t mw = static_cast<size_t>(d.npad) * d.W;
+            engine_rows_item(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, local, &states[jb.slot].changed[ra]);
+            continue;
+        }
         const size_t mdw = static_cast<size_t>(d.npad) * d.W * 2;
         const uint32_t* Bm = reinterpret_cast<const uint32_t*>(d.T) + rb * mdw;
         const uint32_t* CT = reinterpret_cast<const uint32_t*>(d.TT) + trans_tab[d.trans_off + rc] * mdw;
@@ -406,14 +446,14 @@ hipError_t engine_resident(const EngineBuffers& b, const int32_t* ids, int32_t c
 }
 
 hipError_t engine_plan(const EngineBuffers& b, hipStream_t s) {
-    engine_plan_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab, b.go_tab, b.jobs, b.es,
-                                                     b.large_ids);
+    engine_plan_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab, b.go_tab, b.mode_tab, b.jobs,
+                                                     b.es, b.large_ids);
     return hipGetLastError();
 }
 
 hipError_t engine_products(const EngineBuffers& b, int32_t grid, hipStream_t s) {
     engine_product_kernel<<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab,
-                                                                                b.trans_tab, b.jobs, b.es);
+                                                                                b.trans_tab, b.mode_tab, b.jobs, b.es);
     return hipGetLastError();
 }
 

@@ -60,6 +60,7 @@ struct Request {
     bool small = false;
     bool lane = false;  // runs on a lane thread (hybrid closure)
     int32_t n_right = 0;
+    std::vector<int32_t> modes;  // per binary rule: engine product mode (large slots)
     size_t footprint = 0;
     // life cycle
     int32_t slot = -1;
@@ -212,8 +213,8 @@ size_t footprint_of(const Request& r) {
     } while (0)
 
 // Build the descriptor and tables of an admitted request in slot `slot`.
-void fill_slot(cfpq_server* srv, Request& r, SlotDesc& d, std::vector<int32_t>& rules, std::vector<int32_t>& trans,
-               std::vector<int32_t>& term) {
+void fill_slot(cfpq_server* srv, Request& r, SlotDesc& d, std::vector<int32_t>& rules, std::vector<int32_t>& modes,
+               std::vector<int32_t>& trans, std::vector<int32_t>& term) {
     const int32_t s = r.slot;
     std::memset(&d, 0, sizeof(d));
     char* base = srv->arena_base + r.arena_off;
@@ -239,12 +240,12 @@ void fill_slot(cfpq_server* srv, Request& r, SlotDesc& d, std::vector<int32_t>& 
         rules[3 * q + 1] = r.bin[q].left;
         rules[3 * q + 2] = r.bin[q].right;
     }
+    modes.assign(kSrvMaxRules, kModeDense);
+    std::copy(r.modes.begin(), r.modes.end(), modes.begin());
     d.trans_off = s * CFPQ_MAX_NONTERMINALS;
     trans.assign(CFPQ_MAX_NONTERMINALS, -1);
-    int32_t nr = 0;
-    if (!r.small)
-        for (const auto& br : r.bin)
-            if (trans[br.right] < 0) trans[br.right] = nr++;
+    if (!r.small) engine_right_slots(r.bin.data(), static_cast<int32_t>(r.bin.size()), r.modes.data(), r.n_nt,
+                                     trans.data());
     d.n_terminals = r.n_terminals;
     d.term_off = s * kTermStride;
     d.term_lhs_off = d.term_off + kSrvMaxTerminals + 1;
@@ -268,10 +269,12 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
         std::vector<int64_t> ebegin(1, 0);
         for (Request* r : admitted) {
             SlotDesc d;
-            std::vector<int32_t> rules, trans, term;
-            fill_slot(srv, *r, d, rules, trans, term);
+            std::vector<int32_t> rules, modes, trans, term;
+            fill_slot(srv, *r, d, rules, modes, trans, term);
             SRV_HIP(hipMemcpyAsync(srv->b.descs + r->slot, &d, sizeof(d), hipMemcpyHostToDevice, s));
             SRV_HIP(hipMemcpyAsync(srv->b.rules_tab + 3 * d.rule_off, rules.data(), rules.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+            SRV_HIP(hipMemcpyAsync(srv->b.mode_tab + d.rule_off, modes.data(), modes.size() * 4,
                                    hipMemcpyHostToDevice, s));
             SRV_HIP(hipMemcpyAsync(srv->b.trans_tab + d.trans_off, trans.data(), trans.size() * 4,
                                    hipMemcpyHostToDevice, s));
@@ -584,6 +587,7 @@ cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, c
     const size_t o_descs = take(sizeof(SlotDesc) * S), o_states = take(sizeof(SlotState) * S);
     const size_t o_rules = take(4 * 3 * static_cast<size_t>(kSrvMaxRules) * S);
     const size_t o_go = take(4 * static_cast<size_t>(kSrvMaxRules) * S);
+    const size_t o_mode = take(4 * static_cast<size_t>(kSrvMaxRules) * S);
     const size_t o_trans = take(4 * static_cast<size_t>(CFPQ_MAX_NONTERMINALS) * S);
     const size_t o_term = take(4 * static_cast<size_t>(kTermStride) * S);
     const size_t o_jobs = take(sizeof(Job) * kSrvMaxRules * S);
@@ -603,6 +607,7 @@ cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, c
     srv->b.states = reinterpret_cast<SlotState*>(base + o_states);
     srv->b.rules_tab = reinterpret_cast<int32_t*>(base + o_rules);
     srv->b.go_tab = reinterpret_cast<int32_t*>(base + o_go);
+    srv->b.mode_tab = reinterpret_cast<int32_t*>(base + o_mode);
     srv->b.trans_tab = reinterpret_cast<int32_t*>(base + o_trans);
     srv->b.term_tab = reinterpret_cast<int32_t*>(base + o_term);
     srv->b.jobs = reinterpret_cast<Job*>(base + o_jobs);
@@ -679,12 +684,13 @@ cfpq_status cfpq_server_submit(cfpq_server* srv, const cfpq_graph* graph, const 
     r->L = layout_for(graph->n_nodes);
     r->small = r->L.npad <= kSmallMaxPad;
     r->lane = srv->cfg.hybrid_lanes > 0 && r->L.npad >= kHybridMinRows;
-    std::vector<int32_t> seen(r->n_nt, 0);
-    for (const auto& b : r->bin)
-        if (!seen[b.right]) {
-            seen[b.right] = 1;
-            ++r->n_right;
-        }
+    const int32_t nb = static_cast<int32_t>(r->bin.size());
+    r->modes.assign(nb, kModeDense);
+    if (!r->small && !r->lane) {
+        for (int32_t q = 0; q < nb; ++q) r->modes[q] = engine_rule_mode(r->bin.data(), nb, q, r->n_edges, r->L.npad);
+        std::vector<int32_t> tr(r->n_nt);
+        r->n_right = engine_right_slots(r->bin.data(), nb, r->modes.data(), r->n_nt, tr.data());
+    }
     r->footprint = footprint_of(*r);
     if (r->footprint > srv->arena_size)
         return fail(CFPQ_ENOMEM, "request needs " + std::to_string(r->footprint) +

@@ -49,10 +49,11 @@ def _mixed_instances():
     return insts
 
 
-def test_mixed_batch_matches_oracle(cfpq):
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_mixed_batch_matches_oracle(cfpq, hybrid):
     insts = _mixed_instances()
-    _say("mixed batch", len(insts), "instances, sizes", sorted(i.n for i in insts)[-5:])
-    res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts])
+    _say("mixed batch", len(insts), "instances, sizes", sorted(i.n for i in insts)[-5:], "hybrid", hybrid)
+    res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], hybrid=hybrid)
     for inst, r in zip(insts, res):
         want = worklist.closure(inst.n, inst.edges, inst.grammar)
         assert np.array_equal(cfpq.result_bits(r), want), inst.tag
@@ -121,3 +122,29 @@ def test_batch_capture_depths(cfpq, capture):
     res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], capture=capture)
     for inst, r in zip(insts, res):
         assert np.array_equal(cfpq.result_bits(r), worklist.closure(inst.n, inst.edges, inst.grammar)), inst.tag
+
+
+def test_batch_row_gather_rules(cfpq):
+    """Larger instances whose edge-matrix rules run as row gathers (hybrid on)
+    against the oracle: ragged sizes past several 256-row tiles, a node with
+    thousands of out-edges (one long row), two rules with one head, and a
+    graph too dense for the gather (tiles only); the same bits with hybrid
+    off."""
+    insts = []
+    n, e = graphs.erdos_renyi(1000, 3000, 41, labels=2)
+    insts.append(configs.Instance(n, e, grammars.dyck(), "er1000"))
+    n, e = graphs.erdos_renyi(777, 2500, 42, labels=2)
+    star = np.array([[5, 0, j] for j in range(0, 777, 1)], dtype=np.int32)
+    insts.append(configs.Instance(n, np.concatenate([e, star]), grammars.dyck(), "er777_star"))
+    n, e = graphs.hierarchy(2100, 3, roots=2, reverse=False)
+    insts.append(configs.Instance(n, e, grammars.same_generation(), "hier2100"))
+    n, e = graphs.erdos_renyi(600, 40000, 43, labels=2)
+    insts.append(configs.Instance(n, e, grammars.dyck(), "er600_dense"))
+    _say("row-gather batch", [i.tag for i in insts])
+    on = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], hybrid=1)
+    off = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], hybrid=0)
+    for inst, a, b in zip(insts, on, off):
+        want = worklist.closure(inst.n, inst.edges, inst.grammar)
+        assert np.array_equal(cfpq.result_bits(a), want), inst.tag
+        assert np.array_equal(cfpq.result_bits(b), want), inst.tag
+        assert a.stats["converged"] == 1
