@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "closure Gbitop/s at n=16384; batched queries/s + p50/p99 latency vs plain"
 # MI355X peaks used for the roofline fraction.
 PEAK_INT8_TOPS = 5000.0  # dense int8 MFMA, 5.0 POP/s (1 MAC = 2 ops = AND + OR here)
+PEAK_FP4_TOPS = 10100.0  # dense fp4 (e2m1) MFMA, 10.1 PFLOP/s
 # VALU: 256 CUs x 64 lanes per clock x 2.4 GHz x 64 bit-operations per v_and_or_b32
 PEAK_VALU_BITOPS_T = 256 * 64 * 2.4e9 * 64 / 1e12
 
@@ -323,7 +324,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=16384)
-    ap.add_argument("--path", default="auto", choices=["auto", "bits", "mfma"])
+    ap.add_argument("--path", default="auto", choices=["auto", "bits", "mfma", "fp4"])
     ap.add_argument("--schedule", default="inplace", choices=["inplace", "jacobi"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-closure section")
@@ -380,22 +381,24 @@ def main():
     bitops = sum(s["bitops"] for s in stats)
     products = sum(s["products"] for s in stats)
     prod_ms = sum(s["product_ms"] for s in stats)
-    path_used = {1: "bits", 2: "mfma"}[stats[-1]["path_used"]]
+    path_used = {1: "bits", 2: "mfma", 5: "fp4"}[stats[-1]["path_used"]]
     assert all(s["sparse_products"] == 0 for s in stats)
     npad = cfpq.padded_rows(inst.n)
     per_launch = 2.0 * npad ** 3
     achieved_t = per_launch / (prod_ms / products / 1e3) / 1e12 if products else 0.0
-    if path_used == "mfma":
-        roof = {"bound": "mfma", "achieved": round(achieved_t, 1), "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-                "frac": round(achieved_t / PEAK_INT8_TOPS, 4), "traffic": None}
+    if path_used in ("mfma", "fp4"):
+        peak = PEAK_FP4_TOPS if path_used == "fp4" else PEAK_INT8_TOPS
+        roof = {"bound": "mfma", "achieved": round(achieved_t, 1), "peak": peak, "unit": "TOP/s",
+                "frac": round(achieved_t / peak, 4), "traffic": None}
     else:
         roof = {"bound": "alu", "achieved": round(achieved_t, 1), "peak": round(PEAK_VALU_BITOPS_T, 1),
                 "unit": "TOP/s", "frac": round(achieved_t / PEAK_VALU_BITOPS_T, 4), "traffic": None}
-    if path_used == "mfma":
-        roof["traffic"] = profiled_traffic("mfma_product_er16384_dyck.md",
+    if path_used in ("mfma", "fp4"):
+        roof["traffic"] = profiled_traffic(f"{path_used}_product_er16384_dyck.md",
                                            ["paper_1707_01007_amd/csrc/mfma_tile.h",
                                             "paper_1707_01007_amd/csrc/kernels_mfma.hip"])
-    roof["kernel"] = "mfma_product_kernel" if path_used == "mfma" else "bits_product_kernel"
+    roof["kernel"] = {"mfma": "mfma_product_kernel<false>", "fp4": "mfma_product_kernel<true>"}.get(
+        path_used, "bits_product_kernel")
     roof["per_launch_bitops"] = per_launch
     line = {
         "metric": METRIC,
@@ -408,7 +411,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i8" if path_used == "mfma" else "u32",
+        "dtype": {"mfma": "i8", "fp4": "fp4"}.get(path_used, "u32"),
         "data": "synthetic",
         "config": {"workload": inst.tag, "n": inst.n, "edges": int(len(inst.edges)), "grammar": g.name,
                    "path": path_used, "schedule": args.schedule,

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define CFPQ_ABI_VERSION 2
+#define CFPQ_ABI_VERSION 3
 
 #if defined(__GNUC__)
 #define CFPQ_API __attribute__((visibility("default")))
@@ -87,13 +87,20 @@ typedef struct {
 #define CFPQ_MAX_NONTERMINALS 64
 #define CFPQ_MAX_NODES (1 << 20)
 
-/* Product kernels.  AUTO, BITS and MFMA compute the dense product (every
+/* Product kernels.  AUTO, BITS, MFMA and FP4 compute the dense product (every
  * word of both operands is read).  ROWS and COLS skip the zero entries of one
  * operand: ROWS forms row i of B x C as the OR of the rows C[k, :] for the set
  * bits k of B[i, :] (cost ~ nnz(B) rows of C); COLS does the same on the
  * transposed product (B x C)^T = C^T x B^T (cost ~ nnz(C) rows of B^T, plus
  * transposes).  All give identical bits. */
-enum { CFPQ_PATH_AUTO = 0, CFPQ_PATH_BITS = 1, CFPQ_PATH_MFMA = 2, CFPQ_PATH_ROWS = 3, CFPQ_PATH_COLS = 4 };
+enum {
+    CFPQ_PATH_AUTO = 0,
+    CFPQ_PATH_BITS = 1,  /* bit-packed VALU product (AND / OR-reduce) */
+    CFPQ_PATH_MFMA = 2,  /* int8 MFMA, int32 sums */
+    CFPQ_PATH_ROWS = 3,  /* row gathers by the set bits of B */
+    CFPQ_PATH_COLS = 4,  /* row gathers of the transposed product */
+    CFPQ_PATH_FP4 = 5    /* e2m1 (fp4) MFMA, fp32 sums */
+};
 /* Hybrid product choice of cfpq_closure (options.hybrid). */
 enum { CFPQ_HYBRID_OFF = 0, CFPQ_HYBRID_AUTO = 1 };
 enum { CFPQ_SCHEDULE_INPLACE = 0, CFPQ_SCHEDULE_JACOBI = 1 };
@@ -137,7 +144,7 @@ typedef struct {
                                 ROWS / COLS products are not counted */
     double device_ms;        /* device time from matrix initialisation to the last flag */
     double product_ms;       /* summed duration of the product kernels (options.profile), else 0 */
-    int32_t path_used;       /* CFPQ_PATH_BITS or CFPQ_PATH_MFMA (dense kernel), ROWS or COLS */
+    int32_t path_used;       /* CFPQ_PATH_BITS, MFMA or FP4 (dense kernel), ROWS or COLS */
     int32_t converged;       /* 1 if the fixpoint was reached */
     int64_t sparse_products; /* products of `products` that ran as ROWS or COLS */
     int64_t delta_products;  /* products of `products` with a delta operand: a rule A -> B C whose
@@ -203,11 +210,11 @@ CFPQ_API cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* g
  * value read is a subset of the final one).  path = any CFPQ_PATH_* (AUTO
  * picks the autotuned dense kernel); tile as in cfpq_options (0 = default).
  * *d_changed (device int32, required) is OR-ed with 1 when d_a gained a bit.
- * d_workspace may be NULL for BITS; MFMA (one transposed operand), ROWS (a
+ * d_workspace may be NULL for BITS; MFMA and FP4 (one transposed operand), ROWS (a
  * list of rows long enough to be split over several wavefronts) and COLS
  * (two transposed operands, the transposed product, the list) need
- * cfpq_product_workspace_bytes.  The MFMA path requires n_nodes <= 2^19
- * (int32 accumulation bound); larger sizes return CFPQ_EINVAL.  Every product
+ * cfpq_product_workspace_bytes.  The MFMA and FP4 paths require
+ * n_nodes <= 2^19 (exact int32 / fp32 sums); larger sizes return CFPQ_EINVAL.  Every product
  * kernel only reads rows and columns below n_nodes of its operands, which
  * must be zero beyond them (as in every matrix of the bit layout).
  */
@@ -298,7 +305,7 @@ CFPQ_API cfpq_status cfpq_conjunctive_workspace_bytes(const cfpq_graph* graph, c
 /*
  * Closure for a conjunctive grammar: grammar (terminal rules, one-conjunct
  * binary rules) plus n_conj_rules rules with any number of conjuncts.
- * opt: path AUTO, BITS or MFMA (dense products), schedule, dirty_worklist,
+ * opt: path AUTO, BITS, MFMA or FP4 (dense products), schedule, dirty_worklist,
  * tile and max_iters as for cfpq_closure; warm_start must be 0; hybrid,
  * capture and profile are ignored (host-driven loop).  d_result, stream,
  * workspace, stats and the return codes as for cfpq_closure.
@@ -311,24 +318,24 @@ CFPQ_API cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfp
 /* ------------------------------------------------------------------------
  * Autotuner: the fastest product kernel per size bucket.
  *
- * cfpq_autotune times every product variant (int8 MFMA; VALU with 8, 16 and
- * 32-word strips) on synthetic operands of the padded size for n_nodes and
- * records the fastest for the bucket ceil(log2(npad)) in a process-wide
- * table.  The AUTO path of cfpq_closure and cfpq_product then uses it (an
- * untuned bucket uses MFMA up to 2^19 nodes, else BITS).  All variants give
+ * cfpq_autotune times every product variant (fp4 and int8 MFMA; VALU with
+ * 8, 16 and 32-word strips) on synthetic operands of the padded size for
+ * n_nodes and records the fastest for the bucket ceil(log2(npad)) in a
+ * process-wide table.  The AUTO path of cfpq_closure and cfpq_product then
+ * uses it (an untuned bucket uses FP4 up to 2^19 nodes, else BITS).  All variants give
  * identical bits.  The environment variable CFPQ_TUNE_CACHE names a JSON file
  * (as written by cfpq_tune_save) loaded at first use.
  * ------------------------------------------------------------------------ */
 
 typedef struct {
     int32_t npad;              /* padded size the entry was measured at */
-    int32_t path;              /* CFPQ_PATH_MFMA or CFPQ_PATH_BITS */
+    int32_t path;              /* CFPQ_PATH_FP4, CFPQ_PATH_MFMA or CFPQ_PATH_BITS */
     int32_t tile;              /* BITS strip width (0 = default) */
     float ms;                  /* the chosen kernel's time per product */
     int32_t n_candidates;      /* entries used below (filled by cfpq_autotune only) */
-    int32_t candidate_path[4];
-    int32_t candidate_tile[4];
-    float candidates_ms[4];
+    int32_t candidate_path[8];
+    int32_t candidate_tile[8];
+    float candidates_ms[8];
 } cfpq_tune_entry;
 
 /* Device workspace for cfpq_autotune: four matrices of the bit layout. */
@@ -370,7 +377,7 @@ CFPQ_API cfpq_status cfpq_batch_workspace_bytes(int32_t n_instances, const cfpq_
  * Relational closure (Algorithm 1, in-place schedule) of every instance,
  * computed together.  Instances with a padded side of at most 512 run their
  * whole fixpoint in one workgroup each (VALU product); larger ones share a
- * per-loop work list of 256 x 256 int8-MFMA tiles, with `opt->capture` loops
+ * per-loop work list of 256 x 256 fp4-MFMA tiles, with `opt->capture` loops
  * (0 = 8) per captured HIP graph.  With opt->hybrid AUTO (the default), a
  * rule of a larger instance whose left operand heads no binary rule (its
  * matrix is fixed by the edges) runs as row gathers instead of tiles when the

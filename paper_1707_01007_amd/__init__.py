@@ -22,10 +22,11 @@ from typing import Optional
 import numpy as np
 
 from . import _abi
-from ._abi import (CfpqError, PATH_AUTO, PATH_BITS, PATH_MFMA, PATH_ROWS, PATH_COLS, SCHEDULE_INPLACE,  # noqa: F401
+from ._abi import (CfpqError, PATH_AUTO, PATH_BITS, PATH_MFMA, PATH_ROWS, PATH_COLS, PATH_FP4, SCHEDULE_INPLACE,  # noqa: F401
                    SCHEDULE_JACOBI)
 
-_PATHS = {"auto": PATH_AUTO, "bits": PATH_BITS, "mfma": PATH_MFMA, "rows": PATH_ROWS, "cols": PATH_COLS}
+_PATHS = {"auto": PATH_AUTO, "bits": PATH_BITS, "mfma": PATH_MFMA, "rows": PATH_ROWS, "cols": PATH_COLS,
+          "fp4": PATH_FP4}
 _SCHEDULES = {"inplace": SCHEDULE_INPLACE, "jacobi": SCHEDULE_JACOBI}
 
 

@@ -10,9 +10,9 @@ LIB_PATH = os.path.join(HERE, "libcfpq.so")
 
 CFPQ_OK, CFPQ_EINVAL, CFPQ_ENOMEM, CFPQ_EDEVICE, CFPQ_ENOTCONV, CFPQ_EBUSY, CFPQ_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
 CFPQ_ERANGE = -7
-PATH_AUTO, PATH_BITS, PATH_MFMA, PATH_ROWS, PATH_COLS = 0, 1, 2, 3, 4
+PATH_AUTO, PATH_BITS, PATH_MFMA, PATH_ROWS, PATH_COLS, PATH_FP4 = 0, 1, 2, 3, 4, 5
 HYBRID_OFF, HYBRID_AUTO = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 SCHEDULE_INPLACE, SCHEDULE_JACOBI = 0, 1
 STATUS_NAMES = {0: "CFPQ_OK", -1: "CFPQ_EINVAL", -2: "CFPQ_ENOMEM", -3: "CFPQ_EDEVICE",
                 -4: "CFPQ_ENOTCONV", -5: "CFPQ_EBUSY", -6: "CFPQ_ENOTREADY", -7: "CFPQ_ERANGE"}
@@ -84,11 +84,11 @@ class Stats(ctypes.Structure):
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("npad", ctypes.c_int32), ("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("ms", ctypes.c_float),
-                ("n_candidates", ctypes.c_int32), ("candidate_path", ctypes.c_int32 * 4),
-                ("candidate_tile", ctypes.c_int32 * 4), ("candidates_ms", ctypes.c_float * 4)]
+                ("n_candidates", ctypes.c_int32), ("candidate_path", ctypes.c_int32 * 8),
+                ("candidate_tile", ctypes.c_int32 * 8), ("candidates_ms", ctypes.c_float * 8)]
 
     def as_dict(self):
-        names = {PATH_BITS: "bits", PATH_MFMA: "mfma"}
+        names = {PATH_BITS: "bits", PATH_MFMA: "mfma", PATH_FP4: "fp4"}
         cands = {f"{names.get(self.candidate_path[k], '?')}{self.candidate_tile[k] or ''}": round(self.candidates_ms[k], 4)
                  for k in range(self.n_candidates)}
         return {"npad": self.npad, "path": names.get(self.path, "?"), "tile": self.tile,

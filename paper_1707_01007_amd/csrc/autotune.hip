@@ -53,7 +53,7 @@ __global__ void fill_random_kernel(uint64_t* __restrict__ p, size_t words, uint6
     }
 }
 
-const char* path_name(int32_t p) { return p == CFPQ_PATH_MFMA ? "mfma" : "bits"; }
+const char* path_name(int32_t p) { return p == CFPQ_PATH_FP4 ? "fp4" : p == CFPQ_PATH_MFMA ? "mfma" : "bits"; }
 
 cfpq_status load_file(const char* path, std::map<int32_t, cfpq_tune_entry>& out) {
     FILE* f = std::fopen(path, "r");
@@ -66,9 +66,10 @@ cfpq_status load_file(const char* path, std::map<int32_t, cfpq_tune_entry>& out)
         std::memset(&e, 0, sizeof e);
         char name[16] = {0};
         int bucket = 0;
-        if (std::sscanf(line, " {\"bucket\": %d, \"npad\": %d, \"path\": \"%15[a-z]\", \"tile\": %d, \"ms\": %f",
+        if (std::sscanf(line, " {\"bucket\": %d, \"npad\": %d, \"path\": \"%15[a-z0-9]\", \"tile\": %d, \"ms\": %f",
                         &bucket, &e.npad, name, &e.tile, &e.ms) == 5) {
             if (std::strcmp(name, "mfma") == 0) e.path = CFPQ_PATH_MFMA;
+            else if (std::strcmp(name, "fp4") == 0) e.path = CFPQ_PATH_FP4;
             else if (std::strcmp(name, "bits") == 0) e.path = CFPQ_PATH_BITS;
             else continue;
             if (bucket < 0 || bucket > 40 || e.npad <= 0) continue;
@@ -102,7 +103,7 @@ bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile, float* ms) {
     auto it = t.by_bucket.find(bucket_of(L.npad));
     if (it == t.by_bucket.end()) return false;
     const cfpq_tune_entry& e = it->second;
-    if (e.path == CFPQ_PATH_MFMA && L.n > kMfmaMaxNodes) return false;
+    if (reads_ct(e.path) && L.n > kMfmaMaxNodes) return false;
     if (e.path == CFPQ_PATH_BITS && e.tile != 0 && !bits_strip_supported(e.tile, L)) {
         *path = CFPQ_PATH_BITS;
         *tile = 0;
@@ -151,7 +152,10 @@ cfpq_status cfpq_autotune(int32_t n_nodes, void* stream, void* d_workspace, size
         int32_t path, tile;
     };
     std::vector<Cand> cands;
-    if (L.n <= kMfmaMaxNodes) cands.push_back({CFPQ_PATH_MFMA, 0});
+    if (L.n <= kMfmaMaxNodes) {
+        cands.push_back({CFPQ_PATH_FP4, 0});
+        cands.push_back({CFPQ_PATH_MFMA, 0});
+    }
     for (int strip : {8, 16, 32})
         if (bits_strip_supported(strip, L)) cands.push_back({CFPQ_PATH_BITS, strip});
     const double work = static_cast<double>(L.npad) * L.npad * L.npad;
@@ -160,9 +164,9 @@ cfpq_status cfpq_autotune(int32_t n_nodes, void* stream, void* d_workspace, size
     std::memset(&best, 0, sizeof best);
     best.npad = static_cast<int32_t>(L.npad);
     best.ms = 1e30f;
-    for (size_t c = 0; c < cands.size() && c < 4; ++c) {
+    for (size_t c = 0; c < cands.size() && c < 8; ++c) {
         auto launch = [&]() -> hipError_t {
-            if (cands[c].path == CFPQ_PATH_MFMA) return launch_mfma_product(B, CT, A, L, flag, s);
+            if (reads_ct(cands[c].path)) return launch_mfma_path(cands[c].path, B, CT, A, L, flag, s);
             return launch_bits_product(B, C, A, L, flag, s, cands[c].tile);
         };
         CFPQ_HIP(launch());  // warm up
@@ -182,7 +186,7 @@ cfpq_status cfpq_autotune(int32_t n_nodes, void* stream, void* d_workspace, size
             best.tile = cands[c].tile;
         }
     }
-    best.n_candidates = static_cast<int32_t>(std::min<size_t>(cands.size(), 4));
+    best.n_candidates = static_cast<int32_t>(std::min<size_t>(cands.size(), 8));
     {
         TuneTable& t = table();
         std::lock_guard<std::mutex> lk(t.mu);

@@ -358,7 +358,7 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
             st.bitops = 2.0 * static_cast<double>(d.npad) * d.npad * d.npad * static_cast<double>(st.products);
             st.device_ms = ms;
             st.product_ms = 0.0;
-            st.path_used = d.kind == kSlotLarge ? CFPQ_PATH_MFMA : CFPQ_PATH_BITS;
+            st.path_used = d.kind == kSlotLarge ? CFPQ_PATH_FP4 : CFPQ_PATH_BITS;
             st.converged = conv ? 1 : 0;
             st.sparse_products = 0;
             st.delta_products = 0;

@@ -6,13 +6,14 @@
 //    whole fixpoint in a single resident kernel launch (VALU product with the
 //    right operand staged in LDS, change flags in LDS);
 //  * large: every loop, a plan kernel turns the dirty rules of all running
-//    large slots into a work list -- 256 x 256 MFMA tiles for dense rules, and
-//    blocks of four rows for rules whose left operand is derived from terminal
-//    rules only (a sparse edge matrix: the row-gather product reads just the
-//    rows of C its bits select) -- a persistent kernel pulls items from an
-//    atomic counter, transposes of the right operands of dense rules that
-//    changed are rebuilt the same way, and a finish kernel counts the loop and
-//    retires slots that reached their fixpoint.  The loop is captured into a
+//    large slots into work lists -- 256 x 256 fp4-MFMA tiles for dense rules,
+//    pulled from an atomic counter by a persistent kernel, and rows for rules
+//    whose left operand is derived from terminal rules only (a sparse edge
+//    matrix: the row-gather product reads just the rows of C its bits select),
+//    one wavefront per row in a second kernel of high occupancy; transposes of
+//    the right operands of dense rules that changed are rebuilt like the
+//    tiles, and a finish kernel counts the loop and retires slots that reached
+//    their fixpoint.  The loop is captured into a
 //    HIP graph once; which slots take part is data, so the same graph serves a
 //    batch that gains and loses members between replays.
 #pragma once
@@ -68,7 +69,9 @@ struct EngineState {
     int32_t n_tjobs, total_titems, next_titem, pad1;
     int32_t running;  // large slots still running after the last finish
     int32_t n_large;  // entries of the large-slot list (set by the host between replays)
-    int32_t pad2[6];
+    int32_t n_rjobs;     // row-gather jobs of the loop, stored after the n_jobs tile jobs
+    int32_t total_rows;  // their rows (one wavefront each)
+    int32_t pad2[4];
 };
 
 // Device buffers of an engine (all carved from one allocation by the owner).

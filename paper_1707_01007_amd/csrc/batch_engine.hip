@@ -200,20 +200,43 @@ __device__ void scan2(int32_t* sa, int32_t* sb, int32_t& a, int32_t& b, int32_t*
     b = sb[t];
 }
 
+// Exclusive prefix sums over the 256 threads of four per-thread counts
+// (in place) and their totals.
+__device__ void scan4(int32_t (*sh)[256], int32_t (&v)[4], int32_t* const (&tot)[4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sh[c][t] = v[c];
+    __syncthreads();
+    if (t < 4) {
+        int32_t x = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int32_t y = sh[t][i];
+            sh[t][i] = x;
+            x += y;
+        }
+        *tot[t] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = sh[c][t];
+}
+
 // Start of a loop: for every running large slot decide which rules run
-// (dirty worklist), clear the slot's change flags, and lay out the work list
-// of 256 x 256 tiles.  Slots are handled in list order (largest first), so the
-// biggest tiles are handed out first.
+// (dirty worklist), clear the slot's change flags, and lay out the work lists:
+// 256 x 256 tiles of the dense rules (jobs[0, n_jobs)), and rows of the
+// row-gather rules (jobs[n_jobs, n_jobs + n_rjobs), item_begin counting rows).
+// Slots are handled in list order (largest first), so the biggest tiles are
+// handed out first.
 __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
                                                           const int32_t* __restrict__ rules_tab, int32_t* go_tab,
                                                           const int32_t* __restrict__ mode_tab, Job* jobs,
                                                           EngineState* es, const int32_t* __restrict__ large_ids) {
-    __shared__ int32_t sa[256], sb[256];
+    __shared__ int32_t sh[4][256];
     const int t = threadIdx.x;
     const int n_large = es->n_large;
     const int per = (n_large + 255) / 256;
     const int q0 = t * per, q1 = min(n_large, q0 + per);
-    int32_t my_jobs = 0, my_items = 0;
+    int32_t my_jobs = 0, my_items = 0, my_rjobs = 0, my_rows = 0;
     for (int q = q0; q < q1; ++q) {
         const int slot = large_ids[q];
         const SlotDesc& d = descs[slot];
@@ -236,13 +259,27 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             const int go = (!d.dirty || st->iterations == 0 || st->changed_prev[rb] || st->changed_prev[rc]) ? 1 : 0;
             go_tab[d.rule_off + r] = go;
             launched += go;
-            if (go) my_items += mode_tab[d.rule_off + r] == kModeRows ? (d.n + 3) / 4 : dim * dim;
+            if (!go) continue;
+            if (mode_tab[d.rule_off + r] == kModeRows) {
+                ++my_rjobs;
+                my_rows += d.n;
+            } else {
+                ++my_jobs;
+                my_items += dim * dim;
+            }
         }
         st->products += launched;
-        my_jobs += launched;
     }
-    scan2(sa, sb, my_jobs, my_items, &es->n_jobs, &es->total_items);
+    int32_t v[4] = {my_jobs, my_items, my_rjobs, my_rows};
+    int32_t* const tot[4] = {&es->n_jobs, &es->total_items, &es->n_rjobs, &es->total_rows};
+    scan4(sh, v, tot);
+    my_jobs = v[0];
+    my_items = v[1];
+    my_rjobs = v[2];
+    my_rows = v[3];
     if (t == 0) es->next_item = 0;
+    __syncthreads();  // tile-job total visible to every thread (row jobs follow the tile jobs)
+    Job* rjobs = jobs + es->n_jobs;
     for (int q = q0; q < q1; ++q) {
         const int slot = large_ids[q];
         const SlotDesc& d = descs[slot];
@@ -250,21 +287,25 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
         const int dim = d.npad / 256;
         for (int r = 0; r < d.n_rules; ++r) {
             if (!go_tab[d.rule_off + r]) continue;
-            jobs[my_jobs++] = Job{slot, r, my_items, dim};
-            my_items += mode_tab[d.rule_off + r] == kModeRows ? (d.n + 3) / 4 : dim * dim;
+            if (mode_tab[d.rule_off + r] == kModeRows) {
+                rjobs[my_rjobs++] = Job{slot, r, my_rows, 0};
+                my_rows += d.n;
+            } else {
+                jobs[my_jobs++] = Job{slot, r, my_items, dim};
+                my_items += dim * dim;
+            }
         }
     }
 }
 
-// Row-gather item: rows 4 item .. 4 item + 3 of A |= B x C (one per
-// wavefront), C read in place; other items of the loop may write the same
-// rows (several rules with one head), so new bits are OR-ed atomically.
-__device__ void engine_rows_item(const SlotDesc& d, const uint64_t* Bm, const uint64_t* Cm, uint64_t* Am, int local,
-                                 int32_t* changed) {
-    constexpr int WPL = 4;
+// One row of A |= B x C for a row-gather rule, by one wavefront: the OR of
+// the rows of C selected by the bits of B's row (B is an edge matrix, so few),
+// with C read in place.  Other work of the loop may write the same row (rules
+// with one head), so new bits are OR-ed atomically.
+template <int WPL>
+__device__ void engine_gather_row(const SlotDesc& d, const uint64_t* Bm, const uint64_t* Cm, uint64_t* Am,
+                                  int64_t row, int32_t* changed) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = static_cast<int64_t>(local) * 4 + (threadIdx.x >> 6);
-    if (row >= d.n) return;  // whole wavefront
     const int64_t W = d.W;
     const int32_t kwords = (d.n + 63) / 64;
     const uint64_t* brow = Bm + row * W;
@@ -289,11 +330,35 @@ __device__ void engine_rows_item(const SlotDesc& d, const uint64_t* Bm, const ui
     if (__ballot(ch) != 0 && lane == 0) atomicOr(changed, 1);
 }
 
+// The loop's row-gather work: every wavefront takes rows of the row list in
+// grid-stride order (rows of one slot and rule are contiguous in the list).
+__global__ __launch_bounds__(256) void engine_rows_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
+                                                          const int32_t* __restrict__ rules_tab,
+                                                          const Job* __restrict__ jobs,
+                                                          const EngineState* __restrict__ es) {
+    const int n_rjobs = es->n_rjobs;
+    const int total = es->total_rows;
+    const Job* rjobs = jobs + es->n_jobs;
+    const int waves = gridDim.x * 4;
+    for (int x = blockIdx.x * 4 + (threadIdx.x >> 6); x < total; x += waves) {
+        const Job jb = rjobs[job_of(rjobs, n_rjobs, x)];
+        const SlotDesc& d = descs[jb.slot];
+        const int r = d.rule_off + jb.what;
+        const int ra = rules_tab[3 * r], rb = rules_tab[3 * r + 1], rc = rules_tab[3 * r + 2];
+        const size_t mw = static_cast<size_t>(d.npad) * d.W;
+        const int64_t row = x - jb.item_begin;
+        int32_t* changed = &states[jb.slot].changed[ra];
+        if (d.W <= 64)
+            engine_gather_row<1>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed);
+        else
+            engine_gather_row<4>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed);
+    }
+}
+
 // Persistent product kernel: workgroups pull items from the loop's work list.
 __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
                                                              const int32_t* __restrict__ rules_tab,
                                                              const int32_t* __restrict__ trans_tab,
-                                                             const int32_t* __restrict__ mode_tab,
                                                              const Job* __restrict__ jobs, EngineState* es) {
     __shared__ int32_t item_s;
     const int n_jobs = es->n_jobs;
@@ -309,18 +374,13 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
         const int r = d.rule_off + jb.what;
         const int ra = rules_tab[3 * r], rb = rules_tab[3 * r + 1], rc = rules_tab[3 * r + 2];
         const int local = item - jb.item_begin;
-        if (mode_tab[r] == kModeRows) {
-            const size_t mw = static_cast<size_t>(d.npad) * d.W;
-            engine_rows_item(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, local, &states[jb.slot].changed[ra]);
-            continue;
-        }
         const size_t mdw = static_cast<size_t>(d.npad) * d.W * 2;
         const uint32_t* Bm = reinterpret_cast<const uint32_t*>(d.T) + rb * mdw;
         const uint32_t* CT = reinterpret_cast<const uint32_t*>(d.TT) + trans_tab[d.trans_off + rc] * mdw;
         uint32_t* Am = reinterpret_cast<uint32_t*>(d.T) + ra * mdw;
-        const int kchunks = ((d.n + 255) / 256) * 2;
-        mfma::mfma_tile<true>(Bm, CT, Am, 2 * d.W, kchunks, local / jb.dim, local % jb.dim,
-                              &states[jb.slot].changed[ra]);
+        const int kchunks = (d.n + 255) / 256;  // 256-k chunks of the fp4 tile
+        mfma::mfma4_tile<true>(Bm, CT, Am, 2 * d.W, kchunks, local / jb.dim, local % jb.dim,
+                               &states[jb.slot].changed[ra]);
     }
 }
 
@@ -453,7 +513,11 @@ hipError_t engine_plan(const EngineBuffers& b, hipStream_t s) {
 
 hipError_t engine_products(const EngineBuffers& b, int32_t grid, hipStream_t s) {
     engine_product_kernel<<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab,
-                                                                                b.trans_tab, b.mode_tab, b.jobs, b.es);
+                                                                                b.trans_tab, b.jobs, b.es);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    engine_rows_kernel<<<dim3(static_cast<unsigned>(4 * grid)), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab,
+                                                                                 b.jobs, b.es);
     return hipGetLastError();
 }
 

@@ -96,6 +96,20 @@ bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile, float* ms = nul
 // A |= B x C on the int8 matrix cores; CT is the transpose of C.
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
                                int32_t* changed, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1);
+// The same product on the fp4 (e2m1) MFMA with fp32 sums (kernels_mfma.hip).
+hipError_t launch_mfma4_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
+                                int32_t* changed, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1);
+
+// The dense kernels that read C transposed: the two MFMA paths.
+inline bool reads_ct(int32_t path) { return path == CFPQ_PATH_MFMA || path == CFPQ_PATH_FP4; }
+
+// The product of an MFMA path (MFMA: int8, FP4: e2m1).
+inline hipError_t launch_mfma_path(int32_t path, const uint64_t* B, const uint64_t* CT, uint64_t* A,
+                                   const Layout& L, int32_t* changed, hipStream_t s, const int32_t* go = nullptr,
+                                   int32_t want = 1) {
+    return path == CFPQ_PATH_FP4 ? launch_mfma4_product(B, CT, A, L, changed, s, go, want)
+                                 : launch_mfma_product(B, CT, A, L, changed, s, go, want);
+}
 
 // Sparse-operand products (kernels_sparse.hip): A[i,:] |= OR_{k in nz(B[i,:])} C[k,:]
 // for rows i < n, and A |= transpose(Pt).  `changed` may be NULL for the

@@ -118,20 +118,20 @@ struct Plan {
 // AUTO: the autotuned kernel of the size bucket, else MFMA while int32 sums
 // are exact.  *tile is only changed for an autotuned choice.
 int32_t choose_path(const Layout& L, int32_t requested, int32_t* tile = nullptr) {
-    if (requested == CFPQ_PATH_BITS || requested == CFPQ_PATH_MFMA) return requested;
+    if (requested == CFPQ_PATH_BITS || reads_ct(requested)) return requested;
     int32_t p = 0, t = 0;
     if (tuned_choice(L, &p, &t)) {
         if (tile) *tile = t;
         return p;
     }
-    return L.n <= kMfmaMaxNodes ? CFPQ_PATH_MFMA : CFPQ_PATH_BITS;
+    return L.n <= kMfmaMaxNodes ? CFPQ_PATH_FP4 : CFPQ_PATH_BITS;
 }
 
 HybridModel make_model(const Layout& L, int32_t path, float tuned_ms) {
     HybridModel m;
     const double npad = static_cast<double>(L.npad);
-    // dense rates measured for the two kernels at n = 16384 (bit-ops per us)
-    const double rate = path == CFPQ_PATH_MFMA ? 4.0e9 : 1.8e9;
+    // dense rates measured for the kernels at n = 16384 (bit-ops per us)
+    const double rate = path == CFPQ_PATH_FP4 ? 7.0e9 : path == CFPQ_PATH_MFMA ? 4.0e9 : 1.8e9;
     m.dense_us = tuned_ms > 0 ? 1000.0 * tuned_ms : 5.0 + 2.0 * npad * npad * npad / rate;
     m.row_us = static_cast<double>(L.W) * 8.0 / 12.0e6;              // gathered rows, mostly cache hits
     m.mat_us = static_cast<double>(L.mat_words) * 8.0 / 5.0e6;       // streamed, ~5 TB/s
@@ -157,7 +157,7 @@ Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& 
     p.jacobi = o.schedule == CFPQ_SCHEDULE_JACOBI;
     p.temps = p.hybrid || p.forced == kModeCols;
     p.right_slot.assign(p.n_nt, -1);
-    if (p.path == CFPQ_PATH_MFMA || p.temps) {
+    if (reads_ct(p.path) || p.temps) {
         for (int32_t r = 0; r < gr->n_bin_rules; ++r) {
             int32_t c = gr->bin_rules[r].right;
             if (p.right_slot[c] < 0) p.right_slot[c] = p.n_right++;
@@ -284,15 +284,15 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     if (reinterpret_cast<uintptr_t>(d_result) % 16 || reinterpret_cast<uintptr_t>(d_workspace) % 16)
         return fail(CFPQ_EINVAL, "d_result and d_workspace must be 16-byte aligned");
     const cfpq_options o = resolve(opt);
-    if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_COLS) return fail(CFPQ_EINVAL, "unknown path");
+    if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_FP4) return fail(CFPQ_EINVAL, "unknown path");
     if (o.hybrid != CFPQ_HYBRID_OFF && o.hybrid != CFPQ_HYBRID_AUTO) return fail(CFPQ_EINVAL, "unknown hybrid mode");
     if (o.warm_start != 0 && o.warm_start != 1) return fail(CFPQ_EINVAL, "options.warm_start must be 0 or 1");
     if (o.schedule != CFPQ_SCHEDULE_INPLACE && o.schedule != CFPQ_SCHEDULE_JACOBI)
         return fail(CFPQ_EINVAL, "unknown schedule");
     if (o.max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
     if (o.capture < 0) return fail(CFPQ_EINVAL, "options.capture is negative");
-    if (o.path == CFPQ_PATH_MFMA && graph->n_nodes > kMfmaMaxNodes)
-        return fail(CFPQ_EINVAL, "the MFMA path supports at most 2^19 nodes");
+    if (reads_ct(o.path) && graph->n_nodes > kMfmaMaxNodes)
+        return fail(CFPQ_EINVAL, "the MFMA paths support at most 2^19 nodes");
     if (o.tile != 0 && o.path == CFPQ_PATH_BITS && !bits_strip_supported(o.tile, layout_for(graph->n_nodes)))
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
     if (o.tile != 0 && (o.path == CFPQ_PATH_ROWS || o.path == CFPQ_PATH_COLS))
@@ -422,9 +422,9 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             for (int32_t r = 0; r < n_rules && ce == hipSuccess; ++r) {
                 const auto& br = grammar->bin_rules[r];
                 int32_t* flag = &st->changed[br.lhs];
-                if (p.path == CFPQ_PATH_MFMA)
-                    ce = launch_mfma_product(cx + br.left * mat_words, TT + p.right_slot[br.right] * mat_words,
-                                             cy + br.lhs * mat_words, L, flag, cs, d_go + r);
+                if (reads_ct(p.path))
+                    ce = launch_mfma_path(p.path, cx + br.left * mat_words, TT + p.right_slot[br.right] * mat_words,
+                                          cy + br.lhs * mat_words, L, flag, cs, d_go + r);
                 else
                     ce = launch_bits_product(cx + br.left * mat_words, cx + br.right * mat_words,
                                              cy + br.lhs * mat_words, L, flag, cs, p.tile, d_go + r);
@@ -493,7 +493,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             CFPQ_HIP(launch_rowor_product(Bm, Cm, Am, L, flag, ROWOR, s));
             return CFPQ_OK;
         }
-        if ((mode == kModeCols || p.path == CFPQ_PATH_MFMA) && !ct) {
+        if ((mode == kModeCols || reads_ct(p.path)) && !ct) {
             CFPQ_HIP(launch_transpose(Cm, CTT, L, s));
             ct = CTT;
         }
@@ -506,14 +506,14 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             CFPQ_HIP(launch_zero(PT, mat_words, s));
             CFPQ_HIP(launch_rowor_product(ct, bt, PT, L, nullptr, ROWOR, s));
             CFPQ_HIP(launch_transpose_or(PT, Am, L, flag, s));
-        } else if (p.path == CFPQ_PATH_MFMA) {
-            CFPQ_HIP(launch_mfma_product(Bm, ct, Am, L, flag, s));
+        } else if (reads_ct(p.path)) {
+            CFPQ_HIP(launch_mfma_path(p.path, Bm, ct, Am, L, flag, s));
         } else {
             CFPQ_HIP(launch_bits_product(Bm, Cm, Am, L, flag, s, p.tile));
         }
         return CFPQ_OK;
     };
-    const bool mfma = p.path == CFPQ_PATH_MFMA;
+    const bool mfma = reads_ct(p.path);
     while (!captured && !converged && iters < cap) {
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         size_t launched = 0;
@@ -643,7 +643,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
 
 size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path) {
     const size_t mat = static_cast<size_t>(layout_for(n_nodes < 0 ? 0 : n_nodes).mat_words) * 8;
-    if (path == CFPQ_PATH_MFMA) return mat;
+    if (reads_ct(path)) return mat;
     const size_t rs = align_up(rowor_scratch_bytes(layout_for(n_nodes < 0 ? 0 : n_nodes)), 256);
     if (path == CFPQ_PATH_ROWS) return rs;
     if (path == CFPQ_PATH_COLS) return 3 * mat + rs;
@@ -662,12 +662,12 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
         return fail(CFPQ_EINVAL, "matrices and workspace must be 16-byte aligned");
     const Layout L = layout_for(n_nodes);
     if (path == CFPQ_PATH_AUTO) path = choose_path(L, path, tile == 0 ? &tile : nullptr);
-    if (path < CFPQ_PATH_BITS || path > CFPQ_PATH_COLS) return fail(CFPQ_EINVAL, "unknown path");
+    if (path < CFPQ_PATH_BITS || path > CFPQ_PATH_FP4) return fail(CFPQ_EINVAL, "unknown path");
     if (path == CFPQ_PATH_BITS && tile != 0 && !bits_strip_supported(tile, L))
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
     if (path != CFPQ_PATH_BITS && tile != 0) return fail(CFPQ_EINVAL, "only the BITS path has tile variants");
-    if (path == CFPQ_PATH_MFMA && n_nodes > kMfmaMaxNodes)
-        return fail(CFPQ_EINVAL, "the MFMA path supports at most 2^19 nodes");
+    if (reads_ct(path) && n_nodes > kMfmaMaxNodes)
+        return fail(CFPQ_EINVAL, "the MFMA paths support at most 2^19 nodes");
     const size_t need = cfpq_product_workspace_bytes(n_nodes, path);
     if (need > 0 && (workspace_bytes < need || !d_workspace))
         return fail(CFPQ_ENOMEM, "workspace smaller than cfpq_product_workspace_bytes");
@@ -676,8 +676,9 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
     auto* ws = static_cast<uint64_t*>(d_workspace);
     switch (path) {
         case CFPQ_PATH_MFMA:
+        case CFPQ_PATH_FP4:
             CFPQ_HIP(launch_transpose(d_c, ws, L, s));
-            CFPQ_HIP(launch_mfma_product(d_b, ws, d_a, L, d_changed, s));
+            CFPQ_HIP(launch_mfma_path(path, d_b, ws, d_a, L, d_changed, s));
             break;
         case CFPQ_PATH_ROWS:
             CFPQ_HIP(launch_rowor_product(d_b, d_c, d_a, L, d_changed, reinterpret_cast<int32_t*>(ws), s));

@@ -98,12 +98,12 @@ CjPlan cj_plan(const cfpq_graph* g, const cfpq_grammar* gr, const std::vector<Ru
     p.n_nt = gr->n_nonterminals;
     p.tile = o.tile;
     p.path = o.path;
-    if (p.path == CFPQ_PATH_AUTO) p.path = g->n_nodes <= kMfmaMaxNodes ? CFPQ_PATH_MFMA : CFPQ_PATH_BITS;
+    if (p.path == CFPQ_PATH_AUTO) p.path = g->n_nodes <= kMfmaMaxNodes ? CFPQ_PATH_FP4 : CFPQ_PATH_BITS;
     p.jacobi = o.schedule == CFPQ_SCHEDULE_JACOBI;
     p.right_slot.assign(p.n_nt, -1);
     for (const Rule& r : rules) {
         if (r.parts.size() > 1) p.temps = true;
-        if (p.path == CFPQ_PATH_MFMA)
+        if (reads_ct(p.path))
             for (const auto& pc : r.parts)
                 if (p.right_slot[pc.second] < 0) p.right_slot[pc.second] = p.n_right++;
     }
@@ -132,14 +132,14 @@ CjPlan cj_plan(const cfpq_graph* g, const cfpq_grammar* gr, const std::vector<Ru
 }
 
 cfpq_status check_options(const cfpq_options& o, int32_t n_nodes) {
-    if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_MFMA)
-        return fail(CFPQ_EINVAL, "conjunctive closures take the AUTO, BITS or MFMA path");
+    if (o.path != CFPQ_PATH_AUTO && o.path != CFPQ_PATH_BITS && !reads_ct(o.path))
+        return fail(CFPQ_EINVAL, "conjunctive closures take the AUTO, BITS, MFMA or FP4 path");
     if (o.schedule != CFPQ_SCHEDULE_INPLACE && o.schedule != CFPQ_SCHEDULE_JACOBI)
         return fail(CFPQ_EINVAL, "unknown schedule");
     if (o.max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
     if (o.warm_start != 0) return fail(CFPQ_EINVAL, "conjunctive closures have no warm start");
-    if (o.path == CFPQ_PATH_MFMA && n_nodes > kMfmaMaxNodes)
-        return fail(CFPQ_EINVAL, "the MFMA path supports at most 2^19 nodes");
+    if (reads_ct(o.path) && n_nodes > kMfmaMaxNodes)
+        return fail(CFPQ_EINVAL, "the MFMA paths support at most 2^19 nodes");
     if (o.tile != 0 && (o.path != CFPQ_PATH_BITS || !bits_strip_supported(o.tile, layout_for(n_nodes))))
         return fail(CFPQ_EINVAL, "unsupported tile");
     return CFPQ_OK;
@@ -255,8 +255,8 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
         if (p.right_slot[a] >= 0) CFPQ_HIP(launch_transpose(X + a * mw, TT + p.right_slot[a] * mw, L, s));
 
     auto product = [&](int32_t b, int32_t c, uint64_t* out, int32_t* flag) -> cfpq_status {
-        if (p.path == CFPQ_PATH_MFMA)
-            CFPQ_HIP(launch_mfma_product(X + b * mw, TT + p.right_slot[c] * mw, out, L, flag, s));
+        if (reads_ct(p.path))
+            CFPQ_HIP(launch_mfma_path(p.path, X + b * mw, TT + p.right_slot[c] * mw, out, L, flag, s));
         else
             CFPQ_HIP(launch_bits_product(X + b * mw, X + c * mw, out, L, flag, s, p.tile));
         return CFPQ_OK;

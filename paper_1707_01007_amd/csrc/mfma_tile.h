@@ -1,5 +1,6 @@
-// Device code of the int8 MFMA Boolean product tile, shared by the single
-// product kernel and the batched engine.
+// Device code of the MFMA Boolean product tiles (int8 operands with int32
+// sums, and e2m1 fp4 operands with fp32 sums), shared by the single product
+// kernels and the batched engine.
 #pragma once
 
 #include "cfpq_internal.h"
@@ -9,6 +10,8 @@ namespace mfma {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kJT = 4;  // 32-row blocks of j per wavefront
 constexpr int kIT = 4;  // 32-column blocks of i per wavefront
@@ -60,13 +63,57 @@ __device__ __forceinline__ void mma_chunk(v16i (&acc)[kJT][kIT], const Chunk& ch
     }
 }
 
-// One 256 x 256 output tile (rows i of tile_i, columns j of tile_j) of
-// A |= B x C, CT = C^T, over kchunks chunks of 128 k.  Called by all 256 lanes
-// of a workgroup; no barriers, so a caller may loop over several tiles.
+// Epilogue of a tile: threshold the sums, pack them along j into bit words
+// and OR them into A (rows i).  Accumulator e of lane (g, r32) in block
+// (jb, ib) is D[j][i] with i = i0 + 32 ib + r32 and
+// j = j0 + 32 jb + 8 (e / 4) + 4 g + (e % 4).
 // kAtomic: OR new bits into A with 64-bit atomics (needed when other
 // workgroups may update the same words concurrently, e.g. two rules with the
 // same head in one batched loop); otherwise a plain read-modify-write by the
 // tile's only writer.
+template <bool kAtomic, typename Acc>
+__device__ __forceinline__ void store_tile(const Acc (&acc)[kJT][kIT], uint32_t* Am, int W2, int i0, int j0, int g,
+                                           int r32, int lane, int32_t* changed) {
+    bool ch = false;
+#pragma unroll
+    for (int ib = 0; ib < kIT; ++ib) {
+        uint32_t word[kJT];
+#pragma unroll
+        for (int jb = 0; jb < kJT; ++jb) {
+            uint32_t w = 0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                // sums are never negative (squares), so sum > 0 is the Boolean value
+                const uint32_t bit = acc[jb][ib][e] > 0 ? 1u : 0u;
+                w |= bit << (8 * (e / 4) + 4 * g + (e % 4));
+            }
+            word[jb] = w | static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 32, 64));
+        }
+        // lanes with g = 0 write columns j0..j0+63, g = 1 write j0+64..j0+127
+        const uint64_t lo = g == 0 ? word[0] : word[2];
+        const uint64_t hi = g == 0 ? word[1] : word[3];
+        const uint64_t add = lo | (hi << 32);
+        const int i = i0 + ib * 32 + r32;
+        uint64_t* dst = reinterpret_cast<uint64_t*>(Am + static_cast<size_t>(i) * W2) + (j0 / 64) + g;
+        const uint64_t old = *dst;
+        if ((add & ~old) != 0) {
+            if (kAtomic) {
+                const uint64_t prev = atomicOr(reinterpret_cast<unsigned long long*>(dst),
+                                               static_cast<unsigned long long>(add));
+                if ((add & ~prev) != 0) ch = true;
+            } else {
+                *dst = old | add;
+                ch = true;
+            }
+        }
+    }
+    if (__ballot(ch) != 0 && lane == 0) atomicOr(changed, 1);
+}
+
+// One 256 x 256 output tile (rows i of tile_i, columns j of tile_j) of
+// A |= B x C, CT = C^T, over kchunks chunks of 128 k.  Called by all 256 lanes
+// of a workgroup; no barriers, so a caller may loop over several tiles.
+// kAtomic as in store_tile.
 template <bool kAtomic>
 __device__ __forceinline__ void mfma_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
                                           uint32_t* Am, int W2, int kchunks, int tile_i, int tile_j,
@@ -114,43 +161,102 @@ __device__ __forceinline__ void mfma_tile(const uint32_t* __restrict__ Bm, const
         __builtin_amdgcn_sched_barrier(0);
     }
 
-    // ---- epilogue: threshold, pack along j, OR into A ----
-    // Accumulator e of lane (g, r32) in block (jb, ib) is D[j][i] with
-    // i = i0 + 32 ib + r32 and j = j0 + 32 jb + 8 (e / 4) + 4 g + (e % 4).
-    bool ch = false;
+    store_tile<kAtomic>(acc, Am, W2, i0, j0, g, r32, lane, changed);
+}
+
+// ---- fp4 (e2m1) operands, fp32 sums ----
+
+// Scale operands of the f8f6f4 MFMA builtin: 0 on both sides selects the
+// unscaled instruction, which takes the e2m1 values as they are.
+constexpr int kFp4Scale = 0;
+
+// Operand dwords of one 32-bit k-word w for the fp4 MFMA: dword q holds the
+// eight bits 4t + q of w (t = 0..7) as e2m1 nibbles, nibble t nonzero iff
+// that bit is set: q = 0, 1 put the bit at nibble position 1 (value 1.0),
+// q = 2, 3 at position 2 (value 2.0).  The four dwords carry all 32 bits, and
+// both operands give the same value at the same k, so every product term is
+// 1 or 4 and a sum is positive iff some k has both bits set.  Sums stay below
+// 4 * 2^19 < 2^24, exact in fp32 (and a positive sum of positive terms could
+// not round to zero anyway).
+__device__ __forceinline__ v8i spread4(uint32_t w) {
+    v8i r;
+    r[0] = static_cast<int>((w << 1) & 0x22222222u);
+    r[1] = static_cast<int>(w & 0x22222222u);
+    r[2] = static_cast<int>(w & 0x44444444u);
+    r[3] = static_cast<int>((w >> 1) & 0x44444444u);
+    r[4] = r[5] = r[6] = r[7] = 0;  // not read for fp4 operands
+    return r;
+}
+
+// kChunkWords steps of 64 k (this lane's k-word s and its partner's):
+// per step 8 operand fragments and 16 MFMAs.
+__device__ __forceinline__ void mma_chunk4(v16f (&acc)[kJT][kIT], const Chunk& ch) {
 #pragma unroll
-    for (int ib = 0; ib < kIT; ++ib) {
-        uint32_t word[kJT];
+    for (int s = 0; s < kChunkWords; ++s) {
+        v8i ca[kJT], bb[kIT];
 #pragma unroll
-        for (int jb = 0; jb < kJT; ++jb) {
-            uint32_t w = 0;
+        for (int jb = 0; jb < kJT; ++jb) ca[jb] = spread4(word_of(ch.c[jb], s));
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                // sums are never negative (squares), so min(sum, 1) is the Boolean value
-                const uint32_t bit = min(static_cast<uint32_t>(acc[jb][ib][e]), 1u);
-                w |= bit << (8 * (e / 4) + 4 * g + (e % 4));
-            }
-            word[jb] = w | static_cast<uint32_t>(__shfl_xor(static_cast<int>(w), 32, 64));
-        }
-        // lanes with g = 0 write columns j0..j0+63, g = 1 write j0+64..j0+127
-        const uint64_t lo = g == 0 ? word[0] : word[2];
-        const uint64_t hi = g == 0 ? word[1] : word[3];
-        const uint64_t add = lo | (hi << 32);
-        const int i = i0 + ib * 32 + r32;
-        uint64_t* dst = reinterpret_cast<uint64_t*>(Am + static_cast<size_t>(i) * W2) + (j0 / 64) + g;
-        const uint64_t old = *dst;
-        if ((add & ~old) != 0) {
-            if (kAtomic) {
-                const uint64_t prev = atomicOr(reinterpret_cast<unsigned long long*>(dst),
-                                               static_cast<unsigned long long>(add));
-                if ((add & ~prev) != 0) ch = true;
-            } else {
-                *dst = old | add;
-                ch = true;
-            }
-        }
+        for (int ib = 0; ib < kIT; ++ib) bb[ib] = spread4(word_of(ch.b[ib], s));
+#pragma unroll
+        for (int jb = 0; jb < kJT; ++jb)
+#pragma unroll
+            for (int ib = 0; ib < kIT; ++ib)
+                acc[jb][ib] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    ca[jb], bb[ib], acc[jb][ib], 4, 4, 0, kFp4Scale, 0, kFp4Scale);
     }
-    if (__ballot(ch) != 0 && lane == 0) atomicOr(changed, 1);
+}
+
+// The tile of mfma_tile on the fp4 MFMA, over kchunks chunks of 256 k (any
+// count >= 1): lane half g reads dwords 8c + 4g .. 8c + 4g + 3 of chunk c, so
+// one 64-k MFMA step takes k-word s from each half.
+template <bool kAtomic>
+__device__ __forceinline__ void mfma4_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
+                                           uint32_t* Am, int W2, int kchunks, int tile_i, int tile_j,
+                                           int32_t* changed) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 5;
+    const int r32 = lane & 31;
+    const int j0 = tile_j * 256 + (wave & 1) * 128;
+    const int i0 = tile_i * 256 + (wave >> 1) * 128;
+
+    // uint4 index 2c of these pointers is chunk c's dwords for this half
+    const uint4* crow[kJT];
+    const uint4* brow[kIT];
+#pragma unroll
+    for (int jb = 0; jb < kJT; ++jb)
+        crow[jb] = reinterpret_cast<const uint4*>(CT + static_cast<size_t>(j0 + jb * 32 + r32) * W2) + g;
+#pragma unroll
+    for (int ib = 0; ib < kIT; ++ib)
+        brow[ib] = reinterpret_cast<const uint4*>(Bm + static_cast<size_t>(i0 + ib * 32 + r32) * W2) + g;
+
+    v16f acc[kJT][kIT];
+#pragma unroll
+    for (int jb = 0; jb < kJT; ++jb)
+#pragma unroll
+        for (int ib = 0; ib < kIT; ++ib)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[jb][ib][e] = 0.0f;
+
+    // Two alternating chunk buffers as in mfma_tile; an odd last chunk is
+    // multiplied after the loop from the buffer its prefetch filled.
+    Chunk buf0, buf1;
+    load_chunk(buf0, crow, brow, 0);
+    int kc = 0;
+    for (; kc + 1 < kchunks; kc += 2) {
+        load_chunk(buf1, crow, brow, 2 * (kc + 1));
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk4(acc, buf0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_chunk(buf0, crow, brow, 2 * min(kc + 2, kchunks - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        mma_chunk4(acc, buf1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (kc < kchunks) mma_chunk4(acc, buf0);
+
+    store_tile<kAtomic>(acc, Am, W2, i0, j0, g, r32, lane, changed);
 }
 
 }  // namespace mfma

@@ -168,7 +168,7 @@ namespace {
 cfpq_options lane_options() {
     cfpq_options o;
     cfpq_default_options(&o);
-    o.path = CFPQ_PATH_MFMA;  // requests are limited to 2^19 nodes
+    o.path = CFPQ_PATH_FP4;  // requests are limited to 2^19 nodes
     return o;
 }
 
@@ -403,7 +403,7 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
             r->stats.bitops = 2.0 * static_cast<double>(r->L.npad) * r->L.npad * r->L.npad * st.products;
             r->stats.device_ms = (r->t_done - r->t_admit) * 1e3;
             r->stats.product_ms = 0.0;
-            r->stats.path_used = r->small ? CFPQ_PATH_BITS : CFPQ_PATH_MFMA;
+            r->stats.path_used = r->small ? CFPQ_PATH_BITS : CFPQ_PATH_FP4;
             r->stats.converged = (r->status == CFPQ_OK && !st.capped) ? 1 : 0;
             if (r->status == CFPQ_OK && st.capped) r->status = CFPQ_ENOTCONV;
             r->state = 2;

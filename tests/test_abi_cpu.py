@@ -44,7 +44,7 @@ def test_layout_functions():
         assert lib.cfpq_row_words(n) == w
         assert lib.cfpq_padded_rows(n) == 64 * w
         assert lib.cfpq_result_bytes(n, 3) == 3 * 64 * w * w * 8
-    assert lib.cfpq_abi_version() == 2
+    assert lib.cfpq_abi_version() == 3
 
 
 def _structs(n=4, edges=((0, 0, 1), (1, 1, 2)), n_nt=4, n_t=2, term=((2, 0), (3, 1)),
@@ -118,7 +118,7 @@ def test_closure_rejects_small_workspace_and_null_result():
     assert rc == _abi.CFPQ_EINVAL
 
 
-@pytest.mark.parametrize("field,value", [("hybrid", 5), ("warm_start", 2), ("path", 5), ("path", -1)])
+@pytest.mark.parametrize("field,value", [("hybrid", 5), ("warm_start", 2), ("path", 6), ("path", -1)])
 def test_closure_rejects_bad_options_before_device_work(field, value):
     from paper_1707_01007_amd import _abi
     lib = _lib()
@@ -158,8 +158,8 @@ def test_workspace_grows_with_sparse_temporaries():
     opt = _abi.Options()
     lib.cfpq_default_options(ctypes.byref(opt))
     sizes = {}
-    for name, path, hybrid in [("mfma_dense", 2, 0), ("bits_dense", 1, 0), ("rows", 3, 0), ("cols", 4, 0),
-                               ("bits_hybrid", 1, 1)]:
+    for name, path, hybrid in [("mfma_dense", 2, 0), ("fp4_dense", 5, 0), ("bits_dense", 1, 0), ("rows", 3, 0),
+                               ("cols", 4, 0), ("bits_hybrid", 1, 1)]:
         opt.path, opt.hybrid = path, hybrid
         sz = ctypes.c_size_t(0)
         assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz)) == 0
@@ -168,6 +168,8 @@ def test_workspace_grows_with_sparse_temporaries():
     kwords = (n + 63) // 64
     assert rs >= lib.cfpq_padded_rows(n) * (kwords // 16 + 1) * 8 + 256 and rs % 256 == 0
     assert sizes["rows"] == sizes["bits_dense"] + rs
+    assert sizes["fp4_dense"] == sizes["mfma_dense"] == sizes["bits_dense"] + mat  # one transposed right operand
+    assert lib.cfpq_product_workspace_bytes(n, 5) == lib.cfpq_product_workspace_bytes(n, 2) == mat
     assert sizes["cols"] == sizes["mfma_dense"] + 2 * mat + rs  # one right operand (B) transposed in both
     # hybrid: the COLS scratch, plus a transposed right operand, loop-start
     # snapshots and gained bits of every nonterminal, and their counts

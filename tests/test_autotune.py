@@ -53,11 +53,11 @@ def test_autotune_choice_is_used_and_exact():
     cfpq.tune_clear()
     for n in (700, 2048):
         e = cfpq.autotune(n)
-        assert e["path"] in ("mfma", "bits") and e["ms"] > 0 and len(e["candidates_ms"]) >= 2
+        assert e["path"] in ("fp4", "mfma", "bits") and e["ms"] > 0 and len(e["candidates_ms"]) >= 2
         assert min(e["candidates_ms"].values()) == pytest.approx(e["ms"])
         inst = configs.config3(n)
         res = cfpq.closure(inst.n, inst.edges, inst.grammar)
-        assert res.stats["path_used"] == {"bits": 1, "mfma": 2}[e["path"]]
+        assert res.stats["path_used"] == {"bits": 1, "mfma": 2, "fp4": 5}[e["path"]]
         assert np.array_equal(cfpq.result_bits(res), worklist.closure(inst.n, inst.edges, inst.grammar))
     # a forced choice through the table: every variant gives the same bits
     inst = configs.config3(1024)

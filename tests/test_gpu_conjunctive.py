@@ -48,7 +48,7 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
-@pytest.mark.parametrize("path", ["bits", "mfma"])
+@pytest.mark.parametrize("path", ["bits", "mfma", "fp4"])
 @pytest.mark.parametrize("schedule", ["inplace", "jacobi"])
 def test_conjunctive_matches_oracle(cfpq, name, path, schedule):
     n, e, g = CASES[name]()

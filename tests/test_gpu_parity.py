@@ -22,7 +22,7 @@ from workloads import configs, grammars, graphs
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
-PATHS = ["bits", "mfma", "rows", "cols"]
+PATHS = ["bits", "mfma", "fp4", "rows", "cols"]
 SCHEDULES = ["inplace", "jacobi"]
 
 
@@ -99,8 +99,8 @@ MAKERS = {
 
 
 @pytest.mark.parametrize("name", sorted(MAKERS))
-@pytest.mark.parametrize("path,hybrid", [("bits", 0), ("mfma", 0), ("rows", 0), ("cols", 0), ("bits", 1),
-                                         ("mfma", 1)])
+@pytest.mark.parametrize("path,hybrid", [("bits", 0), ("mfma", 0), ("fp4", 0), ("rows", 0), ("cols", 0),
+                                         ("bits", 1), ("mfma", 1), ("fp4", 1)])
 def test_workload_digest(cfpq, name, path, hybrid):
     inst = MAKERS[name]()
     bits, res = _run(cfpq, inst, path=path, hybrid=hybrid)
@@ -269,7 +269,7 @@ def test_closure_with_each_bits_tile(cfpq):
         assert np.array_equal(bits, want), tile
 
 
-@pytest.mark.parametrize("path,hybrid", [("auto", 0), ("auto", 1), ("bits", 1)])
+@pytest.mark.parametrize("path,hybrid", [("auto", 0), ("auto", 1), ("bits", 1), ("mfma", 0), ("fp4", 0)])
 def test_full_size_er16384(cfpq, path, hybrid):
     """The benchmark workload at full size (n = 16384, device-resident edges,
     the benchmark's launch configurations: the dense autotuned kernel, and the
@@ -328,7 +328,7 @@ def test_sparse_paths_under_jacobi_give_algorithm_1_loops(cfpq, path):
 
 # ---------------------------------------------------------------- warm start
 
-@pytest.mark.parametrize("path", ["bits", "mfma", "rows", "cols"])
+@pytest.mark.parametrize("path", PATHS)
 def test_warm_start_resumes_a_partial_result(cfpq, path):
     """A result cut short by max_iters (a sound subset of R) continues to R."""
     inst = configs.config3(1024)
