@@ -330,10 +330,15 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-closure section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--no-next", action="store_true", help="skip the single-path and conjunctive sections")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the dense closure only (every other section off), so that a kernel trace of "
+                         "the command holds exactly the timed products")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.headline_only:
+        args.no_next = args.no_batch = args.no_serve = args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on a single GPU "
               "(one GPU's throughput is the value)", file=sys.stderr)
@@ -419,8 +424,9 @@ def main():
                    "autotune": tuned},
         "roofline": roof,
     }
-    line["hybrid"] = bench_hybrid(cfpq, torch, inst, edges, out, args, wall / args.steps)
-    line["end_to_end"] = bench_end_to_end(cfpq, torch, inst)
+    if not args.headline_only:
+        line["hybrid"] = bench_hybrid(cfpq, torch, inst, edges, out, args, wall / args.steps)
+        line["end_to_end"] = bench_end_to_end(cfpq, torch, inst)
     if not args.no_next:
         line["small_configs"] = bench_small_configs(cfpq, torch)
     if not args.no_next:
