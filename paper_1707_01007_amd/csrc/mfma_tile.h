@@ -172,18 +172,20 @@ constexpr int kFp4Scale = 0;
 
 // Operand dwords of one 32-bit k-word w for the fp4 MFMA: dword q holds the
 // eight bits 4t + q of w (t = 0..7) as e2m1 nibbles, nibble t nonzero iff
-// that bit is set: q = 0, 1 put the bit at nibble position 1 (value 1.0),
-// q = 2, 3 at position 2 (value 2.0).  The four dwords carry all 32 bits, and
-// both operands give the same value at the same k, so every product term is
-// 1 or 4 and a sum is positive iff some k has both bits set.  Sums stay below
-// 4 * 2^19 < 2^24, exact in fp32 (and a positive sum of positive terms could
-// not round to zero anyway).
+// that bit is set.  Dwords 0..2 keep the bits in place (w & mask: nibble 0x1
+// = 0.5, the one subnormal, 0x2 = 1.0, 0x4 = 2.0); bit 3 of a nibble is the
+// sign, so dword 3 takes bits 4t + 3 shifted down to value 0.5.  Five VALU
+// instructions carry all 32 bits.  Both operands give the same value at the
+// same k, so every product term is 0.25, 1 or 4 and a sum is positive iff
+// some k has both bits set.  Sums are multiples of 0.25 below 4 * 2^19 = 2^21,
+// exact in fp32 (and a positive sum of positive terms could not round to
+// zero anyway).
 __device__ __forceinline__ v8i spread4(uint32_t w) {
     v8i r;
-    r[0] = static_cast<int>((w << 1) & 0x22222222u);
+    r[0] = static_cast<int>(w & 0x11111111u);
     r[1] = static_cast<int>(w & 0x22222222u);
     r[2] = static_cast<int>(w & 0x44444444u);
-    r[3] = static_cast<int>((w >> 1) & 0x44444444u);
+    r[3] = static_cast<int>((w >> 3) & 0x11111111u);
     r[4] = r[5] = r[6] = r[7] = 0;  // not read for fp4 operands
     return r;
 }
