@@ -79,9 +79,9 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
             if (o.hybrid == CFPQ_HYBRID_AUTO)
                 for (int32_t r = 0; r < d.n_rules; ++r)
                     md[r] = engine_rule_mode(gr->bin_rules, d.n_rules, r, g.n_edges, L.npad);
-            n_right = engine_right_slots(gr->bin_rules, d.n_rules, md.data(), d.n_nt, tr.data());
+            n_right = engine_trans_slots(gr->bin_rules, d.n_rules, md.data(), d.n_nt, tr.data());
             p.tt_off[i] = tt_bytes;
-            tt_bytes += static_cast<size_t>(n_right) * L.mat_words * 8;
+            tt_bytes += static_cast<size_t>(n_right) * L.mat_words * 8 + engine_rowbits_bytes(d.n_nt, L.W);
             p.large_rules += d.n_rules;
             p.large_trans += n_right;
         }
@@ -226,6 +226,11 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
         SlotDesc& d = p.descs[i];
         d.T = instances[i].d_result;
         d.TT = reinterpret_cast<uint64_t*>(ws + p.off_tt + p.tt_off[i]);
+        if (d.kind == kSlotLarge) {
+            int32_t n_right = 0;
+            for (int32_t a = 0; a < d.n_nt; ++a) n_right += p.trans[d.trans_off + a] >= 0 ? 1 : 0;
+            d.RD = d.TT + static_cast<size_t>(n_right) * d.npad * d.W;
+        }
         if (instances[i].graph.edges_on_device || p.edge_copy_off[i] == SIZE_MAX)
             d.edges = instances[i].graph.edges;
         else

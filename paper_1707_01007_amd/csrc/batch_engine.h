@@ -7,13 +7,13 @@
 //    right operand staged in LDS, change flags in LDS);
 //  * large: every loop, a plan kernel turns the dirty rules of all running
 //    large slots into work lists -- 256 x 256 fp4-MFMA tiles for dense rules,
-//    pulled from an atomic counter by a persistent kernel, and rows for rules
-//    whose left operand is derived from terminal rules only (a sparse edge
-//    matrix: the row-gather product reads just the rows of C its bits select),
-//    one wavefront per row in a second kernel of high occupancy; transposes of
-//    the right operands of dense rules that changed are rebuilt like the
-//    tiles, and a finish kernel counts the loop and retires slots that reached
-//    their fixpoint.  The loop is captured into a
+//    pulled from an atomic counter by a persistent kernel, and 64-row blocks
+//    of C for rules whose left operand is derived from terminal rules only (a
+//    sparse, fixed edge matrix B): a second kernel of high occupancy pushes
+//    every row of C that gained bits into the rows of A that B links to it
+//    (found in B^T); transposes that changed are rebuilt like the tiles, and
+//    a finish kernel counts the loop and retires slots that reached their
+//    fixpoint.  The loop is captured into a
 //    HIP graph once; which slots take part is data, so the same graph serves a
 //    batch that gains and loses members between replays.
 #pragma once
@@ -34,6 +34,8 @@ enum : int32_t { kSlotLarge = 1, kSlotSmall = 2 };
 struct SlotDesc {
     uint64_t* T;              // |N| result matrices (bit layout)
     uint64_t* TT;             // transposed right operands (large slots)
+    uint64_t* RD;             // large slots: changed-row bitmaps [2][n_nt][W] (by loop parity;
+                              // bit i of nonterminal a: row i of T_a gained bits in that loop)
     const cfpq_edge* edges;   // device edges
     int64_t n_edges;
     int64_t max_iters;
@@ -70,7 +72,7 @@ struct EngineState {
     int32_t running;  // large slots still running after the last finish
     int32_t n_large;  // entries of the large-slot list (set by the host between replays)
     int32_t n_rjobs;     // row-gather jobs of the loop, stored after the n_jobs tile jobs
-    int32_t total_rows;  // their rows (one wavefront each)
+    int32_t total_rows;  // their items: rows of A (first loop) or blocks of rows of C (one wavefront each)
     int32_t pad2[4];
 };
 
@@ -103,15 +105,23 @@ inline int32_t engine_rule_mode(const cfpq_bin_rule* rules, int32_t n_rules, int
     return n_edges <= npad * npad / 16 ? kModeRows : kModeDense;
 }
 
-// Transpose slots of a large slot: the right operands of its dense rules.
-// Fills trans[a] (slot or -1, n_nt entries) and returns the slot count.
-inline int32_t engine_right_slots(const cfpq_bin_rule* rules, int32_t n_rules, const int32_t* modes, int32_t n_nt,
+// Bytes of a large slot's changed-row bitmaps.
+inline size_t engine_rowbits_bytes(int32_t n_nt, int64_t W) {
+    return align_up(static_cast<size_t>(2) * n_nt * W * 8, 256);
+}
+
+// Transpose slots of a large slot: the right operands of its dense rules and
+// the left operands of its row-gather rules.  Fills trans[a] (slot or -1,
+// n_nt entries) and returns the slot count.
+inline int32_t engine_trans_slots(const cfpq_bin_rule* rules, int32_t n_rules, const int32_t* modes, int32_t n_nt,
                                   int32_t* trans) {
     for (int32_t a = 0; a < n_nt; ++a) trans[a] = -1;
-    int32_t n_right = 0;
-    for (int32_t r = 0; r < n_rules; ++r)
-        if (modes[r] == kModeDense && trans[rules[r].right] < 0) trans[rules[r].right] = n_right++;
-    return n_right;
+    int32_t count = 0;
+    for (int32_t r = 0; r < n_rules; ++r) {
+        const int32_t a = modes[r] == kModeRows ? rules[r].left : rules[r].right;
+        if (trans[a] < 0) trans[a] = count++;
+    }
+    return count;
 }
 
 // ---- launchers (batch_engine.hip) ----

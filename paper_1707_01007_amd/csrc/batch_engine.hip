@@ -176,6 +176,13 @@ __global__ __launch_bounds__(256) void engine_resident_kernel(const SlotDesc* __
 
 // ---------------------------------------------------------------- large slots
 
+// Rows of C per push item of a row-gather rule (a wavefront walks them one
+// after another, so few keep the loop's latency short).
+constexpr int kPushRows = 16;
+constexpr uint64_t kPushMask = (1ull << kPushRows) - 1;
+// Loops of a slot whose row-gather work is pulled by rows of A.
+constexpr int kPullLoops = 2;
+
 // Exclusive scan of per-thread (a, b) counts over one workgroup of 256; the
 // totals land in *ta, *tb.
 __device__ void scan2(int32_t* sa, int32_t* sb, int32_t& a, int32_t& b, int32_t* ta, int32_t* tb) {
@@ -223,8 +230,10 @@ __device__ void scan4(int32_t (*sh)[256], int32_t (&v)[4], int32_t* const (&tot)
 
 // Start of a loop: for every running large slot decide which rules run
 // (dirty worklist), clear the slot's change flags, and lay out the work lists:
-// 256 x 256 tiles of the dense rules (jobs[0, n_jobs)), and rows of the
-// row-gather rules (jobs[n_jobs, n_jobs + n_rjobs), item_begin counting rows).
+// 256 x 256 tiles of the dense rules (jobs[0, n_jobs)), and the items of the
+// row-gather rules (jobs[n_jobs, n_jobs + n_rjobs)): rows of A in a slot's
+// first kPullLoops loops (dim = 1), kPushRows-row blocks of C after them
+// (dim = 0).
 // Slots are handled in list order (largest first), so the biggest tiles are
 // handed out first.
 __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
@@ -251,6 +260,13 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
         }
         st->in_loop = 1;
         for (int a = 0; a < d.n_nt; ++a) st->changed[a] = 0;
+        if (d.RD != nullptr) {
+            // this loop's changed-row bitmaps (those of loop t - 2) start empty;
+            // n_nt * W words, W a multiple of 4: 16-byte stores
+            uint4* cur = reinterpret_cast<uint4*>(d.RD + static_cast<size_t>(st->iterations & 1) * d.n_nt * d.W);
+            const int64_t quads = static_cast<int64_t>(d.n_nt) * d.W / 2;
+            for (int64_t q = 0; q < quads; ++q) cur[q] = make_uint4(0, 0, 0, 0);
+        }
         const int dim = d.npad / 256;
         int launched = 0;
         for (int r = 0; r < d.n_rules; ++r) {
@@ -262,7 +278,7 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             if (!go) continue;
             if (mode_tab[d.rule_off + r] == kModeRows) {
                 ++my_rjobs;
-                my_rows += d.n;
+                my_rows += st->iterations < kPullLoops ? d.n : (d.n + kPushRows - 1) / kPushRows;
             } else {
                 ++my_jobs;
                 my_items += dim * dim;
@@ -288,8 +304,9 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
         for (int r = 0; r < d.n_rules; ++r) {
             if (!go_tab[d.rule_off + r]) continue;
             if (mode_tab[d.rule_off + r] == kModeRows) {
-                rjobs[my_rjobs++] = Job{slot, r, my_rows, 0};
-                my_rows += d.n;
+                const bool pull = states[slot].iterations < kPullLoops;
+                rjobs[my_rjobs++] = Job{slot, r, my_rows, pull ? 1 : 0};
+                my_rows += pull ? d.n : (d.n + kPushRows - 1) / kPushRows;
             } else {
                 jobs[my_jobs++] = Job{slot, r, my_items, dim};
                 my_items += dim * dim;
@@ -298,13 +315,14 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
     }
 }
 
-// One row of A |= B x C for a row-gather rule, by one wavefront: the OR of
-// the rows of C selected by the bits of B's row (B is an edge matrix, so few),
-// with C read in place.  Other work of the loop may write the same row (rules
-// with one head), so new bits are OR-ed atomically.
+// One row of A |= B x C for a row-gather rule, by one wavefront (the first
+// loops, when most rows of C are new): the OR of the rows of C selected by the
+// bits of B's row.  Rows that gain bits get their bit in `arows`; other work
+// of the loop may write the same row (rules with one head), so the OR is
+// atomic.
 template <int WPL>
 __device__ void engine_gather_row(const SlotDesc& d, const uint64_t* Bm, const uint64_t* Cm, uint64_t* Am,
-                                  int64_t row, int32_t* changed) {
+                                  int64_t row, int32_t* changed, uint64_t* arows) {
     const int lane = threadIdx.x & 63;
     const int64_t W = d.W;
     const int32_t kwords = (d.n + 63) / 64;
@@ -327,13 +345,89 @@ __device__ void engine_gather_row(const SlotDesc& d, const uint64_t* Bm, const u
             }
         }
     }
-    if (__ballot(ch) != 0 && lane == 0) atomicOr(changed, 1);
+    if (__ballot(ch) != 0 && lane == 0) {
+        atomicOr(changed, 1);
+        atomicOr(reinterpret_cast<unsigned long long*>(arows + (row >> 6)), 1ull << (row & 63));
+    }
 }
 
-// The loop's row-gather work: every wavefront takes rows of the row list in
-// grid-stride order (rows of one slot and rule are contiguous in the list).
+// Rows k0 + b of C for a row-gather rule A -> B C, by one wavefront: every
+// row whose bit b is set in `dirty` is OR-ed into the rows
+// i of A with B[i, k] set -- the set bits of row k of BT = B^T.  WPL words of
+// each row per lane and pass.  Rows of A that gain bits get their bit in
+// `arows`; other work of the loop may write the same rows (rules with one
+// head), so the OR is atomic.
+template <int WPL>
+__device__ void engine_push_block(const SlotDesc& d, const uint64_t* BT, const uint64_t* Cm, uint64_t* Am,
+                                  int64_t k0, uint64_t dirty, int32_t* changed, uint64_t* arows) {
+    const int lane = threadIdx.x & 63;
+    const int64_t W = d.W;
+    const int32_t iwords = (d.n + 63) / 64;  // words of a row of B^T that can hold bits
+    bool any = false;
+    while (dirty != 0) {
+        const int64_t k = k0 + (__ffsll(static_cast<unsigned long long>(dirty)) - 1);
+        dirty &= dirty - 1;
+        const uint64_t* crow = Cm + k * W;
+        const uint64_t* trow = BT + k * W;
+        for (int64_t c0 = 0; c0 < W; c0 += 64 * WPL) {
+            uint64_t cw[WPL];
+            bool nz = false;
+#pragma unroll
+            for (int q = 0; q < WPL; ++q) {
+                const int64_t w = c0 + lane + 64 * q;
+                cw[q] = w < W ? crow[w] : 0;
+                nz = nz || cw[q] != 0;
+            }
+            if (__ballot(nz) == 0) continue;  // nothing to push in this pass
+            for (int32_t tb = 0; tb < iwords; tb += 64) {
+                const uint64_t tw = tb + lane < iwords ? trow[tb + lane] : 0;
+                uint64_t nzl = __ballot(tw != 0);
+                while (nzl != 0) {
+                    const int l = __ffsll(static_cast<unsigned long long>(nzl)) - 1;
+                    nzl &= nzl - 1;
+                    uint64_t bits = rowor::readlane64(tw, l);
+                    while (bits != 0) {
+                        const int64_t i = static_cast<int64_t>(tb + l) * 64 +
+                                          (__ffsll(static_cast<unsigned long long>(bits)) - 1);
+                        bits &= bits - 1;
+                        uint64_t* arow = Am + i * W;
+                        bool gained = false;
+#pragma unroll
+                        for (int q = 0; q < WPL; ++q) {
+                            const int64_t w = c0 + lane + 64 * q;
+                            if (cw[q] != 0 && (cw[q] & ~arow[w]) != 0) {
+                                const unsigned long long prev = atomicOr(
+                                    reinterpret_cast<unsigned long long*>(arow + w),
+                                    static_cast<unsigned long long>(cw[q]));
+                                gained = gained || (cw[q] & ~prev) != 0;
+                            }
+                        }
+                        if (__ballot(gained) != 0) {
+                            any = true;
+                            if (lane == 0)
+                                atomicOr(reinterpret_cast<unsigned long long*>(arows + (i >> 6)), 1ull << (i & 63));
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (any && lane == 0) atomicOr(changed, 1);
+}
+
+// The loop's row-gather work, one wavefront per item, grid-stride (items of
+// one slot and rule are contiguous in the list).  In a slot's first
+// kPullLoops loops (most rows of C are new) an item is a row of A, gathered
+// from the rows of C its row of B selects.  After that the work is pushed
+// from the rows of C, semi-naive by rows: B is
+// fixed after initialisation, and the last time the rule ran it read C no
+// earlier than the start of the previous loop (a rule skipped by the dirty
+// worklist had an unchanged C before that), so only the rows of C that
+// gained bits in the previous or the current loop (bitmaps of both loop
+// parities) can add to A; an item is a block of kPushRows rows of C.
 __global__ __launch_bounds__(256) void engine_rows_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
                                                           const int32_t* __restrict__ rules_tab,
+                                                          const int32_t* __restrict__ trans_tab,
                                                           const Job* __restrict__ jobs,
                                                           const EngineState* __restrict__ es) {
     const int n_rjobs = es->n_rjobs;
@@ -346,12 +440,28 @@ __global__ __launch_bounds__(256) void engine_rows_kernel(const SlotDesc* __rest
         const int r = d.rule_off + jb.what;
         const int ra = rules_tab[3 * r], rb = rules_tab[3 * r + 1], rc = rules_tab[3 * r + 2];
         const size_t mw = static_cast<size_t>(d.npad) * d.W;
-        const int64_t row = x - jb.item_begin;
+        const int64_t it = states[jb.slot].iterations;
+        const size_t bw = static_cast<size_t>(d.W);
+        uint64_t* cur = d.RD + static_cast<size_t>(it & 1) * d.n_nt * bw;
+        const uint64_t* prev = d.RD + static_cast<size_t>((it + 1) & 1) * d.n_nt * bw;
         int32_t* changed = &states[jb.slot].changed[ra];
+        if (jb.dim == 1) {  // pull: x - item_begin is a row of A
+            const int64_t row = x - jb.item_begin;
+            if (d.W <= 64)
+                engine_gather_row<1>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed, cur + ra * bw);
+            else
+                engine_gather_row<4>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed, cur + ra * bw);
+            continue;
+        }
+        const int64_t k0 = static_cast<int64_t>(x - jb.item_begin) * kPushRows;
+        const int shift = static_cast<int>(k0 & 63);
+        const uint64_t dirty = ((cur[rc * bw + (k0 >> 6)] | prev[rc * bw + (k0 >> 6)]) >> shift) & kPushMask;
+        if (dirty == 0) continue;
+        const uint64_t* BT = d.TT + static_cast<size_t>(trans_tab[d.trans_off + rb]) * mw;
         if (d.W <= 64)
-            engine_gather_row<1>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed);
+            engine_push_block<1>(d, BT, d.T + rc * mw, d.T + ra * mw, k0, dirty, changed, cur + ra * bw);
         else
-            engine_gather_row<4>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed);
+            engine_push_block<4>(d, BT, d.T + rc * mw, d.T + ra * mw, k0, dirty, changed, cur + ra * bw);
     }
 }
 
@@ -379,8 +489,9 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
         const uint32_t* CT = reinterpret_cast<const uint32_t*>(d.TT) + trans_tab[d.trans_off + rc] * mdw;
         uint32_t* Am = reinterpret_cast<uint32_t*>(d.T) + ra * mdw;
         const int kchunks = (d.n + 255) / 256;  // 256-k chunks of the fp4 tile
+        uint64_t* rows = d.RD + (static_cast<size_t>(states[jb.slot].iterations & 1) * d.n_nt + ra) * d.W;
         mfma::mfma4_tile<true>(Bm, CT, Am, 2 * d.W, kchunks, local / jb.dim, local % jb.dim,
-                               &states[jb.slot].changed[ra]);
+                               &states[jb.slot].changed[ra], rows);
     }
 }
 
@@ -516,8 +627,8 @@ hipError_t engine_products(const EngineBuffers& b, int32_t grid, hipStream_t s) 
                                                                                 b.trans_tab, b.jobs, b.es);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    engine_rows_kernel<<<dim3(static_cast<unsigned>(4 * grid)), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab,
-                                                                                 b.jobs, b.es);
+    engine_rows_kernel<<<dim3(static_cast<unsigned>(2 * grid)), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab,
+                                                                                 b.trans_tab, b.jobs, b.es);
     return hipGetLastError();
 }
 

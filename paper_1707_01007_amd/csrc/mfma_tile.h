@@ -70,10 +70,11 @@ __device__ __forceinline__ void mma_chunk(v16i (&acc)[kJT][kIT], const Chunk& ch
 // kAtomic: OR new bits into A with 64-bit atomics (needed when other
 // workgroups may update the same words concurrently, e.g. two rules with the
 // same head in one batched loop); otherwise a plain read-modify-write by the
-// tile's only writer.
+// tile's only writer.  rowbits (optional): bitmap over the rows of A; the
+// bits of rows that gained bits are OR-ed in.
 template <bool kAtomic, typename Acc>
 __device__ __forceinline__ void store_tile(const Acc (&acc)[kJT][kIT], uint32_t* Am, int W2, int i0, int j0, int g,
-                                           int r32, int lane, int32_t* changed) {
+                                           int r32, int lane, int32_t* changed, uint64_t* rowbits = nullptr) {
     bool ch = false;
 #pragma unroll
     for (int ib = 0; ib < kIT; ++ib) {
@@ -96,15 +97,26 @@ __device__ __forceinline__ void store_tile(const Acc (&acc)[kJT][kIT], uint32_t*
         const int i = i0 + ib * 32 + r32;
         uint64_t* dst = reinterpret_cast<uint64_t*>(Am + static_cast<size_t>(i) * W2) + (j0 / 64) + g;
         const uint64_t old = *dst;
+        bool gained = false;
         if ((add & ~old) != 0) {
             if (kAtomic) {
                 const uint64_t prev = atomicOr(reinterpret_cast<unsigned long long*>(dst),
                                                static_cast<unsigned long long>(add));
-                if ((add & ~prev) != 0) ch = true;
+                gained = (add & ~prev) != 0;
             } else {
                 *dst = old | add;
-                ch = true;
+                gained = true;
             }
+        }
+        ch = ch || gained;
+        if (rowbits != nullptr) {
+            // rows i0 + 32 ib .. + 31 (lanes r32 of both halves) lie in one 64-row word
+            const uint64_t m = __ballot(gained);
+            const uint64_t rows = (m | (m >> 32)) & 0xFFFFFFFFull;
+            const int base = i0 + ib * 32;
+            if (lane == 0 && rows != 0)
+                atomicOr(reinterpret_cast<unsigned long long*>(rowbits + (base >> 6)),
+                         static_cast<unsigned long long>(rows << (base & 63)));
         }
     }
     if (__ballot(ch) != 0 && lane == 0) atomicOr(changed, 1);
@@ -215,7 +227,7 @@ __device__ __forceinline__ void mma_chunk4(v16f (&acc)[kJT][kIT], const Chunk& c
 template <bool kAtomic>
 __device__ __forceinline__ void mfma4_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
                                            uint32_t* Am, int W2, int kchunks, int tile_i, int tile_j,
-                                           int32_t* changed) {
+                                           int32_t* changed, uint64_t* rowbits = nullptr) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 5;
@@ -258,7 +270,7 @@ __device__ __forceinline__ void mfma4_tile(const uint32_t* __restrict__ Bm, cons
     }
     if (kc < kchunks) mma_chunk4(acc, buf0);
 
-    store_tile<kAtomic>(acc, Am, W2, i0, j0, g, r32, lane, changed);
+    store_tile<kAtomic>(acc, Am, W2, i0, j0, g, r32, lane, changed, rowbits);
 }
 
 }  // namespace mfma

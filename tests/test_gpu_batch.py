@@ -124,12 +124,15 @@ def test_batch_capture_depths(cfpq, capture):
         assert np.array_equal(cfpq.result_bits(r), worklist.closure(inst.n, inst.edges, inst.grammar)), inst.tag
 
 
-def test_batch_row_gather_rules(cfpq):
+@pytest.mark.parametrize("dirty", [True, False])
+def test_batch_row_gather_rules(cfpq, dirty):
     """Larger instances whose edge-matrix rules run as row gathers (hybrid on)
     against the oracle: ragged sizes past several 256-row tiles, a node with
-    thousands of out-edges (one long row), two rules with one head, and a
-    graph too dense for the gather (tiles only); the same bits with hybrid
-    off."""
+    hundreds of out-edges (one long row of B, and every row of C pushed into
+    it), two rules with one head, and a graph too dense for the gather (tiles
+    only); the same bits with hybrid off.  With and without the dirty-rule
+    worklist (the rows pushed after the first loops are those that changed
+    since the rule last read them, in either case)."""
     insts = []
     n, e = graphs.erdos_renyi(1000, 3000, 41, labels=2)
     insts.append(configs.Instance(n, e, grammars.dyck(), "er1000"))
@@ -141,10 +144,11 @@ def test_batch_row_gather_rules(cfpq):
     n, e = graphs.erdos_renyi(600, 40000, 43, labels=2)
     insts.append(configs.Instance(n, e, grammars.dyck(), "er600_dense"))
     _say("row-gather batch", [i.tag for i in insts])
-    on = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], hybrid=1)
-    off = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], hybrid=0)
+    on = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], hybrid=1, dirty=dirty)
+    off = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], hybrid=0, dirty=dirty)
     for inst, a, b in zip(insts, on, off):
         want = worklist.closure(inst.n, inst.edges, inst.grammar)
         assert np.array_equal(cfpq.result_bits(a), want), inst.tag
         assert np.array_equal(cfpq.result_bits(b), want), inst.tag
         assert a.stats["converged"] == 1
+        assert a.stats["iterations"] > 2 or inst.tag == "er600_dense"  # the push loops ran
