@@ -79,7 +79,7 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
             if (o.hybrid == CFPQ_HYBRID_AUTO)
                 for (int32_t r = 0; r < d.n_rules; ++r)
                     md[r] = engine_rule_mode(gr->bin_rules, d.n_rules, r, g.n_edges, L.npad);
-            n_right = engine_trans_slots(gr->bin_rules, d.n_rules, md.data(), d.n_nt, tr.data());
+            n_right = engine_trans_slots(gr->bin_rules, d.n_rules, md.data(), d.n_nt, true, tr.data());
             p.tt_off[i] = tt_bytes;
             tt_bytes += static_cast<size_t>(n_right) * L.mat_words * 8 + engine_rowbits_bytes(d.n_nt, L.W);
             p.large_rules += d.n_rules;

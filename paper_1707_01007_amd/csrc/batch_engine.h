@@ -9,11 +9,12 @@
 //    large slots into work lists -- 256 x 256 fp4-MFMA tiles for dense rules,
 //    pulled from an atomic counter by a persistent kernel, and 64-row blocks
 //    of C for rules whose left operand is derived from terminal rules only (a
-//    sparse, fixed edge matrix B): a second kernel of high occupancy pushes
-//    every row of C that gained bits into the rows of A that B links to it
-//    (found in B^T); transposes that changed are rebuilt like the tiles, and
-//    a finish kernel counts the loop and retires slots that reached their
-//    fixpoint.  The loop is captured into a
+//    sparse, fixed edge matrix B): a second kernel of high occupancy gathers
+//    each row of A from the rows of C its row of B selects or (batch slots,
+//    after the first loops) pushes every row of C that gained bits into the
+//    rows of A that B links to it (found in B^T); transposes that changed are
+//    rebuilt like the tiles, and a finish kernel counts the loop and retires
+//    slots that reached their fixpoint.  The loop is captured into a
 //    HIP graph once; which slots take part is data, so the same graph serves a
 //    batch that gains and loses members between replays.
 #pragma once
@@ -34,8 +35,9 @@ enum : int32_t { kSlotLarge = 1, kSlotSmall = 2 };
 struct SlotDesc {
     uint64_t* T;              // |N| result matrices (bit layout)
     uint64_t* TT;             // transposed right operands (large slots)
-    uint64_t* RD;             // large slots: changed-row bitmaps [2][n_nt][W] (by loop parity;
-                              // bit i of nonterminal a: row i of T_a gained bits in that loop)
+    uint64_t* RD;             // large slots with push: changed-row bitmaps [2][n_nt][W] (by loop
+                              // parity; bit i of nonterminal a: row i of T_a gained bits in that
+                              // loop); nullptr: row-gather rules pull in every loop
     const cfpq_edge* edges;   // device edges
     int64_t n_edges;
     int64_t max_iters;
@@ -110,14 +112,15 @@ inline size_t engine_rowbits_bytes(int32_t n_nt, int64_t W) {
     return align_up(static_cast<size_t>(2) * n_nt * W * 8, 256);
 }
 
-// Transpose slots of a large slot: the right operands of its dense rules and
-// the left operands of its row-gather rules.  Fills trans[a] (slot or -1,
-// n_nt entries) and returns the slot count.
+// Transpose slots of a large slot: the right operands of its dense rules and,
+// with push, the left operands of its row-gather rules.  Fills trans[a] (slot
+// or -1, n_nt entries) and returns the slot count.
 inline int32_t engine_trans_slots(const cfpq_bin_rule* rules, int32_t n_rules, const int32_t* modes, int32_t n_nt,
-                                  int32_t* trans) {
+                                  bool push, int32_t* trans) {
     for (int32_t a = 0; a < n_nt; ++a) trans[a] = -1;
     int32_t count = 0;
     for (int32_t r = 0; r < n_rules; ++r) {
+        if (modes[r] == kModeRows && !push) continue;
         const int32_t a = modes[r] == kModeRows ? rules[r].left : rules[r].right;
         if (trans[a] < 0) trans[a] = count++;
     }

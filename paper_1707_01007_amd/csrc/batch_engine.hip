@@ -232,8 +232,8 @@ __device__ void scan4(int32_t (*sh)[256], int32_t (&v)[4], int32_t* const (&tot)
 // (dirty worklist), clear the slot's change flags, and lay out the work lists:
 // 256 x 256 tiles of the dense rules (jobs[0, n_jobs)), and the items of the
 // row-gather rules (jobs[n_jobs, n_jobs + n_rjobs)): rows of A in a slot's
-// first kPullLoops loops (dim = 1), kPushRows-row blocks of C after them
-// (dim = 0).
+// first kPullLoops loops and in every loop of a slot without changed-row
+// bitmaps (dim = 1), kPushRows-row blocks of C otherwise (dim = 0).
 // Slots are handled in list order (largest first), so the biggest tiles are
 // handed out first.
 __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             if (!go) continue;
             if (mode_tab[d.rule_off + r] == kModeRows) {
                 ++my_rjobs;
-                my_rows += st->iterations < kPullLoops ? d.n : (d.n + kPushRows - 1) / kPushRows;
+                my_rows += (st->iterations < kPullLoops || d.RD == nullptr) ? d.n : (d.n + kPushRows - 1) / kPushRows;
             } else {
                 ++my_jobs;
                 my_items += dim * dim;
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
         for (int r = 0; r < d.n_rules; ++r) {
             if (!go_tab[d.rule_off + r]) continue;
             if (mode_tab[d.rule_off + r] == kModeRows) {
-                const bool pull = states[slot].iterations < kPullLoops;
+                const bool pull = states[slot].iterations < kPullLoops || d.RD == nullptr;
                 rjobs[my_rjobs++] = Job{slot, r, my_rows, pull ? 1 : 0};
                 my_rows += pull ? d.n : (d.n + kPushRows - 1) / kPushRows;
             } else {
@@ -347,7 +347,8 @@ __device__ void engine_gather_row(const SlotDesc& d, const uint64_t* Bm, const u
     }
     if (__ballot(ch) != 0 && lane == 0) {
         atomicOr(changed, 1);
-        atomicOr(reinterpret_cast<unsigned long long*>(arows + (row >> 6)), 1ull << (row & 63));
+        if (arows != nullptr)
+            atomicOr(reinterpret_cast<unsigned long long*>(arows + (row >> 6)), 1ull << (row & 63));
     }
 }
 
@@ -417,9 +418,10 @@ __device__ void engine_push_block(const SlotDesc& d, const uint64_t* BT, const u
 
 // The loop's row-gather work, one wavefront per item, grid-stride (items of
 // one slot and rule are contiguous in the list).  In a slot's first
-// kPullLoops loops (most rows of C are new) an item is a row of A, gathered
-// from the rows of C its row of B selects.  After that the work is pushed
-// from the rows of C, semi-naive by rows: B is
+// kPullLoops loops (most rows of C are new), and in every loop of a slot
+// without changed-row bitmaps, an item is a row of A, gathered from the rows
+// of C its row of B selects.  Otherwise the work is pushed from the rows of
+// C, semi-naive by rows: B is
 // fixed after initialisation, and the last time the rule ran it read C no
 // earlier than the start of the previous loop (a rule skipped by the dirty
 // worklist had an unchanged C before that), so only the rows of C that
@@ -442,17 +444,18 @@ __global__ __launch_bounds__(256) void engine_rows_kernel(const SlotDesc* __rest
         const size_t mw = static_cast<size_t>(d.npad) * d.W;
         const int64_t it = states[jb.slot].iterations;
         const size_t bw = static_cast<size_t>(d.W);
-        uint64_t* cur = d.RD + static_cast<size_t>(it & 1) * d.n_nt * bw;
-        const uint64_t* prev = d.RD + static_cast<size_t>((it + 1) & 1) * d.n_nt * bw;
         int32_t* changed = &states[jb.slot].changed[ra];
         if (jb.dim == 1) {  // pull: x - item_begin is a row of A
             const int64_t row = x - jb.item_begin;
+            uint64_t* arows = d.RD ? d.RD + (static_cast<size_t>(it & 1) * d.n_nt + ra) * bw : nullptr;
             if (d.W <= 64)
-                engine_gather_row<1>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed, cur + ra * bw);
+                engine_gather_row<1>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed, arows);
             else
-                engine_gather_row<4>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed, cur + ra * bw);
+                engine_gather_row<4>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed, arows);
             continue;
         }
+        uint64_t* cur = d.RD + static_cast<size_t>(it & 1) * d.n_nt * bw;
+        const uint64_t* prev = d.RD + static_cast<size_t>((it + 1) & 1) * d.n_nt * bw;
         const int64_t k0 = static_cast<int64_t>(x - jb.item_begin) * kPushRows;
         const int shift = static_cast<int>(k0 & 63);
         const uint64_t dirty = ((cur[rc * bw + (k0 >> 6)] | prev[rc * bw + (k0 >> 6)]) >> shift) & kPushMask;
@@ -489,7 +492,8 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
         const uint32_t* CT = reinterpret_cast<const uint32_t*>(d.TT) + trans_tab[d.trans_off + rc] * mdw;
         uint32_t* Am = reinterpret_cast<uint32_t*>(d.T) + ra * mdw;
         const int kchunks = (d.n + 255) / 256;  // 256-k chunks of the fp4 tile
-        uint64_t* rows = d.RD + (static_cast<size_t>(states[jb.slot].iterations & 1) * d.n_nt + ra) * d.W;
+        uint64_t* rows =
+            d.RD ? d.RD + (static_cast<size_t>(states[jb.slot].iterations & 1) * d.n_nt + ra) * d.W : nullptr;
         mfma::mfma4_tile<true>(Bm, CT, Am, 2 * d.W, kchunks, local / jb.dim, local % jb.dim,
                                &states[jb.slot].changed[ra], rows);
     }

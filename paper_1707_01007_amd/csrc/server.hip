@@ -197,7 +197,7 @@ size_t footprint_of(const Request& r) {
     }
     const size_t mat = static_cast<size_t>(r.L.mat_words) * 8;
     size_t f = align_up(mat * r.n_nt, 256);
-    if (!r.small) f += align_up(mat * r.n_right, 256) + engine_rowbits_bytes(r.n_nt, r.L.W);
+    if (!r.small) f += align_up(mat * r.n_right, 256);
     f += align_up(r.host_edges.size() * sizeof(cfpq_edge), 256);
     return f;
 }
@@ -222,11 +222,7 @@ void fill_slot(cfpq_server* srv, Request& r, SlotDesc& d, std::vector<int32_t>& 
     d.T = reinterpret_cast<uint64_t*>(base);
     size_t off = align_up(mat * r.n_nt, 256);
     d.TT = reinterpret_cast<uint64_t*>(base + off);
-    if (!r.small) {
-        off += align_up(mat * r.n_right, 256);
-        d.RD = reinterpret_cast<uint64_t*>(base + off);
-        off += engine_rowbits_bytes(r.n_nt, r.L.W);
-    }
+    if (!r.small) off += align_up(mat * r.n_right, 256);
     d.edges = r.dev_edges ? r.dev_edges : reinterpret_cast<const cfpq_edge*>(base + off);
     d.n_edges = r.n_edges;
     d.n = r.n;
@@ -249,7 +245,7 @@ void fill_slot(cfpq_server* srv, Request& r, SlotDesc& d, std::vector<int32_t>& 
     d.trans_off = s * CFPQ_MAX_NONTERMINALS;
     trans.assign(CFPQ_MAX_NONTERMINALS, -1);
     if (!r.small) engine_trans_slots(r.bin.data(), static_cast<int32_t>(r.bin.size()), r.modes.data(), r.n_nt,
-                                     trans.data());
+                                     false, trans.data());
     d.n_terminals = r.n_terminals;
     d.term_off = s * kTermStride;
     d.term_lhs_off = d.term_off + kSrvMaxTerminals + 1;
@@ -693,7 +689,7 @@ cfpq_status cfpq_server_submit(cfpq_server* srv, const cfpq_graph* graph, const 
     if (!r->small && !r->lane) {
         for (int32_t q = 0; q < nb; ++q) r->modes[q] = engine_rule_mode(r->bin.data(), nb, q, r->n_edges, r->L.npad);
         std::vector<int32_t> tr(r->n_nt);
-        r->n_right = engine_trans_slots(r->bin.data(), nb, r->modes.data(), r->n_nt, tr.data());
+        r->n_right = engine_trans_slots(r->bin.data(), nb, r->modes.data(), r->n_nt, false, tr.data());
     }
     r->footprint = footprint_of(*r);
     if (r->footprint > srv->arena_size)
