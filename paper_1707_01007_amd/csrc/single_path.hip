@@ -60,10 +60,31 @@ __global__ void delta_kernel(const uint64_t* __restrict__ Y, const uint64_t* __r
         D[w] = Y[w] & ~X[w];
 }
 
+// Chunks of 32 k whose skip mask one pass builds (LDS bits).
+constexpr int32_t kSegChunks = 1024;
+
+// First chunk >= from (< n) whose bit is set in m, or -1.  Every thread of
+// the workgroup gets the same answer (m is in LDS).
+__device__ __forceinline__ int32_t next_chunk(const uint32_t* m, int32_t from, int32_t n) {
+    for (int32_t c = from; c < n;) {
+        const uint32_t w = m[c >> 5] >> (c & 31);
+        if (w) {
+            const int32_t r = c + __ffs(w) - 1;
+            return r < n ? r : -1;
+        }
+        c = (c | 31) + 1;
+    }
+    return -1;
+}
+
 // One workgroup per 64 x 64 output tile; 16 x 16 threads, 4 x 4 cells each.
 // Operand chunks of 32 k are staged in LDS k-major, already masked to kInf
-// where the previous step's bit is clear; chunks where either operand block
-// is empty are skipped.
+// where the previous step's bit is clear.  A first pass over the tile's row
+// block of X_B and column word of X_C marks the chunks where both operand
+// blocks hold bits (segments of kSegChunks chunks); only those are staged
+// and multiplied.  (Prefetching the next chunk into registers while the
+// current one is multiplied needed 154 VGPRs and ran slower: occupancy,
+// not the staging latency, hides the loads.)
 __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict__ D, const uint64_t* __restrict__ XB,
                                                       const uint64_t* __restrict__ XC, const uint32_t* LB,
                                                       const uint32_t* LC, uint32_t* LA, int64_t W, int64_t npad,
@@ -74,7 +95,7 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
     const int t = threadIdx.x;
     __shared__ __align__(16) uint32_t As[32][64 + 4];  // As[kk][i]
     __shared__ __align__(16) uint32_t Bs[32][64 + 4];  // Bs[kk][j]
-    __shared__ int any_b, any_c;
+    __shared__ uint32_t bmask[kSegChunks / 32], cmask[kSegChunks / 32];
     // the tile's new cells
     const uint64_t dword = t < 64 ? D[(i0 + t) * W + jw] : 0;
     if (!__syncthreads_or(dword != 0)) return;
@@ -85,51 +106,65 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = 0xFFFFFFFFu;
-    for (int32_t kc = 0; kc < kchunks; ++kc) {
-        const int64_t k0 = static_cast<int64_t>(kc) * 32;
-        // skip a chunk when X_B[i0.., k0..k0+31] or X_C[k0..k0+31, j0..] is empty
-        if (t == 0) {
-            any_b = 0;
-            any_c = 0;
+    for (int32_t seg0 = 0; seg0 < kchunks; seg0 += kSegChunks) {
+        const int32_t seg_n = min(kSegChunks, kchunks - seg0);
+        // ---- chunk marks: bit c = chunk seg0 + c has bits in both operand blocks
+        __syncthreads();  // the previous segment's marks and buffers are no longer read
+        if (t < kSegChunks / 32) {
+            bmask[t] = 0;
+            cmask[t] = 0;
         }
         __syncthreads();
-        if (t < 64) {
-            const uint32_t half = static_cast<uint32_t>(XB[(i0 + t) * W + (k0 >> 6)] >> (k0 & 63));
-            if (half) any_b = 1;
-        } else if (t < 96) {
-            if (XC[(k0 + (t - 64)) * W + jw]) any_c = 1;
+        const int32_t bwords = (seg_n + 1) / 2;  // 64-bit k-words of X_B rows (two chunks each)
+        for (int32_t e = t; e < 64 * bwords; e += 256) {
+            const int32_t r = e / bwords, wq = e % bwords;
+            const uint64_t x = XB[(i0 + r) * W + seg0 / 2 + wq];  // seg0 is even
+            const uint32_t two = (static_cast<uint32_t>(x) != 0 ? 1u : 0u) | ((x >> 32) != 0 ? 2u : 0u);
+            if (two) atomicOr(&bmask[(2 * wq) >> 5], two << ((2 * wq) & 31));
+        }
+        for (int32_t e = t; e < seg_n * 32; e += 256) {
+            const int64_t k = static_cast<int64_t>(seg0) * 32 + e;  // < 32 * kchunks <= npad
+            if (XC[k * W + jw]) atomicOr(&cmask[(e >> 5) >> 5], 1u << ((e >> 5) & 31));
         }
         __syncthreads();
-        const bool skip = !any_b || !any_c;
-        __syncthreads();  // every thread has read the flags before they are reset
-        if (skip) continue;  // uniform
-        ++done_chunks;
-        // stage: 64 x 32 of L_B (rows i, cols k) and 32 x 64 of L_C (rows k, cols j)
+        if (t < kSegChunks / 32) bmask[t] &= cmask[t];
+        __syncthreads();
+        // ---- the marked chunks
+        for (int32_t c = next_chunk(bmask, 0, seg_n); c >= 0; c = next_chunk(bmask, c + 1, seg_n)) {
+            const int64_t k0 = static_cast<int64_t>(seg0 + c) * 32;
+            // stage: 64 x 32 of L_B (rows i, cols k) and 32 x 64 of L_C (rows k,
+            // cols j); thread t takes rows i0 + t/32 + 8q of column k0 + t%32 of
+            // L_B and rows k0 + t/64 + 4q of column 64 jw + t%64 of L_C, q < 8
+            // (all below npad: k0 + 31 < 32 * kchunks <= npad)
+            const int bi = t >> 5, bk = t & 31, ck = t >> 6, cj = t & 63;
+            const int64_t bcol = k0 + bk;
+            const uint32_t* lbp = LB + (i0 + bi) * npad + bcol;
+            const uint64_t* xbp = XB + (i0 + bi) * W + (bcol >> 6);
+            const uint32_t* lcp = LC + (k0 + ck) * npad + 64 * jw + cj;
+            const uint64_t* xcp = XC + (k0 + ck) * W + jw;
+            const int bsh = static_cast<int>(bcol & 63);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int e = t + 256 * q;  // 0..2047
-            const int ii = e >> 5, kk = e & 31;
-            const int64_t row = i0 + ii, col = k0 + kk;
-            const bool set = (XB[row * W + (col >> 6)] >> (col & 63)) & 1ull;
-            As[kk][ii] = set ? LB[row * npad + col] : kInf;
-            const int kr = e >> 6, jj = e & 63;
-            const int64_t krow = k0 + kr;
-            const bool cset = (XC[krow * W + jw] >> jj) & 1ull;
-            Bs[kr][jj] = cset ? LC[krow * npad + 64 * jw + jj] : kInf;
-        }
-        __syncthreads();
+            for (int q = 0; q < 8; ++q) {
+                const bool set = (xbp[q * 8 * W] >> bsh) & 1ull;
+                As[bk][bi + 8 * q] = set ? lbp[q * 8 * npad] : kInf;
+                const bool cset = (xcp[q * 4 * W] >> cj) & 1ull;
+                Bs[ck + 4 * q][cj] = cset ? lcp[q * 4 * npad] : kInf;
+            }
+            __syncthreads();
 #pragma unroll 8
-        for (int kk = 0; kk < 32; ++kk) {
-            const uint4 a = *reinterpret_cast<const uint4*>(&As[kk][ty * 4]);
-            const uint4 b = *reinterpret_cast<const uint4*>(&Bs[kk][tx * 4]);
-            const uint32_t av[4] = {a.x, a.y, a.z, a.w};
-            const uint32_t bv[4] = {b.x, b.y, b.z, b.w};
+            for (int kk = 0; kk < 32; ++kk) {
+                const uint4 a = *reinterpret_cast<const uint4*>(&As[kk][ty * 4]);
+                const uint4 b = *reinterpret_cast<const uint4*>(&Bs[kk][tx * 4]);
+                const uint32_t av[4] = {a.x, a.y, a.z, a.w};
+                const uint32_t bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+                for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = min(acc[r][c], av[r] + bv[c]);
+                    for (int q = 0; q < 4; ++q) acc[r][q] = min(acc[r][q], av[r] + bv[q]);
+            }
+            ++done_chunks;
+            __syncthreads();  // every thread is done with the chunk before the next is staged
         }
-        __syncthreads();
     }
     if (t == 0 && done_chunks) atomicAdd(cells, static_cast<unsigned long long>(done_chunks) * 32 * 64 * 64);
     // new cells only: min with what an earlier rule of this loop stored
