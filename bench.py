@@ -332,6 +332,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-closure section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--no-next", action="store_true", help="skip the single-path and conjunctive sections")
+    ap.add_argument("--section", choices=["single_path", "conjunctive", "small_configs", "batch"],
+                    help="run only this section and print its JSON object (for profiling a kernel that the "
+                         "section runs; no headline line)")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the dense closure only (every other section off), so that a kernel trace of "
                          "the command holds exactly the timed products")
@@ -361,6 +364,11 @@ def main():
     from workloads import configs
 
     torch.cuda.set_device(0)
+    if args.section:
+        fn = {"single_path": bench_single_path, "conjunctive": bench_conjunctive,
+              "small_configs": bench_small_configs, "batch": bench_batch}[args.section]
+        print(json.dumps({"section": args.section, args.section: fn(cfpq, torch)}), flush=True)
+        return
     inst = configs.config3(args.n)
     g = inst.grammar
     edges = torch.from_numpy(inst.edges).cuda()
