@@ -381,7 +381,9 @@ CFPQ_API cfpq_status cfpq_batch_workspace_bytes(int32_t n_instances, const cfpq_
  * (0 = 8) per captured HIP graph.  With opt->hybrid AUTO (the default), a
  * rule of a larger instance whose left operand heads no binary rule (its
  * matrix is fixed by the edges) runs as row gathers instead of tiles when the
- * graph has at most npad^2 / 16 edges; OFF keeps every rule on the tiles.
+ * graph has at most npad^2 / 16 edges -- after the first two loops only the
+ * rows of its right operand that gained bits since it last ran are pushed
+ * into the result; OFF keeps every rule on the tiles.
  * Results are bit-identical to cfpq_closure on each instance alone.  opt:
  * schedule must be INPLACE and warm_start 0; dirty_worklist, capture,
  * hybrid and max_iters apply to every instance; path, tile and profile are
