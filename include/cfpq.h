@@ -195,6 +195,11 @@ CFPQ_API cfpq_status cfpq_workspace_bytes(const cfpq_graph* graph, const cfpq_gr
  *   stats            optional (NULL allowed)
  * Returns CFPQ_OK, CFPQ_ENOTCONV (max_iters reached, d_result is a sound
  * subset of R), CFPQ_EINVAL, CFPQ_ENOMEM (workspace too small) or CFPQ_EDEVICE.
+ * A graph of at most 512 padded rows with path AUTO, the in-place schedule, no
+ * profile and no warm start runs as a one-instance cfpq_batch_closure (the
+ * whole fixpoint in one workgroup, one launch; capture is ignored,
+ * stats.path_used is BITS, the loop count may differ from the loop here); the
+ * bits are the same.
  */
 CFPQ_API cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar,
                          const cfpq_options* opt, void* stream,

@@ -135,6 +135,17 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
     return CFPQ_OK;
 }
 
+}  // namespace
+
+size_t batch_workspace_one(const cfpq_graph& graph, const cfpq_grammar* grammar, const cfpq_options& o) {
+    const cfpq_instance inst{graph, grammar, nullptr};
+    BatchPlan p;
+    plan_batch(1, &inst, o, p);
+    return p.total;
+}
+
+namespace {
+
 cfpq_status validate_batch(int32_t n, const cfpq_instance* inst, const cfpq_options& o) {
     if (n < 0) return fail(CFPQ_EINVAL, "n_instances is negative");
     if (n > 0 && !inst) return fail(CFPQ_EINVAL, "instances is NULL");

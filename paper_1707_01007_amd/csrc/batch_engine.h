@@ -127,6 +127,11 @@ inline int32_t engine_trans_slots(const cfpq_bin_rule* rules, int32_t n_rules, c
     return count;
 }
 
+// Workspace bytes of cfpq_batch_closure for one instance (batch_api.hip);
+// the graph and grammar must be valid.  Used by cfpq_closure for closures it
+// runs as a one-instance batch.
+size_t batch_workspace_one(const cfpq_graph& graph, const cfpq_grammar* grammar, const cfpq_options& o);
+
 // ---- launchers (batch_engine.hip) ----
 hipError_t engine_zero(const EngineBuffers& b, const int32_t* ids, int32_t count, hipStream_t s);
 hipError_t engine_scatter(const EngineBuffers& b, const int32_t* ids, int32_t count, int64_t total_edges,

@@ -68,50 +68,37 @@ __global__ __launch_bounds__(256) void engine_scatter_kernel(const SlotDesc* __r
 
 // ---------------------------------------------------------------- small slots
 
-// One workgroup runs the whole fixpoint of one small slot (npad <= 512,
-// CW = 2 * W 32-bit words per row).  In-place schedule with the dirty-rule
-// worklist.  Thread t always owns rows t, t + 256, so a row of any matrix is
-// only ever written by one thread; the right operand of each product is staged
-// in LDS after a barrier, so every read sees all earlier writes of the
-// workgroup.  A loop in which no rule set a bit ends the fixpoint.
-template <int CW>
-__global__ __launch_bounds__(256) void engine_resident_kernel(const SlotDesc* __restrict__ descs,
-                                                              SlotState* states,
-                                                              const int32_t* __restrict__ rules_tab,
-                                                              const int32_t* __restrict__ ids) {
-    const int slot = ids[blockIdx.x];
-    const SlotDesc d = descs[slot];
-    __shared__ __align__(16) uint32_t cst[kSmallMaxPad * CW];
-    __shared__ int32_t chg[CFPQ_MAX_NONTERMINALS], prev[CFPQ_MAX_NONTERMINALS];
-    __shared__ int32_t any_s;
+// The fixpoint loop of a resident slot (engine_resident_kernel).  kAllLds:
+// every matrix is in LDS (M = lds, matrix stride rows * CW); otherwise the
+// matrices stay in global memory (M = T, stride mdw) and the right operand of
+// each product is staged in lds.  Returns the loop count; *products and
+// *capped as in SlotState.
+template <int CW, bool kAllLds>
+__device__ int64_t resident_loop(const SlotDesc& d, const int32_t* rules, uint32_t* M,
+                                 size_t mstride, const uint32_t* T, size_t mdw, uint32_t* lds, int rows, int kdw,
+                                 int32_t* chg, int32_t* prev, int32_t* any_s, int64_t* products, int* capped) {
     const int tid = threadIdx.x;
-    const int kdw = (d.n + 31) / 32;  // 32-bit k words (and rows / 32) that can hold bits
-    const int rows = kdw * 32;
-    const size_t mdw = static_cast<size_t>(d.npad) * d.W * 2;  // dwords per matrix
-    uint32_t* T = reinterpret_cast<uint32_t*>(d.T);
-    if (tid < CFPQ_MAX_NONTERMINALS) {
-        chg[tid] = 0;
-        prev[tid] = 0;
-    }
-    int64_t iters = 0, products = 0;
-    int capped = 0;
-    __syncthreads();
+    int64_t iters = 0;
     while (true) {
         if (iters >= d.max_iters) {
-            capped = 1;
+            *capped = 1;
             break;
         }
         for (int r = 0; r < d.n_rules; ++r) {
-            const int ra = rules_tab[3 * (d.rule_off + r)];
-            const int rb = rules_tab[3 * (d.rule_off + r) + 1];
-            const int rc = rules_tab[3 * (d.rule_off + r) + 2];
+            const int ra = rules[3 * r], rb = rules[3 * r + 1], rc = rules[3 * r + 2];
             if (d.dirty && iters > 0 && !prev[rb] && !prev[rc]) continue;
-            ++products;
-            const uint32_t* Bm = T + static_cast<size_t>(rb) * mdw;
-            const uint32_t* Cm = T + static_cast<size_t>(rc) * mdw;
-            uint32_t* Am = T + static_cast<size_t>(ra) * mdw;
-            for (int idx = tid; idx < rows * CW; idx += 256) cst[idx] = Cm[idx];  // rows are CW words apart
-            __syncthreads();
+            ++*products;
+            const uint32_t* Bm = M + static_cast<size_t>(rb) * mstride;
+            uint32_t* Am = M + static_cast<size_t>(ra) * mstride;
+            const uint32_t* cst;
+            if (kAllLds) {
+                cst = M + static_cast<size_t>(rc) * mstride;
+            } else {
+                const uint32_t* Cm = T + static_cast<size_t>(rc) * mdw;
+                for (int idx = tid; idx < rows * CW; idx += 256) lds[idx] = Cm[idx];  // rows are CW words apart
+                cst = lds;
+                __syncthreads();
+            }
             bool ch = false;
             for (int row = tid; row < rows; row += 256) {
                 uint32_t acc[CW];
@@ -119,20 +106,19 @@ __global__ __launch_bounds__(256) void engine_resident_kernel(const SlotDesc* __
                 for (int c = 0; c < CW; ++c) acc[c] = 0;
                 const uint32_t* brow = Bm + static_cast<size_t>(row) * CW;
                 for (int kw = 0; kw < kdw; ++kw) {
-                    const uint32_t a = brow[kw];
-                    if (a == 0) continue;
+                    uint32_t a = brow[kw];
                     const uint32_t* cblk = cst + kw * 32 * CW;
-#pragma unroll 4
-                    for (int kk = 0; kk < 32; ++kk) {
-                        const uint32_t mask = static_cast<uint32_t>(-static_cast<int32_t>((a >> kk) & 1u));
+                    while (a != 0) {  // the rows of C at the set bits of this word
+                        const int kk = __ffs(a) - 1;
+                        a &= a - 1;
                         const uint4* crow = reinterpret_cast<const uint4*>(cblk + kk * CW);
 #pragma unroll
                         for (int c4 = 0; c4 < CW / 4; ++c4) {
                             const uint4 v = crow[c4];
-                            acc[4 * c4] |= mask & v.x;
-                            acc[4 * c4 + 1] |= mask & v.y;
-                            acc[4 * c4 + 2] |= mask & v.z;
-                            acc[4 * c4 + 3] |= mask & v.w;
+                            acc[4 * c4] |= v.x;
+                            acc[4 * c4 + 1] |= v.y;
+                            acc[4 * c4 + 2] |= v.z;
+                            acc[4 * c4 + 3] |= v.w;
                         }
                     }
                 }
@@ -154,16 +140,84 @@ __global__ __launch_bounds__(256) void engine_resident_kernel(const SlotDesc* __
         if (tid == 0) {
             int any = 0;
             for (int a = 0; a < d.n_nt; ++a) any |= chg[a];
-            any_s = any;
+            *any_s = any;
         }
         __syncthreads();
-        if (!any_s) break;
+        if (!*any_s) break;
         if (tid < CFPQ_MAX_NONTERMINALS) {
             prev[tid] = chg[tid];
             chg[tid] = 0;
         }
         __syncthreads();
     }
+    return iters;
+}
+
+// Binary rules of a resident slot whose table is copied to LDS (more are read
+// in place).
+constexpr int kMaxResidentRules = 256;
+
+// One workgroup runs the whole fixpoint of one small slot (npad <= 512,
+// CW = 2 * W 32-bit words per row).  In-place schedule with the dirty-rule
+// worklist.  Thread t always owns rows t, t + 256, so a row of any matrix is
+// only ever written by one thread, and a barrier ends every product, so every
+// product reads all earlier writes of the workgroup.  When all |N| matrices
+// fit in LDS (their first `rows` rows; tiny graphs with CW = 8) they are
+// loaded once and the whole loop runs on LDS, written back at the end; a
+// product that reads a row another thread is updating in the same product
+// sees old or new bits (32-bit LDS words), both subsets of the fixpoint, so
+// only the loop count can depend on it.  Otherwise the right operand of each
+// product is staged in LDS and the others are read in place.  A loop in which
+// no rule set a bit ends the fixpoint.
+template <int CW>
+__global__ __launch_bounds__(256) void engine_resident_kernel(const SlotDesc* __restrict__ descs,
+                                                              SlotState* states,
+                                                              const int32_t* __restrict__ rules_tab,
+                                                              const int32_t* __restrict__ ids) {
+    // CW = 8: 48 KiB, all matrices of up to 6 nonterminals at npad 256;
+    // CW = 16: the staging buffer of one right operand
+    constexpr int kLdsWords = CW == 8 ? 12288 : kSmallMaxPad * CW;
+    const int slot = ids[blockIdx.x];
+    const SlotDesc d = descs[slot];
+    __shared__ __align__(16) uint32_t lds[kLdsWords];
+    __shared__ int32_t chg[CFPQ_MAX_NONTERMINALS], prev[CFPQ_MAX_NONTERMINALS];
+    __shared__ int32_t rules[3 * kMaxResidentRules];
+    __shared__ int32_t any_s;
+    const int tid = threadIdx.x;
+    const int kdw = (d.n + 31) / 32;  // 32-bit k words (and rows / 32) that can hold bits
+    const int rows = kdw * 32;
+    const size_t mdw = static_cast<size_t>(d.npad) * d.W * 2;  // dwords per matrix
+    uint32_t* T = reinterpret_cast<uint32_t*>(d.T);
+    const bool all_lds = CW == 8 && d.n_nt * rows * CW <= kLdsWords;
+    // the rule table in LDS (read every loop), or in place for a grammar with more rules
+    const bool rules_in_lds = d.n_rules <= kMaxResidentRules;
+    if (rules_in_lds)
+        for (int q = tid; q < 3 * d.n_rules; q += 256) rules[q] = rules_tab[3 * d.rule_off + q];
+    const int32_t* rl = rules_in_lds ? rules : rules_tab + 3 * d.rule_off;
+    if (all_lds)  // matrix a, row r, word c at lds[(a * rows + r) * CW + c]
+        for (int idx = tid; idx < d.n_nt * rows * CW; idx += 256) {
+            const int a = idx / (rows * CW), w = idx % (rows * CW);
+            lds[idx] = T[static_cast<size_t>(a) * mdw + w];
+        }
+    if (tid < CFPQ_MAX_NONTERMINALS) {
+        chg[tid] = 0;
+        prev[tid] = 0;
+    }
+    __syncthreads();
+    int64_t products = 0;
+    int capped = 0;
+    int64_t iters;
+    if (all_lds)
+        iters = resident_loop<CW, true>(d, rl, lds, static_cast<size_t>(rows) * CW, T, mdw, lds, rows, kdw, chg,
+                                        prev, &any_s, &products, &capped);
+    else
+        iters = resident_loop<CW, false>(d, rl, T, mdw, T, mdw, lds, rows, kdw, chg, prev, &any_s, &products,
+                                         &capped);
+    if (all_lds)  // the loop ended after a barrier: every write is in LDS
+        for (int idx = tid; idx < d.n_nt * rows * CW; idx += 256) {
+            const int a = idx / (rows * CW), w = idx % (rows * CW);
+            T[static_cast<size_t>(a) * mdw + w] = lds[idx];
+        }
     if (tid == 0) {
         SlotState* st = states + slot;
         st->iterations = iters;

@@ -28,6 +28,7 @@
 #include <string>
 #include <vector>
 
+#include "batch_engine.h"
 #include "cfpq_internal.h"
 
 namespace cfpq {
@@ -115,7 +116,18 @@ struct Plan {
     size_t off_rowor = 0;  // scratch of the row-gather product (sparse modes)
 };
 
-// AUTO: the autotuned kernel of the size bucket, else MFMA while int32 sums
+// A closure that fits one workgroup (padded side <= kSmallMaxPad) with the
+// default product choice, the in-place schedule, no per-product timing and no
+// warm start runs as a one-instance batch: the batched engine's resident
+// kernel computes the whole fixpoint in one launch, where the loop here costs
+// a few kernel launches per loop (thousands of loops on long chains).  The
+// bits are the same; only the loop count may differ (another in-place order).
+bool resident_route(const cfpq_graph* g, const cfpq_options& o) {
+    return o.path == CFPQ_PATH_AUTO && o.schedule == CFPQ_SCHEDULE_INPLACE && !o.profile && o.warm_start == 0 &&
+           g->n_nodes > 0 && layout_for(g->n_nodes).npad <= kSmallMaxPad;
+}
+
+// AUTO: the autotuned kernel of the size bucket, else the fp4 MFMA while fp32 sums
 // are exact.  *tile is only changed for an autotuned choice.
 int32_t choose_path(const Layout& L, int32_t requested, int32_t* tile = nullptr) {
     if (requested == CFPQ_PATH_BITS || reads_ct(requested)) return requested;
@@ -268,7 +280,8 @@ cfpq_status cfpq_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* gr
     if (!graph) return fail(CFPQ_EINVAL, "graph is NULL");
     if (graph->n_nodes < 0 || graph->n_nodes > CFPQ_MAX_NODES || graph->n_edges < 0)
         return fail(CFPQ_EINVAL, "graph size out of range");
-    *bytes = make_plan(graph, grammar, resolve(opt)).total;
+    const cfpq_options o = resolve(opt);
+    *bytes = resident_route(graph, o) ? batch_workspace_one(*graph, grammar, o) : make_plan(graph, grammar, o).total;
     return CFPQ_OK;
 }
 
@@ -297,6 +310,10 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
     if (o.tile != 0 && (o.path == CFPQ_PATH_ROWS || o.path == CFPQ_PATH_COLS))
         return fail(CFPQ_EINVAL, "the ROWS and COLS paths have no tile variants");
+    if (resident_route(graph, o)) {
+        const cfpq_instance inst{*graph, grammar, d_result};
+        return cfpq_batch_closure(1, &inst, &o, stream, d_workspace, workspace_bytes, stats);
+    }
     const Plan p = make_plan(graph, grammar, o);
     if (p.total > 0 && !d_workspace) return fail(CFPQ_EINVAL, "d_workspace is NULL");
     if (workspace_bytes < p.total)

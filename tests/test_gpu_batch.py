@@ -152,3 +152,25 @@ def test_batch_row_gather_rules(cfpq, dirty):
         assert np.array_equal(cfpq.result_bits(b), want), inst.tag
         assert a.stats["converged"] == 1
         assert a.stats["iterations"] > 2 or inst.tag == "er600_dense"  # the push loops ran
+
+
+def test_batch_grammar_with_many_rules(cfpq):
+    """A grammar with more binary rules than the resident kernel keeps in LDS
+    (300 rules over 24 nonterminals), on small graphs (one workgroup each,
+    the rule table read in place) and on one that takes the tiles, against the
+    oracle."""
+    rng = np.random.default_rng(71)
+    n_nt = 24
+    rules = set()
+    while len(rules) < 300:
+        rules.add(tuple(int(x) for x in rng.integers(0, n_nt, 3)))
+    g = grammars.CNF(tuple(f"N{i}" for i in range(n_nt)), ("a", "b"),
+                     tuple((i, i % 2) for i in range(0, n_nt, 3)), tuple(sorted(rules)), "many_rules")
+    insts = []
+    for k, (n, m) in enumerate(((60, 90), (200, 250), (700, 900))):
+        n, e = graphs.erdos_renyi(n, m, 72 + k, labels=2)
+        insts.append(configs.Instance(n, e, g, f"many_rules_er{n}"))
+    _say("many rules", [i.tag for i in insts])
+    res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts])
+    for inst, r in zip(insts, res):
+        assert np.array_equal(cfpq.result_bits(r), worklist.closure(inst.n, inst.edges, inst.grammar)), inst.tag

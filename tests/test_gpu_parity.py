@@ -159,6 +159,34 @@ def test_grammars_on_hierarchy_and_er(cfpq, name, path):
     assert np.array_equal(bits, want)
 
 
+# ---------------------------------------------------------------- small closures on the resident kernel
+
+def test_small_default_closure_runs_resident(cfpq):
+    """A default closure of at most 512 padded rows runs as a one-instance
+    batch (one resident workgroup): the oracle's bits, the same as with a
+    forced product path, and a sound subset when max_iters cuts it short."""
+    cases = [configs.config1(), configs.worked_example()]
+    n, e = graphs.erdos_renyi(500, 1500, 61, labels=2)
+    cases.append(configs.Instance(n, e, grammars.dyck(), "er500"))
+    n, e = graphs.hierarchy(450, 62, roots=3, reverse=True)
+    cases.append(configs.Instance(n, e, grammars.same_generation(), "hier450_rev"))
+    for inst in cases:
+        _say("resident", inst.tag, inst.n)
+        want = worklist.closure(inst.n, inst.edges, inst.grammar)
+        res = cfpq.closure(inst.n, inst.edges, inst.grammar)
+        assert res.stats["path_used"] == 1 and res.stats["converged"] == 1, inst.tag  # BITS, the resident product
+        assert np.array_equal(cfpq.result_bits(res), want), inst.tag
+        forced = cfpq.closure(inst.n, inst.edges, inst.grammar, path="fp4")
+        assert forced.stats["path_used"] == 5
+        assert np.array_equal(cfpq.result_bits(forced), want), inst.tag
+    inst = configs.config1()
+    part = cfpq.closure(inst.n, inst.edges, inst.grammar, max_iters=50, allow_partial=True)
+    assert part.status == -4 and part.stats["iterations"] == 50
+    full = worklist.unpack(worklist.closure(inst.n, inst.edges, inst.grammar), inst.n)
+    got = worklist.unpack(cfpq.result_bits(part), inst.n)
+    assert not (got & ~full).any() and got.any()
+
+
 # ---------------------------------------------------------------- degenerate inputs
 
 def test_empty_graph_and_no_edges(cfpq):
