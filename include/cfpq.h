@@ -199,7 +199,8 @@ CFPQ_API cfpq_status cfpq_workspace_bytes(const cfpq_graph* graph, const cfpq_gr
  * profile and no warm start runs as a one-instance cfpq_batch_closure (the
  * whole fixpoint in one workgroup, one launch; capture is ignored,
  * stats.path_used is BITS, the loop count may differ from the loop here); the
- * bits are the same.
+ * bits are the same.  So does the Jacobi schedule on graphs of at most 256
+ * padded rows whose |N| matrices fit twice in 48 KiB (same loop count).
  */
 CFPQ_API cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar,
                          const cfpq_options* opt, void* stream,

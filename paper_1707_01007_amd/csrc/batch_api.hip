@@ -49,6 +49,7 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
         const int64_t nn = g.n_nodes;
         d.max_iters = o.max_iters > 0 ? o.max_iters : nn * nn * gr->n_nonterminals + 1;
         d.dirty = o.dirty_worklist ? 1 : 0;
+        d.jacobi = o.schedule == CFPQ_SCHEDULE_JACOBI ? 1 : 0;
         d.rule_off = static_cast<int32_t>(p.rules.size() / 3);
         d.n_rules = (g.n_nodes > 0) ? gr->n_bin_rules : 0;
         for (int32_t r = 0; r < d.n_rules; ++r) {
@@ -146,11 +147,16 @@ size_t batch_workspace_one(const cfpq_graph& graph, const cfpq_grammar* grammar,
 
 namespace {
 
-cfpq_status validate_batch(int32_t n, const cfpq_instance* inst, const cfpq_options& o) {
+cfpq_status validate_batch(int32_t n, const cfpq_instance* inst, const cfpq_options& o, bool allow_jacobi = false) {
     if (n < 0) return fail(CFPQ_EINVAL, "n_instances is negative");
     if (n > 0 && !inst) return fail(CFPQ_EINVAL, "instances is NULL");
-    if (o.schedule != CFPQ_SCHEDULE_INPLACE)
+    const bool jacobi_ok = allow_jacobi && o.schedule == CFPQ_SCHEDULE_JACOBI;
+    if (o.schedule != CFPQ_SCHEDULE_INPLACE && !jacobi_ok)
         return fail(CFPQ_EINVAL, "the batched engine runs the in-place schedule only");
+    if (jacobi_ok)
+        for (int32_t i = 0; i < n; ++i)
+            if (!inst[i].grammar || !resident_jacobi_fits(inst[i].graph.n_nodes, inst[i].grammar->n_nonterminals))
+                return fail(CFPQ_EINVAL, "instance " + std::to_string(i) + " is too large for a resident Jacobi run");
     if (o.max_iters < 0 || o.capture < 0) return fail(CFPQ_EINVAL, "negative option");
     if (o.warm_start != 0) return fail(CFPQ_EINVAL, "the batched engine has no warm start");
     if (o.hybrid != CFPQ_HYBRID_OFF && o.hybrid != CFPQ_HYBRID_AUTO) return fail(CFPQ_EINVAL, "unknown hybrid mode");
@@ -205,8 +211,18 @@ cfpq_status cfpq_batch_workspace_bytes(int32_t n_instances, const cfpq_instance*
 cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instances, const cfpq_options* opt,
                                void* stream, void* d_workspace, size_t workspace_bytes, cfpq_stats* stats) {
     clear_last_error();
-    const cfpq_options o = resolve_batch(opt);
-    cfpq_status vst = validate_batch(n_instances, instances, o);
+    return batch_closure_run(n_instances, instances, resolve_batch(opt), stream, d_workspace, workspace_bytes, stats,
+                             false);
+}
+
+}  // extern "C"
+
+namespace cfpq {
+
+cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instances, const cfpq_options& o,
+                              void* stream, void* d_workspace, size_t workspace_bytes, cfpq_stats* stats,
+                              bool allow_jacobi) {
+    cfpq_status vst = validate_batch(n_instances, instances, o, allow_jacobi);
     if (vst != CFPQ_OK) return vst;
     BatchPlan p;
     plan_batch(n_instances, instances, o, p);
@@ -385,4 +401,4 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
     return CFPQ_OK;
 }
 
-}  // extern "C"
+}  // namespace cfpq

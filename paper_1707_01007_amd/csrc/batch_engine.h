@@ -49,6 +49,7 @@ struct SlotDesc {
     int32_t n_terminals;
     int32_t kind;
     int32_t dirty;
+    int32_t jacobi;  // small slots only: Algorithm 1's simultaneous step (see resident_jacobi_fits)
 };
 
 struct SlotState {
@@ -126,6 +127,23 @@ inline int32_t engine_trans_slots(const cfpq_bin_rule* rules, int32_t n_rules, c
     }
     return count;
 }
+
+// 32-bit LDS words of the resident kernel's matrix buffer for CW = 8 (48 KiB).
+constexpr int32_t kResidentLdsWords = 12288;
+
+// Whether a graph runs the Jacobi schedule in the resident kernel: padded side
+// 256 (8 words per row) and both buffers of all |N| matrices (their first
+// ceil(n / 32) * 32 rows) in its LDS.
+inline bool resident_jacobi_fits(int32_t n_nodes, int32_t n_nt) {
+    const int64_t rows = (static_cast<int64_t>(n_nodes) + 31) / 32 * 32;
+    return n_nodes > 0 && layout_for(n_nodes).npad <= 256 && 2 * n_nt * rows * 8 <= kResidentLdsWords;
+}
+
+// cfpq_batch_closure with, when allow_jacobi, the JACOBI schedule accepted for
+// instances that resident_jacobi_fits (cfpq_closure's small closures).
+cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instances, const cfpq_options& o,
+                              void* stream, void* d_workspace, size_t workspace_bytes, cfpq_stats* stats,
+                              bool allow_jacobi);
 
 // Workspace bytes of cfpq_batch_closure for one instance (batch_api.hip);
 // the graph and grammar must be valid.  Used by cfpq_closure for closures it

@@ -153,6 +153,92 @@ __device__ int64_t resident_loop(const SlotDesc& d, const int32_t* rules, uint32
     return iters;
 }
 
+// Algorithm 1's simultaneous step for a resident slot, all in LDS: products
+// read X (the matrices after the previous loop) and OR into Y (which starts
+// equal to X); after the loop the nonterminals that changed are copied from Y
+// to X.  The dirty-rule worklist as in the in-place loop (a product of loop t
+// reads X, so if neither operand changed in loop t - 1 it adds nothing).
+// Thread t writes only its rows t, t + 256 of Y and nothing writes X during
+// the products, so one barrier per loop orders them.  Returns the loop count;
+// X holds the result (also when max_iters cuts the fixpoint short).
+template <int CW>
+__device__ int64_t resident_jacobi(const SlotDesc& d, const int32_t* rules, uint32_t* X, uint32_t* Y, size_t mstride,
+                                   int rows, int kdw, int32_t* chg, int32_t* prev, int32_t* any_s, int64_t* products,
+                                   int* capped) {
+    const int tid = threadIdx.x;
+    int64_t iters = 0;
+    while (true) {
+        if (iters >= d.max_iters) {
+            *capped = 1;
+            break;
+        }
+        for (int r = 0; r < d.n_rules; ++r) {
+            const int ra = rules[3 * r], rb = rules[3 * r + 1], rc = rules[3 * r + 2];
+            if (d.dirty && iters > 0 && !prev[rb] && !prev[rc]) continue;
+            ++*products;
+            const uint32_t* Bm = X + static_cast<size_t>(rb) * mstride;
+            const uint32_t* Cm = X + static_cast<size_t>(rc) * mstride;
+            uint32_t* Am = Y + static_cast<size_t>(ra) * mstride;
+            bool ch = false;
+            for (int row = tid; row < rows; row += 256) {
+                uint32_t acc[CW];
+#pragma unroll
+                for (int c = 0; c < CW; ++c) acc[c] = 0;
+                const uint32_t* brow = Bm + static_cast<size_t>(row) * CW;
+                for (int kw = 0; kw < kdw; ++kw) {
+                    uint32_t a = brow[kw];
+                    const uint32_t* cblk = Cm + kw * 32 * CW;
+                    while (a != 0) {
+                        const int kk = __ffs(a) - 1;
+                        a &= a - 1;
+                        const uint4* crow = reinterpret_cast<const uint4*>(cblk + kk * CW);
+#pragma unroll
+                        for (int c4 = 0; c4 < CW / 4; ++c4) {
+                            const uint4 v = crow[c4];
+                            acc[4 * c4] |= v.x;
+                            acc[4 * c4 + 1] |= v.y;
+                            acc[4 * c4 + 2] |= v.z;
+                            acc[4 * c4 + 3] |= v.w;
+                        }
+                    }
+                }
+                uint32_t* arow = Am + static_cast<size_t>(row) * CW;
+#pragma unroll
+                for (int c = 0; c < CW; ++c) {
+                    const uint32_t old = arow[c];
+                    const uint32_t nw = old | acc[c];
+                    if (nw != old) {
+                        arow[c] = nw;
+                        ch = true;
+                    }
+                }
+            }
+            if (ch) chg[ra] = 1;
+        }
+        __syncthreads();
+        ++iters;
+        if (tid == 0) {
+            int any = 0;
+            for (int a = 0; a < d.n_nt; ++a) any |= chg[a];
+            *any_s = any;
+        }
+        __syncthreads();
+        if (!*any_s) break;
+        for (int a = 0; a < d.n_nt; ++a) {  // X = Y where Y changed (uniform: chg is in LDS)
+            if (!chg[a]) continue;
+            const size_t base = static_cast<size_t>(a) * mstride;
+            for (int idx = tid; idx < rows * CW; idx += 256) X[base + idx] = Y[base + idx];
+        }
+        __syncthreads();
+        if (tid < CFPQ_MAX_NONTERMINALS) {
+            prev[tid] = chg[tid];
+            chg[tid] = 0;
+        }
+        __syncthreads();
+    }
+    return iters;
+}
+
 // Binary rules of a resident slot whose table is copied to LDS (more are read
 // in place).
 constexpr int kMaxResidentRules = 256;
@@ -174,9 +260,10 @@ __global__ __launch_bounds__(256) void engine_resident_kernel(const SlotDesc* __
                                                               SlotState* states,
                                                               const int32_t* __restrict__ rules_tab,
                                                               const int32_t* __restrict__ ids) {
-    // CW = 8: 48 KiB, all matrices of up to 6 nonterminals at npad 256;
-    // CW = 16: the staging buffer of one right operand
-    constexpr int kLdsWords = CW == 8 ? 12288 : kSmallMaxPad * CW;
+    // CW = 8: 48 KiB, all matrices of up to 6 nonterminals at npad 256 (3 for
+    // the two buffers of the Jacobi schedule); CW = 16: the staging buffer of
+    // one right operand
+    constexpr int kLdsWords = CW == 8 ? kResidentLdsWords : kSmallMaxPad * CW;
     const int slot = ids[blockIdx.x];
     const SlotDesc d = descs[slot];
     __shared__ __align__(16) uint32_t lds[kLdsWords];
@@ -207,7 +294,18 @@ __global__ __launch_bounds__(256) void engine_resident_kernel(const SlotDesc* __
     int64_t products = 0;
     int capped = 0;
     int64_t iters;
-    if (all_lds)
+    const size_t half = static_cast<size_t>(d.n_nt) * rows * CW;
+    if (d.jacobi && !(CW == 8 && 2 * half <= static_cast<size_t>(kLdsWords))) {
+        // the host admits only slots whose two buffers fit (resident_jacobi_fits);
+        // anything else stops before the first loop, reported as capped
+        iters = 0;
+        capped = 1;
+    } else if (d.jacobi) {
+        for (size_t idx = tid; idx < half; idx += 256) lds[half + idx] = lds[idx];  // Y = X
+        __syncthreads();
+        iters = resident_jacobi<CW>(d, rl, lds, lds + half, static_cast<size_t>(rows) * CW, rows, kdw, chg, prev,
+                                    &any_s, &products, &capped);
+    } else if (all_lds)
         iters = resident_loop<CW, true>(d, rl, lds, static_cast<size_t>(rows) * CW, T, mdw, lds, rows, kdw, chg,
                                         prev, &any_s, &products, &capped);
     else

@@ -122,9 +122,12 @@ struct Plan {
 // kernel computes the whole fixpoint in one launch, where the loop here costs
 // a few kernel launches per loop (thousands of loops on long chains).  The
 // bits are the same; only the loop count may differ (another in-place order).
-bool resident_route(const cfpq_graph* g, const cfpq_options& o) {
-    return o.path == CFPQ_PATH_AUTO && o.schedule == CFPQ_SCHEDULE_INPLACE && !o.profile && o.warm_start == 0 &&
-           g->n_nodes > 0 && layout_for(g->n_nodes).npad <= kSmallMaxPad;
+// The Jacobi schedule goes the same way when both of its buffers fit the
+// resident kernel's LDS (tiny graphs); its loop count is Algorithm 1's.
+bool resident_route(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& o) {
+    if (o.path != CFPQ_PATH_AUTO || o.profile || o.warm_start != 0 || g->n_nodes <= 0) return false;
+    if (o.schedule == CFPQ_SCHEDULE_JACOBI) return resident_jacobi_fits(g->n_nodes, gr->n_nonterminals);
+    return o.schedule == CFPQ_SCHEDULE_INPLACE && layout_for(g->n_nodes).npad <= kSmallMaxPad;
 }
 
 // AUTO: the autotuned kernel of the size bucket, else the fp4 MFMA while fp32 sums
@@ -281,7 +284,8 @@ cfpq_status cfpq_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* gr
     if (graph->n_nodes < 0 || graph->n_nodes > CFPQ_MAX_NODES || graph->n_edges < 0)
         return fail(CFPQ_EINVAL, "graph size out of range");
     const cfpq_options o = resolve(opt);
-    *bytes = resident_route(graph, o) ? batch_workspace_one(*graph, grammar, o) : make_plan(graph, grammar, o).total;
+    *bytes = resident_route(graph, grammar, o) ? batch_workspace_one(*graph, grammar, o)
+                                               : make_plan(graph, grammar, o).total;
     return CFPQ_OK;
 }
 
@@ -310,9 +314,9 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
     if (o.tile != 0 && (o.path == CFPQ_PATH_ROWS || o.path == CFPQ_PATH_COLS))
         return fail(CFPQ_EINVAL, "the ROWS and COLS paths have no tile variants");
-    if (resident_route(graph, o)) {
+    if (resident_route(graph, grammar, o)) {
         const cfpq_instance inst{*graph, grammar, d_result};
-        return cfpq_batch_closure(1, &inst, &o, stream, d_workspace, workspace_bytes, stats);
+        return batch_closure_run(1, &inst, o, stream, d_workspace, workspace_bytes, stats, true);
     }
     const Plan p = make_plan(graph, grammar, o);
     if (p.total > 0 && !d_workspace) return fail(CFPQ_EINVAL, "d_workspace is NULL");

@@ -72,7 +72,15 @@ def test_workspace_bytes_valid_and_invalid():
     opt.schedule = _abi.SCHEDULE_JACOBI
     sz2 = ctypes.c_size_t(0)
     assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz2)) == 0
-    assert sz2.value >= sz.value + 4 * lib.cfpq_result_bytes(4, 1)  # the second buffer
+    # a graph this small runs in one resident workgroup, both Jacobi buffers in LDS
+    assert sz2.value == sz.value
+    opt.path = _abi.PATH_BITS  # the ordinary loop keeps a second buffer in the workspace
+    assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz2)) == 0
+    opt.schedule = _abi.SCHEDULE_INPLACE
+    sz3 = ctypes.c_size_t(0)
+    assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz3)) == 0
+    assert sz2.value >= sz3.value + 4 * lib.cfpq_result_bytes(4, 1)  # the second buffer
+    opt.schedule = _abi.SCHEDULE_JACOBI
     g.n_nonterminals = 0
     assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz)) == _abi.CFPQ_EINVAL
     assert b"n_nonterminals" in lib.cfpq_last_error()

@@ -187,6 +187,31 @@ def test_small_default_closure_runs_resident(cfpq):
     assert not (got & ~full).any() and got.any()
 
 
+def test_small_jacobi_closure_runs_resident(cfpq):
+    """Tiny graphs run the Jacobi schedule in the resident kernel (both buffers
+    in LDS): Algorithm 1's loop counts (6 on the worked example, 8065 on the
+    two cycles) and bits, equal to a forced-path Jacobi closure; a graph whose
+    two buffers do not fit takes the ordinary loop with the same results."""
+    gold = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    for inst, loops in ((configs.worked_example(), gold["loops"]["k"]), (configs.config1(), 8065)):
+        _say("resident jacobi", inst.tag)
+        res = cfpq.closure(inst.n, inst.edges, inst.grammar, schedule="jacobi", dirty=False)
+        assert res.stats["path_used"] == 1 and res.stats["iterations"] == loops, inst.tag
+        forced = cfpq.closure(inst.n, inst.edges, inst.grammar, schedule="jacobi", dirty=False, path="bits")
+        assert forced.stats["iterations"] == loops
+        assert np.array_equal(cfpq.result_bits(res), cfpq.result_bits(forced))
+        assert np.array_equal(cfpq.result_bits(res), worklist.closure(inst.n, inst.edges, inst.grammar))
+        dirty = cfpq.closure(inst.n, inst.edges, inst.grammar, schedule="jacobi")
+        assert dirty.stats["iterations"] == loops and np.array_equal(cfpq.result_bits(dirty), cfpq.result_bits(res))
+    # 7 nonterminals at 250 nodes: 2 x 7 x 256 rows x 8 words > 48 KiB, the ordinary loop
+    n, e = graphs.hierarchy(250, 63, roots=3, reverse=True)
+    g = grammars.same_generation()
+    res = cfpq.closure(n, e, g, schedule="jacobi")
+    assert np.array_equal(cfpq.result_bits(res), worklist.closure(n, e, g))
+    t, loops, _ = alg1.closure(n, e, g)
+    assert res.stats["iterations"] == loops
+
+
 # ---------------------------------------------------------------- degenerate inputs
 
 def test_empty_graph_and_no_edges(cfpq):
