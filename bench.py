@@ -174,8 +174,9 @@ def bench_single_path(cfpq, torch, n=4096, steps=2):
 
 def bench_conjunctive(cfpq, torch, n=8192, steps=3):
     """Conjunctive closure (Dyck conjoined with a^n b^n at the start rules) on
-    the ER recipe at n = 8192 with dense MFMA products: time per closure and
-    Gbit-op/s of its dense products (2 npad^3 each)."""
+    the ER recipe at n = 8192 with the library's default products (fp4 MFMA,
+    and ROWS for conjuncts whose left operand is an edge matrix): time per
+    closure and Gbit-op/s of its dense products (2 npad^3 each)."""
     from workloads import configs, grammars
     inst = configs.config3(n)
     g = grammars.dyck_and_anbn()
@@ -191,7 +192,7 @@ def bench_conjunctive(cfpq, torch, n=8192, steps=3):
     print(f"[bench] conjunctive n={n}: {t * 1e3:.1f} ms, {st['iterations']} loops, {st['products']} products",
           file=sys.stderr, flush=True)
     return {"workload": f"er{n}_dyck_and_anbn", "n": n, "ms_per_closure": round(t * 1e3, 3),
-            "loops": st["iterations"], "products": st["products"],
+            "loops": st["iterations"], "products": st["products"], "sparse_products": st["sparse_products"],
             "Gbitop_per_s": round(st["bitops"] / t / 1e9, 1)}
 
 

@@ -312,7 +312,10 @@ CFPQ_API cfpq_status cfpq_conjunctive_workspace_bytes(const cfpq_graph* graph, c
  * Closure for a conjunctive grammar: grammar (terminal rules, one-conjunct
  * binary rules) plus n_conj_rules rules with any number of conjuncts.
  * opt: path AUTO, BITS, MFMA or FP4 (dense products), schedule, dirty_worklist,
- * tile and max_iters as for cfpq_closure; warm_start must be 0; hybrid,
+ * tile and max_iters as for cfpq_closure; warm_start must be 0; hybrid AUTO
+ * (default) runs a conjunct whose left operand heads no rule as a ROWS
+ * product when the graph has at most npad^2 / 16 edges (counted in
+ * stats.sparse_products, not in bitops), OFF keeps every product dense;
  * capture and profile are ignored (host-driven loop).  d_result, stream,
  * workspace, stats and the return codes as for cfpq_closure.
  */

@@ -215,11 +215,12 @@ def witness(n: int, edges, grammar, lengths, a: int, i: int, j: int):
 
 
 def conjunctive_closure(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=True, max_iters=0,
-                        tile=0, device=None, stream=None, allow_partial=False) -> Result:
+                        tile=0, device=None, stream=None, allow_partial=False, hybrid=None) -> Result:
     """Closure for a conjunctive grammar (``cfpq_conjunctive_closure``).
     ``grammar`` has ``nonterminals``, ``terminals``, ``term`` = [(A, x)] and
     ``conj`` = [(A, ((B1, C1), ..., (Bk, Ck)))]; one-conjunct rules are passed
-    as ordinary binary rules."""
+    as ordinary binary rules.  ``hybrid`` (0/1, default the library's: 1) lets
+    conjuncts with an edge-matrix left operand run as ROWS products."""
     torch = _torch()
     L = lib()
     device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -236,7 +237,7 @@ def conjunctive_closure(n: int, edges, grammar, *, path="auto", schedule="inplac
         *[_abi.ConjRule(a, len(parts), ctypes.cast(pk, ctypes.POINTER(_abi.Conjunct)))
           for (a, parts), pk in zip(multi, parts_keep)])
     graph, e = _graph_struct(n, edges)
-    opt = _options(path, schedule, dirty, max_iters, False, tile, None)
+    opt = _options(path, schedule, dirty, max_iters, False, tile, None, hybrid=hybrid)
     need = ctypes.c_size_t(0)
     _abi.check(L.cfpq_conjunctive_workspace_bytes(ctypes.byref(graph), ctypes.byref(g), len(multi), c_arr,
                                                   ctypes.byref(opt), ctypes.byref(need)))

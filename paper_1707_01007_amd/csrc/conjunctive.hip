@@ -11,7 +11,10 @@
 // every further conjunct R = Bm x Cm into a second scratch matrix and Q &= R,
 // and finally T_A |= Q with the change flag.  One-conjunct rules are ordinary
 // products straight into T_A.  Schedules, dirty-rule worklist and product
-// kernels are those of cfpq_closure (host-driven loop).
+// kernels are those of cfpq_closure (host-driven loop).  With options.hybrid
+// AUTO, a conjunct whose left operand heads no rule (its matrix is fixed by
+// the edges) runs as a ROWS product when the graph has at most npad^2 / 16
+// edges: the rows of C at the set bits of each row of that sparse matrix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -62,9 +65,11 @@ struct CjPlan {
     int32_t n_nt = 0, path = CFPQ_PATH_BITS, tile = 0;
     bool jacobi = false, temps = false;
     std::vector<int32_t> right_slot;
+    std::vector<char> rows_left;  // per nonterminal: conjuncts with it as left operand run as ROWS
     int32_t n_right = 0;
+    bool any_rows = false;
     size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0, off_second = 0,
-           off_trans = 0, off_q = 0, off_r = 0, total = 0;
+           off_trans = 0, off_q = 0, off_r = 0, off_rowor = 0, total = 0;
 };
 
 cfpq_status collect_rules(const cfpq_grammar* gr, int32_t n_conj, const cfpq_conj_rule* conj,
@@ -101,11 +106,21 @@ CjPlan cj_plan(const cfpq_graph* g, const cfpq_grammar* gr, const std::vector<Ru
     if (p.path == CFPQ_PATH_AUTO) p.path = g->n_nodes <= kMfmaMaxNodes ? CFPQ_PATH_FP4 : CFPQ_PATH_BITS;
     p.jacobi = o.schedule == CFPQ_SCHEDULE_JACOBI;
     p.right_slot.assign(p.n_nt, -1);
+    p.rows_left.assign(p.n_nt, 0);
+    if (o.hybrid == CFPQ_HYBRID_AUTO && g->n_edges <= p.L.npad * p.L.npad / 16) {
+        std::vector<char> heads(p.n_nt, 0);
+        for (const Rule& r : rules) heads[r.lhs] = 1;
+        for (int32_t a = 0; a < p.n_nt; ++a) p.rows_left[a] = heads[a] ? 0 : 1;
+    }
     for (const Rule& r : rules) {
         if (r.parts.size() > 1) p.temps = true;
-        if (reads_ct(p.path))
-            for (const auto& pc : r.parts)
-                if (p.right_slot[pc.second] < 0) p.right_slot[pc.second] = p.n_right++;
+        for (const auto& pc : r.parts) {
+            if (p.rows_left[pc.first]) {
+                p.any_rows = true;
+            } else if (reads_ct(p.path) && p.right_slot[pc.second] < 0) {
+                p.right_slot[pc.second] = p.n_right++;
+            }
+        }
     }
     const size_t mat = static_cast<size_t>(p.L.mat_words) * 8;
     size_t off = 0;
@@ -127,6 +142,8 @@ CjPlan cj_plan(const cfpq_graph* g, const cfpq_grammar* gr, const std::vector<Ru
     if (p.temps) off += mat;
     p.off_r = off;
     if (p.temps) off += mat;
+    p.off_rowor = off;
+    if (p.any_rows) off += align_up(rowor_scratch_bytes(p.L), 256);
     p.total = off;
     return p;
 }
@@ -138,6 +155,7 @@ cfpq_status check_options(const cfpq_options& o, int32_t n_nodes) {
         return fail(CFPQ_EINVAL, "unknown schedule");
     if (o.max_iters < 0) return fail(CFPQ_EINVAL, "max_iters is negative");
     if (o.warm_start != 0) return fail(CFPQ_EINVAL, "conjunctive closures have no warm start");
+    if (o.hybrid != CFPQ_HYBRID_OFF && o.hybrid != CFPQ_HYBRID_AUTO) return fail(CFPQ_EINVAL, "unknown hybrid mode");
     if (reads_ct(o.path) && n_nodes > kMfmaMaxNodes)
         return fail(CFPQ_EINVAL, "the MFMA paths support at most 2^19 nodes");
     if (o.tile != 0 && (o.path != CFPQ_PATH_BITS || !bits_strip_supported(o.tile, layout_for(n_nodes))))
@@ -254,8 +272,13 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
     for (int32_t a = 0; a < n_nt; ++a)
         if (p.right_slot[a] >= 0) CFPQ_HIP(launch_transpose(X + a * mw, TT + p.right_slot[a] * mw, L, s));
 
+    int32_t* rowor_ws = reinterpret_cast<int32_t*>(ws + p.off_rowor);
+    int64_t sparse = 0;
     auto product = [&](int32_t b, int32_t c, uint64_t* out, int32_t* flag) -> cfpq_status {
-        if (reads_ct(p.path))
+        if (p.rows_left[b]) {
+            CFPQ_HIP(launch_rowor_product(X + b * mw, X + c * mw, out, L, flag, rowor_ws, s));
+            ++sparse;
+        } else if (reads_ct(p.path))
             CFPQ_HIP(launch_mfma_path(p.path, X + b * mw, TT + p.right_slot[c] * mw, out, L, flag, s));
         else
             CFPQ_HIP(launch_bits_product(X + b * mw, X + c * mw, out, L, flag, s, p.tile));
@@ -325,7 +348,8 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
         std::memset(stats, 0, sizeof(*stats));
         stats->iterations = iters;
         stats->products = products;
-        stats->bitops = 2.0 * static_cast<double>(L.npad) * L.npad * L.npad * static_cast<double>(products);
+        stats->sparse_products = sparse;  // ROWS conjuncts: not counted as bit-operations
+        stats->bitops = 2.0 * static_cast<double>(L.npad) * L.npad * L.npad * static_cast<double>(products - sparse);
         stats->device_ms = ms;
         stats->path_used = p.path;
         stats->converged = converged ? 1 : 0;

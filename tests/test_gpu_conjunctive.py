@@ -50,13 +50,20 @@ CASES = {
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("path", ["bits", "mfma", "fp4"])
 @pytest.mark.parametrize("schedule", ["inplace", "jacobi"])
-def test_conjunctive_matches_oracle(cfpq, name, path, schedule):
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_conjunctive_matches_oracle(cfpq, name, path, schedule, hybrid):
+    """Every dense kernel, both schedules, and with (hybrid 1) or without the
+    ROWS products of conjuncts whose left operand is an edge matrix."""
     n, e, g = CASES[name]()
     want, loops = conjunctive.closure(n, e, g)
-    got, res = _run(cfpq, n, e, g, path=path, schedule=schedule, dirty=(schedule == "inplace"))
+    got, res = _run(cfpq, n, e, g, path=path, schedule=schedule, dirty=(schedule == "inplace"), hybrid=hybrid)
     assert np.array_equal(got, want)
     if schedule == "jacobi":
         assert res.stats["iterations"] == loops
+    if not hybrid:
+        assert res.stats["sparse_products"] == 0
+    elif name == "er257_dyck_and_anbn":  # conjuncts A D1, A E1, A B: left operand A -> a
+        assert 0 < res.stats["sparse_products"] < res.stats["products"]
 
 
 def test_one_conjunct_rules_equal_plain_closure(cfpq):
