@@ -10,7 +10,7 @@
 // not choose; the smallest makes the result unique).
 //
 // One loop on the device:
-//  1. Boolean step: Y = X | OR_rules X_B x X_C (the VALU product kernel),
+//  1. Boolean step: Y = X | OR_rules X_B x X_C (fp4 MFMA or ROWS products),
 //     flags per nonterminal;
 //  2. the new cells D_A = Y_A & ~X_A;
 //  3. for every rule A -> B C whose A gained cells, minplus_kernel: for each
@@ -210,11 +210,19 @@ unsigned grid_for(int64_t items, int64_t cap = 65536) {
     return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((items + 255) / 256, cap)));
 }
 
+// Boolean step products: a rule whose left operand heads no binary rule (a
+// fixed edge matrix) runs as ROWS when the graph has at most npad^2 / 16
+// edges; the others on the fp4 MFMA (right operands kept transposed, rebuilt
+// when they change) up to 2^19 nodes, else on the VALU.
 struct SpPlan {
     Layout L;
     int32_t n_nt = 0;
+    bool mfma = false, any_rows = false;
+    std::vector<char> rows_left;     // per nonterminal
+    std::vector<int32_t> right_slot;  // per nonterminal: transpose slot or -1
+    int32_t n_right = 0;
     size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0, off_second = 0,
-           off_delta = 0, total = 0;
+           off_delta = 0, off_trans = 0, off_rowor = 0, total = 0;
 };
 
 SpPlan sp_plan(const cfpq_graph* g, const cfpq_grammar* gr) {
@@ -237,6 +245,23 @@ SpPlan sp_plan(const cfpq_graph* g, const cfpq_grammar* gr) {
     off += mat * p.n_nt;
     p.off_delta = off;  // D, one per nonterminal
     off += mat * p.n_nt;
+    p.mfma = g->n_nodes <= kMfmaMaxNodes;
+    p.rows_left.assign(p.n_nt, 0);
+    p.right_slot.assign(p.n_nt, -1);
+    if (g->n_edges <= p.L.npad * p.L.npad / 16) {
+        std::vector<char> heads(p.n_nt, 0);
+        for (int32_t r = 0; r < gr->n_bin_rules; ++r) heads[gr->bin_rules[r].lhs] = 1;
+        for (int32_t a = 0; a < p.n_nt; ++a) p.rows_left[a] = heads[a] ? 0 : 1;
+    }
+    for (int32_t r = 0; r < gr->n_bin_rules; ++r) {
+        const cfpq_bin_rule& br = gr->bin_rules[r];
+        if (p.rows_left[br.left]) p.any_rows = true;
+        else if (p.mfma && p.right_slot[br.right] < 0) p.right_slot[br.right] = p.n_right++;
+    }
+    p.off_trans = off;
+    off += mat * p.n_right;
+    p.off_rowor = off;
+    if (p.any_rows) off += align_up(rowor_scratch_bytes(p.L), 256);
     p.total = off;
     return p;
 }
@@ -354,15 +379,30 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
     const size_t lmat = static_cast<size_t>(L.npad) * static_cast<size_t>(L.npad);
     const int32_t kchunks = static_cast<int32_t>((L.n + 31) / 32);
     std::vector<int32_t> flags(n_nt + 1, 0);
-    int64_t iters = 0, products = 0;
+    int64_t iters = 0, products = 0, sparse = 0;
     bool converged = grammar->n_bin_rules == 0 || graph->n_nodes == 0;
     int32_t overflow = 0;
+    uint64_t* TT = reinterpret_cast<uint64_t*>(ws + p.off_trans);
+    int32_t* rowor_ws = reinterpret_cast<int32_t*>(ws + p.off_rowor);
     while (!converged && iters < cap) {
+        // transposed right operands of X: all in the first loop, then those X changed in
+        for (int32_t a = 0; a < n_nt; ++a)
+            if (p.right_slot[a] >= 0 && (iters == 0 || flags[a]))
+                CFPQ_HIP(launch_transpose(X + a * mw, TT + p.right_slot[a] * mw, L, s));
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
             const auto& br = grammar->bin_rules[r];
-            CFPQ_HIP(launch_bits_product(X + br.left * mw, X + br.right * mw, Y + br.lhs * mw, L, d_flags + br.lhs, s,
-                                         0));
+            int32_t* flag = d_flags + br.lhs;
+            if (p.rows_left[br.left]) {
+                CFPQ_HIP(launch_rowor_product(X + br.left * mw, X + br.right * mw, Y + br.lhs * mw, L, flag, rowor_ws,
+                                              s));
+                ++sparse;
+            } else if (p.mfma) {
+                CFPQ_HIP(launch_mfma_path(CFPQ_PATH_FP4, X + br.left * mw, TT + p.right_slot[br.right] * mw,
+                                          Y + br.lhs * mw, L, flag, s));
+            } else {
+                CFPQ_HIP(launch_bits_product(X + br.left * mw, X + br.right * mw, Y + br.lhs * mw, L, flag, s, 0));
+            }
             ++products;
         }
         CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt + 1) * 4, hipMemcpyDeviceToHost, s));
@@ -414,10 +454,11 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
         std::memset(stats, 0, sizeof(*stats));
         stats->iterations = iters;
         stats->products = products;
-        stats->bitops = 2.0 * static_cast<double>(L.npad) * L.npad * L.npad * static_cast<double>(products);
+        stats->sparse_products = sparse;  // ROWS products: not counted as bit-operations
+        stats->bitops = 2.0 * static_cast<double>(L.npad) * L.npad * L.npad * static_cast<double>(products - sparse);
         stats->device_ms = ms;
         stats->product_ms = minplus_ms;
-        stats->path_used = CFPQ_PATH_BITS;
+        stats->path_used = p.mfma ? CFPQ_PATH_FP4 : CFPQ_PATH_BITS;
         stats->converged = converged ? 1 : 0;
         stats->minplus_terms = static_cast<double>(cells);
     }
