@@ -1,0 +1,40 @@
+"""bench.py's command-line contract on the host: more than one GPU is refused
+with a message before anything touches a device, the profiling options exist,
+and the CPU baseline object carries the fields the benchmark line needs."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def _bench(*args, timeout=120):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          timeout=timeout, cwd=ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _bench("--gpus", "2")
+    assert r.returncode != 0
+    assert "single GPU" in r.stderr
+    assert r.stdout.strip() == ""  # no benchmark line
+
+
+def test_options():
+    r = _bench("--help")
+    assert r.returncode == 0
+    for opt in ("--steps", "--warmup", "--gpus", "--headline-only", "--section", "--no-cpu-baseline"):
+        assert opt in r.stdout, opt
+
+
+def test_cpu_baseline_fields():
+    import bench
+    from workloads import configs
+    inst = configs.config3(1024)
+    cb = bench.cpu_baseline(inst, seconds_target=0.05)
+    assert set(cb) == {"value", "unit", "cores", "kind", "sample"}
+    assert cb["kind"] == "oracle" and cb["unit"] == "Gbitop/s" and cb["value"] > 0 and cb["cores"] >= 1
+    assert "n=1024" in cb["sample"]
