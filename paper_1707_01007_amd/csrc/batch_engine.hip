@@ -417,7 +417,7 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             // n_nt * W words, W a multiple of 4: 16-byte stores
             uint4* cur = reinterpret_cast<uint4*>(d.RD + static_cast<size_t>(st->iterations & 1) * d.n_nt * d.W);
             const int64_t quads = static_cast<int64_t>(d.n_nt) * d.W / 2;
-            for (int64_t q = 0; q < quads; ++q) cur[q] = make_uint4(0, 0, 0, 0);
+            for (int64_t x = 0; x < quads; ++x) cur[x] = make_uint4(0, 0, 0, 0);
         }
         const int dim = d.npad / 256;
         int launched = 0;

@@ -411,7 +411,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         const int32_t n_rules = grammar->n_bin_rules;
         auto* d_rules = reinterpret_cast<int32_t*>(ws + p.off_rules);
         auto* d_go = reinterpret_cast<int32_t*>(ws + p.off_go);
-        auto* st = reinterpret_cast<LoopState*>(ws + p.off_state);
+        auto* lst = reinterpret_cast<LoopState*>(ws + p.off_state);
         std::vector<int32_t> rules(3 * static_cast<size_t>(n_rules));
         for (int32_t r = 0; r < n_rules; ++r) {
             rules[3 * r] = grammar->bin_rules[r].lhs;
@@ -419,7 +419,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             rules[3 * r + 2] = grammar->bin_rules[r].right;
         }
         CFPQ_HIP(hipMemcpyAsync(d_rules, rules.data(), rules.size() * 4, hipMemcpyHostToDevice, s));
-        CFPQ_HIP(launch_loop_state_init(st, s));
+        CFPQ_HIP(launch_loop_state_init(lst, s));
         int32_t K = o.capture;
         if (p.jacobi && (K & 1)) ++K;  // buffers swap every loop: an even count restores them
         hipStream_t cs = nullptr;
@@ -439,10 +439,10 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         uint64_t* cx = X;
         uint64_t* cy = Y;
         for (int32_t it = 0; it < K && ce == hipSuccess; ++it) {
-            ce = launch_plan(st, d_go, d_rules, n_rules, n_nt, o.dirty_worklist, cap, cs);
+            ce = launch_plan(lst, d_go, d_rules, n_rules, n_nt, o.dirty_worklist, cap, cs);
             for (int32_t r = 0; r < n_rules && ce == hipSuccess; ++r) {
                 const auto& br = grammar->bin_rules[r];
-                int32_t* flag = &st->changed[br.lhs];
+                int32_t* flag = &lst->changed[br.lhs];
                 if (reads_ct(p.path))
                     ce = launch_mfma_path(p.path, cx + br.left * mat_words, TT + p.right_slot[br.right] * mat_words,
                                           cy + br.lhs * mat_words, L, flag, cs, d_go + r);
@@ -453,11 +453,11 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             for (int32_t a = 0; a < n_nt && ce == hipSuccess; ++a) {
                 if (p.right_slot[a] >= 0)
                     ce = launch_transpose(cy + a * mat_words, TT + p.right_slot[a] * mat_words, L, cs,
-                                          &st->changed[a]);
+                                          &lst->changed[a]);
                 if (ce == hipSuccess && p.jacobi)
-                    ce = launch_copy_if(cy + a * mat_words, cx + a * mat_words, mat_words, &st->changed[a], cs);
+                    ce = launch_copy_if(cy + a * mat_words, cx + a * mat_words, mat_words, &lst->changed[a], cs);
             }
-            if (ce == hipSuccess) ce = launch_finish(st, n_nt, cs);
+            if (ce == hipSuccess) ce = launch_finish(lst, n_nt, cs);
             if (p.jacobi) std::swap(cx, cy);
         }
         hipError_t ee = hipStreamEndCapture(cs, &g);
@@ -467,7 +467,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         LoopState hs;
         do {
             CFPQ_HIP(hipGraphLaunch(exec, s));
-            CFPQ_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+            CFPQ_HIP(hipMemcpyAsync(&hs, lst, sizeof(hs), hipMemcpyDeviceToHost, s));
             CFPQ_HIP(hipStreamSynchronize(s));
         } while (!hs.done);
         iters = hs.iterations;

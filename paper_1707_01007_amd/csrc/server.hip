@@ -428,9 +428,33 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
     return true;
 }
 
+// A device error: recorded (the first message is kept) and every open
+// request completes with CFPQ_EDEVICE, so that no waiter blocks for ever.
+void fail_all(cfpq_server* srv, const std::string& message) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->worker_error == CFPQ_OK) {
+        srv->worker_error = CFPQ_EDEVICE;
+        srv->worker_message = message;
+    }
+    for (auto& kv : srv->tickets) {
+        if (kv.second->state != 2) {
+            kv.second->state = 2;
+            kv.second->status = CFPQ_EDEVICE;
+        }
+    }
+    srv->pending.clear();
+    srv->lane_pending.clear();
+    srv->done_cv.notify_all();
+    srv->cv.notify_all();
+    srv->lane_cv.notify_all();
+}
+
 // One lane: oldest lane request first, admitted when its workspace fits.
 void lane_main(cfpq_server* srv, int idx) {
-    hipSetDevice(srv->device);
+    if (hipSetDevice(srv->device) != hipSuccess) {
+        fail_all(srv, "hipSetDevice failed in a server lane");
+        return;
+    }
     hipStream_t ls = srv->lane_streams[idx];
     while (true) {
         Request* r = nullptr;
@@ -479,7 +503,10 @@ void lane_main(cfpq_server* srv, int idx) {
 }
 
 void worker_main(cfpq_server* srv) {
-    hipSetDevice(srv->device);
+    if (hipSetDevice(srv->device) != hipSuccess) {
+        fail_all(srv, "hipSetDevice failed in the server's worker");
+        return;
+    }
     while (true) {
         std::vector<Request*> admitted;
         {
@@ -515,16 +542,8 @@ void worker_main(cfpq_server* srv) {
                 continue;
             }
         }
-        if (!turn(srv, admitted)) {
-            std::lock_guard<std::mutex> lk(srv->mu);
-            for (auto& kv : srv->tickets) {
-                if (kv.second->state != 2) {
-                    kv.second->state = 2;
-                    kv.second->status = CFPQ_EDEVICE;
-                }
-            }
-            srv->pending.clear();
-            srv->done_cv.notify_all();
+        if (!turn(srv, admitted)) {  // turn recorded the error message
+            fail_all(srv, srv->worker_message);
             return;
         }
         bool busy_small_only = true, any = false;
