@@ -356,7 +356,7 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
         hipError_t ce = hipSuccess;
         for (int32_t it = 0; it < K && ce == hipSuccess; ++it) {
             ce = engine_plan(b, cs);
-            if (ce == hipSuccess) ce = engine_products(b, grid_p, cs);
+            if (ce == hipSuccess) ce = engine_products(b, grid_p, 8 * cus, cs);  // rows: up to 8 waves per SIMD
             if (ce == hipSuccess) ce = engine_tplan(b, 0, cs);
             if (ce == hipSuccess) ce = engine_transposes(b, grid_t, cs);
             if (ce == hipSuccess) ce = engine_finish(b, cs);

@@ -160,7 +160,11 @@ hipError_t engine_resident(const EngineBuffers& b, const int32_t* ids, int32_t c
 // loop serves any membership).  engine_tplan(fresh = 1) builds the first
 // transposes of newly admitted slots and clears their `fresh` flag.
 hipError_t engine_plan(const EngineBuffers& b, hipStream_t s);
-hipError_t engine_products(const EngineBuffers& b, int32_t grid, hipStream_t s);
+// grid: workgroups of the persistent tile kernel (one per CU); rows_grid:
+// workgroups of the row-gather kernel (grid-stride, so any count is correct;
+// more hide the latency of large first loops, fewer cost less when a loop has
+// little row work).
+hipError_t engine_products(const EngineBuffers& b, int32_t grid, int32_t rows_grid, hipStream_t s);
 hipError_t engine_tplan(const EngineBuffers& b, int32_t fresh, hipStream_t s);
 hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, hipStream_t s);
 hipError_t engine_finish(const EngineBuffers& b, hipStream_t s);

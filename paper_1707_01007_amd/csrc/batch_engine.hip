@@ -778,13 +778,13 @@ hipError_t engine_plan(const EngineBuffers& b, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t engine_products(const EngineBuffers& b, int32_t grid, hipStream_t s) {
+hipError_t engine_products(const EngineBuffers& b, int32_t grid, int32_t rows_grid, hipStream_t s) {
     engine_product_kernel<<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab,
                                                                                 b.trans_tab, b.jobs, b.es);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    engine_rows_kernel<<<dim3(static_cast<unsigned>(2 * grid)), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab,
-                                                                                 b.trans_tab, b.jobs, b.es);
+    engine_rows_kernel<<<dim3(static_cast<unsigned>(rows_grid)), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab,
+                                                                                  b.trans_tab, b.jobs, b.es);
     return hipGetLastError();
 }
 
