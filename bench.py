@@ -248,7 +248,7 @@ def _pct(xs, q):
     return round(float(np.percentile(np.asarray(xs), q)), 3) if xs else None
 
 
-def bench_serve(cfpq, torch, warm=100, measured=500, loads=(1.5, 0.5)):
+def bench_serve(cfpq, torch, warm=100, measured=500, loads=(1.5, 0.5), hybrid_lanes=None):
     """Serving stream (sizes log-uniform in [128, 8192], hierarchy or G(n, 4n),
     a^n b^n / same-generation / Dyck), host edges as a request would bring them.
     The first `warm` requests measure the serial plain closure's service rate
@@ -284,7 +284,7 @@ def bench_serve(cfpq, torch, warm=100, measured=500, loads=(1.5, 0.5)):
         print(f"[bench] serving: mu={mu:.1f}/s lambda={lam:.1f}/s over {measured} requests", file=sys.stderr,
               flush=True)
         # (a) server
-        with cfpq.Server(hbm_budget=32 << 30, max_slots=512, capture=4) as srv:
+        with cfpq.Server(hbm_budget=32 << 30, max_slots=512, capture=4, hybrid_lanes=hybrid_lanes) as srv:
             for t in [srv.submit(i.n, i.edges, i.grammar) for i in warm_set[:20]]:  # warm its code paths
                 srv.wait(t)
             start = time.perf_counter()
@@ -333,7 +333,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-closure section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--no-next", action="store_true", help="skip the single-path and conjunctive sections")
-    ap.add_argument("--section", choices=["single_path", "conjunctive", "small_configs", "batch"],
+    ap.add_argument("--section", choices=["single_path", "conjunctive", "small_configs", "batch", "serving"],
                     help="run only this section and print its JSON object (for profiling a kernel that the "
                          "section runs; no headline line)")
     ap.add_argument("--headline-only", action="store_true",
@@ -367,7 +367,7 @@ def main():
     torch.cuda.set_device(0)
     if args.section:
         fn = {"single_path": bench_single_path, "conjunctive": bench_conjunctive,
-              "small_configs": bench_small_configs, "batch": bench_batch}[args.section]
+              "small_configs": bench_small_configs, "batch": bench_batch, "serving": bench_serve}[args.section]
         print(json.dumps({"section": args.section, args.section: fn(cfpq, torch)}), flush=True)
         return
     inst = configs.config3(args.n)
