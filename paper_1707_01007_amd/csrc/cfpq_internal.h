@@ -202,6 +202,30 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t w, int lane) {
     return w;
 }
 
+// 256 x 256 bit transpose across a wavefront, in 64 x 64 blocks.  With W
+// words per row (a multiple of 4) and block coordinates br0, bc0 (multiples
+// of 4, in units of 64 rows / 64-bit words), lane t reads words bc0..bc0+3 of
+// rows 64 (br0 + r) + t, r = 0..3 (32 contiguous bytes a row), and afterwards
+// x[c][r] is word br0 + r of row 64 (bc0 + c) + t of the transpose, so each
+// transposed row is written back as 32 contiguous bytes as well.
+__device__ __forceinline__ void load_transpose256(const uint64_t* __restrict__ src, int64_t W, int64_t br0,
+                                                  int64_t bc0, int lane, uint64_t (&x)[4][4]) {
+    ulonglong2 v[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const ulonglong2* p = reinterpret_cast<const ulonglong2*>(src + ((br0 + r) * 64 + lane) * W + bc0);
+        v[r][0] = p[0];
+        v[r][1] = p[1];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        x[0][r] = transpose64(v[r][0].x, lane);
+        x[1][r] = transpose64(v[r][0].y, lane);
+        x[2][r] = transpose64(v[r][1].x, lane);
+        x[3][r] = transpose64(v[r][1].y, lane);
+    }
+}
+
 // counts[m] = number of set bits of matrix m (count matrices), added to counts.
 hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,
                            unsigned long long* counts, hipStream_t s);

@@ -148,25 +148,34 @@ __global__ __launch_bounds__(256) void rowor_heavy_kernel(const uint64_t* Bm, co
     if (__syncthreads_or(ch) && threadIdx.x == 0 && changed != nullptr) atomicOr(changed, 1);
 }
 
-// A |= transpose(Pt), with the change flag; one wavefront per 64 x 64 block
-// at a time (exchange-stage transpose), the grid striding over blocks.
+// A |= transpose(Pt), with the change flag; one wavefront per 256 x 256 tile
+// at a time (load_transpose256), the grid striding over tiles.  A transposed
+// row segment that adds nothing to A leaves it unread (if all zero) and
+// unwritten.
 __global__ __launch_bounds__(256) void transpose_or_kernel(const uint64_t* __restrict__ Pt, uint64_t* A, int64_t W,
                                                            int32_t* changed, const int32_t* go, int32_t want) {
     if (go != nullptr && *go != want) return;
     const int lane = threadIdx.x & 63;
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
+    const int64_t G = W >> 2;
     bool ch = false;
-    for (int64_t blk = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); blk < W * W;
-         blk += waves) {
-        const int64_t br = blk / W, bc = blk % W;
-        const uint64_t word = Pt[(br * 64 + lane) * W + bc];
-        if (__ballot(word != 0) == 0) continue;  // uniform: nothing to add from this block
-        const uint64_t mine = transpose64(word, lane);
-        uint64_t* dst = A + (bc * 64 + lane) * W + br;
-        const uint64_t old = *dst;
-        if (mine & ~old) {
-            *dst = old | mine;
-            ch = true;
+    for (int64_t item = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); item < G * G;
+         item += waves) {
+        const int64_t br0 = (item / G) * 4, bc0 = (item % G) * 4;
+        uint64_t x[4][4];
+        load_transpose256(Pt, W, br0, bc0, lane, x);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint64_t any = x[c][0] | x[c][1] | x[c][2] | x[c][3];
+            if (any == 0) continue;
+            ulonglong2* d = reinterpret_cast<ulonglong2*>(A + ((bc0 + c) * 64 + lane) * W + br0);
+            const ulonglong2 o0 = d[0], o1 = d[1];
+            const uint64_t add = (x[c][0] & ~o0.x) | (x[c][1] & ~o0.y) | (x[c][2] & ~o1.x) | (x[c][3] & ~o1.y);
+            if (add != 0) {
+                d[0] = make_ulonglong2(o0.x | x[c][0], o0.y | x[c][1]);
+                d[1] = make_ulonglong2(o1.x | x[c][2], o1.y | x[c][3]);
+                ch = true;
+            }
         }
     }
     if (__syncthreads_or(ch) && threadIdx.x == 0) atomicOr(changed, 1);
@@ -215,7 +224,8 @@ size_t rowor_scratch_bytes(const Layout& L) {
 
 hipError_t launch_transpose_or(const uint64_t* Pt, uint64_t* A, const Layout& L, int32_t* changed, hipStream_t s,
                                const int32_t* go, int32_t want) {
-    const int64_t blocks = std::min<int64_t>((L.W * L.W + 3) / 4, kSparseMaxBlocks);
+    const int64_t tiles = (L.W / 4) * (L.W / 4);  // W is a multiple of 4
+    const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, kSparseMaxBlocks);
     transpose_or_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(Pt, A, L.W, changed, go, want);
     return hipGetLastError();
 }

@@ -36,22 +36,27 @@ __global__ void init_scatter_kernel(const cfpq_edge* __restrict__ edges, int64_t
     }
 }
 
-// Bit-matrix transpose, one wavefront per 64 x 64 block: lane t holds row
-// r0 + t of the block as one 64-bit word, and six exchange stages (lanes t and
-// t ^ j swap the off-diagonal j x j sub-blocks of every 2j x 2j block,
-// j = 32, 16, ..., 1) leave row c0 + t of the transpose in lane t.
+// Bit-matrix transpose, one wavefront per 256 x 256 tile (load_transpose256):
+// every lane reads and writes 32 contiguous bytes of four rows, and the four
+// wavefronts of a workgroup take neighbouring tiles of one tile row, so a
+// workgroup reads whole 128-byte lines.
 __global__ __launch_bounds__(256) void transpose_kernel(const uint64_t* __restrict__ src,
                                                         uint64_t* __restrict__ dst, int64_t W,
                                                         const int32_t* __restrict__ pred, int32_t want) {
     if (pred != nullptr && (want == 0 ? *pred == 0 : *pred != want)) return;
     const int lane = threadIdx.x & 63;
-    const int64_t blocks = W * W;  // (npad/64)^2 blocks of 64 x 64
-    int64_t blk = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (blk >= blocks) return;
-    const int64_t br = blk / W;  // block row (word index of the source rows / 64)
-    const int64_t bc = blk % W;  // block column (word column)
-    const uint64_t word = src[(br * 64 + lane) * W + bc];
-    dst[(bc * 64 + lane) * W + br] = transpose64(word, lane);
+    const int64_t G = W >> 2;  // tiles per tile row
+    const int64_t item = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (item >= G * G) return;
+    const int64_t br0 = (item / G) * 4, bc0 = (item % G) * 4;
+    uint64_t x[4][4];
+    load_transpose256(src, W, br0, bc0, lane, x);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        ulonglong2* d = reinterpret_cast<ulonglong2*>(dst + ((bc0 + c) * 64 + lane) * W + br0);
+        d[0] = make_ulonglong2(x[c][0], x[c][1]);
+        d[1] = make_ulonglong2(x[c][2], x[c][3]);
+    }
 }
 
 __global__ __launch_bounds__(256) void popcount_kernel(const uint64_t* __restrict__ mats,
@@ -149,8 +154,8 @@ hipError_t launch_init_scatter(const cfpq_edge* edges, int64_t m, const int32_t*
 hipError_t launch_transpose(const uint64_t* src, uint64_t* dst, const Layout& L, hipStream_t s,
                             const int32_t* pred, int32_t want) {
 
-    int64_t blocks = L.W * L.W;
-    int64_t wgs = (blocks + 3) / 4;
+    const int64_t tiles = (L.W / 4) * (L.W / 4);  // W is a multiple of 4
+    const int64_t wgs = (tiles + 3) / 4;
     transpose_kernel<<<dim3(static_cast<unsigned>(wgs)), dim3(256), 0, s>>>(src, dst, L.W, pred, want);
     return hipGetLastError();
 }
