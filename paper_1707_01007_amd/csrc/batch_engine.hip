@@ -671,7 +671,7 @@ __global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __res
             const SlotDesc& d = descs[slot];
             SlotState& st = states[slot];
             if (fresh ? !(st.active && st.fresh) : !st.in_loop) continue;
-            const int items = d.W * d.W;  // 64 x 64 blocks
+            const int items = (d.W >> 2) * (d.W >> 2);  // 256 x 256 tiles (W is a multiple of 4)
             for (int a = 0; a < d.n_nt; ++a) {
                 if (trans_tab[d.trans_off + a] < 0) continue;
                 if (!fresh && !st.changed[a]) continue;
@@ -688,8 +688,8 @@ __global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __res
     }
 }
 
-// Transposes of the loop's work list: an item is one 64 x 64 block
-// (transpose64, as in transpose_kernel); each wavefront takes items
+// Transposes of the loop's work list: an item is one 256 x 256 tile
+// (load_transpose256, as in transpose_kernel); each wavefront takes items
 // w, w + waves, ... (static striding: items are cheap and uniform).
 __global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* __restrict__ descs,
                                                                const int32_t* __restrict__ trans_tab,
@@ -702,13 +702,20 @@ __global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* _
         const Job jb = tjobs[job_of(tjobs, n_jobs, item)];
         const SlotDesc& d = descs[jb.slot];
         const int64_t W = d.W;
-        const int64_t blk = item - jb.item_begin;
+        const int64_t G = W >> 2;
+        const int64_t tile = item - jb.item_begin;
         const int64_t mw = static_cast<int64_t>(d.npad) * W;
         const uint64_t* src = d.T + jb.what * mw;
         uint64_t* dst = d.TT + trans_tab[d.trans_off + jb.what] * mw;
-        const int64_t br = blk / W, bc = blk % W;
-        const uint64_t word = src[(br * 64 + lane) * W + bc];
-        dst[(bc * 64 + lane) * W + br] = transpose64(word, lane);
+        const int64_t br0 = (tile / G) * 4, bc0 = (tile % G) * 4;
+        uint64_t x[4][4];
+        load_transpose256(src, W, br0, bc0, lane, x);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ulonglong2* o = reinterpret_cast<ulonglong2*>(dst + ((bc0 + c) * 64 + lane) * W + br0);
+            o[0] = make_ulonglong2(x[c][0], x[c][1]);
+            o[1] = make_ulonglong2(x[c][2], x[c][3]);
+        }
     }
 }
 
