@@ -13,11 +13,14 @@
 //  1. Boolean step: Y = X | OR_rules X_B x X_C (fp4 MFMA or ROWS products),
 //     flags per nonterminal;
 //  2. the new cells D_A = Y_A & ~X_A;
-//  3. for every rule A -> B C whose A gained cells, minplus_kernel: for each
-//     64 x 64 output tile that holds new cells of A,
+//  3. for every rule A -> B C whose A gained cells, for each new cell (i, j)
 //        L_A(i, j) = min(L_A(i, j), min_k L_B(i, k) + L_C(k, j))
 //     over the k where X_B(i, k) and X_C(k, j) are set (cells of the previous
-//     step only: a new cell of B written by this loop is never read);
+//     step only: a new cell of B written by this loop is never read).  A rule
+//     whose B is a fixed sparse edge matrix walks the set bits of B's rows
+//     (minplus_rows_kernel); one whose C is, C's columns through a column
+//     index built once (minplus_cols_kernel); the others run minplus_kernel
+//     over every 64 x 64 output tile that holds new cells of A;
 //  4. X = Y.
 // Lengths are uint32 in cells of a |N| x npad x npad array (0 = absent); sums
 // stay below 2^31 - 1 or the call reports CFPQ_ERANGE.
@@ -31,6 +34,7 @@
 #include <vector>
 
 #include "cfpq_internal.h"
+#include "rowor_device.h"
 
 namespace cfpq {
 namespace {
@@ -189,6 +193,148 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
     }
 }
 
+// Min-plus of a rule whose left operand B is a fixed sparse matrix (cells
+// from edges only): one wavefront per row i at a time.  The set bits k of
+// X_B's row become a wave-uniform stream; for each k the lanes take the
+// columns j, 64 at a time, where X_C(k, j) and D_A(i, j) are both set and
+// lower L_A(i, j) to L_B(i, k) + L_C(k, j).  The wavefront owns row i of L_A,
+// so its read-modify-writes need no atomics; sums of kInf or more are left
+// out (no finite term), as in minplus_kernel.
+__global__ __launch_bounds__(256) void minplus_rows_kernel(const uint64_t* __restrict__ D,
+                                                           const uint64_t* __restrict__ XB,
+                                                           const uint64_t* __restrict__ XC, const uint32_t* LB,
+                                                           const uint32_t* LC, uint32_t* LA, int64_t W, int64_t npad,
+                                                           int32_t nrows) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nrows;
+         i += waves) {
+        const uint64_t* drow = D + i * W;
+        bool any = false;
+        for (int64_t w0 = 0; w0 < W && !any; w0 += 64) any = __ballot(w0 + lane < W && drow[w0 + lane] != 0) != 0;
+        if (!any) continue;
+        const uint64_t* brow = XB + i * W;
+        for (int64_t kw0 = 0; kw0 < W; kw0 += 64) {
+            const uint64_t bw = kw0 + lane < W ? brow[kw0 + lane] : 0;
+            for (uint64_t nz = __ballot(bw != 0); nz; nz &= nz - 1) {
+                const int src = __ffsll(static_cast<unsigned long long>(nz)) - 1;
+                for (uint64_t kb = rowor::readlane64(bw, src); kb; kb &= kb - 1) {
+                    const int64_t k = (kw0 + src) * 64 + (__ffsll(static_cast<unsigned long long>(kb)) - 1);
+                    const uint32_t lb = LB[i * npad + k];
+                    const uint64_t* crow = XC + k * W;
+                    for (int64_t jw0 = 0; jw0 < W; jw0 += 64) {
+                        const uint64_t m = jw0 + lane < W ? (crow[jw0 + lane] & drow[jw0 + lane]) : 0;
+                        for (uint64_t mz = __ballot(m != 0); mz; mz &= mz - 1) {
+                            const int s2 = __ffsll(static_cast<unsigned long long>(mz)) - 1;
+                            if (!((rowor::readlane64(m, s2) >> lane) & 1ull)) continue;
+                            const int64_t j = (jw0 + s2) * 64 + lane;
+                            const uint32_t v = lb + LC[k * npad + j];
+                            if (v >= kInf) continue;
+                            uint32_t* dst = LA + i * npad + j;
+                            const uint32_t cur = *dst;
+                            if (cur == 0 || v < cur) *dst = v;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Column index of a fixed sparse bit matrix (compressed columns): cnt[j] =
+// set bits of column j; then ptr = exclusive prefix sums of cnt (ptr[npad] =
+// total); then idx[ptr[j] ...] = the rows k of column j's bits, in any order.
+__global__ void csc_count_kernel(const uint64_t* __restrict__ M, int64_t W, int64_t words, int32_t* cnt) {
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        uint64_t x = M[w];
+        const int64_t j0 = 64 * (w % W);
+        for (; x; x &= x - 1) atomicAdd(cnt + j0 + __ffsll(static_cast<unsigned long long>(x)) - 1, 1);
+    }
+}
+
+// One workgroup of 1024 threads: ptr[0..n] = exclusive scan of cnt[0..n),
+// and cursor = ptr[0..n) for the fill.
+__global__ __launch_bounds__(1024) void csc_scan_kernel(const int32_t* __restrict__ cnt, int32_t* ptr,
+                                                        int32_t* cursor, int64_t n) {
+    __shared__ int32_t part[1024];
+    __shared__ int32_t carry;
+    const int t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n; base += 1024) {
+        const int32_t v = base + t < n ? cnt[base + t] : 0;
+        part[t] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+            const int32_t add = t >= off ? part[t - off] : 0;
+            __syncthreads();
+            part[t] += add;
+            __syncthreads();
+        }
+        const int32_t excl = carry + part[t] - v;
+        if (base + t < n) {
+            ptr[base + t] = excl;
+            cursor[base + t] = excl;
+        }
+        __syncthreads();
+        if (t == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (t == 0) ptr[n] = carry;
+}
+
+__global__ void csc_fill_kernel(const uint64_t* __restrict__ M, int64_t W, int64_t words, int32_t* cursor,
+                                int32_t* idx) {
+    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        uint64_t x = M[w];
+        const int64_t k = w / W, j0 = 64 * (w % W);
+        for (; x; x &= x - 1) {
+            const int32_t pos = atomicAdd(cursor + j0 + __ffsll(static_cast<unsigned long long>(x)) - 1, 1);
+            idx[pos] = static_cast<int32_t>(k);
+        }
+    }
+}
+
+// Min-plus of a rule whose right operand C is a fixed sparse matrix, given
+// its column index: one wavefront per row i at a time, lanes over the new
+// cells (i, j) 64 columns at a time; lane j takes the rows k of column j of C
+// where X_B(i, k) is set.
+__global__ __launch_bounds__(256) void minplus_cols_kernel(const uint64_t* __restrict__ D,
+                                                           const uint64_t* __restrict__ XB,
+                                                           const int32_t* __restrict__ cptr,
+                                                           const int32_t* __restrict__ cidx, const uint32_t* LB,
+                                                           const uint32_t* LC, uint32_t* LA, int64_t W, int64_t npad,
+                                                           int32_t nrows) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nrows;
+         i += waves) {
+        const uint64_t* drow = D + i * W;
+        const uint64_t* brow = XB + i * W;
+        for (int64_t jw0 = 0; jw0 < W; jw0 += 64) {
+            const uint64_t dw = jw0 + lane < W ? drow[jw0 + lane] : 0;
+            for (uint64_t nz = __ballot(dw != 0); nz; nz &= nz - 1) {
+                const int src = __ffsll(static_cast<unsigned long long>(nz)) - 1;
+                if (!((rowor::readlane64(dw, src) >> lane) & 1ull)) continue;
+                const int64_t j = (jw0 + src) * 64 + lane;
+                uint32_t best = kInf;
+                for (int32_t q = cptr[j], e = cptr[j + 1]; q < e; ++q) {
+                    const int64_t k = cidx[q];
+                    if (!((brow[k >> 6] >> (k & 63)) & 1ull)) continue;
+                    const uint32_t v = LB[i * npad + k] + LC[k * npad + j];
+                    best = min(best, v);
+                }
+                if (best >= kInf) continue;
+                uint32_t* dst = LA + i * npad + j;
+                const uint32_t cur = *dst;
+                if (cur == 0 || best < cur) *dst = best;
+            }
+        }
+    }
+}
+
 // Overflow check: a new cell that no rule gave a finite sum has a length that
 // did not fit (its Boolean product term exists, so some sum was >= 2^31 - 1).
 __global__ void check_new_cells_kernel(const uint64_t* __restrict__ D, const uint32_t* __restrict__ LA,
@@ -220,9 +366,11 @@ struct SpPlan {
     bool mfma = false, any_rows = false;
     std::vector<char> rows_left;     // per nonterminal
     std::vector<int32_t> right_slot;  // per nonterminal: transpose slot or -1
-    int32_t n_right = 0;
+    std::vector<int32_t> csc_slot;    // per nonterminal: column index slot or -1
+    int32_t n_right = 0, n_csc = 0;
     size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0, off_second = 0,
-           off_delta = 0, off_trans = 0, off_rowor = 0, total = 0;
+           off_delta = 0, off_trans = 0, off_rowor = 0, off_csc = 0, csc_bytes = 0, off_csc_cursor = 0,
+           off_csc_idx = 0, total = 0;
 };
 
 SpPlan sp_plan(const cfpq_graph* g, const cfpq_grammar* gr) {
@@ -253,15 +401,29 @@ SpPlan sp_plan(const cfpq_graph* g, const cfpq_grammar* gr) {
         for (int32_t r = 0; r < gr->n_bin_rules; ++r) heads[gr->bin_rules[r].lhs] = 1;
         for (int32_t a = 0; a < p.n_nt; ++a) p.rows_left[a] = heads[a] ? 0 : 1;
     }
+    p.csc_slot.assign(p.n_nt, -1);
     for (int32_t r = 0; r < gr->n_bin_rules; ++r) {
         const cfpq_bin_rule& br = gr->bin_rules[r];
-        if (p.rows_left[br.left]) p.any_rows = true;
-        else if (p.mfma && p.right_slot[br.right] < 0) p.right_slot[br.right] = p.n_right++;
+        if (p.rows_left[br.left]) {
+            p.any_rows = true;
+            continue;
+        }
+        if (p.mfma && p.right_slot[br.right] < 0) p.right_slot[br.right] = p.n_right++;
+        // min-plus through the column index of a fixed sparse right operand
+        // (its cells come from edges, so at most n_edges of them)
+        if (p.rows_left[br.right] && p.csc_slot[br.right] < 0 && g->n_edges < INT32_MAX)
+            p.csc_slot[br.right] = p.n_csc++;
     }
     p.off_trans = off;
     off += mat * p.n_right;
     p.off_rowor = off;
     if (p.any_rows) off += align_up(rowor_scratch_bytes(p.L), 256);
+    // per column index: ptr (npad + 1), cursor / counts (npad), rows (n_edges)
+    p.off_csc_cursor = align_up(static_cast<size_t>(p.L.npad + 1) * 4, 256);
+    p.off_csc_idx = p.off_csc_cursor + align_up(static_cast<size_t>(p.L.npad) * 4, 256);
+    p.csc_bytes = p.off_csc_idx + align_up(static_cast<size_t>(std::max<int64_t>(g->n_edges, 1)) * 4, 256);
+    p.off_csc = off;
+    off += p.csc_bytes * p.n_csc;
     p.total = off;
     return p;
 }
@@ -373,6 +535,23 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
         CFPQ_HIP(hipGetLastError());
     }
     CFPQ_HIP(hipMemcpyAsync(Y, X, mw * 8 * n_nt, hipMemcpyDeviceToDevice, s));
+    // column indexes of the fixed right operands (their cells are final now)
+    for (int32_t c = 0; c < n_nt; ++c) {
+        if (p.csc_slot[c] < 0) continue;
+        char* base = ws + p.off_csc + p.csc_bytes * p.csc_slot[c];
+        auto* cptr = reinterpret_cast<int32_t*>(base);
+        auto* cursor = reinterpret_cast<int32_t*>(base + p.off_csc_cursor);
+        auto* cidx = reinterpret_cast<int32_t*>(base + p.off_csc_idx);
+        CFPQ_HIP(launch_zero(reinterpret_cast<uint64_t*>(cursor), static_cast<size_t>(L.npad) / 2, s));
+        csc_count_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 4096)), dim3(256), 0, s>>>(
+            X + c * mw, L.W, static_cast<int64_t>(mw), cursor);
+        CFPQ_HIP(hipGetLastError());
+        csc_scan_kernel<<<dim3(1), dim3(1024), 0, s>>>(cursor, cptr, cursor, L.npad);
+        CFPQ_HIP(hipGetLastError());
+        csc_fill_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 4096)), dim3(256), 0, s>>>(
+            X + c * mw, L.W, static_cast<int64_t>(mw), cursor, cidx);
+        CFPQ_HIP(hipGetLastError());
+    }
 
     const int64_t nn = graph->n_nodes;
     const int64_t cap = max_iters > 0 ? max_iters : nn * nn * n_nt + 1;
@@ -420,10 +599,31 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
                 Y + a * mw, X + a * mw, D + a * mw, static_cast<int64_t>(mw));
             CFPQ_HIP(hipGetLastError());
         }
-        CFPQ_HIP(hipEventRecord(mp0, s));
+        // rules with a fixed sparse operand: row or column gathers
+        const unsigned gather_grid = static_cast<unsigned>(std::min<int64_t>((L.n + 3) / 4, 2048));
         for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
             const auto& br = grammar->bin_rules[r];
             if (!flags[br.lhs]) continue;
+            if (p.rows_left[br.left]) {
+                minplus_rows_kernel<<<dim3(gather_grid), dim3(256), 0, s>>>(
+                    D + br.lhs * mw, X + br.left * mw, X + br.right * mw, d_lengths + br.left * lmat,
+                    d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, L.n);
+            } else if (p.csc_slot[br.right] >= 0) {
+                const char* base = ws + p.off_csc + p.csc_bytes * p.csc_slot[br.right];
+                minplus_cols_kernel<<<dim3(gather_grid), dim3(256), 0, s>>>(
+                    D + br.lhs * mw, X + br.left * mw, reinterpret_cast<const int32_t*>(base),
+                    reinterpret_cast<const int32_t*>(base + p.off_csc_idx), d_lengths + br.left * lmat,
+                    d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, L.n);
+            } else {
+                continue;
+            }
+            CFPQ_HIP(hipGetLastError());
+        }
+        // the others on the tile kernel (timed: its terms are counted)
+        CFPQ_HIP(hipEventRecord(mp0, s));
+        for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
+            const auto& br = grammar->bin_rules[r];
+            if (!flags[br.lhs] || p.rows_left[br.left] || p.csc_slot[br.right] >= 0) continue;
             minplus_kernel<<<dim3(static_cast<unsigned>(L.W * L.W)), dim3(256), 0, s>>>(
                 D + br.lhs * mw, X + br.left * mw, X + br.right * mw, d_lengths + br.left * lmat,
                 d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, kchunks, d_cells);

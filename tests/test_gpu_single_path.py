@@ -62,6 +62,8 @@ CASES = {
     "er257_dyck": lambda: (*graphs.erdos_renyi(257, 700, 6, labels=2), grammars.dyck()),
     "hier300_rev_samegen": lambda: (*graphs.hierarchy(300, 7, roots=2, reverse=True), grammars.same_generation()),
     "first_found": lambda: _first_found_graph(),
+    # more than npad^2 / 16 edges: every rule on the tile min-plus kernel
+    "er90_dense_dyck": lambda: (*graphs.erdos_renyi(90, 4200, 8, labels=2), grammars.dyck()),
 }
 
 
@@ -127,3 +129,32 @@ def test_device_edges_and_larger_graph(cfpq):
     assert np.array_equal(worklist.unpack(bits, inst.n), got > 0)
     assert np.array_equal(cfpq.result_bits(res), bits)
     _check_paths(cfpq, inst.n, inst.edges, inst.grammar, got, count=25)
+
+
+def _shortest_lengths(n, e):
+    """Fewest edges (>= 1) on a path i -> j, 0 if none, for every pair: scipy's
+    unweighted shortest paths, with d[i][i] = the shortest cycle through i."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    src, dst = e[:, 0].astype(np.int64), e[:, 2].astype(np.int64)
+    A = csr_matrix((np.ones(len(src)), (src, dst)), shape=(n, n))
+    d = shortest_path(A, method="D", unweighted=True)
+    diag = np.full(n, np.inf)
+    np.minimum.at(diag, src, 1.0 + d[dst, src])  # leave i by one edge, come back
+    np.fill_diagonal(d, diag)
+    d[~np.isfinite(d)] = 0
+    return d.astype(np.int64)
+
+
+@pytest.mark.parametrize("side", ["right_linear", "left_linear"])
+def test_linear_closure_lengths_are_shortest_paths(cfpq, side):
+    """S -> a | A S (or S A), A -> a: each loop extends paths by one edge, so a
+    cell's length is its shortest path length.  The fixed sparse operand A
+    sends the rule through the row gather (A S) or the column index (S A)
+    min-plus; n = 4500 makes rows longer than 64 words."""
+    g = grammars.CNF(("S", "A"), ("a",), ((0, 0), (1, 0)), ((0, 1, 0) if side == "right_linear" else (0, 0, 1),),
+                     name=side)
+    n, e = graphs.erdos_renyi(4500, 6500, 13, labels=1)
+    res, got = _lengths(cfpq, n, e, g)
+    assert np.array_equal(got[0], _shortest_lengths(n, e))
+    assert np.array_equal(got[1] > 0, _shortest_lengths(n, e) == 1)
