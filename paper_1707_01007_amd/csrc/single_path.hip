@@ -12,15 +12,18 @@
 // One loop on the device:
 //  1. Boolean step: Y = X | OR_rules X_B x X_C (fp4 MFMA or ROWS products),
 //     flags per nonterminal;
-//  2. the new cells D_A = Y_A & ~X_A;
+//  2. the new cells D_A = Y_A & ~X_A, counted (cells, 64 x 64 tiles holding
+//     one), with L_A = kInf on them;
 //  3. for every rule A -> B C whose A gained cells, for each new cell (i, j)
 //        L_A(i, j) = min(L_A(i, j), min_k L_B(i, k) + L_C(k, j))
 //     over the k where X_B(i, k) and X_C(k, j) are set (cells of the previous
 //     step only: a new cell of B written by this loop is never read).  A rule
 //     whose B is a fixed sparse edge matrix walks the set bits of B's rows
 //     (minplus_rows_kernel); one whose C is, C's columns through a column
-//     index built once (minplus_cols_kernel); the others run minplus_kernel
-//     over every 64 x 64 output tile that holds new cells of A;
+//     index built once (minplus_cols_kernel); the others take the row walk
+//     or minplus_kernel over the 64 x 64 output tiles that hold new cells of
+//     A (split along k when they are few), whichever a cost model from the
+//     counts prefers;
 //  4. X = Y.
 // Lengths are uint32 in cells of a |N| x npad x npad array (0 = absent); sums
 // stay below 2^31 - 1 or the call reports CFPQ_ERANGE.
@@ -57,11 +60,35 @@ __global__ void lengths_from_bits_kernel(const uint64_t* __restrict__ T, uint32_
 }
 
 // D = Y & ~X over one matrix.
-__global__ void delta_kernel(const uint64_t* __restrict__ Y, const uint64_t* __restrict__ X,
-                             uint64_t* __restrict__ D, int64_t words) {
+// The step's new cells of every nonterminal (blockIdx.y = A): D_A = Y_A & ~X_A,
+// with per nonterminal the number of new cells (dcount) and of 64 x 64 tiles
+// holding one (tiles, from the flags tflag[A][tile]), and L_A = kInf on every
+// new cell: the min-plus kernels lower it, and a new cell still at kInf after
+// them had no finite sum.
+__global__ __launch_bounds__(256) void delta_all_kernel(const uint64_t* __restrict__ Y,
+                                                        const uint64_t* __restrict__ X, uint64_t* __restrict__ D,
+                                                        uint32_t* __restrict__ lengths, int64_t W, int64_t npad,
+                                                        unsigned long long* dcount, int32_t* tflag, int32_t* tiles) {
+    const int64_t a = blockIdx.y;
+    const int64_t words = npad * W;
+    const uint64_t* y = Y + a * words;
+    const uint64_t* x = X + a * words;
+    uint64_t* d = D + a * words;
+    uint32_t* la = lengths + a * npad * npad;
+    int32_t* tf = tflag + a * W * W;
+    unsigned long long c = 0;
     for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
-         w += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        D[w] = Y[w] & ~X[w];
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        uint64_t v = y[w] & ~x[w];
+        d[w] = v;
+        if (!v) continue;
+        c += __popcll(v);
+        const int64_t i = w / W, jw = w % W;
+        if (atomicOr(tf + (i >> 6) * W + jw, 1) == 0) atomicAdd(tiles + a, 1);
+        for (; v; v &= v - 1) la[i * npad + 64 * jw + __ffsll(static_cast<unsigned long long>(v)) - 1] = kInf;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(dcount + a, c);
 }
 
 // Chunks of 32 k whose skip mask one pass builds (LDS bits).
@@ -92,17 +119,20 @@ __device__ __forceinline__ int32_t next_chunk(const uint32_t* m, int32_t from, i
 __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict__ D, const uint64_t* __restrict__ XB,
                                                       const uint64_t* __restrict__ XC, const uint32_t* LB,
                                                       const uint32_t* LC, uint32_t* LA, int64_t W, int64_t npad,
-                                                      int32_t kchunks, unsigned long long* cells) {
-    const int64_t tiles = W;  // tiles per side (64 cells each)
-    const int64_t ti = blockIdx.x / tiles, tj = blockIdx.x % tiles;
+                                                      int32_t kchunks, const int32_t* __restrict__ tflag,
+                                                      int32_t ksplit, unsigned long long* cells) {
+    const int64_t tile = blockIdx.x / ksplit;
+    if (!tflag[tile]) return;  // no new cell in this tile
+    const int32_t per = ((kchunks + ksplit - 1) / ksplit + 1) & ~1;  // even: the marks read chunk pairs
+    const int32_t c_begin = static_cast<int32_t>(blockIdx.x % ksplit) * per;
+    const int32_t c_end = min(kchunks, c_begin + per);
+    if (c_begin >= c_end) return;
+    const int64_t ti = tile / W, tj = tile % W;  // W tiles per side (64 cells each)
     const int64_t i0 = ti * 64, jw = tj;  // j0 = 64 * jw
     const int t = threadIdx.x;
     __shared__ __align__(16) uint32_t As[32][64 + 4];  // As[kk][i]
     __shared__ __align__(16) uint32_t Bs[32][64 + 4];  // Bs[kk][j]
     __shared__ uint32_t bmask[kSegChunks / 32], cmask[kSegChunks / 32];
-    // the tile's new cells
-    const uint64_t dword = t < 64 ? D[(i0 + t) * W + jw] : 0;
-    if (!__syncthreads_or(dword != 0)) return;
     int32_t done_chunks = 0;
     const int tx = t & 15, ty = t >> 4;
     uint32_t acc[4][4];
@@ -110,8 +140,8 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = 0xFFFFFFFFu;
-    for (int32_t seg0 = 0; seg0 < kchunks; seg0 += kSegChunks) {
-        const int32_t seg_n = min(kSegChunks, kchunks - seg0);
+    for (int32_t seg0 = c_begin; seg0 < c_end; seg0 += kSegChunks) {
+        const int32_t seg_n = min(kSegChunks, c_end - seg0);
         // ---- chunk marks: bit c = chunk seg0 + c has bits in both operand blocks
         __syncthreads();  // the previous segment's marks and buffers are no longer read
         if (t < kSegChunks / 32) {
@@ -181,14 +211,8 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
             const int jj = tx * 4 + c;
             if (!((drow >> jj) & 1ull)) continue;
             const uint32_t v = acc[r][c];
-            if (v >= kInf) {
-                // a new cell of A comes from a product term of this rule or of
-                // another; kInf here only means this rule offered no k
-                continue;
-            }
-            uint32_t* dst = LA + i * npad + 64 * jw + jj;
-            const uint32_t cur = *dst;
-            if (cur == 0 || v < cur) *dst = v;
+            // kInf: this rule (or this k range) offered no k for the cell
+            if (v < kInf) atomicMin(LA + i * npad + 64 * jw + jj, v);
         }
     }
 }
@@ -198,8 +222,8 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
 // X_B's row become a wave-uniform stream; for each k the lanes take the
 // columns j, 64 at a time, where X_C(k, j) and D_A(i, j) are both set and
 // lower L_A(i, j) to L_B(i, k) + L_C(k, j).  The wavefront owns row i of L_A,
-// so its read-modify-writes need no atomics; sums of kInf or more are left
-// out (no finite term), as in minplus_kernel.
+// so its read-modify-writes need no atomics.  New cells hold kInf until a
+// sum lowers them, so sums of kInf or more change nothing.
 __global__ __launch_bounds__(256) void minplus_rows_kernel(const uint64_t* __restrict__ D,
                                                            const uint64_t* __restrict__ XB,
                                                            const uint64_t* __restrict__ XC, const uint32_t* LB,
@@ -229,10 +253,8 @@ __global__ __launch_bounds__(256) void minplus_rows_kernel(const uint64_t* __res
                             if (!((rowor::readlane64(m, s2) >> lane) & 1ull)) continue;
                             const int64_t j = (jw0 + s2) * 64 + lane;
                             const uint32_t v = lb + LC[k * npad + j];
-                            if (v >= kInf) continue;
-                            uint32_t* dst = LA + i * npad + j;
-                            const uint32_t cur = *dst;
-                            if (cur == 0 || v < cur) *dst = v;
+                            uint32_t* dst = LA + i * npad + j;  // kInf until a finite sum lowers it
+                            if (v < *dst) *dst = v;
                         }
                     }
                 }
@@ -326,19 +348,18 @@ __global__ __launch_bounds__(256) void minplus_cols_kernel(const uint64_t* __res
                     const uint32_t v = LB[i * npad + k] + LC[k * npad + j];
                     best = min(best, v);
                 }
-                if (best >= kInf) continue;
-                uint32_t* dst = LA + i * npad + j;
-                const uint32_t cur = *dst;
-                if (cur == 0 || best < cur) *dst = best;
+                uint32_t* dst = LA + i * npad + j;  // kInf until a finite sum lowers it
+                if (best < *dst) *dst = best;
             }
         }
     }
 }
 
-// Overflow check: a new cell that no rule gave a finite sum has a length that
-// did not fit (its Boolean product term exists, so some sum was >= 2^31 - 1).
-__global__ void check_new_cells_kernel(const uint64_t* __restrict__ D, const uint32_t* __restrict__ LA,
-                                       int64_t W, int64_t npad, int32_t* overflow) {
+// Overflow check: a new cell that no rule gave a finite sum (still kInf)
+// has a length that did not fit (its Boolean product term exists, so some sum
+// was >= 2^31 - 1); it goes back to 0 (absent).
+__global__ void check_new_cells_kernel(const uint64_t* __restrict__ D, uint32_t* __restrict__ LA, int64_t W,
+                                       int64_t npad, int32_t* overflow) {
     for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < npad * W;
          w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         uint64_t d = D[w];
@@ -347,10 +368,19 @@ __global__ void check_new_cells_kernel(const uint64_t* __restrict__ D, const uin
         while (d) {
             const int b = __ffsll(static_cast<unsigned long long>(d)) - 1;
             d &= d - 1;
-            if (LA[i * npad + j0 + b] == 0) atomicOr(overflow, 1);
+            uint32_t* cell = LA + i * npad + j0 + b;
+            if (*cell >= kInf) {
+                *cell = 0;
+                atomicOr(overflow, 1);
+            }
         }
     }
 }
+
+// Tile kernel launch shape: split each active tile along k until about
+// kTileTarget workgroups have work (two rounds at 7 per CU), at most kMaxSplit
+// ways, and with at most kMaxTileGrid workgroups in the grid.
+constexpr int64_t kTileTarget = 3584, kMaxSplit = 16, kMaxTileGrid = int64_t{1} << 22;
 
 unsigned grid_for(int64_t items, int64_t cap = 65536) {
     return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((items + 255) / 256, cap)));
@@ -370,7 +400,7 @@ struct SpPlan {
     int32_t n_right = 0, n_csc = 0;
     size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0, off_second = 0,
            off_delta = 0, off_trans = 0, off_rowor = 0, off_csc = 0, csc_bytes = 0, off_csc_cursor = 0,
-           off_csc_idx = 0, total = 0;
+           off_csc_idx = 0, off_tinfo = 0, tinfo_bytes = 0, off_tiles = 0, off_tflag = 0, total = 0;
 };
 
 SpPlan sp_plan(const cfpq_graph* g, const cfpq_grammar* gr) {
@@ -424,6 +454,12 @@ SpPlan sp_plan(const cfpq_graph* g, const cfpq_grammar* gr) {
     p.csc_bytes = p.off_csc_idx + align_up(static_cast<size_t>(std::max<int64_t>(g->n_edges, 1)) * 4, 256);
     p.off_csc = off;
     off += p.csc_bytes * p.n_csc;
+    // per loop: new-cell counts (uint64), active-tile counts and tile flags
+    p.off_tinfo = off;
+    p.off_tiles = align_up(static_cast<size_t>(p.n_nt) * 8, 256);
+    p.off_tflag = p.off_tiles + align_up(static_cast<size_t>(p.n_nt) * 4, 256);
+    p.tinfo_bytes = p.off_tflag + align_up(static_cast<size_t>(p.n_nt) * p.L.W * p.L.W * 4, 256);
+    off += p.tinfo_bytes;
     p.total = off;
     return p;
 }
@@ -553,6 +589,16 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
         CFPQ_HIP(hipGetLastError());
     }
 
+    auto* d_dcount = reinterpret_cast<unsigned long long*>(ws + p.off_tinfo);
+    auto* d_tiles = reinterpret_cast<int32_t*>(ws + p.off_tinfo + p.off_tiles);
+    auto* d_tflag = reinterpret_cast<int32_t*>(ws + p.off_tinfo + p.off_tflag);
+    // set bits of every X_A, kept up to date on the host from the new-cell counts
+    std::vector<unsigned long long> xcount(n_nt, 0), dcount(n_nt, 0);
+    std::vector<int32_t> tiles(n_nt, 0);
+    CFPQ_HIP(launch_zero(reinterpret_cast<uint64_t*>(d_dcount), static_cast<size_t>(n_nt), s));
+    CFPQ_HIP(launch_popcount(X, n_nt, L, d_dcount, s));
+    CFPQ_HIP(hipMemcpyAsync(xcount.data(), d_dcount, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
+    CFPQ_HIP(hipStreamSynchronize(s));
     const int64_t nn = graph->n_nodes;
     const int64_t cap = max_iters > 0 ? max_iters : nn * nn * n_nt + 1;
     const size_t lmat = static_cast<size_t>(L.npad) * static_cast<size_t>(L.npad);
@@ -584,7 +630,14 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
             }
             ++products;
         }
+        // the step's new cells, their counts and tiles, L = kInf on them
+        CFPQ_HIP(launch_zero(reinterpret_cast<uint64_t*>(d_dcount), p.tinfo_bytes / 8, s));
+        delta_all_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 1024), static_cast<unsigned>(n_nt)), dim3(256), 0,
+                           s>>>(Y, X, D, d_lengths, L.W, L.npad, d_dcount, d_tflag, d_tiles);
+        CFPQ_HIP(hipGetLastError());
         CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt + 1) * 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipMemcpyAsync(dcount.data(), d_dcount, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipMemcpyAsync(tiles.data(), d_tiles, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
         CFPQ_HIP(hipStreamSynchronize(s));
         ++iters;
         bool any = false;
@@ -593,18 +646,26 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
             converged = true;
             break;
         }
-        for (int32_t a = 0; a < n_nt; ++a) {
-            if (!flags[a]) continue;
-            delta_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 4096)), dim3(256), 0, s>>>(
-                Y + a * mw, X + a * mw, D + a * mw, static_cast<int64_t>(mw));
-            CFPQ_HIP(hipGetLastError());
-        }
-        // rules with a fixed sparse operand: row or column gathers
+        // Min-plus kernel per rule.  A fixed sparse operand: row or column
+        // gathers.  Otherwise the row gather when its estimated time is below
+        // the tile kernel's: about 10 ns per (row with new cells, set bit of
+        // X_B in it) pair against 20 T (i, j, k) terms/s over the active tiles.
         const unsigned gather_grid = static_cast<unsigned>(std::min<int64_t>((L.n + 3) / 4, 2048));
+        std::vector<char> on_tiles(grammar->n_bin_rules, 0);
         for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
             const auto& br = grammar->bin_rules[r];
             if (!flags[br.lhs]) continue;
-            if (p.rows_left[br.left]) {
+            bool rows = p.rows_left[br.left] != 0;
+            if (!rows && p.csc_slot[br.right] < 0) {
+                const double n = static_cast<double>(L.n);
+                const double active_rows =
+                    std::min({n, static_cast<double>(dcount[br.lhs]), 64.0 * tiles[br.lhs]});
+                const double rows_ms = active_rows * static_cast<double>(xcount[br.left]) / n * 1e-5;
+                const double tile_ms = static_cast<double>(tiles[br.lhs]) * kchunks * 131072.0 / 2e10;
+                rows = rows_ms < tile_ms;
+                on_tiles[r] = rows ? 0 : 1;
+            }
+            if (rows) {
                 minplus_rows_kernel<<<dim3(gather_grid), dim3(256), 0, s>>>(
                     D + br.lhs * mw, X + br.left * mw, X + br.right * mw, d_lengths + br.left * lmat,
                     d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, L.n);
@@ -619,14 +680,21 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
             }
             CFPQ_HIP(hipGetLastError());
         }
-        // the others on the tile kernel (timed: its terms are counted)
+        // the others on the tile kernel (timed: its terms are counted); with
+        // few active tiles each is split along k into ksplit workgroups so
+        // that the launch still fills the chip
         CFPQ_HIP(hipEventRecord(mp0, s));
         for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
             const auto& br = grammar->bin_rules[r];
-            if (!flags[br.lhs] || p.rows_left[br.left] || p.csc_slot[br.right] >= 0) continue;
-            minplus_kernel<<<dim3(static_cast<unsigned>(L.W * L.W)), dim3(256), 0, s>>>(
+            if (!on_tiles[r]) continue;
+            const int64_t all_tiles = L.W * L.W;
+            int64_t ksplit = std::max<int64_t>(1, (kTileTarget + tiles[br.lhs] - 1) / std::max(tiles[br.lhs], 1));
+            ksplit = std::min<int64_t>({ksplit, kMaxSplit, std::max<int64_t>(1, kchunks / 2),
+                                        std::max<int64_t>(1, kMaxTileGrid / all_tiles)});
+            minplus_kernel<<<dim3(static_cast<unsigned>(all_tiles * ksplit)), dim3(256), 0, s>>>(
                 D + br.lhs * mw, X + br.left * mw, X + br.right * mw, d_lengths + br.left * lmat,
-                d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, kchunks, d_cells);
+                d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, kchunks,
+                d_tflag + br.lhs * all_tiles, static_cast<int32_t>(ksplit), d_cells);
             CFPQ_HIP(hipGetLastError());
         }
         CFPQ_HIP(hipEventRecord(mp1, s));
@@ -639,6 +707,7 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
         }
         CFPQ_HIP(hipMemcpyAsync(&overflow, d_overflow, 4, hipMemcpyDeviceToHost, s));
         CFPQ_HIP(hipStreamSynchronize(s));
+        for (int32_t a = 0; a < n_nt; ++a) xcount[a] += dcount[a];
         float mp_ms = 0.f;
         CFPQ_HIP(hipEventElapsedTime(&mp_ms, mp0, mp1));
         minplus_ms += mp_ms;
