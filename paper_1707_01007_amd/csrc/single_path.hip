@@ -69,6 +69,10 @@ __global__ __launch_bounds__(256) void delta_all_kernel(const uint64_t* __restri
                                                         const uint64_t* __restrict__ X, uint64_t* __restrict__ D,
                                                         uint32_t* __restrict__ lengths, int64_t W, int64_t npad,
                                                         unsigned long long* dcount, int32_t* tflag, int32_t* tiles) {
+    // one wavefront per 64 consecutive words at a time (npad * W is a
+    // multiple of 64): lanes form the words, then each new word's cells get
+    // kInf in one coalesced masked store
+    const int lane = threadIdx.x & 63;
     const int64_t a = blockIdx.y;
     const int64_t words = npad * W;
     const uint64_t* y = Y + a * words;
@@ -77,18 +81,25 @@ __global__ __launch_bounds__(256) void delta_all_kernel(const uint64_t* __restri
     uint32_t* la = lengths + a * npad * npad;
     int32_t* tf = tflag + a * W * W;
     unsigned long long c = 0;
-    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
-         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        uint64_t v = y[w] & ~x[w];
+    const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
+    for (int64_t base = (static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
+         base < words; base += waves * 64) {
+        const int64_t w = base + lane;
+        const uint64_t v = y[w] & ~x[w];
         d[w] = v;
-        if (!v) continue;
-        c += __popcll(v);
-        const int64_t i = w / W, jw = w % W;
-        if (atomicOr(tf + (i >> 6) * W + jw, 1) == 0) atomicAdd(tiles + a, 1);
-        for (; v; v &= v - 1) la[i * npad + 64 * jw + __ffsll(static_cast<unsigned long long>(v)) - 1] = kInf;
+        if (v) {
+            c += __popcll(v);
+            int32_t* f = tf + (w / W >> 6) * W + w % W;
+            if (*f == 0 && atomicOr(f, 1) == 0) atomicAdd(tiles + a, 1);
+        }
+        for (uint64_t nz = __ballot(v != 0); nz; nz &= nz - 1) {
+            const int src = __ffsll(static_cast<unsigned long long>(nz)) - 1;
+            const int64_t ws = base + src;
+            if ((rowor::readlane64(v, src) >> lane) & 1ull) la[(ws / W) * npad + 64 * (ws % W) + lane] = kInf;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(dcount + a, c);
+    if (lane == 0 && c) atomicAdd(dcount + a, c);
 }
 
 // Chunks of 32 k whose skip mask one pass builds (LDS bits).
@@ -323,6 +334,19 @@ __global__ void csc_fill_kernel(const uint64_t* __restrict__ M, int64_t W, int64
 // its column index: one wavefront per row i at a time, lanes over the new
 // cells (i, j) 64 columns at a time; lane j takes the rows k of column j of C
 // where X_B(i, k) is set.
+__device__ __forceinline__ void cols_cell(int64_t i, int64_t j, const uint64_t* __restrict__ brow,
+                                          const int32_t* __restrict__ cptr, const int32_t* __restrict__ cidx,
+                                          const uint32_t* LB, const uint32_t* LC, uint32_t* LA, int64_t npad) {
+    uint32_t best = kInf;
+    for (int32_t q = cptr[j], e = cptr[j + 1]; q < e; ++q) {
+        const int64_t k = cidx[q];
+        if (!((brow[k >> 6] >> (k & 63)) & 1ull)) continue;
+        best = min(best, LB[i * npad + k] + LC[k * npad + j]);
+    }
+    uint32_t* dst = LA + i * npad + j;  // kInf until a finite sum lowers it
+    if (best < *dst) *dst = best;
+}
+
 __global__ __launch_bounds__(256) void minplus_cols_kernel(const uint64_t* __restrict__ D,
                                                            const uint64_t* __restrict__ XB,
                                                            const int32_t* __restrict__ cptr,
@@ -337,19 +361,27 @@ __global__ __launch_bounds__(256) void minplus_cols_kernel(const uint64_t* __res
         const uint64_t* brow = XB + i * W;
         for (int64_t jw0 = 0; jw0 < W; jw0 += 64) {
             const uint64_t dw = jw0 + lane < W ? drow[jw0 + lane] : 0;
-            for (uint64_t nz = __ballot(dw != 0); nz; nz &= nz - 1) {
-                const int src = __ffsll(static_cast<unsigned long long>(nz)) - 1;
-                if (!((rowor::readlane64(dw, src) >> lane) & 1ull)) continue;
-                const int64_t j = (jw0 + src) * 64 + lane;
-                uint32_t best = kInf;
-                for (int32_t q = cptr[j], e = cptr[j + 1]; q < e; ++q) {
-                    const int64_t k = cidx[q];
-                    if (!((brow[k >> 6] >> (k & 63)) & 1ull)) continue;
-                    const uint32_t v = LB[i * npad + k] + LC[k * npad + j];
-                    best = min(best, v);
+            const uint64_t nz = __ballot(dw != 0);
+            if (!nz) continue;
+            // the fewer steps: each lane walks its own word's bits (as many
+            // steps as the fullest word has bits), or the wavefront walks the
+            // nonzero words with a lane per bit (as many as there are words)
+            int most = __popcll(dw);
+            for (int off = 32; off > 0; off >>= 1) most = max(most, __shfl_xor(most, off, 64));
+            if (most < __popcll(nz)) {
+                for (uint64_t mine = dw; __ballot(mine != 0); ) {
+                    if (mine) {
+                        const int b = __ffsll(static_cast<unsigned long long>(mine)) - 1;
+                        mine &= mine - 1;
+                        cols_cell(i, (jw0 + lane) * 64 + b, brow, cptr, cidx, LB, LC, LA, npad);
+                    }
                 }
-                uint32_t* dst = LA + i * npad + j;  // kInf until a finite sum lowers it
-                if (best < *dst) *dst = best;
+            } else {
+                for (uint64_t m = nz; m; m &= m - 1) {
+                    const int src = __ffsll(static_cast<unsigned long long>(m)) - 1;
+                    if ((rowor::readlane64(dw, src) >> lane) & 1ull)
+                        cols_cell(i, (jw0 + src) * 64 + lane, brow, cptr, cidx, LB, LC, LA, npad);
+                }
             }
         }
     }
