@@ -228,13 +228,15 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
     }
 }
 
-// Min-plus of a rule whose left operand B is a fixed sparse matrix (cells
-// from edges only): one wavefront per row i at a time.  The set bits k of
-// X_B's row become a wave-uniform stream; for each k the lanes take the
-// columns j, 64 at a time, where X_C(k, j) and D_A(i, j) are both set and
-// lower L_A(i, j) to L_B(i, k) + L_C(k, j).  The wavefront owns row i of L_A,
-// so its read-modify-writes need no atomics.  New cells hold kInf until a
-// sum lowers them, so sums of kInf or more change nothing.
+// Row walk min-plus: L_A(i, j) = min over the set bits k of X_B's row i of
+// L_B(i, k) + L_C(k, j), for the new cells (i, j) where X_C(k, j) is set.
+// A work item is (row i, group of kGatherWords words of X_B's row): long rows
+// spread over many wavefronts.  The k of an item form a wave-uniform stream;
+// for each, the lanes take the columns j, 64 at a time, where X_C(k, j) and
+// D_A(i, j) are both set.  Items of one row can meet at a cell, so cells are
+// lowered with atomicMin (a new cell holds kInf until a finite sum lowers it).
+constexpr int kGatherWords = 8;
+
 __global__ __launch_bounds__(256) void minplus_rows_kernel(const uint64_t* __restrict__ D,
                                                            const uint64_t* __restrict__ XB,
                                                            const uint64_t* __restrict__ XC, const uint32_t* LB,
@@ -242,31 +244,31 @@ __global__ __launch_bounds__(256) void minplus_rows_kernel(const uint64_t* __res
                                                            int32_t nrows) {
     const int lane = threadIdx.x & 63;
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nrows;
-         i += waves) {
+    const int64_t groups = (W + kGatherWords - 1) / kGatherWords;
+    for (int64_t item = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+         item < nrows * groups; item += waves) {
+        const int64_t i = item / groups, kw0 = (item % groups) * kGatherWords;
+        const uint64_t bw = lane < kGatherWords && kw0 + lane < W ? XB[i * W + kw0 + lane] : 0;
+        uint64_t nz = __ballot(bw != 0);
+        if (!nz) continue;
         const uint64_t* drow = D + i * W;
         bool any = false;
         for (int64_t w0 = 0; w0 < W && !any; w0 += 64) any = __ballot(w0 + lane < W && drow[w0 + lane] != 0) != 0;
         if (!any) continue;
-        const uint64_t* brow = XB + i * W;
-        for (int64_t kw0 = 0; kw0 < W; kw0 += 64) {
-            const uint64_t bw = kw0 + lane < W ? brow[kw0 + lane] : 0;
-            for (uint64_t nz = __ballot(bw != 0); nz; nz &= nz - 1) {
-                const int src = __ffsll(static_cast<unsigned long long>(nz)) - 1;
-                for (uint64_t kb = rowor::readlane64(bw, src); kb; kb &= kb - 1) {
-                    const int64_t k = (kw0 + src) * 64 + (__ffsll(static_cast<unsigned long long>(kb)) - 1);
-                    const uint32_t lb = LB[i * npad + k];
-                    const uint64_t* crow = XC + k * W;
-                    for (int64_t jw0 = 0; jw0 < W; jw0 += 64) {
-                        const uint64_t m = jw0 + lane < W ? (crow[jw0 + lane] & drow[jw0 + lane]) : 0;
-                        for (uint64_t mz = __ballot(m != 0); mz; mz &= mz - 1) {
-                            const int s2 = __ffsll(static_cast<unsigned long long>(mz)) - 1;
-                            if (!((rowor::readlane64(m, s2) >> lane) & 1ull)) continue;
-                            const int64_t j = (jw0 + s2) * 64 + lane;
-                            const uint32_t v = lb + LC[k * npad + j];
-                            uint32_t* dst = LA + i * npad + j;  // kInf until a finite sum lowers it
-                            if (v < *dst) *dst = v;
-                        }
+        for (; nz; nz &= nz - 1) {
+            const int src = __ffsll(static_cast<unsigned long long>(nz)) - 1;
+            for (uint64_t kb = rowor::readlane64(bw, src); kb; kb &= kb - 1) {
+                const int64_t k = (kw0 + src) * 64 + (__ffsll(static_cast<unsigned long long>(kb)) - 1);
+                const uint32_t lb = LB[i * npad + k];
+                const uint64_t* crow = XC + k * W;
+                for (int64_t jw0 = 0; jw0 < W; jw0 += 64) {
+                    const uint64_t m = jw0 + lane < W ? (crow[jw0 + lane] & drow[jw0 + lane]) : 0;
+                    for (uint64_t mz = __ballot(m != 0); mz; mz &= mz - 1) {
+                        const int s2 = __ffsll(static_cast<unsigned long long>(mz)) - 1;
+                        if (!((rowor::readlane64(m, s2) >> lane) & 1ull)) continue;
+                        const int64_t j = (jw0 + s2) * 64 + lane;
+                        const uint32_t v = lb + LC[k * npad + j];
+                        if (v < kInf) atomicMin(LA + i * npad + j, v);
                     }
                 }
             }
@@ -353,37 +355,22 @@ __global__ __launch_bounds__(256) void minplus_cols_kernel(const uint64_t* __res
                                                            const int32_t* __restrict__ cidx, const uint32_t* LB,
                                                            const uint32_t* LC, uint32_t* LA, int64_t W, int64_t npad,
                                                            int32_t nrows) {
+    // a work item is (row i, group of kGatherWords words of D_A's row); lane
+    // l takes word l / 8 of the group and its bits b with b % 8 == l % 8, so
+    // a lane walks at most 8 new cells and each cell has one owner
     const int lane = threadIdx.x & 63;
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); i < nrows;
-         i += waves) {
-        const uint64_t* drow = D + i * W;
-        const uint64_t* brow = XB + i * W;
-        for (int64_t jw0 = 0; jw0 < W; jw0 += 64) {
-            const uint64_t dw = jw0 + lane < W ? drow[jw0 + lane] : 0;
-            const uint64_t nz = __ballot(dw != 0);
-            if (!nz) continue;
-            // the fewer steps: each lane walks its own word's bits (as many
-            // steps as the fullest word has bits), or the wavefront walks the
-            // nonzero words with a lane per bit (as many as there are words)
-            int most = __popcll(dw);
-            for (int off = 32; off > 0; off >>= 1) most = max(most, __shfl_xor(most, off, 64));
-            if (most < __popcll(nz)) {
-                for (uint64_t mine = dw; __ballot(mine != 0); ) {
-                    if (mine) {
-                        const int b = __ffsll(static_cast<unsigned long long>(mine)) - 1;
-                        mine &= mine - 1;
-                        cols_cell(i, (jw0 + lane) * 64 + b, brow, cptr, cidx, LB, LC, LA, npad);
-                    }
-                }
-            } else {
-                for (uint64_t m = nz; m; m &= m - 1) {
-                    const int src = __ffsll(static_cast<unsigned long long>(m)) - 1;
-                    if ((rowor::readlane64(dw, src) >> lane) & 1ull)
-                        cols_cell(i, (jw0 + src) * 64 + lane, brow, cptr, cidx, LB, LC, LA, npad);
-                }
-            }
-        }
+    const int64_t groups = (W + kGatherWords - 1) / kGatherWords;
+    const int64_t w_in = lane >> 3;
+    const uint64_t phase = 0x0101010101010101ull << (lane & 7);
+    for (int64_t item = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+         item < nrows * groups; item += waves) {
+        const int64_t i = item / groups, w = (item % groups) * kGatherWords + w_in;
+        uint64_t bits = w < W ? (D[i * W + w] & phase) : 0;
+        if (!__ballot(bits != 0)) continue;
+        for (; bits; bits &= bits - 1)
+            cols_cell(i, w * 64 + __ffsll(static_cast<unsigned long long>(bits)) - 1, XB + i * W, cptr, cidx, LB, LC,
+                      LA, npad);
     }
 }
 
@@ -682,7 +669,8 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
         // gathers.  Otherwise the row gather when its estimated time is below
         // the tile kernel's: about 10 ns per (row with new cells, set bit of
         // X_B in it) pair against 20 T (i, j, k) terms/s over the active tiles.
-        const unsigned gather_grid = static_cast<unsigned>(std::min<int64_t>((L.n + 3) / 4, 2048));
+        const int64_t gather_items = static_cast<int64_t>(L.n) * ((L.W + kGatherWords - 1) / kGatherWords);
+        const unsigned gather_grid = static_cast<unsigned>(std::min<int64_t>((gather_items + 3) / 4, 2048));
         std::vector<char> on_tiles(grammar->n_bin_rules, 0);
         for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
             const auto& br = grammar->bin_rules[r];
