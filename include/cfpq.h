@@ -151,7 +151,7 @@ typedef struct {
                                 operands gained the bits D_B, D_C since the previous loop started
                                 may add D_B x C and B x D_C instead of B x C (hybrid choice) */
     double minplus_terms;    /* cfpq_single_path only: (i, j, k) terms l_B(i,k) + l_C(k,j) the min-plus
-                                kernel evaluated (product_ms is then its summed time); 0 elsewhere */
+                                tile kernel evaluated (product_ms is then its summed time); 0 elsewhere */
 } cfpq_stats;
 
 /* ABI version of the loaded library (CFPQ_ABI_VERSION). */
@@ -254,7 +254,10 @@ CFPQ_API cfpq_status cfpq_popcount(int32_t n_nodes, int32_t count, const uint64_
 CFPQ_API size_t cfpq_lengths_bytes(int32_t n_nodes, int32_t n_nonterminals);
 
 /* Workspace for cfpq_single_path: two more bit matrices per nonterminal
- * (the next step and the step's new cells) plus small tables. */
+ * (the next step and the step's new cells), transposed right operands,
+ * per-loop counts and 64 x 64 tile flags of the new cells (4 bytes per tile
+ * and nonterminal), a column index (npad + 1 offsets, npad cursors, one row
+ * id per edge) for each fixed sparse right operand, plus small tables. */
 CFPQ_API cfpq_status cfpq_single_path_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* grammar,
                                                       size_t* bytes);
 
@@ -265,7 +268,10 @@ CFPQ_API cfpq_status cfpq_single_path_workspace_bytes(const cfpq_graph* graph, c
  * `stream`.  Returns CFPQ_OK, CFPQ_ENOTCONV (cap reached: every stored length
  * is still a valid path length), CFPQ_ERANGE, CFPQ_EINVAL, CFPQ_ENOMEM or
  * CFPQ_EDEVICE.  stats: iterations, Boolean products, device time, the
- * min-plus kernel's terms (minplus_terms) and summed time (product_ms).
+ * min-plus tile kernel's terms (minplus_terms) and summed time (product_ms);
+ * rules whose min-plus runs as a row or column gather (a fixed sparse edge
+ * matrix operand, or a left operand sparse enough in that loop) are in
+ * neither figure.
  */
 CFPQ_API cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* grammar, int64_t max_iters,
                                       void* stream, void* d_workspace, size_t workspace_bytes, uint64_t* d_result,
