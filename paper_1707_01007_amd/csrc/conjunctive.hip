@@ -9,7 +9,8 @@
 // Device work per rule with k >= 2 conjuncts: Q = B1 x C1 into a zeroed
 // scratch matrix (the dense product kernels OR into their output), then for
 // every further conjunct R = Bm x Cm into a second scratch matrix and Q &= R,
-// and finally T_A |= Q with the change flag.  One-conjunct rules are ordinary
+// the last one folded into T_A |= Q & R with the change flag (one pass over
+// Q, R and T_A).  One-conjunct rules are ordinary
 // products straight into T_A.  Schedules, dirty-rule worklist and product
 // kernels are those of cfpq_closure (host-driven loop).  With options.hybrid
 // AUTO, a conjunct whose left operand heads no rule (its matrix is fixed by
@@ -34,17 +35,20 @@ __global__ void and_into_kernel(uint64_t* __restrict__ Q, const uint64_t* __rest
         Q[w] &= R[w];
 }
 
-// A |= Q; *changed |= 1 when a bit was added (one atomic per workgroup).
-__global__ __launch_bounds__(256) void or_into_kernel(uint64_t* A, const uint64_t* __restrict__ Q, int64_t words,
-                                                      int32_t* changed) {
+// A |= Q & R (the last conjunct folded into the union), with the change flag.
+__global__ __launch_bounds__(256) void or_and_into_kernel(uint64_t* A, const uint64_t* __restrict__ Q,
+                                                          const uint64_t* __restrict__ R, int64_t words,
+                                                          int32_t* changed) {
     bool ch = false;
     for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
          w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const uint64_t q = Q[w];
         if (!q) continue;
+        const uint64_t v = q & R[w];
+        if (!v) continue;
         const uint64_t old = A[w];
-        if (q & ~old) {
-            A[w] = old | q;
+        if (v & ~old) {
+            A[w] = old | v;
             ch = true;
         }
     }
@@ -304,20 +308,29 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
                 ++products;
                 continue;
             }
-            CFPQ_HIP(launch_zero(Q, mw, s));
+            // Q = first conjunct, R = each further one; the products OR into
+            // their output, so both start zeroed (one fill: R follows Q)
+            if (R == Q + mw) {
+                CFPQ_HIP(launch_zero(Q, 2 * mw, s));
+            } else {
+                CFPQ_HIP(launch_zero(Q, mw, s));
+                CFPQ_HIP(launch_zero(R, mw, s));
+            }
             st = product(r.parts[0].first, r.parts[0].second, Q, d_spare);
             if (st != CFPQ_OK) return st;
             for (size_t m = 1; m < r.parts.size(); ++m) {
-                CFPQ_HIP(launch_zero(R, mw, s));
+                if (m > 1) CFPQ_HIP(launch_zero(R, mw, s));
                 st = product(r.parts[m].first, r.parts[m].second, R, d_spare);
                 if (st != CFPQ_OK) return st;
-                and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
-                    Q, R, static_cast<int64_t>(mw));
+                if (m + 1 < r.parts.size()) {
+                    and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
+                        Q, R, static_cast<int64_t>(mw));
+                } else {
+                    or_and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
+                        Y + r.lhs * mw, Q, R, static_cast<int64_t>(mw), d_flags + r.lhs);
+                }
                 CFPQ_HIP(hipGetLastError());
             }
-            or_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
-                Y + r.lhs * mw, Q, static_cast<int64_t>(mw), d_flags + r.lhs);
-            CFPQ_HIP(hipGetLastError());
             products += static_cast<int64_t>(r.parts.size());
         }
         CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
