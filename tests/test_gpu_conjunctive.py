@@ -92,3 +92,30 @@ def test_partial_and_device_edges(cfpq):
                     allow_partial=True)
     assert res.status in (0, -4)
     assert np.array_equal(got, want)
+
+
+def _anbncn_three_conjuncts():
+    """S -> P Cp & Ap Q & Ap X with X => (b|c)^+: the same language as
+    anbncn (the third conjunct is implied), through a rule of three conjuncts
+    (Q &= R for the middle one, the last folded into the union)."""
+    return grammars._mk_conj(
+        "anbncn3", ["S", "P", "P1", "Q", "Q1", "Ap", "Cp", "A", "B", "C", "X"], ["a", "b", "c"],
+        [("A", "a"), ("B", "b"), ("C", "c"), ("Ap", "a"), ("Cp", "c"), ("X", "b"), ("X", "c")],
+        [("S", [("P", "Cp"), ("Ap", "Q"), ("Ap", "X")]),
+         ("P", [("A", "B")]), ("P", [("A", "P1")]), ("P1", [("P", "B")]),
+         ("Q", [("B", "C")]), ("Q", [("B", "Q1")]), ("Q1", [("Q", "C")]),
+         ("Ap", [("A", "Ap")]), ("Cp", [("C", "Cp")]), ("X", [("B", "X")]), ("X", [("C", "X")])])
+
+
+@pytest.mark.parametrize("graph", ["chain", "er120"])
+@pytest.mark.parametrize("path", ["bits", "fp4"])
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_three_conjunct_rule_matches_oracle(cfpq, graph, path, hybrid):
+    g = _anbncn_three_conjuncts()
+    n, e = _anbncn_chain([2, 4, 1], 7) if graph == "chain" else graphs.erdos_renyi(120, 600, 8, labels=3)
+    want, _ = conjunctive.closure(n, e, g)
+    got, _ = _run(cfpq, n, e, g, path=path, hybrid=hybrid)
+    assert np.array_equal(got, want)
+    if graph == "chain":  # exactly a^n b^n c^n on a chain
+        plain, _ = conjunctive.closure(n, e, grammars.anbncn())
+        assert np.array_equal(got[g.nt("S")], plain[grammars.anbncn().nt("S")])

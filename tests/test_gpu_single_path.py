@@ -158,3 +158,23 @@ def test_linear_closure_lengths_are_shortest_paths(cfpq, side):
     res, got = _lengths(cfpq, n, e, g)
     assert np.array_equal(got[0], _shortest_lengths(n, e))
     assert np.array_equal(got[1] > 0, _shortest_lengths(n, e) == 1)
+
+
+def test_degenerate_inputs(cfpq):
+    """No edges; edges whose label no rule reads; one node with a self-loop;
+    a grammar without binary rules (lengths are the edge cells only)."""
+    empty = np.zeros((0, 3), dtype=np.int32)
+    res, got = _lengths(cfpq, 50, empty, grammars.dyck())
+    assert not got.any() and not cfpq.result_bits(res).any()
+    tc = grammars.transitive_closure()  # reads label a (0) only
+    res, got = _lengths(cfpq, 30, np.array([[0, 1, 1], [1, 1, 2]], dtype=np.int32), tc)
+    assert not got.any()
+    res, got = _lengths(cfpq, 1, np.array([[0, 0, 0]], dtype=np.int32), tc)
+    assert got.shape == (1, 1, 1) and got[0, 0, 0] == 1
+    only_terms = grammars.CNF(("S",), ("a", "b"), ((0, 0),), (), name="only_terms")
+    n, e = graphs.erdos_renyi(70, 300, 21, labels=2)
+    res, got = _lengths(cfpq, n, e, only_terms)
+    want = np.zeros((n, n), dtype=np.int64)
+    a_edges = e[e[:, 1] == 0]
+    want[a_edges[:, 0], a_edges[:, 2]] = 1
+    assert np.array_equal(got[0], want)
