@@ -93,15 +93,34 @@ __global__ __launch_bounds__(256) void delta_snapshot_kernel(const uint64_t* __r
                                                              unsigned long long* __restrict__ count_cur,
                                                              const int32_t* __restrict__ pred) {
     if (pred != nullptr && *pred == 0) return;
+    // 16-byte accesses, two pairs of words in flight per thread (words is a
+    // multiple of 4: W is)
+    const ulonglong2* c2 = reinterpret_cast<const ulonglong2*>(cur);
+    ulonglong2* p2 = reinterpret_cast<ulonglong2*>(P);
+    ulonglong2* d2 = reinterpret_cast<ulonglong2*>(D);
+    const int64_t pairs = words / 2;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     unsigned long long c = 0, cc = 0;
-    for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
-         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const uint64_t x = cur[w];
-        const uint64_t d = x & ~P[w];
-        D[w] = d;
-        P[w] = x;
-        c += __popcll(d);
-        cc += __popcll(x);
+    int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; w + stride < pairs; w += 2 * stride) {
+        const ulonglong2 x0 = c2[w], x1 = c2[w + stride];
+        const ulonglong2 o0 = p2[w], o1 = p2[w + stride];
+        const ulonglong2 n0 = make_ulonglong2(x0.x & ~o0.x, x0.y & ~o0.y);
+        const ulonglong2 n1 = make_ulonglong2(x1.x & ~o1.x, x1.y & ~o1.y);
+        d2[w] = n0;
+        d2[w + stride] = n1;
+        p2[w] = x0;
+        p2[w + stride] = x1;
+        c += __popcll(n0.x) + __popcll(n0.y) + __popcll(n1.x) + __popcll(n1.y);
+        cc += __popcll(x0.x) + __popcll(x0.y) + __popcll(x1.x) + __popcll(x1.y);
+    }
+    if (w < pairs) {
+        const ulonglong2 x0 = c2[w], o0 = p2[w];
+        const ulonglong2 n0 = make_ulonglong2(x0.x & ~o0.x, x0.y & ~o0.y);
+        d2[w] = n0;
+        p2[w] = x0;
+        c += __popcll(n0.x) + __popcll(n0.y);
+        cc += __popcll(x0.x) + __popcll(x0.y);
     }
     for (int off = 32; off > 0; off >>= 1) {
         c += __shfl_down(c, off, 64);
@@ -126,8 +145,10 @@ __global__ __launch_bounds__(256) void delta_snapshot_kernel(const uint64_t* __r
 hipError_t launch_delta_snapshot(const uint64_t* cur, uint64_t* P, uint64_t* D, const Layout& L,
                                  unsigned long long* count, unsigned long long* count_cur, const int32_t* pred,
                                  hipStream_t s) {
-    int64_t blocks = (L.mat_words + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    // about four pairs of words per thread
+    int64_t blocks = (L.mat_words / 2 + 1023) / 1024;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
     delta_snapshot_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(cur, P, D, L.mat_words, count,
                                                                                    count_cur, pred);
     return hipGetLastError();
