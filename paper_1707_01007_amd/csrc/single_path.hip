@@ -397,9 +397,10 @@ __global__ void check_new_cells_kernel(const uint64_t* __restrict__ D, uint32_t*
 }
 
 // Tile kernel launch shape: split each active tile along k until about
-// kTileTarget workgroups have work (two rounds at 7 per CU), at most kMaxSplit
-// ways, and with at most kMaxTileGrid workgroups in the grid.
-constexpr int64_t kTileTarget = 3584, kMaxSplit = 16, kMaxTileGrid = int64_t{1} << 22;
+// kTileTarget workgroups have work (eight rounds at 7 per CU: short pieces
+// keep the last round's tail small), at most kMaxSplit ways, and with at most
+// kMaxTileGrid workgroups in the grid.
+constexpr int64_t kTileTarget = 14336, kMaxSplit = 16, kMaxTileGrid = int64_t{1} << 22;
 
 unsigned grid_for(int64_t items, int64_t cap = 65536) {
     return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((items + 255) / 256, cap)));
