@@ -145,9 +145,11 @@ __global__ __launch_bounds__(256) void delta_snapshot_kernel(const uint64_t* __r
 hipError_t launch_delta_snapshot(const uint64_t* cur, uint64_t* P, uint64_t* D, const Layout& L,
                                  unsigned long long* count, unsigned long long* count_cur, const int32_t* pred,
                                  hipStream_t s) {
-    // about four pairs of words per thread
+    // at most 256 workgroups: each adds its two counts with one atomic apiece,
+    // and more workgroups queue on those two addresses (2048 cost 0.3 ms per
+    // hybrid closure at n = 16384)
     int64_t blocks = (L.mat_words / 2 + 1023) / 1024;
-    if (blocks > 8192) blocks = 8192;
+    if (blocks > 256) blocks = 256;
     if (blocks < 1) blocks = 1;
     delta_snapshot_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(cur, P, D, L.mat_words, count,
                                                                                    count_cur, pred);
@@ -185,7 +187,7 @@ hipError_t launch_popcount(const uint64_t* mats, int32_t count, const Layout& L,
                            unsigned long long* counts, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     int64_t blocks = (L.mat_words / 2 + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > 256) blocks = 256;  // one same-address atomic per workgroup and matrix
     popcount_kernel<<<dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(count)), dim3(256), 0,
                       s>>>(mats, L.mat_words, counts);
     return hipGetLastError();

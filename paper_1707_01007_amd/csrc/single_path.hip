@@ -81,6 +81,7 @@ __global__ __launch_bounds__(256) void delta_all_kernel(const uint64_t* __restri
     uint32_t* la = lengths + a * npad * npad;
     int32_t* tf = tflag + a * W * W;
     unsigned long long c = 0;
+    uint32_t first = 0;  // tiles this thread flagged first
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
     for (int64_t base = (static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
          base < words; base += waves * 64) {
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void delta_all_kernel(const uint64_t* __restri
         if (v) {
             c += __popcll(v);
             int32_t* f = tf + (w / W >> 6) * W + w % W;
-            if (*f == 0 && atomicOr(f, 1) == 0) atomicAdd(tiles + a, 1);
+            if (*f == 0 && atomicOr(f, 1) == 0) ++first;
         }
         for (uint64_t nz = __ballot(v != 0); nz; nz &= nz - 1) {
             const int src = __ffsll(static_cast<unsigned long long>(nz)) - 1;
@@ -98,8 +99,24 @@ __global__ __launch_bounds__(256) void delta_all_kernel(const uint64_t* __restri
             if ((rowor::readlane64(v, src) >> lane) & 1ull) la[(ws / W) * npad + 64 * (ws % W) + lane] = kInf;
         }
     }
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-    if (lane == 0 && c) atomicAdd(dcount + a, c);
+    // one atomic per workgroup and counter (same-address atomics queue)
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_down(c, off, 64);
+        first += __shfl_down(first, off, 64);
+    }
+    __shared__ unsigned long long pc[4];
+    __shared__ uint32_t pf[4];
+    if (lane == 0) {
+        pc[threadIdx.x >> 6] = c;
+        pf[threadIdx.x >> 6] = first;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long tc = pc[0] + pc[1] + pc[2] + pc[3];
+        const uint32_t tn = pf[0] + pf[1] + pf[2] + pf[3];
+        if (tc) atomicAdd(dcount + a, tc);
+        if (tn) atomicAdd(tiles + a, static_cast<int32_t>(tn));
+    }
 }
 
 // Chunks of 32 k whose skip mask one pass builds (LDS bits).
@@ -652,7 +669,7 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
         }
         // the step's new cells, their counts and tiles, L = kInf on them
         CFPQ_HIP(launch_zero(reinterpret_cast<uint64_t*>(d_dcount), p.tinfo_bytes / 8, s));
-        delta_all_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 1024), static_cast<unsigned>(n_nt)), dim3(256), 0,
+        delta_all_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 256), static_cast<unsigned>(n_nt)), dim3(256), 0,
                            s>>>(Y, X, D, d_lengths, L.W, L.npad, d_dcount, d_tflag, d_tiles);
         CFPQ_HIP(hipGetLastError());
         CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt + 1) * 4, hipMemcpyDeviceToHost, s));
