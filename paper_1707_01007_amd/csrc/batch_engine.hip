@@ -498,7 +498,7 @@ __device__ void engine_gather_row(const SlotDesc& d, const uint64_t* Bm, const u
         }
     }
     if (__ballot(ch) != 0 && lane == 0) {
-        atomicOr(changed, 1);
+        raise_flag(changed);
         if (arows != nullptr)
             atomicOr(reinterpret_cast<unsigned long long*>(arows + (row >> 6)), 1ull << (row & 63));
     }
@@ -565,7 +565,7 @@ __device__ void engine_push_block(const SlotDesc& d, const uint64_t* BT, const u
             }
         }
     }
-    if (any && lane == 0) atomicOr(changed, 1);
+    if (any && lane == 0) raise_flag(changed);
 }
 
 // The loop's row-gather work, one wavefront per item, grid-stride (items of

@@ -185,6 +185,13 @@ inline int32_t hybrid_mode(const HybridModel& m, double nnz_b, double nnz_c, boo
 hipError_t launch_delta_snapshot(const uint64_t* cur, uint64_t* P, uint64_t* D, const Layout& L,
                                  unsigned long long* count, unsigned long long* count_cur, const int32_t* pred,
                                  hipStream_t s);
+// *flag = 1, skipping the atomic when a relaxed device-scope load already
+// reads it set: a change flag only goes from 0 to 1 while products run, and
+// thousands of workgroups OR-ing one address queue behind each other.
+__device__ __forceinline__ void raise_flag(int32_t* flag) {
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) atomicOr(flag, 1);
+}
+
 // 64 x 64 bit transpose across a wavefront: lane t holds row t of the block
 // and gets row t of its transpose.  Six exchange stages: lanes t and t ^ j
 // (j = 32, 16, ..., 1) swap the off-diagonal j x j sub-blocks of every

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void or_and_into_kernel(uint64_t* A, const uin
             ch = true;
         }
     }
-    if (__syncthreads_or(ch) && threadIdx.x == 0) atomicOr(changed, 1);
+    if (__syncthreads_or(ch) && threadIdx.x == 0) raise_flag(changed);
 }
 
 unsigned grid_for(int64_t words) {

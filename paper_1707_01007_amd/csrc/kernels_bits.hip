@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void bits_product_kernel(const uint32_t* __res
             ch = true;
         }
     }
-    if (__ballot(ch) != 0 && (threadIdx.x & 63) == 0) atomicOr(changed, 1);
+    if (__ballot(ch) != 0 && (threadIdx.x & 63) == 0) raise_flag(changed);
 }
 
 }  // namespace

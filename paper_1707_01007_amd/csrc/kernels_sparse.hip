@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void rowor_kernel(const uint64_t* Bm, const ui
             }
         }
     }
-    if (__syncthreads_or(ch) && threadIdx.x == 0 && changed != nullptr) atomicOr(changed, 1);
+    if (__syncthreads_or(ch) && threadIdx.x == 0 && changed != nullptr) raise_flag(changed);
 }
 
 // Long rows: one workgroup per segment of a row (grid-stride over the
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void rowor_heavy_kernel(const uint64_t* Bm, co
             __syncthreads();  // red is reused
         }
     }
-    if (__syncthreads_or(ch) && threadIdx.x == 0 && changed != nullptr) atomicOr(changed, 1);
+    if (__syncthreads_or(ch) && threadIdx.x == 0 && changed != nullptr) raise_flag(changed);
 }
 
 // A |= transpose(Pt), with the change flag; one wavefront per 256 x 256 tile
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void transpose_or_kernel(const uint64_t* __res
             }
         }
     }
-    if (__syncthreads_or(ch) && threadIdx.x == 0) atomicOr(changed, 1);
+    if (__syncthreads_or(ch) && threadIdx.x == 0) raise_flag(changed);
 }
 
 // Enough resident wavefronts to hide the memory latency of the row walks.
