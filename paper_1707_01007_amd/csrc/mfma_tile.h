@@ -119,7 +119,7 @@ __device__ __forceinline__ void store_tile(const Acc (&acc)[kJT][kIT], uint32_t*
                          static_cast<unsigned long long>(rows << (base & 63)));
         }
     }
-    if (__ballot(ch) != 0 && lane == 0) atomicOr(changed, 1);
+    if (__ballot(ch) != 0 && lane == 0) raise_flag(changed);
 }
 
 // One 256 x 256 output tile (rows i of tile_i, columns j of tile_j) of
