@@ -628,12 +628,17 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
     __shared__ int32_t item_s;
     const int n_jobs = es->n_jobs;
     const int total = es->total_items;
+    // the next item's index is fetched while the current one is multiplied,
+    // so the queue's atomic round trip overlaps the work
+    int32_t ahead = 0;
+    if (threadIdx.x == 0) ahead = atomicAdd(&es->next_item, 1);
     while (true) {
-        if (threadIdx.x == 0) item_s = atomicAdd(&es->next_item, 1);
+        if (threadIdx.x == 0) item_s = ahead;
         __syncthreads();
         const int item = item_s;
         __syncthreads();
         if (item >= total) break;
+        if (threadIdx.x == 0) ahead = atomicAdd(&es->next_item, 1);
         const Job jb = jobs[job_of(jobs, n_jobs, item)];
         const SlotDesc& d = descs[jb.slot];
         const int r = d.rule_off + jb.what;
