@@ -116,9 +116,15 @@ inline hipError_t launch_mfma_path(int32_t path, const uint64_t* B, const uint64
 // row product (no flag wanted).  `scratch`: device memory of
 // rowor_scratch_bytes (the list of rows long enough to be split), 16-byte
 // aligned, owned by the caller; not shared by launches in flight at once.
+// call < 0: the list count is cleared before the product (one more launch).
+// call = 0, 1, 2, ... for the products of one stream on one scratch area,
+// after launch_rowor_reset on it: each product clears the count the next one
+// uses (the calls must be numbered without gaps, in stream order).
 size_t rowor_scratch_bytes(const Layout& L);
+hipError_t launch_rowor_reset(int32_t* scratch, hipStream_t s);
 hipError_t launch_rowor_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L, int32_t* changed,
-                                int32_t* scratch, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1);
+                                int32_t* scratch, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1,
+                                int64_t call = -1);
 hipError_t launch_transpose_or(const uint64_t* Pt, uint64_t* A, const Layout& L, int32_t* changed, hipStream_t s,
                                const int32_t* go = nullptr, int32_t want = 1);
 

@@ -491,6 +491,10 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     uint64_t* SNAP = reinterpret_cast<uint64_t*>(ws + p.off_snap);
     uint64_t* DELTA = reinterpret_cast<uint64_t*>(ws + p.off_delta);
     auto* ROWOR = reinterpret_cast<int32_t*>(ws + p.off_rowor);
+    // row-gather products number their calls so each clears the next one's
+    // list count (launch_rowor_product); the count pair starts cleared
+    int64_t rowor_calls = 0;
+    if ((p.hybrid || p.forced != kModeDense) && !converged) CFPQ_HIP(launch_rowor_reset(ROWOR, s));
     std::vector<unsigned long long> nnz(n_nt, 0), dnnz(2 * static_cast<size_t>(n_nt), 0);
     std::vector<char> written(n_nt, 0);  // a product wrote this nonterminal in the current loop
     int64_t sparse_products = 0, delta_products = 0;
@@ -511,7 +515,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     auto product_by = [&](int32_t mode, const uint64_t* Bm, const uint64_t* bt, const uint64_t* Cm,
                           const uint64_t* ct, uint64_t* Am, int32_t* flag) -> cfpq_status {
         if (mode == kModeRows) {
-            CFPQ_HIP(launch_rowor_product(Bm, Cm, Am, L, flag, ROWOR, s));
+            CFPQ_HIP(launch_rowor_product(Bm, Cm, Am, L, flag, ROWOR, s, nullptr, 1, rowor_calls++));
             return CFPQ_OK;
         }
         if ((mode == kModeCols || reads_ct(p.path)) && !ct) {
@@ -525,7 +529,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                 bt = BT;
             }
             CFPQ_HIP(launch_zero(PT, mat_words, s));
-            CFPQ_HIP(launch_rowor_product(ct, bt, PT, L, nullptr, ROWOR, s));
+            CFPQ_HIP(launch_rowor_product(ct, bt, PT, L, nullptr, ROWOR, s, nullptr, 1, rowor_calls++));
             CFPQ_HIP(launch_transpose_or(PT, Am, L, flag, s));
         } else if (reads_ct(p.path)) {
             CFPQ_HIP(launch_mfma_path(p.path, Bm, ct, Am, L, flag, s));

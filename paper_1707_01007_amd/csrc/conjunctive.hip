@@ -277,10 +277,12 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
         if (p.right_slot[a] >= 0) CFPQ_HIP(launch_transpose(X + a * mw, TT + p.right_slot[a] * mw, L, s));
 
     int32_t* rowor_ws = reinterpret_cast<int32_t*>(ws + p.off_rowor);
+    int64_t rowor_calls = 0;  // numbered row-gather calls (launch_rowor_product)
+    if (p.any_rows) CFPQ_HIP(launch_rowor_reset(rowor_ws, s));
     int64_t sparse = 0;
     auto product = [&](int32_t b, int32_t c, uint64_t* out, int32_t* flag) -> cfpq_status {
         if (p.rows_left[b]) {
-            CFPQ_HIP(launch_rowor_product(X + b * mw, X + c * mw, out, L, flag, rowor_ws, s));
+            CFPQ_HIP(launch_rowor_product(X + b * mw, X + c * mw, out, L, flag, rowor_ws, s, nullptr, 1, rowor_calls++));
             ++sparse;
         } else if (reads_ct(p.path))
             CFPQ_HIP(launch_mfma_path(p.path, X + b * mw, TT + p.right_slot[c] * mw, out, L, flag, s));

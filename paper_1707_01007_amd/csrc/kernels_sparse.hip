@@ -35,12 +35,15 @@ constexpr int32_t kSegmentBits = 1024;  // about this many set bits per workgrou
 // heavy_count), so that a long row does not serialise on one wavefront.
 // Bm and Cm may alias Am (in-place update; only bits are ever added, so any
 // mix of old and new words read is a subset of the fixpoint): no __restrict__.
+// next_count: the other list count of a double-buffered pair, cleared here
+// for the next product (or nullptr).
 template <int WPL>
 __global__ __launch_bounds__(256) void rowor_kernel(const uint64_t* Bm, const uint64_t* Cm, uint64_t* Am, int64_t W,
                                                     int32_t nrows, int32_t kwords, int32_t* changed,
-                                                    int32_t* heavy_count, int32_t* heavy, const int32_t* go,
-                                                    int32_t want) {
+                                                    int32_t* heavy_count, int32_t* heavy, int32_t* next_count,
+                                                    const int32_t* go, int32_t want) {
     if (go != nullptr && *go != want) return;  // uniform over the grid
+    if (next_count != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     const int lane = threadIdx.x & 63;
     const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
     bool ch = false;
@@ -187,33 +190,46 @@ constexpr int64_t kSparseMaxBlocks = 2048;
 }  // namespace
 
 hipError_t launch_rowor_product(const uint64_t* B, const uint64_t* C, uint64_t* A, const Layout& L, int32_t* changed,
-                                int32_t* scratch, hipStream_t s, const int32_t* go, int32_t want) {
+                                int32_t* scratch, hipStream_t s, const int32_t* go, int32_t want, int64_t call) {
     const int32_t nrows = L.n;
     if (nrows == 0) return hipSuccess;
     const int32_t kwords = static_cast<int32_t>((L.n + 63) / 64);
     const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((nrows + 3) / 4, kSparseMaxBlocks));
-    int32_t* heavy_count = scratch;
     int32_t* heavy = scratch + 64;  // segments (row, seg << 16 | count) from byte 256 on
-    hipError_t e = launch_zero(reinterpret_cast<uint64_t*>(scratch), 1, s, go, want);
-    if (e != hipSuccess) return e;
+    // list count: scratch[0] cleared here, or (call >= 0, no predicate) the
+    // double-buffered pair scratch[call & 1] / scratch[(call + 1) & 1]: this
+    // product's light kernel clears the other one for the next product
+    int32_t* heavy_count = scratch;
+    int32_t* next_count = nullptr;
+    if (call >= 0 && go == nullptr) {
+        heavy_count = scratch + (call & 1);
+        next_count = scratch + ((call + 1) & 1);
+    } else {
+        hipError_t e = launch_zero(reinterpret_cast<uint64_t*>(scratch), 1, s, go, want);
+        if (e != hipSuccess) return e;
+    }
     const unsigned hblocks = 1024;
     if (L.W <= 64 * 2) {
         rowor_kernel<2><<<dim3(blocks), dim3(256), 0, s>>>(B, C, A, L.W, nrows, kwords, changed, heavy_count, heavy,
-                                                          go, want);
+                                                          next_count, go, want);
         rowor_heavy_kernel<2><<<dim3(hblocks), dim3(256), 0, s>>>(B, C, A, L.W, kwords, changed, heavy_count, heavy,
                                                                  go, want);
     } else if (L.W <= 64 * 4) {
         rowor_kernel<4><<<dim3(blocks), dim3(256), 0, s>>>(B, C, A, L.W, nrows, kwords, changed, heavy_count, heavy,
-                                                          go, want);
+                                                          next_count, go, want);
         rowor_heavy_kernel<4><<<dim3(hblocks), dim3(256), 0, s>>>(B, C, A, L.W, kwords, changed, heavy_count, heavy,
                                                                  go, want);
     } else {
         rowor_kernel<kMaxWordsPerLane><<<dim3(blocks), dim3(256), 0, s>>>(B, C, A, L.W, nrows, kwords, changed,
-                                                                          heavy_count, heavy, go, want);
+                                                                          heavy_count, heavy, next_count, go, want);
         rowor_heavy_kernel<kMaxWordsPerLane><<<dim3(hblocks), dim3(256), 0, s>>>(B, C, A, L.W, kwords, changed,
                                                                                  heavy_count, heavy, go, want);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_rowor_reset(int32_t* scratch, hipStream_t s) {
+    return launch_zero(reinterpret_cast<uint64_t*>(scratch), 1, s);
 }
 
 // A row of at most 64 * kwords bits has at most kwords / 16 + 1 segments.

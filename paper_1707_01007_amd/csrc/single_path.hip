@@ -646,6 +646,8 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
     int32_t overflow = 0;
     uint64_t* TT = reinterpret_cast<uint64_t*>(ws + p.off_trans);
     int32_t* rowor_ws = reinterpret_cast<int32_t*>(ws + p.off_rowor);
+    int64_t rowor_calls = 0;  // numbered row-gather calls (launch_rowor_product)
+    if (p.any_rows) CFPQ_HIP(launch_rowor_reset(rowor_ws, s));
     while (!converged && iters < cap) {
         // transposed right operands of X: all in the first loop, then those X changed in
         for (int32_t a = 0; a < n_nt; ++a)
@@ -657,7 +659,7 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
             int32_t* flag = d_flags + br.lhs;
             if (p.rows_left[br.left]) {
                 CFPQ_HIP(launch_rowor_product(X + br.left * mw, X + br.right * mw, Y + br.lhs * mw, L, flag, rowor_ws,
-                                              s));
+                                              s, nullptr, 1, rowor_calls++));
                 ++sparse;
             } else if (p.mfma) {
                 CFPQ_HIP(launch_mfma_path(CFPQ_PATH_FP4, X + br.left * mw, TT + p.right_slot[br.right] * mw,
