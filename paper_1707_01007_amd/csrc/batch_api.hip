@@ -357,9 +357,8 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
         for (int32_t it = 0; it < K && ce == hipSuccess; ++it) {
             ce = engine_plan(b, cs);
             if (ce == hipSuccess) ce = engine_products(b, grid_p, 8 * cus, cs);  // rows: up to 8 waves per SIMD
-            if (ce == hipSuccess) ce = engine_tplan(b, 0, cs);
+            if (ce == hipSuccess) ce = engine_tplan_finish(b, cs);
             if (ce == hipSuccess) ce = engine_transposes(b, grid_t, cs);
-            if (ce == hipSuccess) ce = engine_finish(b, cs);
         }
         hipError_t ee = hipStreamEndCapture(cs, &g);
         if (ce != hipSuccess) return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));

@@ -167,6 +167,9 @@ hipError_t engine_plan(const EngineBuffers& b, hipStream_t s);
 hipError_t engine_products(const EngineBuffers& b, int32_t grid, int32_t rows_grid, hipStream_t s);
 hipError_t engine_tplan(const EngineBuffers& b, int32_t fresh, hipStream_t s);
 hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, hipStream_t s);
-hipError_t engine_finish(const EngineBuffers& b, hipStream_t s);
+// End of a loop: the transposes of the right operands it changed are listed
+// (as engine_tplan with fresh = 0), then each slot that took part counts the
+// loop and stops if it set no bit; engine_transposes then runs the list.
+hipError_t engine_tplan_finish(const EngineBuffers& b, hipStream_t s);
 
 }  // namespace cfpq

@@ -659,11 +659,9 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
 // Work list of transposes: every right operand of every running large slot
 // that changed in this loop (fresh = 1: every right operand of every newly
 // admitted slot, whose `fresh` flag is then cleared).
-__global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __restrict__ descs,
-                                                           SlotState* states,
-                                                           const int32_t* __restrict__ trans_tab, Job* tjobs,
-                                                           EngineState* es, const int32_t* __restrict__ large_ids,
-                                                           int32_t fresh) {
+__device__ void engine_tplan_body(const SlotDesc* __restrict__ descs, SlotState* states,
+                                  const int32_t* __restrict__ trans_tab, Job* tjobs, EngineState* es,
+                                  const int32_t* __restrict__ large_ids, int32_t fresh) {
     __shared__ int32_t sa[256], sb[256];
     const int t = threadIdx.x;
     const int n_large = es->n_large;
@@ -691,6 +689,14 @@ __global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __res
             if (t == 0) es->next_titem = 0;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __restrict__ descs,
+                                                           SlotState* states,
+                                                           const int32_t* __restrict__ trans_tab, Job* tjobs,
+                                                           EngineState* es, const int32_t* __restrict__ large_ids,
+                                                           int32_t fresh) {
+    engine_tplan_body(descs, states, trans_tab, tjobs, es, large_ids, fresh);
 }
 
 // Transposes of the loop's work list: an item is one 256 x 256 tile
@@ -726,9 +732,8 @@ __global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* _
 
 // End of a loop: count it for every slot that took part; a slot whose loop set
 // no bit has reached its fixpoint.
-__global__ __launch_bounds__(256) void engine_finish_kernel(SlotState* states, EngineState* es,
-                                                            const SlotDesc* __restrict__ descs,
-                                                            const int32_t* __restrict__ large_ids) {
+__device__ void engine_finish_body(SlotState* states, EngineState* es, const SlotDesc* __restrict__ descs,
+                                   const int32_t* __restrict__ large_ids) {
     __shared__ int32_t running;
     const int n_large = es->n_large;
     if (threadIdx.x == 0) running = 0;
@@ -753,6 +758,20 @@ __global__ __launch_bounds__(256) void engine_finish_kernel(SlotState* states, E
     }
     __syncthreads();
     if (threadIdx.x == 0) es->running = running;
+}
+
+// The end of a loop in one launch: the transposes of the right operands this
+// loop changed are listed first (they read in_loop and the change flags),
+// then the loop is finished (which clears in_loop).  The transposes then run
+// from the list; they do not read what finishing changes.
+__global__ __launch_bounds__(256) void engine_tplan_finish_kernel(const SlotDesc* __restrict__ descs,
+                                                                  SlotState* states,
+                                                                  const int32_t* __restrict__ trans_tab,
+                                                                  Job* tjobs, EngineState* es,
+                                                                  const int32_t* __restrict__ large_ids) {
+    engine_tplan_body(descs, states, trans_tab, tjobs, es, large_ids, 0);
+    __syncthreads();
+    engine_finish_body(states, es, descs, large_ids);
 }
 
 }  // namespace
@@ -812,8 +831,9 @@ hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t engine_finish(const EngineBuffers& b, hipStream_t s) {
-    engine_finish_kernel<<<dim3(1), dim3(256), 0, s>>>(b.states, b.es, b.descs, b.large_ids);
+hipError_t engine_tplan_finish(const EngineBuffers& b, hipStream_t s) {
+    engine_tplan_finish_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.trans_tab, b.tjobs, b.es,
+                                                             b.large_ids);
     return hipGetLastError();
 }
 

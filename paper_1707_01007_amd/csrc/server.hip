@@ -649,9 +649,8 @@ cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, c
     for (int32_t it = 0; it < cfg.capture && ce == hipSuccess; ++it) {
         ce = engine_plan(srv->b, cs);
         if (ce == hipSuccess) ce = engine_products(srv->b, srv->cus, 2 * srv->cus, cs);
-        if (ce == hipSuccess) ce = engine_tplan(srv->b, 0, cs);
+        if (ce == hipSuccess) ce = engine_tplan_finish(srv->b, cs);
         if (ce == hipSuccess) ce = engine_transposes(srv->b, 4 * srv->cus, cs);
-        if (ce == hipSuccess) ce = engine_finish(srv->b, cs);
     }
     hipError_t ee = hipStreamEndCapture(cs, &srv->graph);
     if (ce != hipSuccess || ee != hipSuccess) {
