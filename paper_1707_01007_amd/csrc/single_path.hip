@@ -648,6 +648,7 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
     int32_t* rowor_ws = reinterpret_cast<int32_t*>(ws + p.off_rowor);
     int64_t rowor_calls = 0;  // numbered row-gather calls (launch_rowor_product)
     if (p.any_rows) CFPQ_HIP(launch_rowor_reset(rowor_ws, s));
+    bool pending = false;
     while (!converged && iters < cap) {
         // transposed right operands of X: all in the first loop, then those X changed in
         for (int32_t a = 0; a < n_nt; ++a)
@@ -678,6 +679,19 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
         CFPQ_HIP(hipMemcpyAsync(dcount.data(), d_dcount, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
         CFPQ_HIP(hipMemcpyAsync(tiles.data(), d_tiles, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
         CFPQ_HIP(hipStreamSynchronize(s));
+        if (pending) {
+            // the previous loop's min-plus time, and its overflow check (the
+            // flag after the change flags, read back with them): on overflow
+            // this loop's Boolean step is dropped (X is untouched)
+            float mp_ms = 0.f;
+            CFPQ_HIP(hipEventElapsedTime(&mp_ms, mp0, mp1));
+            minplus_ms += mp_ms;
+            pending = false;
+            if (flags[n_nt]) {
+                overflow = 1;
+                break;
+            }
+        }
         ++iters;
         bool any = false;
         for (int32_t a = 0; a < n_nt; ++a) any = any || flags[a] != 0;
@@ -745,16 +759,17 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
             CFPQ_HIP(hipGetLastError());
             CFPQ_HIP(hipMemcpyAsync(X + a * mw, Y + a * mw, mw * 8, hipMemcpyDeviceToDevice, s));
         }
-        CFPQ_HIP(hipMemcpyAsync(&overflow, d_overflow, 4, hipMemcpyDeviceToHost, s));
-        CFPQ_HIP(hipStreamSynchronize(s));
         for (int32_t a = 0; a < n_nt; ++a) xcount[a] += dcount[a];
-        float mp_ms = 0.f;
-        CFPQ_HIP(hipEventElapsedTime(&mp_ms, mp0, mp1));
-        minplus_ms += mp_ms;
-        if (overflow) break;
+        pending = true;  // min-plus time and overflow are read at the next synchronisation
     }
     CFPQ_HIP(hipEventRecord(ev1, s));
     CFPQ_HIP(hipEventSynchronize(ev1));
+    if (pending) {
+        float mp_ms = 0.f;
+        CFPQ_HIP(hipEventElapsedTime(&mp_ms, mp0, mp1));
+        minplus_ms += mp_ms;
+        CFPQ_HIP(hipMemcpy(&overflow, d_overflow, 4, hipMemcpyDeviceToHost));
+    }
     float ms = 0.f;
     CFPQ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     if (stats) {
