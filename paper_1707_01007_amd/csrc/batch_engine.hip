@@ -599,7 +599,12 @@ __global__ __launch_bounds__(256) void engine_rows_kernel(const SlotDesc* __rest
         int32_t* changed = &states[jb.slot].changed[ra];
         if (jb.dim == 1) {  // pull: x - item_begin is a row of A
             const int64_t row = x - jb.item_begin;
-            uint64_t* arows = d.RD ? d.RD + (static_cast<size_t>(it & 1) * d.n_nt + ra) * bw : nullptr;
+            // changed rows are recorded from the last pull loop on: the first
+            // push loop reads the bitmaps of that loop and its own, and the
+            // bitmap of an earlier loop is cleared before anything reads it
+            uint64_t* arows = d.RD && it >= kPullLoops - 1
+                                  ? d.RD + (static_cast<size_t>(it & 1) * d.n_nt + ra) * bw
+                                  : nullptr;
             if (d.W <= 64)
                 engine_gather_row<1>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed, arows);
             else
@@ -649,8 +654,9 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
         const uint32_t* CT = reinterpret_cast<const uint32_t*>(d.TT) + trans_tab[d.trans_off + rc] * mdw;
         uint32_t* Am = reinterpret_cast<uint32_t*>(d.T) + ra * mdw;
         const int kchunks = (d.n + 255) / 256;  // 256-k chunks of the fp4 tile
-        uint64_t* rows =
-            d.RD ? d.RD + (static_cast<size_t>(states[jb.slot].iterations & 1) * d.n_nt + ra) * d.W : nullptr;
+        const int64_t it = states[jb.slot].iterations;
+        uint64_t* rows =  // recorded from the last pull loop on, as in engine_rows_kernel
+            d.RD && it >= kPullLoops - 1 ? d.RD + (static_cast<size_t>(it & 1) * d.n_nt + ra) * d.W : nullptr;
         mfma::mfma4_tile<true>(Bm, CT, Am, 2 * d.W, kchunks, local / jb.dim, local % jb.dim,
                                &states[jb.slot].changed[ra], rows);
     }
