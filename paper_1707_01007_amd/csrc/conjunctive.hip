@@ -72,8 +72,17 @@ struct CjPlan {
     std::vector<char> rows_left;  // per nonterminal: conjuncts with it as left operand run as ROWS
     int32_t n_right = 0;
     bool any_rows = false;
+    // dense conjuncts B C that occur more than once in the grammar: each is
+    // multiplied once per loop into its own matrix, read by every use
+    std::vector<std::pair<int32_t, int32_t>> shared;
     size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0, off_second = 0,
-           off_trans = 0, off_q = 0, off_r = 0, off_rowor = 0, total = 0;
+           off_trans = 0, off_q = 0, off_r = 0, off_rowor = 0, off_shared = 0, total = 0;
+
+    int32_t shared_slot(int32_t b, int32_t c) const {
+        for (size_t k = 0; k < shared.size(); ++k)
+            if (shared[k].first == b && shared[k].second == c) return static_cast<int32_t>(k);
+        return -1;
+    }
 };
 
 cfpq_status collect_rules(const cfpq_grammar* gr, int32_t n_conj, const cfpq_conj_rule* conj,
@@ -148,6 +157,20 @@ CjPlan cj_plan(const cfpq_graph* g, const cfpq_grammar* gr, const std::vector<Ru
     if (p.temps) off += mat;
     p.off_rowor = off;
     if (p.any_rows) off += align_up(rowor_scratch_bytes(p.L), 256);
+    {
+        std::vector<std::pair<int32_t, int32_t>> seen;
+        for (const Rule& r : rules)
+            for (const auto& pc : r.parts) {
+                if (p.rows_left[pc.first]) continue;
+                if (std::find(seen.begin(), seen.end(), pc) == seen.end()) {
+                    seen.push_back(pc);
+                } else if (std::find(p.shared.begin(), p.shared.end(), pc) == p.shared.end()) {
+                    p.shared.push_back(pc);
+                }
+            }
+    }
+    p.off_shared = off;
+    off += mat * p.shared.size();
     p.total = off;
     return p;
 }
@@ -244,6 +267,8 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
     uint64_t* TT = reinterpret_cast<uint64_t*>(ws + p.off_trans);
     uint64_t* Q = reinterpret_cast<uint64_t*>(ws + p.off_q);
     uint64_t* R = reinterpret_cast<uint64_t*>(ws + p.off_r);
+    uint64_t* SH = reinterpret_cast<uint64_t*>(ws + p.off_shared);
+    std::vector<char> shared_ready(p.shared.size(), 0);
     const cfpq_edge* d_edges = graph->edges;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -251,7 +276,10 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
     CFPQ_HIP(hipEventCreate(&ev1));
     struct EvGuard {
         hipEvent_t a, b;
-        ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); }
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
     } guard{ev0, ev1};
     CFPQ_HIP(hipMemcpyAsync(d_term_off, term_off.data(), term_off.size() * 4, hipMemcpyHostToDevice, s));
     CFPQ_HIP(hipMemcpyAsync(d_term_lhs, term_lhs.data(), term_lhs.size() * 4, hipMemcpyHostToDevice, s));
@@ -298,6 +326,26 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
     bool converged = rules.empty() || graph->n_nodes == 0;
     while (!converged && iters < cap) {
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
+        std::fill(shared_ready.begin(), shared_ready.end(), 0);
+        // a dense conjunct that occurs more than once: its product this loop
+        // (computed at its first use; a later rule may read a product older
+        // than bits set since, in place, which only delays them a loop: the
+        // loop that changes nothing reads every product exact)
+        auto shared_product = [&](int32_t b, int32_t c, const uint64_t** out) -> cfpq_status {
+            *out = nullptr;
+            const int32_t k = p.shared_slot(b, c);
+            if (k < 0) return CFPQ_OK;
+            uint64_t* m = SH + static_cast<size_t>(k) * mw;
+            if (!shared_ready[k]) {
+                CFPQ_HIP(launch_zero(m, mw, s));
+                const cfpq_status e = product(b, c, m, d_spare);
+                if (e != CFPQ_OK) return e;
+                ++products;
+                shared_ready[k] = 1;
+            }
+            *out = m;
+            return CFPQ_OK;
+        };
         for (const Rule& r : rules) {
             if (o.dirty_worklist && iters > 0) {
                 bool dirty = false;
@@ -305,35 +353,57 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
                 if (!dirty) continue;
             }
             if (r.parts.size() == 1) {
-                st = product(r.parts[0].first, r.parts[0].second, Y + r.lhs * mw, d_flags + r.lhs);
+                const uint64_t* sp = nullptr;
+                st = shared_product(r.parts[0].first, r.parts[0].second, &sp);
                 if (st != CFPQ_OK) return st;
-                ++products;
+                if (sp != nullptr) {
+                    or_and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
+                        Y + r.lhs * mw, sp, sp, static_cast<int64_t>(mw), d_flags + r.lhs);
+                    CFPQ_HIP(hipGetLastError());
+                } else {
+                    st = product(r.parts[0].first, r.parts[0].second, Y + r.lhs * mw, d_flags + r.lhs);
+                    if (st != CFPQ_OK) return st;
+                    ++products;
+                }
                 continue;
             }
-            // Q = first conjunct, R = each further one; the products OR into
-            // their output, so both start zeroed (one fill: R follows Q)
-            if (R == Q + mw) {
-                CFPQ_HIP(launch_zero(Q, 2 * mw, s));
-            } else {
-                CFPQ_HIP(launch_zero(Q, mw, s));
-                CFPQ_HIP(launch_zero(R, mw, s));
-            }
-            st = product(r.parts[0].first, r.parts[0].second, Q, d_spare);
+            // the first conjunct (shared, or into the zeroed scratch Q), then
+            // each further one (shared, or into the zeroed scratch R): Q &= it,
+            // the last folded into T_A |= Q & R
+            const uint64_t* acc = nullptr;
+            st = shared_product(r.parts[0].first, r.parts[0].second, &acc);
             if (st != CFPQ_OK) return st;
-            for (size_t m = 1; m < r.parts.size(); ++m) {
-                if (m > 1) CFPQ_HIP(launch_zero(R, mw, s));
-                st = product(r.parts[m].first, r.parts[m].second, R, d_spare);
+            if (acc == nullptr) {
+                CFPQ_HIP(launch_zero(Q, mw, s));
+                st = product(r.parts[0].first, r.parts[0].second, Q, d_spare);
                 if (st != CFPQ_OK) return st;
+                ++products;
+                acc = Q;
+            }
+            for (size_t m = 1; m < r.parts.size(); ++m) {
+                const uint64_t* pm = nullptr;
+                st = shared_product(r.parts[m].first, r.parts[m].second, &pm);
+                if (st != CFPQ_OK) return st;
+                if (pm == nullptr) {
+                    CFPQ_HIP(launch_zero(R, mw, s));
+                    st = product(r.parts[m].first, r.parts[m].second, R, d_spare);
+                    if (st != CFPQ_OK) return st;
+                    ++products;
+                    pm = R;
+                }
                 if (m + 1 < r.parts.size()) {
+                    if (acc != Q) {  // keep the shared product intact
+                        CFPQ_HIP(hipMemcpyAsync(Q, acc, mw * 8, hipMemcpyDeviceToDevice, s));
+                        acc = Q;
+                    }
                     and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
-                        Q, R, static_cast<int64_t>(mw));
+                        Q, pm, static_cast<int64_t>(mw));
                 } else {
                     or_and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
-                        Y + r.lhs * mw, Q, R, static_cast<int64_t>(mw), d_flags + r.lhs);
+                        Y + r.lhs * mw, acc, pm, static_cast<int64_t>(mw), d_flags + r.lhs);
                 }
                 CFPQ_HIP(hipGetLastError());
             }
-            products += static_cast<int64_t>(r.parts.size());
         }
         CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
         CFPQ_HIP(hipStreamSynchronize(s));
