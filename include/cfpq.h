@@ -309,7 +309,9 @@ typedef struct {
 } cfpq_conj_rule;
 
 /* Workspace for cfpq_conjunctive_closure (as cfpq_workspace_bytes, plus two
- * scratch matrices when some rule has k >= 2). */
+ * scratch matrices when some rule has k >= 2, plus one matrix per dense
+ * conjunct B C that occurs in more than one rule: its product is computed
+ * once per loop and read by every use). */
 CFPQ_API cfpq_status cfpq_conjunctive_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* grammar,
                                                       int32_t n_conj_rules, const cfpq_conj_rule* conj_rules,
                                                       const cfpq_options* opt, size_t* bytes);
