@@ -71,12 +71,12 @@ struct CjPlan {
     std::vector<int32_t> right_slot;
     std::vector<char> rows_left;  // per nonterminal: conjuncts with it as left operand run as ROWS
     int32_t n_right = 0;
-    bool any_rows = false;
+    bool any_rows = false, any_cols = false;  // ROWS conjuncts; COLS conjuncts (a fixed sparse right operand)
     // dense conjuncts B C that occur more than once in the grammar: each is
     // multiplied once per loop into its own matrix, read by every use
     std::vector<std::pair<int32_t, int32_t>> shared;
     size_t off_edges = 0, off_term_off = 0, off_term_lhs = 0, off_flags = 0, off_bad = 0, off_second = 0,
-           off_trans = 0, off_q = 0, off_r = 0, off_rowor = 0, off_shared = 0, total = 0;
+           off_trans = 0, off_q = 0, off_r = 0, off_rowor = 0, off_shared = 0, off_pt = 0, off_bt = 0, total = 0;
 
     int32_t shared_slot(int32_t b, int32_t c) const {
         for (size_t k = 0; k < shared.size(); ++k)
@@ -130,6 +130,10 @@ CjPlan cj_plan(const cfpq_graph* g, const cfpq_grammar* gr, const std::vector<Ru
         for (const auto& pc : r.parts) {
             if (p.rows_left[pc.first]) {
                 p.any_rows = true;
+            } else if (p.rows_left[pc.second]) {
+                // COLS: (B x C)^T = C^T x B^T by rows of the fixed C^T
+                p.any_rows = p.any_cols = true;
+                if (p.right_slot[pc.second] < 0) p.right_slot[pc.second] = p.n_right++;
             } else if (reads_ct(p.path) && p.right_slot[pc.second] < 0) {
                 p.right_slot[pc.second] = p.n_right++;
             }
@@ -157,6 +161,9 @@ CjPlan cj_plan(const cfpq_graph* g, const cfpq_grammar* gr, const std::vector<Ru
     if (p.temps) off += mat;
     p.off_rowor = off;
     if (p.any_rows) off += align_up(rowor_scratch_bytes(p.L), 256);
+    p.off_pt = off;  // COLS: the product's transpose, and B^T when B is kept no transpose of
+    if (p.any_cols) off += 2 * mat;
+    p.off_bt = p.off_pt + mat;
     {
         std::vector<std::pair<int32_t, int32_t>> seen;
         for (const Rule& r : rules)
@@ -308,9 +315,25 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
     int64_t rowor_calls = 0;  // numbered row-gather calls (launch_rowor_product)
     if (p.any_rows) CFPQ_HIP(launch_rowor_reset(rowor_ws, s));
     int64_t sparse = 0;
+    uint64_t* PT = reinterpret_cast<uint64_t*>(ws + p.off_pt);
+    uint64_t* BT = reinterpret_cast<uint64_t*>(ws + p.off_bt);
     auto product = [&](int32_t b, int32_t c, uint64_t* out, int32_t* flag) -> cfpq_status {
         if (p.rows_left[b]) {
             CFPQ_HIP(launch_rowor_product(X + b * mw, X + c * mw, out, L, flag, rowor_ws, s, nullptr, 1, rowor_calls++));
+            ++sparse;
+        } else if (p.rows_left[c]) {
+            // COLS: rows of C^T (kept: C is fixed) select rows of B^T (the
+            // kept transpose when B has one, of the loop's start; else fresh)
+            const uint64_t* bt = BT;
+            if (p.right_slot[b] >= 0) {
+                bt = TT + p.right_slot[b] * mw;
+            } else {
+                CFPQ_HIP(launch_transpose(X + b * mw, BT, L, s));
+            }
+            CFPQ_HIP(launch_zero(PT, mw, s));
+            CFPQ_HIP(launch_rowor_product(TT + p.right_slot[c] * mw, bt, PT, L, nullptr, rowor_ws, s, nullptr, 1,
+                                          rowor_calls++));
+            CFPQ_HIP(launch_transpose_or(PT, out, L, flag, s));
             ++sparse;
         } else if (reads_ct(p.path))
             CFPQ_HIP(launch_mfma_path(p.path, X + b * mw, TT + p.right_slot[c] * mw, out, L, flag, s));
