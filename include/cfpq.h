@@ -309,9 +309,10 @@ typedef struct {
 } cfpq_conj_rule;
 
 /* Workspace for cfpq_conjunctive_closure (as cfpq_workspace_bytes, plus two
- * scratch matrices when some rule has k >= 2, plus one matrix per dense
- * conjunct B C that occurs in more than one rule: its product is computed
- * once per loop and read by every use). */
+ * scratch matrices when some rule has k >= 2, two more when some conjunct
+ * runs as COLS, plus one matrix per dense conjunct B C that occurs in more
+ * than one rule: its product is computed once per loop and read by every
+ * use). */
 CFPQ_API cfpq_status cfpq_conjunctive_workspace_bytes(const cfpq_graph* graph, const cfpq_grammar* grammar,
                                                       int32_t n_conj_rules, const cfpq_conj_rule* conj_rules,
                                                       const cfpq_options* opt, size_t* bytes);
@@ -321,9 +322,10 @@ CFPQ_API cfpq_status cfpq_conjunctive_workspace_bytes(const cfpq_graph* graph, c
  * binary rules) plus n_conj_rules rules with any number of conjuncts.
  * opt: path AUTO, BITS, MFMA or FP4 (dense products), schedule, dirty_worklist,
  * tile and max_iters as for cfpq_closure; warm_start must be 0; hybrid AUTO
- * (default) runs a conjunct whose left operand heads no rule as a ROWS
- * product when the graph has at most npad^2 / 16 edges (counted in
- * stats.sparse_products, not in bitops), OFF keeps every product dense;
+ * (default), when the graph has at most npad^2 / 16 edges, runs a conjunct
+ * whose left operand heads no rule as a ROWS product, and else one whose
+ * right operand heads no rule as a COLS product (both counted in
+ * stats.sparse_products, not in bitops); OFF keeps every product dense;
  * capture and profile are ignored (host-driven loop).  d_result, stream,
  * workspace, stats and the return codes as for cfpq_closure.
  */
