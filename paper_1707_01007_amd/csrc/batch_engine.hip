@@ -73,6 +73,37 @@ __global__ __launch_bounds__(256) void engine_scatter_kernel(const SlotDesc* __r
 // matrices stay in global memory (M = T, stride mdw) and the right operand of
 // each product is staged in lds.  Returns the loop count; *products and
 // *capped as in SlotState.
+// acc |= the rows cblk[k], k the set bits of a (CW words a row), four rows
+// per step so that their loads are in flight together; a step with fewer
+// than four bits left repeats its first row (OR is idempotent).
+template <int CW>
+__device__ __forceinline__ void or_rows_of_bits(uint32_t (&acc)[CW], uint32_t a, const uint32_t* cblk) {
+    while (a != 0) {
+        int kk[4];
+        kk[0] = __ffs(a) - 1;
+        a &= a - 1;
+#pragma unroll
+        for (int u = 1; u < 4; ++u) {
+            kk[u] = a != 0 ? __ffs(a) - 1 : kk[0];
+            a &= a - 1;  // a == 0 stays 0
+        }
+        uint4 v[4][CW / 4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c4 = 0; c4 < CW / 4; ++c4) v[u][c4] = reinterpret_cast<const uint4*>(cblk + kk[u] * CW)[c4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c4 = 0; c4 < CW / 4; ++c4) {
+                acc[4 * c4] |= v[u][c4].x;
+                acc[4 * c4 + 1] |= v[u][c4].y;
+                acc[4 * c4 + 2] |= v[u][c4].z;
+                acc[4 * c4 + 3] |= v[u][c4].w;
+            }
+    }
+}
+
 template <int CW, bool kAllLds>
 __device__ int64_t resident_loop(const SlotDesc& d, const int32_t* rules, uint32_t* M,
                                  size_t mstride, const uint32_t* T, size_t mdw, uint32_t* lds, int rows, int kdw,
@@ -107,20 +138,7 @@ __device__ int64_t resident_loop(const SlotDesc& d, const int32_t* rules, uint32
                 const uint32_t* brow = Bm + static_cast<size_t>(row) * CW;
                 for (int kw = 0; kw < kdw; ++kw) {
                     uint32_t a = brow[kw];
-                    const uint32_t* cblk = cst + kw * 32 * CW;
-                    while (a != 0) {  // the rows of C at the set bits of this word
-                        const int kk = __ffs(a) - 1;
-                        a &= a - 1;
-                        const uint4* crow = reinterpret_cast<const uint4*>(cblk + kk * CW);
-#pragma unroll
-                        for (int c4 = 0; c4 < CW / 4; ++c4) {
-                            const uint4 v = crow[c4];
-                            acc[4 * c4] |= v.x;
-                            acc[4 * c4 + 1] |= v.y;
-                            acc[4 * c4 + 2] |= v.z;
-                            acc[4 * c4 + 3] |= v.w;
-                        }
-                    }
+                    or_rows_of_bits<CW>(acc, a, cst + kw * 32 * CW);  // the rows of C at the set bits
                 }
                 uint32_t* arow = Am + static_cast<size_t>(row) * CW;
 #pragma unroll
@@ -187,20 +205,7 @@ __device__ int64_t resident_jacobi(const SlotDesc& d, const int32_t* rules, uint
                 const uint32_t* brow = Bm + static_cast<size_t>(row) * CW;
                 for (int kw = 0; kw < kdw; ++kw) {
                     uint32_t a = brow[kw];
-                    const uint32_t* cblk = Cm + kw * 32 * CW;
-                    while (a != 0) {
-                        const int kk = __ffs(a) - 1;
-                        a &= a - 1;
-                        const uint4* crow = reinterpret_cast<const uint4*>(cblk + kk * CW);
-#pragma unroll
-                        for (int c4 = 0; c4 < CW / 4; ++c4) {
-                            const uint4 v = crow[c4];
-                            acc[4 * c4] |= v.x;
-                            acc[4 * c4 + 1] |= v.y;
-                            acc[4 * c4 + 2] |= v.z;
-                            acc[4 * c4 + 3] |= v.w;
-                        }
-                    }
+                    or_rows_of_bits<CW>(acc, a, Cm + kw * 32 * CW);
                 }
                 uint32_t* arow = Am + static_cast<size_t>(row) * CW;
 #pragma unroll
