@@ -64,6 +64,8 @@ CASES = {
     "first_found": lambda: _first_found_graph(),
     # more than npad^2 / 16 edges: every rule on the tile min-plus kernel
     "er90_dense_dyck": lambda: (*graphs.erdos_renyi(90, 4200, 8, labels=2), grammars.dyck()),
+    # 15 k-chunks of 32: S -> S S on tiles split along k in its later loops
+    "er450_dyck": lambda: (*graphs.erdos_renyi(450, 1350, 14, labels=2), grammars.dyck()),
 }
 
 
@@ -74,6 +76,8 @@ def test_lengths_match_oracle(cfpq, name):
     res, got = _lengths(cfpq, n, e, g)
     assert res.stats["iterations"] == loops
     assert np.array_equal(got, want)
+    if name in ("er450_dyck", "er90_dense_dyck"):
+        assert res.stats["minplus_terms"] > 0  # the tile kernel ran
     bits = cfpq.result_bits(res)
     from oracle import worklist
     assert np.array_equal(bits, worklist.closure(n, e, g))
