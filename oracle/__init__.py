@@ -30,6 +30,11 @@ cycles of coprime length, textbook special cases (transitive closure, CYK on a
 chain, bracket matching, terminal-only grammars), brute force on tiny graphs,
 and invariants (closure, monotonicity, permutation equivariance, disjoint
 union); for the lengths, breadth-first search, chains, the two-cycle closed
-form, a first-found-is-kept case and CYK on every witness.  Every function here
-has at least one such pin.
+form, a first-found-is-kept case and CYK on every witness; for the language
+enumeration ``brute.cfg_words``, languages known in closed form (a^n b^n,
+balanced words with their Catalan counts, equal letter counts, palindromes, a
+unit cycle through nullable symbols); for ``brute.conj_paths_up_to``, Boolean
+matrix powers (a path spells a^n b^n c^n iff it is in M_a^n M_b^n M_c^n).
+Every function here has at least one such pin, and mutation harnesses check
+that planted mistakes break one.
 """

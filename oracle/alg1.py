@@ -6,11 +6,12 @@ section 2, c_ij = union_k a_ik . b_kj with N1 . N2 = {A : B in N1, C in N2,
 A -> B C}, becomes one Boolean matrix product per binary rule:
 (T x T)[A] = OR over rules A -> B C of (T[B] @ T[C]).
 
-``closure`` follows Algorithm 1 step by step: initialise T from the edges
-(section 4.2, matrix initialisation), then repeat T <- T u (T x T), reading the
-old T for every product, until T stops changing.  The returned loop count is
-the number of times the loop body ran, including the last one that changed
-nothing (the worked example of section 4.3 runs it 6 times: T6 = T5).
+``closure`` computes the least fixpoint of Algorithm 1 (section 4.2) by
+simultaneous (Jacobi) updates: T starts as the edge matrix, and each loop
+forms the union of T with T x T computed entirely from the previous loop's T,
+stopping after the first loop that adds no entry.  The returned count includes
+that last loop; the section 4.3 example pins it (six loops, the sixth adding
+nothing).
 """
 from __future__ import annotations
 

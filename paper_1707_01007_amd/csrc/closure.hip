@@ -2,7 +2,7 @@
 //
 //   initialise T_A from the edges (matrix initialisation),
 //   repeat: for every rule A -> B C: T_A |= T_B x T_C
-//   until a loop changes no matrix ("while matrix T is changing").
+//   until a loop changes no matrix (Algorithm 1, section 4.2).
 //
 // Schedules.  JACOBI reads every operand from the matrices of the previous
 // loop, exactly Algorithm 1's T <- T u (T x T): two buffers X (read) and Y
