@@ -19,9 +19,14 @@ step of Algorithm 1): L[A][i, j] = 0 for an absent pair.  ``witness``
 recovers one such path: a stored length l > 1 was set as l_B(i, k) + l_C(k, j)
 with both stored earlier, each shorter than l, so splitting any cell into two
 stored cells whose lengths add up to l recurses down to single edges.
+``lengths_native`` runs the same definition in plain C (cfpq_single_path.c)
+for graphs of thousands of nodes.
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
 from typing import List, Tuple
 
 import numpy as np
@@ -105,3 +110,51 @@ def witness(n: int, edges: np.ndarray, grammar, L: np.ndarray, a: int, i: int, j
         else:
             raise ValueError(f"no split of length {l} for ({A}, {s}, {t})")
     return out
+
+
+# ---- the same definition in plain C (cfpq_single_path.c), for larger graphs ----
+
+_C_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cfpq_single_path.c")
+_C_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcfpq_single_path_oracle.so")
+_c_lib = None
+
+
+def build_native(force: bool = False, src: str = _C_SRC, lib: str = _C_LIB) -> str:
+    """Compile the C transcription with gcc -O3 (integer code only)."""
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-o", tmp, src])
+        os.replace(tmp, lib)
+    return lib
+
+
+def load_native(path: str):
+    lib = ctypes.CDLL(path)
+    i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.cfpq_single_path_oracle.argtypes = [i32, i64, p, i32, i32, i32, p, i32, p, i64, p, p]
+    lib.cfpq_single_path_oracle.restype = ctypes.c_int
+    return lib
+
+
+def lengths_native(n: int, edges: np.ndarray, grammar, max_loops: int | None = None, lib=None):
+    """``lengths`` computed by the C transcription: returns (L as uint32
+    [|N|, n, n], loop count, status) with status 0 (fixpoint reached), 1 (some
+    length reached 2^31 - 1) or 3 (stopped by max_loops)."""
+    global _c_lib
+    if lib is None:
+        if _c_lib is None:
+            _c_lib = load_native(build_native())
+        lib = _c_lib
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
+    term = np.ascontiguousarray(np.asarray(grammar.term, dtype=np.int32).reshape(-1, 2))
+    binr = np.ascontiguousarray(np.asarray(grammar.bin, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros((grammar.n_nonterminals, n, n), dtype=np.uint32)
+    loops = ctypes.c_int64(0)
+    rc = lib.cfpq_single_path_oracle(n, len(e), e.ctypes.data, grammar.n_nonterminals, grammar.n_terminals,
+                                     len(term), term.ctypes.data, len(binr), binr.ctypes.data,
+                                     int(max_loops or 0), out.ctypes.data, ctypes.byref(loops))
+    if rc == -1:
+        raise ValueError("single-path oracle: invalid graph or grammar")
+    if rc == -2:
+        raise MemoryError("single-path oracle: out of memory")
+    return out, int(loops.value), rc

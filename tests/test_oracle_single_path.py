@@ -210,3 +210,85 @@ def test_single_path_mutant_is_caught(name):
     except (ValueError, IndexError):
         held = False
     assert not held, f"mutant {name} passed every pin"
+
+
+# ---- the C transcription (cfpq_single_path.c), used for the larger digests ----
+
+def _native_module(lib=None):
+    """``lengths`` of the C transcription with the numpy ``witness``, in the
+    shape the pin harness takes."""
+    def lengths(n, e, g, max_loops=None):
+        L, loops, rc = single_path.lengths_native(n, e, g, max_loops, lib=lib)
+        assert rc in (0, 3), rc
+        return L.astype(np.int64), loops
+    return types.SimpleNamespace(lengths=lengths, witness=single_path.witness)
+
+
+def test_native_oracle_passes_harness():
+    assert _pins_hold(_native_module())
+
+
+@pytest.mark.parametrize("grammar", ["dyck", "anbn", "same_generation", "transitive_closure"])
+def test_native_equals_numpy(grammar):
+    g = grammars.BY_NAME[grammar]()
+    for seed, (n, m) in enumerate([(1, 1), (13, 30), (64, 150), (97, 260)]):
+        if grammar == "same_generation":
+            n, e = graphs.hierarchy(max(n, 2), seed, roots=1, reverse=bool(seed % 2))
+        else:
+            n, e = graphs.erdos_renyi(n, min(m, n * (n - 1)) if n > 1 else 0, 40 + seed, labels=len(g.terminals))
+        L, loops = single_path.lengths(n, e, g)
+        Lc, loops_c, rc = single_path.lengths_native(n, e, g)
+        assert rc == 0 and loops_c == loops
+        assert np.array_equal(Lc.astype(np.int64), L), (grammar, n)
+    # a cap on the loop count stops both at the same state
+    n, e = graphs.erdos_renyi(50, 140, 3, labels=len(g.terminals))
+    L, loops = single_path.lengths(n, e, g, max_loops=2)
+    Lc, loops_c, rc = single_path.lengths_native(n, e, g, max_loops=2)
+    assert loops_c == loops == 2 and np.array_equal(Lc.astype(np.int64), L)
+
+
+def doubling_grammar(k_max: int):
+    """A0 -> a, A_k -> A_(k-1) A_(k-1): on one node with an a-loop, A_k has the
+    single length 2^k (its only derivation tree is complete of height k)."""
+    names = [f"A{k}" for k in range(k_max + 1)]
+    return grammars._mk(f"doubling{k_max}", names, ["a"], [("A0", "a")],
+                        [(names[k], names[k - 1], names[k - 1]) for k in range(1, k_max + 1)])
+
+
+def test_native_doubling_lengths_and_overflow():
+    e = np.array([[0, 0, 0]], dtype=np.int32)
+    L, loops, rc = single_path.lengths_native(1, e, doubling_grammar(30))
+    assert rc == 0 and loops == 31
+    assert [int(L[k, 0, 0]) for k in range(31)] == [2 ** k for k in range(31)]
+    # 2^31 does not fit the GPU path's lengths: the oracle says so
+    _, _, rc = single_path.lengths_native(1, e, doubling_grammar(31))
+    assert rc == 1
+
+
+SP_C_MUTANTS = {
+    "length_plus_one": ("ABSENT : b + crk[j];", "ABSENT : b + crk[j] + 1;"),
+    "largest_split_wins": ("crow[j] = s < crow[j] ? s : crow[j];",
+                           "crow[j] = (crow[j] == ABSENT || (s != ABSENT && s > crow[j])) ? s : crow[j];"),
+    "later_shorter_replaces": ("if (L[x] == ABSENT && cand[x] != ABSENT) {", "if (cand[x] < L[x]) {"),
+    "transposed_right_operand": ("const uint32_t *crk = lc + (size_t)k * n;\n                    for (int32_t j = 0; j < n; ++j) {\n                        /* both lengths are below 2^31, so the sum fits */\n                        const uint32_t s = crk[j] == ABSENT ? ABSENT : b + crk[j];",
+                                 "const uint32_t *crk = lc + (size_t)k;\n                    for (int32_t j = 0; j < n; ++j) {\n                        /* both lengths are below 2^31, so the sum fits */\n                        const uint32_t s = crk[(size_t)j * n] == ABSENT ? ABSENT : b + crk[(size_t)j * n];"),
+    "first_rule_only": ("for (int32_t r = 0; r < n_bin; ++r) {\n            const uint32_t *lb", "for (int32_t r = 0; r < 1 && r < n_bin; ++r) {\n            const uint32_t *lb"),
+    "last_step_not_counted": ("        if (added == 0) {\n            capped = 0;", "        if (added == 0) {\n            --loops;\n            capped = 0;"),
+    "reversed_edges": ("L[(size_t)term[2 * r] * cells + (size_t)t[0] * n + t[2]] = 1;",
+                       "L[(size_t)term[2 * r] * cells + (size_t)t[2] * n + t[0]] = 1;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SP_C_MUTANTS))
+def test_native_mutant_is_caught(name, tmp_path):
+    old, new = SP_C_MUTANTS[name]
+    src = open(single_path._C_SRC).read()
+    assert src.count(old) == 1, name
+    msrc = tmp_path / "mutant.c"
+    msrc.write_text(src.replace(old, new))
+    lib = single_path.load_native(single_path.build_native(True, str(msrc), str(tmp_path / "libmutant.so")))
+    try:
+        held = _pins_hold(_native_module(lib))
+    except (ValueError, IndexError, AssertionError):
+        held = False
+    assert not held, f"mutant {name} passed every pin"
