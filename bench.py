@@ -33,16 +33,16 @@ PEAK_FP4_TOPS = 10100.0  # dense fp4 (e2m1) MFMA, 10.1 PFLOP/s
 PEAK_VALU_BITOPS_T = 256 * 64 * 2.4e9 * 64 / 1e12
 
 
-def cpu_baseline(inst, seconds_target=12.0):
+def _blas_product_rate(inst, seconds_target=4.0):
     """The oracle's own Boolean product (oracle/alg1.py, float64 BLAS) timed on
     a bounded row block of the first product of the same workload."""
     import numpy as np
     from oracle import alg1
     try:
         from threadpoolctl import threadpool_info
-        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
     except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
+        threads = os.cpu_count() or 1
     t0 = alg1.initial_matrix(inst.n, inst.edges, inst.grammar)
     b, c = t0[inst.grammar.nt("A")], t0[inst.grammar.nt("B")]
     n = inst.n
@@ -56,10 +56,42 @@ def cpu_baseline(inst, seconds_target=12.0):
         alg1.bool_product(b[:rows], c)
         dt += time.perf_counter() - t
         reps += 1
-    return {"value": round(2.0 * rows * n * n * reps / dt / 1e9, 3), "unit": "Gbitop/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"oracle Boolean product (float64 BLAS) of rows 0..{rows - 1} of T_A by T_B at n={n}, "
+    return {"value": round(2.0 * rows * n * n * reps / dt / 1e9, 3), "unit": "Gbitop/s", "threads": threads,
+            "sample": f"Boolean product (float64 BLAS) of rows 0..{rows - 1} of T_A by T_B at n={n}, "
                       f"{reps} time(s), {dt:.1f} s"}
+
+
+def cpu_baseline(cfpq, torch, inst, sample_n=8192):
+    """The C worklist oracle's time to the fixpoint, single-threaded, on the
+    same recipe (ER Dyck, seed 3) at n = sample_n, a bounded sample of the
+    n = 16384 workload (about 15-90 s of CPU work, by the host).  ``value`` puts it in the
+    metric's unit: the bit-operations the GPU's dense closure executes on that
+    instance (2 npad^3 per product, as for the headline) divided by the
+    oracle's time to the same relations.  The full-size oracle time comes from
+    the digest run that stored the n = 16384 result; the oracle's float64
+    BLAS product rate is a second, separate figure."""
+    import json as _json
+    from oracle import worklist
+    from workloads import configs
+    sample = configs.config3(sample_n, seed=3)
+    worklist.closure(64, sample.edges[:0], sample.grammar)  # loads the oracle library
+    t = time.perf_counter()
+    want = worklist.closure(sample.n, sample.edges, sample.grammar)
+    dt = time.perf_counter() - t
+    res = cfpq.closure(sample.n, torch.from_numpy(sample.edges).cuda(), sample.grammar, hybrid=0)
+    same = bool((cfpq.result_bits(res) == want).all())
+    full = _json.load(open(os.path.join(ROOT, "tests", "golden", "digests.json"))).get("er16384_dyck", {})
+    return {"value": round(res.stats["bitops"] / dt / 1e9, 3), "unit": "Gbitop/s", "cores": 1,
+            "kind": "oracle_closure",
+            "sample": f"C worklist oracle (one thread), closure of the ER Dyck recipe at n={sample.n}, "
+                      f"{len(sample.edges)} edges: {dt:.2f} s; value = the dense GPU closure's "
+                      f"{res.stats['bitops']:.3e} bit-ops on that instance / that time",
+            "time_to_solution_s": round(dt, 3), "sample_n": sample.n, "identical_to_gpu": same,
+            "host_nproc": len(os.sched_getaffinity(0)),
+            "full_size": {"n": inst.n, "time_to_solution_s": full.get("oracle_seconds"),
+                          "where": full.get("oracle_host", "digest run on the build host"),
+                          "date": full.get("oracle_date")},
+            "blas_product": _blas_product_rate(inst)}
 
 
 def profiled_traffic(profile_md, sources):
@@ -86,21 +118,34 @@ def bench_batch(cfpq, torch, steps=3):
     """Batched closure of the 512-instance workload (sizes log-uniform in
     [64, 2048], hierarchy or G(n, 3n), same-generation or Dyck) against the
     same queries run one at a time with the plain closure (no batching, no
-    captured loops).  Edges are in device memory for both."""
+    captured loops).  Edges are in device memory for both.  The engine's route
+    per padded side (resident workgroup, or the tile work list with 256 or 128
+    tiles) comes from the batch autotuner run on this workload first; the
+    batch is also timed with the untuned default routes."""
     from workloads import configs
     insts = configs.config4()
     items = [(i.n, torch.from_numpy(i.edges).cuda(), i.grammar) for i in insts]
     torch.cuda.synchronize()
+
+    def timed(outs):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = cfpq.batch_closure(items, outs=outs)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, res
+
+    cfpq.tune_clear()
     res = cfpq.batch_closure(items)  # warmup + buffers
     outs = [r.bits.view(-1) for r in res]
-    torch.cuda.synchronize()
+    t_default, _ = timed(outs)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        res = cfpq.batch_closure(items, outs=outs)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / steps
+    table = cfpq.batch_autotune(items, max_per_bucket=0, reps=3)
+    t_tune = time.perf_counter() - t0
+    cfpq.batch_closure(items, outs=outs)
+    t_batch, res = timed(outs)
     bitops = sum(r.stats["bitops"] for r in res)
-    print(f"[bench] batch of {len(items)}: {t_batch * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    print(f"[bench] batch of {len(items)}: {t_batch * 1e3:.2f} ms tuned, {t_default * 1e3:.2f} ms default routes "
+          f"(tuning {t_tune:.2f} s)", file=sys.stderr, flush=True)
     for it, o in zip(items[:8], outs[:8]):  # warm the plain path
         cfpq.closure(*it, capture=0, out=o)
     torch.cuda.synchronize()
@@ -110,11 +155,37 @@ def bench_batch(cfpq, torch, steps=3):
     torch.cuda.synchronize()
     t_serial = time.perf_counter() - t0
     print(f"[bench] serial plain: {t_serial * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    routes = {str(e["npad"]): (e["route"] if e["route"] == "resident" else f"tiles{e['tile']}") for e in table}
     return {"workload": "batch512_seed4", "instances": len(items),
             "queries_per_s": round(len(items) / t_batch, 1), "ms_per_batch": round(t_batch * 1e3, 3),
             "Gbitop_per_s": round(bitops / t_batch / 1e9, 1),
             "serial_plain_queries_per_s": round(len(items) / t_serial, 1),
-            "speedup_vs_serial_plain": round(t_serial / t_batch, 2)}
+            "speedup_vs_serial_plain": round(t_serial / t_batch, 2),
+            "route_table": {"source": "cfpq_batch_autotune on this workload", "tuning_s": round(t_tune, 2),
+                            "routes_by_npad": routes,
+                            "candidates_ms_by_npad": {str(e["npad"]): e["candidates_ms"] for e in table}},
+            "default_routes_ms_per_batch": round(t_default * 1e3, 3)}
+
+
+def bench_hybrid_only(cfpq, torch, steps=5):
+    """Only the hybrid closure of the n = 16384 workload (library defaults),
+    `steps` times after one warm-up: a kernel trace of this section holds the
+    hybrid closure's kernels alone."""
+    from workloads import configs
+    inst = configs.config3(16384)
+    edges = torch.from_numpy(inst.edges).cuda()
+    res = cfpq.closure(inst.n, edges, inst.grammar)
+    out = res.bits.view(-1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = cfpq.closure(inst.n, edges, inst.grammar, out=out)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    st = res.stats
+    return {"workload": inst.tag, "ms_per_closure": round(t * 1e3, 3), "loops": st["iterations"],
+            "products": st["products"], "sparse_products": st["sparse_products"],
+            "delta_products": st["delta_products"]}
 
 
 def bench_hybrid(cfpq, torch, inst, edges, dense_out, args, dense_s):
@@ -133,11 +204,21 @@ def bench_hybrid(cfpq, torch, inst, edges, dense_out, args, dense_s):
     t = (time.perf_counter() - t0) / args.steps
     same = bool(torch.equal(out, dense_out))
     st = res.stats
+    # one more closure with per-product events: the sparse products' time and
+    # algorithmic bytes (rows gathered at the set bits of the sparse operand,
+    # its bit scan, and the read and write of the result) give their roofline
+    prof = cfpq.closure(inst.n, edges, inst.grammar, out=out, profile=True, **kw).stats
+    sp_gbs = prof["sparse_bytes"] / (prof["sparse_ms"] / 1e3) / 1e9 if prof["sparse_ms"] else 0.0
     print(f"[bench] hybrid: {t * 1e3:.1f} ms per closure ({st['products'] - st['sparse_products']} dense + "
           f"{st['sparse_products']} sparse products), identical bits: {same}", file=sys.stderr, flush=True)
     return {"ms_per_closure": round(t * 1e3, 3), "speedup_vs_dense": round(dense_s / t, 2),
             "closures_per_s": round(1.0 / t, 2), "dense_products": st["products"] - st["sparse_products"],
-            "sparse_products": st["sparse_products"], "loops": st["iterations"], "identical_to_dense": same}
+            "sparse_products": st["sparse_products"], "loops": st["iterations"], "identical_to_dense": same,
+            "roofline": {"bound": "hbm", "kernels": "sparse products (rowor_kernel, rowor_heavy_kernel, "
+                                                    "transpose_or_kernel and their transposes)",
+                         "achieved": round(sp_gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(sp_gbs / 8000.0, 4), "bytes_per_closure": prof["sparse_bytes"],
+                         "ms_per_closure": round(prof["sparse_ms"], 3)}}
 
 
 # VALU: 256 CUs x 64 lanes per clock x 2.4 GHz 32-bit integer instructions; a
@@ -255,7 +336,9 @@ def bench_serve(cfpq, torch, warm=100, measured=500, loads=(1.5, 0.5), hybrid_la
     mu; the next `measured` arrive as a Poisson process at lambda = load * mu
     and are served (a) by the continuous-batching server and (b) one at a time,
     in arrival order, by the plain closure (no batching, no captured loops; the
-    library's default product choice, as for any single query)."""
+    library's default product choice, as for any single query).  After both
+    timed runs every served result is compared with the serial closure's bits
+    for the same request (``results_differing_from_serial``)."""
     from workloads import configs
     insts, gaps = configs.config5(count=warm + measured)
     warm_set, meas = insts[:warm], insts[warm:]
@@ -299,19 +382,23 @@ def bench_serve(cfpq, torch, warm=100, measured=500, loads=(1.5, 0.5), hybrid_la
         qps_srv = measured / (end - start)
         # (b) serial plain closure on the same trace
         start = time.perf_counter()
-        lat_ser = []
+        lat_ser, ser = [], []
         for a, i in zip(arrivals, meas):
             spin_until(start + a)
-            cfpq.closure(i.n, i.edges, i.grammar, capture=0)
+            ser.append(cfpq.closure(i.n, i.edges, i.grammar, capture=0))
             lat_ser.append((time.perf_counter() - (start + a)) * 1e3)
         end = time.perf_counter()
         qps_ser = measured / (end - start)
+        # after the timed runs: every served result against the serial closure's bits
+        differ = sum(1 for x, r in zip(infos, ser) if not torch.equal(x["result"].bits, r.bits))
+        del infos, ser
         print(f"[bench] server {qps_srv:.1f} q/s p50 {_pct(lat_srv, 50)} p99 {_pct(lat_srv, 99)} ms; serial "
               f"{qps_ser:.1f} q/s p50 {_pct(lat_ser, 50)} p99 {_pct(lat_ser, 99)} ms", file=sys.stderr, flush=True)
         return {"lambda_per_s": round(lam, 1), "load_vs_serial": load,
                 "queries_per_s": round(qps_srv, 1), "p50_ms": _pct(lat_srv, 50), "p99_ms": _pct(lat_srv, 99),
                 "serial_plain_queries_per_s": round(qps_ser, 1), "serial_plain_p50_ms": _pct(lat_ser, 50),
-                "serial_plain_p99_ms": _pct(lat_ser, 99), "failed": bad}
+                "serial_plain_p99_ms": _pct(lat_ser, 99), "failed": bad,
+                "results_differing_from_serial": differ}
 
     out = {"workload": f"serve_seed5_{measured}req", "arrival": "poisson",
            "serial_service_rate_per_s": round(mu, 1)}
@@ -333,7 +420,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-closure section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--no-next", action="store_true", help="skip the single-path and conjunctive sections")
-    ap.add_argument("--section", choices=["single_path", "conjunctive", "small_configs", "batch", "serving"],
+    ap.add_argument("--section", choices=["single_path", "conjunctive", "small_configs", "batch", "serving",
+                                          "hybrid"],
                     help="run only this section and print its JSON object (for profiling a kernel that the "
                          "section runs; no headline line)")
     ap.add_argument("--headline-only", action="store_true",
@@ -367,7 +455,8 @@ def main():
     torch.cuda.set_device(0)
     if args.section:
         fn = {"single_path": bench_single_path, "conjunctive": bench_conjunctive,
-              "small_configs": bench_small_configs, "batch": bench_batch, "serving": bench_serve}[args.section]
+              "small_configs": bench_small_configs, "batch": bench_batch, "serving": bench_serve,
+              "hybrid": bench_hybrid_only}[args.section]
         print(json.dumps({"section": args.section, args.section: fn(cfpq, torch)}), flush=True)
         return
     inst = configs.config3(args.n)
@@ -448,7 +537,7 @@ def main():
     if not args.no_serve:
         line["serving"] = bench_serve(cfpq, torch)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(inst)
+        line["cpu_baseline"] = cpu_baseline(cfpq, torch, inst)
     print(json.dumps(line), flush=True)
 
 

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define CFPQ_ABI_VERSION 3
+#define CFPQ_ABI_VERSION 4
 
 #if defined(__GNUC__)
 #define CFPQ_API __attribute__((visibility("default")))
@@ -152,6 +152,11 @@ typedef struct {
                                 may add D_B x C and B x D_C instead of B x C (hybrid choice) */
     double minplus_terms;    /* cfpq_single_path only: (i, j, k) terms l_B(i,k) + l_C(k,j) the min-plus
                                 tile kernel evaluated (product_ms is then its summed time); 0 elsewhere */
+    double sparse_bytes;     /* cfpq_closure: algorithmic bytes of the rules whose every part ran as ROWS or
+                                COLS -- per part nz * row bytes (the rows gathered at the nz set bits of its
+                                sparse operand) + 3 matrices (the bit scan of that operand, read and write
+                                of the result) */
+    double sparse_ms;        /* summed duration of those rules (options.profile), else 0 */
 } cfpq_stats;
 
 /* ABI version of the loaded library (CFPQ_ABI_VERSION). */
@@ -266,8 +271,9 @@ CFPQ_API cfpq_status cfpq_single_path_workspace_bytes(const cfpq_graph* graph, c
  * (R in the bit layout); d_lengths: device buffer of cfpq_lengths_bytes,
  * overwritten.  max_iters: loop cap, 0 = Theorem 3's bound.  Synchronises
  * `stream`.  Returns CFPQ_OK, CFPQ_ENOTCONV (cap reached: every stored length
- * is still a valid path length), CFPQ_ERANGE, CFPQ_EINVAL, CFPQ_ENOMEM or
- * CFPQ_EDEVICE.  stats: iterations, Boolean products, device time, the
+ * is still a valid path length), CFPQ_ERANGE (a length reached 2^31 - 1: the
+ * contents of d_result and d_lengths are then unspecified), CFPQ_EINVAL,
+ * CFPQ_ENOMEM or CFPQ_EDEVICE.  stats: iterations, Boolean products, device time, the
  * min-plus tile kernel's terms (minplus_terms) and summed time (product_ms);
  * rules whose min-plus runs as a row or column gather (a fixed sparse edge
  * matrix operand, or a left operand sparse enough in that loop) are in
@@ -388,15 +394,77 @@ typedef struct {
     uint64_t* d_result;
 } cfpq_instance;
 
-/* Workspace bytes for cfpq_batch_closure with these instances and options. */
+/* Workspace bytes for cfpq_batch_closure with these instances and options
+ * (enough for any route the batch tuning table may choose). */
 CFPQ_API cfpq_status cfpq_batch_workspace_bytes(int32_t n_instances, const cfpq_instance* instances,
                                                 const cfpq_options* opt, size_t* bytes);
 
+/* Routes of the batched engine (cfpq_batch_closure and the server): how the
+ * instances of one size bucket (one padded side) run. */
+enum {
+    CFPQ_ROUTE_RESIDENT = 1, /* one workgroup runs the instance's whole fixpoint (VALU products,
+                                right operand in LDS); padded side <= 512 only */
+    CFPQ_ROUTE_TILES = 2     /* the engine's per-loop work list shared by all such instances: fp4-MFMA
+                                tiles of `tile` x `tile` (256: a workgroup per tile; 128: a wavefront per
+                                tile), row gathers for rules with an edge-matrix left operand */
+};
+
+/* The batch tuning table: one entry per padded side (a multiple of 256).
+ * Untuned sides use RESIDENT up to 512 and TILES 256 above. */
+typedef struct {
+    int32_t npad;              /* padded side of the bucket */
+    int32_t route;             /* CFPQ_ROUTE_* */
+    int32_t tile;              /* TILES: 256 or 128 (0 for RESIDENT) */
+    float ms;                  /* cfpq_batch_autotune: the sample's time with the chosen route */
+    int32_t instances;         /* cfpq_batch_autotune: instances of this side in the sample */
+    int32_t n_candidates;      /* entries used below */
+    int32_t candidate_route[4];
+    int32_t candidate_tile[4];
+    float candidates_ms[4];
+} cfpq_batch_tune_entry;
+
+/* Device workspace for cfpq_batch_autotune with these instances. */
+CFPQ_API cfpq_status cfpq_batch_autotune_workspace_bytes(int32_t n_instances, const cfpq_instance* instances,
+                                                         const cfpq_options* opt, size_t* bytes);
+
+/*
+ * Batch autotuner.  The sample is the first max_per_bucket instances of every
+ * padded side present (0 = all instances).  Side by side, smallest first,
+ * each candidate route of that side (RESIDENT where the side allows it, TILES
+ * 256, TILES 128) is timed on the whole sample while the other sides keep
+ * their current route (the table's, or the default) -- so the overlap of
+ * resident workgroups with the tile work list is part of the measurement --
+ * as the median host wall time of `reps` runs (0 = 3) after one warm-up run.
+ * A candidate replaces the current route only if it is more than 2% faster.
+ * Every choice is recorded in the batch tuning table, which
+ * cfpq_batch_closure and servers created afterwards read.  The sample's
+ * results are written to its instances' d_result (every route gives the same
+ * bits).  out: NULL or room for max_out entries, filled in ascending padded
+ * side (ms: the sample's time with the chosen route; candidates_ms: with each
+ * candidate); *n_out (nullable) receives the number of sides tuned.  opt as
+ * for cfpq_batch_closure.  Synchronises `stream`.  Returns CFPQ_OK,
+ * CFPQ_EINVAL, CFPQ_ENOMEM (workspace) or CFPQ_EDEVICE.
+ */
+CFPQ_API cfpq_status cfpq_batch_autotune(int32_t n_instances, const cfpq_instance* instances,
+                                         const cfpq_options* opt, void* stream, void* d_workspace,
+                                         size_t workspace_bytes, int32_t max_per_bucket, int32_t reps,
+                                         cfpq_batch_tune_entry* out, int32_t max_out, int32_t* n_out);
+
+/* The table's entry for padded side npad; CFPQ_ENOTREADY if none. */
+CFPQ_API cfpq_status cfpq_batch_tune_get(int32_t npad, cfpq_batch_tune_entry* out);
+
+/* Set (route != 0) or remove (route == 0) the entry of entry->npad by hand.
+ * CFPQ_EINVAL for a padded side that is not a positive multiple of 256, a
+ * RESIDENT route above 512 or a TILES tile other than 128 / 256.
+ * cfpq_tune_save / cfpq_tune_load / cfpq_tune_clear cover this table too. */
+CFPQ_API cfpq_status cfpq_batch_tune_set(const cfpq_batch_tune_entry* entry);
+
 /*
  * Relational closure (Algorithm 1, in-place schedule) of every instance,
- * computed together.  Instances with a padded side of at most 512 run their
- * whole fixpoint in one workgroup each (VALU product); larger ones share a
- * per-loop work list of 256 x 256 fp4-MFMA tiles, with `opt->capture` loops
+ * computed together.  Each instance takes the route of its padded side from
+ * the batch tuning table (untuned: padded side <= 512 runs its whole fixpoint
+ * in one workgroup, VALU product; larger ones share a per-loop work list of
+ * 256 x 256 fp4-MFMA tiles), with `opt->capture` loops
  * (0 = 8) per captured HIP graph.  With opt->hybrid AUTO (the default), a
  * rule of a larger instance whose left operand heads no binary rule (its
  * matrix is fixed by the edges) runs as row gathers instead of tiles when the
@@ -480,8 +548,23 @@ CFPQ_API cfpq_status cfpq_server_poll(cfpq_server* srv, int64_t ticket, cfpq_req
 CFPQ_API cfpq_status cfpq_server_wait(cfpq_server* srv, int64_t ticket, cfpq_request_info* info);
 
 /* Stop admitting, finish the queries already admitted, drop queued ones,
- * free everything.  Returns CFPQ_EDEVICE if the worker hit a HIP error. */
+ * free everything.  Returns CFPQ_EDEVICE if the worker hit a HIP error.
+ *
+ * After a HIP error in the worker (or a lane's failure to select the device)
+ * the server stops: queued queries complete at once with CFPQ_EDEVICE, and
+ * every admitted query completes only after the thread that runs it has
+ * finished with its buffers (its stream synchronised or abandoned) -- a
+ * lane's query with the status of its closure, the worker's with
+ * CFPQ_EDEVICE -- so d_result may be freed as soon as wait/poll reports the
+ * query done.  Later submits return CFPQ_EDEVICE. */
 CFPQ_API cfpq_status cfpq_server_destroy(cfpq_server* srv);
+
+/* For tests of the failure handling above, which cannot make a device fail on
+ * purpose: the worker stops at its next turn exactly as after a HIP error
+ * (no device work is involved).  Returns once the worker has stopped
+ * (queued queries are then done with CFPQ_EDEVICE; lanes may still be
+ * finishing theirs); CFPQ_OK, or CFPQ_EINVAL for a NULL server. */
+CFPQ_API cfpq_status cfpq_server_inject_fault(cfpq_server* srv);
 
 #ifdef __cplusplus
 }

@@ -254,18 +254,11 @@ def conjunctive_closure(n: int, edges, grammar, *, path="auto", schedule="inplac
     return Result(int(n), nnt, out.view(nnt, npad, W), st.as_dict(), status)
 
 
-def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=None, stream=None,
-                  outs=None, workspace=None, allow_partial=False, hybrid=None):
-    """Closure of many independent instances in one call (``cfpq_batch_closure``).
-
-    ``instances`` is a sequence of (n, edges, grammar); edges on the host or as
-    int32 CUDA tensors.  Returns one ``Result`` per instance (each with its own
-    device result buffer, or the buffers in ``outs``).  ``hybrid`` (0/1,
-    default the library's: 1) lets rules of larger instances with an
-    edge-matrix left operand run as row gathers."""
+def _instance_array(instances, outs, device):
+    """cfpq_instance records for (n, edges, grammar) triples, the objects they
+    point into, and one result buffer per instance (from ``outs`` or new)."""
     torch = _torch()
     L = lib()
-    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     k = len(instances)
     arr = (_abi.Instance * max(1, k))()
     keep, results_out = [], []
@@ -283,6 +276,67 @@ def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=No
         out = outs[i] if outs is not None else torch.empty(words, dtype=torch.int64, device=device)
         results_out.append(out)
         arr[i] = _abi.Instance(graph, ctypes.pointer(g), ctypes.c_void_p(out.data_ptr()))
+    return arr, keep, results_out
+
+
+def batch_autotune(instances, *, max_per_bucket=0, reps=3, dirty=True, hybrid=None, device=None, stream=None,
+                   outs=None):
+    """Time the batched engine's routes per padded side on these instances
+    (``cfpq_batch_autotune``) and record the fastest in the batch tuning
+    table, which ``batch_closure`` and servers created afterwards use.
+    Returns one dict per padded side tuned."""
+    torch = _torch()
+    L = lib()
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    k = len(instances)
+    arr, keep, _ = _instance_array(instances, outs, device)
+    opt = _options("auto", "inplace", dirty, 0, False, 0, None, hybrid=hybrid)
+    need = ctypes.c_size_t(0)
+    _abi.check(L.cfpq_batch_autotune_workspace_bytes(k, arr, ctypes.byref(opt), ctypes.byref(need)))
+    ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=device)
+    out = (_abi.BatchTuneEntry * 64)()
+    got = ctypes.c_int32(0)
+    _abi.check(L.cfpq_batch_autotune(k, arr, ctypes.byref(opt), _stream_ptr(stream), ctypes.c_void_p(ws.data_ptr()),
+                                     ctypes.c_size_t(ws.numel()), int(max_per_bucket), int(reps), out, 64,
+                                     ctypes.byref(got)))
+    del keep
+    return [out[i].as_dict() for i in range(min(got.value, 64))]
+
+
+def batch_tune_get(npad: int):
+    """The batch tuning table's entry for padded side npad, or None."""
+    e = _abi.BatchTuneEntry()
+    st = lib().cfpq_batch_tune_get(int(npad), ctypes.byref(e))
+    if st == _abi.CFPQ_ENOTREADY:
+        return None
+    _abi.check(st)
+    return e.as_dict()
+
+
+def batch_tune_set(npad: int, route: str | None, tile: int = 256):
+    """Set the route of padded side npad by hand ("resident", or "tiles" with
+    tile 128 / 256); route None removes the entry."""
+    e = _abi.BatchTuneEntry()
+    e.npad = int(npad)
+    e.route = {None: 0, "resident": _abi.ROUTE_RESIDENT, "tiles": _abi.ROUTE_TILES}[route]
+    e.tile = int(tile) if route == "tiles" else 0
+    _abi.check(lib().cfpq_batch_tune_set(ctypes.byref(e)))
+
+
+def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=None, stream=None,
+                  outs=None, workspace=None, allow_partial=False, hybrid=None):
+    """Closure of many independent instances in one call (``cfpq_batch_closure``).
+
+    ``instances`` is a sequence of (n, edges, grammar); edges on the host or as
+    int32 CUDA tensors.  Returns one ``Result`` per instance (each with its own
+    device result buffer, or the buffers in ``outs``).  ``hybrid`` (0/1,
+    default the library's: 1) lets rules of larger instances with an
+    edge-matrix left operand run as row gathers."""
+    torch = _torch()
+    L = lib()
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    k = len(instances)
+    arr, keep, results_out = _instance_array(instances, outs, device)
     opt = _options("auto", "inplace", dirty, max_iters, False, 0, capture, hybrid=hybrid)
     need = ctypes.c_size_t(0)
     _abi.check(L.cfpq_batch_workspace_bytes(k, arr, ctypes.byref(opt), ctypes.byref(need)))
@@ -362,6 +416,11 @@ class Server:
         info = _abi.RequestInfo()
         st = lib().cfpq_server_wait(self._handle, ctypes.c_int64(ticket), ctypes.byref(info))
         return self._finish(ticket, st, info)
+
+    def inject_fault(self):
+        """Make the worker stop at its next turn as after a HIP error
+        (``cfpq_server_inject_fault``; for tests of the failure handling)."""
+        _abi.check(lib().cfpq_server_inject_fault(self._handle))
 
     def close(self):
         if self._handle:

@@ -12,7 +12,8 @@ CFPQ_OK, CFPQ_EINVAL, CFPQ_ENOMEM, CFPQ_EDEVICE, CFPQ_ENOTCONV, CFPQ_EBUSY, CFPQ
 CFPQ_ERANGE = -7
 PATH_AUTO, PATH_BITS, PATH_MFMA, PATH_ROWS, PATH_COLS, PATH_FP4 = 0, 1, 2, 3, 4, 5
 HYBRID_OFF, HYBRID_AUTO = 0, 1
-ABI_VERSION = 3
+ROUTE_RESIDENT, ROUTE_TILES = 1, 2
+ABI_VERSION = 4
 SCHEDULE_INPLACE, SCHEDULE_JACOBI = 0, 1
 STATUS_NAMES = {0: "CFPQ_OK", -1: "CFPQ_EINVAL", -2: "CFPQ_ENOMEM", -3: "CFPQ_EDEVICE",
                 -4: "CFPQ_ENOTCONV", -5: "CFPQ_EBUSY", -6: "CFPQ_ENOTREADY", -7: "CFPQ_ERANGE"}
@@ -23,9 +24,10 @@ EXPORTED = (
     "cfpq_product_workspace_bytes", "cfpq_product", "cfpq_popcount",
     "cfpq_batch_workspace_bytes", "cfpq_batch_closure",
     "cfpq_server_default_config", "cfpq_server_create", "cfpq_server_submit", "cfpq_server_poll",
-    "cfpq_server_wait", "cfpq_server_destroy",
+    "cfpq_server_wait", "cfpq_server_destroy", "cfpq_server_inject_fault",
     "cfpq_autotune_workspace_bytes", "cfpq_autotune", "cfpq_tune_get", "cfpq_tune_save", "cfpq_tune_load",
-    "cfpq_tune_clear",
+    "cfpq_tune_clear", "cfpq_batch_autotune_workspace_bytes", "cfpq_batch_autotune", "cfpq_batch_tune_get",
+    "cfpq_batch_tune_set",
     "cfpq_lengths_bytes", "cfpq_single_path_workspace_bytes", "cfpq_single_path", "cfpq_witness",
     "cfpq_conjunctive_workspace_bytes", "cfpq_conjunctive_closure",
 )
@@ -76,7 +78,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("products", ctypes.c_int64), ("bitops", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("product_ms", ctypes.c_double), ("path_used", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("sparse_products", ctypes.c_int64), ("delta_products", ctypes.c_int64),
-                ("minplus_terms", ctypes.c_double)]
+                ("minplus_terms", ctypes.c_double), ("sparse_bytes", ctypes.c_double), ("sparse_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -93,6 +95,23 @@ class TuneEntry(ctypes.Structure):
                  for k in range(self.n_candidates)}
         return {"npad": self.npad, "path": names.get(self.path, "?"), "tile": self.tile,
                 "ms": round(self.ms, 4), "candidates_ms": cands}
+
+
+class BatchTuneEntry(ctypes.Structure):
+    _fields_ = [("npad", ctypes.c_int32), ("route", ctypes.c_int32), ("tile", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("instances", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("candidate_route", ctypes.c_int32 * 4), ("candidate_tile", ctypes.c_int32 * 4),
+                ("candidates_ms", ctypes.c_float * 4)]
+
+    @staticmethod
+    def _name(route, tile):
+        return "resident" if route == ROUTE_RESIDENT else f"tiles{tile}"
+
+    def as_dict(self):
+        cands = {self._name(self.candidate_route[k], self.candidate_tile[k]): round(self.candidates_ms[k], 4)
+                 for k in range(self.n_candidates)}
+        return {"npad": self.npad, "route": "resident" if self.route == ROUTE_RESIDENT else "tiles",
+                "tile": self.tile, "ms": round(self.ms, 4), "instances": self.instances, "candidates_ms": cands}
 
 
 class ServerConfig(ctypes.Structure):
@@ -168,6 +187,8 @@ def load(path: str = LIB_PATH):
     lib.cfpq_server_wait.restype = ctypes.c_int
     lib.cfpq_server_destroy.argtypes = [p]
     lib.cfpq_server_destroy.restype = ctypes.c_int
+    lib.cfpq_server_inject_fault.argtypes = [p]
+    lib.cfpq_server_inject_fault.restype = ctypes.c_int
     lib.cfpq_autotune_workspace_bytes.argtypes = [i32]
     lib.cfpq_autotune_workspace_bytes.restype = sz
     lib.cfpq_autotune.argtypes = [i32, p, p, sz, ctypes.POINTER(TuneEntry)]
@@ -180,6 +201,16 @@ def load(path: str = LIB_PATH):
     lib.cfpq_tune_load.restype = ctypes.c_int
     lib.cfpq_tune_clear.argtypes = []
     lib.cfpq_tune_clear.restype = None
+    lib.cfpq_batch_autotune_workspace_bytes.argtypes = [i32, ctypes.POINTER(Instance), ctypes.POINTER(Options),
+                                                        ctypes.POINTER(sz)]
+    lib.cfpq_batch_autotune_workspace_bytes.restype = ctypes.c_int
+    lib.cfpq_batch_autotune.argtypes = [i32, ctypes.POINTER(Instance), ctypes.POINTER(Options), p, p, sz, i32, i32,
+                                        ctypes.POINTER(BatchTuneEntry), i32, ctypes.POINTER(i32)]
+    lib.cfpq_batch_autotune.restype = ctypes.c_int
+    lib.cfpq_batch_tune_get.argtypes = [i32, ctypes.POINTER(BatchTuneEntry)]
+    lib.cfpq_batch_tune_get.restype = ctypes.c_int
+    lib.cfpq_batch_tune_set.argtypes = [ctypes.POINTER(BatchTuneEntry)]
+    lib.cfpq_batch_tune_set.restype = ctypes.c_int
     lib.cfpq_lengths_bytes.argtypes = [i32, i32]
     lib.cfpq_lengths_bytes.restype = sz
     lib.cfpq_single_path_workspace_bytes.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar),

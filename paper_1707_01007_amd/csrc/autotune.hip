@@ -1,12 +1,17 @@
-// Autotuner: per size bucket, the fastest product kernel (path and tile).
+// Autotuner tables.
 //
-// cfpq_autotune(n) times every candidate -- the int8 MFMA product and the
-// VALU product with 8, 16 and 32-word strips -- on synthetic operands of the
-// padded size for n (counter-based pseudo-random bits, density 1/2, made on
-// the device), keeps the fastest in a process-wide table keyed by
-// ceil(log2(npad)), and the AUTO path of cfpq_closure / cfpq_product uses
-// that entry.  The table can be saved to and loaded from a small JSON file;
-// the environment variable CFPQ_TUNE_CACHE names a file loaded at first use.
+// Products: cfpq_autotune(n) times every candidate -- the fp4 and int8 MFMA
+// products and the VALU product with 8, 16 and 32-word strips -- on synthetic
+// operands of the padded size for n (counter-based pseudo-random bits,
+// density 1/2, made on the device), keeps the fastest in a process-wide table
+// keyed by ceil(log2(npad)), and the AUTO path of cfpq_closure / cfpq_product
+// uses that entry.
+// Batched engine: one route per padded side (resident workgroup, or the tile
+// work list with 256 or 128 tiles), filled by cfpq_batch_autotune (which
+// times the candidates on the caller's own instances, batch_api.hip) or by
+// hand (cfpq_batch_tune_set); cfpq_batch_closure and the server read it.
+// Both tables can be saved to and loaded from a small JSON file; the
+// environment variable CFPQ_TUNE_CACHE names a file loaded at first use.
 // Every candidate computes the same bits, so tuning never changes a result.
 #include <hip/hip_runtime.h>
 
@@ -19,7 +24,7 @@
 #include <string>
 #include <vector>
 
-#include "cfpq_internal.h"
+#include "batch_engine.h"
 
 namespace cfpq {
 namespace {
@@ -27,6 +32,7 @@ namespace {
 struct TuneTable {
     std::mutex mu;
     std::map<int32_t, cfpq_tune_entry> by_bucket;
+    std::map<int32_t, cfpq_batch_tune_entry> batch;  // by padded side
     bool env_loaded = false;
 };
 
@@ -55,12 +61,40 @@ __global__ void fill_random_kernel(uint64_t* __restrict__ p, size_t words, uint6
 
 const char* path_name(int32_t p) { return p == CFPQ_PATH_FP4 ? "fp4" : p == CFPQ_PATH_MFMA ? "mfma" : "bits"; }
 
-cfpq_status load_file(const char* path, std::map<int32_t, cfpq_tune_entry>& out) {
+const char* route_name(int32_t r) { return r == CFPQ_ROUTE_RESIDENT ? "resident" : "tiles"; }
+
+// A batch route the engine can run: RESIDENT only up to kSmallMaxPad, TILES
+// with 128 or 256 tiles, a padded side that is a positive multiple of 256.
+bool batch_entry_valid(const cfpq_batch_tune_entry& e) {
+    if (e.npad <= 0 || e.npad % 256 != 0) return false;
+    if (e.route == CFPQ_ROUTE_RESIDENT) return e.npad <= kSmallMaxPad;
+    if (e.route == CFPQ_ROUTE_TILES) return e.tile == 128 || e.tile == 256;
+    return false;
+}
+
+cfpq_status load_file(const char* path, std::map<int32_t, cfpq_tune_entry>& out,
+                      std::map<int32_t, cfpq_batch_tune_entry>& batch_out) {
     FILE* f = std::fopen(path, "r");
     if (!f) return fail(CFPQ_EINVAL, std::string("cannot open ") + path);
     char line[512];
     int n_ok = 0;
     while (std::fgets(line, sizeof line, f)) {
+        {
+            // {"batch_npad": P, "route": "tiles", "tile": T, "ms": X, "instances": K}
+            cfpq_batch_tune_entry b;
+            std::memset(&b, 0, sizeof b);
+            char rname[16] = {0};
+            if (std::sscanf(line, " {\"batch_npad\": %d, \"route\": \"%15[a-z]\", \"tile\": %d, \"ms\": %f, "
+                                  "\"instances\": %d",
+                            &b.npad, rname, &b.tile, &b.ms, &b.instances) == 5) {
+                b.route = std::strcmp(rname, "resident") == 0 ? CFPQ_ROUTE_RESIDENT
+                          : std::strcmp(rname, "tiles") == 0  ? CFPQ_ROUTE_TILES
+                                                              : 0;
+                if (b.route == CFPQ_ROUTE_RESIDENT) b.tile = 0;
+                if (batch_entry_valid(b)) batch_out[b.npad] = b;
+                continue;
+            }
+        }
         // {"bucket": B, "npad": P, "path": "mfma", "tile": T, "ms": X}
         cfpq_tune_entry e;
         std::memset(&e, 0, sizeof e);
@@ -88,13 +122,44 @@ void ensure_env_loaded(TuneTable& t) {
     const char* p = std::getenv("CFPQ_TUNE_CACHE");
     if (p && *p) {
         std::map<int32_t, cfpq_tune_entry> m;
-        if (load_file(p, m) == CFPQ_OK)
+        std::map<int32_t, cfpq_batch_tune_entry> mb;
+        if (load_file(p, m, mb) == CFPQ_OK) {
             for (auto& kv : m) t.by_bucket[kv.first] = kv.second;
+            for (auto& kv : mb) t.batch[kv.first] = kv.second;
+        }
         clear_last_error();
     }
 }
 
 }  // namespace
+
+BatchRoute batch_route(int64_t npad, const BatchRoute* forced) {
+    BatchRoute r;
+    if (forced) {
+        r = *forced;
+    } else {
+        r.route = npad <= kSmallMaxPad ? kRouteResident : kRouteTiles;
+        r.tile = 256;
+        TuneTable& t = table();
+        std::lock_guard<std::mutex> lk(t.mu);
+        ensure_env_loaded(t);
+        auto it = t.batch.find(static_cast<int32_t>(npad));
+        if (it != t.batch.end()) {
+            r.route = it->second.route;
+            r.tile = it->second.tile;
+        }
+    }
+    if (r.route == kRouteResident && npad > kSmallMaxPad) r = BatchRoute{};
+    if (r.route == kRouteTiles && r.tile != 128) r.tile = 256;
+    return r;
+}
+
+void batch_tune_record(const cfpq_batch_tune_entry& e) {
+    TuneTable& t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    ensure_env_loaded(t);
+    t.batch[e.npad] = e;
+}
 
 bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile, float* ms) {
     TuneTable& t = table();
@@ -223,6 +288,13 @@ cfpq_status cfpq_tune_save(const char* path) {
         std::fprintf(f, " {\"bucket\": %d, \"npad\": %d, \"path\": \"%s\", \"tile\": %d, \"ms\": %.6f}%s\n", kv.first,
                      e.npad, path_name(e.path), e.tile, e.ms, (++k < t.by_bucket.size()) ? "," : "");
     }
+    std::fprintf(f, "], \"batch\": [\n");
+    k = 0;
+    for (auto& kv : t.batch) {
+        const cfpq_batch_tune_entry& e = kv.second;
+        std::fprintf(f, " {\"batch_npad\": %d, \"route\": \"%s\", \"tile\": %d, \"ms\": %.6f, \"instances\": %d}%s\n",
+                     e.npad, route_name(e.route), e.tile, e.ms, e.instances, (++k < t.batch.size()) ? "," : "");
+    }
     std::fprintf(f, "]}\n");
     std::fclose(f);
     return CFPQ_OK;
@@ -232,12 +304,14 @@ cfpq_status cfpq_tune_load(const char* path) {
     clear_last_error();
     if (!path) return fail(CFPQ_EINVAL, "path is NULL");
     std::map<int32_t, cfpq_tune_entry> m;
-    cfpq_status st = load_file(path, m);
+    std::map<int32_t, cfpq_batch_tune_entry> mb;
+    cfpq_status st = load_file(path, m, mb);
     if (st != CFPQ_OK) return st;
     TuneTable& t = table();
     std::lock_guard<std::mutex> lk(t.mu);
     t.env_loaded = true;
     for (auto& kv : m) t.by_bucket[kv.first] = kv.second;
+    for (auto& kv : mb) t.batch[kv.first] = kv.second;
     return CFPQ_OK;
 }
 
@@ -245,7 +319,39 @@ void cfpq_tune_clear(void) {
     TuneTable& t = table();
     std::lock_guard<std::mutex> lk(t.mu);
     t.by_bucket.clear();
+    t.batch.clear();
     t.env_loaded = true;
+}
+
+cfpq_status cfpq_batch_tune_get(int32_t npad, cfpq_batch_tune_entry* out) {
+    clear_last_error();
+    if (!out) return fail(CFPQ_EINVAL, "out is NULL");
+    TuneTable& t = table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    ensure_env_loaded(t);
+    auto it = t.batch.find(npad);
+    if (it == t.batch.end()) return CFPQ_ENOTREADY;
+    *out = it->second;
+    return CFPQ_OK;
+}
+
+cfpq_status cfpq_batch_tune_set(const cfpq_batch_tune_entry* entry) {
+    clear_last_error();
+    if (!entry) return fail(CFPQ_EINVAL, "entry is NULL");
+    TuneTable& t = table();
+    if (entry->route == 0) {
+        std::lock_guard<std::mutex> lk(t.mu);
+        ensure_env_loaded(t);
+        t.batch.erase(entry->npad);
+        return CFPQ_OK;
+    }
+    cfpq_batch_tune_entry e = *entry;
+    if (e.route == CFPQ_ROUTE_RESIDENT) e.tile = 0;
+    if (!batch_entry_valid(e))
+        return fail(CFPQ_EINVAL, "batch route: padded side must be a positive multiple of 256, RESIDENT at most "
+                                 "512, TILES with tile 128 or 256");
+    batch_tune_record(e);
+    return CFPQ_OK;
 }
 
 }  // extern "C"

@@ -2,7 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -28,7 +30,12 @@ struct BatchPlan {
     std::vector<size_t> tt_off;  // per slot: byte offset of its transposes (large) in the tt region
 };
 
-cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options& o, BatchPlan& p) {
+// Tables and workspace layout of a batch.  Each instance takes its route
+// from batch_route (forced, or the tuning table); the workspace reserves the
+// transposes and changed-row bitmaps of every instance with rules whatever its
+// route, so its size does not depend on the table.
+cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options& o, BatchPlan& p,
+                       const RouteMap* overrides = nullptr, bool jacobi_resident = false) {
     p.n = n;
     p.descs.resize(n);
     p.edge_copy_off.assign(n, SIZE_MAX);
@@ -71,12 +78,20 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
                 lhs[fill[gr->term_rules[r].terminal]++] = gr->term_rules[r].lhs;
         }
         p.term.insert(p.term.end(), lhs.begin(), lhs.end());
-        d.kind = (L.npad <= kSmallMaxPad) ? kSlotSmall : kSlotLarge;
+        // the Jacobi schedule runs only on the resident kernel (cfpq_closure's small closures)
+        const BatchRoute* forced = nullptr;
+        if (overrides) {
+            auto it = overrides->find(L.npad);
+            if (it != overrides->end()) forced = &it->second;
+        }
+        const BatchRoute rt = jacobi_resident ? BatchRoute{kRouteResident, 0} : batch_route(L.npad, forced);
+        d.kind = rt.route == kRouteResident ? kSlotSmall : kSlotLarge;
+        d.tile = rt.route == kRouteResident ? 0 : rt.tile;
         d.trans_off = static_cast<int32_t>(p.trans.size());
         int32_t n_right = 0;
         std::vector<int32_t> tr(d.n_nt, -1);
         std::vector<int32_t> md(d.n_rules, kModeDense);
-        if (d.kind == kSlotLarge) {
+        if (d.n_rules > 0) {
             if (o.hybrid == CFPQ_HYBRID_AUTO)
                 for (int32_t r = 0; r < d.n_rules; ++r)
                     md[r] = engine_rule_mode(gr->bin_rules, d.n_rules, r, g.n_edges, L.npad);
@@ -85,6 +100,10 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
             tt_bytes += static_cast<size_t>(n_right) * L.mat_words * 8 + engine_rowbits_bytes(d.n_nt, L.W);
             p.large_rules += d.n_rules;
             p.large_trans += n_right;
+        }
+        if (d.kind == kSlotSmall) {
+            std::fill(tr.begin(), tr.end(), -1);
+            std::fill(md.begin(), md.end(), kModeDense);
         }
         p.trans.insert(p.trans.end(), tr.begin(), tr.end());
         p.modes.insert(p.modes.end(), md.begin(), md.end());
@@ -124,9 +143,10 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
     p.off_term = take(4 * p.term.size());
     p.off_jobs = take(sizeof(Job) * std::max(p.large_rules, 1));
     p.off_tjobs = take(sizeof(Job) * std::max(p.large_trans, 1));
-    p.off_large = take(4 * p.large.size());
-    p.off_small8 = take(4 * p.small8.size());
-    p.off_small16 = take(4 * p.small16.size());
+    // slot-id lists sized for every instance, so the total does not depend on the routes
+    p.off_large = take(4 * static_cast<size_t>(n));
+    p.off_small8 = take(4 * static_cast<size_t>(n));
+    p.off_small16 = take(4 * static_cast<size_t>(n));
     p.off_all = take(4 * p.all_ids.size());
     p.off_edge_begin = take(8 * p.edge_begin.size());
     p.off_es = take(sizeof(EngineState));
@@ -141,7 +161,7 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
 size_t batch_workspace_one(const cfpq_graph& graph, const cfpq_grammar* grammar, const cfpq_options& o) {
     const cfpq_instance inst{graph, grammar, nullptr};
     BatchPlan p;
-    plan_batch(1, &inst, o, p);
+    plan_batch(1, &inst, o, p, nullptr, true);
     return p.total;
 }
 
@@ -215,17 +235,126 @@ cfpq_status cfpq_batch_closure(int32_t n_instances, const cfpq_instance* instanc
                              false);
 }
 
+cfpq_status cfpq_batch_autotune_workspace_bytes(int32_t n_instances, const cfpq_instance* instances,
+                                                const cfpq_options* opt, size_t* bytes) {
+    // every sub-batch the tuner runs is a subset of the instances, and the
+    // workspace of a batch does not depend on the routes
+    return cfpq_batch_workspace_bytes(n_instances, instances, opt, bytes);
+}
+
+cfpq_status cfpq_batch_autotune(int32_t n_instances, const cfpq_instance* instances, const cfpq_options* opt,
+                                void* stream, void* d_workspace, size_t workspace_bytes, int32_t max_per_bucket,
+                                int32_t reps, cfpq_batch_tune_entry* out, int32_t max_out, int32_t* n_out) {
+    clear_last_error();
+    if (n_out) *n_out = 0;
+    if (max_per_bucket < 0 || reps < 0 || max_out < 0) return fail(CFPQ_EINVAL, "negative argument");
+    if (max_out > 0 && !out) return fail(CFPQ_EINVAL, "out is NULL");
+    const cfpq_options o = resolve_batch(opt);
+    cfpq_status st = validate_batch(n_instances, instances, o);
+    if (st != CFPQ_OK) return st;
+    BatchPlan whole;
+    plan_batch(n_instances, instances, o, whole);
+    if (workspace_bytes < whole.total || (whole.total > 0 && !d_workspace))
+        return fail(CFPQ_ENOMEM, "workspace too small: need " + std::to_string(whole.total) + " bytes");
+    if (reps == 0) reps = 3;
+    // The sample: the first max_per_bucket instances of every padded side (all
+    // with max_per_bucket = 0) that have something to iterate, in input order.
+    std::map<int64_t, int32_t> per_side;
+    std::vector<cfpq_instance> sample;
+    for (int32_t i = 0; i < n_instances; ++i) {
+        const cfpq_instance& in = instances[i];
+        if (in.graph.n_nodes == 0 || in.grammar->n_bin_rules == 0) continue;
+        int32_t& k = per_side[layout_for(in.graph.n_nodes).npad];
+        if (max_per_bucket > 0 && k >= max_per_bucket) continue;
+        ++k;
+        sample.push_back(in);
+    }
+    const int32_t count = static_cast<int32_t>(sample.size());
+    // Median wall time of `reps` runs of the whole sample (each synchronises
+    // the stream), after one warm-up run.
+    auto time_sample = [&](const RouteMap& routes, float* ms) -> cfpq_status {
+        cfpq_status s2 = batch_closure_run(count, sample.data(), o, stream, d_workspace, workspace_bytes, nullptr,
+                                           false, &routes);
+        if (s2 != CFPQ_OK && s2 != CFPQ_ENOTCONV) return s2;
+        std::vector<double> times;
+        for (int32_t r = 0; r < reps; ++r) {
+            const auto t0 = std::chrono::steady_clock::now();
+            s2 = batch_closure_run(count, sample.data(), o, stream, d_workspace, workspace_bytes, nullptr, false,
+                                   &routes);
+            if (s2 != CFPQ_OK && s2 != CFPQ_ENOTCONV) return s2;
+            times.push_back(
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        std::sort(times.begin(), times.end());
+        *ms = static_cast<float>(times[times.size() / 2]);
+        return CFPQ_OK;
+    };
+    // Coordinate descent over the sides, smallest first: each side tries every
+    // candidate route while the others keep their current one (the table's,
+    // or the default), inside the whole sample -- so the overlap of resident
+    // workgroups with the tile work list counts -- and keeps the fastest; a
+    // candidate replaces the current route only when it is faster by more
+    // than 2% (run-to-run noise).
+    RouteMap routes;
+    for (auto& kv : per_side) routes[kv.first] = batch_route(kv.first, nullptr);
+    int32_t written = 0;
+    for (auto& kv : per_side) {
+        const int64_t npad = kv.first;
+        std::vector<BatchRoute> cands;
+        if (npad <= kSmallMaxPad) cands.push_back(BatchRoute{kRouteResident, 0});
+        cands.push_back(BatchRoute{kRouteTiles, 256});
+        cands.push_back(BatchRoute{kRouteTiles, 128});
+        const BatchRoute current = routes[npad];
+        cfpq_batch_tune_entry e;
+        std::memset(&e, 0, sizeof e);
+        e.npad = static_cast<int32_t>(npad);
+        e.instances = kv.second;
+        float cur_ms = 0.f, best_ms = 0.f;
+        BatchRoute best = current;
+        for (size_t c = 0; c < cands.size(); ++c) {
+            routes[npad] = cands[c];
+            float ms = 0.f;
+            st = time_sample(routes, &ms);
+            if (st != CFPQ_OK) return st;
+            e.candidate_route[c] = cands[c].route;
+            e.candidate_tile[c] = cands[c].route == kRouteTiles ? cands[c].tile : 0;
+            e.candidates_ms[c] = ms;
+            const bool is_current = cands[c].route == current.route &&
+                                    (cands[c].route == kRouteResident || cands[c].tile == current.tile);
+            if (is_current) cur_ms = ms;
+        }
+        best_ms = cur_ms;
+        for (size_t c = 0; c < cands.size(); ++c)
+            if (e.candidates_ms[c] < 0.98f * cur_ms && e.candidates_ms[c] < best_ms) {
+                best_ms = e.candidates_ms[c];
+                best = cands[c];
+            }
+        routes[npad] = best;
+        e.n_candidates = static_cast<int32_t>(cands.size());
+        e.route = best.route;
+        e.tile = best.route == kRouteTiles ? best.tile : 0;
+        e.ms = best_ms;
+        batch_tune_record(e);
+        if (written < max_out) out[written] = e;
+        ++written;
+    }
+    if (n_out) *n_out = written;
+    clear_last_error();
+    return CFPQ_OK;
+}
+
 }  // extern "C"
 
 namespace cfpq {
 
 cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instances, const cfpq_options& o,
                               void* stream, void* d_workspace, size_t workspace_bytes, cfpq_stats* stats,
-                              bool allow_jacobi) {
+                              bool allow_jacobi, const RouteMap* overrides) {
     cfpq_status vst = validate_batch(n_instances, instances, o, allow_jacobi);
     if (vst != CFPQ_OK) return vst;
     BatchPlan p;
-    plan_batch(n_instances, instances, o, p);
+    // cfpq_closure's small closures (allow_jacobi) always run resident
+    plan_batch(n_instances, instances, o, p, overrides, allow_jacobi);
     if (workspace_bytes < p.total || (p.total > 0 && !d_workspace))
         return fail(CFPQ_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");
     if (n_instances == 0) return CFPQ_OK;
@@ -394,6 +523,8 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
             st.sparse_products = 0;
             st.delta_products = 0;
             st.minplus_terms = 0.0;
+            st.sparse_bytes = 0.0;
+            st.sparse_ms = 0.0;
         }
     }
     if (!all_conv) return fail(CFPQ_ENOTCONV, "max_iters reached before the fixpoint in some instance");

@@ -6,8 +6,9 @@
 //    whole fixpoint in a single resident kernel launch (VALU product with the
 //    right operand staged in LDS, change flags in LDS);
 //  * large: every loop, a plan kernel turns the dirty rules of all running
-//    large slots into work lists -- 256 x 256 fp4-MFMA tiles for dense rules,
-//    pulled from an atomic counter by a persistent kernel, and 64-row blocks
+//    large slots into work lists -- fp4-MFMA tiles for dense rules (256 x 256
+//    per workgroup, or 128 x 128 per wavefront, by the slot's size bucket),
+//    pulled from atomic counters by a persistent kernel, and 64-row blocks
 //    of C for rules whose left operand is derived from terminal rules only (a
 //    sparse, fixed edge matrix B): a second kernel of high occupancy gathers
 //    each row of A from the rows of C its row of B selects or (batch slots,
@@ -21,6 +22,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -28,7 +30,25 @@
 
 namespace cfpq {
 
+// Largest padded side the resident kernel takes (its LDS staging).
 constexpr int32_t kSmallMaxPad = 512;
+
+// Engine route of a size bucket (padded side npad): the resident kernel
+// (npad <= kSmallMaxPad) or the shared tile work list with 256 or 128 tiles.
+enum : int32_t { kRouteResident = CFPQ_ROUTE_RESIDENT, kRouteTiles = CFPQ_ROUTE_TILES };
+struct BatchRoute {
+    int32_t route = kRouteTiles;
+    int32_t tile = 256;
+};
+
+// The route of padded side npad: a forced one, else the batch tuning table's
+// entry (cfpq_batch_autotune, cfpq_batch_tune_set / load), else the default
+// (resident up to kSmallMaxPad, 256 tiles above).  A resident route for a
+// larger side, or a tile other than 128 / 256, is never returned.
+BatchRoute batch_route(int64_t npad, const BatchRoute* forced);
+
+// Record a measured entry in the batch tuning table (autotune.hip).
+void batch_tune_record(const cfpq_batch_tune_entry& e);
 
 enum : int32_t { kSlotLarge = 1, kSlotSmall = 2 };
 
@@ -50,6 +70,7 @@ struct SlotDesc {
     int32_t kind;
     int32_t dirty;
     int32_t jacobi;  // small slots only: Algorithm 1's simultaneous step (see resident_jacobi_fits)
+    int32_t tile;    // large slots: 256 (workgroup tiles) or 128 (wavefront tiles) of the dense rules
 };
 
 struct SlotState {
@@ -69,14 +90,17 @@ struct Job {
     int32_t slot, what, item_begin, dim;  // what: rule index (products) or nonterminal (transposes)
 };
 
+// Work lists of a loop: jobs[0, n_jobs) are dense rules on 256 x 256
+// workgroup tiles, the next n_jobs128 dense rules on 128 x 128 wavefront
+// tiles, the next n_rjobs row-gather rules.
 struct EngineState {
     int32_t n_jobs, total_items, next_item, pad0;
     int32_t n_tjobs, total_titems, next_titem, pad1;
     int32_t running;  // large slots still running after the last finish
     int32_t n_large;  // entries of the large-slot list (set by the host between replays)
-    int32_t n_rjobs;     // row-gather jobs of the loop, stored after the n_jobs tile jobs
+    int32_t n_rjobs;     // row-gather jobs of the loop
     int32_t total_rows;  // their items: rows of A (first loop) or blocks of rows of C (one wavefront each)
-    int32_t pad2[4];
+    int32_t n_jobs128, total_items128, next_item128, pad2;
 };
 
 // Device buffers of an engine (all carved from one allocation by the owner).
@@ -141,9 +165,14 @@ inline bool resident_jacobi_fits(int32_t n_nodes, int32_t n_nt) {
 
 // cfpq_batch_closure with, when allow_jacobi, the JACOBI schedule accepted for
 // instances that resident_jacobi_fits (cfpq_closure's small closures).
+// Routes by padded side that override the tuning table (the tuner's trials).
+using RouteMap = std::map<int64_t, BatchRoute>;
+
+// overrides: nullptr, or routes of some padded sides (the others from the
+// table or the default).
 cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instances, const cfpq_options& o,
                               void* stream, void* d_workspace, size_t workspace_bytes, cfpq_stats* stats,
-                              bool allow_jacobi);
+                              bool allow_jacobi, const RouteMap* overrides = nullptr);
 
 // Workspace bytes of cfpq_batch_closure for one instance (batch_api.hip);
 // the graph and grammar must be valid.  Used by cfpq_closure for closures it

@@ -364,14 +364,15 @@ __device__ void scan2(int32_t* sa, int32_t* sb, int32_t& a, int32_t& b, int32_t*
     b = sb[t];
 }
 
-// Exclusive prefix sums over the 256 threads of four per-thread counts
+// Exclusive prefix sums over the 256 threads of kN per-thread counts
 // (in place) and their totals.
-__device__ void scan4(int32_t (*sh)[256], int32_t (&v)[4], int32_t* const (&tot)[4]) {
+template <int kN>
+__device__ void scan_n(int32_t (*sh)[256], int32_t (&v)[kN], int32_t* const (&tot)[kN]) {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) sh[c][t] = v[c];
+    for (int c = 0; c < kN; ++c) sh[c][t] = v[c];
     __syncthreads();
-    if (t < 4) {
+    if (t < kN) {
         int32_t x = 0;
         for (int i = 0; i < 256; ++i) {
             const int32_t y = sh[t][i];
@@ -382,27 +383,29 @@ __device__ void scan4(int32_t (*sh)[256], int32_t (&v)[4], int32_t* const (&tot)
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 4; ++c) v[c] = sh[c][t];
+    for (int c = 0; c < kN; ++c) v[c] = sh[c][t];
 }
 
 // Start of a loop: for every running large slot decide which rules run
-// (dirty worklist), clear the slot's change flags, and lay out the work lists:
-// 256 x 256 tiles of the dense rules (jobs[0, n_jobs)), and the items of the
-// row-gather rules (jobs[n_jobs, n_jobs + n_rjobs)): rows of A in a slot's
-// first kPullLoops loops and in every loop of a slot without changed-row
-// bitmaps (dim = 1), kPushRows-row blocks of C otherwise (dim = 0).
+// (dirty worklist), clear the slot's change flags, and lay out the work lists
+// (EngineState): the tiles of the dense rules -- 256 x 256 workgroup tiles
+// for slots with tile 256, 128 x 128 wavefront tiles for slots with tile 128
+// -- and the items of the row-gather rules: rows of A in a slot's first
+// kPullLoops loops and in every loop of a slot without changed-row bitmaps
+// (dim = 1), kPushRows-row blocks of C otherwise (dim = 0).
 // Slots are handled in list order (largest first), so the biggest tiles are
 // handed out first.
 __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
                                                           const int32_t* __restrict__ rules_tab, int32_t* go_tab,
                                                           const int32_t* __restrict__ mode_tab, Job* jobs,
                                                           EngineState* es, const int32_t* __restrict__ large_ids) {
-    __shared__ int32_t sh[4][256];
+    __shared__ int32_t sh[6][256];
     const int t = threadIdx.x;
     const int n_large = es->n_large;
     const int per = (n_large + 255) / 256;
     const int q0 = t * per, q1 = min(n_large, q0 + per);
-    int32_t my_jobs = 0, my_items = 0, my_rjobs = 0, my_rows = 0;
+    // counts per thread: 256-tile jobs and items, 128-tile jobs and items, row jobs and items
+    int32_t v[6] = {0, 0, 0, 0, 0, 0};
     for (int q = q0; q < q1; ++q) {
         const int slot = large_ids[q];
         const SlotDesc& d = descs[slot];
@@ -424,7 +427,9 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             const int64_t quads = static_cast<int64_t>(d.n_nt) * d.W / 2;
             for (int64_t x = 0; x < quads; ++x) cur[x] = make_uint4(0, 0, 0, 0);
         }
-        const int dim = d.npad / 256;
+        const bool t128 = d.tile == 128;  // any other value means 256 tiles
+        const int dim = d.npad / (t128 ? 128 : 256);
+        const int ts = t128 ? 2 : 0;  // index of the slot's tile counts in v
         int launched = 0;
         for (int r = 0; r < d.n_rules; ++r) {
             const int rb = rules_tab[3 * (d.rule_off + r) + 1];
@@ -434,39 +439,43 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             launched += go;
             if (!go) continue;
             if (mode_tab[d.rule_off + r] == kModeRows) {
-                ++my_rjobs;
-                my_rows += (st->iterations < kPullLoops || d.RD == nullptr) ? d.n : (d.n + kPushRows - 1) / kPushRows;
+                v[4] += 1;
+                v[5] += (st->iterations < kPullLoops || d.RD == nullptr) ? d.n : (d.n + kPushRows - 1) / kPushRows;
             } else {
-                ++my_jobs;
-                my_items += dim * dim;
+                v[ts] += 1;
+                v[ts + 1] += dim * dim;
             }
         }
         st->products += launched;
     }
-    int32_t v[4] = {my_jobs, my_items, my_rjobs, my_rows};
-    int32_t* const tot[4] = {&es->n_jobs, &es->total_items, &es->n_rjobs, &es->total_rows};
-    scan4(sh, v, tot);
-    my_jobs = v[0];
-    my_items = v[1];
-    my_rjobs = v[2];
-    my_rows = v[3];
-    if (t == 0) es->next_item = 0;
-    __syncthreads();  // tile-job total visible to every thread (row jobs follow the tile jobs)
-    Job* rjobs = jobs + es->n_jobs;
+    int32_t* const tot[6] = {&es->n_jobs, &es->total_items, &es->n_jobs128, &es->total_items128, &es->n_rjobs,
+                             &es->total_rows};
+    scan_n<6>(sh, v, tot);
+    if (t == 0) {
+        es->next_item = 0;
+        es->next_item128 = 0;
+    }
+    __syncthreads();  // job totals visible to every thread (the lists follow each other)
+    Job* jobs128 = jobs + es->n_jobs;
+    Job* rjobs = jobs128 + es->n_jobs128;
     for (int q = q0; q < q1; ++q) {
         const int slot = large_ids[q];
         const SlotDesc& d = descs[slot];
         if (!states[slot].in_loop) continue;
-        const int dim = d.npad / 256;
+        const bool t128 = d.tile == 128;
+        const int dim = d.npad / (t128 ? 128 : 256);
         for (int r = 0; r < d.n_rules; ++r) {
             if (!go_tab[d.rule_off + r]) continue;
             if (mode_tab[d.rule_off + r] == kModeRows) {
                 const bool pull = states[slot].iterations < kPullLoops || d.RD == nullptr;
-                rjobs[my_rjobs++] = Job{slot, r, my_rows, pull ? 1 : 0};
-                my_rows += pull ? d.n : (d.n + kPushRows - 1) / kPushRows;
+                rjobs[v[4]++] = Job{slot, r, v[5], pull ? 1 : 0};
+                v[5] += pull ? d.n : (d.n + kPushRows - 1) / kPushRows;
+            } else if (t128) {
+                jobs128[v[2]++] = Job{slot, r, v[3], dim};
+                v[3] += dim * dim;
             } else {
-                jobs[my_jobs++] = Job{slot, r, my_items, dim};
-                my_items += dim * dim;
+                jobs[v[0]++] = Job{slot, r, v[1], dim};
+                v[1] += dim * dim;
             }
         }
     }
@@ -591,7 +600,7 @@ __global__ __launch_bounds__(256) void engine_rows_kernel(const SlotDesc* __rest
                                                           const EngineState* __restrict__ es) {
     const int n_rjobs = es->n_rjobs;
     const int total = es->total_rows;
-    const Job* rjobs = jobs + es->n_jobs;
+    const Job* rjobs = jobs + es->n_jobs + es->n_jobs128;
     const int waves = gridDim.x * 4;
     for (int x = blockIdx.x * 4 + (threadIdx.x >> 6); x < total; x += waves) {
         const Job jb = rjobs[job_of(rjobs, n_rjobs, x)];
@@ -630,7 +639,42 @@ __global__ __launch_bounds__(256) void engine_rows_kernel(const SlotDesc* __rest
     }
 }
 
-// Persistent product kernel: workgroups pull items from the loop's work list.
+// Operands of item `item` of dense job jb (its rule's B, C^T and A) and the
+// rows bitmap its epilogue marks.
+struct TileArgs {
+    const uint32_t* Bm;
+    const uint32_t* CT;
+    uint32_t* Am;
+    int32_t* changed;
+    uint64_t* rows;
+    int W2, kchunks, local, dim;
+};
+
+__device__ __forceinline__ TileArgs tile_args(const SlotDesc& d, SlotState* states, const int32_t* rules_tab,
+                                              const int32_t* trans_tab, const Job& jb, int item) {
+    const int r = d.rule_off + jb.what;
+    const int ra = rules_tab[3 * r], rb = rules_tab[3 * r + 1], rc = rules_tab[3 * r + 2];
+    const size_t mdw = static_cast<size_t>(d.npad) * d.W * 2;
+    const int64_t it = states[jb.slot].iterations;
+    TileArgs a;
+    a.Bm = reinterpret_cast<const uint32_t*>(d.T) + rb * mdw;
+    a.CT = reinterpret_cast<const uint32_t*>(d.TT) + trans_tab[d.trans_off + rc] * mdw;
+    a.Am = reinterpret_cast<uint32_t*>(d.T) + ra * mdw;
+    a.changed = &states[jb.slot].changed[ra];
+    // recorded from the last pull loop on, as in engine_rows_kernel
+    a.rows = d.RD && it >= kPullLoops - 1 ? d.RD + (static_cast<size_t>(it & 1) * d.n_nt + ra) * d.W : nullptr;
+    a.W2 = 2 * d.W;
+    a.kchunks = (d.n + 255) / 256;  // 256-k chunks of the fp4 tile
+    a.local = item - jb.item_begin;
+    a.dim = jb.dim;
+    return a;
+}
+
+// Persistent product kernel.  First the workgroups pull 256 x 256 tiles (all
+// four wavefronts on one tile), then each wavefront pulls 128 x 128 tiles on
+// its own (no barriers) until both lists are empty.  Either way the next
+// item's index is fetched while the current one is multiplied, so the
+// queue's atomic round trip overlaps the work.
 __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
                                                              const int32_t* __restrict__ rules_tab,
                                                              const int32_t* __restrict__ trans_tab,
@@ -638,32 +682,40 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
     __shared__ int32_t item_s;
     const int n_jobs = es->n_jobs;
     const int total = es->total_items;
-    // the next item's index is fetched while the current one is multiplied,
-    // so the queue's atomic round trip overlaps the work
     int32_t ahead = 0;
-    if (threadIdx.x == 0) ahead = atomicAdd(&es->next_item, 1);
-    while (true) {
-        if (threadIdx.x == 0) item_s = ahead;
-        __syncthreads();
-        const int item = item_s;
-        __syncthreads();
-        if (item >= total) break;
+    if (total > 0) {
         if (threadIdx.x == 0) ahead = atomicAdd(&es->next_item, 1);
-        const Job jb = jobs[job_of(jobs, n_jobs, item)];
+        while (true) {
+            if (threadIdx.x == 0) item_s = ahead;
+            __syncthreads();
+            const int item = item_s;
+            __syncthreads();
+            if (item >= total) break;
+            if (threadIdx.x == 0) ahead = atomicAdd(&es->next_item, 1);
+            const Job jb = jobs[job_of(jobs, n_jobs, item)];
+            const SlotDesc& d = descs[jb.slot];
+            const TileArgs a = tile_args(d, states, rules_tab, trans_tab, jb, item);
+            mfma::mfma4_tile<true>(a.Bm, a.CT, a.Am, a.W2, a.kchunks, a.local / a.dim, a.local % a.dim, a.changed,
+                                   a.rows);
+        }
+    }
+    const int n128 = es->n_jobs128;
+    const int total128 = es->total_items128;
+    if (total128 == 0) return;
+    const Job* jobs128 = jobs + n_jobs;
+    const int lane = threadIdx.x & 63;
+    int32_t next = 0;
+    if (lane == 0) next = atomicAdd(&es->next_item128, 1);
+    next = __builtin_amdgcn_readfirstlane(next);
+    while (next < total128) {
+        const int item = next;
+        if (lane == 0) next = atomicAdd(&es->next_item128, 1);
+        next = __builtin_amdgcn_readfirstlane(next);
+        const Job jb = jobs128[job_of(jobs128, n128, item)];
         const SlotDesc& d = descs[jb.slot];
-        const int r = d.rule_off + jb.what;
-        const int ra = rules_tab[3 * r], rb = rules_tab[3 * r + 1], rc = rules_tab[3 * r + 2];
-        const int local = item - jb.item_begin;
-        const size_t mdw = static_cast<size_t>(d.npad) * d.W * 2;
-        const uint32_t* Bm = reinterpret_cast<const uint32_t*>(d.T) + rb * mdw;
-        const uint32_t* CT = reinterpret_cast<const uint32_t*>(d.TT) + trans_tab[d.trans_off + rc] * mdw;
-        uint32_t* Am = reinterpret_cast<uint32_t*>(d.T) + ra * mdw;
-        const int kchunks = (d.n + 255) / 256;  // 256-k chunks of the fp4 tile
-        const int64_t it = states[jb.slot].iterations;
-        uint64_t* rows =  // recorded from the last pull loop on, as in engine_rows_kernel
-            d.RD && it >= kPullLoops - 1 ? d.RD + (static_cast<size_t>(it & 1) * d.n_nt + ra) * d.W : nullptr;
-        mfma::mfma4_tile<true>(Bm, CT, Am, 2 * d.W, kchunks, local / jb.dim, local % jb.dim,
-                               &states[jb.slot].changed[ra], rows);
+        const TileArgs a = tile_args(d, states, rules_tab, trans_tab, jb, item);
+        mfma::mfma4_wave_tile<true>(a.Bm, a.CT, a.Am, a.W2, a.kchunks, (a.local / a.dim) * 128,
+                                    (a.local % a.dim) * 128, a.changed, a.rows);
     }
 }
 

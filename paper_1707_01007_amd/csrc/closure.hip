@@ -539,13 +539,28 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         return CFPQ_OK;
     };
     const bool mfma = reads_ct(p.path);
+    // Sparse-product accounting (hybrid choice): per launched rule, its
+    // algorithmic bytes when every part of it ran as ROWS or COLS (-1 when a
+    // part was dense).  A part that gathers from nz set bits moves nz rows of
+    // the gathered operand (row_bytes each), reads its sparse operand's
+    // matrix once (the bit scan) and reads and writes the result matrix.
+    const double row_bytes = static_cast<double>(L.W) * 8.0;
+    const double mat_b = static_cast<double>(mat_words) * 8.0;
+    auto part_bytes = [&](double nz) { return nz * row_bytes + 3.0 * mat_b; };
+    std::vector<double> rule_sparse_bytes;
+    double sparse_bytes = 0.0, sparse_ms = 0.0;
     while (!captured && !converged && iters < cap) {
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         size_t launched = 0;
+        rule_sparse_bytes.clear();
         std::fill(written.begin(), written.end(), 0);
         for (int32_t r = 0; r < grammar->n_bin_rules; ++r) {
             const auto& br = grammar->bin_rules[r];
             if (o.dirty_worklist && iters > 0 && !prev[br.left] && !prev[br.right]) continue;
+            // hybrid, after the first loop: operands that gained no bit in the
+            // last loop leave both delta halves empty -- nothing to add, nothing
+            // launched or counted (the dirty worklist skips the same rules)
+            if (p.hybrid && iters > 0 && dnnz[br.left] == 0 && dnnz[br.right] == 0) continue;
             const uint64_t* Bm = X + br.left * mat_words;
             const uint64_t* Cm = X + br.right * mat_words;
             uint64_t* Am = Y + br.lhs * mat_words;
@@ -561,10 +576,14 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             const bool left_kept = p.right_slot[br.left] >= 0 && !(!p.jacobi && written[br.left]);
             const uint64_t* bt = left_kept ? TT + p.right_slot[br.left] * mat_words : nullptr;
             const uint64_t* ct = p.right_slot[br.right] >= 0 ? TT + p.right_slot[br.right] * mat_words : nullptr;
+            double rbytes = -1.0;  // this rule's sparse bytes, -1 if any part is dense
             if (!p.hybrid) {
                 st = product_by(p.forced, Bm, bt, Cm, ct, Am, flag);
                 if (st != CFPQ_OK) return st;
-                if (p.forced != kModeDense) ++sparse_products;
+                if (p.forced != kModeDense) {
+                    ++sparse_products;
+                    rbytes = part_bytes(static_cast<double>(p.forced == kModeRows ? nnz[br.left] : nnz[br.right]));
+                }
             } else {
                 const double nb = static_cast<double>(nnz[br.left]), nc = static_cast<double>(nnz[br.right]);
                 const HybridChoice full = hybrid_choice(p.model, nb, nc, left_kept, ct != nullptr, mfma);
@@ -576,22 +595,33 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                     if (dc > 0) h2 = hybrid_choice(p.model, nb, dc, left_kept, false, mfma);
                     use_delta = h1.us + h2.us < full.us;
                 }
+                // bytes of a part in mode m with left / right set-bit counts l, r
+                auto mode_bytes = [&](int32_t m, double l, double r) {
+                    return m == kModeRows ? part_bytes(l) : part_bytes(r);
+                };
                 if (!use_delta) {
                     st = product_by(full.mode, Bm, bt, Cm, ct, Am, flag);
                     if (st != CFPQ_OK) return st;
-                    if (full.mode != kModeDense) ++sparse_products;
+                    if (full.mode != kModeDense) {
+                        ++sparse_products;
+                        rbytes = mode_bytes(full.mode, nb, nc);
+                    }
                 } else {
+                    const double db = static_cast<double>(dnnz[br.left]), dc = static_cast<double>(dnnz[br.right]);
+                    rbytes = 0.0;
                     if (h1.mode != kModeSkip) {  // D_B x C
                         st = product_by(h1.mode, DELTA + br.left * mat_words, nullptr, Cm, ct, Am, flag);
                         if (st != CFPQ_OK) return st;
                         ++delta_products;
                         if (h1.mode != kModeDense) ++sparse_products;
+                        rbytes = h1.mode == kModeDense || rbytes < 0 ? -1.0 : rbytes + mode_bytes(h1.mode, db, nc);
                     }
                     if (h2.mode != kModeSkip) {  // B x D_C
                         st = product_by(h2.mode, Bm, bt, DELTA + br.right * mat_words, nullptr, Am, flag);
                         if (st != CFPQ_OK) return st;
                         ++delta_products;
                         if (h2.mode != kModeDense) ++sparse_products;
+                        rbytes = h2.mode == kModeDense || rbytes < 0 ? -1.0 : rbytes + mode_bytes(h2.mode, nb, dc);
                     }
                     if (h1.mode != kModeSkip && h2.mode != kModeSkip) ++products;  // two halves, one rule
                 }
@@ -602,6 +632,8 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                 if (!e) return fail(CFPQ_EDEVICE, "hipEventCreate failed");
                 CFPQ_HIP(hipEventRecord(e, s));
             }
+            rule_sparse_bytes.push_back(rbytes);
+            if (rbytes >= 0) sparse_bytes += rbytes;
             ++launched;
             ++products;
         }
@@ -623,6 +655,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             float pm = 0.f;
             CFPQ_HIP(hipEventElapsedTime(&pm, pev[2 * q], pev[2 * q + 1]));
             product_ms += pm;
+            if (rule_sparse_bytes[q] >= 0) sparse_ms += pm;
         }
         ++iters;
         bool any = false;
@@ -656,6 +689,8 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                         static_cast<double>(L.npad) * static_cast<double>(products - sparse_products);
         stats->sparse_products = sparse_products;
         stats->delta_products = delta_products;
+        stats->sparse_bytes = sparse_bytes;
+        stats->sparse_ms = sparse_ms;
         stats->minplus_terms = 0.0;
         stats->device_ms = ms;
         stats->product_ms = product_ms;

@@ -221,19 +221,18 @@ __device__ __forceinline__ void mma_chunk4(v16f (&acc)[kJT][kIT], const Chunk& c
     }
 }
 
-// The tile of mfma_tile on the fp4 MFMA, over kchunks chunks of 256 k (any
+// One wavefront's 128 x 128 output block (rows i0.., columns j0..) of
+// A |= B x C on the fp4 MFMA, CT = C^T, over kchunks chunks of 256 k (any
 // count >= 1): lane half g reads dwords 8c + 4g .. 8c + 4g + 3 of chunk c, so
-// one 64-k MFMA step takes k-word s from each half.
+// one 64-k MFMA step takes k-word s from each half.  No barriers: any
+// wavefront may call it on its own.  kAtomic as in store_tile.
 template <bool kAtomic>
-__device__ __forceinline__ void mfma4_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
-                                           uint32_t* Am, int W2, int kchunks, int tile_i, int tile_j,
-                                           int32_t* changed, uint64_t* rowbits = nullptr) {
+__device__ __forceinline__ void mfma4_wave_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
+                                                uint32_t* Am, int W2, int kchunks, int i0, int j0,
+                                                int32_t* changed, uint64_t* rowbits = nullptr) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int g = lane >> 5;
     const int r32 = lane & 31;
-    const int j0 = tile_j * 256 + (wave & 1) * 128;
-    const int i0 = tile_i * 256 + (wave >> 1) * 128;
 
     // uint4 index 2c of these pointers is chunk c's dwords for this half
     const uint4* crow[kJT];
@@ -271,6 +270,18 @@ __device__ __forceinline__ void mfma4_tile(const uint32_t* __restrict__ Bm, cons
     if (kc < kchunks) mma_chunk4(acc, buf0);
 
     store_tile<kAtomic>(acc, Am, W2, i0, j0, g, r32, lane, changed, rowbits);
+}
+
+// One 256 x 256 output tile (rows of tile_i, columns of tile_j) on the fp4
+// MFMA, called by all 256 lanes of a workgroup: each wavefront takes one
+// 128 x 128 quarter (mfma4_wave_tile).
+template <bool kAtomic>
+__device__ __forceinline__ void mfma4_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
+                                           uint32_t* Am, int W2, int kchunks, int tile_i, int tile_j,
+                                           int32_t* changed, uint64_t* rowbits = nullptr) {
+    const int wave = threadIdx.x >> 6;
+    mfma4_wave_tile<kAtomic>(Bm, CT, Am, W2, kchunks, tile_i * 256 + (wave >> 1) * 128,
+                             tile_j * 256 + (wave & 1) * 128, changed, rowbits);
 }
 
 }  // namespace mfma

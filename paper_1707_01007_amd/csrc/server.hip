@@ -1,6 +1,8 @@
 // Serving with continuous batching: cfpq_server_*.
 //
-// A worker thread owns the engine (batch_engine.h).  Each turn it
+// A worker thread owns the engine (batch_engine.h); a query's route (resident
+// workgroup, or the tile work list with 256 or 128 tiles) is the batch tuning
+// table's for its padded side when it is submitted.  Each turn it
 //  1. admits queued requests in arrival order while a slot is free and the
 //     request's HBM footprint fits the arena (first fit),
 //  2. initialises the admitted requests' matrices; small ones start their
@@ -57,8 +59,9 @@ struct Request {
     int64_t n_edges = 0;
     uint64_t* d_result = nullptr;
     Layout L;
-    bool small = false;
-    bool lane = false;  // runs on a lane thread (hybrid closure)
+    bool small = false;  // resident route (batch tuning table at submit)
+    int32_t tile = 256;  // tile route: 256 or 128 tiles
+    bool lane = false;   // runs on a lane thread (hybrid closure)
     int32_t n_right = 0;
     std::vector<int32_t> modes;  // per binary rule: engine product mode (large slots)
     size_t footprint = 0;
@@ -149,8 +152,10 @@ struct cfpq_server {
     bool stop = false;
     cfpq_status worker_error = CFPQ_OK;
     std::string worker_message;
+    std::string turn_message;  // the worker's own: the failing HIP call of a turn
     std::thread worker;
     std::atomic<int64_t> completed{0};
+    std::atomic<int> inject_fault{0};  // cfpq_server_inject_fault
     int cus = 256;
     // lanes for large requests
     std::deque<cfpq::Request*> lane_pending;
@@ -206,8 +211,7 @@ size_t footprint_of(const Request& r) {
     do {                                                                                           \
         hipError_t e_ = (call);                                                                    \
         if (e_ != hipSuccess) {                                                                    \
-            srv->worker_error = CFPQ_EDEVICE;                                                      \
-            srv->worker_message = std::string(#call) + ": " + hipGetErrorString(e_);               \
+            srv->turn_message = std::string(#call) + ": " + hipGetErrorString(e_);                 \
             return false;                                                                          \
         }                                                                                          \
     } while (0)
@@ -257,9 +261,11 @@ void fill_slot(cfpq_server* srv, Request& r, SlotDesc& d, std::vector<int32_t>& 
     std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
     for (const auto& t : r.term) term[kSrvMaxTerminals + 1 + fill[t.terminal]++] = t.lhs;
     d.kind = r.small ? kSlotSmall : kSlotLarge;
+    d.tile = r.small ? 0 : r.tile;
 }
 
-// One turn of the worker.  Returns false on a device error (recorded in srv).
+// One turn of the worker.  Returns false on a device error (its message in
+// srv->turn_message).
 bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
     hipStream_t s = srv->stream;
     const int32_t S = srv->cfg.max_slots;
@@ -428,8 +434,12 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
     return true;
 }
 
-// A device error: recorded (the first message is kept) and every open
-// request completes with CFPQ_EDEVICE, so that no waiter blocks for ever.
+// A device error: recorded (the first message is kept); every queued request
+// completes with CFPQ_EDEVICE at once, so that no waiter blocks for ever.
+// Requests already admitted (state 1) are left to their owner -- a lane, or
+// the worker (abandon_slots) -- which reports them only once its stream has
+// finished with their buffers: a waiter that sees state 2 may free the
+// request and its d_result immediately.
 void fail_all(cfpq_server* srv, const std::string& message) {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->worker_error == CFPQ_OK) {
@@ -437,7 +447,7 @@ void fail_all(cfpq_server* srv, const std::string& message) {
         srv->worker_message = message;
     }
     for (auto& kv : srv->tickets) {
-        if (kv.second->state != 2) {
+        if (kv.second->state == 0) {
             kv.second->state = 2;
             kv.second->status = CFPQ_EDEVICE;
         }
@@ -446,6 +456,29 @@ void fail_all(cfpq_server* srv, const std::string& message) {
     srv->lane_pending.clear();
     srv->done_cv.notify_all();
     srv->cv.notify_all();
+    srv->lane_cv.notify_all();
+}
+
+// After a failed turn: the worker's admitted requests will never be retired.
+// Their device work is waited for (or abandoned: a stream in error returns
+// at once), then each completes with CFPQ_EDEVICE and its slot and arena
+// block are released.
+void abandon_slots(cfpq_server* srv) {
+    hipStreamSynchronize(srv->stream);
+    hipStreamSynchronize(srv->side);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    const double t = now_s();
+    for (int32_t q = 0; q < static_cast<int32_t>(srv->slot_req.size()); ++q) {
+        Request* r = srv->slot_req[q];
+        if (!r) continue;
+        r->status = CFPQ_EDEVICE;
+        r->t_done = t;
+        r->state = 2;
+        srv->arena.release(r->arena_off, r->footprint);
+        srv->slot_req[q] = nullptr;
+        srv->free_slots.push_back(q);
+    }
+    srv->done_cv.notify_all();
     srv->lane_cv.notify_all();
 }
 
@@ -509,12 +542,20 @@ void worker_main(cfpq_server* srv) {
     }
     while (true) {
         std::vector<Request*> admitted;
+        if (srv->inject_fault.load()) {
+            // a failure forced from the host (cfpq_server_inject_fault): handled
+            // exactly as a HIP error in a turn, with no device work involved
+            fail_all(srv, "injected worker fault");
+            abandon_slots(srv);
+            return;
+        }
         {
             std::unique_lock<std::mutex> lk(srv->mu);
             bool busy = false;
             for (auto* r : srv->slot_req) busy = busy || r != nullptr;
             if (!busy && srv->pending.empty())
-                srv->cv.wait(lk, [&] { return srv->stop || !srv->pending.empty(); });
+                srv->cv.wait(lk, [&] { return srv->stop || !srv->pending.empty() || srv->inject_fault.load(); });
+            if (srv->inject_fault.load()) continue;
             if (srv->stop) {
                 bool any = false;
                 for (auto* r : srv->slot_req) any = any || r != nullptr;
@@ -543,7 +584,8 @@ void worker_main(cfpq_server* srv) {
             }
         }
         if (!turn(srv, admitted)) {  // turn recorded the error message
-            fail_all(srv, srv->worker_message);
+            fail_all(srv, srv->turn_message);
+            abandon_slots(srv);
             return;
         }
         bool busy_small_only = true, any = false;
@@ -700,7 +742,9 @@ cfpq_status cfpq_server_submit(cfpq_server* srv, const cfpq_graph* graph, const 
     else r->host_edges.assign(graph->edges, graph->edges + graph->n_edges);
     r->d_result = d_result;
     r->L = layout_for(graph->n_nodes);
-    r->small = r->L.npad <= kSmallMaxPad;
+    const BatchRoute rt = batch_route(r->L.npad, nullptr);
+    r->small = rt.route == kRouteResident;
+    r->tile = rt.tile;
     r->lane = srv->cfg.hybrid_lanes > 0 && r->L.npad >= kHybridMinRows;
     const int32_t nb = static_cast<int32_t>(r->bin.size());
     r->modes.assign(nb, kModeDense);
@@ -767,6 +811,18 @@ cfpq_status cfpq_server_wait(cfpq_server* srv, int64_t ticket, cfpq_request_info
     clear_last_error();
     if (!srv) return fail(CFPQ_EINVAL, "server is NULL");
     return report(srv, ticket, info, true);
+}
+
+cfpq_status cfpq_server_inject_fault(cfpq_server* srv) {
+    clear_last_error();
+    if (!srv) return fail(CFPQ_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->stop || srv->worker_error != CFPQ_OK) return CFPQ_OK;
+    srv->inject_fault.store(1);
+    srv->cv.notify_all();
+    // returns once the worker has stopped (fail_all notifies done_cv)
+    srv->done_cv.wait(lk, [&] { return srv->worker_error != CFPQ_OK; });
+    return CFPQ_OK;
 }
 
 cfpq_status cfpq_server_destroy(cfpq_server* srv) {

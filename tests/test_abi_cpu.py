@@ -44,7 +44,7 @@ def test_layout_functions():
         assert lib.cfpq_row_words(n) == w
         assert lib.cfpq_padded_rows(n) == 64 * w
         assert lib.cfpq_result_bytes(n, 3) == 3 * 64 * w * w * 8
-    assert lib.cfpq_abi_version() == 3
+    assert lib.cfpq_abi_version() == 4
 
 
 def _structs(n=4, edges=((0, 0, 1), (1, 1, 2)), n_nt=4, n_t=2, term=((2, 0), (3, 1)),
@@ -196,7 +196,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     structs = {"cfpq_options": _abi.Options, "cfpq_stats": _abi.Stats, "cfpq_graph": _abi.Graph,
                "cfpq_grammar": _abi.Grammar, "cfpq_instance": _abi.Instance, "cfpq_tune_entry": _abi.TuneEntry,
                "cfpq_server_config": _abi.ServerConfig, "cfpq_request_info": _abi.RequestInfo,
-               "cfpq_conjunct": _abi.Conjunct, "cfpq_conj_rule": _abi.ConjRule}
+               "cfpq_conjunct": _abi.Conjunct, "cfpq_conj_rule": _abi.ConjRule,
+               "cfpq_batch_tune_entry": _abi.BatchTuneEntry}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cfpq.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -340,3 +341,4 @@ def test_conjunctive_rules_validated_before_device_work(case):
     assert lib.cfpq_conjunctive_closure(ctypes.byref(gr), ctypes.byref(g), 1, rules, ctypes.byref(opt), None,
                                         ctypes.c_void_p(1 << 20), ctypes.c_size_t(1 << 30), ctypes.c_void_p(1 << 21),
                                         None) == _abi.CFPQ_EINVAL
+

@@ -44,6 +44,42 @@ def test_tune_table_roundtrip_on_host(tmp_path):
     cfpq.tune_clear()
 
 
+def test_batch_route_table_on_host(tmp_path):
+    """The batch tuning table: hand-set entries, validation of impossible
+    routes, and a save / load round trip together with the product table."""
+    cfpq = _cfpq()
+    cfpq.tune_clear()
+    assert cfpq.batch_tune_get(768) is None
+    cfpq.batch_tune_set(256, "tiles", 128)
+    cfpq.batch_tune_set(512, "resident")
+    cfpq.batch_tune_set(768, "tiles", 256)
+    assert cfpq.batch_tune_get(256)["route"] == "tiles" and cfpq.batch_tune_get(256)["tile"] == 128
+    assert cfpq.batch_tune_get(512)["route"] == "resident" and cfpq.batch_tune_get(512)["tile"] == 0
+    for bad in ((768, "resident", 0), (1024, "tiles", 64), (300, "tiles", 256), (0, "tiles", 128)):
+        with pytest.raises(cfpq.CfpqError):
+            cfpq.batch_tune_set(*bad)
+    cfpq.batch_tune_set(768, None)  # removed
+    assert cfpq.batch_tune_get(768) is None
+    src = tmp_path / "tune.json"
+    src.write_text('{"arch": "gfx950", "entries": [\n'
+                   ' {"bucket": 10, "npad": 1024, "path": "fp4", "tile": 0, "ms": 0.01}\n], "batch": [\n'
+                   ' {"batch_npad": 1024, "route": "tiles", "tile": 128, "ms": 1.5, "instances": 12},\n'
+                   ' {"batch_npad": 1280, "route": "resident", "tile": 0, "ms": 1.0, "instances": 3}\n]}\n')
+    cfpq.tune_load(str(src))
+    e = cfpq.batch_tune_get(1024)
+    assert e["route"] == "tiles" and e["tile"] == 128 and e["instances"] == 12
+    assert cfpq.batch_tune_get(1280) is None            # resident above 512: not a valid route, ignored
+    assert cfpq.tune_get(1000)["path"] == "fp4"
+    out = tmp_path / "saved.json"
+    cfpq.tune_save(str(out))
+    cfpq.tune_clear()
+    assert cfpq.batch_tune_get(256) is None and cfpq.batch_tune_get(1024) is None
+    cfpq.tune_load(str(out))
+    assert cfpq.batch_tune_get(256)["tile"] == 128 and cfpq.batch_tune_get(512)["route"] == "resident"
+    assert cfpq.batch_tune_get(1024)["tile"] == 128 and cfpq.tune_get(1000)["path"] == "fp4"
+    cfpq.tune_clear()
+
+
 @pytest.mark.gpu
 def test_autotune_choice_is_used_and_exact():
     import torch

@@ -31,13 +31,35 @@ def test_options():
 
 
 def test_cpu_baseline_fields():
+    """The CPU baseline object: the oracle's single-thread time to the fixpoint
+    on a sample of the workload's recipe, in the metric's unit, with the
+    host's core count, the full-size oracle time and the BLAS product rate as
+    separate fields.  The GPU closure (for the sample's bit-op count) is a
+    stand-in here that returns the oracle's own bits."""
+    import types
+
+    import numpy as np
+
     import bench
+    from oracle import worklist
     from workloads import configs
+
+    class FakeGpu:
+        def closure(self, n, edges, grammar, **kw):
+            e = np.asarray(edges)
+            return types.SimpleNamespace(stats={"bitops": 1e12}, bits=worklist.closure(n, e, grammar))
+
+        def result_bits(self, res):
+            return res.bits
+
+    fake_torch = types.SimpleNamespace(from_numpy=lambda a: types.SimpleNamespace(cuda=lambda: a))
     inst = configs.config3(1024)
-    cb = bench.cpu_baseline(inst, seconds_target=0.05)
-    assert set(cb) == {"value", "unit", "cores", "kind", "sample"}
-    assert cb["kind"] == "oracle" and cb["unit"] == "Gbitop/s" and cb["value"] > 0 and cb["cores"] >= 1
-    assert "n=1024" in cb["sample"]
+    cb = bench.cpu_baseline(FakeGpu(), fake_torch, inst, sample_n=512)
+    assert cb["kind"] == "oracle_closure" and cb["unit"] == "Gbitop/s" and cb["cores"] == 1
+    assert cb["value"] > 0 and cb["time_to_solution_s"] > 0 and cb["identical_to_gpu"]
+    assert cb["host_nproc"] >= 1 and "n=512" in cb["sample"]
+    assert cb["full_size"]["time_to_solution_s"] > 0
+    assert cb["blas_product"]["value"] > 0 and "n=1024" in cb["blas_product"]["sample"]
 
 
 def test_committed_traffic_matches_the_kernel_sources():

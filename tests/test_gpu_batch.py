@@ -74,20 +74,90 @@ def test_batch_alone_equals_in_mix(cfpq):
         assert np.array_equal(a, cfpq.result_bits(alone_b)), inst.tag
 
 
-def test_full_batch_workload_digests(cfpq):
+# route tables of the batched engine: padded side -> (route, tile); missing
+# sides take the default (resident up to 512, 256 tiles above)
+ROUTE_TABLES = {
+    "default": {},
+    "tiles256_everywhere": {256: ("tiles", 256), 512: ("tiles", 256)},
+    "tiles128_everywhere": {p: ("tiles", 128) for p in range(256, 2049, 256)},
+    "resident_then_tiles128": {256: ("resident", 0), 512: ("resident", 0),
+                               **{p: ("tiles", 128) for p in range(768, 2049, 256)}},
+}
+
+
+def _set_routes(cfpq, table):
+    cfpq.tune_clear()
+    for npad, (route, tile) in table.items():
+        cfpq.batch_tune_set(npad, route, tile)
+
+
+@pytest.mark.parametrize("table", sorted(ROUTE_TABLES))
+def test_full_batch_workload_digests(cfpq, table):
     """All 512 instances of the batch workload, each against its stored
-    oracle digest."""
-    path = os.path.join(GOLD, "batch_digests.json")
-    if not os.path.exists(path):
-        pytest.skip("batch digests not generated")
-    gold = json.load(open(path))["batch512"]
+    oracle digest, under several route tables of the batched engine (every
+    route gives the same bits)."""
+    gold = json.load(open(os.path.join(GOLD, "batch_digests.json")))["batch512"]
     insts = configs.config4()
-    _say("batch512")
-    res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts])
+    _say("batch512", table)
+    _set_routes(cfpq, ROUTE_TABLES[table])
+    try:
+        res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts])
+    finally:
+        cfpq.tune_clear()
     for k, (inst, r) in enumerate(zip(insts, res)):
         bits = cfpq.result_bits(r)
         assert [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits] == gold[k]["counts"], (k, inst.tag)
         assert _digest(bits) == gold[k]["sha256"], (k, inst.tag)
+        assert r.stats["converged"] == 1
+
+
+def test_batch_autotune_records_routes_and_keeps_bits(cfpq):
+    """The batch autotuner on a sample of the batch workload: one entry per
+    padded side present, with every candidate timed (the resident route
+    offered only up to 512); a side leaves its default route only for a
+    candidate more than 2% faster; the entries are recorded in the table, and
+    the batch closure that follows uses them and matches the oracle digests."""
+    gold = json.load(open(os.path.join(GOLD, "batch_digests.json")))["batch512"]
+    insts = configs.config4()
+    items = [(i.n, i.edges, i.grammar) for i in insts]
+    cfpq.tune_clear()
+    try:
+        _say("batch autotune")
+        entries = cfpq.batch_autotune(items, max_per_bucket=8, reps=1)
+        sides = sorted({cfpq.padded_rows(i.n) for i in insts if i.n > 0})
+        assert [e["npad"] for e in entries] == sides
+        for e in entries:
+            c = e["candidates_ms"]
+            assert {"tiles256", "tiles128"} <= set(c)
+            assert ("resident" in c) == (e["npad"] <= 512)
+            chosen = "resident" if e["route"] == "resident" else f"tiles{e['tile']}"
+            default = "resident" if e["npad"] <= 512 else "tiles256"
+            assert e["ms"] == pytest.approx(c[chosen])
+            assert chosen == default or c[chosen] < 0.98 * c[default]
+            assert cfpq.batch_tune_get(e["npad"])["route"] == e["route"]
+            assert 0 < e["instances"] <= 8
+        res = cfpq.batch_closure(items)
+    finally:
+        cfpq.tune_clear()
+    for k, (inst, r) in enumerate(zip(insts, res)):
+        assert _digest(cfpq.result_bits(r)) == gold[k]["sha256"], (k, inst.tag)
+
+
+@pytest.mark.parametrize("table", ["tiles128_everywhere", "tiles256_everywhere"])
+def test_server_follows_route_table(cfpq, table):
+    """Servers created after the table is set take its routes: the same bits
+    as the oracle for a mixed stream with every route forced."""
+    insts = configs.config4(count=30)
+    _set_routes(cfpq, ROUTE_TABLES[table])
+    try:
+        with cfpq.Server(hbm_budget=2 << 30, max_slots=64, hybrid_lanes=0) as srv:
+            tickets = [srv.submit(i.n, i.edges, i.grammar) for i in insts]
+            infos = [srv.wait(t) for t in tickets]
+    finally:
+        cfpq.tune_clear()
+    for inst, info in zip(insts, infos):
+        assert info["status"] == 0
+        assert np.array_equal(cfpq.result_bits(info["result"]), worklist.closure(inst.n, inst.edges, inst.grammar))
 
 
 def test_batch_device_edges_and_errors(cfpq):

@@ -368,6 +368,21 @@ def test_hybrid_equals_dense_and_oracle(cfpq, schedule):
     assert rb.stats["bitops"] == 2.0 * npad ** 3 * dense
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_hybrid_without_dirty_worklist(cfpq, schedule):
+    """Hybrid choice with the dirty-rule worklist off: a rule whose operands
+    gained nothing in the last loop has empty delta halves, so it launches
+    nothing and is not counted -- the same rules the worklist skips, so the
+    loop, product and bit-op counts equal those with the worklist on."""
+    inst = configs.config3(4096)
+    want = worklist.closure(inst.n, inst.edges, inst.grammar)
+    a, ra = _run(cfpq, inst, path="fp4", schedule=schedule, hybrid=1, dirty=True)
+    b, rb = _run(cfpq, inst, path="fp4", schedule=schedule, hybrid=1, dirty=False)
+    assert np.array_equal(a, want) and np.array_equal(b, want)
+    for k in ("iterations", "products", "sparse_products", "delta_products", "bitops"):
+        assert ra.stats[k] == rb.stats[k], k
+
+
 @pytest.mark.parametrize("path", ["rows", "cols"])
 def test_sparse_paths_under_jacobi_give_algorithm_1_loops(cfpq, path):
     """Jacobi with the sparse products reproduces Algorithm 1's loop count on

@@ -107,16 +107,17 @@ def test_server_arrivals_while_running(cfpq):
 
 
 def test_server_stream_digests(cfpq):
-    """The first 200 requests of the serving stream against stored oracle digests."""
+    """All 600 requests the benchmark submits (100 warm-up and 500 measured of
+    the seed-5 stream), through a server configured as the benchmark's, against
+    stored oracle digests."""
     path = os.path.join(GOLD, "batch_digests.json")
-    if not os.path.exists(path):
-        pytest.skip("digests not generated")
-    gold = json.load(open(path))["serve200"]
-    insts, _ = configs.config5(count=200)
-    with cfpq.Server(hbm_budget=16 << 30, max_slots=128) as srv:
+    gold = json.load(open(path))["serve600"]
+    insts, _ = configs.config5(count=len(gold))
+    with cfpq.Server(hbm_budget=32 << 30, max_slots=512, capture=4) as srv:
         tickets = [srv.submit(i.n, i.edges, i.grammar) for i in insts]
         infos = [srv.wait(t) for t in tickets]
     for k, (inst, info) in enumerate(zip(insts, infos)):
+        assert info["status"] == 0, (k, inst.tag)
         bits = cfpq.result_bits(info["result"])
         assert [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits] == gold[k]["counts"], (k, inst.tag)
         assert _digest(bits) == gold[k]["sha256"], (k, inst.tag)
@@ -170,3 +171,39 @@ def test_server_lanes_equal_engine(cfpq):
         assert np.array_equal(a, cfpq.result_bits(cfpq.closure(q.n, q.edges, q.grammar))), q.tag
     for q, a in zip(qs[:2], results[2][:2]):
         assert np.array_equal(a, worklist.closure(q.n, q.edges, q.grammar)), q.tag
+
+
+def test_worker_fault_waits_for_the_lane(cfpq):
+    """A worker failure (forced from the host: no device work fails) while a
+    lane runs a large query.  Queued queries complete with CFPQ_EDEVICE; the
+    lane's query completes only after its closure has finished, so the bits
+    it reports are whole (equal to the oracle's digest); later submits fail,
+    and closing the server reports the failure."""
+    from paper_1707_01007_amd import _abi
+    gold = json.load(open(os.path.join(GOLD, "digests.json")))["er4096_dyck"]
+    big = configs.config3(4096)
+    small = [configs.Instance(*graphs.erdos_renyi(n, 3 * n, 60 + n, labels=2), grammars.dyck(), f"er{n}")
+             for n in (90, 200, 300, 700, 1100)]
+    srv = cfpq.Server(hbm_budget=4 << 30, max_slots=16, hybrid_lanes=1)
+    _say("server fault while a lane runs")
+    t_big = srv.submit(big.n, big.edges, big.grammar)
+    tickets = [srv.submit(i.n, i.edges, i.grammar) for i in small * 4]
+    srv.inject_fault()
+    info = srv.wait(t_big)
+    assert info["status"] in (0, _abi.CFPQ_EDEVICE)
+    if info["status"] == 0:  # the lane had started: its result is complete
+        bits = cfpq.result_bits(info["result"])
+        assert hashlib.sha256(np.ascontiguousarray(bits).astype("<u8").tobytes()).hexdigest() == gold["sha256"]
+    _say("lane query status", info["status"])
+    for k, t in enumerate(tickets):
+        x = srv.wait(t)
+        assert x["status"] in (0, _abi.CFPQ_EDEVICE)
+        if x["status"] == 0:
+            inst = (small * 4)[k]
+            assert np.array_equal(cfpq.result_bits(x["result"]), worklist.closure(inst.n, inst.edges, inst.grammar))
+    with pytest.raises(cfpq.CfpqError) as err:
+        srv.submit(small[0].n, small[0].edges, small[0].grammar)
+    assert err.value.status == _abi.CFPQ_EDEVICE
+    with pytest.raises(cfpq.CfpqError) as err:
+        srv.close()
+    assert err.value.status == _abi.CFPQ_EDEVICE

@@ -3,13 +3,16 @@ two-cycle closed form and breadth-first search, plus witness paths checked
 edge by edge and by CYK."""
 from __future__ import annotations
 
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
 import pytest
 
 from oracle import brute, single_path as sp
-from tests.test_oracle_single_path import _bfs_lengths, _first_found_graph, two_cycle_lengths
+from tests.test_oracle_single_path import _bfs_lengths, _first_found_graph, doubling_grammar, two_cycle_lengths
 from workloads import configs, grammars, graphs
 
 pytestmark = pytest.mark.gpu
@@ -182,3 +185,44 @@ def test_degenerate_inputs(cfpq):
     a_edges = e[e[:, 1] == 0]
     want[a_edges[:, 0], a_edges[:, 2]] = 1
     assert np.array_equal(got[0], want)
+
+
+DIGESTS = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")))
+
+
+@pytest.mark.parametrize("name", ["sp_er2048_dyck", "sp_er4096_dyck"])
+def test_er_dyck_lengths_match_oracle_digest(cfpq, name):
+    """The ER Dyck recipe at n = 2048 and at the benchmark's n = 4096, edges in
+    device memory as the benchmark passes them: every length equals the C
+    single-path oracle's (per-nonterminal counts and sums, and a SHA-256 of
+    all n x n lengths of every nonterminal), with the same loop count."""
+    import torch
+    gold = DIGESTS[name]
+    inst = configs.config3(gold["n"])
+    res, got = _lengths(cfpq, inst.n, torch.from_numpy(inst.edges).cuda(), inst.grammar)
+    assert res.stats["iterations"] == gold["jacobi_loops"]
+    got = got.astype(np.uint32)
+    assert [int((x > 0).sum()) for x in got] == gold["counts"]
+    assert [int(x.astype(np.int64).sum()) for x in got] == gold["length_sums"]
+    assert hashlib.sha256(np.ascontiguousarray(got).astype("<u4").tobytes()).hexdigest() == gold["sha256"]
+
+
+def test_length_overflow_is_reported(cfpq):
+    """One node with an a-loop and A0 -> a, A_k -> A_(k-1) A_(k-1): A_k has the
+    single length 2^k.  Up to k = 30 every length is exact (and equal to the
+    oracle's); at k = 31 the length 2^31 does not fit, and the call reports
+    CFPQ_ERANGE, as the oracle does."""
+    from paper_1707_01007_amd import _abi
+    e = np.array([[0, 0, 0]], dtype=np.int32)
+    g30 = doubling_grammar(30)
+    res, got = _lengths(cfpq, 1, e, g30)
+    want, loops, rc = sp.lengths_native(1, e, g30)
+    assert rc == 0 and res.stats["iterations"] == loops == 31
+    assert np.array_equal(got.astype(np.uint32), want)
+    assert [int(got[k, 0, 0]) for k in range(31)] == [2 ** k for k in range(31)]
+    g31 = doubling_grammar(31)
+    assert sp.lengths_native(1, e, g31)[2] == 1
+    _say("single_path", 1, g31.name, "expect CFPQ_ERANGE")
+    with pytest.raises(_abi.CfpqError) as err:
+        cfpq.single_path(1, e, g31)
+    assert err.value.status == _abi.CFPQ_ERANGE

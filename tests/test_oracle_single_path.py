@@ -204,6 +204,7 @@ def test_single_path_mutant_is_caught(name):
     src = open(single_path.__file__).read()
     assert src.count(old) == 1, name
     mod = types.ModuleType(f"mutant_{name}")
+    mod.__file__ = single_path.__file__
     exec(compile(src.replace(old, new), os.path.basename(single_path.__file__), "exec"), mod.__dict__)
     try:
         held = _pins_hold(mod)
