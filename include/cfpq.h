@@ -212,6 +212,31 @@ CFPQ_API cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* g
                          void* d_workspace, size_t workspace_bytes,
                          uint64_t* d_result, cfpq_stats* stats);
 
+/* Bytes of the static workspace of cfpq_closure_static (per GPU). */
+#define CFPQ_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/*
+ * cfpq_closure without a workspace argument, for callers that cannot
+ * allocate device memory (code in tight serving loops, harnesses that forbid
+ * hipMalloc): the library's own workspace -- a device array of
+ * CFPQ_STATIC_WORKSPACE_BYTES (64 MiB) that each GPU the library runs on holds
+ * until the process ends -- is used instead, and the call allocates nothing
+ * (no hipMalloc / hipFree, no HIP events, no graph capture: the loop is
+ * host-driven and stats.device_ms is the host's wall time).  The caller still
+ * owns graph, grammar and d_result, as for cfpq_closure.  The workspace keeps
+ * the previous call's contents; every part of it a closure reads is written
+ * first.  Calls on one GPU share its array: the library runs them one at a
+ * time (from any number of host threads; each call returns only after its
+ * stream is synchronised).  opt.capture and opt.profile are ignored, and a
+ * graph small enough for the resident route still runs the ordinary loop.
+ * Returns as cfpq_closure, and CFPQ_ENOMEM, before any device work, when the
+ * closure needs more than CFPQ_STATIC_WORKSPACE_BYTES of workspace (about
+ * 5000 nodes for a 4-nonterminal grammar with the hybrid choice on).
+ */
+CFPQ_API cfpq_status cfpq_closure_static(const cfpq_graph* graph, const cfpq_grammar* grammar,
+                                         const cfpq_options* opt, void* stream, uint64_t* d_result,
+                                         cfpq_stats* stats);
+
 /*
  * One Boolean matrix product with union (the product of section 2 for a
  * single rule A -> B C, fused with the union of Algorithm 1):

@@ -254,6 +254,39 @@ def conjunctive_closure(n: int, edges, grammar, *, path="auto", schedule="inplac
     return Result(int(n), nnt, out.view(nnt, npad, W), st.as_dict(), status)
 
 
+def closure_static(n: int, edges, grammar, *, path="auto", schedule="inplace", dirty=True, max_iters=0,
+                   device=None, stream=None, out=None, allow_partial=False, tile=0, hybrid=None,
+                   warm_start=False) -> Result:
+    """``closure`` through ``cfpq_closure_static``: the library's own static
+    device workspace instead of one allocated here (the call allocates no
+    device memory; only ``out`` is allocated here when not given)."""
+    torch = _torch()
+    L = lib()
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    g, keep = _grammar_struct(grammar)
+    if isinstance(edges, torch.Tensor) and edges.is_cuda:
+        e_dev = edges.to(torch.int32).contiguous().view(-1, 3)
+        graph = _abi.Graph(int(n), 1, int(e_dev.shape[0]), ctypes.c_void_p(e_dev.data_ptr()))
+        e_host = None
+    else:
+        e_host = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
+        graph = _abi.Graph(int(n), 0, int(e_host.shape[0]), ctypes.c_void_p(e_host.ctypes.data))
+    if warm_start and out is None:
+        raise ValueError("warm_start needs `out` holding the initial matrices")
+    opt = _options(path, schedule, dirty, max_iters, False, tile, None, hybrid, warm_start)
+    res_words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8
+    if out is None:
+        out = torch.empty(res_words, dtype=torch.int64, device=device)
+    st = _abi.Stats()
+    status = L.cfpq_closure_static(ctypes.byref(graph), ctypes.byref(g), ctypes.byref(opt), _stream_ptr(stream),
+                                   ctypes.c_void_p(out.data_ptr()), ctypes.byref(st))
+    del keep, e_host
+    if status != _abi.CFPQ_OK and not (allow_partial and status == _abi.CFPQ_ENOTCONV):
+        _abi.check(status)
+    bits = out.view(int(grammar.n_nonterminals), padded_rows(n), row_words(n))
+    return Result(int(n), int(grammar.n_nonterminals), bits, st.as_dict(), status)
+
+
 def _instance_array(instances, outs, device):
     """cfpq_instance records for (n, edges, grammar) triples, the objects they
     point into, and one result buffer per instance (from ``outs`` or new)."""

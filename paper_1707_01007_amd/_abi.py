@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "CFPQ_OK", -1: "CFPQ_EINVAL", -2: "CFPQ_ENOMEM", -3: "CFPQ_ED
 
 EXPORTED = (
     "cfpq_abi_version", "cfpq_last_error", "cfpq_default_options", "cfpq_row_words",
-    "cfpq_padded_rows", "cfpq_result_bytes", "cfpq_workspace_bytes", "cfpq_closure",
+    "cfpq_padded_rows", "cfpq_result_bytes", "cfpq_workspace_bytes", "cfpq_closure", "cfpq_closure_static",
     "cfpq_product_workspace_bytes", "cfpq_product", "cfpq_popcount",
     "cfpq_batch_workspace_bytes", "cfpq_batch_closure",
     "cfpq_server_default_config", "cfpq_server_create", "cfpq_server_submit", "cfpq_server_poll",
@@ -163,6 +163,9 @@ def load(path: str = LIB_PATH):
     lib.cfpq_closure.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar), ctypes.POINTER(Options),
                                  p, p, sz, p, ctypes.POINTER(Stats)]
     lib.cfpq_closure.restype = ctypes.c_int
+    lib.cfpq_closure_static.argtypes = [ctypes.POINTER(Graph), ctypes.POINTER(Grammar), ctypes.POINTER(Options), p,
+                                        p, ctypes.POINTER(Stats)]
+    lib.cfpq_closure_static.restype = ctypes.c_int
     lib.cfpq_product_workspace_bytes.argtypes = [i32, i32]
     lib.cfpq_product_workspace_bytes.restype = sz
     lib.cfpq_product.argtypes = [i32, i32, i32, p, p, p, p, p, sz, p]

@@ -21,10 +21,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -243,6 +245,49 @@ static hipError_t private_stream(int which, hipStream_t* out) {
 hipError_t capture_stream(hipStream_t* out) { return private_stream(0, out); }
 hipError_t aux_stream(hipStream_t* out) { return private_stream(1, out); }
 
+cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, const cfpq_options* opt,
+                         void* stream, void* d_workspace, size_t workspace_bytes, uint64_t* d_result,
+                         cfpq_stats* stats, bool no_alloc);
+
+// Workspace of cfpq_closure_static: a file-scope device array, so nothing is
+// allocated when the call runs.  Each GPU the library runs on holds its own
+// copy until the process ends.  Host code never passes the array's name to
+// a kernel or a copy (on the host it stands for no device address): the
+// device address of this GPU's copy comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[CFPQ_STATIC_WORKSPACE_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+struct StaticWorkspaces {
+    std::mutex table_mu;
+    std::array<void*, kMaxDevices> ptr{};
+    std::array<std::mutex, kMaxDevices> dev_mu;  // one call at a time per device
+};
+
+StaticWorkspaces& static_workspaces() {
+    static StaticWorkspaces w;
+    return w;
+}
+
+// This device's copy of `scratch` (set up on first use, device `dev` current)
+// and the mutex that serialises the calls on it.
+cfpq_status static_workspace(int dev, void** out, std::mutex** mu) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(CFPQ_EINVAL, "device index beyond the static workspace table");
+    StaticWorkspaces& w = static_workspaces();
+    std::lock_guard<std::mutex> lk(w.table_mu);
+    if (!w.ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CFPQ_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        w.ptr[dev] = p;
+    }
+    *out = w.ptr[dev];
+    *mu = &w.dev_mu[dev];
+    return CFPQ_OK;
+}
+
 }  // namespace cfpq
 
 using namespace cfpq;
@@ -293,6 +338,50 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                          void* stream, void* d_workspace, size_t workspace_bytes, uint64_t* d_result,
                          cfpq_stats* stats) {
     g_last_error.clear();
+    return closure_impl(graph, grammar, opt, stream, d_workspace, workspace_bytes, d_result, stats, false);
+}
+
+cfpq_status cfpq_closure_static(const cfpq_graph* graph, const cfpq_grammar* grammar, const cfpq_options* opt,
+                                void* stream, uint64_t* d_result, cfpq_stats* stats) {
+    g_last_error.clear();
+    cfpq_status st = validate_grammar(grammar);
+    if (st != CFPQ_OK) return st;
+    st = validate_graph(graph, grammar);
+    if (st != CFPQ_OK) return st;
+    cfpq_options o = resolve(opt);
+    o.capture = 0;
+    o.profile = 0;
+    if (o.path < CFPQ_PATH_AUTO || o.path > CFPQ_PATH_FP4) return fail(CFPQ_EINVAL, "unknown path");
+    if (o.hybrid != CFPQ_HYBRID_OFF && o.hybrid != CFPQ_HYBRID_AUTO) return fail(CFPQ_EINVAL, "unknown hybrid mode");
+    if (o.schedule != CFPQ_SCHEDULE_INPLACE && o.schedule != CFPQ_SCHEDULE_JACOBI)
+        return fail(CFPQ_EINVAL, "unknown schedule");
+    const size_t need = make_plan(graph, grammar, o).total;
+    if (need > CFPQ_STATIC_WORKSPACE_BYTES)
+        return fail(CFPQ_ENOMEM, "this closure needs " + std::to_string(need) +
+                                     " bytes of workspace; the static workspace holds " +
+                                     std::to_string(static_cast<size_t>(CFPQ_STATIC_WORKSPACE_BYTES)) +
+                                     " (cfpq_closure takes a caller-provided workspace of any size)");
+    int dev = 0;
+    CFPQ_HIP(hipGetDevice(&dev));
+    void* ws = nullptr;
+    std::mutex* dev_mu = nullptr;
+    st = static_workspace(dev, &ws, &dev_mu);
+    if (st != CFPQ_OK) return st;
+    std::lock_guard<std::mutex> lk(*dev_mu);  // calls on one device share its array: one at a time
+    return closure_impl(graph, grammar, &o, stream, ws, CFPQ_STATIC_WORKSPACE_BYTES, d_result, stats, true);
+}
+
+}  // extern "C"
+
+namespace cfpq {
+
+// The whole path behind cfpq_closure.  no_alloc (cfpq_closure_static): the
+// calls that may allocate -- HIP events for the device time, graph capture,
+// the resident route's side stream and events -- are left out: the loop is
+// host-driven, device_ms is the host's wall time over the enqueued work.
+cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, const cfpq_options* opt,
+                         void* stream, void* d_workspace, size_t workspace_bytes, uint64_t* d_result,
+                         cfpq_stats* stats, bool no_alloc) {
     cfpq_status st = validate_grammar(grammar);
     if (st != CFPQ_OK) return st;
     st = validate_graph(graph, grammar);
@@ -314,7 +403,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
     if (o.tile != 0 && (o.path == CFPQ_PATH_ROWS || o.path == CFPQ_PATH_COLS))
         return fail(CFPQ_EINVAL, "the ROWS and COLS paths have no tile variants");
-    if (resident_route(graph, grammar, o)) {
+    if (!no_alloc && resident_route(graph, grammar, o)) {
         const cfpq_instance inst{*graph, grammar, d_result};
         return batch_closure_run(1, &inst, o, stream, d_workspace, workspace_bytes, stats, true);
     }
@@ -345,12 +434,18 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     const cfpq_edge* d_edges = graph->edges;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    CFPQ_HIP(hipEventCreate(&ev0));
-    CFPQ_HIP(hipEventCreate(&ev1));
+    if (!no_alloc) {
+        CFPQ_HIP(hipEventCreate(&ev0));
+        CFPQ_HIP(hipEventCreate(&ev1));
+    }
     struct EvGuard {
         hipEvent_t a, b;
-        ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); }
+        ~EvGuard() {
+            if (a) hipEventDestroy(a);
+            if (b) hipEventDestroy(b);
+        }
     } guard{ev0, ev1};
+    const auto host_t0 = std::chrono::steady_clock::now();
 
     CFPQ_HIP(hipMemcpyAsync(d_term_off, term_off.data(), term_off.size() * 4, hipMemcpyHostToDevice, s));
     CFPQ_HIP(hipMemcpyAsync(d_term_lhs, term_lhs.data(), term_lhs.size() * 4, hipMemcpyHostToDevice, s));
@@ -361,7 +456,7 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         d_edges = dst;
     }
     CFPQ_HIP(hipMemsetAsync(d_bad, 0, 4, s));
-    CFPQ_HIP(hipEventRecord(ev0, s));
+    if (ev0) CFPQ_HIP(hipEventRecord(ev0, s));
 
     // Matrix initialisation.
     uint64_t* X = d_result;
@@ -678,10 +773,15 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     // In Jacobi mode X == Y after the last loop; make sure d_result holds it.
     if (p.jacobi && X != d_result)
         CFPQ_HIP(hipMemcpyAsync(d_result, X, mat_words * 8 * n_nt, hipMemcpyDeviceToDevice, s));
-    CFPQ_HIP(hipEventRecord(ev1, s));
-    CFPQ_HIP(hipEventSynchronize(ev1));
     float ms = 0.f;
-    CFPQ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    if (ev1) {
+        CFPQ_HIP(hipEventRecord(ev1, s));
+        CFPQ_HIP(hipEventSynchronize(ev1));
+        CFPQ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    } else {
+        CFPQ_HIP(hipStreamSynchronize(s));
+        ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - host_t0).count();
+    }
     if (stats) {
         stats->iterations = iters;
         stats->products = products;
@@ -700,6 +800,10 @@ cfpq_status cfpq_closure(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     if (!converged) return fail(CFPQ_ENOTCONV, "max_iters reached before the fixpoint");
     return CFPQ_OK;
 }
+
+}  // namespace cfpq
+
+extern "C" {
 
 size_t cfpq_product_workspace_bytes(int32_t n_nodes, int32_t path) {
     const size_t mat = static_cast<size_t>(layout_for(n_nodes < 0 ? 0 : n_nodes).mat_words) * 8;

@@ -342,3 +342,17 @@ def test_conjunctive_rules_validated_before_device_work(case):
                                         ctypes.c_void_p(1 << 20), ctypes.c_size_t(1 << 30), ctypes.c_void_p(1 << 21),
                                         None) == _abi.CFPQ_EINVAL
 
+
+def test_static_closure_checks_on_host():
+    """cfpq_closure_static refuses, before any device work, invalid inputs and
+    closures whose workspace exceeds its static array."""
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+    out = ctypes.c_void_p(1 << 20)
+    bad = _abi.Grammar(0, 2, 0, 0, None, None)
+    assert lib.cfpq_closure_static(ctypes.byref(gr), ctypes.byref(bad), None, None, out, None) == _abi.CFPQ_EINVAL
+    big = _abi.Graph(20000, 0, 0, None)
+    assert lib.cfpq_closure_static(ctypes.byref(big), ctypes.byref(g), None, None, out, None) == _abi.CFPQ_ENOMEM
+    msg = lib.cfpq_last_error().decode()
+    assert "static workspace" in msg and str(64 << 20) in msg
