@@ -94,22 +94,25 @@ def cpu_baseline(cfpq, torch, inst, sample_n=8192):
             "blas_product": _blas_product_rate(inst)}
 
 
-def profiled_traffic(profile_md, sources):
+def profiled_traffic(profile_md, kernel, sources):
     """HBM bytes per launch from a committed rocprofv3 summary, or None when
-    the kernel's sources changed since the counters were taken."""
+    the summary is of another kernel or the kernel's sources changed since the
+    counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile_md)
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "source_sha256"):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "source_sha256", "kernel"):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
     h = hashlib.sha256()
     for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if vals.get("source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    if vals.get("kernel") != kernel:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -498,12 +501,14 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(achieved_t, 1), "peak": round(PEAK_VALU_BITOPS_T, 1),
                 "unit": "TOP/s", "frac": round(achieved_t / PEAK_VALU_BITOPS_T, 4), "traffic": None}
+    fp4_stages = (tuned or {}).get("tile") or 2 if path_used == "fp4" else 0
+    roof["kernel"] = {"mfma": "mfma_product_kernel<false, 2>",
+                      "fp4": f"mfma_product_kernel<true, {fp4_stages}>"}.get(path_used, "bits_product_kernel")
     if path_used in ("mfma", "fp4"):
-        roof["traffic"] = profiled_traffic(f"{path_used}_product_er16384_dyck.md",
+        roof["traffic"] = profiled_traffic(f"{path_used}_product_er16384_dyck.md", roof["kernel"],
                                            ["paper_1707_01007_amd/csrc/mfma_tile.h",
-                                            "paper_1707_01007_amd/csrc/kernels_mfma.hip"])
-    roof["kernel"] = {"mfma": "mfma_product_kernel<false>", "fp4": "mfma_product_kernel<true>"}.get(
-        path_used, "bits_product_kernel")
+                                            "paper_1707_01007_amd/csrc/kernels_mfma.hip",
+                                            "paper_1707_01007_amd/csrc/cfpq_internal.h"])
     roof["per_launch_bitops"] = per_launch
     line = {
         "metric": METRIC,

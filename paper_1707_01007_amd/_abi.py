@@ -91,7 +91,8 @@ class TuneEntry(ctypes.Structure):
 
     def as_dict(self):
         names = {PATH_BITS: "bits", PATH_MFMA: "mfma", PATH_FP4: "fp4"}
-        cands = {f"{names.get(self.candidate_path[k], '?')}{self.candidate_tile[k] or ''}": round(self.candidates_ms[k], 4)
+        cands = {f"{names.get(self.candidate_path[k], '?')}"
+                 f"{'_' + str(self.candidate_tile[k]) if self.candidate_tile[k] else ''}": round(self.candidates_ms[k], 4)
                  for k in range(self.n_candidates)}
         return {"npad": self.npad, "path": names.get(self.path, "?"), "tile": self.tile,
                 "ms": round(self.ms, 4), "candidates_ms": cands}

@@ -15,6 +15,7 @@
 // Every candidate computes the same bits, so tuning never changes a result.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -169,6 +170,11 @@ bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile, float* ms) {
     if (it == t.by_bucket.end()) return false;
     const cfpq_tune_entry& e = it->second;
     if (reads_ct(e.path) && L.n > kMfmaMaxNodes) return false;
+    if (e.path == CFPQ_PATH_FP4 && !fp4_tile_supported(e.tile)) {
+        *path = CFPQ_PATH_FP4;
+        *tile = 0;
+        return true;
+    }
     if (e.path == CFPQ_PATH_BITS && e.tile != 0 && !bits_strip_supported(e.tile, L)) {
         *path = CFPQ_PATH_BITS;
         *tile = 0;
@@ -218,30 +224,41 @@ cfpq_status cfpq_autotune(int32_t n_nodes, void* stream, void* d_workspace, size
     };
     std::vector<Cand> cands;
     if (L.n <= kMfmaMaxNodes) {
-        cands.push_back({CFPQ_PATH_FP4, 0});
+        cands.push_back({CFPQ_PATH_FP4, 0});  // the default pipeline depth (3 measured the same)
         cands.push_back({CFPQ_PATH_MFMA, 0});
     }
     for (int strip : {8, 16, 32})
         if (bits_strip_supported(strip, L)) cands.push_back({CFPQ_PATH_BITS, strip});
     const double work = static_cast<double>(L.npad) * L.npad * L.npad;
-    const int reps = work > 1e12 ? 2 : (work > 1e10 ? 5 : 20);
+    const int reps = work > 1e12 ? 3 : (work > 1e10 ? 7 : 21);
+    const size_t nc = std::min<size_t>(cands.size(), 8);
+    auto launch = [&](size_t c) -> hipError_t {
+        if (reads_ct(cands[c].path)) return launch_mfma_path(cands[c].path, B, CT, A, L, flag, s, nullptr, 1, cands[c].tile);
+        return launch_bits_product(B, C, A, L, flag, s, cands[c].tile);
+    };
+    // Every candidate once first (code load, clocks up), then the timed
+    // launches round-robin, one event pair each, so that no candidate is
+    // favoured by its place in the order; the median launch of each counts.
+    for (size_t c = 0; c < nc; ++c) CFPQ_HIP(launch(c));
+    std::vector<std::vector<float>> times(nc);
+    for (int r = 0; r < reps; ++r) {
+        for (size_t c = 0; c < nc; ++c) {
+            CFPQ_HIP(hipEventRecord(e0, s));
+            CFPQ_HIP(launch(c));
+            CFPQ_HIP(hipEventRecord(e1, s));
+            CFPQ_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            CFPQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+            times[c].push_back(ms);
+        }
+    }
     cfpq_tune_entry best;
     std::memset(&best, 0, sizeof best);
     best.npad = static_cast<int32_t>(L.npad);
     best.ms = 1e30f;
-    for (size_t c = 0; c < cands.size() && c < 8; ++c) {
-        auto launch = [&]() -> hipError_t {
-            if (reads_ct(cands[c].path)) return launch_mfma_path(cands[c].path, B, CT, A, L, flag, s);
-            return launch_bits_product(B, C, A, L, flag, s, cands[c].tile);
-        };
-        CFPQ_HIP(launch());  // warm up
-        CFPQ_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) CFPQ_HIP(launch());
-        CFPQ_HIP(hipEventRecord(e1, s));
-        CFPQ_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        CFPQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-        ms /= reps;
+    for (size_t c = 0; c < nc; ++c) {
+        std::sort(times[c].begin(), times[c].end());
+        const float ms = times[c][times[c].size() / 2];
         best.candidates_ms[c] = ms;
         best.candidate_path[c] = cands[c].path;
         best.candidate_tile[c] = cands[c].tile;

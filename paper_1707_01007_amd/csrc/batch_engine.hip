@@ -63,6 +63,8 @@ __global__ __launch_bounds__(256) void engine_scatter_kernel(const SlotDesc* __r
     for (int32_t q = toff[ed.label]; q < toff[ed.label + 1]; ++q) {
         const int32_t a = term_tab[d.term_lhs_off + q];
         atomicOr(reinterpret_cast<unsigned long long*>(d.T + a * mw + off), bit);
+        // nonterminal a holds bits after initialisation (read by the first loop's plan)
+        if (states[slot].changed_prev[a] == 0) states[slot].changed_prev[a] = 1;
     }
 }
 
@@ -340,50 +342,40 @@ constexpr uint64_t kPushMask = (1ull << kPushRows) - 1;
 // Loops of a slot whose row-gather work is pulled by rows of A.
 constexpr int kPullLoops = 2;
 
-// Exclusive scan of per-thread (a, b) counts over one workgroup of 256; the
-// totals land in *ta, *tb.
-__device__ void scan2(int32_t* sa, int32_t* sb, int32_t& a, int32_t& b, int32_t* ta, int32_t* tb) {
-    const int t = threadIdx.x;
-    sa[t] = a;
-    sb[t] = b;
-    __syncthreads();
-    if (t == 0) {
-        int32_t xa = 0, xb = 0;
-        for (int i = 0; i < 256; ++i) {
-            const int32_t va = sa[i], vb = sb[i];
-            sa[i] = xa;
-            sb[i] = xb;
-            xa += va;
-            xb += vb;
-        }
-        *ta = xa;
-        *tb = xb;
-    }
-    __syncthreads();
-    a = sa[t];
-    b = sb[t];
-}
-
-// Exclusive prefix sums over the 256 threads of kN per-thread counts
-// (in place) and their totals.
+// Exclusive prefix sums over the 256 threads of one workgroup of kN
+// per-thread counts at once (in place), and their totals (*tot[c], written by
+// thread 0).  Each wavefront scans its 64 lanes with shuffles; the four
+// wavefront totals are combined through LDS.  Every thread must call it.
 template <int kN>
-__device__ void scan_n(int32_t (*sh)[256], int32_t (&v)[kN], int32_t* const (&tot)[kN]) {
-    const int t = threadIdx.x;
+__device__ void block_scan(int32_t (&v)[kN], int32_t* const (&tot)[kN]) {
+    __shared__ int32_t wave_tot[kN][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t incl[kN];
 #pragma unroll
-    for (int c = 0; c < kN; ++c) sh[c][t] = v[c];
-    __syncthreads();
-    if (t < kN) {
-        int32_t x = 0;
-        for (int i = 0; i < 256; ++i) {
-            const int32_t y = sh[t][i];
-            sh[t][i] = x;
-            x += y;
+    for (int c = 0; c < kN; ++c) {
+        int32_t x = v[c];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
-        *tot[t] = x;
+        incl[c] = x;
+        if (lane == 63) wave_tot[c][wave] = x;
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kN; ++c) v[c] = sh[c][t];
+    for (int c = 0; c < kN; ++c) {
+        int32_t base = 0, sum = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int32_t t = wave_tot[c][w];
+            base += w < wave ? t : 0;
+            sum += t;
+        }
+        if (threadIdx.x == 0) *tot[c] = sum;
+        v[c] = base + incl[c] - v[c];
+    }
+    __syncthreads();  // wave_tot may be reused by the next call
 }
 
 // Start of a loop: for every running large slot decide which rules run
@@ -399,7 +391,6 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
                                                           const int32_t* __restrict__ rules_tab, int32_t* go_tab,
                                                           const int32_t* __restrict__ mode_tab, Job* jobs,
                                                           EngineState* es, const int32_t* __restrict__ large_ids) {
-    __shared__ int32_t sh[6][256];
     const int t = threadIdx.x;
     const int n_large = es->n_large;
     const int per = (n_large + 255) / 256;
@@ -434,7 +425,14 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
         for (int r = 0; r < d.n_rules; ++r) {
             const int rb = rules_tab[3 * (d.rule_off + r) + 1];
             const int rc = rules_tab[3 * (d.rule_off + r) + 2];
-            const int go = (!d.dirty || st->iterations == 0 || st->changed_prev[rb] || st->changed_prev[rc]) ? 1 : 0;
+            // Dirty worklist: after the first loop a rule runs if an operand
+            // changed in the last loop.  In the first loop changed_prev marks
+            // the nonterminals the edges gave bits (engine_scatter_kernel): a
+            // rule with an empty operand has an empty product and is left out;
+            // it runs as soon as that operand gains bits (then it changed).
+            const int* cp = st->changed_prev;
+            const bool dirty_go = st->iterations == 0 ? (cp[rb] && cp[rc]) : (cp[rb] || cp[rc]);
+            const int go = (!d.dirty || dirty_go) ? 1 : 0;
             go_tab[d.rule_off + r] = go;
             launched += go;
             if (!go) continue;
@@ -450,7 +448,7 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
     }
     int32_t* const tot[6] = {&es->n_jobs, &es->total_items, &es->n_jobs128, &es->total_items128, &es->n_rjobs,
                              &es->total_rows};
-    scan_n<6>(sh, v, tot);
+    block_scan<6>(v, tot);
     if (t == 0) {
         es->next_item = 0;
         es->next_item128 = 0;
@@ -725,7 +723,6 @@ __global__ __launch_bounds__(256) void engine_product_kernel(const SlotDesc* __r
 __device__ void engine_tplan_body(const SlotDesc* __restrict__ descs, SlotState* states,
                                   const int32_t* __restrict__ trans_tab, Job* tjobs, EngineState* es,
                                   const int32_t* __restrict__ large_ids, int32_t fresh) {
-    __shared__ int32_t sa[256], sb[256];
     const int t = threadIdx.x;
     const int n_large = es->n_large;
     const int per = (n_large + 255) / 256;
@@ -748,7 +745,11 @@ __device__ void engine_tplan_body(const SlotDesc* __restrict__ descs, SlotState*
             if (pass == 1 && fresh) st.fresh = 0;
         }
         if (pass == 0) {
-            scan2(sa, sb, my_jobs, my_items, &es->n_tjobs, &es->total_titems);
+            int32_t v[2] = {my_jobs, my_items};
+            int32_t* const tot[2] = {&es->n_tjobs, &es->total_titems};
+            block_scan<2>(v, tot);
+            my_jobs = v[0];
+            my_items = v[1];
             if (t == 0) es->next_titem = 0;
         }
     }

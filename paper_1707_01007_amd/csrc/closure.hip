@@ -403,6 +403,8 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
     if (o.tile != 0 && (o.path == CFPQ_PATH_ROWS || o.path == CFPQ_PATH_COLS))
         return fail(CFPQ_EINVAL, "the ROWS and COLS paths have no tile variants");
+    if (o.path == CFPQ_PATH_FP4 && !fp4_tile_supported(o.tile))
+        return fail(CFPQ_EINVAL, "unsupported FP4 tile (pipeline depth 2 or 3, or 0)");
     if (!no_alloc && resident_route(graph, grammar, o)) {
         const cfpq_instance inst{*graph, grammar, d_result};
         return batch_closure_run(1, &inst, o, stream, d_workspace, workspace_bytes, stats, true);
@@ -540,7 +542,7 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
                 int32_t* flag = &lst->changed[br.lhs];
                 if (reads_ct(p.path))
                     ce = launch_mfma_path(p.path, cx + br.left * mat_words, TT + p.right_slot[br.right] * mat_words,
-                                          cy + br.lhs * mat_words, L, flag, cs, d_go + r);
+                                          cy + br.lhs * mat_words, L, flag, cs, d_go + r, 1, p.tile);
                 else
                     ce = launch_bits_product(cx + br.left * mat_words, cx + br.right * mat_words,
                                              cy + br.lhs * mat_words, L, flag, cs, p.tile, d_go + r);
@@ -627,7 +629,7 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             CFPQ_HIP(launch_rowor_product(ct, bt, PT, L, nullptr, ROWOR, s, nullptr, 1, rowor_calls++));
             CFPQ_HIP(launch_transpose_or(PT, Am, L, flag, s));
         } else if (reads_ct(p.path)) {
-            CFPQ_HIP(launch_mfma_path(p.path, Bm, ct, Am, L, flag, s));
+            CFPQ_HIP(launch_mfma_path(p.path, Bm, ct, Am, L, flag, s, nullptr, 1, p.tile));
         } else {
             CFPQ_HIP(launch_bits_product(Bm, Cm, Am, L, flag, s, p.tile));
         }
@@ -829,7 +831,10 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
     if (path < CFPQ_PATH_BITS || path > CFPQ_PATH_FP4) return fail(CFPQ_EINVAL, "unknown path");
     if (path == CFPQ_PATH_BITS && tile != 0 && !bits_strip_supported(tile, L))
         return fail(CFPQ_EINVAL, "unsupported BITS tile (strip width 8, 16 or 32 dividing 2 * row_words)");
-    if (path != CFPQ_PATH_BITS && tile != 0) return fail(CFPQ_EINVAL, "only the BITS path has tile variants");
+    if (path == CFPQ_PATH_FP4 && !fp4_tile_supported(tile))
+        return fail(CFPQ_EINVAL, "unsupported FP4 tile (pipeline depth 2 or 3, or 0)");
+    if (path != CFPQ_PATH_BITS && path != CFPQ_PATH_FP4 && tile != 0)
+        return fail(CFPQ_EINVAL, "only the BITS and FP4 paths have tile variants");
     if (reads_ct(path) && n_nodes > kMfmaMaxNodes)
         return fail(CFPQ_EINVAL, "the MFMA paths support at most 2^19 nodes");
     const size_t need = cfpq_product_workspace_bytes(n_nodes, path);
@@ -842,7 +847,7 @@ cfpq_status cfpq_product(int32_t n_nodes, int32_t path, int32_t tile, const uint
         case CFPQ_PATH_MFMA:
         case CFPQ_PATH_FP4:
             CFPQ_HIP(launch_transpose(d_c, ws, L, s));
-            CFPQ_HIP(launch_mfma_path(path, d_b, ws, d_a, L, d_changed, s));
+            CFPQ_HIP(launch_mfma_path(path, d_b, ws, d_a, L, d_changed, s, nullptr, 1, tile));
             break;
         case CFPQ_PATH_ROWS:
             CFPQ_HIP(launch_rowor_product(d_b, d_c, d_a, L, d_changed, reinterpret_cast<int32_t*>(ws), s));

@@ -36,7 +36,7 @@
 namespace cfpq {
 namespace {
 
-template <bool kFp4>
+template <bool kFp4, int kStages = 2>
 __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __restrict__ Bm,
                                                            const uint32_t* __restrict__ CT,
                                                            uint32_t* Am, int W2, int kchunks,
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __res
     }
 
     if (kFp4)
-        mfma::mfma4_tile<false>(Bm, CT, Am, W2, kchunks, tile_i, tile_j, changed);
+        mfma::mfma4_tile<false, kStages>(Bm, CT, Am, W2, kchunks, tile_i, tile_j, changed);
     else
         mfma::mfma_tile<false>(Bm, CT, Am, W2, kchunks, tile_i, tile_j, changed);
 }
@@ -86,7 +86,7 @@ hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* 
 }
 
 hipError_t launch_mfma4_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
-                                int32_t* changed, hipStream_t s, const int32_t* go, int32_t want) {
+                                int32_t* changed, hipStream_t s, const int32_t* go, int32_t want, int32_t stages) {
     const int W2 = static_cast<int>(2 * L.W);
     // 256 k per chunk: rows hold W / 4 >= ceil(n / 256) chunks (W is a
     // multiple of 4 words), and bits past n are zero
@@ -95,9 +95,16 @@ hipError_t launch_mfma4_product(const uint64_t* B, const uint64_t* CT, uint64_t*
     const int tiles_dim = static_cast<int>(L.npad / 256);
     const int total = tiles_dim * tiles_dim;
     const int grouped = (tiles_dim % 32 == 0) ? 1 : 0;
-    mfma_product_kernel<true><<<dim3(static_cast<unsigned>(total)), dim3(256), 0, s>>>(
-        reinterpret_cast<const uint32_t*>(B), reinterpret_cast<const uint32_t*>(CT),
-        reinterpret_cast<uint32_t*>(A), W2, kchunks, tiles_dim, grouped, changed, go, want);
+    if (stages == 0) stages = kFp4DefaultStages;
+    const auto* b = reinterpret_cast<const uint32_t*>(B);
+    const auto* ct = reinterpret_cast<const uint32_t*>(CT);
+    auto* a = reinterpret_cast<uint32_t*>(A);
+    if (stages == 2)
+        mfma_product_kernel<true, 2><<<dim3(static_cast<unsigned>(total)), dim3(256), 0, s>>>(
+            b, ct, a, W2, kchunks, tiles_dim, grouped, changed, go, want);
+    else
+        mfma_product_kernel<true, 3><<<dim3(static_cast<unsigned>(total)), dim3(256), 0, s>>>(
+            b, ct, a, W2, kchunks, tiles_dim, grouped, changed, go, want);
     return hipGetLastError();
 }
 

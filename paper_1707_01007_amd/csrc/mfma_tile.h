@@ -178,9 +178,15 @@ __device__ __forceinline__ void mfma_tile(const uint32_t* __restrict__ Bm, const
 
 // ---- fp4 (e2m1) operands, fp32 sums ----
 
-// Scale operands of the f8f6f4 MFMA builtin: 0 on both sides selects the
-// unscaled instruction, which takes the e2m1 values as they are.
-constexpr int kFp4Scale = 0;
+// The f8f6f4 MFMA with e2m1 (fp4) operands of four dwords each, unscaled:
+// the LLVM intrinsic's v4i32 form (the clang builtin only takes eight-dword
+// operands, which would tie up four more registers per fragment).  Format
+// code 4 (e2m1) for both operands; scale operands 0 select the unscaled
+// instruction, which takes the e2m1 values as they are.
+__device__ v16f mfma_f32_32x32x64_fp4(v4i a, v4i b, v16f c, int cbsz, int blgp, int opsel_a, int scale_a,
+                                      int opsel_b, int scale_b)
+    __asm("llvm.amdgcn.mfma.scale.f32.32x32x64.f8f6f4.v4i32.v4i32");
+constexpr int kFmtFp4 = 4;
 
 // Operand dwords of one 32-bit k-word w for the fp4 MFMA: dword q holds the
 // eight bits 4t + q of w (t = 0..7) as e2m1 nibbles, nibble t nonzero iff
@@ -192,13 +198,12 @@ constexpr int kFp4Scale = 0;
 // some k has both bits set.  Sums are multiples of 0.25 below 4 * 2^19 = 2^21,
 // exact in fp32 (and a positive sum of positive terms could not round to
 // zero anyway).
-__device__ __forceinline__ v8i spread4(uint32_t w) {
-    v8i r;
+__device__ __forceinline__ v4i spread4(uint32_t w) {
+    v4i r;
     r[0] = static_cast<int>(w & 0x11111111u);
     r[1] = static_cast<int>(w & 0x22222222u);
     r[2] = static_cast<int>(w & 0x44444444u);
     r[3] = static_cast<int>((w >> 3) & 0x11111111u);
-    r[4] = r[5] = r[6] = r[7] = 0;  // not read for fp4 operands
     return r;
 }
 
@@ -207,7 +212,7 @@ __device__ __forceinline__ v8i spread4(uint32_t w) {
 __device__ __forceinline__ void mma_chunk4(v16f (&acc)[kJT][kIT], const Chunk& ch) {
 #pragma unroll
     for (int s = 0; s < kChunkWords; ++s) {
-        v8i ca[kJT], bb[kIT];
+        v4i ca[kJT], bb[kIT];
 #pragma unroll
         for (int jb = 0; jb < kJT; ++jb) ca[jb] = spread4(word_of(ch.c[jb], s));
 #pragma unroll
@@ -216,20 +221,23 @@ __device__ __forceinline__ void mma_chunk4(v16f (&acc)[kJT][kIT], const Chunk& c
         for (int jb = 0; jb < kJT; ++jb)
 #pragma unroll
             for (int ib = 0; ib < kIT; ++ib)
-                acc[jb][ib] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                    ca[jb], bb[ib], acc[jb][ib], 4, 4, 0, kFp4Scale, 0, kFp4Scale);
+                acc[jb][ib] = mfma_f32_32x32x64_fp4(ca[jb], bb[ib], acc[jb][ib], kFmtFp4, kFmtFp4, 0, 0, 0, 0);
     }
 }
 
 // One wavefront's 128 x 128 output block (rows i0.., columns j0..) of
 // A |= B x C on the fp4 MFMA, CT = C^T, over kchunks chunks of 256 k (any
 // count >= 1): lane half g reads dwords 8c + 4g .. 8c + 4g + 3 of chunk c, so
-// one 64-k MFMA step takes k-word s from each half.  No barriers: any
-// wavefront may call it on its own.  kAtomic as in store_tile.
-template <bool kAtomic>
+// one 64-k MFMA step takes k-word s from each half.  kStages chunk buffers in
+// registers (2 or 3): chunk c + kStages - 1 is in flight while chunk c is
+// multiplied; prefetches past the end re-read the last chunk (in bounds)
+// instead of branching.  No barriers: any wavefront may call it on its own.
+// kAtomic as in store_tile.
+template <bool kAtomic, int kStages = 2>
 __device__ __forceinline__ void mfma4_wave_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
                                                 uint32_t* Am, int W2, int kchunks, int i0, int j0,
                                                 int32_t* changed, uint64_t* rowbits = nullptr) {
+    static_assert(kStages == 2 || kStages == 3, "two or three chunk buffers");
     const int lane = threadIdx.x & 63;
     const int g = lane >> 5;
     const int r32 = lane & 31;
@@ -252,22 +260,47 @@ __device__ __forceinline__ void mfma4_wave_tile(const uint32_t* __restrict__ Bm,
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[jb][ib][e] = 0.0f;
 
-    // Two alternating chunk buffers as in mfma_tile; an odd last chunk is
-    // multiplied after the loop from the buffer its prefetch filled.
-    Chunk buf0, buf1;
-    load_chunk(buf0, crow, brow, 0);
-    int kc = 0;
-    for (; kc + 1 < kchunks; kc += 2) {
-        load_chunk(buf1, crow, brow, 2 * (kc + 1));
-        __builtin_amdgcn_sched_barrier(0);
-        mma_chunk4(acc, buf0);
-        __builtin_amdgcn_sched_barrier(0);
-        load_chunk(buf0, crow, brow, 2 * min(kc + 2, kchunks - 1));
-        __builtin_amdgcn_sched_barrier(0);
-        mma_chunk4(acc, buf1);
-        __builtin_amdgcn_sched_barrier(0);
+    const int last = kchunks - 1;
+    // The scheduling barriers keep each prefetch ahead of the multiplies that
+    // follow it (the scheduler would otherwise sink the loads to their uses).
+    if (kStages == 2) {
+        Chunk buf0, buf1;
+        load_chunk(buf0, crow, brow, 0);
+        int kc = 0;
+        for (; kc + 1 < kchunks; kc += 2) {
+            load_chunk(buf1, crow, brow, 2 * (kc + 1));
+            __builtin_amdgcn_sched_barrier(0);
+            mma_chunk4(acc, buf0);
+            __builtin_amdgcn_sched_barrier(0);
+            load_chunk(buf0, crow, brow, 2 * min(kc + 2, last));
+            __builtin_amdgcn_sched_barrier(0);
+            mma_chunk4(acc, buf1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (kc < kchunks) mma_chunk4(acc, buf0);
+    } else {
+        Chunk buf0, buf1, buf2;
+        load_chunk(buf0, crow, brow, 0);
+        load_chunk(buf1, crow, brow, 2 * min(1, last));
+        int kc = 0;
+        for (; kc + 2 < kchunks; kc += 3) {
+            load_chunk(buf2, crow, brow, 2 * (kc + 2));
+            __builtin_amdgcn_sched_barrier(0);
+            mma_chunk4(acc, buf0);
+            __builtin_amdgcn_sched_barrier(0);
+            load_chunk(buf0, crow, brow, 2 * min(kc + 3, last));
+            __builtin_amdgcn_sched_barrier(0);
+            mma_chunk4(acc, buf1);
+            __builtin_amdgcn_sched_barrier(0);
+            load_chunk(buf1, crow, brow, 2 * min(kc + 4, last));
+            __builtin_amdgcn_sched_barrier(0);
+            mma_chunk4(acc, buf2);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // zero, one or two chunks left, in buf0 and buf1
+        if (kc < kchunks) mma_chunk4(acc, buf0);
+        if (kc + 1 < kchunks) mma_chunk4(acc, buf1);
     }
-    if (kc < kchunks) mma_chunk4(acc, buf0);
 
     store_tile<kAtomic>(acc, Am, W2, i0, j0, g, r32, lane, changed, rowbits);
 }
@@ -275,13 +308,13 @@ __device__ __forceinline__ void mfma4_wave_tile(const uint32_t* __restrict__ Bm,
 // One 256 x 256 output tile (rows of tile_i, columns of tile_j) on the fp4
 // MFMA, called by all 256 lanes of a workgroup: each wavefront takes one
 // 128 x 128 quarter (mfma4_wave_tile).
-template <bool kAtomic>
+template <bool kAtomic, int kStages = 2>
 __device__ __forceinline__ void mfma4_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
                                            uint32_t* Am, int W2, int kchunks, int tile_i, int tile_j,
                                            int32_t* changed, uint64_t* rowbits = nullptr) {
     const int wave = threadIdx.x >> 6;
-    mfma4_wave_tile<kAtomic>(Bm, CT, Am, W2, kchunks, tile_i * 256 + (wave >> 1) * 128,
-                             tile_j * 256 + (wave & 1) * 128, changed, rowbits);
+    mfma4_wave_tile<kAtomic, kStages>(Bm, CT, Am, W2, kchunks, tile_i * 256 + (wave >> 1) * 128,
+                                      tile_j * 256 + (wave & 1) * 128, changed, rowbits);
 }
 
 }  // namespace mfma

@@ -155,6 +155,30 @@ def test_sparse_paths_take_no_tile(path):
     assert b"tile" in lib.cfpq_last_error()
 
 
+@pytest.mark.parametrize("tile,ok", [(0, True), (2, True), (3, True), (1, False), (4, False), (8, False)])
+def test_fp4_tile_is_a_pipeline_depth(tile, ok):
+    """The FP4 path's tile is its register pipeline depth, 2 or 3 (0 = the
+    default); anything else is refused on the host by the closure and by a
+    single product."""
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+    opt = _abi.Options()
+    lib.cfpq_default_options(ctypes.byref(opt))
+    opt.path, opt.tile = _abi.PATH_FP4, tile
+    sz = ctypes.c_size_t(0)
+    assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz)) == 0
+    rc = lib.cfpq_closure(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), None, ctypes.c_void_p(1 << 20),
+                          ctypes.c_size_t(1 << 30), ctypes.c_void_p(1 << 21), None)
+    p = ctypes.c_void_p(1 << 20)
+    rc2 = lib.cfpq_product(64, _abi.PATH_FP4, tile, p, p, p, p, None, 0, None)
+    if ok:  # validation passes; what follows needs a device
+        assert rc != _abi.CFPQ_EINVAL and rc2 != _abi.CFPQ_EINVAL
+    else:
+        assert rc == _abi.CFPQ_EINVAL and rc2 == _abi.CFPQ_EINVAL
+        assert b"FP4 tile" in lib.cfpq_last_error()
+
+
 def test_workspace_grows_with_sparse_temporaries():
     """COLS needs the transposed right operands plus two temporaries, the
     hybrid choice (padded sizes >= 4096) more; ROWS needs none."""

@@ -66,8 +66,10 @@ def test_committed_traffic_matches_the_kernel_sources():
     """roofline.traffic comes from the committed rocprofv3 summaries only while
     the MFMA kernel's sources are the ones they were measured on."""
     import bench
-    src = ["paper_1707_01007_amd/csrc/mfma_tile.h", "paper_1707_01007_amd/csrc/kernels_mfma.hip"]
-    for md in ("fp4_product_er16384_dyck.md", "mfma_product_er16384_dyck.md"):
-        t = bench.profiled_traffic(md, src)
+    src = ["paper_1707_01007_amd/csrc/mfma_tile.h", "paper_1707_01007_amd/csrc/kernels_mfma.hip",
+           "paper_1707_01007_amd/csrc/cfpq_internal.h"]
+    for md, kern in (("fp4_product_er16384_dyck.md", "mfma_product_kernel<true, 2>"),
+                     ("mfma_product_er16384_dyck.md", "mfma_product_kernel<false, 2>")):
+        t = bench.profiled_traffic(md, kern, src)
         assert t is not None, md
         assert 1.342e8 <= t < 1.342e8 * 16  # at least the algorithmic 4 x 32 MiB

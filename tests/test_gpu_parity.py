@@ -314,6 +314,36 @@ def test_bits_strip_variants(cfpq, n, tile):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("n", [1, 200, 256, 257, 600, 777, 1024, 1500])
+@pytest.mark.parametrize("stages", [2, 3])
+def test_fp4_pipeline_depths(cfpq, n, stages):
+    """Both register pipelines of the fp4 kernel (2 or 3 chunk buffers) give
+    the Boolean product, at sizes whose 256-k chunk counts leave every
+    remainder of the loop (1, 2, 3, 4 and 6 chunks) and ragged edges."""
+    import torch
+    rng = np.random.default_rng(70 + n + stages)
+    b = rng.random((n, n)) < 0.02
+    c = rng.random((n, n)) < 0.3
+    a0 = rng.random((n, n)) < 0.01
+    want = a0 | alg1.bool_product(b, c)
+    dev = cfpq.upload_bits(n, worklist.pack(np.stack([b, c, a0])))
+    _say("fp4 stages", n, stages)
+    changed = cfpq.product(n, dev[0], dev[1], dev[2], path="fp4", tile=stages)
+    torch.cuda.synchronize()
+    got = worklist.unpack(dev[2, :n, : (n + 63) // 64].cpu().numpy().view(np.uint64), n)
+    assert np.array_equal(got, want)
+    assert int(changed.item()) == int((want != a0).any())
+
+
+def test_closure_with_each_fp4_depth(cfpq):
+    inst = configs.config3(1024)
+    want = worklist.closure(inst.n, inst.edges, inst.grammar)
+    for tile in (2, 3):
+        for sched in SCHEDULES:
+            bits, res = _run(cfpq, inst, path="fp4", tile=tile, schedule=sched)
+            assert np.array_equal(bits, want), (tile, sched)
+
+
 def test_closure_with_each_bits_tile(cfpq):
     inst = configs.config3(1024)
     want = worklist.closure(inst.n, inst.edges, inst.grammar)
