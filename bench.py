@@ -419,6 +419,9 @@ def main():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--path", default="auto", choices=["auto", "bits", "mfma", "fp4"])
     ap.add_argument("--schedule", default="inplace", choices=["inplace", "jacobi"])
+    ap.add_argument("--tile", type=int, default=0,
+                    help="kernel variant of the dense path (VALU strip width; fp4: 2 or 3 pipeline stages); "
+                         "0 = the default or the autotuned one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-closure section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
@@ -470,7 +473,7 @@ def main():
         print(f"[bench] autotune n={inst.n}: {tuned}", file=sys.stderr, flush=True)
     # Every closure here uses the same options as the timed ones: per-product
     # HIP events on the library's stream (host-driven loop, no skipped launches).
-    kw = dict(path=args.path, schedule=args.schedule, profile=True, hybrid=0)
+    kw = dict(path=args.path, schedule=args.schedule, profile=True, hybrid=0, tile=args.tile)
     res = cfpq.closure(inst.n, edges, g, **kw)  # sizes buffers
     out = res.bits.view(-1)
     print(f"[bench] warmup {args.warmup} x closure n={inst.n} path={args.path}", file=sys.stderr, flush=True)
@@ -501,9 +504,9 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(achieved_t, 1), "peak": round(PEAK_VALU_BITOPS_T, 1),
                 "unit": "TOP/s", "frac": round(achieved_t / PEAK_VALU_BITOPS_T, 4), "traffic": None}
-    fp4_stages = (tuned or {}).get("tile") or 2 if path_used == "fp4" else 0
+    fp4_tile = args.tile or (tuned or {}).get("tile") or 2 if path_used == "fp4" else 0
     roof["kernel"] = {"mfma": "mfma_product_kernel<false, 2>",
-                      "fp4": f"mfma_product_kernel<true, {fp4_stages}>"}.get(path_used, "bits_product_kernel")
+                      "fp4": f"mfma_product_kernel<true, {fp4_tile}>"}.get(path_used, "bits_product_kernel")
     if path_used in ("mfma", "fp4"):
         roof["traffic"] = profiled_traffic(f"{path_used}_product_er16384_dyck.md", roof["kernel"],
                                            ["paper_1707_01007_amd/csrc/mfma_tile.h",
