@@ -3,13 +3,16 @@
 product kernels and both schedules."""
 from __future__ import annotations
 
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
 import pytest
 
 from oracle import conjunctive, worklist
-from workloads import grammars, graphs
+from workloads import configs, grammars, graphs
 
 pytestmark = pytest.mark.gpu
 
@@ -119,3 +122,21 @@ def test_three_conjunct_rule_matches_oracle(cfpq, graph, path, hybrid):
     if graph == "chain":  # exactly a^n b^n c^n on a chain
         plain, _ = conjunctive.closure(n, e, grammars.anbncn())
         assert np.array_equal(got[g.nt("S")], plain[grammars.anbncn().nt("S")])
+
+
+def test_er8192_benchmark_matches_oracle_digest(cfpq):
+    """The benchmark's conjunctive workload (Dyck conjoined with a^n b^n, ER
+    recipe at n = 8192), edges in device memory and the library's default
+    products as the benchmark runs it: every bit equals the conjunctive
+    oracle's (per-nonterminal counts and a SHA-256 of the packed result)."""
+    import torch
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "digests.json")))["er8192_dyck_and_anbn"]
+    inst = configs.config3(gold["n"])
+    g = grammars.dyck_and_anbn()
+    print("[gpu-case] conjunctive", inst.n, g.name, "benchmark", file=sys.stderr, flush=True)
+    res = cfpq.conjunctive_closure(inst.n, torch.from_numpy(inst.edges).cuda(), g)
+    bits = cfpq.result_bits(res)
+    assert [int(np.unpackbits(b.view(np.uint8)).sum()) for b in bits] == gold["counts"]
+    assert hashlib.sha256(np.ascontiguousarray(bits).astype("<u8").tobytes()).hexdigest() == gold["sha256"]
+    assert res.stats["sparse_products"] > 0  # conjuncts with an edge-matrix operand ran as ROWS / COLS
