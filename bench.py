@@ -31,6 +31,13 @@ PEAK_INT8_TOPS = 5000.0  # dense int8 MFMA, 5.0 POP/s (1 MAC = 2 ops = AND + OR 
 PEAK_FP4_TOPS = 10100.0  # dense fp4 (e2m1) MFMA, 10.1 PFLOP/s
 # VALU: 256 CUs x 64 lanes per clock x 2.4 GHz x 64 bit-operations per v_and_or_b32
 PEAK_VALU_BITOPS_T = 256 * 64 * 2.4e9 * 64 / 1e12
+# The fp4 product's kernel variants: tile 2 or 3 = one workgroup per output
+# tile with that many pipeline stages, 5 = the persistent kernel (the default).
+FP4_DEFAULT_TILE = 5
+
+
+def fp4_kernel_name(tile):
+    return "mfma4_persistent_kernel" if tile == 5 else f"mfma_product_kernel<true, {tile}>"
 
 
 def _blas_product_rate(inst, seconds_target=4.0):
@@ -420,7 +427,7 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "bits", "mfma", "fp4"])
     ap.add_argument("--schedule", default="inplace", choices=["inplace", "jacobi"])
     ap.add_argument("--tile", type=int, default=0,
-                    help="kernel variant of the dense path (VALU strip width; fp4: 2 or 3 pipeline stages); "
+                    help="kernel variant of the dense path (VALU strip width; fp4: 2 or 3 pipeline stages, 5 persistent); "
                          "0 = the default or the autotuned one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-closure section")
@@ -504,9 +511,9 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(achieved_t, 1), "peak": round(PEAK_VALU_BITOPS_T, 1),
                 "unit": "TOP/s", "frac": round(achieved_t / PEAK_VALU_BITOPS_T, 4), "traffic": None}
-    fp4_tile = args.tile or (tuned or {}).get("tile") or 2 if path_used == "fp4" else 0
+    fp4_tile = args.tile or (tuned or {}).get("tile") or FP4_DEFAULT_TILE if path_used == "fp4" else 0
     roof["kernel"] = {"mfma": "mfma_product_kernel<false, 2>",
-                      "fp4": f"mfma_product_kernel<true, {fp4_tile}>"}.get(path_used, "bits_product_kernel")
+                      "fp4": fp4_kernel_name(fp4_tile)}.get(path_used, "bits_product_kernel")
     if path_used in ("mfma", "fp4"):
         roof["traffic"] = profiled_traffic(f"{path_used}_product_er16384_dyck.md", roof["kernel"],
                                            ["paper_1707_01007_amd/csrc/mfma_tile.h",

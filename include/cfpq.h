@@ -117,7 +117,10 @@ typedef struct {
     int32_t profile;         /* nonzero: time every product with HIP events on `stream`
                                 (stats.product_ms); costs one event pair per product */
     int32_t tile;            /* product kernel variant; 0 = autotuned or default.  BITS: output
-                                strip width in 32-bit words per workgroup (8, 16 or 32) */
+                                strip width in 32-bit words per workgroup (8, 16 or 32).  FP4:
+                                2 or 3 = a workgroup per 256 x 256 tile with that many chunk
+                                buffers, 5 = persistent workgroups (the default); other
+                                values give CFPQ_EINVAL */
     int32_t capture;         /* loops per captured HIP graph: the loop state (per-rule dirty
                                 decisions, change flags, loop count) lives on the device and the
                                 host reads it back once per `capture` loops; 0 = host-driven

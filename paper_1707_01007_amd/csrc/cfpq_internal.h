@@ -97,13 +97,16 @@ bool tuned_choice(const Layout& L, int32_t* path, int32_t* tile, float* ms = nul
 hipError_t launch_mfma_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
                                int32_t* changed, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1);
 // The same product on the fp4 (e2m1) MFMA with fp32 sums (kernels_mfma.hip).
-// stages: chunk buffers of its register pipeline, 2 or 3 (0 = kFp4DefaultStages).
-constexpr int32_t kFp4DefaultStages = 2;
+// stages: the kernel variant, 0 = kFp4DefaultStages; 2 or 3 = one workgroup
+// per 256 x 256 tile with that many chunk buffers in its register pipeline;
+// 5 = the persistent kernel (two buffers, one workgroup per CU walking the
+// tiles, the next tile's first chunk loaded under the current tile's last).
+constexpr int32_t kFp4DefaultStages = 5;
 hipError_t launch_mfma4_product(const uint64_t* B, const uint64_t* CT, uint64_t* A, const Layout& L,
                                 int32_t* changed, hipStream_t s, const int32_t* go = nullptr, int32_t want = 1,
                                 int32_t stages = 0);
 // Whether an FP4 tile value (options.tile / the tuning table) is valid: 0, 2, 3.
-inline bool fp4_tile_supported(int32_t tile) { return tile == 0 || tile == 2 || tile == 3; }
+inline bool fp4_tile_supported(int32_t tile) { return tile == 0 || tile == 2 || tile == 3 || tile == 5; }
 
 // The dense kernels that read C transposed: the two MFMA paths.
 inline bool reads_ct(int32_t path) { return path == CFPQ_PATH_MFMA || path == CFPQ_PATH_FP4; }

@@ -31,10 +31,31 @@
 // Workgroups go round-robin to the 8 XCDs; the tile order gives each XCD a
 // band of output rows walked in 4 x 8 groups of tiles, so the workgroups that
 // run together on one XCD share 4 row blocks of B and 8 of CT in its L2.
+#include <algorithm>
+
 #include "mfma_tile.h"
 
 namespace cfpq {
 namespace {
+
+// Workgroup (or persistent step) t -> output tile, XCD-aware.  grouped:
+// tiles_dim is a multiple of 32, so each XCD (t mod 8) owns tiles_dim / 8
+// consecutive tile rows, walked in groups of 4 tile rows x 8 tile columns.
+__device__ __forceinline__ void grouped_tile(int t, int tiles_dim, int grouped, int* tile_i, int* tile_j) {
+    if (grouped) {
+        const int xcd = t & 7;
+        const int idx = t >> 3;  // position in this XCD's sequence
+        const int rows_per_xcd = tiles_dim >> 3;
+        const int group = idx >> 5, within = idx & 31;
+        const int groups_per_row = tiles_dim >> 3;  // 8-column groups across
+        const int gr = group / groups_per_row, gc = group % groups_per_row;
+        *tile_i = xcd * rows_per_xcd + gr * 4 + (within >> 3);
+        *tile_j = gc * 8 + (within & 7);
+    } else {
+        *tile_i = t / tiles_dim;
+        *tile_j = t % tiles_dim;
+    }
+}
 
 template <bool kFp4, int kStages = 2>
 __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __restrict__ Bm,
@@ -43,29 +64,101 @@ __global__ __launch_bounds__(256) void mfma_product_kernel(const uint32_t* __res
                                                            int tiles_dim, int grouped,
                                                            int32_t* changed, const int32_t* go, int32_t want) {
     if (go != nullptr && *go != want) return;
-    // ---- workgroup -> tile, XCD-aware ----
-    // grouped: tiles_dim is a multiple of 32, so each XCD owns tiles_dim / 8
-    // consecutive tile rows, walked in groups of 4 tile rows x 8 tile columns.
-    const int wg = blockIdx.x;
     int tile_i, tile_j;
-    if (grouped) {
-        const int xcd = wg & 7;
-        const int idx = wg >> 3;                   // position in this XCD's sequence
-        const int rows_per_xcd = tiles_dim >> 3;
-        const int group = idx >> 5, within = idx & 31;
-        const int groups_per_row = tiles_dim >> 3;  // 8-column groups across
-        const int gr = group / groups_per_row, gc = group % groups_per_row;
-        tile_i = xcd * rows_per_xcd + gr * 4 + (within >> 3);
-        tile_j = gc * 8 + (within & 7);
-    } else {
-        tile_i = wg / tiles_dim;
-        tile_j = wg % tiles_dim;
-    }
+    grouped_tile(blockIdx.x, tiles_dim, grouped, &tile_i, &tile_j);
 
     if (kFp4)
         mfma::mfma4_tile<false, kStages>(Bm, CT, Am, W2, kchunks, tile_i, tile_j, changed);
     else
         mfma::mfma_tile<false>(Bm, CT, Am, W2, kchunks, tile_i, tile_j, changed);
+}
+
+// Persistent fp4 product (tile variant 5): one workgroup per CU walks the
+// tiles t = blockIdx.x, + gridDim.x, ... (gridDim a multiple of 8, so a
+// workgroup stays on its XCD and the XCD-aware tile order is kept).  While a
+// tile's last chunk is multiplied the next tile's first chunk is already being
+// loaded, so the epilogue and the next tile's start overlap that load.
+__global__ __launch_bounds__(256) void mfma4_persistent_kernel(const uint32_t* __restrict__ Bm,
+                                                               const uint32_t* __restrict__ CT, uint32_t* Am,
+                                                               int W2, int kchunks, int tiles_dim, int grouped,
+                                                               int32_t* changed, const int32_t* go, int32_t want) {
+    using namespace mfma;
+    if (go != nullptr && *go != want) return;
+    const int total = tiles_dim * tiles_dim;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 5;
+    const int r32 = lane & 31;
+    // This wavefront's corner (i0, j0) of tile t and the lane's operand rows
+    // (uint4 index 2c = chunk c).  Rebuilt where needed rather than kept live
+    // across the products, so the persistent loop needs no more registers
+    // than one tile does.
+    auto corner = [&](int t, int* i0, int* j0) {
+        int ti, tj;
+        grouped_tile(t, tiles_dim, grouped, &ti, &tj);
+        *j0 = tj * 256 + (wave & 1) * 128;
+        *i0 = ti * 256 + (wave >> 1) * 128;
+    };
+    auto rows = [&](int i0, int j0, const uint4* (&crow)[kJT], const uint4* (&brow)[kIT]) {
+#pragma unroll
+        for (int jb = 0; jb < kJT; ++jb)
+            crow[jb] = reinterpret_cast<const uint4*>(CT + static_cast<size_t>(j0 + jb * 32 + r32) * W2) + g;
+#pragma unroll
+        for (int ib = 0; ib < kIT; ++ib)
+            brow[ib] = reinterpret_cast<const uint4*>(Bm + static_cast<size_t>(i0 + ib * 32 + r32) * W2) + g;
+    };
+    auto load_first = [&](Chunk& ch, int t) {
+        int i0, j0;
+        corner(t, &i0, &j0);
+        const uint4* crow[kJT];
+        const uint4* brow[kIT];
+        rows(i0, j0, crow, brow);
+        load_chunk(ch, crow, brow, 0);
+    };
+    int t = blockIdx.x;
+    if (t >= total) return;
+    Chunk buf0, buf1;
+    load_first(buf0, t);
+    while (true) {
+        const int tn = t + gridDim.x;
+        const int tload = tn < total ? tn : t;  // the last tile reloads its own chunk 0 (unused)
+        int i0, j0;
+        corner(t, &i0, &j0);
+        const uint4* crow[kJT];
+        const uint4* brow[kIT];
+        rows(i0, j0, crow, brow);
+        v16f acc[kJT][kIT];
+#pragma unroll
+        for (int jb = 0; jb < kJT; ++jb)
+#pragma unroll
+            for (int ib = 0; ib < kIT; ++ib)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[jb][ib][e] = 0.0f;
+        int kc = 0;
+        for (; kc + 1 < kchunks; kc += 2) {
+            load_chunk(buf1, crow, brow, 2 * (kc + 1));
+            __builtin_amdgcn_sched_barrier(0);
+            mma_chunk4(acc, buf0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (kc + 2 < kchunks)
+                load_chunk(buf0, crow, brow, 2 * (kc + 2));
+            else  // even chunk count: the next tile's first chunk
+                load_first(buf0, tload);
+            __builtin_amdgcn_sched_barrier(0);
+            mma_chunk4(acc, buf1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (kc < kchunks) {  // odd chunk count: the last chunk is in buf0
+            load_first(buf1, tload);
+            __builtin_amdgcn_sched_barrier(0);
+            mma_chunk4(acc, buf0);
+            __builtin_amdgcn_sched_barrier(0);
+            buf0 = buf1;
+        }
+        store_tile<false>(acc, Am, W2, i0, j0, g, r32, lane, changed);
+        if (tn >= total) break;
+        t = tn;
+    }
 }
 
 }  // namespace
@@ -99,7 +192,16 @@ hipError_t launch_mfma4_product(const uint64_t* B, const uint64_t* CT, uint64_t*
     const auto* b = reinterpret_cast<const uint32_t*>(B);
     const auto* ct = reinterpret_cast<const uint32_t*>(CT);
     auto* a = reinterpret_cast<uint32_t*>(A);
-    if (stages == 2)
+    if (stages == 5) {
+        // one workgroup per CU (a multiple of 8, at least one per XCD)
+        int dev = 0, cus = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        const int grid = std::max(8, std::min(total, cus) / 8 * 8);
+        mfma4_persistent_kernel<<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, s>>>(
+            b, ct, a, W2, kchunks, tiles_dim, grouped, changed, go, want);
+    } else if (stages == 2)
         mfma_product_kernel<true, 2><<<dim3(static_cast<unsigned>(total)), dim3(256), 0, s>>>(
             b, ct, a, W2, kchunks, tiles_dim, grouped, changed, go, want);
     else

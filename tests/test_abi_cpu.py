@@ -155,11 +155,12 @@ def test_sparse_paths_take_no_tile(path):
     assert b"tile" in lib.cfpq_last_error()
 
 
-@pytest.mark.parametrize("tile,ok", [(0, True), (2, True), (3, True), (1, False), (4, False), (8, False)])
+@pytest.mark.parametrize("tile,ok", [(0, True), (2, True), (3, True), (5, True), (1, False), (4, False),
+                                     (8, False)])
 def test_fp4_tile_is_a_pipeline_depth(tile, ok):
-    """The FP4 path's tile is its register pipeline depth, 2 or 3 (0 = the
-    default); anything else is refused on the host by the closure and by a
-    single product."""
+    """The FP4 path's tile names its kernel variant: register pipeline depth
+    2 or 3, or 5 for the persistent kernel (0 = the default); anything else
+    is refused on the host by the closure and by a single product."""
     from paper_1707_01007_amd import _abi
     lib = _lib()
     gr, g, keep = _structs()

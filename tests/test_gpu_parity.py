@@ -315,11 +315,13 @@ def test_bits_strip_variants(cfpq, n, tile):
 
 
 @pytest.mark.parametrize("n", [1, 200, 256, 257, 600, 777, 1024, 1500])
-@pytest.mark.parametrize("stages", [2, 3])
+@pytest.mark.parametrize("stages", [2, 3, 5])
 def test_fp4_pipeline_depths(cfpq, n, stages):
-    """Both register pipelines of the fp4 kernel (2 or 3 chunk buffers) give
-    the Boolean product, at sizes whose 256-k chunk counts leave every
-    remainder of the loop (1, 2, 3, 4 and 6 chunks) and ragged edges."""
+    """Every fp4 kernel variant (register pipelines of 2 or 3 chunk buffers,
+    and the persistent kernel, tile 5) gives the Boolean product, at sizes
+    whose 256-k chunk counts leave every remainder of the loop (1, 2, 3, 4
+    and 6 chunks) and ragged edges; below 8 x 256 tiles some persistent
+    workgroups have no tile at all."""
     import torch
     rng = np.random.default_rng(70 + n + stages)
     b = rng.random((n, n)) < 0.02
@@ -338,7 +340,7 @@ def test_fp4_pipeline_depths(cfpq, n, stages):
 def test_closure_with_each_fp4_depth(cfpq):
     inst = configs.config3(1024)
     want = worklist.closure(inst.n, inst.edges, inst.grammar)
-    for tile in (2, 3):
+    for tile in (2, 3, 5):
         for sched in SCHEDULES:
             bits, res = _run(cfpq, inst, path="fp4", tile=tile, schedule=sched)
             assert np.array_equal(bits, want), (tile, sched)
