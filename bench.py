@@ -389,6 +389,18 @@ def bench_serve(cfpq, torch, warm=100, measured=500, loads=(1.5, 0.5), hybrid_la
             end = time.perf_counter()
         lat_srv = [x["latency_ms"] for x in infos]
         bad = sum(1 for x in infos if x["status"] != 0)
+        # what the tail is made of: the server's slowest 1% of requests, and the
+        # percentiles of the requests its hybrid lanes take (padded side >= 4096)
+        # and of those the batched engine takes
+        lane = [cfpq.padded_rows(i.n) >= 4096 for i in meas]
+        slow = sorted(range(measured), key=lambda q: -lat_srv[q])[:max(1, measured // 100)]
+        tail = {"slowest_1pct": [{"n": int(meas[q].n), "grammar": meas[q].grammar.name,
+                                  "latency_ms": round(lat_srv[q], 3)} for q in slow],
+                "lanes": {"requests": sum(lane), "p50_ms": _pct([x for x, ln in zip(lat_srv, lane) if ln], 50),
+                          "p99_ms": _pct([x for x, ln in zip(lat_srv, lane) if ln], 99)},
+                "engine": {"requests": measured - sum(lane),
+                           "p50_ms": _pct([x for x, ln in zip(lat_srv, lane) if not ln], 50),
+                           "p99_ms": _pct([x for x, ln in zip(lat_srv, lane) if not ln], 99)}}
         qps_srv = measured / (end - start)
         # (b) serial plain closure on the same trace
         start = time.perf_counter()
@@ -408,7 +420,7 @@ def bench_serve(cfpq, torch, warm=100, measured=500, loads=(1.5, 0.5), hybrid_la
                 "queries_per_s": round(qps_srv, 1), "p50_ms": _pct(lat_srv, 50), "p99_ms": _pct(lat_srv, 99),
                 "serial_plain_queries_per_s": round(qps_ser, 1), "serial_plain_p50_ms": _pct(lat_ser, 50),
                 "serial_plain_p99_ms": _pct(lat_ser, 99), "failed": bad,
-                "results_differing_from_serial": differ}
+                "results_differing_from_serial": differ, "server_tail": tail}
 
     out = {"workload": f"serve_seed5_{measured}req", "arrival": "poisson",
            "serial_service_rate_per_s": round(mu, 1)}

@@ -467,7 +467,7 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
         const int cus = device_cus();
         const int32_t grid_p = cus, grid_t = 4 * cus;
         CFPQ_HIP(engine_tplan(b, 1, s));
-        CFPQ_HIP(engine_transposes(b, grid_t, s));
+        CFPQ_HIP(engine_transposes(b, grid_t, 1, s));  // and the first loop's plan
         const int32_t K = o.capture > 0 ? o.capture : 8;
         hipStream_t cs = nullptr;
         CFPQ_HIP(capture_stream(&cs));
@@ -481,17 +481,9 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
                 if (g) hipGraphDestroy(g);
             }
         } gguard{g, exec};
-        CFPQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        hipError_t ce = hipSuccess;
-        for (int32_t it = 0; it < K && ce == hipSuccess; ++it) {
-            ce = engine_plan(b, cs);
-            if (ce == hipSuccess) ce = engine_products(b, grid_p, 8 * cus, cs);  // rows: up to 8 waves per SIMD
-            if (ce == hipSuccess) ce = engine_tplan_finish(b, cs);
-            if (ce == hipSuccess) ce = engine_transposes(b, grid_t, cs);
-        }
-        hipError_t ee = hipStreamEndCapture(cs, &g);
+        // rows: up to 8 waves per SIMD
+        const hipError_t ce = engine_capture_loops(b, K, grid_p, 8 * cus, grid_t, cs, &g);
         if (ce != hipSuccess) return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
-        if (ee != hipSuccess) return fail(CFPQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
         CFPQ_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
         EngineState hes;
         do {

@@ -14,8 +14,9 @@
 //    each row of A from the rows of C its row of B selects or (batch slots,
 //    after the first loops) pushes every row of C that gained bits into the
 //    rows of A that B links to it (found in B^T); transposes that changed are
-//    rebuilt like the tiles, and a finish kernel counts the loop and retires
-//    slots that reached their fixpoint.  The loop is captured into a
+//    rebuilt like the tiles (beside them, the next loop is planned), and a
+//    finish kernel counts the loop and retires slots that reached their
+//    fixpoint.  The loop is captured into a
 //    HIP graph once; which slots take part is data, so the same graph serves a
 //    batch that gains and loses members between replays.
 #pragma once
@@ -96,7 +97,7 @@ struct Job {
 struct EngineState {
     int32_t n_jobs, total_items, next_item, pad0;
     int32_t n_tjobs, total_titems, next_titem, pad1;
-    int32_t running;  // large slots still running after the last finish
+    int32_t running;  // large slots in the planned loop (set by the plan)
     int32_t n_large;  // entries of the large-slot list (set by the host between replays)
     int32_t n_rjobs;     // row-gather jobs of the loop
     int32_t total_rows;  // their items: rows of A (first loop) or blocks of rows of C (one wavefront each)
@@ -188,6 +189,8 @@ hipError_t engine_resident(const EngineBuffers& b, const int32_t* ids, int32_t c
 // The large-slot list has es->n_large entries (device memory, so a captured
 // loop serves any membership).  engine_tplan(fresh = 1) builds the first
 // transposes of newly admitted slots and clears their `fresh` flag.
+// engine_plan plans the next loop (work lists, es->running = slots in it);
+// planning again before the loop runs gives the same plan.
 hipError_t engine_plan(const EngineBuffers& b, hipStream_t s);
 // grid: workgroups of the persistent tile kernel (one per CU); rows_grid:
 // workgroups of the row-gather kernel (grid-stride, so any count is correct;
@@ -195,10 +198,18 @@ hipError_t engine_plan(const EngineBuffers& b, hipStream_t s);
 // little row work).
 hipError_t engine_products(const EngineBuffers& b, int32_t grid, int32_t rows_grid, hipStream_t s);
 hipError_t engine_tplan(const EngineBuffers& b, int32_t fresh, hipStream_t s);
-hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, hipStream_t s);
+// Runs the transpose list on `grid` workgroups; plan != 0 adds one workgroup
+// that plans the next loop (as engine_plan) beside them.
+hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, int32_t plan, hipStream_t s);
 // End of a loop: the transposes of the right operands it changed are listed
 // (as engine_tplan with fresh = 0), then each slot that took part counts the
-// loop and stops if it set no bit; engine_transposes then runs the list.
+// loop and its products and stops if it set no bit; engine_transposes then
+// runs the list.
 hipError_t engine_tplan_finish(const EngineBuffers& b, hipStream_t s);
+// Captures `loops` engine loops from stream cs into *graph: per loop the tile
+// and row-gather kernels, tplan_finish, and the transposes with the next
+// loop's plan.  The first replay must follow a plan.
+hipError_t engine_capture_loops(const EngineBuffers& b, int32_t loops, int32_t grid, int32_t rows_grid,
+                                int32_t grid_t, hipStream_t cs, hipGraph_t* graph);
 
 }  // namespace cfpq

@@ -386,17 +386,21 @@ __device__ void block_scan(int32_t (&v)[kN], int32_t* const (&tot)[kN]) {
 // kPullLoops loops and in every loop of a slot without changed-row bitmaps
 // (dim = 1), kPushRows-row blocks of C otherwise (dim = 0).
 // Slots are handled in list order (largest first), so the biggest tiles are
-// handed out first.
-__global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
-                                                          const int32_t* __restrict__ rules_tab, int32_t* go_tab,
-                                                          const int32_t* __restrict__ mode_tab, Job* jobs,
-                                                          EngineState* es, const int32_t* __restrict__ large_ids) {
+// handed out first.  es->running gets the number of slots in the loop.  The
+// plan only reads what the last finish wrote, so planning twice before a loop
+// gives the same lists (the server plans again after changing the slot list).
+// Called by all 256 threads of one workgroup.
+__device__ void engine_plan_body(const SlotDesc* __restrict__ descs, SlotState* states,
+                                 const int32_t* __restrict__ rules_tab, int32_t* go_tab,
+                                 const int32_t* __restrict__ mode_tab, Job* jobs, EngineState* es,
+                                 const int32_t* __restrict__ large_ids) {
     const int t = threadIdx.x;
     const int n_large = es->n_large;
     const int per = (n_large + 255) / 256;
     const int q0 = t * per, q1 = min(n_large, q0 + per);
-    // counts per thread: 256-tile jobs and items, 128-tile jobs and items, row jobs and items
-    int32_t v[6] = {0, 0, 0, 0, 0, 0};
+    // counts per thread: 256-tile jobs and items, 128-tile jobs and items, row
+    // jobs and items, slots in the loop
+    int32_t v[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int q = q0; q < q1; ++q) {
         const int slot = large_ids[q];
         const SlotDesc& d = descs[slot];
@@ -410,6 +414,7 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             continue;
         }
         st->in_loop = 1;
+        v[6] += 1;
         for (int a = 0; a < d.n_nt; ++a) st->changed[a] = 0;
         if (d.RD != nullptr) {
             // this loop's changed-row bitmaps (those of loop t - 2) start empty;
@@ -421,7 +426,6 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
         const bool t128 = d.tile == 128;  // any other value means 256 tiles
         const int dim = d.npad / (t128 ? 128 : 256);
         const int ts = t128 ? 2 : 0;  // index of the slot's tile counts in v
-        int launched = 0;
         for (int r = 0; r < d.n_rules; ++r) {
             const int rb = rules_tab[3 * (d.rule_off + r) + 1];
             const int rc = rules_tab[3 * (d.rule_off + r) + 2];
@@ -434,7 +438,6 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             const bool dirty_go = st->iterations == 0 ? (cp[rb] && cp[rc]) : (cp[rb] || cp[rc]);
             const int go = (!d.dirty || dirty_go) ? 1 : 0;
             go_tab[d.rule_off + r] = go;
-            launched += go;
             if (!go) continue;
             if (mode_tab[d.rule_off + r] == kModeRows) {
                 v[4] += 1;
@@ -444,11 +447,10 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
                 v[ts + 1] += dim * dim;
             }
         }
-        st->products += launched;
     }
-    int32_t* const tot[6] = {&es->n_jobs, &es->total_items, &es->n_jobs128, &es->total_items128, &es->n_rjobs,
-                             &es->total_rows};
-    block_scan<6>(v, tot);
+    int32_t* const tot[7] = {&es->n_jobs, &es->total_items, &es->n_jobs128, &es->total_items128, &es->n_rjobs,
+                             &es->total_rows, &es->running};
+    block_scan<7>(v, tot);
     if (t == 0) {
         es->next_item = 0;
         es->next_item128 = 0;
@@ -477,6 +479,13 @@ __global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __rest
             }
         }
     }
+}
+
+__global__ __launch_bounds__(256) void engine_plan_kernel(const SlotDesc* __restrict__ descs, SlotState* states,
+                                                          const int32_t* __restrict__ rules_tab, int32_t* go_tab,
+                                                          const int32_t* __restrict__ mode_tab, Job* jobs,
+                                                          EngineState* es, const int32_t* __restrict__ large_ids) {
+    engine_plan_body(descs, states, rules_tab, go_tab, mode_tab, jobs, es, large_ids);
 }
 
 // One row of A |= B x C for a row-gather rule, by one wavefront (the first
@@ -765,14 +774,26 @@ __global__ __launch_bounds__(256) void engine_tplan_kernel(const SlotDesc* __res
 
 // Transposes of the loop's work list: an item is one 256 x 256 tile
 // (load_transpose256, as in transpose_kernel); each wavefront takes items
-// w, w + waves, ... (static striding: items are cheap and uniform).
+// w, w + waves, ... (static striding: items are cheap and uniform).  With
+// `plan` set, the last workgroup plans the next loop instead (the plan reads
+// nothing the transposes write, and the next loop's products wait for both):
+// one launch less per loop.
 __global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* __restrict__ descs,
+                                                               SlotState* states,
+                                                               const int32_t* __restrict__ rules_tab,
                                                                const int32_t* __restrict__ trans_tab,
-                                                               const Job* __restrict__ tjobs, EngineState* es) {
+                                                               int32_t* go_tab, const int32_t* __restrict__ mode_tab,
+                                                               Job* jobs, const Job* __restrict__ tjobs,
+                                                               EngineState* es, const int32_t* __restrict__ large_ids,
+                                                               int32_t plan) {
+    if (plan && blockIdx.x == gridDim.x - 1) {
+        engine_plan_body(descs, states, rules_tab, go_tab, mode_tab, jobs, es, large_ids);
+        return;
+    }
     const int n_jobs = es->n_tjobs;
     const int total = es->total_titems;
     const int lane = threadIdx.x & 63;
-    const int waves = gridDim.x * (blockDim.x >> 6);
+    const int waves = (gridDim.x - (plan ? 1 : 0)) * (blockDim.x >> 6);
     for (int item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); item < total; item += waves) {
         const Job jb = tjobs[job_of(tjobs, n_jobs, item)];
         const SlotDesc& d = descs[jb.slot];
@@ -794,20 +815,21 @@ __global__ __launch_bounds__(256) void engine_transpose_kernel(const SlotDesc* _
     }
 }
 
-// End of a loop: count it for every slot that took part; a slot whose loop set
-// no bit has reached its fixpoint.
+// End of a loop: count it and its products for every slot that took part; a
+// slot whose loop set no bit has reached its fixpoint.
 __device__ void engine_finish_body(SlotState* states, EngineState* es, const SlotDesc* __restrict__ descs,
-                                   const int32_t* __restrict__ large_ids) {
-    __shared__ int32_t running;
+                                   const int32_t* __restrict__ go_tab, const int32_t* __restrict__ large_ids) {
     const int n_large = es->n_large;
-    if (threadIdx.x == 0) running = 0;
-    __syncthreads();
     for (int q = threadIdx.x; q < n_large; q += blockDim.x) {
         const int slot = large_ids[q];
         SlotState* st = states + slot;
         if (st->in_loop) {
             st->iterations += 1;
-            const int n_nt = descs[slot].n_nt;
+            const SlotDesc& d = descs[slot];
+            int launched = 0;
+            for (int r = 0; r < d.n_rules; ++r) launched += go_tab[d.rule_off + r];
+            st->products += launched;
+            const int n_nt = d.n_nt;
             int any = 0;
             for (int a = 0; a < n_nt; ++a) any |= st->changed[a];
             if (!any) {
@@ -818,10 +840,7 @@ __device__ void engine_finish_body(SlotState* states, EngineState* es, const Slo
             }
             st->in_loop = 0;
         }
-        if (st->active) atomicAdd(&running, 1);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) es->running = running;
 }
 
 // The end of a loop in one launch: the transposes of the right operands this
@@ -831,11 +850,12 @@ __device__ void engine_finish_body(SlotState* states, EngineState* es, const Slo
 __global__ __launch_bounds__(256) void engine_tplan_finish_kernel(const SlotDesc* __restrict__ descs,
                                                                   SlotState* states,
                                                                   const int32_t* __restrict__ trans_tab,
-                                                                  Job* tjobs, EngineState* es,
+                                                                  const int32_t* __restrict__ go_tab, Job* tjobs,
+                                                                  EngineState* es,
                                                                   const int32_t* __restrict__ large_ids) {
     engine_tplan_body(descs, states, trans_tab, tjobs, es, large_ids, 0);
     __syncthreads();
-    engine_finish_body(states, es, descs, large_ids);
+    engine_finish_body(states, es, descs, go_tab, large_ids);
 }
 
 }  // namespace
@@ -883,21 +903,37 @@ hipError_t engine_products(const EngineBuffers& b, int32_t grid, int32_t rows_gr
     return hipGetLastError();
 }
 
+hipError_t engine_capture_loops(const EngineBuffers& b, int32_t loops, int32_t grid, int32_t rows_grid,
+                                int32_t grid_t, hipStream_t cs, hipGraph_t* graph) {
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t ce = hipSuccess;
+    for (int32_t it = 0; it < loops && ce == hipSuccess; ++it) {
+        ce = engine_products(b, grid, rows_grid, cs);
+        if (ce == hipSuccess) ce = engine_tplan_finish(b, cs);
+        if (ce == hipSuccess) ce = engine_transposes(b, grid_t, 1, cs);
+    }
+    e = hipStreamEndCapture(cs, graph);
+    return ce != hipSuccess ? ce : e;
+}
+
 hipError_t engine_tplan(const EngineBuffers& b, int32_t fresh, hipStream_t s) {
     engine_tplan_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.trans_tab, b.tjobs, b.es, b.large_ids,
                                                       fresh);
     return hipGetLastError();
 }
 
-hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, hipStream_t s) {
-    engine_transpose_kernel<<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, s>>>(b.descs, b.trans_tab, b.tjobs,
-                                                                                  b.es);
+hipError_t engine_transposes(const EngineBuffers& b, int32_t grid, int32_t plan, hipStream_t s) {
+    const unsigned blocks = static_cast<unsigned>(grid + (plan ? 1 : 0));
+    engine_transpose_kernel<<<dim3(blocks), dim3(256), 0, s>>>(b.descs, b.states, b.rules_tab, b.trans_tab,
+                                                               b.go_tab, b.mode_tab, b.jobs, b.tjobs, b.es,
+                                                               b.large_ids, plan ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t engine_tplan_finish(const EngineBuffers& b, hipStream_t s) {
-    engine_tplan_finish_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.trans_tab, b.tjobs, b.es,
-                                                             b.large_ids);
+    engine_tplan_finish_kernel<<<dim3(1), dim3(256), 0, s>>>(b.descs, b.states, b.trans_tab, b.go_tab, b.tjobs,
+                                                             b.es, b.large_ids);
     return hipGetLastError();
 }
 

@@ -366,9 +366,13 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
             SRV_HIP(hipMemcpyAsync(srv->b.large_ids, large.data(), 4 * large.size(), hipMemcpyHostToDevice, s));
         SRV_HIP(hipMemcpyAsync(&srv->b.es->n_large, &nl, 4, hipMemcpyHostToDevice, s));
     }
+    // The captured loops start planned: the plan comes from the slot list just
+    // written (a plan left by the last replay may name slots retired since).
     if (!admitted.empty() && nl > 0) {
         SRV_HIP(engine_tplan(srv->b, 1, s));
-        SRV_HIP(engine_transposes(srv->b, 4 * srv->cus, s));
+        SRV_HIP(engine_transposes(srv->b, 4 * srv->cus, 1, s));
+    } else if (nl > 0) {
+        SRV_HIP(engine_plan(srv->b, s));
     }
     if (nl > 0) SRV_HIP(hipGraphLaunch(srv->exec, s));
     // ---- 4. retire ----
@@ -686,18 +690,11 @@ cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, c
     // The large engine's loops, captured once; membership is read from the device.
     hipStream_t cs = nullptr;
     CFPQ_HIP(capture_stream(&cs));
-    CFPQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = hipSuccess;
-    for (int32_t it = 0; it < cfg.capture && ce == hipSuccess; ++it) {
-        ce = engine_plan(srv->b, cs);
-        if (ce == hipSuccess) ce = engine_products(srv->b, srv->cus, 2 * srv->cus, cs);
-        if (ce == hipSuccess) ce = engine_tplan_finish(srv->b, cs);
-        if (ce == hipSuccess) ce = engine_transposes(srv->b, 4 * srv->cus, cs);
-    }
-    hipError_t ee = hipStreamEndCapture(cs, &srv->graph);
-    if (ce != hipSuccess || ee != hipSuccess) {
+    const hipError_t ce = engine_capture_loops(srv->b, cfg.capture, srv->cus, 2 * srv->cus, 4 * srv->cus, cs,
+                                               &srv->graph);
+    if (ce != hipSuccess) {
         hipFree(srv->dmem);
-        return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
+        return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
     }
     CFPQ_HIP(hipGraphInstantiate(&srv->exec, srv->graph, nullptr, nullptr, 0));
     CFPQ_HIP(hipStreamSynchronize(srv->stream));
