@@ -529,8 +529,7 @@ def main():
     if path_used in ("mfma", "fp4"):
         roof["traffic"] = profiled_traffic(f"{path_used}_product_er16384_dyck.md", roof["kernel"],
                                            ["paper_1707_01007_amd/csrc/mfma_tile.h",
-                                            "paper_1707_01007_amd/csrc/kernels_mfma.hip",
-                                            "paper_1707_01007_amd/csrc/cfpq_internal.h"])
+                                            "paper_1707_01007_amd/csrc/kernels_mfma.hip"])
     roof["per_launch_bitops"] = per_launch
     line = {
         "metric": METRIC,

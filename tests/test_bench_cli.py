@@ -66,8 +66,7 @@ def test_committed_traffic_matches_the_kernel_sources():
     """roofline.traffic comes from the committed rocprofv3 summaries only while
     the MFMA kernel's sources are the ones they were measured on."""
     import bench
-    src = ["paper_1707_01007_amd/csrc/mfma_tile.h", "paper_1707_01007_amd/csrc/kernels_mfma.hip",
-           "paper_1707_01007_amd/csrc/cfpq_internal.h"]
+    src = ["paper_1707_01007_amd/csrc/mfma_tile.h", "paper_1707_01007_amd/csrc/kernels_mfma.hip"]
     for md, kern in (("fp4_product_er16384_dyck.md", bench.fp4_kernel_name(bench.FP4_DEFAULT_TILE)),
                      ("mfma_product_er16384_dyck.md", "mfma_product_kernel<false, 2>")):
         t = bench.profiled_traffic(md, kern, src)
