@@ -68,15 +68,41 @@ def _blas_product_rate(inst, seconds_target=4.0):
                       f"{reps} time(s), {dt:.1f} s"}
 
 
-def cpu_baseline(cfpq, torch, inst, sample_n=8192):
+def _bitset_closure_rate(inst, closure_bitops):
+    """Algorithm 1 on bit-packed rows (oracle/cfpq_bitset.c, OpenMP over the
+    rows of each product) on the whole benchmark workload, all host cores: the
+    plain multi-core CPU closure.  Its result is checked against the worklist
+    oracle's stored digest for this workload."""
+    import hashlib
+    import json as _json
+    import numpy as np
+    from oracle import bitset
+    threads = len(os.sched_getaffinity(0))
+    bitset.closure(64, inst.edges[:0], inst.grammar, threads=threads)  # loads the library
+    t = time.perf_counter()
+    bits, loops, rc = bitset.closure(inst.n, inst.edges, inst.grammar, threads=threads)
+    dt = time.perf_counter() - t
+    gold = _json.load(open(os.path.join(ROOT, "tests", "golden", "digests.json"))).get(inst.tag, {})
+    digest = hashlib.sha256(np.ascontiguousarray(bits).astype("<u8").tobytes()).hexdigest()
+    return {"value": round(closure_bitops / dt / 1e9, 3), "unit": "Gbitop/s", "threads": threads,
+            "time_to_solution_s": round(dt, 3), "jacobi_loops": loops, "n": inst.n,
+            "identical_to_oracle_digest": digest == gold.get("sha256") if gold else None,
+            "sample": f"bit-packed Algorithm 1 (Jacobi, OpenMP over rows), whole closure of {inst.tag} on "
+                      f"{threads} threads: {dt:.2f} s; value = the dense GPU closure's {closure_bitops:.3e} "
+                      f"bit-ops / that time"}
+
+
+def cpu_baseline(cfpq, torch, inst, sample_n=8192, closure_bitops=None):
     """The C worklist oracle's time to the fixpoint, single-threaded, on the
     same recipe (ER Dyck, seed 3) at n = sample_n, a bounded sample of the
     n = 16384 workload (about 15-90 s of CPU work, by the host).  ``value`` puts it in the
     metric's unit: the bit-operations the GPU's dense closure executes on that
     instance (2 npad^3 per product, as for the headline) divided by the
     oracle's time to the same relations.  The full-size oracle time comes from
-    the digest run that stored the n = 16384 result; the oracle's float64
-    BLAS product rate is a second, separate figure."""
+    the digest run that stored the n = 16384 result.  Separate figures: the
+    oracle's float64 BLAS product rate, and the bit-packed Algorithm 1 on all
+    host cores over the whole workload (``closure_bitops``: the GPU closure's
+    bit-operations on it)."""
     import json as _json
     from oracle import worklist
     from workloads import configs
@@ -98,7 +124,8 @@ def cpu_baseline(cfpq, torch, inst, sample_n=8192):
             "full_size": {"n": inst.n, "time_to_solution_s": full.get("oracle_seconds"),
                           "where": full.get("oracle_host", "digest run on the build host"),
                           "date": full.get("oracle_date")},
-            "blas_product": _blas_product_rate(inst)}
+            "blas_product": _blas_product_rate(inst),
+            "bitset_closure": _bitset_closure_rate(inst, closure_bitops) if closure_bitops else None}
 
 
 def profiled_traffic(profile_md, kernel, sources):
@@ -563,7 +590,7 @@ def main():
     if not args.no_serve:
         line["serving"] = bench_serve(cfpq, torch)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfpq, torch, inst)
+        line["cpu_baseline"] = cpu_baseline(cfpq, torch, inst, closure_bitops=res.stats["bitops"])
     print(json.dumps(line), flush=True)
 
 

@@ -33,8 +33,8 @@ def test_options():
 def test_cpu_baseline_fields():
     """The CPU baseline object: the oracle's single-thread time to the fixpoint
     on a sample of the workload's recipe, in the metric's unit, with the
-    host's core count, the full-size oracle time and the BLAS product rate as
-    separate fields.  The GPU closure (for the sample's bit-op count) is a
+    host's core count, the full-size oracle time, the BLAS product rate and
+    the all-core bit-packed closure as separate fields.  The GPU closure (for the sample's bit-op count) is a
     stand-in here that returns the oracle's own bits."""
     import types
 
@@ -54,12 +54,16 @@ def test_cpu_baseline_fields():
 
     fake_torch = types.SimpleNamespace(from_numpy=lambda a: types.SimpleNamespace(cuda=lambda: a))
     inst = configs.config3(1024)
-    cb = bench.cpu_baseline(FakeGpu(), fake_torch, inst, sample_n=512)
+    cb = bench.cpu_baseline(FakeGpu(), fake_torch, inst, sample_n=512, closure_bitops=1e12)
     assert cb["kind"] == "oracle_closure" and cb["unit"] == "Gbitop/s" and cb["cores"] == 1
     assert cb["value"] > 0 and cb["time_to_solution_s"] > 0 and cb["identical_to_gpu"]
     assert cb["host_nproc"] >= 1 and "n=512" in cb["sample"]
     assert cb["full_size"]["time_to_solution_s"] > 0
     assert cb["blas_product"]["value"] > 0 and "n=1024" in cb["blas_product"]["sample"]
+    # the all-core bit-packed closure of the whole workload, checked against the oracle's digest
+    bs = cb["bitset_closure"]
+    assert bs["value"] > 0 and bs["threads"] == cb["host_nproc"] and bs["n"] == 1024
+    assert bs["identical_to_oracle_digest"] is True and bs["jacobi_loops"] > 1
 
 
 def test_committed_traffic_matches_the_kernel_sources():
