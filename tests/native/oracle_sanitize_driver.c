@@ -4,9 +4,9 @@
  *   n n_edges n_nt n_terminals n_term n_bin
  *   n_edges lines "src label dst", n_term lines "lhs terminal",
  *   n_bin lines "lhs left right"
- * runs cfpq_oracle and cfpq_single_path_oracle on it, and prints one line per
- * case: the two return codes, the single-path loop count and FNV-1a 64
- * checksums of both output buffers.  Built with -fsanitize=address,undefined
+ * runs cfpq_oracle, cfpq_single_path_oracle and cfpq_bitset_closure on it,
+ * and prints one line per case: the three return codes, the single-path and
+ * bit-packed loop counts and FNV-1a 64 checksums of the three output buffers.  Built with -fsanitize=address,undefined
  * together with the oracle sources; any report aborts the process.
  */
 #include <stdint.h>
@@ -19,6 +19,9 @@ int cfpq_oracle(int32_t n, int64_t n_edges, const int32_t *edges, int32_t n_nt, 
 int cfpq_single_path_oracle(int32_t n, int64_t n_edges, const int32_t *edges, int32_t n_nt, int32_t n_terminals,
                             int32_t n_term, const int32_t *term, int32_t n_bin, const int32_t *bin,
                             int64_t max_loops, uint32_t *out, int64_t *loops_out);
+int cfpq_bitset_closure(int32_t n, int64_t n_edges, const int32_t *edges, int32_t n_nt, int32_t n_terminals,
+                        int32_t n_term, const int32_t *term, int32_t n_bin, const int32_t *bin, int64_t max_loops,
+                        int32_t threads, uint64_t *out, int64_t *loops_out);
 
 static uint64_t fnv(const void *p, size_t bytes) {
     const unsigned char *c = (const unsigned char *)p;
@@ -48,20 +51,25 @@ int main(void) {
         const long words = n > 0 ? (n + 63) / 64 : 1;
         uint64_t *bits = calloc((size_t)(nnt * (n > 0 ? n : 1) * words), sizeof(uint64_t));
         uint32_t *lengths = calloc((size_t)(nnt * (n > 0 ? n * n : 1)), sizeof(uint32_t));
-        int64_t loops = 0;
-        if (!bits || !lengths) return 2;
+        uint64_t *bits3 = calloc((size_t)(nnt * (n > 0 ? n : 1) * words), sizeof(uint64_t));
+        int64_t loops = 0, loops3 = 0;
+        if (!bits || !lengths || !bits3) return 2;
         const int rc1 = cfpq_oracle((int32_t)n, m, edges, (int32_t)nnt, (int32_t)nt, (int32_t)nterm, term,
                                     (int32_t)nbin, bin, bits, words);
         const int rc2 = cfpq_single_path_oracle((int32_t)n, m, edges, (int32_t)nnt, (int32_t)nt, (int32_t)nterm,
                                                 term, (int32_t)nbin, bin, 0, lengths, &loops);
-        printf("%d %d %lld %016llx %016llx\n", rc1, rc2, (long long)loops,
+        const int rc3 = cfpq_bitset_closure((int32_t)n, m, edges, (int32_t)nnt, (int32_t)nt, (int32_t)nterm, term,
+                                            (int32_t)nbin, bin, 0, 2, bits3, &loops3);
+        printf("%d %d %d %lld %lld %016llx %016llx %016llx\n", rc1, rc2, rc3, (long long)loops, (long long)loops3,
                (unsigned long long)fnv(bits, sizeof(uint64_t) * (size_t)(nnt * n * words)),
-               (unsigned long long)fnv(lengths, sizeof(uint32_t) * (size_t)(nnt * n * n)));
+               (unsigned long long)fnv(lengths, sizeof(uint32_t) * (size_t)(nnt * n * n)),
+               (unsigned long long)fnv(bits3, sizeof(uint64_t) * (size_t)(nnt * n * words)));
         free(edges);
         free(term);
         free(bin);
         free(bits);
         free(lengths);
+        free(bits3);
     }
     return 0;
 }

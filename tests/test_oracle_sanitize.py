@@ -1,7 +1,9 @@
-"""The C oracles built with AddressSanitizer and UndefinedBehaviorSanitizer
-(host code only; a small C driver feeds them the cases): no report on the
-worked example, ragged random graphs, empty and one-node graphs and a grammar
-without binary rules, and the same outputs as the ordinary builds."""
+"""The C oracles (worklist closure, single-path lengths, bit-packed Algorithm
+1 on two OpenMP threads) built with AddressSanitizer and
+UndefinedBehaviorSanitizer (host code only; a small C driver feeds them the
+cases): no report on the worked example, ragged random graphs, empty and
+one-node graphs and a grammar without binary rules, and the same outputs as
+the ordinary builds."""
 from __future__ import annotations
 
 import os
@@ -11,7 +13,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from oracle import single_path, worklist
+from oracle import bitset, single_path, worklist
 from workloads import configs, grammars, graphs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -44,11 +46,11 @@ def test_oracles_under_sanitizers(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("no gcc")
     exe = tmp_path / "driver"
-    r = subprocess.run(["gcc", "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer",
+    r = subprocess.run(["gcc", "-std=gnu11", "-O1", "-g", "-fno-omit-frame-pointer", "-fopenmp",
                         "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                         os.path.join(HERE, "native", "oracle_sanitize_driver.c"),
                         os.path.join(ORACLE, "cfpq_worklist.c"), os.path.join(ORACLE, "cfpq_single_path.c"),
-                        "-o", str(exe)], capture_output=True, text=True)
+                        os.path.join(ORACLE, "cfpq_bitset.c"), "-o", str(exe)], capture_output=True, text=True)
     if r.returncode != 0 and "sanitize" in r.stderr:
         pytest.skip("gcc without sanitizer runtimes: " + r.stderr[-200:])
     assert r.returncode == 0, r.stderr
@@ -67,9 +69,12 @@ def test_oracles_under_sanitizers(tmp_path):
     assert "runtime error" not in run.stderr and "AddressSanitizer" not in run.stderr, run.stderr[-2000:]
     got = run.stdout.split("\n")
     for (n, e, g), line in zip(cases, got):
-        rc1, rc2, loops, h1, h2 = line.split()
+        rc1, rc2, rc3, loops, loops3, h1, h2, h3 = line.split()
         bits = worklist.closure(n, e, g)
         L, loops_c, rc = single_path.lengths_native(n, e, g)
+        _, loops_b, _ = bitset.closure(n, e, g)
         assert int(rc1) == 0 and int(rc2) == rc and int(loops) == loops_c
+        assert int(rc3) == 0 and int(loops3) == loops_b
         assert int(h1, 16) == _fnv(np.ascontiguousarray(bits).tobytes())
         assert int(h2, 16) == _fnv(np.ascontiguousarray(L).tobytes())
+        assert int(h3, 16) == int(h1, 16)  # the same relations in the same layout
