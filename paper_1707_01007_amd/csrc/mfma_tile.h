@@ -14,7 +14,8 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kJT = 4;  // 32-row blocks of j per wavefront
-constexpr int kIT = 4;  // 32-column blocks of i per wavefront
+constexpr int kIT = 4;  // 32-column blocks of i per wavefront (the default; the fp4
+                        // tile also comes with 2, for two wavefronts per SIMD)
 
 // Operand dwords of one 32-bit k-word for lane half g: dword q keeps bits
 // 8t + q + 4g (t = 0..3) in place, i.e. byte t = (bit ? 2^(q+4g) : 0).
@@ -29,17 +30,20 @@ __device__ __forceinline__ v4i spread(uint32_t w, uint32_t mask0) {
 
 constexpr int kChunkWords = 4;  // 32-bit k-words per fragment row and chunk (128 k)
 
-struct Chunk {
+template <int kI = kIT>
+struct ChunkT {
     uint4 c[kJT];
-    uint4 b[kIT];
+    uint4 b[kI];
 };
+using Chunk = ChunkT<kIT>;
 
-__device__ __forceinline__ void load_chunk(Chunk& ch, const uint4* const (&crow)[kJT],
-                                           const uint4* const (&brow)[kIT], int kc) {
+template <int kI>
+__device__ __forceinline__ void load_chunk(ChunkT<kI>& ch, const uint4* const (&crow)[kJT],
+                                           const uint4* const (&brow)[kI], int kc) {
 #pragma unroll
     for (int jb = 0; jb < kJT; ++jb) ch.c[jb] = crow[jb][kc];
 #pragma unroll
-    for (int ib = 0; ib < kIT; ++ib) ch.b[ib] = brow[ib][kc];
+    for (int ib = 0; ib < kI; ++ib) ch.b[ib] = brow[ib][kc];
 }
 
 __device__ __forceinline__ uint32_t word_of(const uint4& u, int q) {
@@ -72,12 +76,14 @@ __device__ __forceinline__ void mma_chunk(v16i (&acc)[kJT][kIT], const Chunk& ch
 // same head in one batched loop); otherwise a plain read-modify-write by the
 // tile's only writer.  rowbits (optional): bitmap over the rows of A; the
 // bits of rows that gained bits are OR-ed in.
-template <bool kAtomic, typename Acc>
-__device__ __forceinline__ void store_tile(const Acc (&acc)[kJT][kIT], uint32_t* Am, int W2, int i0, int j0, int g,
+template <bool kAtomic, typename Acc, int kI>
+__device__ __forceinline__ void store_tile(const Acc (&acc)[kJT][kI], uint32_t* Am, int W2, int i0, int j0, int g,
                                            int r32, int lane, int32_t* changed, uint64_t* rowbits = nullptr) {
-    bool ch = false;
+    // The lane's new bits for its kI rows (one 64-bit word each) ...
+    uint64_t add[kI];
+    uint64_t* dst[kI];
 #pragma unroll
-    for (int ib = 0; ib < kIT; ++ib) {
+    for (int ib = 0; ib < kI; ++ib) {
         uint32_t word[kJT];
 #pragma unroll
         for (int jb = 0; jb < kJT; ++jb) {
@@ -93,25 +99,38 @@ __device__ __forceinline__ void store_tile(const Acc (&acc)[kJT][kIT], uint32_t*
         // lanes with g = 0 write columns j0..j0+63, g = 1 write j0+64..j0+127
         const uint64_t lo = g == 0 ? word[0] : word[2];
         const uint64_t hi = g == 0 ? word[1] : word[3];
-        const uint64_t add = lo | (hi << 32);
+        add[ib] = lo | (hi << 32);
         const int i = i0 + ib * 32 + r32;
-        uint64_t* dst = reinterpret_cast<uint64_t*>(Am + static_cast<size_t>(i) * W2) + (j0 / 64) + g;
-        const uint64_t old = *dst;
-        bool gained = false;
-        if ((add & ~old) != 0) {
-            if (kAtomic) {
-                const uint64_t prev = atomicOr(reinterpret_cast<unsigned long long*>(dst),
-                                               static_cast<unsigned long long>(add));
-                gained = (add & ~prev) != 0;
-            } else {
-                *dst = old | add;
-                gained = true;
-            }
+        dst[ib] = reinterpret_cast<uint64_t*>(Am + static_cast<size_t>(i) * W2) + (j0 / 64) + g;
+    }
+    // ... then every old word read before any is written (different rows),
+    // and every atomic issued before any result is used: one memory round
+    // trip each instead of one per row block.
+    uint64_t old[kI];
+#pragma unroll
+    for (int ib = 0; ib < kI; ++ib) old[ib] = *dst[ib];
+    bool gained[kI];
+    uint64_t prev[kI];
+#pragma unroll
+    for (int ib = 0; ib < kI; ++ib) {
+        gained[ib] = (add[ib] & ~old[ib]) != 0;
+        prev[ib] = old[ib];
+        if (gained[ib]) {
+            if (kAtomic)
+                prev[ib] = atomicOr(reinterpret_cast<unsigned long long*>(dst[ib]),
+                                    static_cast<unsigned long long>(add[ib]));
+            else
+                *dst[ib] = old[ib] | add[ib];
         }
-        ch = ch || gained;
+    }
+    bool ch = false;
+#pragma unroll
+    for (int ib = 0; ib < kI; ++ib) {
+        if (kAtomic) gained[ib] = gained[ib] && (add[ib] & ~prev[ib]) != 0;
+        ch = ch || gained[ib];
         if (rowbits != nullptr) {
             // rows i0 + 32 ib .. + 31 (lanes r32 of both halves) lie in one 64-row word
-            const uint64_t m = __ballot(gained);
+            const uint64_t m = __ballot(gained[ib]);
             const uint64_t rows = (m | (m >> 32)) & 0xFFFFFFFFull;
             const int base = i0 + ib * 32;
             if (lane == 0 && rows != 0)
@@ -209,23 +228,25 @@ __device__ __forceinline__ v4i spread4(uint32_t w) {
 
 // kChunkWords steps of 64 k (this lane's k-word s and its partner's):
 // per step 8 operand fragments and 16 MFMAs.
-__device__ __forceinline__ void mma_chunk4(v16f (&acc)[kJT][kIT], const Chunk& ch) {
+template <int kI>
+__device__ __forceinline__ void mma_chunk4(v16f (&acc)[kJT][kI], const ChunkT<kI>& ch) {
 #pragma unroll
     for (int s = 0; s < kChunkWords; ++s) {
-        v4i ca[kJT], bb[kIT];
+        v4i ca[kJT], bb[kI];
 #pragma unroll
         for (int jb = 0; jb < kJT; ++jb) ca[jb] = spread4(word_of(ch.c[jb], s));
 #pragma unroll
-        for (int ib = 0; ib < kIT; ++ib) bb[ib] = spread4(word_of(ch.b[ib], s));
+        for (int ib = 0; ib < kI; ++ib) bb[ib] = spread4(word_of(ch.b[ib], s));
 #pragma unroll
         for (int jb = 0; jb < kJT; ++jb)
 #pragma unroll
-            for (int ib = 0; ib < kIT; ++ib)
+            for (int ib = 0; ib < kI; ++ib)
                 acc[jb][ib] = mfma_f32_32x32x64_fp4(ca[jb], bb[ib], acc[jb][ib], kFmtFp4, kFmtFp4, 0, 0, 0, 0);
     }
 }
 
-// One wavefront's 128 x 128 output block (rows i0.., columns j0..) of
+// One wavefront's 32 kI x 128 output block (rows i0.., columns j0..; 128 x
+// 128 with the default kI = 4) of
 // A |= B x C on the fp4 MFMA, CT = C^T, over kchunks chunks of 256 k (any
 // count >= 1): lane half g reads dwords 8c + 4g .. 8c + 4g + 3 of chunk c, so
 // one 64-k MFMA step takes k-word s from each half.  kStages chunk buffers in
@@ -233,7 +254,7 @@ __device__ __forceinline__ void mma_chunk4(v16f (&acc)[kJT][kIT], const Chunk& c
 // multiplied; prefetches past the end re-read the last chunk (in bounds)
 // instead of branching.  No barriers: any wavefront may call it on its own.
 // kAtomic as in store_tile.
-template <bool kAtomic, int kStages = 2>
+template <bool kAtomic, int kStages = 2, int kI = kIT>
 __device__ __forceinline__ void mfma4_wave_tile(const uint32_t* __restrict__ Bm, const uint32_t* __restrict__ CT,
                                                 uint32_t* Am, int W2, int kchunks, int i0, int j0,
                                                 int32_t* changed, uint64_t* rowbits = nullptr) {
@@ -244,19 +265,19 @@ __device__ __forceinline__ void mfma4_wave_tile(const uint32_t* __restrict__ Bm,
 
     // uint4 index 2c of these pointers is chunk c's dwords for this half
     const uint4* crow[kJT];
-    const uint4* brow[kIT];
+    const uint4* brow[kI];
 #pragma unroll
     for (int jb = 0; jb < kJT; ++jb)
         crow[jb] = reinterpret_cast<const uint4*>(CT + static_cast<size_t>(j0 + jb * 32 + r32) * W2) + g;
 #pragma unroll
-    for (int ib = 0; ib < kIT; ++ib)
+    for (int ib = 0; ib < kI; ++ib)
         brow[ib] = reinterpret_cast<const uint4*>(Bm + static_cast<size_t>(i0 + ib * 32 + r32) * W2) + g;
 
-    v16f acc[kJT][kIT];
+    v16f acc[kJT][kI];
 #pragma unroll
     for (int jb = 0; jb < kJT; ++jb)
 #pragma unroll
-        for (int ib = 0; ib < kIT; ++ib)
+        for (int ib = 0; ib < kI; ++ib)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[jb][ib][e] = 0.0f;
 
@@ -264,7 +285,7 @@ __device__ __forceinline__ void mfma4_wave_tile(const uint32_t* __restrict__ Bm,
     // The scheduling barriers keep each prefetch ahead of the multiplies that
     // follow it (the scheduler would otherwise sink the loads to their uses).
     if (kStages == 2) {
-        Chunk buf0, buf1;
+        ChunkT<kI> buf0, buf1;
         load_chunk(buf0, crow, brow, 0);
         int kc = 0;
         for (; kc + 1 < kchunks; kc += 2) {
@@ -279,7 +300,7 @@ __device__ __forceinline__ void mfma4_wave_tile(const uint32_t* __restrict__ Bm,
         }
         if (kc < kchunks) mma_chunk4(acc, buf0);
     } else {
-        Chunk buf0, buf1, buf2;
+        ChunkT<kI> buf0, buf1, buf2;
         load_chunk(buf0, crow, brow, 0);
         load_chunk(buf1, crow, brow, 2 * min(1, last));
         int kc = 0;
