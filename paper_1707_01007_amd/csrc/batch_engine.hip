@@ -589,8 +589,9 @@ __device__ void engine_push_block(const SlotDesc& d, const uint64_t* BT, const u
     if (any && lane == 0) raise_flag(changed);
 }
 
-// The loop's row-gather work, one wavefront per item, grid-stride (items of
-// one slot and rule are contiguous in the list).  In a slot's first
+// The loop's row-gather work, one wavefront per item, in runs of items
+// strided over the wavefronts (items of one slot and rule are contiguous in
+// the list).  In a slot's first
 // kPullLoops loops (most rows of C are new), and in every loop of a slot
 // without changed-row bitmaps, an item is a row of A, gathered from the rows
 // of C its row of B selects.  Otherwise the work is pushed from the rows of
@@ -609,40 +610,68 @@ __global__ __launch_bounds__(256) void engine_rows_kernel(const SlotDesc* __rest
     const int total = es->total_rows;
     const Job* rjobs = jobs + es->n_jobs + es->n_jobs128;
     const int waves = gridDim.x * 4;
-    for (int x = blockIdx.x * 4 + (threadIdx.x >> 6); x < total; x += waves) {
-        const Job jb = rjobs[job_of(rjobs, n_rjobs, x)];
-        const SlotDesc& d = descs[jb.slot];
-        const int r = d.rule_off + jb.what;
-        const int ra = rules_tab[3 * r], rb = rules_tab[3 * r + 1], rc = rules_tab[3 * r + 2];
-        const size_t mw = static_cast<size_t>(d.npad) * d.W;
-        const int64_t it = states[jb.slot].iterations;
-        const size_t bw = static_cast<size_t>(d.W);
-        int32_t* changed = &states[jb.slot].changed[ra];
-        if (jb.dim == 1) {  // pull: x - item_begin is a row of A
-            const int64_t row = x - jb.item_begin;
-            // changed rows are recorded from the last pull loop on: the first
-            // push loop reads the bitmaps of that loop and its own, and the
-            // bitmap of an earlier loop is cleared before anything reads it
-            uint64_t* arows = d.RD && it >= kPullLoops - 1
-                                  ? d.RD + (static_cast<size_t>(it & 1) * d.n_nt + ra) * bw
-                                  : nullptr;
-            if (d.W <= 64)
-                engine_gather_row<1>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed, arows);
+    // Each wavefront takes runs of `run` consecutive items (strided over the
+    // waves): the item's job is searched once per run and then followed
+    // forward, and its slot's descriptor and state are read once per job --
+    // against a binary search and a few dependent reads per row, which were
+    // most of the latency of a row.  Runs shrink to single items when the loop
+    // has few, so they still spread over every wavefront.
+    const int run = max(1, min(16, total / (2 * waves)));
+    for (int x0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * run; x0 < total; x0 += waves * run) {
+        const int x1 = min(total, x0 + run);
+        int j = job_of(rjobs, n_rjobs, x0) - 1;
+        int j_end = x0;  // loads job j + 1 at the first item
+        // the current job's slot, rule operands and row bitmaps
+        Job jb{};
+        const SlotDesc* d = nullptr;
+        int ra = 0, rb = 0, rc = 0;
+        size_t mw = 0, bw = 0;
+        int32_t* changed = nullptr;
+        uint64_t* arows = nullptr;
+        uint64_t* cur = nullptr;
+        const uint64_t* prev = nullptr;
+        for (int x = x0; x < x1; ++x) {
+            if (x >= j_end) {  // the next job (also where the run crosses into one)
+                do {
+                    ++j;
+                    j_end = j + 1 < n_rjobs ? rjobs[j + 1].item_begin : total;
+                } while (x >= j_end);
+                jb = rjobs[j];
+                d = descs + jb.slot;
+                const int r = d->rule_off + jb.what;
+                ra = rules_tab[3 * r];
+                rb = rules_tab[3 * r + 1];
+                rc = rules_tab[3 * r + 2];
+                mw = static_cast<size_t>(d->npad) * d->W;
+                bw = static_cast<size_t>(d->W);
+                const int64_t it = states[jb.slot].iterations;
+                changed = &states[jb.slot].changed[ra];
+                // changed rows are recorded from the last pull loop on: the first
+                // push loop reads the bitmaps of that loop and its own, and the
+                // bitmap of an earlier loop is cleared before anything reads it
+                arows = d->RD && it >= kPullLoops - 1 ? d->RD + (static_cast<size_t>(it & 1) * d->n_nt + ra) * bw
+                                                      : nullptr;
+                cur = d->RD + static_cast<size_t>(it & 1) * d->n_nt * bw;
+                prev = d->RD + static_cast<size_t>((it + 1) & 1) * d->n_nt * bw;
+            }
+            if (jb.dim == 1) {  // pull: x - item_begin is a row of A
+                const int64_t row = x - jb.item_begin;
+                if (d->W <= 64)
+                    engine_gather_row<1>(*d, d->T + rb * mw, d->T + rc * mw, d->T + ra * mw, row, changed, arows);
+                else
+                    engine_gather_row<4>(*d, d->T + rb * mw, d->T + rc * mw, d->T + ra * mw, row, changed, arows);
+                continue;
+            }
+            const int64_t k0 = static_cast<int64_t>(x - jb.item_begin) * kPushRows;
+            const int shift = static_cast<int>(k0 & 63);
+            const uint64_t dirty = ((cur[rc * bw + (k0 >> 6)] | prev[rc * bw + (k0 >> 6)]) >> shift) & kPushMask;
+            if (dirty == 0) continue;
+            const uint64_t* BT = d->TT + static_cast<size_t>(trans_tab[d->trans_off + rb]) * mw;
+            if (d->W <= 64)
+                engine_push_block<1>(*d, BT, d->T + rc * mw, d->T + ra * mw, k0, dirty, changed, cur + ra * bw);
             else
-                engine_gather_row<4>(d, d.T + rb * mw, d.T + rc * mw, d.T + ra * mw, row, changed, arows);
-            continue;
+                engine_push_block<4>(*d, BT, d->T + rc * mw, d->T + ra * mw, k0, dirty, changed, cur + ra * bw);
         }
-        uint64_t* cur = d.RD + static_cast<size_t>(it & 1) * d.n_nt * bw;
-        const uint64_t* prev = d.RD + static_cast<size_t>((it + 1) & 1) * d.n_nt * bw;
-        const int64_t k0 = static_cast<int64_t>(x - jb.item_begin) * kPushRows;
-        const int shift = static_cast<int>(k0 & 63);
-        const uint64_t dirty = ((cur[rc * bw + (k0 >> 6)] | prev[rc * bw + (k0 >> 6)]) >> shift) & kPushMask;
-        if (dirty == 0) continue;
-        const uint64_t* BT = d.TT + static_cast<size_t>(trans_tab[d.trans_off + rb]) * mw;
-        if (d.W <= 64)
-            engine_push_block<1>(d, BT, d.T + rc * mw, d.T + ra * mw, k0, dirty, changed, cur + ra * bw);
-        else
-            engine_push_block<4>(d, BT, d.T + rc * mw, d.T + ra * mw, k0, dirty, changed, cur + ra * bw);
     }
 }
 
