@@ -19,6 +19,13 @@ cfpq_status validate_graph(const cfpq_graph* g, const cfpq_grammar* gr);  // hos
 size_t align_up(size_t x, size_t a);
 hipError_t capture_stream(hipStream_t* out);  // private stream for graph capture
 hipError_t aux_stream(hipStream_t* out);      // private stream for overlapping side work
+// Pinned host memory of at least `bytes` for a loop's read-backs: one buffer
+// per thread, grown on demand, freed when the thread ends.  Copies into it
+// queue behind the stream's work, where a copy into pageable memory returns
+// only once it has landed (a round trip per copy).  The caller synchronises
+// the stream before the buffer is reused; the no-allocation entry point does
+// not use it.
+hipError_t pinned_readback(size_t bytes, void** out);
 
 #define CFPQ_HIP(call)                                                                        \
     do {                                                                                      \

@@ -242,6 +242,28 @@ static hipError_t private_stream(int which, hipStream_t* out) {
     return hipSuccess;
 }
 
+hipError_t pinned_readback(size_t bytes, void** out) {
+    struct Buf {
+        void* p = nullptr;
+        size_t n = 0;
+        ~Buf() {
+            if (p) hipHostFree(p);
+        }
+    };
+    thread_local Buf b;
+    if (b.n < bytes) {
+        const size_t n = std::max<size_t>(bytes, 4096);
+        void* p = nullptr;
+        const hipError_t e = hipHostMalloc(&p, n, hipHostMallocPortable);
+        if (e != hipSuccess) return e;
+        if (b.p) hipHostFree(b.p);  // every copy into it has completed (callers synchronise)
+        b.p = p;
+        b.n = n;
+    }
+    *out = b.p;
+    return hipSuccess;
+}
+
 hipError_t capture_stream(hipStream_t* out) { return private_stream(0, out); }
 hipError_t aux_stream(hipStream_t* out) { return private_stream(1, out); }
 
@@ -594,6 +616,15 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     if ((p.hybrid || p.forced != kModeDense) && !converged) CFPQ_HIP(launch_rowor_reset(ROWOR, s));
     std::vector<unsigned long long> nnz(n_nt, 0), dnnz(2 * static_cast<size_t>(n_nt), 0);
     std::vector<char> written(n_nt, 0);  // a product wrote this nonterminal in the current loop
+    // read-back staging: |D| and |T| per nonterminal, then the change flags
+    unsigned long long* h_dnnz = dnnz.data();
+    int32_t* h_flags = flags.data();
+    if (!no_alloc && !captured && !converged) {
+        void* pb = nullptr;
+        CFPQ_HIP(pinned_readback(static_cast<size_t>(n_nt) * 20, &pb));
+        h_dnnz = static_cast<unsigned long long*>(pb);
+        h_flags = reinterpret_cast<int32_t*>(h_dnnz + 2 * static_cast<size_t>(n_nt));
+    }
     int64_t sparse_products = 0, delta_products = 0;
     auto count_bits = [&](const uint64_t* mats) -> cfpq_status {
         CFPQ_HIP(hipMemsetAsync(d_nnz, 0, static_cast<size_t>(n_nt) * 8, s));
@@ -734,7 +765,7 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             ++launched;
             ++products;
         }
-        CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipMemcpyAsync(h_flags, d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
         if (p.hybrid) {
             // for the nonterminals that changed: bits gained this loop, new
             // snapshot, new set-bit count (the others keep theirs)
@@ -742,9 +773,13 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             for (int32_t a = 0; a < n_nt; ++a)
                 CFPQ_HIP(launch_delta_snapshot(Y + a * mat_words, SNAP + a * mat_words, DELTA + a * mat_words, L,
                                                d_dnnz + a, d_dnnz + n_nt + a, d_flags + a, s));
-            CFPQ_HIP(hipMemcpyAsync(dnnz.data(), d_dnnz, static_cast<size_t>(n_nt) * 16, hipMemcpyDeviceToHost, s));
+            CFPQ_HIP(hipMemcpyAsync(h_dnnz, d_dnnz, static_cast<size_t>(n_nt) * 16, hipMemcpyDeviceToHost, s));
         }
         CFPQ_HIP(hipStreamSynchronize(s));
+        if (h_flags != flags.data()) {
+            std::copy(h_flags, h_flags + n_nt, flags.begin());
+            if (p.hybrid) std::copy(h_dnnz, h_dnnz + 2 * n_nt, dnnz.begin());
+        }
         if (p.hybrid)
             for (int32_t a = 0; a < n_nt; ++a)
                 if (flags[a]) nnz[a] = dnnz[n_nt + a];

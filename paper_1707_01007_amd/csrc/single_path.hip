@@ -641,6 +641,14 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
     const size_t lmat = static_cast<size_t>(L.npad) * static_cast<size_t>(L.npad);
     const int32_t kchunks = static_cast<int32_t>((L.n + 31) / 32);
     std::vector<int32_t> flags(n_nt + 1, 0);
+    // a loop's read-backs land in pinned memory (new-cell counts, change flags
+    // with the overflow flag, new-cell tiles) and one synchronisation waits
+    // for all three
+    void* pb = nullptr;
+    CFPQ_HIP(pinned_readback(static_cast<size_t>(n_nt) * 16 + 4, &pb));
+    auto* h_dcount = static_cast<unsigned long long*>(pb);
+    auto* h_flags = reinterpret_cast<int32_t*>(h_dcount + n_nt);
+    int32_t* h_tiles = h_flags + n_nt + 1;
     int64_t iters = 0, products = 0, sparse = 0;
     bool converged = grammar->n_bin_rules == 0 || graph->n_nodes == 0;
     int32_t overflow = 0;
@@ -675,10 +683,13 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
         delta_all_kernel<<<dim3(grid_for(static_cast<int64_t>(mw), 256), static_cast<unsigned>(n_nt)), dim3(256), 0,
                            s>>>(Y, X, D, d_lengths, L.W, L.npad, d_dcount, d_tflag, d_tiles);
         CFPQ_HIP(hipGetLastError());
-        CFPQ_HIP(hipMemcpyAsync(flags.data(), d_flags, static_cast<size_t>(n_nt + 1) * 4, hipMemcpyDeviceToHost, s));
-        CFPQ_HIP(hipMemcpyAsync(dcount.data(), d_dcount, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
-        CFPQ_HIP(hipMemcpyAsync(tiles.data(), d_tiles, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipMemcpyAsync(h_flags, d_flags, static_cast<size_t>(n_nt + 1) * 4, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipMemcpyAsync(h_dcount, d_dcount, static_cast<size_t>(n_nt) * 8, hipMemcpyDeviceToHost, s));
+        CFPQ_HIP(hipMemcpyAsync(h_tiles, d_tiles, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
         CFPQ_HIP(hipStreamSynchronize(s));
+        std::copy(h_flags, h_flags + n_nt + 1, flags.begin());
+        std::copy(h_dcount, h_dcount + n_nt, dcount.begin());
+        std::copy(h_tiles, h_tiles + n_nt, tiles.begin());
         if (pending) {
             // the previous loop's min-plus time, and its overflow check (the
             // flag after the change flags, read back with them): on overflow
