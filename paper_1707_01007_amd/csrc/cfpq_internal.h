@@ -201,12 +201,13 @@ inline int32_t hybrid_mode(const HybridModel& m, double nnz_b, double nnz_c, boo
     return hybrid_choice(m, nnz_b, nnz_c, left_kept, true, false).mode;
 }
 
-// Delta step of the hybrid closure (closure.hip): where *pred != 0,
-// D = cur & ~P (bits gained since the snapshot), P = cur, *count += |D|,
-// *count_cur += |cur|.
+// Delta step of the hybrid closure (closure.hip), for `matrices` consecutive
+// matrices y (mat_words apart, counts and predicates indexed by y): where
+// pred[y] != 0, D = cur & ~P (bits gained since the snapshot), P = cur,
+// count[y] += |D|, count_cur[y] += |cur|.  One launch for all of them.
 hipError_t launch_delta_snapshot(const uint64_t* cur, uint64_t* P, uint64_t* D, const Layout& L,
                                  unsigned long long* count, unsigned long long* count_cur, const int32_t* pred,
-                                 hipStream_t s);
+                                 hipStream_t s, int32_t matrices = 1);
 // *flag = 1, skipping the atomic when a relaxed device-scope load already
 // reads it set: a change flag only goes from 0 to 1 while products run, and
 // thousands of workgroups OR-ing one address queue behind each other.

@@ -770,9 +770,7 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             // for the nonterminals that changed: bits gained this loop, new
             // snapshot, new set-bit count (the others keep theirs)
             CFPQ_HIP(hipMemsetAsync(d_dnnz, 0, static_cast<size_t>(n_nt) * 16, s));
-            for (int32_t a = 0; a < n_nt; ++a)
-                CFPQ_HIP(launch_delta_snapshot(Y + a * mat_words, SNAP + a * mat_words, DELTA + a * mat_words, L,
-                                               d_dnnz + a, d_dnnz + n_nt + a, d_flags + a, s));
+            CFPQ_HIP(launch_delta_snapshot(Y, SNAP, DELTA, L, d_dnnz, d_dnnz + n_nt, d_flags, s, n_nt));
             CFPQ_HIP(hipMemcpyAsync(h_dnnz, d_dnnz, static_cast<size_t>(n_nt) * 16, hipMemcpyDeviceToHost, s));
         }
         CFPQ_HIP(hipStreamSynchronize(s));

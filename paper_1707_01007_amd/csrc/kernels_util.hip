@@ -87,12 +87,20 @@ __global__ __launch_bounds__(256) void popcount_kernel(const uint64_t* __restric
     }
 }
 
+// Matrix blockIdx.y of `count` consecutive ones (words apart): its counts at
+// count[y] and count_cur[y], its predicate pred[y].
 __global__ __launch_bounds__(256) void delta_snapshot_kernel(const uint64_t* __restrict__ cur,
                                                              uint64_t* __restrict__ P, uint64_t* __restrict__ D,
                                                              int64_t words, unsigned long long* __restrict__ count,
                                                              unsigned long long* __restrict__ count_cur,
                                                              const int32_t* __restrict__ pred) {
-    if (pred != nullptr && *pred == 0) return;
+    const int y = blockIdx.y;
+    if (pred != nullptr && pred[y] == 0) return;
+    cur += y * words;
+    P += y * words;
+    D += y * words;
+    count += y;
+    count_cur += y;
     // 16-byte accesses, two pairs of words in flight per thread (words is a
     // multiple of 4: W is)
     const ulonglong2* c2 = reinterpret_cast<const ulonglong2*>(cur);
@@ -144,15 +152,16 @@ __global__ __launch_bounds__(256) void delta_snapshot_kernel(const uint64_t* __r
 
 hipError_t launch_delta_snapshot(const uint64_t* cur, uint64_t* P, uint64_t* D, const Layout& L,
                                  unsigned long long* count, unsigned long long* count_cur, const int32_t* pred,
-                                 hipStream_t s) {
-    // at most 256 workgroups: each adds its two counts with one atomic apiece,
-    // and more workgroups queue on those two addresses (2048 cost 0.3 ms per
-    // hybrid closure at n = 16384)
+                                 hipStream_t s, int32_t matrices) {
+    // at most 256 workgroups per matrix: each adds its two counts with one
+    // atomic apiece, and more workgroups queue on those two addresses (2048
+    // cost 0.3 ms per hybrid closure at n = 16384)
     int64_t blocks = (L.mat_words / 2 + 1023) / 1024;
     if (blocks > 256) blocks = 256;
     if (blocks < 1) blocks = 1;
-    delta_snapshot_kernel<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s>>>(cur, P, D, L.mat_words, count,
-                                                                                   count_cur, pred);
+    if (matrices < 1) return hipSuccess;
+    delta_snapshot_kernel<<<dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(matrices)), dim3(256), 0, s>>>(
+        cur, P, D, L.mat_words, count, count_cur, pred);
     return hipGetLastError();
 }
 
