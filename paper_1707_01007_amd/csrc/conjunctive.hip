@@ -29,22 +29,32 @@
 namespace cfpq {
 namespace {
 
-__global__ void and_into_kernel(uint64_t* __restrict__ Q, const uint64_t* __restrict__ R, int64_t words) {
+// Q &= R; with clear_r, R is left zero (the scratch is then ready for the
+// next product without a launch of its own).
+__global__ void and_into_kernel(uint64_t* __restrict__ Q, uint64_t* __restrict__ R, int64_t words,
+                                int32_t clear_r) {
     for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
-         w += static_cast<int64_t>(gridDim.x) * blockDim.x)
+         w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         Q[w] &= R[w];
+        if (clear_r) R[w] = 0;
+    }
 }
 
-// A |= Q & R (the last conjunct folded into the union), with the change flag.
-__global__ __launch_bounds__(256) void or_and_into_kernel(uint64_t* A, const uint64_t* __restrict__ Q,
-                                                          const uint64_t* __restrict__ R, int64_t words,
-                                                          int32_t* changed) {
+// A |= Q & R (the last conjunct folded into the union), with the change flag;
+// clear_q / clear_r leave the scratch matrices Q / R zero for the next rule.
+// Q and R may be the same matrix (one shared product, never cleared).
+__global__ __launch_bounds__(256) void or_and_into_kernel(uint64_t* A, uint64_t* Q, uint64_t* R, int64_t words,
+                                                          int32_t* changed, int32_t clear_q, int32_t clear_r) {
     bool ch = false;
     for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words;
          w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const uint64_t q = Q[w];
-        if (!q) continue;
-        const uint64_t v = q & R[w];
+        uint64_t v = 0;
+        if (q) {
+            v = q & R[w];
+            if (clear_q) Q[w] = 0;
+        }
+        if (clear_r) R[w] = 0;  // R may hold bits where Q has none
         if (!v) continue;
         const uint64_t old = A[w];
         if (v & ~old) {
@@ -347,6 +357,10 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
     std::vector<int32_t> prev(n_nt, 1), flags(n_nt, 0);
     int64_t iters = 0, products = 0;
     bool converged = rules.empty() || graph->n_nodes == 0;
+    if (!converged) {
+        CFPQ_HIP(launch_zero(Q, mw, s));
+        CFPQ_HIP(launch_zero(R, mw, s));
+    }
     while (!converged && iters < cap) {
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         std::fill(shared_ready.begin(), shared_ready.end(), 0);
@@ -380,8 +394,9 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
                 st = shared_product(r.parts[0].first, r.parts[0].second, &sp);
                 if (st != CFPQ_OK) return st;
                 if (sp != nullptr) {
+                    uint64_t* spw = const_cast<uint64_t*>(sp);  // read only: no clearing
                     or_and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
-                        Y + r.lhs * mw, sp, sp, static_cast<int64_t>(mw), d_flags + r.lhs);
+                        Y + r.lhs * mw, spw, spw, static_cast<int64_t>(mw), d_flags + r.lhs, 0, 0);
                     CFPQ_HIP(hipGetLastError());
                 } else {
                     st = product(r.parts[0].first, r.parts[0].second, Y + r.lhs * mw, d_flags + r.lhs);
@@ -390,14 +405,15 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
                 }
                 continue;
             }
-            // the first conjunct (shared, or into the zeroed scratch Q), then
-            // each further one (shared, or into the zeroed scratch R): Q &= it,
-            // the last folded into T_A |= Q & R
+            // the first conjunct (shared, or into the scratch Q), then each
+            // further one (shared, or into the scratch R): Q &= it, the last
+            // folded into T_A |= Q & R.  Q and R are zero whenever a rule
+            // starts: zeroed before the loop, and left zero by the kernels
+            // that consume them.
             const uint64_t* acc = nullptr;
             st = shared_product(r.parts[0].first, r.parts[0].second, &acc);
             if (st != CFPQ_OK) return st;
             if (acc == nullptr) {
-                CFPQ_HIP(launch_zero(Q, mw, s));
                 st = product(r.parts[0].first, r.parts[0].second, Q, d_spare);
                 if (st != CFPQ_OK) return st;
                 ++products;
@@ -408,7 +424,6 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
                 st = shared_product(r.parts[m].first, r.parts[m].second, &pm);
                 if (st != CFPQ_OK) return st;
                 if (pm == nullptr) {
-                    CFPQ_HIP(launch_zero(R, mw, s));
                     st = product(r.parts[m].first, r.parts[m].second, R, d_spare);
                     if (st != CFPQ_OK) return st;
                     ++products;
@@ -420,10 +435,11 @@ cfpq_status cfpq_conjunctive_closure(const cfpq_graph* graph, const cfpq_grammar
                         acc = Q;
                     }
                     and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
-                        Q, pm, static_cast<int64_t>(mw));
+                        Q, const_cast<uint64_t*>(pm), static_cast<int64_t>(mw), pm == R ? 1 : 0);
                 } else {
                     or_and_into_kernel<<<dim3(grid_for(static_cast<int64_t>(mw))), dim3(256), 0, s>>>(
-                        Y + r.lhs * mw, acc, pm, static_cast<int64_t>(mw), d_flags + r.lhs);
+                        Y + r.lhs * mw, const_cast<uint64_t*>(acc), const_cast<uint64_t*>(pm),
+                        static_cast<int64_t>(mw), d_flags + r.lhs, acc == Q ? 1 : 0, pm == R ? 1 : 0);
                 }
                 CFPQ_HIP(hipGetLastError());
             }
