@@ -217,7 +217,7 @@ cfpq_status cfpq_autotune(int32_t n_nodes, void* stream, void* d_workspace, size
     CFPQ_HIP(hipEventCreate(&e1));
     struct Ev {
         hipEvent_t a, b;
-        ~Ev() { hipEventDestroy(a); hipEventDestroy(b); }
+        ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } guard{e0, e1};
     struct Cand {
         int32_t path, tile;

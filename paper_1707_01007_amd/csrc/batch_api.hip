@@ -407,7 +407,7 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
     CFPQ_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
     struct Ev {
         hipEvent_t a, b, c, d;
-        ~Ev() { hipEventDestroy(a); hipEventDestroy(b); hipEventDestroy(c); hipEventDestroy(d); }
+        ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); (void)hipEventDestroy(d); }
     } evguard{ev0, ev1, fork, join};
 
     auto h2d = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
@@ -477,8 +477,8 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
             hipGraph_t& g;
             hipGraphExec_t& e;
             ~GraphGuard() {
-                if (e) hipGraphExecDestroy(e);
-                if (g) hipGraphDestroy(g);
+                if (e) (void)hipGraphExecDestroy(e);
+                if (g) (void)hipGraphDestroy(g);
             }
         } gguard{g, exec};
         // rows: up to 8 waves per SIMD

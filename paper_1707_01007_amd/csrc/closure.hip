@@ -247,7 +247,7 @@ hipError_t pinned_readback(size_t bytes, void** out) {
         void* p = nullptr;
         size_t n = 0;
         ~Buf() {
-            if (p) hipHostFree(p);
+            if (p) (void)hipHostFree(p);
         }
     };
     thread_local Buf b;
@@ -256,7 +256,7 @@ hipError_t pinned_readback(size_t bytes, void** out) {
         void* p = nullptr;
         const hipError_t e = hipHostMalloc(&p, n, hipHostMallocPortable);
         if (e != hipSuccess) return e;
-        if (b.p) hipHostFree(b.p);  // every copy into it has completed (callers synchronise)
+        if (b.p) (void)hipHostFree(b.p);  // every copy into it has completed (callers synchronise)
         b.p = p;
         b.n = n;
     }
@@ -465,8 +465,8 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     struct EvGuard {
         hipEvent_t a, b;
         ~EvGuard() {
-            if (a) hipEventDestroy(a);
-            if (b) hipEventDestroy(b);
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
         }
     } guard{ev0, ev1};
     const auto host_t0 = std::chrono::steady_clock::now();
@@ -504,7 +504,7 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     std::vector<hipEvent_t> pev;
     struct PevGuard {
         std::vector<hipEvent_t>& v;
-        ~PevGuard() { for (auto e : v) hipEventDestroy(e); }
+        ~PevGuard() { for (auto e : v) (void)hipEventDestroy(e); }
     } pguard{pev};
     auto product_event = [&](size_t idx) -> hipEvent_t {
         while (pev.size() <= idx) {
@@ -549,8 +549,8 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             hipGraph_t& g;
             hipGraphExec_t& e;
             ~GraphGuard() {
-                if (e) hipGraphExecDestroy(e);
-                if (g) hipGraphDestroy(g);
+                if (e) (void)hipGraphExecDestroy(e);
+                if (g) (void)hipGraphDestroy(g);
             }
         } gguard{g, exec};
         CFPQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));

@@ -340,7 +340,7 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
             SRV_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
             SRV_HIP(hipEventRecord(ready, s));
             SRV_HIP(hipStreamWaitEvent(srv->side, ready, 0));
-            hipEventDestroy(ready);
+            (void)hipEventDestroy(ready);
             SRV_HIP(engine_resident(srv->b, list, static_cast<int32_t>(s8.size()), 8, srv->side));
             SRV_HIP(engine_resident(srv->b, list + s8.size(), static_cast<int32_t>(s16.size()), 16, srv->side));
             SRV_HIP(hipEventRecord(sb.done, srv->side));
@@ -429,7 +429,7 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
     // drop small batches whose requests are all retired
     for (auto it = srv->small_batches.begin(); it != srv->small_batches.end();) {
         if (it->second.live == 0) {
-            hipEventDestroy(it->second.done);
+            (void)hipEventDestroy(it->second.done);
             it = srv->small_batches.erase(it);
         } else {
             ++it;
@@ -468,8 +468,8 @@ void fail_all(cfpq_server* srv, const std::string& message) {
 // at once), then each completes with CFPQ_EDEVICE and its slot and arena
 // block are released.
 void abandon_slots(cfpq_server* srv) {
-    hipStreamSynchronize(srv->stream);
-    hipStreamSynchronize(srv->side);
+    (void)hipStreamSynchronize(srv->stream);
+    (void)hipStreamSynchronize(srv->side);
     std::lock_guard<std::mutex> lk(srv->mu);
     const double t = now_s();
     for (int32_t q = 0; q < static_cast<int32_t>(srv->slot_req.size()); ++q) {
@@ -693,7 +693,7 @@ cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, c
     const hipError_t ce = engine_capture_loops(srv->b, cfg.capture, srv->cus, 2 * srv->cus, 4 * srv->cus, cs,
                                                &srv->graph);
     if (ce != hipSuccess) {
-        hipFree(srv->dmem);
+        (void)hipFree(srv->dmem);
         return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
     }
     CFPQ_HIP(hipGraphInstantiate(&srv->exec, srv->graph, nullptr, nullptr, 0));
@@ -835,17 +835,17 @@ cfpq_status cfpq_server_destroy(cfpq_server* srv) {
     for (auto& t : srv->lanes)
         if (t.joinable()) t.join();
     for (hipStream_t ls : srv->lane_streams) {
-        hipStreamSynchronize(ls);
-        hipStreamDestroy(ls);
+        (void)hipStreamSynchronize(ls);
+        (void)hipStreamDestroy(ls);
     }
-    hipStreamSynchronize(srv->stream);
-    hipStreamSynchronize(srv->side);
+    (void)hipStreamSynchronize(srv->stream);
+    (void)hipStreamSynchronize(srv->side);
     for (auto& kv : srv->small_batches)
-        if (kv.second.done) hipEventDestroy(kv.second.done);
-    if (srv->exec) hipGraphExecDestroy(srv->exec);
-    if (srv->graph) hipGraphDestroy(srv->graph);
-    hipStreamDestroy(srv->side);
-    hipFree(srv->dmem);
+        if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+    if (srv->exec) (void)hipGraphExecDestroy(srv->exec);
+    if (srv->graph) (void)hipGraphDestroy(srv->graph);
+    (void)hipStreamDestroy(srv->side);
+    (void)hipFree(srv->dmem);
     cfpq_status st = srv->worker_error;
     delete srv;
     return st;

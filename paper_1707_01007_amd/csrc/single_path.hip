@@ -144,6 +144,18 @@ __device__ __forceinline__ int32_t next_chunk(const uint32_t* m, int32_t from, i
 // and multiplied.  (Prefetching the next chunk into registers while the
 // current one is multiplied needed 154 VGPRs and ran slower: occupancy,
 // not the staging latency, hides the loads.)
+//
+// kNarrow: every operand length is at most 2^14 - 1, so lengths and their
+// sums fit 16 bits below kInf16 and two cells go through each VALU
+// instruction (v_pk_add_u16, v_pk_min_u16: one instruction per term instead
+// of the 32-bit loop's add per term and three-way min per two).  L_B is
+// staged with its value in both halves of a dword, L_C as 16-bit pairs along
+// j; the sums are the same integers, so the lengths are identical.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+constexpr uint32_t kInf16 = 0x7FFFu;  // absent operand in the narrow kernel; kInf16 + kInf16 does not wrap
+constexpr int64_t kNarrowMaxLength = (1 << 14) - 1;
+
+template <bool kNarrow>
 __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict__ D, const uint64_t* __restrict__ XB,
                                                       const uint64_t* __restrict__ XC, const uint32_t* LB,
                                                       const uint32_t* LC, uint32_t* LA, int64_t W, int64_t npad,
@@ -158,12 +170,12 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
     const int64_t ti = tile / W, tj = tile % W;  // W tiles per side (64 cells each)
     const int64_t i0 = ti * 64, jw = tj;  // j0 = 64 * jw
     const int t = threadIdx.x;
-    __shared__ __align__(16) uint32_t As[32][64 + 4];  // As[kk][i]
-    __shared__ __align__(16) uint32_t Bs[32][64 + 4];  // Bs[kk][j]
+    __shared__ __align__(16) uint32_t As[32][64 + 4];  // As[kk][i] (narrow: the 16-bit value twice)
+    __shared__ __align__(16) uint32_t Bs[32][64 + 4];  // Bs[kk][j] (narrow: 16-bit, first half of each row)
     __shared__ uint32_t bmask[kSegChunks / 32], cmask[kSegChunks / 32];
     int32_t done_chunks = 0;
     const int tx = t & 15, ty = t >> 4;
-    uint32_t acc[4][4];
+    uint32_t acc[4][4];  // narrow: acc[r][0..1] hold the four cells as 16-bit pairs
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -208,21 +220,46 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const bool set = (xbp[q * 8 * W] >> bsh) & 1ull;
-                As[bk][bi + 8 * q] = set ? lbp[q * 8 * npad] : kInf;
                 const bool cset = (xcp[q * 4 * W] >> cj) & 1ull;
-                Bs[ck + 4 * q][cj] = cset ? lcp[q * 4 * npad] : kInf;
+                if (kNarrow) {
+                    const uint32_t a = set ? lbp[q * 8 * npad] : kInf16;
+                    As[bk][bi + 8 * q] = a | (a << 16);
+                    reinterpret_cast<uint16_t*>(&Bs[ck + 4 * q][0])[cj] =
+                        static_cast<uint16_t>(cset ? lcp[q * 4 * npad] : kInf16);
+                } else {
+                    As[bk][bi + 8 * q] = set ? lbp[q * 8 * npad] : kInf;
+                    Bs[ck + 4 * q][cj] = cset ? lcp[q * 4 * npad] : kInf;
+                }
             }
             __syncthreads();
+            if (kNarrow) {
 #pragma unroll 8
-            for (int kk = 0; kk < 32; ++kk) {
-                const uint4 a = *reinterpret_cast<const uint4*>(&As[kk][ty * 4]);
-                const uint4 b = *reinterpret_cast<const uint4*>(&Bs[kk][tx * 4]);
-                const uint32_t av[4] = {a.x, a.y, a.z, a.w};
-                const uint32_t bv[4] = {b.x, b.y, b.z, b.w};
+                for (int kk = 0; kk < 32; ++kk) {
+                    const uint4 a = *reinterpret_cast<const uint4*>(&As[kk][ty * 4]);
+                    const uint2 b = reinterpret_cast<const uint2*>(&Bs[kk][0])[tx];  // j = 4 tx .. 4 tx + 3
+                    const uint32_t av[4] = {a.x, a.y, a.z, a.w};
+                    const u16x2 b0 = __builtin_bit_cast(u16x2, b.x), b1 = __builtin_bit_cast(u16x2, b.y);
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                    for (int r = 0; r < 4; ++r) {
+                        const u16x2 a2 = __builtin_bit_cast(u16x2, av[r]);
+                        const u16x2 m0 = __builtin_elementwise_min(__builtin_bit_cast(u16x2, acc[r][0]), a2 + b0);
+                        const u16x2 m1 = __builtin_elementwise_min(__builtin_bit_cast(u16x2, acc[r][1]), a2 + b1);
+                        acc[r][0] = __builtin_bit_cast(uint32_t, m0);
+                        acc[r][1] = __builtin_bit_cast(uint32_t, m1);
+                    }
+                }
+            } else {
+#pragma unroll 8
+                for (int kk = 0; kk < 32; ++kk) {
+                    const uint4 a = *reinterpret_cast<const uint4*>(&As[kk][ty * 4]);
+                    const uint4 b = *reinterpret_cast<const uint4*>(&Bs[kk][tx * 4]);
+                    const uint32_t av[4] = {a.x, a.y, a.z, a.w};
+                    const uint32_t bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[r][q] = min(acc[r][q], av[r] + bv[q]);
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[r][q] = min(acc[r][q], av[r] + bv[q]);
+                }
             }
             ++done_chunks;
             __syncthreads();  // every thread is done with the chunk before the next is staged
@@ -238,9 +275,10 @@ __global__ __launch_bounds__(256) void minplus_kernel(const uint64_t* __restrict
         for (int c = 0; c < 4; ++c) {
             const int jj = tx * 4 + c;
             if (!((drow >> jj) & 1ull)) continue;
-            const uint32_t v = acc[r][c];
-            // kInf: this rule (or this k range) offered no k for the cell
-            if (v < kInf) atomicMin(LA + i * npad + 64 * jw + jj, v);
+            const uint32_t v = kNarrow ? (acc[r][c >> 1] >> (16 * (c & 1))) & 0xFFFFu : acc[r][c];
+            // kInf (kInf16 and above when narrow: a sum with an absent operand):
+            // this rule (or this k range) offered no k for the cell
+            if (v < (kNarrow ? kInf16 : kInf)) atomicMin(LA + i * npad + 64 * jw + jj, v);
         }
     }
 }
@@ -574,10 +612,10 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
     struct EvGuard {
         hipEvent_t a, b, c, d;
         ~EvGuard() {
-            hipEventDestroy(a);
-            hipEventDestroy(b);
-            hipEventDestroy(c);
-            hipEventDestroy(d);
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            (void)hipEventDestroy(c);
+            (void)hipEventDestroy(d);
         }
     } guard{ev0, ev1, mp0, mp1};
     auto* d_cells = reinterpret_cast<unsigned long long*>(d_bad + 2);  // in the same 256-byte block
@@ -756,10 +794,20 @@ cfpq_status cfpq_single_path(const cfpq_graph* graph, const cfpq_grammar* gramma
             int64_t ksplit = std::max<int64_t>(1, (kTileTarget + tiles[br.lhs] - 1) / std::max(tiles[br.lhs], 1));
             ksplit = std::min<int64_t>({ksplit, kMaxSplit, std::max<int64_t>(1, kchunks / 2),
                                         std::max<int64_t>(1, kMaxTileGrid / all_tiles)});
-            minplus_kernel<<<dim3(static_cast<unsigned>(all_tiles * ksplit)), dim3(256), 0, s>>>(
-                D + br.lhs * mw, X + br.left * mw, X + br.right * mw, d_lengths + br.left * lmat,
-                d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, kchunks,
-                d_tflag + br.lhs * all_tiles, static_cast<int32_t>(ksplit), d_cells);
+            // a length of step t is at most 2^t (each step's sums add two
+            // lengths of the previous one), so the first 14 steps run narrow
+            const bool narrow = iters < 14 && (int64_t{1} << iters) <= kNarrowMaxLength;
+            const dim3 grid(static_cast<unsigned>(all_tiles * ksplit));
+            if (narrow)
+                minplus_kernel<true><<<grid, dim3(256), 0, s>>>(
+                    D + br.lhs * mw, X + br.left * mw, X + br.right * mw, d_lengths + br.left * lmat,
+                    d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, kchunks,
+                    d_tflag + br.lhs * all_tiles, static_cast<int32_t>(ksplit), d_cells);
+            else
+                minplus_kernel<false><<<grid, dim3(256), 0, s>>>(
+                    D + br.lhs * mw, X + br.left * mw, X + br.right * mw, d_lengths + br.left * lmat,
+                    d_lengths + br.right * lmat, d_lengths + br.lhs * lmat, L.W, L.npad, kchunks,
+                    d_tflag + br.lhs * all_tiles, static_cast<int32_t>(ksplit), d_cells);
             CFPQ_HIP(hipGetLastError());
         }
         CFPQ_HIP(hipEventRecord(mp1, s));
