@@ -56,6 +56,18 @@ def _check_paths(cfpq, n, e, g, L, count=40, seed=0):
             assert int(a) in brute.cyk_table(word, g)[0][len(word)]
 
 
+def _dense_nested_dyck():
+    """Two components: the nested chain a^40 b^40 (its outermost pair found only
+    after about 80 steps) and a dense G(90, 4200), together more than npad^2 /
+    16 edges.  The dense part's full matrices make the tile min-plus kernel the
+    cheaper choice for S -> S S in every step where S gains cells, so it runs
+    past the first 14 steps (narrow, 16-bit) on the 32-bit kernel."""
+    n1, chain = graphs.chain([0] * 40 + [1] * 40)
+    n2, dense = graphs.erdos_renyi(90, 4200, 8, labels=2)
+    dense = np.asarray(dense, np.int32).reshape(-1, 3) + np.array([n1, 0, n1], np.int32)
+    return n1 + n2, np.concatenate([np.asarray(chain, np.int32).reshape(-1, 3), dense]), grammars.dyck()
+
+
 CASES = {
     "worked_example": lambda: (configs.worked_example().n, configs.worked_example().edges,
                                configs.worked_example().grammar),
@@ -69,6 +81,8 @@ CASES = {
     "er90_dense_dyck": lambda: (*graphs.erdos_renyi(90, 4200, 8, labels=2), grammars.dyck()),
     # 15 k-chunks of 32: S -> S S on tiles split along k in its later loops
     "er450_dyck": lambda: (*graphs.erdos_renyi(450, 1350, 14, labels=2), grammars.dyck()),
+    # tile kernel past the narrow steps
+    "dense_nested_dyck": _dense_nested_dyck,
 }
 
 
@@ -79,8 +93,10 @@ def test_lengths_match_oracle(cfpq, name):
     res, got = _lengths(cfpq, n, e, g)
     assert res.stats["iterations"] == loops
     assert np.array_equal(got, want)
-    if name in ("er450_dyck", "er90_dense_dyck"):
+    if name in ("er450_dyck", "er90_dense_dyck", "dense_nested_dyck"):
         assert res.stats["minplus_terms"] > 0  # the tile kernel ran
+    if name == "dense_nested_dyck":
+        assert res.stats["iterations"] > 14 and int(got[0, 0, 80]) == 80  # S over the whole chain: 80 edges
     bits = cfpq.result_bits(res)
     from oracle import worklist
     assert np.array_equal(bits, worklist.closure(n, e, g))
