@@ -39,12 +39,25 @@ def lib():
     return _abi.load()
 
 
+_LAYOUT_CACHE = {}
+
+
+def _layout(n: int):
+    """(padded rows, words per row) of the library's bit layout for n nodes,
+    asked of the library once per n."""
+    hit = _LAYOUT_CACHE.get(n)
+    if hit is None:
+        L = lib()
+        hit = _LAYOUT_CACHE[n] = (int(L.cfpq_padded_rows(n)), int(L.cfpq_row_words(n)))
+    return hit
+
+
 def row_words(n: int) -> int:
-    return int(lib().cfpq_row_words(n))
+    return _layout(int(n))[1]
 
 
 def padded_rows(n: int) -> int:
-    return int(lib().cfpq_padded_rows(n))
+    return _layout(int(n))[0]
 
 
 _GRAMMAR_CACHE = {}
@@ -287,29 +300,89 @@ def closure_static(n: int, edges, grammar, *, path="auto", schedule="inplace", d
     return Result(int(n), int(grammar.n_nonterminals), bits, st.as_dict(), status)
 
 
+_INSTANCE_DTYPE = None
+
+
+def _instance_dtype():
+    """numpy record with the byte layout of ``cfpq_instance``."""
+    global _INSTANCE_DTYPE
+    if _INSTANCE_DTYPE is None:
+        G, I = _abi.Graph, _abi.Instance
+        go = I.graph.offset
+        _INSTANCE_DTYPE = np.dtype({
+            "names": ["n_nodes", "edges_on_device", "n_edges", "edges", "grammar", "d_result"],
+            "formats": [np.int32, np.int32, np.int64, np.uintp, np.uintp, np.uintp],
+            "offsets": [go + G.n_nodes.offset, go + G.edges_on_device.offset, go + G.n_edges.offset,
+                        go + G.edges.offset, I.grammar.offset, I.d_result.offset],
+            "itemsize": ctypes.sizeof(I)})
+    return _INSTANCE_DTYPE
+
+
 def _instance_array(instances, outs, device):
-    """cfpq_instance records for (n, edges, grammar) triples, the objects they
-    point into, and one result buffer per instance (from ``outs`` or new)."""
+    """cfpq_instance records for (n, edges, grammar) triples (a pointer to
+    them), the objects they point into, and one result buffer per instance
+    (from ``outs`` or new).  Filled column by column: a batch holds hundreds
+    of instances, and per-record ctypes structures cost more host time than
+    the batch's smaller closures."""
     torch = _torch()
     L = lib()
     k = len(instances)
-    arr = (_abi.Instance * max(1, k))()
     keep, results_out = [], []
+    gptr = {}  # id(grammar) -> address of its cfpq_grammar
+    cols = ([], [], [], [], [], [])
+    ns, on_dev, ms, eps, gps, rps = cols
+    i32 = torch.int32
     for i, (n, edges, grammar) in enumerate(instances):
-        g, kg = _grammar_struct(grammar)
-        keep.append((g, kg))
+        gp = gptr.get(id(grammar))
+        if gp is None:
+            g, kg = _grammar_struct(grammar)
+            keep.append((grammar, g, kg))
+            gp = gptr[id(grammar)] = ctypes.addressof(g)
         if isinstance(edges, torch.Tensor) and edges.is_cuda:
-            e = edges.to(torch.int32).contiguous().view(-1, 3)
-            graph = _abi.Graph(int(n), 1, int(e.shape[0]), ctypes.c_void_p(e.data_ptr()))
+            if edges.dtype == i32 and edges.is_contiguous() and edges.numel() % 3 == 0:
+                e = edges
+            else:
+                e = edges.to(i32).contiguous().view(-1, 3)
+            dev, m, ep = 1, e.numel() // 3, e.data_ptr()
         else:
             e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 3))
-            graph = _abi.Graph(int(n), 0, int(e.shape[0]), ctypes.c_void_p(e.ctypes.data))
+            dev, m, ep = 0, e.shape[0], e.ctypes.data
         keep.append(e)
-        words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8
-        out = outs[i] if outs is not None else torch.empty(words, dtype=torch.int64, device=device)
+        if outs is not None:
+            out = outs[i]
+        else:
+            words = int(L.cfpq_result_bytes(int(n), int(grammar.n_nonterminals))) // 8
+            out = torch.empty(words, dtype=torch.int64, device=device)
         results_out.append(out)
-        arr[i] = _abi.Instance(graph, ctypes.pointer(g), ctypes.c_void_p(out.data_ptr()))
-    return arr, keep, results_out
+        ns.append(n)
+        on_dev.append(dev)
+        ms.append(m)
+        eps.append(ep)
+        gps.append(gp)
+        rps.append(out.data_ptr())
+    rec = np.zeros(max(1, k), dtype=_instance_dtype())
+    if k:
+        for name, col in zip(rec.dtype.names, cols):
+            rec[name][:k] = col
+    keep.append(rec)
+    return rec.ctypes.data_as(ctypes.POINTER(_abi.Instance)), keep, results_out
+
+
+_STATS_DTYPE = None
+
+
+def _stats_dicts(stats, k):
+    """One dict per ``cfpq_stats`` record of a ctypes array (read in bulk)."""
+    global _STATS_DTYPE
+    S = _abi.Stats
+    names = [f for f, _ in S._fields_]
+    if _STATS_DTYPE is None:
+        _STATS_DTYPE = np.dtype({"names": names,
+                                 "formats": [np.dtype(t) for _, t in S._fields_],
+                                 "offsets": [getattr(S, f).offset for f in names],
+                                 "itemsize": ctypes.sizeof(S)})
+    rows = np.frombuffer(stats, dtype=_STATS_DTYPE, count=k).tolist()
+    return [dict(zip(names, r)) for r in rows]
 
 
 def batch_autotune(instances, *, max_per_bucket=0, reps=3, dirty=True, hybrid=None, device=None, stream=None,
@@ -381,9 +454,10 @@ def batch_closure(instances, *, dirty=True, max_iters=0, capture=None, device=No
     if status != _abi.CFPQ_OK and not (allow_partial and status == _abi.CFPQ_ENOTCONV):
         _abi.check(status)
     res = []
-    for i, (n, edges, grammar) in enumerate(instances):
-        bits = results_out[i].view(int(grammar.n_nonterminals), padded_rows(n), row_words(n))
-        res.append(Result(int(n), int(grammar.n_nonterminals), bits, stats[i].as_dict(), status))
+    for (n, edges, grammar), out, st in zip(instances, results_out, _stats_dicts(stats, k)):
+        nnt = int(grammar.n_nonterminals)
+        rows, words = _layout(int(n))
+        res.append(Result(int(n), nnt, out.view(nnt, rows, words), st, status))
     del keep
     return res
 

@@ -485,12 +485,37 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
         const hipError_t ce = engine_capture_loops(b, K, grid_p, 8 * cus, grid_t, cs, &g);
         if (ce != hipSuccess) return fail(CFPQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
         CFPQ_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
-        EngineState hes;
-        do {
-            CFPQ_HIP(hipGraphLaunch(exec, s));
-            CFPQ_HIP(hipMemcpyAsync(&hes, b.es, sizeof(hes), hipMemcpyDeviceToHost, s));
-            CFPQ_HIP(hipStreamSynchronize(s));
-        } while (hes.running > 0);
+        // The host checks the state after launch k while launch k + 1 is
+        // already queued, so the device does not idle through the host's
+        // round trip; the one launch queued past the fixpoint finds nothing
+        // running and its kernels return at once.  Two pinned slots: a slot
+        // is written again only after the host has waited for its last copy.
+        void* pb = nullptr;
+        CFPQ_HIP(pinned_readback(2 * sizeof(EngineState), &pb));
+        auto* hes = static_cast<EngineState*>(pb);
+        hipEvent_t got[2] = {nullptr, nullptr};
+        struct GotGuard {
+            hipEvent_t* e;
+            ~GotGuard() {
+                for (int i = 0; i < 2; ++i)
+                    if (e[i]) (void)hipEventDestroy(e[i]);
+            }
+        } got_guard{got};
+        CFPQ_HIP(hipEventCreateWithFlags(&got[0], hipEventDisableTiming));
+        CFPQ_HIP(hipEventCreateWithFlags(&got[1], hipEventDisableTiming));
+        auto launch_and_read = [&](int slot) -> hipError_t {
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&hes[slot], b.es, sizeof(EngineState), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipEventRecord(got[slot], s);
+            return e;
+        };
+        CFPQ_HIP(launch_and_read(0));
+        for (int cur = 0;; cur ^= 1) {
+            CFPQ_HIP(launch_and_read(cur ^ 1));
+            CFPQ_HIP(hipEventSynchronize(got[cur]));
+            if (hes[cur].running <= 0) break;
+        }
     }
     if (any_small) CFPQ_HIP(hipStreamWaitEvent(s, join, 0));
     CFPQ_HIP(hipEventRecord(ev1, s));

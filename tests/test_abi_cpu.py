@@ -282,6 +282,48 @@ def test_batch_validation_on_host():
                                   None) == _abi.CFPQ_EINVAL
 
 
+def test_batch_records_match_the_ctypes_structures():
+    """The binding fills a batch's cfpq_instance records column by column;
+    each must read back, field for field, as the ctypes structure would, and
+    the library must plan the same workspace from them."""
+    import torch
+    import paper_1707_01007_amd as cfpq
+    from paper_1707_01007_amd import _abi
+    from workloads import grammars
+    lib = _lib()
+    gs = [grammars.dyck(), grammars.anbn(), grammars.same_generation()]
+    items, outs = [], []
+    for i in range(7):
+        n = 40 + 97 * i
+        edges = np.array([(j % n, j % 2, (3 * j + 1) % n) for j in range(2 * n + i)], np.int32)
+        g = gs[i % 3]
+        items.append((n, edges, g))
+        outs.append(torch.empty(int(lib.cfpq_result_bytes(n, g.n_nonterminals)) // 8, dtype=torch.int64))
+    ptr, keep, res_out = cfpq._instance_array(items, outs, None)
+    ref = (_abi.Instance * len(items))()
+    for i, (n, edges, g) in enumerate(items):
+        gs_, _ = cfpq._grammar_struct(g)
+        rec = ptr[i]
+        assert (rec.graph.n_nodes, rec.graph.edges_on_device, rec.graph.n_edges) == (n, 0, len(edges))
+        assert ctypes.addressof(rec.grammar.contents) == ctypes.addressof(gs_)
+        assert rec.d_result == outs[i].data_ptr() and res_out[i] is outs[i]
+        assert np.array_equal(np.ctypeslib.as_array(ctypes.cast(rec.graph.edges, ctypes.POINTER(ctypes.c_int32)),
+                                                    (len(edges), 3)), edges)
+        ref[i] = _abi.Instance(_abi.Graph(n, 0, len(edges), ctypes.c_void_p(rec.graph.edges)), ctypes.pointer(gs_),
+                               ctypes.c_void_p(outs[i].data_ptr()))
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.cfpq_batch_workspace_bytes(len(items), ptr, None, ctypes.byref(a)) == 0
+    assert lib.cfpq_batch_workspace_bytes(len(items), ref, None, ctypes.byref(b)) == 0
+    assert a.value == b.value > 0
+    # stats records read in bulk equal the per-record reading
+    stats = (_abi.Stats * 5)()
+    for i in range(5):
+        stats[i].iterations, stats[i].products, stats[i].bitops, stats[i].converged = i, 3 * i, 0.5 * i, i % 2
+        stats[i].sparse_ms = 1.25 * i
+    assert cfpq._stats_dicts(stats, 5) == [stats[i].as_dict() for i in range(5)]
+    assert cfpq._stats_dicts(stats, 2) == [stats[i].as_dict() for i in range(2)]
+
+
 def test_server_config_validation_on_host():
     from paper_1707_01007_amd import _abi
     lib = _lib()
