@@ -504,6 +504,9 @@ CFPQ_API cfpq_status cfpq_batch_tune_set(const cfpq_batch_tune_entry* entry);
  * hybrid and max_iters apply to every instance; path, tile and profile are
  * ignored.  Instances are limited to 2^19 nodes.
  * stats: NULL or n_instances entries (device_ms is the whole batch's time).
+ * Device edges are checked by the initialisation kernel, which skips an
+ * out-of-range edge; the call then returns CFPQ_EINVAL naming the instance,
+ * after the batch has run (results unspecified).
  * Returns CFPQ_OK, CFPQ_ENOTCONV (some instance hit max_iters; all results
  * are sound), CFPQ_EINVAL (message names the instance), CFPQ_ENOMEM or
  * CFPQ_EDEVICE.  Synchronises `stream` before returning.

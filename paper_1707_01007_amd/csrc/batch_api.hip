@@ -23,7 +23,6 @@ struct BatchPlan {
     std::vector<size_t> edge_copy_off;  // per slot: byte offset in the edge region, or SIZE_MAX (device edges)
     int64_t total_edges = 0;
     int32_t large_rules = 0, large_trans = 0;
-    bool any_device_edges = false;
     size_t off_descs = 0, off_states = 0, off_rules = 0, off_go = 0, off_mode = 0, off_trans = 0, off_term = 0;
     size_t off_jobs = 0, off_tjobs = 0, off_large = 0, off_small8 = 0, off_small16 = 0, off_all = 0;
     size_t off_edge_begin = 0, off_es = 0, off_edges = 0, off_tt = 0, total = 0;
@@ -108,9 +107,7 @@ cfpq_status plan_batch(int32_t n, const cfpq_instance* inst, const cfpq_options&
         p.trans.insert(p.trans.end(), tr.begin(), tr.end());
         p.modes.insert(p.modes.end(), md.begin(), md.end());
         p.edge_begin[i + 1] = p.edge_begin[i] + g.n_edges;
-        if (g.edges_on_device) {
-            p.any_device_edges = true;
-        } else if (g.n_edges > 0) {
+        if (!g.edges_on_device && g.n_edges > 0) {
             p.edge_copy_off[i] = edge_bytes;
             edge_bytes += align_up(static_cast<size_t>(g.n_edges) * sizeof(cfpq_edge), 256);
         }
@@ -410,44 +407,49 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
         ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); (void)hipEventDestroy(d); }
     } evguard{ev0, ev1, fork, join};
 
-    auto h2d = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
-        if (bytes == 0) return hipSuccess;
-        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    // Every table goes over in one copy: the host image of the workspace's
+    // table region (descs .. engine state, contiguous), built in pinned
+    // memory, followed there by two engine-state slots for the loop's checks.
+    const size_t tab_begin = p.off_descs, tab_bytes = p.off_es + sizeof(EngineState) - p.off_descs;
+    const size_t es_slots = align_up(tab_bytes, 64);
+    void* pb = nullptr;
+    CFPQ_HIP(pinned_readback(es_slots + 2 * sizeof(EngineState), &pb));
+    char* img = static_cast<char*>(pb);
+    std::memset(img, 0, tab_bytes);
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(img + (off - tab_begin), src, bytes);
     };
-    CFPQ_HIP(h2d(b.descs, p.descs.data(), sizeof(SlotDesc) * p.descs.size()));
-    CFPQ_HIP(h2d(b.states, hstates.data(), sizeof(SlotState) * hstates.size()));
-    CFPQ_HIP(h2d(b.rules_tab, p.rules.data(), 4 * p.rules.size()));
-    CFPQ_HIP(h2d(b.mode_tab, p.modes.data(), 4 * p.modes.size()));
-    CFPQ_HIP(h2d(b.trans_tab, p.trans.data(), 4 * p.trans.size()));
-    CFPQ_HIP(h2d(b.term_tab, p.term.data(), 4 * p.term.size()));
-    CFPQ_HIP(h2d(b.large_ids, p.large.data(), 4 * p.large.size()));
-    CFPQ_HIP(h2d(b.small_ids, p.small8.data(), 4 * p.small8.size()));
-    CFPQ_HIP(h2d(small16_ids, p.small16.data(), 4 * p.small16.size()));
-    CFPQ_HIP(h2d(all_ids, p.all_ids.data(), 4 * p.all_ids.size()));
-    CFPQ_HIP(h2d(b.edge_begin, p.edge_begin.data(), 8 * p.edge_begin.size()));
-    for (int32_t i = 0; i < n_instances; ++i) {
-        if (p.edge_copy_off[i] == SIZE_MAX || instances[i].graph.edges_on_device) continue;
-        CFPQ_HIP(h2d(ws + p.off_edges + p.edge_copy_off[i], instances[i].graph.edges,
-                     static_cast<size_t>(instances[i].graph.n_edges) * sizeof(cfpq_edge)));
-    }
+    put(p.off_descs, p.descs.data(), sizeof(SlotDesc) * p.descs.size());
+    put(p.off_states, hstates.data(), sizeof(SlotState) * hstates.size());
+    put(p.off_rules, p.rules.data(), 4 * p.rules.size());
+    put(p.off_mode, p.modes.data(), 4 * p.modes.size());
+    put(p.off_trans, p.trans.data(), 4 * p.trans.size());
+    put(p.off_term, p.term.data(), 4 * p.term.size());
+    put(p.off_large, p.large.data(), 4 * p.large.size());
+    put(p.off_small8, p.small8.data(), 4 * p.small8.size());
+    put(p.off_small16, p.small16.data(), 4 * p.small16.size());
+    put(p.off_all, p.all_ids.data(), 4 * p.all_ids.size());
+    put(p.off_edge_begin, p.edge_begin.data(), 8 * p.edge_begin.size());
     EngineState es0;
     std::memset(&es0, 0, sizeof(es0));
     es0.n_large = static_cast<int32_t>(p.large.size());
-    CFPQ_HIP(h2d(b.es, &es0, sizeof(es0)));
+    put(p.off_es, &es0, sizeof(es0));
+    CFPQ_HIP(hipMemcpyAsync(ws + tab_begin, img, tab_bytes, hipMemcpyHostToDevice, s));
+    for (int32_t i = 0; i < n_instances; ++i) {
+        if (p.edge_copy_off[i] == SIZE_MAX || instances[i].graph.edges_on_device ||
+            instances[i].graph.n_edges == 0)
+            continue;
+        CFPQ_HIP(hipMemcpyAsync(ws + p.off_edges + p.edge_copy_off[i], instances[i].graph.edges,
+                                static_cast<size_t>(instances[i].graph.n_edges) * sizeof(cfpq_edge),
+                                hipMemcpyHostToDevice, s));
+    }
     CFPQ_HIP(hipEventRecord(ev0, s));
 
     // Matrix initialisation of every instance.
     CFPQ_HIP(engine_zero(b, all_ids, n_instances, s));
+    // Device edges with an id out of range are counted and skipped by the
+    // scatter; the count is read with the final states (no round trip here).
     CFPQ_HIP(engine_scatter(b, all_ids, n_instances, p.total_edges, s));
-    if (p.any_device_edges) {
-        CFPQ_HIP(hipMemcpyAsync(hstates.data(), b.states, sizeof(SlotState) * hstates.size(),
-                                hipMemcpyDeviceToHost, s));
-        CFPQ_HIP(hipStreamSynchronize(s));
-        for (int32_t i = 0; i < n_instances; ++i)
-            if (hstates[i].bad_edges)
-                return fail(CFPQ_EINVAL, "instance " + std::to_string(i) + ": " +
-                                             std::to_string(hstates[i].bad_edges) + " device edges out of range");
-    }
 
     // Small instances: one resident workgroup each, on a side stream.
     const bool any_small = !p.small8.empty() || !p.small16.empty();
@@ -488,11 +490,10 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
         // The host checks the state after launch k while launch k + 1 is
         // already queued, so the device does not idle through the host's
         // round trip; the one launch queued past the fixpoint finds nothing
-        // running and its kernels return at once.  Two pinned slots: a slot
-        // is written again only after the host has waited for its last copy.
-        void* pb = nullptr;
-        CFPQ_HIP(pinned_readback(2 * sizeof(EngineState), &pb));
-        auto* hes = static_cast<EngineState*>(pb);
+        // running and its kernels return at once.  Two pinned slots (after
+        // the table image): a slot is written again only after the host has
+        // waited for its last copy.
+        auto* hes = reinterpret_cast<EngineState*>(img + es_slots);
         hipEvent_t got[2] = {nullptr, nullptr};
         struct GotGuard {
             hipEvent_t* e;
@@ -521,6 +522,10 @@ cfpq_status batch_closure_run(int32_t n_instances, const cfpq_instance* instance
     CFPQ_HIP(hipEventRecord(ev1, s));
     CFPQ_HIP(hipMemcpyAsync(hstates.data(), b.states, sizeof(SlotState) * hstates.size(), hipMemcpyDeviceToHost, s));
     CFPQ_HIP(hipStreamSynchronize(s));
+    for (int32_t i = 0; i < n_instances; ++i)
+        if (hstates[i].bad_edges)
+            return fail(CFPQ_EINVAL, "instance " + std::to_string(i) + ": " + std::to_string(hstates[i].bad_edges) +
+                                         " device edges out of range");
     float ms = 0.f;
     CFPQ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     bool all_conv = true;
