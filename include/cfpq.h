@@ -562,8 +562,10 @@ CFPQ_API void cfpq_server_default_config(cfpq_server_config* cfg);
 CFPQ_API cfpq_status cfpq_server_create(const cfpq_server_config* cfg, void* stream, cfpq_server** out);
 
 /* Queue one query.  graph/grammar are copied (host edges are copied at submit;
- * device edges must stay valid until the query is done).  d_result: device
- * buffer of cfpq_result_bytes(n, |N|) bytes, written when the query completes.
+ * device edges must stay valid until the query is done; their ids are checked
+ * on the device, and a query with an id out of range completes with status
+ * CFPQ_EINVAL and d_result unwritten).  d_result: device buffer of
+ * cfpq_result_bytes(n, |N|) bytes, written when the query completes.
  * Limits: 2^19 nodes, 64 binary rules, 64 terminals, 256 terminal rules.
  * Returns CFPQ_OK with *ticket set, CFPQ_EINVAL, CFPQ_ENOMEM (the query can
  * never fit the arena) or CFPQ_EBUSY (queue full).  Thread-safe. */

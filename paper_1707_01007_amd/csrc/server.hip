@@ -303,26 +303,10 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
         SRV_HIP(hipMemcpyAsync(srv->ids_init, init_ids.data(), 4 * k, hipMemcpyHostToDevice, s));
         SRV_HIP(hipMemcpyAsync(srv->b.edge_begin, ebegin.data(), 8 * ebegin.size(), hipMemcpyHostToDevice, s));
         SRV_HIP(engine_zero(srv->b, srv->ids_init, k, s));
+        // Device edges with an id out of range are counted and skipped by the
+        // scatter; the request runs on the rest and fails when it retires (the
+        // count comes back with the states, no round trip here).
         SRV_HIP(engine_scatter(srv->b, srv->ids_init, k, ebegin.back(), s));
-        bool any_dev = false;
-        for (Request* r : admitted) any_dev = any_dev || r->dev_edges != nullptr;
-        if (any_dev) {
-            std::vector<SlotState> tmp(S);
-            SRV_HIP(hipMemcpyAsync(tmp.data(), srv->b.states, sizeof(SlotState) * S, hipMemcpyDeviceToHost, s));
-            SRV_HIP(hipStreamSynchronize(s));
-            for (Request* r : admitted) {
-                if (tmp[r->slot].bad_edges) {
-                    r->status = CFPQ_EINVAL;
-                    SlotState st;
-                    std::memset(&st, 0, sizeof(st));
-                    st.done = 1;
-                    SRV_HIP(hipMemcpyAsync(srv->b.states + r->slot, &st, sizeof(st), hipMemcpyHostToDevice, s));
-                    srv->hstates[r->slot] = st;
-                    s8.erase(std::remove(s8.begin(), s8.end(), r->slot), s8.end());
-                    s16.erase(std::remove(s16.begin(), s16.end(), r->slot), s16.end());
-                }
-            }
-        }
         if (!s8.empty() || !s16.empty()) {
             // The slot list of a launch sits at one of 64 ring positions in
             // device memory; the batch that used the position before must have
@@ -376,24 +360,33 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
     }
     if (nl > 0) SRV_HIP(hipGraphLaunch(srv->exec, s));
     // ---- 4. retire ----
-    SRV_HIP(hipMemcpyAsync(srv->hstates.data(), srv->b.states, sizeof(SlotState) * S, hipMemcpyDeviceToHost, s));
+    // Small batches whose resident launches have finished, found before the
+    // states are read, so that the one read below sees their final states.
+    std::vector<int64_t> small_done;
+    for (auto& kv : srv->small_batches) {
+        const hipError_t e = hipEventQuery(kv.second.done);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) SRV_HIP(e);
+        small_done.push_back(kv.first);
+    }
+    void* pb = nullptr;
+    SRV_HIP(pinned_readback(sizeof(SlotState) * S, &pb));
+    SRV_HIP(hipMemcpyAsync(pb, srv->b.states, sizeof(SlotState) * S, hipMemcpyDeviceToHost, s));
     SRV_HIP(hipStreamSynchronize(s));
+    std::memcpy(srv->hstates.data(), pb, sizeof(SlotState) * S);
     std::vector<int32_t> finished;
     for (int32_t q = 0; q < S; ++q) {
         Request* r = srv->slot_req[q];
         if (!r) continue;
         if (r->small && r->small_batch >= 0 && r->status == CFPQ_OK) {
-            hipError_t e = hipEventQuery(srv->small_batches.at(r->small_batch).done);
-            if (e == hipErrorNotReady) continue;
-            if (e != hipSuccess) SRV_HIP(e);
-            SlotState st;
-            SRV_HIP(hipMemcpy(&st, srv->b.states + q, sizeof(st), hipMemcpyDeviceToHost));
-            srv->hstates[q] = st;
-            finished.push_back(q);
+            if (std::find(small_done.begin(), small_done.end(), r->small_batch) != small_done.end())
+                finished.push_back(q);
         } else if (r->status != CFPQ_OK || srv->hstates[q].done || !srv->hstates[q].active) {
             finished.push_back(q);
         }
     }
+    for (int32_t q : finished)
+        if (srv->hstates[q].bad_edges && srv->slot_req[q]->status == CFPQ_OK) srv->slot_req[q]->status = CFPQ_EINVAL;
     if (!finished.empty()) {
         for (int32_t q : finished) {
             Request* r = srv->slot_req[q];
