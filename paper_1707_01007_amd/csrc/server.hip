@@ -44,6 +44,44 @@ constexpr int32_t kSrvMaxTerminals = 64;   // terminals per query
 constexpr int32_t kSrvMaxTermRules = 256;  // terminal rules per query
 constexpr int32_t kTermStride = kSrvMaxTerminals + 1 + kSrvMaxTermRules;
 
+// Upload record of one admitted request, in 32-bit words: a header (slot,
+// its edges' end in the admission's edge list as two words), then its
+// descriptor, rules, modes, transpose slots, terminal table and initial
+// state, copied by upload_slots_kernel to the slot's places in the tables.
+constexpr int32_t kUpHead = 4;
+constexpr int32_t kUpDesc = kUpHead;
+constexpr int32_t kUpRules = kUpDesc + static_cast<int32_t>(sizeof(SlotDesc) / 4);
+constexpr int32_t kUpModes = kUpRules + 3 * kSrvMaxRules;
+constexpr int32_t kUpTrans = kUpModes + kSrvMaxRules;
+constexpr int32_t kUpTerm = kUpTrans + CFPQ_MAX_NONTERMINALS;
+constexpr int32_t kUpState = kUpTerm + kTermStride;
+constexpr int32_t kUpWords = (kUpState + static_cast<int32_t>(sizeof(SlotState) / 4) + 63) / 64 * 64;
+static_assert(sizeof(SlotDesc) % 8 == 0 && sizeof(SlotState) % 4 == 0, "records hold whole words");
+
+// One workgroup per admitted request: its tables to their slot's places, and
+// its entries of the initialisation list and the edge offsets.
+__global__ __launch_bounds__(256) void upload_slots_kernel(const uint32_t* __restrict__ recs, int32_t k,
+                                                           EngineBuffers b, int32_t* ids_init) {
+    const uint32_t* r = recs + static_cast<size_t>(blockIdx.x) * kUpWords;
+    const int32_t slot = static_cast<int32_t>(r[0]);
+    auto copy = [&](uint32_t* dst, int32_t from, int32_t words) {
+        for (int32_t w = threadIdx.x; w < words; w += blockDim.x) dst[w] = r[from + w];
+    };
+    copy(reinterpret_cast<uint32_t*>(b.descs + slot), kUpDesc, kUpRules - kUpDesc);
+    copy(reinterpret_cast<uint32_t*>(b.rules_tab) + static_cast<size_t>(slot) * 3 * kSrvMaxRules, kUpRules,
+         3 * kSrvMaxRules);
+    copy(reinterpret_cast<uint32_t*>(b.mode_tab) + static_cast<size_t>(slot) * kSrvMaxRules, kUpModes, kSrvMaxRules);
+    copy(reinterpret_cast<uint32_t*>(b.trans_tab) + static_cast<size_t>(slot) * CFPQ_MAX_NONTERMINALS, kUpTrans,
+         CFPQ_MAX_NONTERMINALS);
+    copy(reinterpret_cast<uint32_t*>(b.term_tab) + static_cast<size_t>(slot) * kTermStride, kUpTerm, kTermStride);
+    copy(reinterpret_cast<uint32_t*>(b.states + slot), kUpState, static_cast<int32_t>(sizeof(SlotState) / 4));
+    if (threadIdx.x == 0) {
+        ids_init[blockIdx.x] = slot;
+        b.edge_begin[blockIdx.x + 1] = static_cast<int64_t>(r[1]) | (static_cast<int64_t>(r[2]) << 32);
+        if (blockIdx.x == 0) b.edge_begin[0] = 0;
+    }
+}
+
 double now_s() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -132,6 +170,7 @@ struct cfpq_server {
     void* dmem = nullptr;
     cfpq::EngineBuffers b;
     int32_t* ids_init = nullptr;   // per admission round: slots to initialise
+    uint32_t* upload = nullptr;    // per admission round: the admitted requests' upload records
     int32_t* ids_small8 = nullptr;
     int32_t* ids_small16 = nullptr;
     char* arena_base = nullptr;
@@ -269,23 +308,25 @@ void fill_slot(cfpq_server* srv, Request& r, SlotDesc& d, std::vector<int32_t>& 
 bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
     hipStream_t s = srv->stream;
     const int32_t S = srv->cfg.max_slots;
+    // Pinned host memory of the turn (the same size every turn, so it is
+    // allocated once): the admitted requests' upload records, then the
+    // states read back at retirement.  The last turn ended synchronised, so
+    // no copy still reads it.
+    const size_t up_bytes = static_cast<size_t>(S) * kUpWords * 4;
+    void* pin = nullptr;
+    SRV_HIP(pinned_readback(up_bytes + sizeof(SlotState) * S, &pin));
+    uint32_t* up = static_cast<uint32_t*>(pin);
+    void* pin_states = static_cast<char*>(pin) + up_bytes;
     // ---- 2. initialise admitted requests ----
     if (!admitted.empty()) {
-        std::vector<int32_t> init_ids, s8, s16;
-        std::vector<int64_t> ebegin(1, 0);
-        for (Request* r : admitted) {
+        std::vector<int32_t> s8, s16;
+        int64_t edges_end = 0;
+        const int32_t k = static_cast<int32_t>(admitted.size());
+        std::vector<int32_t> rules, modes, trans, term;
+        for (int32_t x = 0; x < k; ++x) {
+            Request* r = admitted[x];
             SlotDesc d;
-            std::vector<int32_t> rules, modes, trans, term;
             fill_slot(srv, *r, d, rules, modes, trans, term);
-            SRV_HIP(hipMemcpyAsync(srv->b.descs + r->slot, &d, sizeof(d), hipMemcpyHostToDevice, s));
-            SRV_HIP(hipMemcpyAsync(srv->b.rules_tab + 3 * d.rule_off, rules.data(), rules.size() * 4,
-                                   hipMemcpyHostToDevice, s));
-            SRV_HIP(hipMemcpyAsync(srv->b.mode_tab + d.rule_off, modes.data(), modes.size() * 4,
-                                   hipMemcpyHostToDevice, s));
-            SRV_HIP(hipMemcpyAsync(srv->b.trans_tab + d.trans_off, trans.data(), trans.size() * 4,
-                                   hipMemcpyHostToDevice, s));
-            SRV_HIP(hipMemcpyAsync(srv->b.term_tab + d.term_off, term.data(), term.size() * 4,
-                                   hipMemcpyHostToDevice, s));
             if (!r->host_edges.empty())
                 SRV_HIP(hipMemcpyAsync(const_cast<cfpq_edge*>(d.edges), r->host_edges.data(),
                                        r->host_edges.size() * sizeof(cfpq_edge), hipMemcpyHostToDevice, s));
@@ -293,20 +334,30 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
             std::memset(&st, 0, sizeof(st));
             st.active = d.n_rules > 0 ? 1 : 0;
             st.fresh = 1;
-            SRV_HIP(hipMemcpyAsync(srv->b.states + r->slot, &st, sizeof(st), hipMemcpyHostToDevice, s));
             srv->hstates[r->slot] = st;
-            init_ids.push_back(r->slot);
-            ebegin.push_back(ebegin.back() + r->n_edges);
+            edges_end += r->n_edges;
+            uint32_t* rec = up + static_cast<size_t>(x) * kUpWords;
+            rec[0] = static_cast<uint32_t>(r->slot);
+            rec[1] = static_cast<uint32_t>(edges_end & 0xFFFFFFFF);
+            rec[2] = static_cast<uint32_t>(edges_end >> 32);
+            std::memcpy(rec + kUpDesc, &d, sizeof(d));
+            std::memcpy(rec + kUpRules, rules.data(), 4 * rules.size());
+            std::memcpy(rec + kUpModes, modes.data(), 4 * modes.size());
+            std::memcpy(rec + kUpTrans, trans.data(), 4 * trans.size());
+            std::memcpy(rec + kUpTerm, term.data(), 4 * term.size());
+            std::memcpy(rec + kUpState, &st, sizeof(st));
             if (d.n_rules > 0 && r->small) (d.W == 4 ? s8 : s16).push_back(r->slot);
         }
-        const int32_t k = static_cast<int32_t>(init_ids.size());
-        SRV_HIP(hipMemcpyAsync(srv->ids_init, init_ids.data(), 4 * k, hipMemcpyHostToDevice, s));
-        SRV_HIP(hipMemcpyAsync(srv->b.edge_begin, ebegin.data(), 8 * ebegin.size(), hipMemcpyHostToDevice, s));
+        // every table of every admitted request in one copy and one launch
+        SRV_HIP(hipMemcpyAsync(srv->upload, up, static_cast<size_t>(k) * kUpWords * 4, hipMemcpyHostToDevice, s));
+        upload_slots_kernel<<<dim3(static_cast<unsigned>(k)), dim3(256), 0, s>>>(srv->upload, k, srv->b,
+                                                                                 srv->ids_init);
+        SRV_HIP(hipGetLastError());
         SRV_HIP(engine_zero(srv->b, srv->ids_init, k, s));
         // Device edges with an id out of range are counted and skipped by the
         // scatter; the request runs on the rest and fails when it retires (the
         // count comes back with the states, no round trip here).
-        SRV_HIP(engine_scatter(srv->b, srv->ids_init, k, ebegin.back(), s));
+        SRV_HIP(engine_scatter(srv->b, srv->ids_init, k, edges_end, s));
         if (!s8.empty() || !s16.empty()) {
             // The slot list of a launch sits at one of 64 ring positions in
             // device memory; the batch that used the position before must have
@@ -369,11 +420,9 @@ bool turn(cfpq_server* srv, std::vector<Request*>& admitted) {
         if (e != hipSuccess) SRV_HIP(e);
         small_done.push_back(kv.first);
     }
-    void* pb = nullptr;
-    SRV_HIP(pinned_readback(sizeof(SlotState) * S, &pb));
-    SRV_HIP(hipMemcpyAsync(pb, srv->b.states, sizeof(SlotState) * S, hipMemcpyDeviceToHost, s));
+    SRV_HIP(hipMemcpyAsync(pin_states, srv->b.states, sizeof(SlotState) * S, hipMemcpyDeviceToHost, s));
     SRV_HIP(hipStreamSynchronize(s));
-    std::memcpy(srv->hstates.data(), pb, sizeof(SlotState) * S);
+    std::memcpy(srv->hstates.data(), pin_states, sizeof(SlotState) * S);
     std::vector<int32_t> finished;
     for (int32_t q = 0; q < S; ++q) {
         Request* r = srv->slot_req[q];
@@ -656,6 +705,7 @@ cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, c
     const size_t o_s16 = take(4 * static_cast<size_t>(S));
     const size_t o_eb = take(8 * (static_cast<size_t>(S) + 1));
     const size_t o_es = take(sizeof(EngineState));
+    const size_t o_up = take(4 * static_cast<size_t>(kUpWords) * S);
     const size_t tables = off;
     if (cfg.hbm_budget <= tables) return fail(CFPQ_ENOMEM, "hbm_budget does not cover the server's tables");
     // One allocation at creation; nothing is allocated per request.
@@ -674,6 +724,7 @@ cfpq_status cfpq_server_create(const cfpq_server_config* cfg_in, void* stream, c
     srv->b.edge_begin = reinterpret_cast<int64_t*>(base + o_eb);
     srv->b.es = reinterpret_cast<EngineState*>(base + o_es);
     srv->ids_init = reinterpret_cast<int32_t*>(base + o_init);
+    srv->upload = reinterpret_cast<uint32_t*>(base + o_up);
     srv->ids_small8 = reinterpret_cast<int32_t*>(base + o_s8);
     srv->ids_small16 = reinterpret_cast<int32_t*>(base + o_s16);
     srv->arena_base = base + align_up(tables, 4096);
