@@ -92,7 +92,18 @@ typedef struct {
  * operand: ROWS forms row i of B x C as the OR of the rows C[k, :] for the set
  * bits k of B[i, :] (cost ~ nnz(B) rows of C); COLS does the same on the
  * transposed product (B x C)^T = C^T x B^T (cost ~ nnz(C) rows of B^T, plus
- * transposes).  All give identical bits. */
+ * transposes).  All give identical bits.
+ *
+ * Environment (read on every call of cfpq_closure, cfpq_closure_static and
+ * cfpq_workspace_bytes):
+ *   CFPQ_PATH  bits, mfma, fp4, rows or cols: used where options.path is
+ *              AUTO (any other value is ignored); the bits are the same.
+ *   CFPQ_LOG   a file name, or "-" for stderr: cfpq_closure appends JSON
+ *              lines -- {"event": "loop", ...} per host-driven loop (loop,
+ *              rules_launched, changed nonterminals, products so far,
+ *              host_ms), {"event": "replay", ...} per replay of captured
+ *              loops, and {"event": "closure", ...} per call with its totals.
+ */
 enum {
     CFPQ_PATH_AUTO = 0,
     CFPQ_PATH_BITS = 1,  /* bit-packed VALU product (AND / OR-reduce) */

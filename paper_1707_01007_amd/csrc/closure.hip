@@ -24,6 +24,7 @@
 #include <array>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -89,11 +90,68 @@ cfpq_status validate_graph(const cfpq_graph* g, const cfpq_grammar* gr) {
 
 namespace {
 
+// CFPQ_PATH in the environment (bits, mfma, fp4, rows, cols) replaces the
+// AUTO choice; other values leave it.  Every path gives the same bits.
+int32_t env_path() {
+    const char* v = std::getenv("CFPQ_PATH");
+    if (!v) return CFPQ_PATH_AUTO;
+    static const struct {
+        const char* name;
+        int32_t path;
+    } names[] = {{"bits", CFPQ_PATH_BITS}, {"mfma", CFPQ_PATH_MFMA}, {"fp4", CFPQ_PATH_FP4},
+                 {"rows", CFPQ_PATH_ROWS}, {"cols", CFPQ_PATH_COLS}};
+    for (const auto& e : names)
+        if (std::strcmp(v, e.name) == 0) return e.path;
+    return CFPQ_PATH_AUTO;
+}
+
 cfpq_options resolve(const cfpq_options* opt) {
     cfpq_options o;
     cfpq_default_options(&o);
     if (opt) o = *opt;
+    if (o.path == CFPQ_PATH_AUTO) o.path = env_path();
     return o;
+}
+
+// CFPQ_LOG in the environment names a file ("-": stderr) that receives JSON
+// lines: one per loop of the host-driven closure, one per replay of captured
+// loops, and one per closure call with its totals.  Each line is written
+// with one call and flushed, so calls on several threads do not interleave
+// within a line.
+struct JsonLog {
+    FILE* f = nullptr;
+    bool own = false;
+    JsonLog() {
+        const char* v = std::getenv("CFPQ_LOG");
+        if (!v || !*v) return;
+        if (std::strcmp(v, "-") == 0) {
+            f = stderr;
+        } else {
+            f = std::fopen(v, "a");
+            own = f != nullptr;
+        }
+    }
+    ~JsonLog() {
+        if (own) std::fclose(f);
+    }
+    JsonLog(const JsonLog&) = delete;
+    JsonLog& operator=(const JsonLog&) = delete;
+    void line(const std::string& text) {
+        if (!f) return;
+        std::fputs((text + "\n").c_str(), f);
+        std::fflush(f);
+    }
+};
+
+const char* path_name(int32_t path) {
+    switch (path) {
+        case CFPQ_PATH_BITS: return "bits";
+        case CFPQ_PATH_MFMA: return "mfma";
+        case CFPQ_PATH_FP4: return "fp4";
+        case CFPQ_PATH_ROWS: return "rows";
+        case CFPQ_PATH_COLS: return "cols";
+        default: return "auto";
+    }
 }
 
 // Workspace carve-up (all offsets 256-byte aligned).
@@ -429,12 +487,28 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         return fail(CFPQ_EINVAL, "unsupported FP4 tile (pipeline depth 2 or 3, or 0)");
     if (!no_alloc && resident_route(graph, grammar, o)) {
         const cfpq_instance inst{*graph, grammar, d_result};
-        return batch_closure_run(1, &inst, o, stream, d_workspace, workspace_bytes, stats, true);
+        JsonLog rlog;
+        cfpq_stats local{};
+        cfpq_stats* sp = stats ? stats : (rlog.f ? &local : nullptr);
+        const cfpq_status rs = batch_closure_run(1, &inst, o, stream, d_workspace, workspace_bytes, sp, true);
+        if (rlog.f && sp) {
+            char buf[320];
+            std::snprintf(buf, sizeof(buf),
+                          "{\"event\": \"closure\", \"n\": %d, \"edges\": %lld, \"nonterminals\": %d, "
+                          "\"path\": \"resident\", \"iterations\": %lld, \"products\": %lld, "
+                          "\"converged\": %d, \"device_ms\": %.4f}",
+                          graph->n_nodes, static_cast<long long>(graph->n_edges), grammar->n_nonterminals,
+                          static_cast<long long>(sp->iterations), static_cast<long long>(sp->products),
+                          sp->converged, sp->device_ms);
+            rlog.line(buf);
+        }
+        return rs;
     }
     const Plan p = make_plan(graph, grammar, o);
     if (p.total > 0 && !d_workspace) return fail(CFPQ_EINVAL, "d_workspace is NULL");
     if (workspace_bytes < p.total)
         return fail(CFPQ_ENOMEM, "workspace too small: need " + std::to_string(p.total) + " bytes");
+    JsonLog jlog;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* ws = static_cast<char*>(d_workspace);
@@ -584,10 +658,15 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         if (ee != hipSuccess) return fail(CFPQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
         CFPQ_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
         LoopState hs;
+        int64_t replay = 0;
         do {
             CFPQ_HIP(hipGraphLaunch(exec, s));
             CFPQ_HIP(hipMemcpyAsync(&hs, lst, sizeof(hs), hipMemcpyDeviceToHost, s));
             CFPQ_HIP(hipStreamSynchronize(s));
+            if (jlog.f)
+                jlog.line("{\"event\": \"replay\", \"replay\": " + std::to_string(++replay) +
+                         ", \"loops\": " + std::to_string(hs.iterations) + ", \"products\": " +
+                         std::to_string(hs.products) + ", \"done\": " + std::to_string(hs.done ? 1 : 0) + "}");
         } while (!hs.done);
         iters = hs.iterations;
         products = hs.products;
@@ -678,6 +757,7 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     std::vector<double> rule_sparse_bytes;
     double sparse_bytes = 0.0, sparse_ms = 0.0;
     while (!captured && !converged && iters < cap) {
+        const auto loop_t0 = std::chrono::steady_clock::now();
         CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         size_t launched = 0;
         rule_sparse_bytes.clear();
@@ -790,6 +870,20 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         ++iters;
         bool any = false;
         for (int32_t a = 0; a < n_nt; ++a) any = any || flags[a] != 0;
+        if (jlog.f) {
+            int32_t changed_nt = 0;
+            for (int32_t a = 0; a < n_nt; ++a) changed_nt += flags[a] != 0 ? 1 : 0;
+            const double loop_ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - loop_t0).count();
+            char buf[320];
+            std::snprintf(buf, sizeof(buf),
+                          "{\"event\": \"loop\", \"loop\": %lld, \"rules_launched\": %zu, \"changed\": %d, "
+                          "\"products\": %lld, \"sparse_products\": %lld, \"delta_products\": %lld, "
+                          "\"host_ms\": %.4f}",
+                          static_cast<long long>(iters), launched, changed_nt, static_cast<long long>(products),
+                          static_cast<long long>(sparse_products), static_cast<long long>(delta_products), loop_ms);
+            jlog.line(buf);
+        }
         if (!any) {
             converged = true;
             break;
@@ -831,6 +925,20 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
         stats->product_ms = product_ms;
         stats->path_used = p.path;
         stats->converged = converged ? 1 : 0;
+    }
+    if (jlog.f) {
+        char buf[512];
+        std::snprintf(buf, sizeof(buf),
+                      "{\"event\": \"closure\", \"n\": %d, \"edges\": %lld, \"nonterminals\": %d, "
+                      "\"path\": \"%s\", \"hybrid\": %d, \"schedule\": \"%s\", \"captured\": %d, "
+                      "\"iterations\": %lld, \"products\": %lld, \"sparse_products\": %lld, "
+                      "\"delta_products\": %lld, \"converged\": %d, \"device_ms\": %.4f}",
+                      graph->n_nodes, static_cast<long long>(graph->n_edges), n_nt, path_name(p.path),
+                      p.hybrid ? 1 : 0, p.jacobi ? "jacobi" : "inplace", captured ? o.capture : 0,
+                      static_cast<long long>(iters), static_cast<long long>(products),
+                      static_cast<long long>(sparse_products), static_cast<long long>(delta_products),
+                      converged ? 1 : 0, static_cast<double>(ms));
+        jlog.line(buf);
     }
     if (!converged) return fail(CFPQ_ENOTCONV, "max_iters reached before the fixpoint");
     return CFPQ_OK;

@@ -324,6 +324,31 @@ def test_batch_records_match_the_ctypes_structures():
     assert cfpq._stats_dicts(stats, 2) == [stats[i].as_dict() for i in range(2)]
 
 
+def test_path_variable_sizes_the_workspace(monkeypatch):
+    """CFPQ_PATH replaces AUTO in cfpq_workspace_bytes as in the closure, so
+    the workspace asked for fits the path the closure will take."""
+    from paper_1707_01007_amd import _abi
+    lib = _lib()
+    gr, g, keep = _structs()
+
+    def need(path, env):
+        if env is None:
+            monkeypatch.delenv("CFPQ_PATH", raising=False)
+        else:
+            monkeypatch.setenv("CFPQ_PATH", env)
+        opt = _abi.Options()
+        lib.cfpq_default_options(ctypes.byref(opt))
+        opt.path = path
+        sz = ctypes.c_size_t(0)
+        assert lib.cfpq_workspace_bytes(ctypes.byref(gr), ctypes.byref(g), ctypes.byref(opt), ctypes.byref(sz)) == 0
+        return sz.value
+
+    for name, code in (("cols", _abi.PATH_COLS), ("rows", _abi.PATH_ROWS), ("bits", _abi.PATH_BITS)):
+        assert need(_abi.PATH_AUTO, name) == need(code, None)
+        assert need(code, "cols") == need(code, None)  # explicit paths are left alone
+    assert need(_abi.PATH_AUTO, "nonsense") == need(_abi.PATH_AUTO, None)
+
+
 def test_server_config_validation_on_host():
     from paper_1707_01007_amd import _abi
     lib = _lib()
