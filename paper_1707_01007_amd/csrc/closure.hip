@@ -272,8 +272,11 @@ Plan make_plan(const cfpq_graph* g, const cfpq_grammar* gr, const cfpq_options& 
     if (p.hybrid) off += mat_bytes * p.n_nt;
     p.off_delta = off;
     if (p.hybrid) off += mat_bytes * p.n_nt;
-    p.off_dnnz = off;  // |D| then |T| per nonterminal
-    if (p.hybrid) off += align_up(static_cast<size_t>(p.n_nt) * 16, 256);
+    p.off_dnnz = off;  // |D| then |T| per nonterminal, then (hybrid) the loop's change flags
+    if (p.hybrid) {
+        p.off_flags = off + static_cast<size_t>(p.n_nt) * 16;
+        off += align_up(static_cast<size_t>(p.n_nt) * 20, 256);
+    }
     p.off_rowor = off;
     if (p.hybrid || p.forced != kModeDense) off += align_up(rowor_scratch_bytes(p.L), 256);
     p.total = off;
@@ -758,7 +761,11 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
     double sparse_bytes = 0.0, sparse_ms = 0.0;
     while (!captured && !converged && iters < cap) {
         const auto loop_t0 = std::chrono::steady_clock::now();
-        CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
+        // hybrid: the counts of the delta snapshot and the flags are one block
+        if (p.hybrid)
+            CFPQ_HIP(hipMemsetAsync(d_dnnz, 0, static_cast<size_t>(n_nt) * 20, s));
+        else
+            CFPQ_HIP(hipMemsetAsync(d_flags, 0, static_cast<size_t>(n_nt) * 4, s));
         size_t launched = 0;
         rule_sparse_bytes.clear();
         std::fill(written.begin(), written.end(), 0);
@@ -845,13 +852,19 @@ cfpq_status closure_impl(const cfpq_graph* graph, const cfpq_grammar* grammar, c
             ++launched;
             ++products;
         }
-        CFPQ_HIP(hipMemcpyAsync(h_flags, d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
         if (p.hybrid) {
             // for the nonterminals that changed: bits gained this loop, new
-            // snapshot, new set-bit count (the others keep theirs)
-            CFPQ_HIP(hipMemsetAsync(d_dnnz, 0, static_cast<size_t>(n_nt) * 16, s));
+            // snapshot, new set-bit count (the others keep theirs); counts and
+            // flags come back in one copy when the host staging is one block
             CFPQ_HIP(launch_delta_snapshot(Y, SNAP, DELTA, L, d_dnnz, d_dnnz + n_nt, d_flags, s, n_nt));
-            CFPQ_HIP(hipMemcpyAsync(h_dnnz, d_dnnz, static_cast<size_t>(n_nt) * 16, hipMemcpyDeviceToHost, s));
+            if (h_flags == reinterpret_cast<int32_t*>(h_dnnz + 2 * static_cast<size_t>(n_nt))) {
+                CFPQ_HIP(hipMemcpyAsync(h_dnnz, d_dnnz, static_cast<size_t>(n_nt) * 20, hipMemcpyDeviceToHost, s));
+            } else {
+                CFPQ_HIP(hipMemcpyAsync(h_dnnz, d_dnnz, static_cast<size_t>(n_nt) * 16, hipMemcpyDeviceToHost, s));
+                CFPQ_HIP(hipMemcpyAsync(h_flags, d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
+            }
+        } else {
+            CFPQ_HIP(hipMemcpyAsync(h_flags, d_flags, static_cast<size_t>(n_nt) * 4, hipMemcpyDeviceToHost, s));
         }
         CFPQ_HIP(hipStreamSynchronize(s));
         if (h_flags != flags.data()) {
