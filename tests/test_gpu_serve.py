@@ -145,6 +145,30 @@ def test_server_errors(cfpq):
         assert np.array_equal(cfpq.result_bits(ok["result"]), worklist.closure(n, e, g))
 
 
+def test_server_bad_device_edges_on_every_route(cfpq):
+    """A request whose device edges hold an id out of range completes with
+    CFPQ_EINVAL whichever route runs it -- a resident workgroup (padded side
+    <= 512), the engine's tile list (up to 2048) or a hybrid lane (4096 and up)
+    -- while the good requests submitted with it are served exactly."""
+    import torch
+    g = grammars.dyck()
+    with cfpq.Server(hbm_budget=2 << 30, max_slots=16) as srv:
+        jobs = []
+        for size, seed in ((300, 11), (1500, 12), (4500, 13)):
+            n, e = graphs.erdos_renyi(size, 3 * size, seed)
+            bad = e.copy()
+            bad[len(e) // 2, 0] = -1 if size == 1500 else size
+            jobs.append((srv.submit(n, torch.from_numpy(bad).cuda(), g), None, None))
+            jobs.append((srv.submit(n, torch.from_numpy(e).cuda(), g), n, e))
+        for t, n, e in jobs:
+            info = srv.wait(t)
+            if n is None:
+                assert info["status"] == -1
+            else:
+                assert info["status"] == 0
+                assert np.array_equal(cfpq.result_bits(info["result"]), worklist.closure(n, e, g))
+
+
 def test_server_lanes_equal_engine(cfpq):
     """Large queries (padded side >= 4096) go to the hybrid lanes; the same
     mix served with no lanes (everything in the batched engine) gives the same
