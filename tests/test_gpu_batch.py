@@ -175,6 +175,27 @@ def test_batch_device_edges_and_errors(cfpq):
     assert ei.value.status == -1 and "instance 3" in str(ei.value)
 
 
+@pytest.mark.parametrize("size", [300, 1500])
+def test_batch_bad_device_edge_on_each_route(cfpq, size):
+    """An out-of-range device edge in a resident-route instance (padded side
+    <= 512) or a tile-route one fails the batch with CFPQ_EINVAL naming it;
+    the same batch without it matches the oracle."""
+    import torch
+    g = grammars.dyck()
+    insts = [graphs.erdos_renyi(sz, 3 * sz, 20 + k) for k, sz in enumerate((200, size, 900))]
+    items = [(n, torch.from_numpy(e).cuda(), g) for n, e in insts]
+    res = cfpq.batch_closure(items)
+    for (n, e), r in zip(insts, res):
+        assert np.array_equal(cfpq.result_bits(r), worklist.closure(n, e, g))
+    n, e = insts[1]
+    bad = e.copy()
+    bad[-1, 2] = n
+    items[1] = (n, torch.from_numpy(bad).cuda(), g)
+    with pytest.raises(cfpq.CfpqError) as ei:
+        cfpq.batch_closure(items)
+    assert ei.value.status == -1 and "instance 1" in str(ei.value)
+
+
 def test_batch_max_iters_partial_is_sound(cfpq):
     insts = [configs.config1(), configs.config3(1024)]
     res = cfpq.batch_closure([(i.n, i.edges, i.grammar) for i in insts], max_iters=3, allow_partial=True)
