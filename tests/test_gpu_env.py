@@ -60,6 +60,30 @@ def test_log_lines_follow_the_loops(cfpq, tmp_path, monkeypatch):
     assert len(ev) == 1 and ev[0]["path"] == "resident" and ev[0]["iterations"] == res.stats["iterations"]
 
 
+def test_log_of_a_hybrid_closure(cfpq, tmp_path, monkeypatch):
+    """The hybrid closure (padded side 4608: dense, row-gather and delta
+    products chosen per loop) logs every loop; its running counts end at the
+    call's statistics."""
+    log = tmp_path / "hybrid.jsonl"
+    monkeypatch.setenv("CFPQ_LOG", str(log))
+    n, e = graphs.erdos_renyi(4500, 13500, 43, labels=2)
+    g = grammars.anbn()
+    res = cfpq.closure(n, e, g)
+    assert np.array_equal(cfpq.result_bits(res), worklist.closure(n, e, g))
+    ev = _events(log)
+    loops = [x for x in ev if x["event"] == "loop"]
+    call = ev[-1]
+    assert call["event"] == "closure" and call["hybrid"] == 1 and call["iterations"] == res.stats["iterations"]
+    assert [x["loop"] for x in loops] == list(range(1, res.stats["iterations"] + 1))
+    assert loops[-1]["changed"] == 0 and all(x["changed"] > 0 for x in loops[:-1])
+    assert loops[-1]["products"] == res.stats["products"] == call["products"]
+    assert loops[-1]["sparse_products"] == res.stats["sparse_products"] == call["sparse_products"]
+    assert loops[-1]["delta_products"] == res.stats["delta_products"] == call["delta_products"]
+    assert res.stats["sparse_products"] > 0
+    counts = [x["products"] for x in loops]
+    assert counts == sorted(counts)
+
+
 @pytest.mark.parametrize("name,code", [("rows", 3), ("cols", 4), ("bits", 1), ("fp4", 5)])
 def test_path_variable_replaces_auto(cfpq, monkeypatch, name, code):
     n, e = graphs.erdos_renyi(700, 2100, 41, labels=2)
